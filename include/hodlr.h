@@ -1,0 +1,168 @@
+/*
+ * hodlr.h - C ABI of the MI355X (gfx950) HODLR-preconditioned GMRES library.
+ *
+ * The library solves K x = F for a dense frontal matrix K (n x n, float64,
+ * column-major) and s right-hand sides (the problem statement of Sec. 4.2,
+ * eq. denseSystem) with GMRES (Sec. 3) preconditioned by a low-accuracy
+ * HODLR factorization of K (Sec. 4): off-diagonal blocks compressed by
+ * partial-pivoting ACA (Sec. 5.1) or by the boundary-distance pseudo-skeleton
+ * BDLR (Sec. 5.3), then factorized level by level with the Woodbury formula
+ * (Sec. 4.3).
+ *
+ * Conventions shared by every entry point
+ *   - Matrices are column-major with a leading dimension >= their row count.
+ *   - Every matrix/vector pointer is DEVICE memory owned by the caller unless
+ *     the argument says "host".  The library never frees caller memory.
+ *   - Work is enqueued on the given HIP stream; calls are asynchronous unless
+ *     stated otherwise.  Pass 0 for the default stream.
+ *   - Every function returns a hodlr_status.  No exception crosses the ABI.
+ *     On failure hodlr_last_error() returns a thread-local message.
+ *   - A handle is not thread-safe; distinct handles are independent.
+ */
+#ifndef HODLR_H_
+#define HODLR_H_
+
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct hodlr_s* hodlr_t; /* opaque; created by hodlr_build*, freed by hodlr_destroy */
+
+typedef enum {
+  HODLR_OK = 0,
+  HODLR_EINVAL = 1,    /* bad argument (size, pointer, option) */
+  HODLR_ENOMEM = 2,    /* device allocation failed */
+  HODLR_ESINGULAR = 3, /* a leaf block or a Woodbury capacitance matrix is singular */
+  HODLR_ENOCONV = 4,   /* GMRES stopped at maxit above tol; X holds the last iterate */
+  HODLR_EHIP = 5       /* a HIP runtime call or kernel failed */
+} hodlr_status;
+
+enum { HODLR_ACA = 0, HODLR_BDLR = 1 };
+
+typedef struct {
+  int leaf;       /* largest leaf block (>= 1).  The tree splits [lo,hi) at
+                     lo + floor((hi-lo)/2) to the smallest depth L with
+                     ceil(n / 2^L) <= leaf (Sec. 4.1 block sizes n/2^p). */
+  double tol;     /* compression tolerance eps: the ACA stopping ratio
+                     |u_k||v_k| <= eps |U V^T|_F (Sec. 5.1), or the BDLR
+                     relative pivot threshold |pivot| >= eps |first pivot|
+                     (Sec. 7.1). */
+  int method;     /* HODLR_ACA or HODLR_BDLR */
+  int bdlr_depth; /* BDLR: pick rows/cols at graph distance < depth from the
+                     block boundary (Sec. 5.3) */
+  int max_rank;   /* cap on every off-diagonal rank (0 = library maximum) */
+  int precision;  /* 32 or 64: arithmetic of the factorization and solve */
+} hodlr_opts;
+
+/* Fill *opts with defaults: leaf 128, tol 1e-4, ACA, depth 1, max_rank 0,
+ * precision 32. */
+void hodlr_default_opts(hodlr_opts* opts);
+
+/* Compress K into a HODLR matrix (Sec. 4.3.1 step 1).
+ *   K       device, n x n float64, leading dimension ldk >= n.  Read only;
+ *           not retained after the call returns (the handle keeps copies of
+ *           the leaf blocks and the low-rank factors).
+ *   g_rowptr, g_col
+ *           device CSR (int32, n+1 and nnz entries) of the separator's
+ *           sparse interaction graph in K's numbering (Sec. 5.3); required
+ *           for HODLR_BDLR, ignored (may be NULL) for HODLR_ACA.
+ *   opts    host; NULL = defaults.
+ *   out     host; receives the new handle.
+ * Synchronizes the stream once (to size the factor storage from the ranks
+ * found).  Errors: EINVAL (n < 1, ldk < n, NULL K/out, bad opts), ENOMEM,
+ * EHIP. */
+int hodlr_build(const double* K, int n, int ldk, const int* g_rowptr, const int* g_col,
+                const hodlr_opts* opts, hipStream_t stream, hodlr_t* out);
+
+/* Test/benchmark hook: a HODLR matrix given directly by its pieces.
+ *   leaves  device float64, the leaf blocks packed leaf after leaf, each
+ *           b_i x b_i column-major with leading dimension b_i, leaves in
+ *           left-to-right order of the tree for (n, leaf).
+ *   Upanel, Vpanel
+ *           device float64, n x R column-major (ld n) with R = sum of
+ *           rcols[p-1] for p = 1..L.  Column block p (offset sum of
+ *           rcols[q-1], q < p) holds, in the rows of node (p,i), that node's
+ *           U, and in the rows of its sibling, that node's V, so
+ *           K(node, sibling) = U V^T.
+ *   ranks   host int, one per node below the root in level order
+ *           (level 1 left to right, then level 2, ...), each <= rcols[p-1].
+ *   rcols   host int[L], width of each level's column block.
+ * Errors: EINVAL on inconsistent sizes, ENOMEM, EHIP. */
+int hodlr_build_from_factors(int n, int leaf, int precision, const double* leaves,
+                             const double* Upanel, const double* Vpanel, const int* ranks,
+                             const int* rcols, int nlevels, hipStream_t stream, hodlr_t* out);
+
+/* Factorize (Sec. 4.3.1 steps 2-5): leaf LU with partial pivoting (kept as
+ * the leaf inverse), leaf solves of the stacked panels Z = [U | ancestor U],
+ * then, from the leaves up, per node the capacitance matrix
+ * S = [[I, V_b^T d_a], [V_a^T d_b, I]] (eq. SchurSum), its inverse, and the
+ * correction of the ancestor columns.  Synchronizes once to report
+ * ESINGULAR (message names the node). */
+int hodlr_factor(hodlr_t h, hipStream_t stream);
+
+/* X = Ktilde^-1 B (Sec. 4.3.2) in the handle's precision.
+ *   B, X    device, n x nrhs, leading dimensions ldb, ldx >= n; element
+ *           type float (precision 32) or double (precision 64).  X may alias
+ *           B (ldx == ldb).
+ * Requires hodlr_factor.  Asynchronous.  Errors: EINVAL, ENOMEM, EHIP. */
+int hodlr_solve(hodlr_t h, const void* B, int nrhs, int ldb, void* X, int ldx,
+                hipStream_t stream);
+
+/* Flexible right-preconditioned GMRES in float64 (Sec. 3; Table 3 settings
+ * as defaults of the caller): Arnoldi with classical Gram-Schmidt applied
+ * twice, Givens rotations, each right-hand side converging on its own when
+ * its Givens residual estimate drops to tol * |b|, confirmed with the true
+ * residual |b - K x| at the end of the cycle; restarts every `restart`
+ * steps; at most `maxit` steps per right-hand side.
+ *   K       device n x n float64 (ld ldk), read for the whole call.
+ *   precond handle from hodlr_factor, or NULL for no preconditioner.
+ *   B       device n x nrhs float64 (ld ldb).
+ *   X       device n x nrhs float64 (ld ldx): initial guess in, solution out.
+ *   iters   host int[nrhs]: steps taken per right-hand side.
+ *   relres  host double[nrhs]: final true |b - K x| / |b|.
+ * Synchronizes the stream.  Returns ENOCONV if any right-hand side is above
+ * tol at maxit (X still holds the last iterates). */
+int gmres_solve(const double* K, int n, int ldk, hodlr_t precond, const double* B, int nrhs,
+                int ldb, double* X, int ldx, double tol, int maxit, int restart, int* iters,
+                double* relres, hipStream_t stream);
+
+/* Recursive coordinate bisection order of n dofs for the HODLR tree of
+ * (n, leaf): for every node from the root down, sort its dofs by the
+ * coordinate of largest extent (first axis on ties, stable) and give the
+ * first floor(len/2) to the left child.  coords: device n x 3 float32,
+ * row-major (x, y, z per dof).  perm: device int32[n], out, new dof i = old
+ * dof perm[i].  n <= 16384.  Asynchronous. */
+int hodlr_order_rcb(const float* coords, int n, int leaf, int* perm, hipStream_t stream);
+
+/* Kout(i, j) = Kin(perm[i], perm[j]).  Kin, Kout device float64 (ld ldi,
+ * ldo >= n), must not overlap; perm device int32[n].  Asynchronous. */
+int hodlr_permute(const double* Kin, int n, int ldi, const int* perm, double* Kout, int ldo,
+                  hipStream_t stream);
+
+/* Relabel a CSR graph: new vertex i = old vertex perm[i].  All device int32:
+ * rowptr[n+1], col[nnz] in; rowptr_out[n+1], col_out[nnz] out (neighbours
+ * sorted).  Asynchronous. */
+int hodlr_permute_graph(const int* rowptr, const int* col, int n, const int* perm,
+                        int* rowptr_out, int* col_out, hipStream_t stream);
+
+/* Introspection (host arrays): number of levels L, ranks of the nodes below
+ * the root in level order (capacity 2^(L+1)-2 ints), per-level column widths
+ * (capacity L ints).  Any pointer may be NULL. */
+int hodlr_stats(hodlr_t h, int* nlevels, int* ranks, int* rcols);
+
+/* Copy out the low-rank factors as float64 in the layout of
+ * hodlr_build_from_factors (device, n x R, ld n).  Valid before
+ * hodlr_factor (afterwards the U panel holds the factorization). */
+int hodlr_get_factors(hodlr_t h, double* Upanel, double* Vpanel, hipStream_t stream);
+
+int hodlr_destroy(hodlr_t h);
+
+/* Thread-local message of the last failing call on this thread. */
+const char* hodlr_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* HODLR_H_ */

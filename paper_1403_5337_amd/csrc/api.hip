@@ -1,0 +1,369 @@
+// C ABI entry points: argument validation, handle lifetime, tree set-up.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <memory>
+#include <string>
+
+#include "hodlr_internal.h"
+
+namespace hodlr {
+
+static thread_local std::string g_last_error;
+
+void set_error(const std::string& msg) { g_last_error = msg; }
+
+int fail(int code, const std::string& msg) {
+  set_error(msg);
+  return code;
+}
+
+int DevBuf::ensure(size_t nbytes) {
+  if (nbytes <= bytes && p) return HODLR_OK;
+  release();
+  if (nbytes == 0) nbytes = 256;
+  hipError_t e = hipMalloc(&p, nbytes);
+  if (e != hipSuccess) {
+    p = nullptr;
+    return fail(HODLR_ENOMEM, std::string("hipMalloc(") + std::to_string(nbytes) +
+                                  "): " + hipGetErrorString(e));
+  }
+  bytes = nbytes;
+  return HODLR_OK;
+}
+
+void Tree::build(int n_, int leaf_) {
+  n = n_;
+  leaf = leaf_;
+  L = 0;
+  while ((n + (1 << L) - 1) / (1 << L) > leaf) ++L;
+  lo.assign((2 << L) - 1, 0);
+  hi.assign((2 << L) - 1, 0);
+  lo[0] = 0;
+  hi[0] = n;
+  for (int p = 0; p < L; ++p) {
+    for (int i = 0; i < (1 << p); ++i) {
+      int id = node_id(p, i);
+      int mid = lo[id] + (hi[id] - lo[id]) / 2;
+      int a = node_id(p + 1, 2 * i), b = node_id(p + 1, 2 * i + 1);
+      lo[a] = lo[id];
+      hi[a] = mid;
+      lo[b] = mid;
+      hi[b] = hi[id];
+    }
+  }
+}
+
+int Tree::min_size(int p) const {
+  int m = n;
+  for (int i = 0; i < (1 << p); ++i) m = std::min(m, size(node_id(p, i)));
+  return m;
+}
+
+int Tree::max_size(int p) const {
+  int m = 0;
+  for (int i = 0; i < (1 << p); ++i) m = std::max(m, size(node_id(p, i)));
+  return m;
+}
+
+// Common set-up of a new handle once the tree is known.
+static int init_handle(hodlr_s* h, int n, int leaf, int precision) {
+  h->tree.build(n, leaf);
+  h->precision = precision;
+  h->esize = precision == 64 ? 8 : 4;
+  HODLR_HIP(hipGetDevice(&h->device));
+  const Tree& t = h->tree;
+  h->nleaf = 1 << t.L;
+  h->bmax = t.max_size(t.L);
+  int nn = t.nnodes();
+  h->rank.assign(nn, 0);
+  HODLR_TRY(h->d_lo.ensure(nn * sizeof(int)));
+  HODLR_TRY(h->d_hi.ensure(nn * sizeof(int)));
+  HODLR_TRY(h->d_rank.ensure(nn * sizeof(int)));
+  HODLR_HIP(hipMemcpy(h->d_lo.p, t.lo.data(), nn * sizeof(int), hipMemcpyHostToDevice));
+  HODLR_HIP(hipMemcpy(h->d_hi.p, t.hi.data(), nn * sizeof(int), hipMemcpyHostToDevice));
+  HODLR_TRY(h->status.ensure(4 * sizeof(int)));
+  HODLR_HIP(hipMemset(h->status.p, 0, 4 * sizeof(int)));
+  HODLR_TRY(h->Kinv.ensure((size_t)h->nleaf * h->bmax * h->bmax * h->esize));
+  return HODLR_OK;
+}
+
+// Column layout from the per-node ranks: level q's block is as wide as the
+// largest rank at that level.
+int set_layout_from_ranks(hodlr_s* h) {
+  const Tree& t = h->tree;
+  h->rcols.assign(t.L, 0);
+  h->off.assign(t.L, 0);
+  int R = 0;
+  for (int q = 1; q <= t.L; ++q) {
+    int rq = 0;
+    for (int i = 0; i < (1 << q); ++i) rq = std::max(rq, h->rank[node_id(q, i)]);
+    h->rcols[q - 1] = rq;
+    h->off[q - 1] = R;
+    R += rq;
+  }
+  h->R = R;
+  HODLR_TRY(h->Y.ensure((size_t)t.n * std::max(R, 1) * h->esize));
+  HODLR_TRY(h->W.ensure((size_t)t.n * std::max(R, 1) * h->esize));
+  // inverse capacitance matrices, per parent level p: 2^p nodes of (2 r_{p+1})^2
+  h->sinv_off.assign(t.L, 0);
+  size_t tot = 0;
+  for (int p = 0; p < t.L; ++p) {
+    h->sinv_off[p] = tot;
+    size_t rq = h->rcols[p];
+    tot += (size_t)(1 << p) * (2 * rq) * (2 * rq);
+  }
+  HODLR_TRY(h->Sinv.ensure(std::max<size_t>(tot, 1) * h->esize));
+  return ensure_work(h, 8);
+}
+
+}  // namespace hodlr
+
+using namespace hodlr;
+
+extern "C" {
+
+void hodlr_default_opts(hodlr_opts* o) {
+  if (!o) return;
+  o->leaf = 128;
+  o->tol = 1e-4;
+  o->method = HODLR_ACA;
+  o->bdlr_depth = 1;
+  o->max_rank = 0;
+  o->precision = 32;
+}
+
+const char* hodlr_last_error(void) { return g_last_error.c_str(); }
+
+static int check_opts(const hodlr_opts& o) {
+  if (o.leaf < 1 || o.leaf > kLeafMax)
+    return fail(HODLR_EINVAL, "opts.leaf must be in [1, " + std::to_string(kLeafMax) + "]");
+  if (!(o.tol >= 0.0) || !std::isfinite(o.tol)) return fail(HODLR_EINVAL, "opts.tol must be >= 0");
+  if (o.method != HODLR_ACA && o.method != HODLR_BDLR)
+    return fail(HODLR_EINVAL, "opts.method must be HODLR_ACA or HODLR_BDLR");
+  if (o.precision != 32 && o.precision != 64)
+    return fail(HODLR_EINVAL, "opts.precision must be 32 or 64");
+  if (o.max_rank < 0) return fail(HODLR_EINVAL, "opts.max_rank must be >= 0");
+  if (o.method == HODLR_BDLR && o.bdlr_depth < 1)
+    return fail(HODLR_EINVAL, "opts.bdlr_depth must be >= 1");
+  return HODLR_OK;
+}
+
+int hodlr_build(const double* K, int n, int ldk, const int* g_rowptr, const int* g_col,
+                const hodlr_opts* opts, hipStream_t stream, hodlr_t* out) {
+  if (!out) return fail(HODLR_EINVAL, "out is NULL");
+  *out = nullptr;
+  hodlr_opts o;
+  hodlr_default_opts(&o);
+  if (opts) o = *opts;
+  if (!K) return fail(HODLR_EINVAL, "K is NULL");
+  if (n < 1 || n > kMaxN) return fail(HODLR_EINVAL, "n out of range");
+  if (ldk < n) return fail(HODLR_EINVAL, "ldk < n");
+  HODLR_TRY(check_opts(o));
+  if (o.method == HODLR_BDLR && (!g_rowptr || !g_col))
+    return fail(HODLR_EINVAL, "BDLR needs the separator graph (g_rowptr, g_col)");
+  if (o.method == HODLR_BDLR) return fail(HODLR_EINVAL, "BDLR compression is not built yet");
+  std::unique_ptr<hodlr_s> h(new hodlr_s());
+  h->method = o.method;
+  h->depth = o.bdlr_depth;
+  h->max_rank = o.max_rank;
+  h->tol = o.tol;
+  HODLR_TRY(init_handle(h.get(), n, o.leaf, o.precision));
+  const Tree& t = h->tree;
+  // a1: leaf blocks to the factorization precision
+  HODLR_TRY(launch_stage_leaves_from_K(h.get(), K, ldk, stream));
+  if (t.L > 0) {
+    int cap = rank_cap(o.precision);
+    if (o.max_rank > 0) cap = std::min(cap, o.max_rank);
+    std::vector<int> capq(t.L), capoff(t.L);
+    int C = 0;
+    for (int q = 1; q <= t.L; ++q) {
+      capq[q - 1] = std::min(cap, t.min_size(q));
+      capoff[q - 1] = C;
+      C += capq[q - 1];
+    }
+    DevBuf Ucap, Vcap;
+    HODLR_TRY(Ucap.ensure((size_t)n * C * h->esize));
+    HODLR_TRY(Vcap.ensure((size_t)n * C * h->esize));
+    HODLR_HIP(hipMemsetAsync(Ucap.p, 0, (size_t)n * C * h->esize, stream));
+    HODLR_HIP(hipMemsetAsync(Vcap.p, 0, (size_t)n * C * h->esize, stream));
+    // a2: compression of every off-diagonal block
+    HODLR_TRY(launch_aca(h.get(), K, ldk, Ucap.p, Vcap.p, capoff, capq, stream));
+    HODLR_HIP(hipMemcpyAsync(h->rank.data(), h->d_rank.p, t.nnodes() * sizeof(int),
+                             hipMemcpyDeviceToHost, stream));
+    HODLR_HIP(hipStreamSynchronize(stream));
+    int st[4];
+    HODLR_HIP(hipMemcpy(st, h->status.p, sizeof(st), hipMemcpyDeviceToHost));
+    if (st[2]) return fail(HODLR_EHIP, "ACA workgroup barrier timed out");
+    h->rank[0] = 0;
+    HODLR_TRY(set_layout_from_ranks(h.get()));
+    HODLR_TRY(launch_repack(h.get(), Ucap.p, Vcap.p, n, capoff, stream));
+    HODLR_HIP(hipStreamSynchronize(stream));  // Ucap/Vcap are freed on return
+  } else {
+    HODLR_TRY(set_layout_from_ranks(h.get()));
+  }
+  *out = h.release();
+  return HODLR_OK;
+}
+
+int hodlr_build_from_factors(int n, int leaf, int precision, const double* leaves,
+                             const double* Upanel, const double* Vpanel, const int* ranks,
+                             const int* rcols, int nlevels, hipStream_t stream, hodlr_t* out) {
+  if (!out) return fail(HODLR_EINVAL, "out is NULL");
+  *out = nullptr;
+  if (n < 1 || n > kMaxN) return fail(HODLR_EINVAL, "n out of range");
+  if (leaf < 1 || leaf > kLeafMax) return fail(HODLR_EINVAL, "leaf out of range");
+  if (precision != 32 && precision != 64) return fail(HODLR_EINVAL, "precision must be 32 or 64");
+  if (!leaves) return fail(HODLR_EINVAL, "leaves is NULL");
+  {
+    Tree t0;
+    t0.build(n, leaf);
+    if (nlevels != t0.L)
+      return fail(HODLR_EINVAL, "nlevels = " + std::to_string(nlevels) + " but the tree has " +
+                                    std::to_string(t0.L) + " levels");
+    if (t0.L > 0 && (!Upanel || !Vpanel || !ranks || !rcols))
+      return fail(HODLR_EINVAL, "panels, ranks and rcols are required when L > 0");
+  }
+  std::unique_ptr<hodlr_s> h(new hodlr_s());
+  HODLR_TRY(init_handle(h.get(), n, leaf, precision));
+  const Tree& t = h->tree;
+  int cap = rank_cap(precision);
+  for (int q = 1; q <= t.L; ++q) {
+    if (rcols[q - 1] < 0 || rcols[q - 1] > cap || rcols[q - 1] > t.min_size(q))
+      return fail(HODLR_EINVAL, "rcols out of range at level " + std::to_string(q));
+    for (int i = 0; i < (1 << q); ++i) {
+      int r = ranks[node_id(q, i) - 1];
+      if (r < 0 || r > rcols[q - 1])
+        return fail(HODLR_EINVAL, "rank out of range at node " + std::to_string(node_id(q, i)));
+      h->rank[node_id(q, i)] = r;
+    }
+  }
+  // layout = the caller's column widths (they bound the ranks)
+  h->rcols.assign(rcols, rcols + t.L);
+  h->off.assign(t.L, 0);
+  int R = 0;
+  for (int q = 1; q <= t.L; ++q) {
+    h->off[q - 1] = R;
+    R += h->rcols[q - 1];
+  }
+  h->R = R;
+  HODLR_TRY(h->Y.ensure((size_t)n * std::max(R, 1) * h->esize));
+  HODLR_TRY(h->W.ensure((size_t)n * std::max(R, 1) * h->esize));
+  h->sinv_off.assign(t.L, 0);
+  size_t tot = 0;
+  for (int p = 0; p < t.L; ++p) {
+    h->sinv_off[p] = tot;
+    tot += (size_t)(1 << p) * (2 * (size_t)h->rcols[p]) * (2 * (size_t)h->rcols[p]);
+  }
+  HODLR_TRY(h->Sinv.ensure(std::max<size_t>(tot, 1) * h->esize));
+  HODLR_TRY(ensure_work(h.get(), 8));
+  HODLR_HIP(hipMemcpyAsync(h->d_rank.p, h->rank.data(), t.nnodes() * sizeof(int),
+                           hipMemcpyHostToDevice, stream));
+  HODLR_TRY(launch_stage_leaves_packed(h.get(), leaves, stream));
+  if (t.L > 0) HODLR_TRY(launch_from_f64_panels(h.get(), Upanel, Vpanel, stream));
+  HODLR_HIP(hipStreamSynchronize(stream));
+  *out = h.release();
+  return HODLR_OK;
+}
+
+int hodlr_factor(hodlr_t h, hipStream_t stream) {
+  if (!h) return fail(HODLR_EINVAL, "handle is NULL");
+  if (h->factored) return fail(HODLR_EINVAL, "handle is already factorized");
+  HODLR_TRY(factor_impl(h, stream));
+  HODLR_HIP(hipStreamSynchronize(stream));
+  int st[4];
+  HODLR_HIP(hipMemcpy(st, h->status.p, sizeof(st), hipMemcpyDeviceToHost));
+  if (st[0]) {
+    return fail(HODLR_ESINGULAR, st[0] == 1 ? "singular leaf block " + std::to_string(st[1])
+                                            : "singular capacitance matrix at node " +
+                                                  std::to_string(st[1]));
+  }
+  h->factored = true;
+  return HODLR_OK;
+}
+
+int hodlr_solve(hodlr_t h, const void* B, int nrhs, int ldb, void* X, int ldx,
+                hipStream_t stream) {
+  if (!h) return fail(HODLR_EINVAL, "handle is NULL");
+  if (!h->factored) return fail(HODLR_EINVAL, "call hodlr_factor first");
+  int n = h->tree.n;
+  if (nrhs < 0) return fail(HODLR_EINVAL, "nrhs < 0");
+  if (nrhs == 0) return HODLR_OK;
+  if (!B || !X) return fail(HODLR_EINVAL, "B or X is NULL");
+  if (ldb < n || ldx < n) return fail(HODLR_EINVAL, "ldb or ldx < n");
+  if (B != X) {
+    HODLR_HIP(hipMemcpy2DAsync(X, (size_t)ldx * h->esize, B, (size_t)ldb * h->esize,
+                               (size_t)n * h->esize, nrhs, hipMemcpyDeviceToDevice, stream));
+  } else if (ldb != ldx) {
+    return fail(HODLR_EINVAL, "aliased B and X need ldb == ldx");
+  }
+  return apply_impl(h, X, ldx, nrhs, stream);
+}
+
+int gmres_solve(const double* K, int n, int ldk, hodlr_t precond, const double* B, int nrhs,
+                int ldb, double* X, int ldx, double tol, int maxit, int restart, int* iters,
+                double* relres, hipStream_t stream) {
+  if (!K || !B || !X) return fail(HODLR_EINVAL, "K, B or X is NULL");
+  if (n < 1 || n > kMaxN) return fail(HODLR_EINVAL, "n out of range");
+  if (ldk < n || ldb < n || ldx < n) return fail(HODLR_EINVAL, "leading dimension < n");
+  if (nrhs < 1 || nrhs > 64) return fail(HODLR_EINVAL, "nrhs must be in [1, 64]");
+  if (!(tol > 0.0)) return fail(HODLR_EINVAL, "tol must be > 0");
+  if (maxit < 1 || restart < 1) return fail(HODLR_EINVAL, "maxit and restart must be >= 1");
+  if (!iters || !relres) return fail(HODLR_EINVAL, "iters or relres is NULL");
+  if (precond) {
+    if (!precond->factored) return fail(HODLR_EINVAL, "preconditioner is not factorized");
+    if (precond->tree.n != n) return fail(HODLR_EINVAL, "preconditioner size differs from n");
+  }
+  return gmres_impl(K, n, ldk, precond, B, nrhs, ldb, X, ldx, tol, maxit, restart, iters, relres,
+                    stream);
+}
+
+int hodlr_order_rcb(const float* coords, int n, int leaf, int* perm, hipStream_t stream) {
+  if (!coords || !perm) return fail(HODLR_EINVAL, "coords or perm is NULL");
+  if (n < 1 || n > 16384) return fail(HODLR_EINVAL, "n must be in [1, 16384]");
+  if (leaf < 1) return fail(HODLR_EINVAL, "leaf must be >= 1");
+  Tree t;
+  t.build(n, leaf);
+  return launch_rcb(coords, n, t, perm, stream);
+}
+
+int hodlr_permute(const double* Kin, int n, int ldi, const int* perm, double* Kout, int ldo,
+                  hipStream_t stream) {
+  if (!Kin || !Kout || !perm) return fail(HODLR_EINVAL, "NULL pointer");
+  if (n < 1 || ldi < n || ldo < n) return fail(HODLR_EINVAL, "bad size");
+  if (Kin == Kout) return fail(HODLR_EINVAL, "Kin and Kout must not overlap");
+  return launch_permute(Kin, n, ldi, perm, Kout, ldo, stream);
+}
+
+int hodlr_permute_graph(const int* rowptr, const int* col, int n, const int* perm,
+                        int* rowptr_out, int* col_out, hipStream_t stream) {
+  if (!rowptr || !col || !perm || !rowptr_out || !col_out) return fail(HODLR_EINVAL, "NULL pointer");
+  if (n < 1) return fail(HODLR_EINVAL, "n < 1");
+  return launch_permute_graph(rowptr, col, n, perm, rowptr_out, col_out, stream);
+}
+
+int hodlr_stats(hodlr_t h, int* nlevels, int* ranks, int* rcols) {
+  if (!h) return fail(HODLR_EINVAL, "handle is NULL");
+  const Tree& t = h->tree;
+  if (nlevels) *nlevels = t.L;
+  if (ranks)
+    for (int id = 1; id < t.nnodes(); ++id) ranks[id - 1] = h->rank[id];
+  if (rcols)
+    for (int q = 0; q < t.L; ++q) rcols[q] = h->rcols[q];
+  return HODLR_OK;
+}
+
+int hodlr_get_factors(hodlr_t h, double* Upanel, double* Vpanel, hipStream_t stream) {
+  if (!h) return fail(HODLR_EINVAL, "handle is NULL");
+  if (h->factored) return fail(HODLR_EINVAL, "factors are overwritten by hodlr_factor");
+  if (!Upanel || !Vpanel) return fail(HODLR_EINVAL, "NULL pointer");
+  if (h->tree.L == 0 || h->R == 0) return HODLR_OK;
+  return launch_to_f64_panels(h, Upanel, Vpanel, stream);
+}
+
+int hodlr_destroy(hodlr_t h) {
+  delete h;
+  return HODLR_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,516 @@
+// HODLR factorization and solve (Sec. 4.3), level by level on the GPU.
+//
+// Storage (T = float or double, column-major, leading dimension n):
+//   Y  n x R  column block q (offset off[q-1], width rcols[q-1]) holds, in the
+//             rows of each level-q node c, U_c; the factorization overwrites
+//             it with d_c = K_c^-1 U_c and, in the columns of the blocks
+//             above q, with the partially solved ancestor panels.
+//   W  n x R  column block q holds, in the rows of the sibling of c, V_c, so
+//             K(c, sibling) = U_c V_c^T.
+//   Kinv      leaf inverses from an LU with partial pivoting (Gauss-Jordan).
+//   Sinv      per internal node, the inverse of the capacitance matrix
+//             S = [[I, V_b^T d_a], [V_a^T d_b, I]] (eq. SchurSum), stored for
+//             the ranks (r_b + r_a) with leading dimension 2 r_q.
+//
+// With the leaf inverses applied to every column of Y at once (the stacked
+// right-hand sides Z = [U | ancestor U] of Sec. 4.3.1 step 2-3), each level q,
+// from the leaves up, needs for every node c of level q the products
+// G_c = W_c^T Y_c (giving V^T d and V^T c at once), then per parent the
+// capacitance inverse and y = S^-1 [V_b^T c_a; V_a^T c_b], and finally the
+// corrections c_a -= d_a y_b, c_b -= d_b y_a (step 5).  The solve (Sec. 4.3.2)
+// runs the same three kernels on the right-hand side after the leaf solve.
+#include <algorithm>
+#include <string>
+
+#include "device_util.h"
+#include "hodlr_internal.h"
+
+namespace hodlr {
+
+// ---------------------------------------------------------------------------
+// Staging
+// ---------------------------------------------------------------------------
+template <typename T>
+__global__ void k_stage_leaves_K(const double* __restrict__ K, int ldk, const int* __restrict__ lo,
+                                 const int* __restrict__ hi, int id0, int bmax, T* __restrict__ out) {
+  const int leaf = blockIdx.y, id = id0 + leaf;
+  const int l0 = lo[id], b = hi[id] - l0;
+  T* o = out + (size_t)leaf * bmax * bmax;
+  for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < b * b; e += gridDim.x * blockDim.x) {
+    const int i = e % b, j = e / b;
+    o[i + (size_t)j * bmax] = (T)K[(size_t)(l0 + j) * ldk + l0 + i];
+  }
+}
+
+template <typename T>
+__global__ void k_stage_leaves_packed(const double* __restrict__ leaves, const int* __restrict__ lo,
+                                      const int* __restrict__ hi, int id0, int bmax,
+                                      T* __restrict__ out) {
+  const int leaf = blockIdx.y, id = id0 + leaf;
+  size_t base = 0;
+  for (int k = 0; k < leaf; ++k) {
+    const size_t bk = hi[id0 + k] - lo[id0 + k];
+    base += bk * bk;
+  }
+  const int b = hi[id] - lo[id];
+  T* o = out + (size_t)leaf * bmax * bmax;
+  for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < b * b; e += gridDim.x * blockDim.x) {
+    const int i = e % b, j = e / b;
+    o[i + (size_t)j * bmax] = (T)leaves[base + i + (size_t)j * b];
+  }
+}
+
+template <typename S, typename D>
+__global__ void k_convert(const S* __restrict__ src, D* __restrict__ dst, size_t count) {
+  for (size_t e = blockIdx.x * (size_t)blockDim.x + threadIdx.x; e < count;
+       e += (size_t)gridDim.x * blockDim.x)
+    dst[e] = (D)src[e];
+}
+
+// ---------------------------------------------------------------------------
+// Leaf LU (partial pivoting) kept as the explicit inverse
+// ---------------------------------------------------------------------------
+template <typename T>
+__global__ void __launch_bounds__(kBlock)
+    k_leaf_inverse(T* __restrict__ Kinv, int bmax, const int* __restrict__ lo,
+                   const int* __restrict__ hi, int id0, int* __restrict__ status) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  T* A = reinterpret_cast<T*>(smem);
+  __shared__ int ipiv[kLeafMax], src[kLeafMax];
+  __shared__ T colk[kLeafMax];
+  __shared__ T sv[kBlock / 64];
+  __shared__ int si[kBlock / 64];
+  const int leaf = blockIdx.x, id = id0 + leaf, t = threadIdx.x;
+  const int b = hi[id] - lo[id], ld = b + 1;
+  T* Gm = Kinv + (size_t)leaf * bmax * bmax;
+  for (int e = t; e < b * b; e += blockDim.x) A[e % b + (e / b) * ld] = Gm[e % b + (size_t)(e / b) * bmax];
+  __syncthreads();
+  const bool ok = gj_inverse(A, b, ld, ipiv, src, colk, sv, si);
+  if (!ok) {
+    if (t == 0) {
+      atomicExch(status + 0, 1);
+      atomicExch(status + 1, id);
+    }
+    return;
+  }
+  for (int e = t; e < b * b; e += blockDim.x) {
+    const int i = e % b, j = e / b;
+    Gm[i + (size_t)j * bmax] = A[i + src[j] * ld];
+  }
+}
+
+// Z(rows of leaf, c0 : c0+CT) = Kinv_leaf * Z(rows of leaf, c0 : c0+CT), in place.
+template <typename T, int CT>
+__global__ void __launch_bounds__(kBlock)
+    k_leaf_apply(const T* __restrict__ Kinv, int bmax, const int* __restrict__ lo,
+                 const int* __restrict__ hi, int id0, T* __restrict__ Z, int ldz, int ncols) {
+  __shared__ T Zt[kLeafMax * CT];
+  const int leaf = blockIdx.x, c0 = blockIdx.y * CT, id = id0 + leaf, t = threadIdx.x;
+  const int l0 = lo[id], b = hi[id] - l0;
+  const int nc = min(CT, ncols - c0);
+  const T* Ki = Kinv + (size_t)leaf * bmax * bmax;
+  for (int e = t; e < b * CT; e += blockDim.x) {
+    const int i = e % b, c = e / b;
+    Zt[i + c * b] = (c < nc) ? Z[(size_t)(c0 + c) * ldz + l0 + i] : T(0);
+  }
+  __syncthreads();
+  for (int i = t; i < b; i += blockDim.x) {
+    T acc[CT];
+#pragma unroll
+    for (int c = 0; c < CT; ++c) acc[c] = T(0);
+    for (int kk = 0; kk < b; ++kk) {
+      const T a = Ki[i + (size_t)kk * bmax];
+#pragma unroll
+      for (int c = 0; c < CT; ++c) acc[c] += a * Zt[kk + c * b];
+    }
+    for (int c = 0; c < nc; ++c) Z[(size_t)(c0 + c) * ldz + l0 + i] = acc[c];
+  }
+}
+
+// ---------------------------------------------------------------------------
+// G_c = W(rows c, wcol0 : wcol0+rq)^T * Z(rows c, 0 : zcols) for every node c
+// of one level; G_c is rq x zcols (ld rq), node stride rq * zcols.
+// ---------------------------------------------------------------------------
+template <typename T>
+__global__ void __launch_bounds__(kBlock)
+    k_panel_tn(const T* __restrict__ W, int ldw, int wcol0, int rq, const T* __restrict__ Z,
+               int ldz, int zcols, const int* __restrict__ lo, const int* __restrict__ hi, int id0,
+               T* __restrict__ G) {
+  constexpr int TR = 64, TM = 64, KC = 16;
+  __shared__ T Ws[KC][TR + 1];
+  __shared__ T Zs[KC][TM + 1];
+  const int node = blockIdx.x, id = id0 + node, r0 = blockIdx.y * TR, m0 = blockIdx.z * TM;
+  const int t = threadIdx.x, tx = t % 16, ty = t / 16;
+  const int l0 = lo[id], len = hi[id] - l0;
+  T acc[4][4];
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int c = 0; c < 4; ++c) acc[a][c] = T(0);
+  for (int k0 = 0; k0 < len; k0 += KC) {
+    for (int e = t; e < KC * TR; e += blockDim.x) {
+      const int kk = e % KC, r = e / KC, row = k0 + kk, col = r0 + r;
+      Ws[kk][r] = (row < len && col < rq) ? W[(size_t)(wcol0 + col) * ldw + l0 + row] : T(0);
+      const int m = m0 + r;
+      Zs[kk][r] = (row < len && m < zcols) ? Z[(size_t)m * ldz + l0 + row] : T(0);
+    }
+    __syncthreads();
+#pragma unroll
+    for (int kk = 0; kk < KC; ++kk) {
+      T a[4], z[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        a[u] = Ws[kk][tx + 16 * u];
+        z[u] = Zs[kk][ty + 16 * u];
+      }
+#pragma unroll
+      for (int u = 0; u < 4; ++u)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) acc[u][v] += a[u] * z[v];
+    }
+    __syncthreads();
+  }
+  T* Gc = G + (size_t)node * rq * zcols;
+#pragma unroll
+  for (int u = 0; u < 4; ++u)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int r = r0 + tx + 16 * u, m = m0 + ty + 16 * v;
+      if (r < rq && m < zcols) Gc[r + (size_t)m * rq] = acc[u][v];
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Inverse capacitance matrix of every parent of level q (one workgroup each).
+// With A = V_b^T d_a (r_b x r_a) and B = V_a^T d_b (r_a x r_b) read from the
+// d-columns of G, S = [[I, A], [B, I]] and, with M = I - B A,
+//   S^-1 = [[I + A M^-1 B, -A M^-1], [-M^-1 B, M^-1]].
+// ---------------------------------------------------------------------------
+template <typename T>
+__global__ void __launch_bounds__(kBlock)
+    k_schur_form(const T* __restrict__ G, int rq, int gcols, int offq, const int* __restrict__ rank,
+                 int q, T* __restrict__ Sinv, int* __restrict__ status) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  T* M = reinterpret_cast<T*>(smem);
+  __shared__ int ipiv[kLeafMax], src[kLeafMax];
+  __shared__ T colk[kLeafMax];
+  __shared__ T sv[kBlock / 64];
+  __shared__ int si[kBlock / 64];
+  const int i = blockIdx.x, t = threadIdx.x, nt = blockDim.x;
+  const int a = node_id(q, 2 * i), b = node_id(q, 2 * i + 1);
+  const int ra = rank[a], rb = rank[b], ldm = ra + 1, lds = 2 * rq;
+  const T* Ga = G + (size_t)(2 * i) * rq * gcols;
+  const T* Gb = G + (size_t)(2 * i + 1) * rq * gcols;
+  auto Am = [&](int x, int y) { return Ga[x + (size_t)(offq + y) * rq]; };  // r_b x r_a
+  auto Bm = [&](int x, int y) { return Gb[x + (size_t)(offq + y) * rq]; };  // r_a x r_b
+  T* S = Sinv + (size_t)i * lds * lds;
+  for (int e = t; e < ra * ra; e += nt) {
+    const int x = e % ra, y = e / ra;
+    T s = (x == y) ? T(1) : T(0);
+    for (int z = 0; z < rb; ++z) s -= Bm(x, z) * Am(z, y);
+    M[x + y * ldm] = s;
+  }
+  __syncthreads();
+  if (ra > 0) {
+    const bool ok = gj_inverse(M, ra, ldm, ipiv, src, colk, sv, si);
+    if (!ok) {
+      if (t == 0) {
+        atomicExch(status + 0, 2);
+        atomicExch(status + 1, node_id(q - 1, i));
+      }
+      return;
+    }
+  }
+  auto Mi = [&](int x, int y) { return M[x + src[y] * ldm]; };  // M^-1
+  // S[rb + x, rb + y] = M^-1 ; S[rb + x, y] = -M^-1 B ; S[x, rb + y] = -A M^-1
+  for (int e = t; e < ra * ra; e += nt) {
+    const int x = e % ra, y = e / ra;
+    S[(rb + x) + (size_t)(rb + y) * lds] = Mi(x, y);
+  }
+  for (int e = t; e < ra * rb; e += nt) {
+    const int x = e % ra, y = e / ra;
+    T s = 0;
+    for (int z = 0; z < ra; ++z) s += Mi(x, z) * Bm(z, y);
+    S[(rb + x) + (size_t)y * lds] = -s;
+  }
+  for (int e = t; e < rb * ra; e += nt) {
+    const int x = e % rb, y = e / rb;
+    T s = 0;
+    for (int z = 0; z < ra; ++z) s += Am(x, z) * Mi(z, y);
+    S[x + (size_t)(rb + y) * lds] = -s;
+  }
+  __syncthreads();
+  // S[x, y] = I - A * S[rb : rb+ra, y]   (= I + A M^-1 B)
+  for (int e = t; e < rb * rb; e += nt) {
+    const int x = e % rb, y = e / rb;
+    T s = (x == y) ? T(1) : T(0);
+    for (int z = 0; z < ra; ++z) s -= Am(x, z) * S[(rb + z) + (size_t)y * lds];
+    S[x + (size_t)y * lds] = s;
+  }
+}
+
+// y = S^-1 [t_a; t_b] for every parent of level q: t_a = G_a(0:r_b, 0:ccols),
+// t_b = G_b(0:r_a, 0:ccols).  Y is (2 rq) x ccols per parent (ld 2 rq).
+template <typename T, int CT>
+__global__ void __launch_bounds__(kBlock)
+    k_schur_apply(const T* __restrict__ G, int rq, int gcols, int ccols, const int* __restrict__ rank,
+                  int q, const T* __restrict__ Sinv, T* __restrict__ Yb) {
+  __shared__ T Tc[2 * kRankCap32 * CT];
+  const int i = blockIdx.x, c0 = blockIdx.y * CT, t = threadIdx.x, nt = blockDim.x;
+  const int ra = rank[node_id(q, 2 * i)], rb = rank[node_id(q, 2 * i + 1)], r = ra + rb;
+  const int lds = 2 * rq, nc = min(CT, ccols - c0);
+  const T* Ga = G + (size_t)(2 * i) * rq * gcols;
+  const T* Gb = G + (size_t)(2 * i + 1) * rq * gcols;
+  for (int e = t; e < r * CT; e += nt) {
+    const int z = e % r, c = e / r;
+    T v = T(0);
+    if (c < nc) v = (z < rb) ? Ga[z + (size_t)(c0 + c) * rq] : Gb[(z - rb) + (size_t)(c0 + c) * rq];
+    Tc[z + c * r] = v;
+  }
+  __syncthreads();
+  const T* S = Sinv + (size_t)i * lds * lds;
+  T* Y = Yb + (size_t)i * lds * ccols;
+  for (int x = t; x < r; x += nt) {
+    T acc[CT];
+#pragma unroll
+    for (int c = 0; c < CT; ++c) acc[c] = T(0);
+    for (int z = 0; z < r; ++z) {
+      const T s = S[x + (size_t)z * lds];
+#pragma unroll
+      for (int c = 0; c < CT; ++c) acc[c] += s * Tc[z + c * r];
+    }
+    for (int c = 0; c < nc; ++c) Y[x + (size_t)(c0 + c) * lds] = acc[c];
+  }
+}
+
+// Z(rows c, 0:zcols) -= d_c * y_other for every node c of level q, where d_c =
+// Y(rows c, offq : offq + r_c) and y_other is the part of the parent's y that
+// multiplies it: y_b (rows r_b .. r_b + r_a) for a left child, y_a (rows
+// 0 .. r_b) for a right child.
+template <typename T, int CT>
+__global__ void __launch_bounds__(kBlock)
+    k_correct(const T* __restrict__ Yd, int ldy, int offq, T* __restrict__ Z, int ldz, int zcols,
+              const T* __restrict__ Yb, int rq, const int* __restrict__ lo,
+              const int* __restrict__ hi, const int* __restrict__ rank, int q) {
+  __shared__ T Yo[kRankCap32 * CT];
+  const int c = blockIdx.x, par = c >> 1, left = (c & 1) == 0, t = threadIdx.x;
+  const int id = node_id(q, c);
+  const int ra = rank[node_id(q, 2 * par)], rb = rank[node_id(q, 2 * par + 1)];
+  const int rc = left ? ra : rb, yoff = left ? rb : 0, lds = 2 * rq;
+  const int c0 = blockIdx.z * CT, nc = min(CT, zcols - c0);
+  const T* Yp = Yb + (size_t)par * lds * zcols;
+  for (int e = t; e < rc * CT; e += blockDim.x) {
+    const int l = e % rc, k = e / rc;
+    Yo[l + k * rc] = (k < nc) ? Yp[(yoff + l) + (size_t)(c0 + k) * lds] : T(0);
+  }
+  __syncthreads();
+  const int row = lo[id] + blockIdx.y * blockDim.x + t;
+  if (row >= hi[id] || rc == 0) return;
+  T acc[CT];
+#pragma unroll
+  for (int k = 0; k < CT; ++k) acc[k] = T(0);
+  for (int l = 0; l < rc; ++l) {
+    const T d = Yd[(size_t)(offq + l) * ldy + row];
+#pragma unroll
+    for (int k = 0; k < CT; ++k) acc[k] += d * Yo[l + k * rc];
+  }
+  for (int k = 0; k < nc; ++k) Z[(size_t)(c0 + k) * ldz + row] -= acc[k];
+}
+
+// ---------------------------------------------------------------------------
+// Host side
+// ---------------------------------------------------------------------------
+static inline int cdiv(int a, int b) { return (a + b - 1) / b; }
+
+template <typename F>
+static int allow_lds(F kernel, size_t bytes) {
+  if (bytes > 64 * 1024)
+    HODLR_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(kernel),
+                                  hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes));
+  return HODLR_OK;
+}
+
+int ensure_work(hodlr_s* h, int ncols) {
+  const Tree& t = h->tree;
+  ncols = std::max(ncols, 64);
+  size_t g = 1, y = 1;
+  for (int q = 1; q <= t.L; ++q) {
+    size_t rq = h->rcols.empty() ? 0 : h->rcols[q - 1];
+    size_t offq = h->off.empty() ? 0 : h->off[q - 1];
+    g = std::max(g, (size_t)(1 << q) * rq * std::max<size_t>(offq + rq, ncols));
+    y = std::max(y, (size_t)(1 << (q - 1)) * 2 * rq * std::max<size_t>(offq, ncols));
+  }
+  HODLR_TRY(h->G.ensure(g * h->esize));
+  HODLR_TRY(h->Ybuf.ensure(y * h->esize));
+  return HODLR_OK;
+}
+
+template <typename T>
+static int stage_from_K(hodlr_s* h, const double* K, int ldk, hipStream_t s) {
+  const Tree& t = h->tree;
+  dim3 grid(cdiv(h->bmax * h->bmax, kBlock), h->nleaf);
+  k_stage_leaves_K<T><<<grid, kBlock, 0, s>>>(K, ldk, h->d_lo.as<int>(), h->d_hi.as<int>(),
+                                              node_id(t.L, 0), h->bmax, h->Kinv.as<T>());
+  HODLR_HIP(hipGetLastError());
+  return HODLR_OK;
+}
+
+int launch_stage_leaves_from_K(hodlr_s* h, const double* K, int ldk, hipStream_t s) {
+  return h->precision == 64 ? stage_from_K<double>(h, K, ldk, s) : stage_from_K<float>(h, K, ldk, s);
+}
+
+template <typename T>
+static int stage_packed(hodlr_s* h, const double* leaves, hipStream_t s) {
+  const Tree& t = h->tree;
+  dim3 grid(cdiv(h->bmax * h->bmax, kBlock), h->nleaf);
+  k_stage_leaves_packed<T><<<grid, kBlock, 0, s>>>(leaves, h->d_lo.as<int>(), h->d_hi.as<int>(),
+                                                   node_id(t.L, 0), h->bmax, h->Kinv.as<T>());
+  HODLR_HIP(hipGetLastError());
+  return HODLR_OK;
+}
+
+int launch_stage_leaves_packed(hodlr_s* h, const double* leaves, hipStream_t s) {
+  return h->precision == 64 ? stage_packed<double>(h, leaves, s) : stage_packed<float>(h, leaves, s);
+}
+
+int launch_repack(hodlr_s* h, const void* Ucap, const void* Vcap, int ldcap,
+                  const std::vector<int>& capoff, hipStream_t s) {
+  const Tree& t = h->tree;
+  const size_t n = t.n, es = h->esize;
+  for (int q = 1; q <= t.L; ++q) {
+    const size_t rq = h->rcols[q - 1];
+    if (rq == 0) continue;
+    const char* us = static_cast<const char*>(Ucap) + (size_t)capoff[q - 1] * ldcap * es;
+    const char* vs = static_cast<const char*>(Vcap) + (size_t)capoff[q - 1] * ldcap * es;
+    char* ud = static_cast<char*>(h->Y.p) + (size_t)h->off[q - 1] * n * es;
+    char* vd = static_cast<char*>(h->W.p) + (size_t)h->off[q - 1] * n * es;
+    HODLR_HIP(hipMemcpy2DAsync(ud, n * es, us, (size_t)ldcap * es, n * es, rq,
+                               hipMemcpyDeviceToDevice, s));
+    HODLR_HIP(hipMemcpy2DAsync(vd, n * es, vs, (size_t)ldcap * es, n * es, rq,
+                               hipMemcpyDeviceToDevice, s));
+  }
+  return HODLR_OK;
+}
+
+template <typename S, typename D>
+static int convert(const S* src, D* dst, size_t count, hipStream_t s) {
+  if (count == 0) return HODLR_OK;
+  const int grid = (int)std::min<size_t>((count + kBlock - 1) / kBlock, 4096);
+  k_convert<S, D><<<grid, kBlock, 0, s>>>(src, dst, count);
+  HODLR_HIP(hipGetLastError());
+  return HODLR_OK;
+}
+
+int launch_from_f64_panels(hodlr_s* h, const double* Up, const double* Vp, hipStream_t s) {
+  const size_t cnt = (size_t)h->tree.n * h->R;
+  if (h->precision == 64) {
+    HODLR_HIP(hipMemcpyAsync(h->Y.p, Up, cnt * 8, hipMemcpyDeviceToDevice, s));
+    HODLR_HIP(hipMemcpyAsync(h->W.p, Vp, cnt * 8, hipMemcpyDeviceToDevice, s));
+    return HODLR_OK;
+  }
+  HODLR_TRY(convert(Up, h->Y.as<float>(), cnt, s));
+  return convert(Vp, h->W.as<float>(), cnt, s);
+}
+
+int launch_to_f64_panels(hodlr_s* h, double* Up, double* Vp, hipStream_t s) {
+  const size_t cnt = (size_t)h->tree.n * h->R;
+  if (h->precision == 64) {
+    HODLR_HIP(hipMemcpyAsync(Up, h->Y.p, cnt * 8, hipMemcpyDeviceToDevice, s));
+    HODLR_HIP(hipMemcpyAsync(Vp, h->W.p, cnt * 8, hipMemcpyDeviceToDevice, s));
+    return HODLR_OK;
+  }
+  HODLR_TRY(convert(h->Y.as<float>(), Up, cnt, s));
+  return convert(h->W.as<float>(), Vp, cnt, s);
+}
+
+constexpr int kCT = 8;  // columns per workgroup in the leaf / Woodbury kernels
+
+template <typename T>
+static int level_solve(hodlr_s* h, int q, T* Z, int ldz, int zcols, const T* G, int gcols,
+                       hipStream_t s) {
+  // y = S^-1 t for every parent, then the corrections of the level-q nodes
+  const Tree& t = h->tree;
+  const int rq = h->rcols[q - 1], offq = h->off[q - 1];
+  const T* Sinv = h->Sinv.as<T>() + h->sinv_off[q - 1];
+  T* Yb = h->Ybuf.as<T>();
+  k_schur_apply<T, kCT><<<dim3(1 << (q - 1), cdiv(zcols, kCT)), kBlock, 0, s>>>(
+      G, rq, gcols, zcols, h->d_rank.as<int>(), q, Sinv, Yb);
+  HODLR_HIP(hipGetLastError());
+  k_correct<T, kCT><<<dim3(1 << q, cdiv(t.max_size(q), kBlock), cdiv(zcols, kCT)), kBlock, 0, s>>>(
+      h->Y.as<T>(), t.n, offq, Z, ldz, zcols, Yb, rq, h->d_lo.as<int>(), h->d_hi.as<int>(),
+      h->d_rank.as<int>(), q);
+  HODLR_HIP(hipGetLastError());
+  return HODLR_OK;
+}
+
+template <typename T>
+static int factor_t(hodlr_s* h, hipStream_t s) {
+  const Tree& t = h->tree;
+  const int n = t.n, L = t.L;
+  HODLR_HIP(hipMemsetAsync(h->status.p, 0, 4 * sizeof(int), s));
+  const size_t lds_leaf = (size_t)h->bmax * (h->bmax + 1) * sizeof(T);
+  HODLR_TRY(allow_lds(k_leaf_inverse<T>, lds_leaf));
+  k_leaf_inverse<T><<<h->nleaf, kBlock, lds_leaf, s>>>(h->Kinv.as<T>(), h->bmax, h->d_lo.as<int>(),
+                                                       h->d_hi.as<int>(), node_id(L, 0),
+                                                       h->status.as<int>());
+  HODLR_HIP(hipGetLastError());
+  if (L == 0 || h->R == 0) return HODLR_OK;
+  HODLR_TRY(ensure_work(h, 64));
+  T* Y = h->Y.as<T>();
+  const T* W = h->W.as<T>();
+  k_leaf_apply<T, kCT><<<dim3(h->nleaf, cdiv(h->R, kCT)), kBlock, 0, s>>>(
+      h->Kinv.as<T>(), h->bmax, h->d_lo.as<int>(), h->d_hi.as<int>(), node_id(L, 0), Y, n, h->R);
+  HODLR_HIP(hipGetLastError());
+  for (int q = L; q >= 1; --q) {
+    const int rq = h->rcols[q - 1], offq = h->off[q - 1];
+    if (rq == 0) continue;
+    const int zc = offq + rq;
+    T* G = h->G.as<T>();
+    k_panel_tn<T><<<dim3(1 << q, cdiv(rq, 64), cdiv(zc, 64)), kBlock, 0, s>>>(
+        W, n, offq, rq, Y, n, zc, h->d_lo.as<int>(), h->d_hi.as<int>(), node_id(q, 0), G);
+    HODLR_HIP(hipGetLastError());
+    const size_t lds_s = (size_t)rq * (rq + 1) * sizeof(T);
+    HODLR_TRY(allow_lds(k_schur_form<T>, lds_s));
+    k_schur_form<T><<<1 << (q - 1), kBlock, lds_s, s>>>(G, rq, zc, offq, h->d_rank.as<int>(), q,
+                                                         h->Sinv.as<T>() + h->sinv_off[q - 1],
+                                                         h->status.as<int>());
+    HODLR_HIP(hipGetLastError());
+    if (offq > 0) HODLR_TRY(level_solve<T>(h, q, Y, n, offq, G, zc, s));
+  }
+  return HODLR_OK;
+}
+
+int factor_impl(hodlr_s* h, hipStream_t s) {
+  return h->precision == 64 ? factor_t<double>(h, s) : factor_t<float>(h, s);
+}
+
+template <typename T>
+static int apply_t(hodlr_s* h, T* X, int ldx, int nrhs, hipStream_t s) {
+  const Tree& t = h->tree;
+  const int n = t.n, L = t.L;
+  for (int c0 = 0; c0 < nrhs; c0 += 64) {
+    const int nc = std::min(64, nrhs - c0);
+    T* Xc = X + (size_t)c0 * ldx;
+    k_leaf_apply<T, kCT><<<dim3(h->nleaf, cdiv(nc, kCT)), kBlock, 0, s>>>(
+        h->Kinv.as<T>(), h->bmax, h->d_lo.as<int>(), h->d_hi.as<int>(), node_id(L, 0), Xc, ldx, nc);
+    HODLR_HIP(hipGetLastError());
+    for (int q = L; q >= 1; --q) {
+      const int rq = h->rcols[q - 1], offq = h->off[q - 1];
+      if (rq == 0) continue;
+      T* G = h->G.as<T>();
+      k_panel_tn<T><<<dim3(1 << q, cdiv(rq, 64), cdiv(nc, 64)), kBlock, 0, s>>>(
+          h->W.as<T>(), n, offq, rq, Xc, ldx, nc, h->d_lo.as<int>(), h->d_hi.as<int>(),
+          node_id(q, 0), G);
+      HODLR_HIP(hipGetLastError());
+      HODLR_TRY(level_solve<T>(h, q, Xc, ldx, nc, G, nc, s));
+    }
+  }
+  return HODLR_OK;
+}
+
+int apply_impl(hodlr_s* h, void* X, int ldx, int nrhs, hipStream_t s) {
+  return h->precision == 64 ? apply_t<double>(h, static_cast<double*>(X), ldx, nrhs, s)
+                            : apply_t<float>(h, static_cast<float*>(X), ldx, nrhs, s);
+}
+
+}  // namespace hodlr

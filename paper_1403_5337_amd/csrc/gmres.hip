@@ -1,0 +1,411 @@
+// Flexible right-preconditioned GMRES in float64 (Sec. 3), s right-hand sides
+// at once, each with its own Krylov basis and its own convergence.
+//
+// Per step j, for every still-active right-hand side k:
+//   z_j = M^-1 v_j   (HODLR solve in the handle's precision, in place on the
+//                     z_j slot, which the previous step filled with v_j)
+//   w   = K z_j      (float64 split-K matrix product)
+//   classical Gram-Schmidt applied twice against v_0..v_j, the Hessenberg
+//   column, one Givens rotation, the residual estimate |g_{j+1}|;
+//   v_{j+1} = w / h_{j+1,j}.
+// A right-hand side stops taking steps when |g_{j+1}| <= tol |b| (or maxit,
+// or breakdown); at the end of a cycle x += Z y with H y = g, and the true
+// residual b - K x decides whether it restarts.
+//
+// Storage, all column-major with leading dimension n: basis vector j of
+// right-hand side k at V + (j s + k) n (so the s vectors of step j form one
+// n x s matrix), preconditioned vectors likewise in Z.
+#include <algorithm>
+#include <cmath>
+#include <mutex>
+
+#include "device_util.h"
+#include "hodlr_internal.h"
+
+namespace hodlr {
+
+constexpr int kRowsPerWG = 256;
+constexpr int kMatvecCols = 128;  // columns of K per workgroup (split-K)
+constexpr int kMaxRestart = 512;
+
+// part[(sp s + k) n + i] = sum over the columns c of split sp of K(i, c) src(c, k)
+template <typename TZ, int SMAX>
+__global__ void __launch_bounds__(kRowsPerWG)
+    k_matvec(const double* __restrict__ K, int ldk, int n, const TZ* __restrict__ src, int lds, int s,
+             double* __restrict__ part) {
+  __shared__ double zs[kMatvecCols * SMAX];
+  const int t = threadIdx.x, sp = blockIdx.y;
+  const int c0 = sp * kMatvecCols, cn = min(kMatvecCols, n - c0);
+  for (int e = t; e < cn * s; e += blockDim.x) {
+    const int c = e % cn, k = e / cn;
+    zs[c * SMAX + k] = (double)src[(size_t)k * lds + c0 + c];
+  }
+  __syncthreads();
+  const int i = blockIdx.x * kRowsPerWG + t;
+  if (i >= n) return;
+  double acc[SMAX];
+#pragma unroll
+  for (int k = 0; k < SMAX; ++k) acc[k] = 0.0;
+  const double* Kc = K + (size_t)c0 * ldk + i;
+  int c = 0;
+  for (; c + 8 <= cn; c += 8) {
+    double a[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) a[u] = __builtin_nontemporal_load(Kc + (size_t)(c + u) * ldk);
+#pragma unroll
+    for (int u = 0; u < 8; ++u)
+#pragma unroll
+      for (int k = 0; k < SMAX; ++k) acc[k] += a[u] * zs[(c + u) * SMAX + k];
+  }
+  for (; c < cn; ++c) {
+    const double a = Kc[(size_t)c * ldk];
+#pragma unroll
+    for (int k = 0; k < SMAX; ++k) acc[k] += a * zs[c * SMAX + k];
+  }
+#pragma unroll
+  for (int k = 0; k < SMAX; ++k)
+    if (k < s) part[((size_t)sp * s + k) * n + i] = acc[k];
+}
+
+// PASS 0: w = sum of the split-K partials (minus b when residual != 0), dots
+//         of w with v_0..v_j into hout
+// PASS 1: h = sum of hin over chunks; w -= V h; hcol = h; dots into hout
+// PASS 2: h = sum of hin; w -= V h; hcol += h; |w|^2 partial into npart
+// (the residual variant of PASS 0 takes no dots; it writes |b - K x|^2)
+template <int PASS>
+__global__ void __launch_bounds__(kRowsPerWG)
+    k_orth(int n, int s, int j, int m1, const double* __restrict__ V, double* __restrict__ w,
+           const double* __restrict__ part, int nsplit, const double* __restrict__ b, int ldb,
+           const double* __restrict__ hin, double* __restrict__ hout, double* __restrict__ hcol,
+           double* __restrict__ npart, const int* __restrict__ active) {
+  __shared__ double ws[kRowsPerWG];
+  __shared__ double hs[kMaxRestart + 1];
+  __shared__ double red[kRowsPerWG / 64];
+  const int k = blockIdx.y, ch = blockIdx.x, t = threadIdx.x, nt = blockDim.x;
+  if (!active[k]) return;
+  const int nch = gridDim.x;
+  const int i = ch * kRowsPerWG + t;
+  const bool valid = i < n;
+  double wi = 0.0;
+  if (PASS == 0) {
+    if (valid) {
+      for (int sp = 0; sp < nsplit; ++sp) wi += part[((size_t)sp * s + k) * n + i];
+      if (b) wi = b[(size_t)k * ldb + i] - wi;
+      w[(size_t)k * n + i] = wi;
+    }
+  } else {
+    for (int l = t; l <= j; l += nt) {
+      double h = 0.0;
+      for (int c = 0; c < nch; ++c) h += hin[((size_t)c * s + k) * m1 + l];
+      hs[l] = h;
+    }
+    __syncthreads();
+    if (ch == 0) {
+      for (int l = t; l <= j; l += nt) {
+        if (PASS == 1) hcol[(size_t)k * m1 + l] = hs[l];
+        else hcol[(size_t)k * m1 + l] += hs[l];
+      }
+    }
+    if (valid) {
+      wi = w[(size_t)k * n + i];
+      for (int l = 0; l <= j; ++l) wi -= V[((size_t)l * s + k) * n + i] * hs[l];
+      w[(size_t)k * n + i] = wi;
+    }
+  }
+  if (PASS == 2 || (PASS == 0 && b)) {
+    const double sq = block_sum(valid ? wi * wi : 0.0, red);
+    if (t == 0) npart[(size_t)ch * s + k] = sq;
+    return;
+  }
+  ws[t] = valid ? wi : 0.0;
+  __syncthreads();
+  const int wave = t >> 6, lane = t & 63, nw = nt >> 6;
+  const int r0 = ch * kRowsPerWG;
+  for (int l = wave; l <= j; l += nw) {
+    double d = 0.0;
+#pragma unroll
+    for (int r = 0; r < kRowsPerWG / 64; ++r) {
+      const int row = r0 + lane + 64 * r;
+      if (row < n) d += V[((size_t)l * s + k) * n + row] * ws[lane + 64 * r];
+    }
+    d = wave_sum(d);
+    if (lane == 0) hout[((size_t)ch * s + k) * m1 + l] = d;
+  }
+}
+
+// One thread per right-hand side: Hessenberg column j, Givens rotation,
+// residual estimate, convergence.
+__global__ void k_givens(int s, int j, int m, int nch, const double* __restrict__ hcol,
+                         const double* __restrict__ npart, double* __restrict__ H,
+                         double* __restrict__ cs, double* __restrict__ sn, double* __restrict__ g,
+                         double* __restrict__ scal, const double* __restrict__ bnorm,
+                         int* __restrict__ active, int* __restrict__ steps, int* __restrict__ total,
+                         double tol, int maxit) {
+  const int k = threadIdx.x;
+  if (k >= s || !active[k]) return;
+  const int m1 = m + 1;
+  double hn2 = 0.0;
+  for (int c = 0; c < nch; ++c) hn2 += npart[(size_t)c * s + k];
+  const double hn = sqrt(hn2);
+  double* Hk = H + (size_t)k * m1 * m + (size_t)j * m1;
+  for (int l = 0; l <= j; ++l) Hk[l] = hcol[(size_t)k * m1 + l];
+  Hk[j + 1] = hn;
+  double* ck = cs + (size_t)k * m;
+  double* sk = sn + (size_t)k * m;
+  for (int l = 0; l < j; ++l) {
+    const double a = Hk[l], bb = Hk[l + 1];
+    Hk[l] = ck[l] * a + sk[l] * bb;
+    Hk[l + 1] = -sk[l] * a + ck[l] * bb;
+  }
+  double c = 1.0, sv = 0.0;
+  const double a = Hk[j], bb = Hk[j + 1];
+  if (bb != 0.0) {
+    const double r = hypot(a, bb);
+    c = a / r;
+    sv = bb / r;
+  }
+  ck[j] = c;
+  sk[j] = sv;
+  Hk[j] = c * a + sv * bb;
+  Hk[j + 1] = 0.0;
+  double* gk = g + (size_t)k * m1;
+  gk[j + 1] = -sv * gk[j];
+  gk[j] = c * gk[j];
+  scal[k] = hn;
+  steps[k] = j + 1;
+  total[k] += 1;
+  const bool conv = fabs(gk[j + 1]) <= tol * bnorm[k];
+  if (conv || total[k] >= maxit || !(hn > 0.0) || j + 1 >= m) active[k] = 0;
+}
+
+// v_{slot}(k) = w(k) / scal(k) for active k, copied (rounded to TP) into the
+// z slot as the next preconditioner input.  Inactive columns of the z slot
+// are zeroed.
+template <typename TP>
+__global__ void k_normalize(int n, int s, int slot, const double* __restrict__ w,
+                            const double* __restrict__ scal, const int* __restrict__ active,
+                            double* __restrict__ V, TP* __restrict__ Z) {
+  const int k = blockIdx.y;
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const size_t o = ((size_t)slot * s + k) * n + i;
+  if (active[k]) {
+    const double v = w[(size_t)k * n + i] / scal[k];
+    V[o] = v;
+    if (Z) Z[o] = (TP)v;
+  } else if (Z) {
+    Z[o] = TP(0);
+  }
+}
+
+// Start of a cycle: true residual norms, decide who iterates, g = beta e_1.
+__global__ void k_cycle_init(int s, int m, int nch, const double* __restrict__ npart,
+                             const double* __restrict__ bnorm, double* __restrict__ scal,
+                             double* __restrict__ g, double* __restrict__ relres,
+                             int* __restrict__ active, int* __restrict__ steps,
+                             const int* __restrict__ total, double tol, int maxit) {
+  const int k = threadIdx.x;
+  if (k >= s) return;
+  double r2 = 0.0;
+  for (int c = 0; c < nch; ++c) r2 += npart[(size_t)c * s + k];
+  const double beta = sqrt(r2);
+  const double rr = bnorm[k] > 0.0 ? beta / bnorm[k] : 0.0;
+  relres[k] = rr;
+  const int go = (bnorm[k] > 0.0) && (rr > tol) && (total[k] < maxit) && (beta > 0.0);
+  active[k] = go;
+  steps[k] = 0;
+  scal[k] = go ? beta : 1.0;
+  for (int l = 0; l <= m; ++l) g[(size_t)k * (m + 1) + l] = 0.0;
+  g[(size_t)k * (m + 1)] = beta;
+}
+
+__global__ void k_bnorm(int s, int nch, const double* __restrict__ npart, double* __restrict__ bnorm) {
+  const int k = threadIdx.x;
+  if (k >= s) return;
+  double r2 = 0.0;
+  for (int c = 0; c < nch; ++c) r2 += npart[(size_t)c * s + k];
+  bnorm[k] = sqrt(r2);
+}
+
+__global__ void __launch_bounds__(kRowsPerWG)
+    k_sqnorm(int n, int s, const double* __restrict__ B, int ldb, double* __restrict__ npart) {
+  __shared__ double red[kRowsPerWG / 64];
+  const int k = blockIdx.y, i = blockIdx.x * kRowsPerWG + threadIdx.x;
+  const double v = i < n ? B[(size_t)k * ldb + i] : 0.0;
+  const double sq = block_sum(v * v, red);
+  if (threadIdx.x == 0) npart[(size_t)blockIdx.x * s + k] = sq;
+}
+
+// Back substitution H y = g per right-hand side (H upper triangular after
+// the rotations), one thread each.
+__global__ void k_trisolve(int s, int m, const double* __restrict__ H, const double* __restrict__ g,
+                           const int* __restrict__ steps, double* __restrict__ y) {
+  const int k = threadIdx.x;
+  if (k >= s) return;
+  const int m1 = m + 1, nk = steps[k];
+  const double* Hk = H + (size_t)k * m1 * m;
+  double* yk = y + (size_t)k * m;
+  for (int l = nk - 1; l >= 0; --l) {
+    double v = g[(size_t)k * m1 + l];
+    for (int c = l + 1; c < nk; ++c) v -= Hk[l + (size_t)c * m1] * yk[c];
+    yk[l] = v / Hk[l + (size_t)l * m1];
+  }
+}
+
+template <typename TZ>
+__global__ void k_xupdate(int n, int s, int m, double* __restrict__ X, int ldx, const TZ* __restrict__ Z,
+                          const double* __restrict__ y, const int* __restrict__ steps) {
+  const int k = blockIdx.y, i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const int nk = steps[k];
+  if (nk == 0) return;
+  double acc = 0.0;
+  for (int l = 0; l < nk; ++l) acc += (double)Z[((size_t)l * s + k) * n + i] * y[(size_t)k * m + l];
+  X[(size_t)k * ldx + i] += acc;
+}
+
+// ---------------------------------------------------------------------------
+struct GmresWork {
+  DevBuf V, Z, w, part, hA, hB, hcol, H, cs, sn, g, y, npart, scal, bnorm, relres, ints;
+  int* host_flags = nullptr;
+  std::mutex mu;
+};
+
+static GmresWork& work() {
+  static GmresWork* ws = new GmresWork();  // lives until the process ends
+  return *ws;
+}
+
+template <typename TZ>
+static int launch_matvec(const double* K, int ldk, int n, const TZ* src, int lds, int s, double* part,
+                         hipStream_t st) {
+  const dim3 grid((n + kRowsPerWG - 1) / kRowsPerWG, (n + kMatvecCols - 1) / kMatvecCols);
+#define HODLR_MV(SM) k_matvec<TZ, SM><<<grid, kRowsPerWG, 0, st>>>(K, ldk, n, src, lds, s, part)
+  if (s <= 1) HODLR_MV(1);
+  else if (s <= 2) HODLR_MV(2);
+  else if (s <= 4) HODLR_MV(4);
+  else if (s <= 8) HODLR_MV(8);
+  else if (s <= 16) HODLR_MV(16);
+  else if (s <= 32) HODLR_MV(32);
+  else HODLR_MV(64);
+#undef HODLR_MV
+  HODLR_HIP(hipGetLastError());
+  return HODLR_OK;
+}
+
+template <typename TP>
+static int gmres_t(const double* K, int n, int ldk, hodlr_s* M, const double* B, int s, int ldb,
+                   double* X, int ldx, double tol, int maxit, int m, int* iters, double* relres,
+                   hipStream_t st) {
+  GmresWork& ws = work();
+  std::lock_guard<std::mutex> lock(ws.mu);
+  const int m1 = m + 1;
+  const int nch = (n + kRowsPerWG - 1) / kRowsPerWG;
+  const int nsplit = (n + kMatvecCols - 1) / kMatvecCols;
+  const size_t ns = (size_t)n * s;
+  HODLR_TRY(ws.V.ensure(ns * m1 * sizeof(double)));
+  if (M) HODLR_TRY(ws.Z.ensure(ns * m1 * sizeof(TP)));
+  HODLR_TRY(ws.w.ensure(ns * sizeof(double)));
+  HODLR_TRY(ws.part.ensure(ns * nsplit * sizeof(double)));
+  HODLR_TRY(ws.hA.ensure((size_t)nch * s * m1 * sizeof(double)));
+  HODLR_TRY(ws.hB.ensure((size_t)nch * s * m1 * sizeof(double)));
+  HODLR_TRY(ws.hcol.ensure((size_t)s * m1 * sizeof(double)));
+  HODLR_TRY(ws.H.ensure((size_t)s * m1 * m * sizeof(double)));
+  HODLR_TRY(ws.cs.ensure((size_t)s * m * sizeof(double)));
+  HODLR_TRY(ws.sn.ensure((size_t)s * m * sizeof(double)));
+  HODLR_TRY(ws.g.ensure((size_t)s * m1 * sizeof(double)));
+  HODLR_TRY(ws.y.ensure((size_t)s * m * sizeof(double)));
+  HODLR_TRY(ws.npart.ensure((size_t)nch * s * sizeof(double)));
+  HODLR_TRY(ws.scal.ensure(s * sizeof(double)));
+  HODLR_TRY(ws.bnorm.ensure(s * sizeof(double)));
+  HODLR_TRY(ws.relres.ensure(s * sizeof(double)));
+  HODLR_TRY(ws.ints.ensure(3 * 64 * sizeof(int)));
+  if (!ws.host_flags) HODLR_HIP(hipHostMalloc(reinterpret_cast<void**>(&ws.host_flags), 64 * sizeof(int)));
+  double* V = ws.V.as<double>();
+  TP* Z = M ? ws.Z.as<TP>() : nullptr;
+  double* w = ws.w.as<double>();
+  double* part = ws.part.as<double>();
+  int* active = ws.ints.as<int>();
+  int* steps = active + 64;
+  int* total = active + 128;
+  HODLR_HIP(hipMemsetAsync(total, 0, s * sizeof(int), st));
+
+  const dim3 gch(nch, s), gvec((n + kBlock - 1) / kBlock, s);
+  k_sqnorm<<<gch, kRowsPerWG, 0, st>>>(n, s, B, ldb, ws.npart.as<double>());
+  k_bnorm<<<1, 64, 0, st>>>(s, nch, ws.npart.as<double>(), ws.bnorm.as<double>());
+  HODLR_HIP(hipGetLastError());
+
+  while (true) {
+    // true residual of the current x, start of a cycle
+    HODLR_TRY(launch_matvec<double>(K, ldk, n, X, ldx, s, part, st));
+    HODLR_HIP(hipMemsetAsync(active, 0xff, s * sizeof(int), st));  // nonzero: every column
+    k_orth<0><<<gch, kRowsPerWG, 0, st>>>(n, s, 0, m1, V, w, part, nsplit, B, ldb, nullptr, nullptr,
+                                          nullptr, ws.npart.as<double>(), active);
+    k_cycle_init<<<1, 64, 0, st>>>(s, m, nch, ws.npart.as<double>(), ws.bnorm.as<double>(),
+                                   ws.scal.as<double>(), ws.g.as<double>(), ws.relres.as<double>(),
+                                   active, steps, total, tol, maxit);
+    HODLR_HIP(hipGetLastError());
+    HODLR_HIP(hipMemcpyAsync(ws.host_flags, active, s * sizeof(int), hipMemcpyDeviceToHost, st));
+    HODLR_HIP(hipStreamSynchronize(st));
+    bool any = false;
+    for (int k = 0; k < s; ++k) any |= ws.host_flags[k] != 0;
+    if (!any) break;
+    k_normalize<TP><<<gvec, kBlock, 0, st>>>(n, s, 0, w, ws.scal.as<double>(), active, V, Z);
+    for (int j = 0; j < m; ++j) {
+      const double* src_d = V + (size_t)j * ns;
+      if (M) {
+        TP* zj = Z + (size_t)j * ns;
+        HODLR_TRY(apply_impl(M, zj, n, s, st));
+        HODLR_TRY(launch_matvec<TP>(K, ldk, n, zj, n, s, part, st));
+      } else {
+        HODLR_TRY(launch_matvec<double>(K, ldk, n, src_d, n, s, part, st));
+      }
+      k_orth<0><<<gch, kRowsPerWG, 0, st>>>(n, s, j, m1, V, w, part, nsplit, nullptr, 0, nullptr,
+                                            ws.hA.as<double>(), nullptr, nullptr, active);
+      k_orth<1><<<gch, kRowsPerWG, 0, st>>>(n, s, j, m1, V, w, part, nsplit, nullptr, 0,
+                                            ws.hA.as<double>(), ws.hB.as<double>(),
+                                            ws.hcol.as<double>(), nullptr, active);
+      k_orth<2><<<gch, kRowsPerWG, 0, st>>>(n, s, j, m1, V, w, part, nsplit, nullptr, 0,
+                                            ws.hB.as<double>(), nullptr, ws.hcol.as<double>(),
+                                            ws.npart.as<double>(), active);
+      k_givens<<<1, 64, 0, st>>>(s, j, m, nch, ws.hcol.as<double>(), ws.npart.as<double>(),
+                                 ws.H.as<double>(), ws.cs.as<double>(), ws.sn.as<double>(),
+                                 ws.g.as<double>(), ws.scal.as<double>(), ws.bnorm.as<double>(),
+                                 active, steps, total, tol, maxit);
+      k_normalize<TP><<<gvec, kBlock, 0, st>>>(n, s, j + 1, w, ws.scal.as<double>(), active, V, Z);
+      HODLR_HIP(hipGetLastError());
+      HODLR_HIP(hipMemcpyAsync(ws.host_flags, active, s * sizeof(int), hipMemcpyDeviceToHost, st));
+      HODLR_HIP(hipStreamSynchronize(st));
+      bool more = false;
+      for (int k = 0; k < s; ++k) more |= ws.host_flags[k] != 0;
+      if (!more) break;
+    }
+    k_trisolve<<<1, 64, 0, st>>>(s, m, ws.H.as<double>(), ws.g.as<double>(), steps, ws.y.as<double>());
+    if (M)
+      k_xupdate<TP><<<gvec, kBlock, 0, st>>>(n, s, m, X, ldx, Z, ws.y.as<double>(), steps);
+    else
+      k_xupdate<double><<<gvec, kBlock, 0, st>>>(n, s, m, X, ldx, V, ws.y.as<double>(), steps);
+    HODLR_HIP(hipGetLastError());
+  }
+  HODLR_HIP(hipMemcpyAsync(relres, ws.relres.p, s * sizeof(double), hipMemcpyDeviceToHost, st));
+  HODLR_HIP(hipMemcpyAsync(ws.host_flags, total, s * sizeof(int), hipMemcpyDeviceToHost, st));
+  HODLR_HIP(hipStreamSynchronize(st));
+  bool conv = true;
+  for (int k = 0; k < s; ++k) {
+    iters[k] = ws.host_flags[k];
+    conv &= relres[k] <= tol;
+  }
+  if (!conv) return fail(HODLR_ENOCONV, "GMRES reached maxit above tol");
+  return HODLR_OK;
+}
+
+int gmres_impl(const double* K, int n, int ldk, hodlr_s* M, const double* B, int nrhs, int ldb,
+               double* X, int ldx, double tol, int maxit, int restart, int* iters,
+               double* relres, hipStream_t s) {
+  const int m = std::min(restart, kMaxRestart);
+  if (M && M->precision == 32)
+    return gmres_t<float>(K, n, ldk, M, B, nrhs, ldb, X, ldx, tol, maxit, m, iters, relres, s);
+  return gmres_t<double>(K, n, ldk, M, B, nrhs, ldb, X, ldx, tol, maxit, m, iters, relres, s);
+}
+
+}  // namespace hodlr

@@ -1,0 +1,148 @@
+// Internal declarations shared by the HIP translation units of libhodlr.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "hodlr.h"
+
+namespace hodlr {
+
+// ---------------------------------------------------------------------------
+// Errors
+// ---------------------------------------------------------------------------
+void set_error(const std::string& msg);
+int fail(int code, const std::string& msg);
+
+#define HODLR_HIP(call)                                                                    \
+  do {                                                                                     \
+    hipError_t e_ = (call);                                                                \
+    if (e_ != hipSuccess)                                                                  \
+      return ::hodlr::fail(HODLR_EHIP, std::string(#call) + ": " + hipGetErrorString(e_)); \
+  } while (0)
+
+#define HODLR_TRY(call)          \
+  do {                           \
+    int s_ = (call);             \
+    if (s_ != HODLR_OK) return s_; \
+  } while (0)
+
+// ---------------------------------------------------------------------------
+// Limits.  Off-diagonal ranks are capped so that the per-node capacitance
+// matrix and the ACA working slices fit in the 160 KB of LDS of one CU.
+// ---------------------------------------------------------------------------
+constexpr int kBlock = 256;          // threads per workgroup for most kernels
+constexpr int kRankCap32 = 184;      // float: 184*185*4 B = 133 KB
+constexpr int kRankCap64 = 128;      // double: 128*129*8 B = 132 KB
+constexpr int kAcaSlice32 = 96;      // ACA rows/cols per workgroup (float)
+constexpr int kAcaSlice64 = 64;      // (double)
+constexpr int kLeafMax = 256;        // largest leaf block
+constexpr int kMaxN = 1 << 20;
+
+inline int rank_cap(int precision) { return precision == 64 ? kRankCap64 : kRankCap32; }
+
+// ---------------------------------------------------------------------------
+// Tree: node id of (level p, index i) is (1 << p) - 1 + i.
+// ---------------------------------------------------------------------------
+__host__ __device__ inline int node_id(int p, int i) { return (1 << p) - 1 + i; }
+
+struct Tree {
+  int n = 0, leaf = 0, L = 0;
+  std::vector<int> lo, hi;  // per node id
+  void build(int n_, int leaf_);
+  int nnodes() const { return (2 << L) - 1; }
+  int size(int id) const { return hi[id] - lo[id]; }
+  int min_size(int p) const;
+  int max_size(int p) const;
+};
+
+// ---------------------------------------------------------------------------
+// Device buffer (RAII, hipMalloc / hipFree)
+// ---------------------------------------------------------------------------
+struct DevBuf {
+  void* p = nullptr;
+  size_t bytes = 0;
+  DevBuf() = default;
+  DevBuf(const DevBuf&) = delete;
+  DevBuf& operator=(const DevBuf&) = delete;
+  ~DevBuf() { release(); }
+  void release() {
+    if (p) (void)hipFree(p);
+    p = nullptr;
+    bytes = 0;
+  }
+  int ensure(size_t nbytes);  // grow-only; contents not preserved
+  template <typename T> T* as() const { return static_cast<T*>(p); }
+};
+
+}  // namespace hodlr
+
+// ---------------------------------------------------------------------------
+// The handle
+// ---------------------------------------------------------------------------
+struct hodlr_s {
+  hodlr::Tree tree;
+  int precision = 32;
+  size_t esize = 4;  // bytes per element of the factorization
+  int method = HODLR_ACA;
+  int depth = 1;
+  int max_rank = 0;
+  double tol = 1e-4;
+  int device = 0;
+
+  std::vector<int> rank;   // per node id (root 0)
+  std::vector<int> rcols;  // per level q = 1..L at index q-1: column width
+  std::vector<int> off;    // per level q at index q-1: column offset
+  int R = 0;               // total columns of the panels
+  int bmax = 0;            // largest leaf
+  int nleaf = 0;
+
+  hodlr::DevBuf d_lo, d_hi, d_rank;
+  hodlr::DevBuf Y;      // n x R: U panels, then the factorization (d / c)
+  hodlr::DevBuf W;      // n x R: V panels
+  hodlr::DevBuf Kinv;   // nleaf x bmax x bmax: leaf inverses
+  hodlr::DevBuf Sinv;   // per internal node: (2 rq)^2 inverse capacitance
+  std::vector<size_t> sinv_off;  // per parent level p = 0..L-1 (elements)
+  hodlr::DevBuf G;      // work: per-node panel products
+  hodlr::DevBuf Ybuf;   // work: per-node Woodbury solutions
+  hodlr::DevBuf status; // int[4]: 0 singular flag, 1 node, 2 abort
+  bool factored = false;
+};
+
+namespace hodlr {
+
+// ---------------------------------------------------------------------------
+// Kernel launchers (one translation unit each)
+// ---------------------------------------------------------------------------
+// order.hip
+int launch_rcb(const float* coords, int n, const Tree& t, int* perm, hipStream_t s);
+int launch_permute(const double* Kin, int n, int ldi, const int* perm, double* Kout, int ldo,
+                   hipStream_t s);
+int launch_permute_graph(const int* rowptr, const int* col, int n, const int* perm,
+                         int* rowptr_out, int* col_out, hipStream_t s);
+
+// aca.hip: compress every off-diagonal block into capped panels
+int launch_aca(hodlr_s* h, const double* K, int ldk, void* Ucap, void* Vcap,
+               const std::vector<int>& capoff, const std::vector<int>& cap, hipStream_t s);
+
+// factor.hip
+int launch_stage_leaves_from_K(hodlr_s* h, const double* K, int ldk, hipStream_t s);
+int launch_stage_leaves_packed(hodlr_s* h, const double* leaves, hipStream_t s);
+int launch_repack(hodlr_s* h, const void* Ucap, const void* Vcap, int ldcap,
+                  const std::vector<int>& capoff, hipStream_t s);
+int launch_from_f64_panels(hodlr_s* h, const double* Up, const double* Vp, hipStream_t s);
+int launch_to_f64_panels(hodlr_s* h, double* Up, double* Vp, hipStream_t s);
+int factor_impl(hodlr_s* h, hipStream_t s);
+int apply_impl(hodlr_s* h, void* X, int ldx, int nrhs, hipStream_t s);  // in place
+int ensure_work(hodlr_s* h, int ncols);
+
+// gmres.hip
+int gmres_impl(const double* K, int n, int ldk, hodlr_s* M, const double* B, int nrhs, int ldb,
+               double* X, int ldx, double tol, int maxit, int restart, int* iters,
+               double* relres, hipStream_t s);
+
+}  // namespace hodlr

@@ -1,0 +1,225 @@
+// Dof ordering for the HODLR index halving, and relabelling of a front.
+//
+// The HODLR tree halves index ranges (Sec. 4.1), so neighbouring dofs must be
+// close in the order; the paper takes the order from SCOTCH (Sec. 6).  Here a
+// recursive coordinate bisection follows the tree itself: for every node,
+// from the root down, its dofs are sorted by the coordinate of largest
+// extent (first axis on ties; equal keys keep their current order) and the
+// left child takes the first floor(len/2).  One workgroup sorts one node with
+// a bitonic sort of (key, position) pairs in LDS, which is stable by
+// construction because positions break ties.
+#include <algorithm>
+#include <cfloat>
+#include <climits>
+
+#include "device_util.h"
+#include "hodlr_internal.h"
+
+namespace hodlr {
+
+constexpr int kRcbMax = 16384;
+
+__global__ void __launch_bounds__(kBlock)
+    k_rcb_level(const float* __restrict__ coords, int* __restrict__ perm, const int* __restrict__ lo,
+                const int* __restrict__ hi, int id0) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  const int node = blockIdx.x, id = id0 + node, t = threadIdx.x, nt = blockDim.x;
+  const int l0 = lo[id], len = hi[id] - l0;
+  if (len <= 1) return;
+  int P = 1;
+  while (P < len) P <<= 1;
+  float* key = reinterpret_cast<float*>(smem);
+  int* pos = reinterpret_cast<int*>(key + kRcbMax);
+  __shared__ float red[6][kBlock / 64];
+  __shared__ int s_axis;
+  float mn[3] = {FLT_MAX, FLT_MAX, FLT_MAX}, mx[3] = {-FLT_MAX, -FLT_MAX, -FLT_MAX};
+  for (int e = t; e < len; e += nt) {
+    const int v = perm[l0 + e];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      const float c = coords[3 * (size_t)v + a];
+      mn[a] = fminf(mn[a], c);
+      mx[a] = fmaxf(mx[a], c);
+    }
+  }
+#pragma unroll
+  for (int a = 0; a < 3; ++a)
+    for (int o = 32; o > 0; o >>= 1) {
+      mn[a] = fminf(mn[a], __shfl_xor(mn[a], o, 64));
+      mx[a] = fmaxf(mx[a], __shfl_xor(mx[a], o, 64));
+    }
+  const int w = t >> 6, nw = nt >> 6;
+  if ((t & 63) == 0)
+    for (int a = 0; a < 3; ++a) {
+      red[a][w] = mn[a];
+      red[3 + a][w] = mx[a];
+    }
+  __syncthreads();
+  if (t == 0) {
+    float ext[3];
+    for (int a = 0; a < 3; ++a) {
+      float lo_a = red[a][0], hi_a = red[3 + a][0];
+      for (int k = 1; k < nw; ++k) {
+        lo_a = fminf(lo_a, red[a][k]);
+        hi_a = fmaxf(hi_a, red[3 + a][k]);
+      }
+      ext[a] = hi_a - lo_a;
+    }
+    int ax = 0;
+    if (ext[1] > ext[ax]) ax = 1;
+    if (ext[2] > ext[ax]) ax = 2;
+    s_axis = ax;
+  }
+  __syncthreads();
+  const int ax = s_axis;
+  for (int e = t; e < P; e += nt) {
+    if (e < len) {
+      key[e] = coords[3 * (size_t)perm[l0 + e] + ax];
+      pos[e] = e;
+    } else {
+      key[e] = INFINITY;
+      pos[e] = INT_MAX;
+    }
+  }
+  __syncthreads();
+  for (int k = 2; k <= P; k <<= 1) {
+    for (int j = k >> 1; j > 0; j >>= 1) {
+      for (int e = t; e < P; e += nt) {
+        const int x = e ^ j;
+        if (x > e) {
+          const float ka = key[e], kb = key[x];
+          const int pa = pos[e], pb = pos[x];
+          const bool a_gt_b = (ka > kb) || (ka == kb && pa > pb);
+          const bool up = (e & k) == 0;
+          if (a_gt_b == up) {
+            key[e] = kb;
+            key[x] = ka;
+            pos[e] = pb;
+            pos[x] = pa;
+          }
+        }
+      }
+      __syncthreads();
+    }
+  }
+  int* old = reinterpret_cast<int*>(key);  // keys are no longer needed
+  for (int e = t; e < len; e += nt) old[e] = perm[l0 + e];
+  __syncthreads();
+  for (int e = t; e < len; e += nt) perm[l0 + e] = old[pos[e]];
+}
+
+__global__ void k_iota(int* p, int n) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = i;
+}
+
+int launch_rcb(const float* coords, int n, const Tree& t, int* perm, hipStream_t s) {
+  k_iota<<<(n + kBlock - 1) / kBlock, kBlock, 0, s>>>(perm, n);
+  HODLR_HIP(hipGetLastError());
+  if (t.L == 0) return HODLR_OK;
+  DevBuf dlo, dhi;
+  const int nn = t.nnodes();
+  HODLR_TRY(dlo.ensure(nn * sizeof(int)));
+  HODLR_TRY(dhi.ensure(nn * sizeof(int)));
+  HODLR_HIP(hipMemcpyAsync(dlo.p, t.lo.data(), nn * sizeof(int), hipMemcpyHostToDevice, s));
+  HODLR_HIP(hipMemcpyAsync(dhi.p, t.hi.data(), nn * sizeof(int), hipMemcpyHostToDevice, s));
+  const size_t lds = (size_t)kRcbMax * (sizeof(float) + sizeof(int));
+  HODLR_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(k_rcb_level),
+                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+  for (int p = 0; p < t.L; ++p) {
+    k_rcb_level<<<1 << p, kBlock, lds, s>>>(coords, perm, dlo.as<int>(), dhi.as<int>(), node_id(p, 0));
+    HODLR_HIP(hipGetLastError());
+  }
+  HODLR_HIP(hipStreamSynchronize(s));  // dlo/dhi are released on return
+  return HODLR_OK;
+}
+
+// ---------------------------------------------------------------------------
+__global__ void k_permute(const double* __restrict__ Kin, int n, int ldi, const int* __restrict__ perm,
+                          double* __restrict__ Kout, int ldo) {
+  const int j = blockIdx.y;
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const int pj = perm[j];
+  Kout[(size_t)j * ldo + i] = Kin[(size_t)pj * ldi + perm[i]];
+}
+
+int launch_permute(const double* Kin, int n, int ldi, const int* perm, double* Kout, int ldo,
+                   hipStream_t s) {
+  k_permute<<<dim3((n + kBlock - 1) / kBlock, n), kBlock, 0, s>>>(Kin, n, ldi, perm, Kout, ldo);
+  HODLR_HIP(hipGetLastError());
+  return HODLR_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Graph relabelling: new vertex i = old vertex perm[i].
+__global__ void k_inverse_perm(const int* __restrict__ perm, int* __restrict__ inv, int n) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) inv[perm[i]] = i;
+}
+
+__global__ void k_new_degree(const int* __restrict__ rowptr, const int* __restrict__ perm,
+                             int* __restrict__ deg, int n) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) deg[i] = rowptr[perm[i] + 1] - rowptr[perm[i]];
+}
+
+// Exclusive scan of deg into rowptr_out[0..n] by one workgroup.
+__global__ void __launch_bounds__(kBlock) k_scan(const int* __restrict__ deg, int* __restrict__ out, int n) {
+  __shared__ int part[kBlock];
+  __shared__ int carry;
+  const int t = threadIdx.x;
+  if (t == 0) carry = 0;
+  __syncthreads();
+  for (int base = 0; base < n; base += kBlock) {
+    const int i = base + t;
+    const int v = i < n ? deg[i] : 0;
+    part[t] = v;
+    __syncthreads();
+    for (int o = 1; o < kBlock; o <<= 1) {
+      const int add = t >= o ? part[t - o] : 0;
+      __syncthreads();
+      part[t] += add;
+      __syncthreads();
+    }
+    if (i < n) out[i] = carry + part[t] - v;
+    __syncthreads();
+    if (t == kBlock - 1) carry += part[t];
+    __syncthreads();
+  }
+  if (t == 0) out[n] = carry;
+}
+
+__global__ void k_fill_sorted(const int* __restrict__ rowptr, const int* __restrict__ col,
+                              const int* __restrict__ perm, const int* __restrict__ inv,
+                              const int* __restrict__ rowptr_out, int* __restrict__ col_out, int n) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const int src = perm[i], b = rowptr[src], e = rowptr[src + 1], o = rowptr_out[i];
+  for (int x = b; x < e; ++x) {
+    const int v = inv[col[x]];
+    int y = o + (x - b);
+    while (y > o && col_out[y - 1] > v) {  // insertion sort of the short row
+      col_out[y] = col_out[y - 1];
+      --y;
+    }
+    col_out[y] = v;
+  }
+}
+
+int launch_permute_graph(const int* rowptr, const int* col, int n, const int* perm,
+                         int* rowptr_out, int* col_out, hipStream_t s) {
+  DevBuf inv, deg;
+  HODLR_TRY(inv.ensure(n * sizeof(int)));
+  HODLR_TRY(deg.ensure(n * sizeof(int)));
+  const int g = (n + kBlock - 1) / kBlock;
+  k_inverse_perm<<<g, kBlock, 0, s>>>(perm, inv.as<int>(), n);
+  k_new_degree<<<g, kBlock, 0, s>>>(rowptr, perm, deg.as<int>(), n);
+  k_scan<<<1, kBlock, 0, s>>>(deg.as<int>(), rowptr_out, n);
+  k_fill_sorted<<<g, kBlock, 0, s>>>(rowptr, col, perm, inv.as<int>(), rowptr_out, col_out, n);
+  HODLR_HIP(hipGetLastError());
+  HODLR_HIP(hipStreamSynchronize(s));
+  return HODLR_OK;
+}
+
+}  // namespace hodlr

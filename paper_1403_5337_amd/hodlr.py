@@ -1,0 +1,267 @@
+"""Thin ctypes binding of libhodlr (include/hodlr.h), same names as the C ABI.
+
+Argument marshalling only: torch tensors provide device memory and the
+current HIP stream; every step of the computation runs in the library's HIP
+kernels.  Calls fail loudly (HodlrError) when the library is missing or a
+call returns an error status.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Optional
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libhodlr.so")
+
+HODLR_OK, HODLR_EINVAL, HODLR_ENOMEM, HODLR_ESINGULAR, HODLR_ENOCONV, HODLR_EHIP = range(6)
+HODLR_ACA, HODLR_BDLR = 0, 1
+STATUS_NAMES = {0: "OK", 1: "EINVAL", 2: "ENOMEM", 3: "ESINGULAR", 4: "ENOCONV", 5: "EHIP"}
+
+
+class HodlrError(RuntimeError):
+    def __init__(self, status: int, message: str):
+        super().__init__(f"{STATUS_NAMES.get(status, status)}: {message}")
+        self.status = status
+
+
+class Opts(ctypes.Structure):
+    _fields_ = [("leaf", ctypes.c_int), ("tol", ctypes.c_double), ("method", ctypes.c_int),
+                ("bdlr_depth", ctypes.c_int), ("max_rank", ctypes.c_int), ("precision", ctypes.c_int)]
+
+
+_c_int_p = ctypes.POINTER(ctypes.c_int)
+_c_dbl_p = ctypes.POINTER(ctypes.c_double)
+_vp = ctypes.c_void_p
+
+# name -> (restype, argtypes)
+_SIGNATURES = {
+    "hodlr_default_opts": (None, [ctypes.POINTER(Opts)]),
+    "hodlr_build": (ctypes.c_int, [_vp, ctypes.c_int, ctypes.c_int, _vp, _vp, ctypes.POINTER(Opts), _vp,
+                                   ctypes.POINTER(_vp)]),
+    "hodlr_build_from_factors": (ctypes.c_int, [ctypes.c_int, ctypes.c_int, ctypes.c_int, _vp, _vp, _vp,
+                                                _c_int_p, _c_int_p, ctypes.c_int, _vp, ctypes.POINTER(_vp)]),
+    "hodlr_factor": (ctypes.c_int, [_vp, _vp]),
+    "hodlr_solve": (ctypes.c_int, [_vp, _vp, ctypes.c_int, ctypes.c_int, _vp, ctypes.c_int, _vp]),
+    "gmres_solve": (ctypes.c_int, [_vp, ctypes.c_int, ctypes.c_int, _vp, _vp, ctypes.c_int, ctypes.c_int,
+                                   _vp, ctypes.c_int, ctypes.c_double, ctypes.c_int, ctypes.c_int,
+                                   _c_int_p, _c_dbl_p, _vp]),
+    "hodlr_order_rcb": (ctypes.c_int, [_vp, ctypes.c_int, ctypes.c_int, _vp, _vp]),
+    "hodlr_permute": (ctypes.c_int, [_vp, ctypes.c_int, ctypes.c_int, _vp, _vp, ctypes.c_int, _vp]),
+    "hodlr_permute_graph": (ctypes.c_int, [_vp, _vp, ctypes.c_int, _vp, _vp, _vp, _vp]),
+    "hodlr_stats": (ctypes.c_int, [_vp, _c_int_p, _c_int_p, _c_int_p]),
+    "hodlr_get_factors": (ctypes.c_int, [_vp, _vp, _vp, _vp]),
+    "hodlr_destroy": (ctypes.c_int, [_vp]),
+    "hodlr_last_error": (ctypes.c_char_p, []),
+}
+
+_lib = None
+
+
+def lib() -> ctypes.CDLL:
+    """Load libhodlr.so (built in-tree); raise if it is missing."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise HodlrError(HODLR_EHIP, f"{LIB_PATH} is not built (python -m paper_1403_5337_amd.build)")
+        L = ctypes.CDLL(LIB_PATH)
+        for name, (res, args) in _SIGNATURES.items():
+            f = getattr(L, name)
+            f.restype = res
+            f.argtypes = args
+        _lib = L
+    return _lib
+
+
+def _check(status: int):
+    if status != HODLR_OK:
+        raise HodlrError(status, lib().hodlr_last_error().decode())
+
+
+def _stream(stream=None):
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def _ptr(t: Optional[torch.Tensor]):
+    return ctypes.c_void_p(0 if t is None else t.data_ptr())
+
+
+def _need_gpu(*ts):
+    for t in ts:
+        if t is not None and not t.is_cuda:
+            raise HodlrError(HODLR_EINVAL, "tensors must live on the GPU")
+
+
+def colmajor(A: torch.Tensor, dtype=None):
+    """Return (tensor, ld) with A's values laid out column-major on A's device.
+
+    A (n, m) tensor whose strides are (1, ld) is used as is; otherwise a
+    column-major copy is made."""
+    if dtype is not None and A.dtype != dtype:
+        A = A.to(dtype)
+    if A.dim() == 1:
+        A = A[:, None]
+    n, m = A.shape
+    if A.stride(0) == 1 and (m == 1 or A.stride(1) >= n):
+        return A, max(A.stride(1) if m > 1 else n, n)
+    C = A.t().contiguous().t()
+    return C, n
+
+
+def default_opts() -> Opts:
+    o = Opts()
+    lib().hodlr_default_opts(ctypes.byref(o))
+    return o
+
+
+class Hodlr:
+    """Owning wrapper of a hodlr_t handle."""
+
+    def __init__(self, handle: ctypes.c_void_p, n: int, precision: int, keep=()):
+        self._h = handle
+        self.n = n
+        self.precision = precision
+        self._keep = keep
+
+    @property
+    def handle(self):
+        return self._h
+
+    @classmethod
+    def build(cls, K: torch.Tensor, leaf=128, tol=1e-4, method="aca", depth=1, max_rank=0,
+              precision=32, graph=None, stream=None) -> "Hodlr":
+        _need_gpu(K)
+        Kc, ldk = colmajor(K, torch.float64)
+        n = Kc.shape[0]
+        o = Opts(leaf=leaf, tol=tol, method=HODLR_BDLR if method == "bdlr" else HODLR_ACA,
+                 bdlr_depth=depth, max_rank=max_rank, precision=precision)
+        rp, cp = (None, None) if graph is None else graph
+        h = ctypes.c_void_p()
+        _check(lib().hodlr_build(_ptr(Kc), n, ldk, _ptr(rp), _ptr(cp), ctypes.byref(o), _stream(stream),
+                                 ctypes.byref(h)))
+        return cls(h, n, precision)
+
+    @classmethod
+    def from_factors(cls, n, leaf, precision, leaves: torch.Tensor, Upanel: torch.Tensor,
+                     Vpanel: torch.Tensor, ranks, rcols, stream=None) -> "Hodlr":
+        """leaves: packed float64 device buffer; Upanel/Vpanel: (n, R) float64
+        device tensors (made column-major here); ranks/rcols: host ints."""
+        _need_gpu(leaves, Upanel, Vpanel)
+        U, _ = colmajor(Upanel, torch.float64)
+        V, _ = colmajor(Vpanel, torch.float64)
+        rk = (ctypes.c_int * max(len(ranks), 1))(*ranks)
+        rc = (ctypes.c_int * max(len(rcols), 1))(*rcols)
+        h = ctypes.c_void_p()
+        _check(lib().hodlr_build_from_factors(n, leaf, precision, _ptr(leaves.contiguous()), _ptr(U),
+                                              _ptr(V), rk, rc, len(rcols), _stream(stream), ctypes.byref(h)))
+        return cls(h, n, precision)
+
+    def factor(self, stream=None):
+        _check(lib().hodlr_factor(self._h, _stream(stream)))
+        return self
+
+    def solve(self, B: torch.Tensor, stream=None) -> torch.Tensor:
+        """X = Ktilde^-1 B in the handle's precision; returns a new (n, s) tensor."""
+        _need_gpu(B)
+        dt = torch.float64 if self.precision == 64 else torch.float32
+        Bc, ldb = colmajor(B, dt)
+        X = torch.empty((Bc.shape[1], self.n), dtype=dt, device=B.device).t()
+        _check(lib().hodlr_solve(self._h, _ptr(Bc), Bc.shape[1], ldb, _ptr(X), self.n, _stream(stream)))
+        return X
+
+    def stats(self):
+        L = ctypes.c_int()
+        lib().hodlr_stats(self._h, ctypes.byref(L), None, None)
+        nn = (2 << L.value) - 2
+        rk = (ctypes.c_int * max(nn, 1))()
+        rc = (ctypes.c_int * max(L.value, 1))()
+        _check(lib().hodlr_stats(self._h, None, rk, rc))
+        ranks, o = [], 0
+        for p in range(1, L.value + 1):
+            ranks.append(list(rk[o:o + (1 << p)]))
+            o += 1 << p
+        return dict(levels=L.value, ranks=ranks, rcols=list(rc[:L.value]))
+
+    def factors(self, stream=None):
+        """(U, V) panels as float64 (n, R) tensors (before factor())."""
+        st = self.stats()
+        R = sum(st["rcols"])
+        U = torch.zeros((max(R, 1), self.n), dtype=torch.float64, device="cuda").t()
+        V = torch.zeros_like(U)
+        _check(lib().hodlr_get_factors(self._h, _ptr(U), _ptr(V), _stream(stream)))
+        return U[:, :R], V[:, :R]
+
+    def close(self):
+        if self._h:
+            lib().hodlr_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def hodlr_build(K, **kw) -> Hodlr:
+    return Hodlr.build(K, **kw)
+
+
+def hodlr_factor(h: Hodlr, stream=None) -> Hodlr:
+    return h.factor(stream)
+
+
+def hodlr_solve(h: Hodlr, B, stream=None):
+    return h.solve(B, stream)
+
+
+def gmres_solve(K: torch.Tensor, B: torch.Tensor, precond: Optional[Hodlr] = None, X0=None, tol=1e-12,
+                maxit=1000, restart=200, stream=None, raise_on_noconv=False):
+    """Returns (X (n, s) float64, iters list, relres list, status)."""
+    _need_gpu(K, B)
+    Kc, ldk = colmajor(K, torch.float64)
+    Bc, ldb = colmajor(B, torch.float64)
+    n, s = Bc.shape
+    X = torch.zeros((s, n), dtype=torch.float64, device=B.device).t()
+    if X0 is not None:
+        X.copy_(X0.reshape(n, s))
+    it = (ctypes.c_int * s)()
+    rr = (ctypes.c_double * s)()
+    st = lib().gmres_solve(_ptr(Kc), n, ldk, None if precond is None else precond.handle, _ptr(Bc), s, ldb,
+                           _ptr(X), n, tol, maxit, restart, it, rr, _stream(stream))
+    if st not in (HODLR_OK, HODLR_ENOCONV) or (raise_on_noconv and st == HODLR_ENOCONV):
+        _check(st)
+    return X, list(it), list(rr), st
+
+
+def hodlr_order_rcb(coords: torch.Tensor, leaf: int, stream=None) -> torch.Tensor:
+    _need_gpu(coords)
+    c = coords.to(torch.float32).contiguous()
+    n = c.shape[0]
+    perm = torch.empty(n, dtype=torch.int32, device=c.device)
+    _check(lib().hodlr_order_rcb(_ptr(c), n, leaf, _ptr(perm), _stream(stream)))
+    return perm
+
+
+def hodlr_permute(K: torch.Tensor, perm: torch.Tensor, stream=None) -> torch.Tensor:
+    _need_gpu(K, perm)
+    Kc, ldk = colmajor(K, torch.float64)
+    n = Kc.shape[0]
+    out = torch.empty((n, n), dtype=torch.float64, device=K.device).t()
+    _check(lib().hodlr_permute(_ptr(Kc), n, ldk, _ptr(perm.to(torch.int32).contiguous()), _ptr(out), n,
+                               _stream(stream)))
+    return out
+
+
+def hodlr_permute_graph(rowptr: torch.Tensor, col: torch.Tensor, perm: torch.Tensor, stream=None):
+    _need_gpu(rowptr, col, perm)
+    n = rowptr.numel() - 1
+    ro = torch.empty_like(rowptr, dtype=torch.int32)
+    co = torch.empty_like(col, dtype=torch.int32)
+    _check(lib().hodlr_permute_graph(_ptr(rowptr.to(torch.int32).contiguous()), _ptr(col.to(torch.int32).contiguous()),
+                                     n, _ptr(perm.to(torch.int32).contiguous()), _ptr(ro), _ptr(co),
+                                     _stream(stream)))
+    return ro, co

@@ -1,0 +1,79 @@
+"""CPU checks of the C ABI: the library builds, loads, exports every entry
+point declared in include/hodlr.h, and rejects bad arguments before touching
+the GPU."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+@pytest.fixture(scope="module")
+def L():
+    from paper_1403_5337_amd import build, hodlr
+    if not os.path.exists(hodlr.LIB_PATH):
+        build.build()
+    return hodlr.lib()
+
+
+def declared_functions():
+    src = open(os.path.join(ROOT, "include", "hodlr.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"^\s*(?:const\s+)?\w+\s*\*?\s*(\w+)\s*\(", src, flags=re.M)))
+
+
+def test_exports_every_declared_symbol(L):
+    names = declared_functions()
+    assert "hodlr_build" in names and "gmres_solve" in names and len(names) >= 13
+    raw = ctypes.CDLL(os.path.join(ROOT, "paper_1403_5337_amd", "libhodlr.so"))
+    for nm in names:
+        assert hasattr(raw, nm), nm
+
+
+def test_default_opts(L):
+    from paper_1403_5337_amd import hodlr
+    o = hodlr.default_opts()
+    assert (o.leaf, o.tol, o.method, o.bdlr_depth, o.max_rank, o.precision) == (128, 1e-4, 0, 1, 0, 32)
+
+
+def test_argument_validation(L):
+    from paper_1403_5337_amd import hodlr as H
+    out = ctypes.c_void_p()
+    o = H.default_opts()
+    st = L.hodlr_build(None, 10, 10, None, None, ctypes.byref(o), None, ctypes.byref(out))
+    assert st == H.HODLR_EINVAL and b"K is NULL" in L.hodlr_last_error()
+    st = L.hodlr_build(ctypes.c_void_p(16), 10, 5, None, None, ctypes.byref(o), None, ctypes.byref(out))
+    assert st == H.HODLR_EINVAL and b"ldk" in L.hodlr_last_error()
+    o.precision = 16
+    st = L.hodlr_build(ctypes.c_void_p(16), 10, 10, None, None, ctypes.byref(o), None, ctypes.byref(out))
+    assert st == H.HODLR_EINVAL and b"precision" in L.hodlr_last_error()
+    o = H.default_opts()
+    o.method = H.HODLR_BDLR
+    st = L.hodlr_build(ctypes.c_void_p(16), 10, 10, None, None, ctypes.byref(o), None, ctypes.byref(out))
+    assert st == H.HODLR_EINVAL and b"graph" in L.hodlr_last_error()
+    assert L.hodlr_factor(None, None) == H.HODLR_EINVAL
+    assert L.hodlr_solve(None, None, 1, 1, None, 1, None) == H.HODLR_EINVAL
+    it = (ctypes.c_int * 1)()
+    rr = (ctypes.c_double * 1)()
+    p = ctypes.c_void_p(16)
+    assert L.gmres_solve(p, 10, 10, None, p, 1, 10, p, 10, 0.0, 10, 10, it, rr, None) == H.HODLR_EINVAL
+    assert L.gmres_solve(p, 10, 10, None, p, 0, 10, p, 10, 1e-12, 10, 10, it, rr, None) == H.HODLR_EINVAL
+    assert L.gmres_solve(p, 10, 9, None, p, 1, 10, p, 10, 1e-12, 10, 10, it, rr, None) == H.HODLR_EINVAL
+    assert L.hodlr_order_rcb(p, 0, 4, p, None) == H.HODLR_EINVAL
+    assert L.hodlr_order_rcb(p, 20000, 4, p, None) == H.HODLR_EINVAL
+    assert L.hodlr_permute(p, 10, 10, p, p, 10, None) == H.HODLR_EINVAL  # in place
+    assert L.hodlr_destroy(None) == H.HODLR_OK
+    out2 = ctypes.c_void_p()
+    rk = (ctypes.c_int * 2)(1, 1)
+    rc = (ctypes.c_int * 1)(1)
+    st = L.hodlr_build_from_factors(10, 5, 32, p, p, p, rk, rc, 3, None, ctypes.byref(out2))
+    assert st == H.HODLR_EINVAL and b"levels" in L.hodlr_last_error()
+
+
+def test_binding_refuses_cpu_tensors(L):
+    import torch
+    from paper_1403_5337_amd import hodlr as H
+    with pytest.raises(H.HodlrError):
+        H.Hodlr.build(torch.eye(4, dtype=torch.float64))
