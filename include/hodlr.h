@@ -159,6 +159,16 @@ int hodlr_get_factors(hodlr_t h, double* Upanel, double* Vpanel, hipStream_t str
 
 int hodlr_destroy(hodlr_t h);
 
+/* Kernel timing for benchmarks.  hodlr_prof_enable(1) clears earlier records
+ * and makes the library record a HIP event pair around each launch of its
+ * main kernels, on the launch stream; hodlr_prof_enable(0) stops recording.
+ * hodlr_prof_query(name) synchronizes those events and returns how many
+ * launches of kernel `name` were recorded and their summed duration in ms.
+ * Names: "aca", "leaf_inverse", "leaf_apply", "panel_tn", "schur_form",
+ * "schur_apply", "correct", "matvec", "orth".  Host-side pointers. */
+int hodlr_prof_enable(int on);
+int hodlr_prof_query(const char* name, int* launches, double* total_ms);
+
 /* Thread-local message of the last failing call on this thread. */
 const char* hodlr_last_error(void);
 

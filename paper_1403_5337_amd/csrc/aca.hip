@@ -378,6 +378,8 @@ static int aca_t(hodlr_s* h, const double* K, int ldk, T* Ucap, T* Vcap,
   T teps = (T)h->tol;
   int ldu = tr.n;
   // contiguous ranges of whole groups that fit on the device at once
+  {
+  ProfScope prof("aca", s);
   size_t x = 0;
   while (x < tasks.size()) {
     int wg_base = tasks[x].g0, cnt = 0;
@@ -391,6 +393,7 @@ static int aca_t(hodlr_s* h, const double* K, int ldk, T* Ucap, T* Vcap,
                     (void*)&p_status, (void*)&teps};
     HODLR_HIP(hipLaunchCooperativeKernel(reinterpret_cast<const void*>(kern), dim3(cnt),
                                          dim3(kBlock), args, (unsigned)lds, s));
+  }
   }
   // the scratch buffers are released on return: wait for the kernels
   HODLR_HIP(hipStreamSynchronize(s));

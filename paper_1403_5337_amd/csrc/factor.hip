@@ -433,12 +433,18 @@ static int level_solve(hodlr_s* h, int q, T* Z, int ldz, int zcols, const T* G, 
   const int rq = h->rcols[q - 1], offq = h->off[q - 1];
   const T* Sinv = h->Sinv.as<T>() + h->sinv_off[q - 1];
   T* Yb = h->Ybuf.as<T>();
-  k_schur_apply<T, kCT><<<dim3(1 << (q - 1), cdiv(zcols, kCT)), kBlock, 0, s>>>(
-      G, rq, gcols, zcols, h->d_rank.as<int>(), q, Sinv, Yb);
+  {
+    ProfScope prof_("schur_apply", s);
+    k_schur_apply<T, kCT><<<dim3(1 << (q - 1), cdiv(zcols, kCT)), kBlock, 0, s>>>(
+        G, rq, gcols, zcols, h->d_rank.as<int>(), q, Sinv, Yb);
+  }
   HODLR_HIP(hipGetLastError());
-  k_correct<T, kCT><<<dim3(1 << q, cdiv(t.max_size(q), kBlock), cdiv(zcols, kCT)), kBlock, 0, s>>>(
-      h->Y.as<T>(), t.n, offq, Z, ldz, zcols, Yb, rq, h->d_lo.as<int>(), h->d_hi.as<int>(),
-      h->d_rank.as<int>(), q);
+  {
+    ProfScope prof_("correct", s);
+    k_correct<T, kCT><<<dim3(1 << q, cdiv(t.max_size(q), kBlock), cdiv(zcols, kCT)), kBlock, 0, s>>>(
+        h->Y.as<T>(), t.n, offq, Z, ldz, zcols, Yb, rq, h->d_lo.as<int>(), h->d_hi.as<int>(),
+        h->d_rank.as<int>(), q);
+  }
   HODLR_HIP(hipGetLastError());
   return HODLR_OK;
 }
@@ -450,30 +456,42 @@ static int factor_t(hodlr_s* h, hipStream_t s) {
   HODLR_HIP(hipMemsetAsync(h->status.p, 0, 4 * sizeof(int), s));
   const size_t lds_leaf = (size_t)h->bmax * (h->bmax + 1) * sizeof(T);
   HODLR_TRY(allow_lds(k_leaf_inverse<T>, lds_leaf));
-  k_leaf_inverse<T><<<h->nleaf, kBlock, lds_leaf, s>>>(h->Kinv.as<T>(), h->bmax, h->d_lo.as<int>(),
-                                                       h->d_hi.as<int>(), node_id(L, 0),
-                                                       h->status.as<int>());
+  {
+    ProfScope prof_("leaf_inverse", s);
+    k_leaf_inverse<T><<<h->nleaf, kBlock, lds_leaf, s>>>(h->Kinv.as<T>(), h->bmax, h->d_lo.as<int>(),
+                                                         h->d_hi.as<int>(), node_id(L, 0),
+                                                         h->status.as<int>());
+  }
   HODLR_HIP(hipGetLastError());
   if (L == 0 || h->R == 0) return HODLR_OK;
   HODLR_TRY(ensure_work(h, 64));
   T* Y = h->Y.as<T>();
   const T* W = h->W.as<T>();
-  k_leaf_apply<T, kCT><<<dim3(h->nleaf, cdiv(h->R, kCT)), kBlock, 0, s>>>(
-      h->Kinv.as<T>(), h->bmax, h->d_lo.as<int>(), h->d_hi.as<int>(), node_id(L, 0), Y, n, h->R);
+  {
+    ProfScope prof_("leaf_apply", s);
+    k_leaf_apply<T, kCT><<<dim3(h->nleaf, cdiv(h->R, kCT)), kBlock, 0, s>>>(
+        h->Kinv.as<T>(), h->bmax, h->d_lo.as<int>(), h->d_hi.as<int>(), node_id(L, 0), Y, n, h->R);
+  }
   HODLR_HIP(hipGetLastError());
   for (int q = L; q >= 1; --q) {
     const int rq = h->rcols[q - 1], offq = h->off[q - 1];
     if (rq == 0) continue;
     const int zc = offq + rq;
     T* G = h->G.as<T>();
-    k_panel_tn<T><<<dim3(1 << q, cdiv(rq, 64), cdiv(zc, 64)), kBlock, 0, s>>>(
-        W, n, offq, rq, Y, n, zc, h->d_lo.as<int>(), h->d_hi.as<int>(), node_id(q, 0), G);
+    {
+      ProfScope prof_("panel_tn", s);
+      k_panel_tn<T><<<dim3(1 << q, cdiv(rq, 64), cdiv(zc, 64)), kBlock, 0, s>>>(
+          W, n, offq, rq, Y, n, zc, h->d_lo.as<int>(), h->d_hi.as<int>(), node_id(q, 0), G);
+    }
     HODLR_HIP(hipGetLastError());
     const size_t lds_s = (size_t)rq * (rq + 1) * sizeof(T);
     HODLR_TRY(allow_lds(k_schur_form<T>, lds_s));
-    k_schur_form<T><<<1 << (q - 1), kBlock, lds_s, s>>>(G, rq, zc, offq, h->d_rank.as<int>(), q,
-                                                         h->Sinv.as<T>() + h->sinv_off[q - 1],
-                                                         h->status.as<int>());
+    {
+      ProfScope prof_("schur_form", s);
+      k_schur_form<T><<<1 << (q - 1), kBlock, lds_s, s>>>(G, rq, zc, offq, h->d_rank.as<int>(), q,
+                                                           h->Sinv.as<T>() + h->sinv_off[q - 1],
+                                                           h->status.as<int>());
+    }
     HODLR_HIP(hipGetLastError());
     if (offq > 0) HODLR_TRY(level_solve<T>(h, q, Y, n, offq, G, zc, s));
   }
@@ -491,16 +509,22 @@ static int apply_t(hodlr_s* h, T* X, int ldx, int nrhs, hipStream_t s) {
   for (int c0 = 0; c0 < nrhs; c0 += 64) {
     const int nc = std::min(64, nrhs - c0);
     T* Xc = X + (size_t)c0 * ldx;
-    k_leaf_apply<T, kCT><<<dim3(h->nleaf, cdiv(nc, kCT)), kBlock, 0, s>>>(
-        h->Kinv.as<T>(), h->bmax, h->d_lo.as<int>(), h->d_hi.as<int>(), node_id(L, 0), Xc, ldx, nc);
+    {
+      ProfScope prof_("leaf_apply", s);
+      k_leaf_apply<T, kCT><<<dim3(h->nleaf, cdiv(nc, kCT)), kBlock, 0, s>>>(
+          h->Kinv.as<T>(), h->bmax, h->d_lo.as<int>(), h->d_hi.as<int>(), node_id(L, 0), Xc, ldx, nc);
+    }
     HODLR_HIP(hipGetLastError());
     for (int q = L; q >= 1; --q) {
       const int rq = h->rcols[q - 1], offq = h->off[q - 1];
       if (rq == 0) continue;
       T* G = h->G.as<T>();
-      k_panel_tn<T><<<dim3(1 << q, cdiv(rq, 64), cdiv(nc, 64)), kBlock, 0, s>>>(
-          h->W.as<T>(), n, offq, rq, Xc, ldx, nc, h->d_lo.as<int>(), h->d_hi.as<int>(),
-          node_id(q, 0), G);
+      {
+        ProfScope prof_("panel_tn", s);
+        k_panel_tn<T><<<dim3(1 << q, cdiv(rq, 64), cdiv(nc, 64)), kBlock, 0, s>>>(
+            h->W.as<T>(), n, offq, rq, Xc, ldx, nc, h->d_lo.as<int>(), h->d_hi.as<int>(),
+            node_id(q, 0), G);
+      }
       HODLR_HIP(hipGetLastError());
       HODLR_TRY(level_solve<T>(h, q, Xc, ldx, nc, G, nc, s));
     }

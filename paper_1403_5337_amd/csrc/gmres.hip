@@ -280,6 +280,7 @@ template <typename TZ>
 static int launch_matvec(const double* K, int ldk, int n, const TZ* src, int lds, int s, double* part,
                          hipStream_t st) {
   const dim3 grid((n + kRowsPerWG - 1) / kRowsPerWG, (n + kMatvecCols - 1) / kMatvecCols);
+  ProfScope prof("matvec", st);
 #define HODLR_MV(SM) k_matvec<TZ, SM><<<grid, kRowsPerWG, 0, st>>>(K, ldk, n, src, lds, s, part)
   if (s <= 1) HODLR_MV(1);
   else if (s <= 2) HODLR_MV(2);
@@ -360,14 +361,23 @@ static int gmres_t(const double* K, int n, int ldk, hodlr_s* M, const double* B,
       } else {
         HODLR_TRY(launch_matvec<double>(K, ldk, n, src_d, n, s, part, st));
       }
-      k_orth<0><<<gch, kRowsPerWG, 0, st>>>(n, s, j, m1, V, w, part, nsplit, nullptr, 0, nullptr,
-                                            ws.hA.as<double>(), nullptr, nullptr, active);
-      k_orth<1><<<gch, kRowsPerWG, 0, st>>>(n, s, j, m1, V, w, part, nsplit, nullptr, 0,
-                                            ws.hA.as<double>(), ws.hB.as<double>(),
-                                            ws.hcol.as<double>(), nullptr, active);
-      k_orth<2><<<gch, kRowsPerWG, 0, st>>>(n, s, j, m1, V, w, part, nsplit, nullptr, 0,
-                                            ws.hB.as<double>(), nullptr, ws.hcol.as<double>(),
-                                            ws.npart.as<double>(), active);
+      {
+        ProfScope po("orth", st);
+        k_orth<0><<<gch, kRowsPerWG, 0, st>>>(n, s, j, m1, V, w, part, nsplit, nullptr, 0, nullptr,
+                                              ws.hA.as<double>(), nullptr, nullptr, active);
+      }
+      {
+        ProfScope po("orth", st);
+        k_orth<1><<<gch, kRowsPerWG, 0, st>>>(n, s, j, m1, V, w, part, nsplit, nullptr, 0,
+                                              ws.hA.as<double>(), ws.hB.as<double>(),
+                                              ws.hcol.as<double>(), nullptr, active);
+      }
+      {
+        ProfScope po("orth", st);
+        k_orth<2><<<gch, kRowsPerWG, 0, st>>>(n, s, j, m1, V, w, part, nsplit, nullptr, 0,
+                                              ws.hB.as<double>(), nullptr, ws.hcol.as<double>(),
+                                              ws.npart.as<double>(), active);
+      }
       k_givens<<<1, 64, 0, st>>>(s, j, m, nch, ws.hcol.as<double>(), ws.npart.as<double>(),
                                  ws.H.as<double>(), ws.cs.as<double>(), ws.sn.as<double>(),
                                  ws.g.as<double>(), ws.scal.as<double>(), ws.bnorm.as<double>(),

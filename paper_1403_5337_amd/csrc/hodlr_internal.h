@@ -140,6 +140,21 @@ int factor_impl(hodlr_s* h, hipStream_t s);
 int apply_impl(hodlr_s* h, void* X, int ldx, int nrhs, hipStream_t s);  // in place
 int ensure_work(hodlr_s* h, int ncols);
 
+// prof.hip: event timing of wrapped launches (hodlr_prof_enable)
+bool prof_on();
+void prof_mark(const char* name, hipStream_t s, bool begin);
+struct ProfScope {
+  const char* name;
+  hipStream_t s;
+  bool on;
+  ProfScope(const char* n, hipStream_t st) : name(n), s(st), on(prof_on()) {
+    if (on) prof_mark(name, s, true);
+  }
+  ~ProfScope() {
+    if (on) prof_mark(name, s, false);
+  }
+};
+
 // gmres.hip
 int gmres_impl(const double* K, int n, int ldk, hodlr_s* M, const double* B, int nrhs, int ldb,
                double* X, int ldx, double tol, int maxit, int restart, int* iters,

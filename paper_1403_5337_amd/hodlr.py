@@ -55,6 +55,8 @@ _SIGNATURES = {
     "hodlr_get_factors": (ctypes.c_int, [_vp, _vp, _vp, _vp]),
     "hodlr_destroy": (ctypes.c_int, [_vp]),
     "hodlr_last_error": (ctypes.c_char_p, []),
+    "hodlr_prof_enable": (ctypes.c_int, [ctypes.c_int]),
+    "hodlr_prof_query": (ctypes.c_int, [ctypes.c_char_p, _c_int_p, _c_dbl_p]),
 }
 
 _lib = None
@@ -265,3 +267,15 @@ def hodlr_permute_graph(rowptr: torch.Tensor, col: torch.Tensor, perm: torch.Ten
                                      n, _ptr(perm.to(torch.int32).contiguous()), _ptr(ro), _ptr(co),
                                      _stream(stream)))
     return ro, co
+
+
+def hodlr_prof_enable(on: bool):
+    _check(lib().hodlr_prof_enable(1 if on else 0))
+
+
+def hodlr_prof_query(name: str):
+    """(launches, total_ms) of the recorded launches of kernel `name`."""
+    n = ctypes.c_int()
+    ms = ctypes.c_double()
+    _check(lib().hodlr_prof_query(name.encode(), ctypes.byref(n), ctypes.byref(ms)))
+    return n.value, ms.value
