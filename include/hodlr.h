@@ -42,7 +42,8 @@ typedef enum {
 enum { HODLR_ACA = 0, HODLR_BDLR = 1 };
 
 typedef struct {
-  int leaf;       /* largest leaf block (>= 1).  The tree splits [lo,hi) at
+  int leaf;       /* largest leaf block, 1..184 (precision 32) or 1..128
+                     (precision 64).  The tree splits [lo,hi) at
                      lo + floor((hi-lo)/2) to the smallest depth L with
                      ceil(n / 2^L) <= leaf (Sec. 4.1 block sizes n/2^p). */
   double tol;     /* compression tolerance eps: the ACA stopping ratio
@@ -157,14 +158,20 @@ int hodlr_stats(hodlr_t h, int* nlevels, int* ranks, int* rcols);
  * hodlr_factor (afterwards the U panel holds the factorization). */
 int hodlr_get_factors(hodlr_t h, double* Upanel, double* Vpanel, hipStream_t stream);
 
+/* Frees the handle.  Synchronizes the device first (its device blocks go
+ * back to the library's allocator cache for reuse). */
 int hodlr_destroy(hodlr_t h);
+
+/* Returns every cached device block to the HIP runtime (synchronizes the
+ * device).  The library keeps freed device memory for reuse otherwise. */
+int hodlr_release_memory(void);
 
 /* Kernel timing for benchmarks.  hodlr_prof_enable(1) clears earlier records
  * and makes the library record a HIP event pair around each launch of its
  * main kernels, on the launch stream; hodlr_prof_enable(0) stops recording.
  * hodlr_prof_query(name) synchronizes those events and returns how many
  * launches of kernel `name` were recorded and their summed duration in ms.
- * Names: "aca", "leaf_inverse", "leaf_apply", "panel_tn", "schur_form",
+ * Names: "aca", "leaf_inverse", "leaf_apply", "panel_tn", "schur_form", "apply_leaf", "apply_level",
  * "schur_apply", "correct", "matvec", "orth".  Host-side pointers. */
 int hodlr_prof_enable(int on);
 int hodlr_prof_query(const char* name, int* launches, double* total_ms);

@@ -39,6 +39,9 @@ struct AcaTask {
 constexpr int kMaxBlockDim = 8192;  // largest block side (n <= 16384)
 constexpr unsigned kSpinLimit = 1u << 21;
 
+// Device-scope (agent) atomic loads and stores: coherent across the XCDs
+// without L2 write-back or invalidation.  The pivot records are only ever
+// accessed through these.
 __device__ __forceinline__ void st_agent(float* p, float v) {
   __hip_atomic_store(reinterpret_cast<unsigned*>(p), __float_as_uint(v), __ATOMIC_RELAXED,
                      __HIP_MEMORY_SCOPE_AGENT);
@@ -58,16 +61,20 @@ __device__ __forceinline__ double ld_agent(const double* p) {
       __HIP_MEMORY_SCOPE_AGENT));
 }
 
-// Barrier of the G workgroups of one group.  Returns false (uniformly) if
-// the wait timed out or another workgroup aborted.
+// Barrier of the G workgroups of one group.  Every record store is a
+// device-scope atomic store; each thread waits for its own stores to
+// complete (s_waitcnt), the workgroup meets, one thread bumps the group
+// counter and spins on it, and the records are then read with device-scope
+// atomic loads.  Returns false (uniformly) if the wait timed out or another
+// workgroup aborted.
 __device__ bool group_barrier(unsigned* bar, unsigned target, int* abort_flag, int* s_ok) {
-  __threadfence();
+  __builtin_amdgcn_s_waitcnt(0);
   __syncthreads();
   if (threadIdx.x == 0) {
-    __hip_atomic_fetch_add(bar, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+    __hip_atomic_fetch_add(bar, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     int ok = 1;
     unsigned spins = 0;
-    while (__hip_atomic_load(bar, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) < target) {
+    while (__hip_atomic_load(bar, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
       if (__hip_atomic_load(abort_flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
         ok = 0;
         break;
@@ -79,10 +86,10 @@ __device__ bool group_barrier(unsigned* bar, unsigned target, int* abort_flag, i
         break;
       }
     }
+    __builtin_amdgcn_s_waitcnt(0);
     *s_ok = ok;
   }
   __syncthreads();
-  __threadfence();
   return *s_ok != 0;
 }
 
@@ -92,7 +99,7 @@ template <typename T, int KCAP, int SLICE>
 __global__ void __launch_bounds__(kBlock)
     k_aca(const double* __restrict__ K, int ldk, const AcaTask* __restrict__ tasks,
           const int* __restrict__ wg_task, int wg_base, T* __restrict__ Ucap, T* __restrict__ Vcap,
-          int ldu, T* __restrict__ rec, int rec_stride, unsigned* __restrict__ bars,
+          int ldu, T* rec, int rec_stride, unsigned* bars,
           int* __restrict__ rank_out, int* __restrict__ status, T eps) {
   constexpr int LD = SLICE + 1;
   extern __shared__ __align__(16) unsigned char smem[];
@@ -163,24 +170,22 @@ __global__ void __launch_bounds__(kBlock)
         aborted = true;
         break;
       }
+      // one candidate record per workgroup, read in parallel after the fence
+      T hv = T(-2);
+      int hg = INT_MAX;
+      if (t < G) {
+        hv = ld_agent(recp(nb & 1, t));
+        hg = t;
+      }
+      T wv;
+      int win;
+      block_argmax(hv, hg, sv, si, wv, win);
+      const T* Rw = recp(nb & 1, win);
       if (t == 0) {
-        int win = 0;
-        T wv = ld_agent(recp(nb & 1, 0));
-        for (int gg = 1; gg < G; ++gg) {
-          const T v = ld_agent(recp(nb & 1, gg));
-          if (v > wv) {
-            wv = v;
-            win = gg;
-          }
-        }
-        const T* Rw = recp(nb & 1, win);
         s_bv = wv;
         s_j = (int)ld_agent(Rw + 1);
         s_piv = ld_agent(Rw + 2);
-        s_i = win;
       }
-      __syncthreads();
-      const T* Rw = recp(nb & 1, s_i);
       for (int l = t; l < k; l += nt) vrow[l] = ld_agent(Rw + 3 + l);
       ++nb;
     } else {
@@ -263,26 +268,32 @@ __global__ void __launch_bounds__(kBlock)
         break;
       }
       for (int idx = t; idx < 2 * k + 2; idx += nt) {
-        T s = T(0);
-        for (int gg = 0; gg < G; ++gg) s += ld_agent(recp(nb & 1, gg) + 3 + KCAP + idx);
-        dsum[idx] = s;
-      }
-      if (t == 0) {
-        int win = 0;
-        T wv = ld_agent(recp(nb & 1, 0));
-        for (int gg = 1; gg < G; ++gg) {
-          const T v = ld_agent(recp(nb & 1, gg));
-          if (v > wv) {
-            wv = v;
-            win = gg;
-          }
+        // issue up to 16 record loads before waiting on any of them
+        T acc = T(0);
+        for (int g0 = 0; g0 < G; g0 += 16) {
+          T v[16];
+#pragma unroll
+          for (int u = 0; u < 16; ++u)
+            v[u] = (g0 + u < G) ? ld_agent(recp(nb & 1, g0 + u) + 3 + KCAP + idx) : T(0);
+#pragma unroll
+          for (int u = 0; u < 16; ++u) acc += v[u];
         }
-        s_bv = wv;
-        s_i = (int)ld_agent(recp(nb & 1, win) + 1);
-        s_j = win;
+        dsum[idx] = acc;
       }
-      __syncthreads();
-      const T* Rw = recp(nb & 1, s_j);
+      T hv = T(-2);
+      int hg = INT_MAX;
+      if (t < G) {
+        hv = ld_agent(recp(nb & 1, t));
+        hg = t;
+      }
+      T wv;
+      int win;
+      block_argmax(hv, hg, sv, si, wv, win);
+      const T* Rw = recp(nb & 1, win);
+      if (t == 0) {
+        s_bv = wv;
+        s_i = (int)ld_agent(Rw + 1);
+      }
       for (int l = t; l <= k; l += nt) urow[l] = ld_agent(Rw + 3 + l);
       ++nb;
     } else {
@@ -358,21 +369,23 @@ static int aca_t(hodlr_s* h, const double* K, int ldk, T* Ucap, T* Vcap,
     if (tk.G > resident) return fail(HODLR_EINVAL, "ACA block needs more workgroups than fit");
 
   const int rec_stride = 3 + KCAP + 2 * KCAP + 2;
-  DevBuf d_tasks, d_wg, d_rec, d_bars;
+  DevBuf d_tasks, d_wg;
   HODLR_TRY(d_tasks.ensure(tasks.size() * sizeof(AcaTask)));
   HODLR_TRY(d_wg.ensure(total * sizeof(int)));
-  HODLR_TRY(d_rec.ensure((size_t)total * 2 * rec_stride * sizeof(T)));
-  HODLR_TRY(d_bars.ensure(total * sizeof(unsigned)));
+  const size_t rec_bytes = ((size_t)total * 2 * rec_stride * sizeof(T) + 255) / 256 * 256;
+  DevBuf d_rec;
+  HODLR_TRY(d_rec.ensure(rec_bytes + total * sizeof(unsigned)));
+  void* uc = d_rec.p;
   HODLR_HIP(hipMemcpyAsync(d_tasks.p, tasks.data(), tasks.size() * sizeof(AcaTask),
                            hipMemcpyHostToDevice, s));
   HODLR_HIP(hipMemcpyAsync(d_wg.p, wg_task.data(), total * sizeof(int), hipMemcpyHostToDevice, s));
-  HODLR_HIP(hipMemsetAsync(d_bars.p, 0, total * sizeof(unsigned), s));
+  T* p_rec = static_cast<T*>(uc);
+  unsigned* p_bars = reinterpret_cast<unsigned*>(static_cast<char*>(uc) + rec_bytes);
+  HODLR_HIP(hipMemsetAsync(p_bars, 0, total * sizeof(unsigned), s));
   HODLR_HIP(hipMemsetAsync(h->d_rank.p, 0, tr.nnodes() * sizeof(int), s));
 
   const AcaTask* p_tasks = d_tasks.as<AcaTask>();
   const int* p_wg = d_wg.as<int>();
-  T* p_rec = d_rec.as<T>();
-  unsigned* p_bars = d_bars.as<unsigned>();
   int* p_rank = h->d_rank.as<int>();
   int* p_status = h->status.as<int>();
   T teps = (T)h->tol;

@@ -2,7 +2,9 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <map>
 #include <memory>
+#include <mutex>
 #include <string>
 
 #include "hodlr_internal.h"
@@ -18,17 +20,81 @@ int fail(int code, const std::string& msg) {
   return code;
 }
 
+// ---------------------------------------------------------------------------
+// Caching device allocator.  Freed blocks go to a per-device free list and
+// are handed out again for requests between half their size and their size,
+// so repeated builds and solves do not call hipMalloc / hipFree (which also
+// synchronizes the device).  Blocks are returned only by
+// hodlr_release_memory().  A block is reused by later work on any stream, so
+// every internal temporary is released only after the work that used it has
+// been synchronized.
+// ---------------------------------------------------------------------------
+namespace {
+std::mutex g_alloc_mu;
+std::multimap<size_t, void*> g_free[64];
+int cur_device() {
+  int d = 0;
+  (void)hipGetDevice(&d);
+  return d < 0 ? 0 : (d > 63 ? 63 : d);
+}
+}  // namespace
+
+int dev_alloc(size_t nbytes, void** out) {
+  nbytes = (nbytes + 255) / 256 * 256;
+  {
+    std::lock_guard<std::mutex> lk(g_alloc_mu);
+    auto& fl = g_free[cur_device()];
+    auto it = fl.lower_bound(nbytes);
+    if (it != fl.end() && it->first <= 2 * nbytes) {
+      *out = it->second;
+      fl.erase(it);
+      return HODLR_OK;
+    }
+  }
+  void* p = nullptr;
+  hipError_t e = hipMalloc(&p, nbytes);
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    // give the cache back to the runtime once and retry
+    release_cached_memory();
+    e = hipMalloc(&p, nbytes);
+    if (e != hipSuccess)
+      return fail(HODLR_ENOMEM, std::string("hipMalloc(") + std::to_string(nbytes) +
+                                    "): " + hipGetErrorString(e));
+  }
+  *out = p;
+  return HODLR_OK;
+}
+
+void dev_free(void* p, size_t nbytes) {
+  if (!p) return;
+  nbytes = (nbytes + 255) / 256 * 256;
+  std::lock_guard<std::mutex> lk(g_alloc_mu);
+  g_free[cur_device()].emplace(nbytes, p);
+}
+
+void release_cached_memory() {
+  std::lock_guard<std::mutex> lk(g_alloc_mu);
+  int dev = cur_device();
+  (void)hipDeviceSynchronize();
+  for (auto& kv : g_free[dev]) (void)hipFree(kv.second);
+  g_free[dev].clear();
+}
+
+void DevBuf::release() {
+  if (p) dev_free(p, bytes);
+  p = nullptr;
+  bytes = 0;
+}
+
 int DevBuf::ensure(size_t nbytes) {
   if (nbytes <= bytes && p) return HODLR_OK;
   release();
   if (nbytes == 0) nbytes = 256;
-  hipError_t e = hipMalloc(&p, nbytes);
-  if (e != hipSuccess) {
-    p = nullptr;
-    return fail(HODLR_ENOMEM, std::string("hipMalloc(") + std::to_string(nbytes) +
-                                  "): " + hipGetErrorString(e));
-  }
-  bytes = nbytes;
+  void* q = nullptr;
+  HODLR_TRY(dev_alloc(nbytes, &q));
+  p = q;
+  bytes = (nbytes + 255) / 256 * 256;
   return HODLR_OK;
 }
 
@@ -143,6 +209,9 @@ static int check_opts(const hodlr_opts& o) {
     return fail(HODLR_EINVAL, "opts.method must be HODLR_ACA or HODLR_BDLR");
   if (o.precision != 32 && o.precision != 64)
     return fail(HODLR_EINVAL, "opts.precision must be 32 or 64");
+  if (o.leaf > leaf_cap(o.precision))
+    return fail(HODLR_EINVAL, "opts.leaf must be <= " + std::to_string(leaf_cap(o.precision)) +
+                                  " at this precision");
   if (o.max_rank < 0) return fail(HODLR_EINVAL, "opts.max_rank must be >= 0");
   if (o.method == HODLR_BDLR && o.bdlr_depth < 1)
     return fail(HODLR_EINVAL, "opts.bdlr_depth must be >= 1");
@@ -214,6 +283,7 @@ int hodlr_build_from_factors(int n, int leaf, int precision, const double* leave
   if (n < 1 || n > kMaxN) return fail(HODLR_EINVAL, "n out of range");
   if (leaf < 1 || leaf > kLeafMax) return fail(HODLR_EINVAL, "leaf out of range");
   if (precision != 32 && precision != 64) return fail(HODLR_EINVAL, "precision must be 32 or 64");
+  if (leaf > leaf_cap(precision)) return fail(HODLR_EINVAL, "leaf too large for this precision");
   if (!leaves) return fail(HODLR_EINVAL, "leaves is NULL");
   {
     Tree t0;
@@ -362,7 +432,15 @@ int hodlr_get_factors(hodlr_t h, double* Upanel, double* Vpanel, hipStream_t str
 }
 
 int hodlr_destroy(hodlr_t h) {
+  if (!h) return HODLR_OK;
+  // the handle's blocks go back to the allocator cache: finish pending work
+  HODLR_HIP(hipDeviceSynchronize());
   delete h;
+  return HODLR_OK;
+}
+
+int hodlr_release_memory(void) {
+  release_cached_memory();
   return HODLR_OK;
 }
 

@@ -65,62 +65,161 @@ template <typename T> __device__ T block_sum(T v, T* sv) {
 }
 
 // In-place Gauss-Jordan inversion with partial (row) pivoting of the b x b
-// matrix A (LDS, column-major, leading dimension ld).  On return A holds the
-// inverse of the row-permuted matrix; src[j] (LDS, b ints) names the column
-// of A that is column j of the inverse of the original matrix.  Returns false
-// (uniformly) if a zero or non-finite pivot is met.  ipiv, colk: LDS scratch
-// of b entries; sv/si: reduction scratch.
+// matrix A (LDS, column-major, leading dimension ld, b <= kGjMax).  On return
+// A holds the inverse of the row-permuted matrix; src[j] names the column of
+// A that is column j of the inverse of the original matrix.  Returns false
+// (uniformly) if a zero or non-finite pivot is met.
+//
+// Each pivot step costs three workgroup barriers: one wave finds the pivot
+// row p of column k; every thread snapshots row p, row k and column k; then
+// every thread rewrites the elements it owns as the row swap, the scaling of
+// the pivot row and the elimination of the other rows at once.
+constexpr int kGjMax = 256;
+
 template <typename T>
-__device__ bool gj_inverse(T* A, int b, int ld, int* ipiv, int* src, T* colk, T* sv, int* si) {
+struct GjScratch {
+  int ipiv[kGjMax], src[kGjMax];
+  T colk[kGjMax], prow[kGjMax], krow[kGjMax];
+  T pv;
+  int p;
+};
+
+template <typename T>
+__device__ bool gj_inverse(T* A, int b, int ld, GjScratch<T>& w) {
   const int t = threadIdx.x, nt = blockDim.x;
+  int lb = 0;
+  while ((1 << lb) < b) ++lb;
+  // thread t owns row (t & (bp-1)) of every (nt/bp)-th column: no div/mod
+  const int bp = 1 << lb, ri = t & (bp - 1), cstep = nt >> lb, c0 = t >> lb;
+  const bool owner = cstep > 0 && ri < b;
   bool ok = true;
   for (int k = 0; k < b; ++k) {
-    T v = T(-1);
-    int idx = INT_MAX;
-    for (int i = k + t; i < b; i += nt) argmax_merge(v, idx, dabs(A[i + k * ld]), i);
-    T pv;
-    int p;
-    block_argmax(v, idx, sv, si, pv, p);
+    if (t < 64) {
+      T v = T(-1);
+      int idx = INT_MAX;
+      for (int i = k + t; i < b; i += 64) argmax_merge(v, idx, dabs(A[i + k * ld]), i);
+      for (int o = 32; o > 0; o >>= 1) {
+        const T v2 = __shfl_xor(v, o, 64);
+        const int i2 = __shfl_xor(idx, o, 64);
+        argmax_merge(v, idx, v2, i2);
+      }
+      if (t == 0) {
+        w.pv = v;
+        w.p = idx;
+        w.ipiv[k] = idx;
+      }
+    }
+    __syncthreads();
+    const int p = w.p;
+    const T pv = w.pv;
     if (!(pv > T(0)) || !(pv < T(INFINITY)) || p >= b) {
       ok = false;
       break;
     }
-    if (t == 0) ipiv[k] = p;
-    if (p != k) {
-      for (int j = t; j < b; j += nt) {
-        T x = A[k + j * ld];
-        A[k + j * ld] = A[p + j * ld];
-        A[p + j * ld] = x;
-      }
+    const T inv = T(1) / A[p + k * ld];
+    // snapshot: scaled pivot row, old row k, column k
+    for (int j = t; j < b; j += nt) {
+      w.prow[j] = A[p + j * ld] * inv;
+      w.krow[j] = A[k + j * ld];
     }
+    for (int i = t; i < b; i += nt) w.colk[i] = A[i + k * ld];
     __syncthreads();
-    const T inv = T(1) / A[k + k * ld];
-    for (int i = t; i < b; i += nt) colk[i] = A[i + k * ld];
-    __syncthreads();
-    for (int j = t; j < b; j += nt) A[k + j * ld] = (j == k) ? inv : A[k + j * ld] * inv;
-    __syncthreads();
-    for (int e = t; e < b * b; e += nt) {
-      const int i = e % b, j = e / b;
-      if (i != k) {
-        const T rk = A[k + j * ld];
-        A[i + j * ld] = (j == k ? T(0) : A[i + j * ld]) - colk[i] * rk;
+    if (owner) {
+      T* Ai = A + ri;
+      const T* pr = w.prow;
+      if (ri == k) {
+#pragma unroll 4
+        for (int j = c0; j < b; j += cstep) Ai[j * ld] = pr[j];
+      } else if (ri == p) {  // old row k lands here
+        const T f = w.krow[k];
+        const T* kr = w.krow;
+#pragma unroll 4
+        for (int j = c0; j < b; j += cstep) Ai[j * ld] = kr[j] - f * pr[j];
+      } else {
+        const T f = w.colk[ri];
+#pragma unroll 4
+        for (int j = c0; j < b; j += cstep) Ai[j * ld] -= f * pr[j];
+      }
+      if (((k - c0) & (cstep - 1)) == 0 && k >= c0) {
+        // column k holds the multipliers: inv on the pivot row, -f * inv elsewhere
+        const T f = (ri == p) ? w.krow[k] : w.colk[ri];
+        Ai[k * ld] = (ri == k) ? inv : -f * inv;
       }
     }
     __syncthreads();
   }
   if (ok) {
     if (t == 0) {
-      for (int j = 0; j < b; ++j) src[j] = j;
+      for (int j = 0; j < b; ++j) w.src[j] = j;
       for (int k = b - 1; k >= 0; --k) {
-        int p = ipiv[k];
-        int x = src[k];
-        src[k] = src[p];
-        src[p] = x;
+        const int p = w.ipiv[k];
+        const int x = w.src[k];
+        w.src[k] = w.src[p];
+        w.src[p] = x;
       }
     }
     __syncthreads();
   }
   return ok;
+}
+
+// C = alpha * A * B + beta * C for column-major operands (any address space)
+// computed by the whole workgroup through 32 x 32 LDS tiles.  As, Bs: LDS,
+// 32 * 33 elements each.  beta == 0 does not read C.  C must not alias A, B.
+template <typename T>
+__device__ void wg_gemm(int m, int n, int k, T alpha, const T* A, int lda, const T* B, int ldb, T beta,
+                        T* C, int ldc, T* As, T* Bs) {
+  const int t = threadIdx.x, nt = blockDim.x, tx = t & 15, ty = (t >> 4) & 15;
+  const bool active = t < 256;
+  for (int i0 = 0; i0 < m; i0 += 32)
+    for (int j0 = 0; j0 < n; j0 += 32) {
+      T acc[2][2] = {{T(0), T(0)}, {T(0), T(0)}};
+      for (int k0 = 0; k0 < k; k0 += 32) {
+        // all loads of the two tiles are issued before any is stored
+        T av[4], bv[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          const int e = t + u * 256;
+          const int ii = e & 31, kk = e >> 5;
+          av[u] = (e < 1024 && i0 + ii < m && k0 + kk < k) ? A[(i0 + ii) + (size_t)(k0 + kk) * lda] : T(0);
+          bv[u] = (e < 1024 && k0 + ii < k && j0 + kk < n) ? B[(k0 + ii) + (size_t)(j0 + kk) * ldb] : T(0);
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          const int e = t + u * 256;
+          if (e < 1024 && t < 256) {
+            As[(e >> 5) * 33 + (e & 31)] = av[u];
+            Bs[(e >> 5) * 33 + (e & 31)] = bv[u];
+          }
+        }
+        __syncthreads();
+        if (active) {
+#pragma unroll 8
+          for (int kk = 0; kk < 32; ++kk) {
+            const T a0 = As[kk * 33 + tx], a1 = As[kk * 33 + tx + 16];
+            const T b0 = Bs[ty * 33 + kk], b1 = Bs[(ty + 16) * 33 + kk];
+            acc[0][0] += a0 * b0;
+            acc[0][1] += a0 * b1;
+            acc[1][0] += a1 * b0;
+            acc[1][1] += a1 * b1;
+          }
+        }
+        __syncthreads();
+      }
+      if (active) {
+#pragma unroll
+        for (int a = 0; a < 2; ++a)
+#pragma unroll
+          for (int c = 0; c < 2; ++c) {
+            const int i = i0 + tx + 16 * a, j = j0 + ty + 16 * c;
+            if (i < m && j < n) {
+              T* cp = C + i + (size_t)j * ldc;
+              *cp = (beta == T(0) ? T(0) : beta * *cp) + alpha * acc[a][c];
+            }
+          }
+      }
+      __syncthreads();
+    }
 }
 
 }  // namespace hodlr

@@ -76,16 +76,13 @@ __global__ void __launch_bounds__(kBlock)
                    const int* __restrict__ hi, int id0, int* __restrict__ status) {
   extern __shared__ __align__(16) unsigned char smem[];
   T* A = reinterpret_cast<T*>(smem);
-  __shared__ int ipiv[kLeafMax], src[kLeafMax];
-  __shared__ T colk[kLeafMax];
-  __shared__ T sv[kBlock / 64];
-  __shared__ int si[kBlock / 64];
+  __shared__ GjScratch<T> gw;
   const int leaf = blockIdx.x, id = id0 + leaf, t = threadIdx.x;
   const int b = hi[id] - lo[id], ld = b + 1;
   T* Gm = Kinv + (size_t)leaf * bmax * bmax;
   for (int e = t; e < b * b; e += blockDim.x) A[e % b + (e / b) * ld] = Gm[e % b + (size_t)(e / b) * bmax];
   __syncthreads();
-  const bool ok = gj_inverse(A, b, ld, ipiv, src, colk, sv, si);
+  const bool ok = gj_inverse(A, b, ld, gw);
   if (!ok) {
     if (t == 0) {
       atomicExch(status + 0, 1);
@@ -95,7 +92,7 @@ __global__ void __launch_bounds__(kBlock)
   }
   for (int e = t; e < b * b; e += blockDim.x) {
     const int i = e % b, j = e / b;
-    Gm[i + (size_t)j * bmax] = A[i + src[j] * ld];
+    Gm[i + (size_t)j * bmax] = A[i + gw.src[j] * ld];
   }
 }
 
@@ -118,7 +115,17 @@ __global__ void __launch_bounds__(kBlock)
     T acc[CT];
 #pragma unroll
     for (int c = 0; c < CT; ++c) acc[c] = T(0);
-    for (int kk = 0; kk < b; ++kk) {
+    int kk = 0;
+    for (; kk + 8 <= b; kk += 8) {
+      T a[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) a[u] = Ki[i + (size_t)(kk + u) * bmax];
+#pragma unroll
+      for (int u = 0; u < 8; ++u)
+#pragma unroll
+        for (int c = 0; c < CT; ++c) acc[c] += a[u] * Zt[kk + u + c * b];
+    }
+    for (; kk < b; ++kk) {
       const T a = Ki[i + (size_t)kk * bmax];
 #pragma unroll
       for (int c = 0; c < CT; ++c) acc[c] += a * Zt[kk + c * b];
@@ -148,11 +155,19 @@ __global__ void __launch_bounds__(kBlock)
 #pragma unroll
     for (int c = 0; c < 4; ++c) acc[a][c] = T(0);
   for (int k0 = 0; k0 < len; k0 += KC) {
-    for (int e = t; e < KC * TR; e += blockDim.x) {
-      const int kk = e % KC, r = e / KC, row = k0 + kk, col = r0 + r;
-      Ws[kk][r] = (row < len && col < rq) ? W[(size_t)(wcol0 + col) * ldw + l0 + row] : T(0);
-      const int m = m0 + r;
-      Zs[kk][r] = (row < len && m < zcols) ? Z[(size_t)m * ldz + l0 + row] : T(0);
+    T wv[KC * TR / kBlock], zv[KC * TR / kBlock];
+#pragma unroll
+    for (int u = 0; u < KC * TR / kBlock; ++u) {
+      const int e = t + u * kBlock;
+      const int kk = e % KC, r = e / KC, row = k0 + kk, col = r0 + r, m = m0 + r;
+      wv[u] = (row < len && col < rq) ? W[(size_t)(wcol0 + col) * ldw + l0 + row] : T(0);
+      zv[u] = (row < len && m < zcols) ? Z[(size_t)m * ldz + l0 + row] : T(0);
+    }
+#pragma unroll
+    for (int u = 0; u < KC * TR / kBlock; ++u) {
+      const int e = t + u * kBlock;
+      Ws[e % KC][e / KC] = wv[u];
+      Zs[e % KC][e / KC] = zv[u];
     }
     __syncthreads();
 #pragma unroll
@@ -180,6 +195,9 @@ __global__ void __launch_bounds__(kBlock)
     }
 }
 
+// Rows of a node are cut into chunks of kChunk rows in the fused solve.
+constexpr int kChunk = 256;
+
 // ---------------------------------------------------------------------------
 // Inverse capacitance matrix of every parent of level q (one workgroup each).
 // With A = V_b^T d_a (r_b x r_a) and B = V_a^T d_b (r_a x r_b) read from the
@@ -191,28 +209,25 @@ __global__ void __launch_bounds__(kBlock)
     k_schur_form(const T* __restrict__ G, int rq, int gcols, int offq, const int* __restrict__ rank,
                  int q, T* __restrict__ Sinv, int* __restrict__ status) {
   extern __shared__ __align__(16) unsigned char smem[];
-  T* M = reinterpret_cast<T*>(smem);
-  __shared__ int ipiv[kLeafMax], src[kLeafMax];
-  __shared__ T colk[kLeafMax];
-  __shared__ T sv[kBlock / 64];
-  __shared__ int si[kBlock / 64];
+  T* M = reinterpret_cast<T*>(smem);        // rq x (rq + 1)
+  T* As = M + (size_t)rq * (rq + 1);        // GEMM tiles
+  T* Bs = As + 32 * 33;
+  __shared__ GjScratch<T> gw;
   const int i = blockIdx.x, t = threadIdx.x, nt = blockDim.x;
   const int a = node_id(q, 2 * i), b = node_id(q, 2 * i + 1);
   const int ra = rank[a], rb = rank[b], ldm = ra + 1, lds = 2 * rq;
-  const T* Ga = G + (size_t)(2 * i) * rq * gcols;
-  const T* Gb = G + (size_t)(2 * i + 1) * rq * gcols;
-  auto Am = [&](int x, int y) { return Ga[x + (size_t)(offq + y) * rq]; };  // r_b x r_a
-  auto Bm = [&](int x, int y) { return Gb[x + (size_t)(offq + y) * rq]; };  // r_a x r_b
+  const T* Am = G + (size_t)(2 * i) * rq * gcols + (size_t)offq * rq;      // r_b x r_a, ld rq
+  const T* Bm = G + (size_t)(2 * i + 1) * rq * gcols + (size_t)offq * rq;  // r_a x r_b, ld rq
   T* S = Sinv + (size_t)i * lds * lds;
-  for (int e = t; e < ra * ra; e += nt) {
-    const int x = e % ra, y = e / ra;
-    T s = (x == y) ? T(1) : T(0);
-    for (int z = 0; z < rb; ++z) s -= Bm(x, z) * Am(z, y);
-    M[x + y * ldm] = s;
-  }
+  T* S22 = S + rb + (size_t)rb * lds;  // M^-1      (r_a x r_a)
+  T* S21 = S + rb;                     // -M^-1 B   (r_a x r_b)
+  T* S12 = S + (size_t)rb * lds;       // -A M^-1   (r_b x r_a)
+  // M = I - B A
+  wg_gemm(ra, ra, rb, T(-1), Bm, rq, Am, rq, T(0), M, ldm, As, Bs);
+  for (int x = t; x < ra; x += nt) M[x + x * ldm] += T(1);
   __syncthreads();
   if (ra > 0) {
-    const bool ok = gj_inverse(M, ra, ldm, ipiv, src, colk, sv, si);
+    const bool ok = gj_inverse(M, ra, ldm, gw);
     if (!ok) {
       if (t == 0) {
         atomicExch(status + 0, 2);
@@ -221,50 +236,36 @@ __global__ void __launch_bounds__(kBlock)
       return;
     }
   }
-  auto Mi = [&](int x, int y) { return M[x + src[y] * ldm]; };  // M^-1
-  // S[rb + x, rb + y] = M^-1 ; S[rb + x, y] = -M^-1 B ; S[x, rb + y] = -A M^-1
-  for (int e = t; e < ra * ra; e += nt) {
-    const int x = e % ra, y = e / ra;
-    S[(rb + x) + (size_t)(rb + y) * lds] = Mi(x, y);
-  }
-  for (int e = t; e < ra * rb; e += nt) {
-    const int x = e % ra, y = e / ra;
-    T s = 0;
-    for (int z = 0; z < ra; ++z) s += Mi(x, z) * Bm(z, y);
-    S[(rb + x) + (size_t)y * lds] = -s;
-  }
-  for (int e = t; e < rb * ra; e += nt) {
-    const int x = e % rb, y = e / rb;
-    T s = 0;
-    for (int z = 0; z < ra; ++z) s += Am(x, z) * Mi(z, y);
-    S[x + (size_t)(rb + y) * lds] = -s;
-  }
+  for (int y = 0; y < ra; ++y)
+    for (int x = t; x < ra; x += nt) S22[x + (size_t)y * lds] = M[x + gw.src[y] * ldm];
   __syncthreads();
-  // S[x, y] = I - A * S[rb : rb+ra, y]   (= I + A M^-1 B)
-  for (int e = t; e < rb * rb; e += nt) {
-    const int x = e % rb, y = e / rb;
-    T s = (x == y) ? T(1) : T(0);
-    for (int z = 0; z < ra; ++z) s -= Am(x, z) * S[(rb + z) + (size_t)y * lds];
-    S[x + (size_t)y * lds] = s;
-  }
+  wg_gemm(ra, rb, ra, T(-1), S22, lds, Bm, rq, T(0), S21, lds, As, Bs);
+  wg_gemm(rb, ra, ra, T(-1), Am, rq, S22, lds, T(0), S12, lds, As, Bs);
+  // S11 = I + A M^-1 B = I - A S21
+  wg_gemm(rb, rb, ra, T(-1), Am, rq, S21, lds, T(0), S, lds, As, Bs);
+  for (int x = t; x < rb; x += nt) S[x + (size_t)x * lds] += T(1);
 }
 
 // y = S^-1 [t_a; t_b] for every parent of level q: t_a = G_a(0:r_b, 0:ccols),
 // t_b = G_b(0:r_a, 0:ccols).  Y is (2 rq) x ccols per parent (ld 2 rq).
 template <typename T, int CT>
 __global__ void __launch_bounds__(kBlock)
-    k_schur_apply(const T* __restrict__ G, int rq, int gcols, int ccols, const int* __restrict__ rank,
-                  int q, const T* __restrict__ Sinv, T* __restrict__ Yb) {
+    k_schur_apply(const T* __restrict__ G, int rq, int gcols, int ccols, int nchunk,
+                  const int* __restrict__ rank, int q, const T* __restrict__ Sinv, T* __restrict__ Yb) {
   __shared__ T Tc[2 * kRankCap32 * CT];
   const int i = blockIdx.x, c0 = blockIdx.y * CT, t = threadIdx.x, nt = blockDim.x;
   const int ra = rank[node_id(q, 2 * i)], rb = rank[node_id(q, 2 * i + 1)], r = ra + rb;
   const int lds = 2 * rq, nc = min(CT, ccols - c0);
-  const T* Ga = G + (size_t)(2 * i) * rq * gcols;
-  const T* Gb = G + (size_t)(2 * i + 1) * rq * gcols;
+  const size_t cs = (size_t)rq * gcols;  // one chunk's products
+  const T* Ga = G + (size_t)(2 * i) * nchunk * cs;
+  const T* Gb = G + (size_t)(2 * i + 1) * nchunk * cs;
   for (int e = t; e < r * CT; e += nt) {
     const int z = e % r, c = e / r;
     T v = T(0);
-    if (c < nc) v = (z < rb) ? Ga[z + (size_t)(c0 + c) * rq] : Gb[(z - rb) + (size_t)(c0 + c) * rq];
+    if (c < nc) {
+      const T* Gx = (z < rb) ? Ga + z : Gb + (z - rb);
+      for (int ch = 0; ch < nchunk; ++ch) v += Gx[ch * cs + (size_t)(c0 + c) * rq];
+    }
     Tc[z + c * r] = v;
   }
   __syncthreads();
@@ -274,7 +275,17 @@ __global__ void __launch_bounds__(kBlock)
     T acc[CT];
 #pragma unroll
     for (int c = 0; c < CT; ++c) acc[c] = T(0);
-    for (int z = 0; z < r; ++z) {
+    int z = 0;
+    for (; z + 8 <= r; z += 8) {
+      T sv[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) sv[u] = S[x + (size_t)(z + u) * lds];
+#pragma unroll
+      for (int u = 0; u < 8; ++u)
+#pragma unroll
+        for (int c = 0; c < CT; ++c) acc[c] += sv[u] * Tc[z + u + c * r];
+    }
+    for (; z < r; ++z) {
       const T s = S[x + (size_t)z * lds];
 #pragma unroll
       for (int c = 0; c < CT; ++c) acc[c] += s * Tc[z + c * r];
@@ -309,12 +320,243 @@ __global__ void __launch_bounds__(kBlock)
   T acc[CT];
 #pragma unroll
   for (int k = 0; k < CT; ++k) acc[k] = T(0);
-  for (int l = 0; l < rc; ++l) {
+  int l = 0;
+  for (; l + 8 <= rc; l += 8) {
+    T d[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) d[u] = Yd[(size_t)(offq + l + u) * ldy + row];
+#pragma unroll
+    for (int u = 0; u < 8; ++u)
+#pragma unroll
+      for (int k = 0; k < CT; ++k) acc[k] += d[u] * Yo[l + u + k * rc];
+  }
+  for (; l < rc; ++l) {
     const T d = Yd[(size_t)(offq + l) * ldy + row];
 #pragma unroll
     for (int k = 0; k < CT; ++k) acc[k] += d * Yo[l + k * rc];
   }
   for (int k = 0; k < nc; ++k) Z[(size_t)(c0 + k) * ldz + row] -= acc[k];
+}
+
+// ---------------------------------------------------------------------------
+// The solve (Sec. 4.3.2) fused into L + 1 launches for few right-hand sides.
+//
+// P^(q) holds partial products W(rows, level-q block)^T x(rows) over "units"
+// of rows: for q = L one unit per leaf; for q < L one unit per (level-(q+1)
+// node, row chunk), so the units of a level-q node are contiguous.
+// Launch "leaf": x_leaf = Kinv_leaf x_leaf, then the units of P^(L).
+// Launch "level q" (one workgroup per level-q node and row chunk): add the
+// units of both siblings into t = [t_a; t_b], form the part of y = S^-1 t
+// that multiplies this node's d, correct the chunk's rows of x, then write
+// the chunk's unit of P^(q-1).
+// ---------------------------------------------------------------------------
+template <typename T, int SM>
+__device__ void unit_products(const T* __restrict__ W, int ldw, int wcol0, int rp, int row0, int rn,
+                              const T* xs, int nc, T* __restrict__ Pu) {
+  // xs holds kChunk rows per column (zero beyond rn); a wave takes two
+  // columns of W at a time and issues all their loads before reducing
+  constexpr int NR = kChunk / 64;
+  const int t = threadIdx.x, wave = t >> 6, lane = t & 63, nw = blockDim.x >> 6;
+  for (int r0 = wave; r0 < rp; r0 += 2 * nw) {
+    const int r1 = r0 + nw;
+    const bool two = r1 < rp;
+    const T* W0 = W + (size_t)(wcol0 + r0) * ldw + row0;
+    const T* W1 = W + (size_t)(wcol0 + (two ? r1 : r0)) * ldw + row0;
+    T w0[NR], w1[NR];
+#pragma unroll
+    for (int u = 0; u < NR; ++u) {
+      const int i = lane + 64 * u;
+      w0[u] = i < rn ? W0[i] : T(0);
+      w1[u] = i < rn ? W1[i] : T(0);
+    }
+    T a0[SM], a1[SM];
+#pragma unroll
+    for (int c = 0; c < SM; ++c) {
+      a0[c] = T(0);
+      a1[c] = T(0);
+    }
+#pragma unroll
+    for (int u = 0; u < NR; ++u)
+#pragma unroll
+      for (int c = 0; c < SM; ++c) {
+        const T x = xs[c * kChunk + lane + 64 * u];
+        a0[c] += w0[u] * x;
+        a1[c] += w1[u] * x;
+      }
+#pragma unroll
+    for (int c = 0; c < SM; ++c) {
+      a0[c] = wave_sum(a0[c]);
+      a1[c] = wave_sum(a1[c]);
+    }
+    if (lane < nc) {
+      T v0 = a0[0], v1 = a1[0];
+#pragma unroll
+      for (int c = 1; c < SM; ++c)
+        if (lane == c) {
+          v0 = a0[c];
+          v1 = a1[c];
+        }
+      Pu[r0 + (size_t)lane * rp] = v0;
+      if (two) Pu[r1 + (size_t)lane * rp] = v1;
+    }
+  }
+}
+
+template <typename T, int SM>
+__global__ void __launch_bounds__(kBlock)
+    k_apply_leaf(const T* __restrict__ Kinv, int bmax, const int* __restrict__ lo,
+                 const int* __restrict__ hi, int idL, T* __restrict__ X, int ldx, int nc,
+                 const T* __restrict__ W, int ldw, int offL, int rL, T* __restrict__ P) {
+  __shared__ T xs[SM * kChunk];
+  __shared__ T ys[SM * kChunk];
+  const int leaf = blockIdx.x, id = idL + leaf, t = threadIdx.x;
+  const int l0 = lo[id], b = hi[id] - l0;
+  const T* Ki = Kinv + (size_t)leaf * bmax * bmax;
+  for (int e = t; e < SM * kChunk; e += blockDim.x) {
+    const int i = e % kChunk, c = e / kChunk;
+    xs[e] = (i < b && c < nc) ? X[(size_t)c * ldx + l0 + i] : T(0);
+  }
+  __syncthreads();
+  for (int i = t; i < b; i += blockDim.x) {
+    T acc[SM];
+#pragma unroll
+    for (int c = 0; c < SM; ++c) acc[c] = T(0);
+    int kk = 0;
+    for (; kk + 8 <= b; kk += 8) {
+      T a[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) a[u] = Ki[i + (size_t)(kk + u) * bmax];
+#pragma unroll
+      for (int u = 0; u < 8; ++u)
+#pragma unroll
+        for (int c = 0; c < SM; ++c) acc[c] += a[u] * xs[c * kChunk + kk + u];
+    }
+    for (; kk < b; ++kk) {
+      const T a = Ki[i + (size_t)kk * bmax];
+#pragma unroll
+      for (int c = 0; c < SM; ++c) acc[c] += a * xs[c * kChunk + kk];
+    }
+#pragma unroll
+    for (int c = 0; c < SM; ++c) {
+      ys[c * kChunk + i] = acc[c];
+      if (c < nc) X[(size_t)c * ldx + l0 + i] = acc[c];
+    }
+  }
+  for (int e = t; e < SM * kChunk; e += blockDim.x)
+    if (e % kChunk >= b) ys[e] = T(0);
+  __syncthreads();
+  if (rL > 0) unit_products<T, SM>(W, ldw, offL, rL, l0, b, ys, nc, P + (size_t)leaf * rL * nc);
+}
+
+template <typename T, int SM>
+__global__ void __launch_bounds__(kBlock)
+    k_apply_level(int q, const int* __restrict__ lo, const int* __restrict__ hi,
+                  const int* __restrict__ rank, T* __restrict__ X, int ldx, int nc,
+                  const T* __restrict__ Y, int ldy, int offq, int rq, const T* __restrict__ Sinv,
+                  const T* __restrict__ Pin, int upn, int nch, const T* __restrict__ W, int offp,
+                  int rp, T* __restrict__ Pout) {
+  constexpr int ZT = 32;  // columns of S^-1 staged per LDS tile
+  __shared__ T tcat[2 * kRankCap32 * SM];
+  __shared__ T yo[kRankCap32 * SM];
+  __shared__ T xs[SM * kChunk];
+  __shared__ T Stile[kRankCap32 * ZT];
+  const int c = blockIdx.x, ch = blockIdx.y, t = threadIdx.x, nt = blockDim.x;
+  const int par = c >> 1, left = (c & 1) == 0;
+  const int ia = node_id(q, 2 * par), ib = node_id(q, 2 * par + 1), id = node_id(q, c);
+  const int ra = rank[ia], rb = rank[ib], r = ra + rb;
+  const size_t us = (size_t)rq * nc;  // one unit's products
+  // t_a = V_b^T x_a (r_b x nc) from the units of a, t_b = V_a^T x_b from those of b
+  for (int e = t; e < r * nc; e += nt) {
+    const int z = e % r, cc = e / r;
+    const int node = (z < rb) ? 2 * par : 2 * par + 1;
+    const int zz = (z < rb) ? z : z - rb;
+    const T* P0 = Pin + (size_t)node * upn * us + zz + (size_t)cc * rq;
+    T v = T(0);
+    int u = 0;
+    for (; u + 8 <= upn; u += 8) {
+      T pv[8];
+#pragma unroll
+      for (int x = 0; x < 8; ++x) pv[x] = P0[(u + x) * us];
+#pragma unroll
+      for (int x = 0; x < 8; ++x) v += pv[x];
+    }
+    for (; u < upn; ++u) v += P0[u * us];
+    tcat[z + cc * r] = v;
+  }
+  __syncthreads();
+  const int rc = left ? ra : rb, yoff = left ? rb : 0, lds = 2 * rq;
+  const T* S = Sinv + (size_t)par * lds * lds + yoff;
+  // y_other = S^-1(yoff : yoff + rc, :) t, the rows of S^-1 staged through LDS
+  T yacc[SM];
+#pragma unroll
+  for (int cc = 0; cc < SM; ++cc) yacc[cc] = T(0);
+  for (int z0 = 0; z0 < r; z0 += ZT) {
+    const int zn = min(ZT, r - z0);
+    for (int e0 = 0; e0 < rc * ZT; e0 += 4 * nt) {
+      T sv4[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int e = e0 + t + u * nt;
+        const int x = e % rc, zz = e / rc;
+        sv4[u] = (e < rc * ZT && zz < zn) ? S[x + (size_t)(z0 + zz) * lds] : T(0);
+      }
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int e = e0 + t + u * nt;
+        if (e < rc * ZT) Stile[e] = sv4[u];
+      }
+    }
+    __syncthreads();
+    if (t < rc) {
+      for (int zz = 0; zz < zn; ++zz) {
+        const T sv = Stile[t + zz * rc];
+#pragma unroll
+        for (int cc = 0; cc < SM; ++cc) yacc[cc] += sv * tcat[z0 + zz + cc * r];
+      }
+    }
+    __syncthreads();
+  }
+  if (t < rc)
+#pragma unroll
+    for (int cc = 0; cc < SM; ++cc) yo[t + cc * rc] = yacc[cc];
+  __syncthreads();
+  const int row0 = lo[id] + ch * kChunk, rn = min(kChunk, hi[id] - row0);
+  for (int i = t; i < kChunk; i += nt) {
+    T acc[SM];
+#pragma unroll
+    for (int cc = 0; cc < SM; ++cc) acc[cc] = T(0);
+    if (i < rn) {
+      int l = 0;
+      for (; l + 8 <= rc; l += 8) {
+        T d[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) d[u] = Y[(size_t)(offq + l + u) * ldy + row0 + i];
+#pragma unroll
+        for (int u = 0; u < 8; ++u)
+#pragma unroll
+          for (int cc = 0; cc < SM; ++cc) acc[cc] += d[u] * yo[l + u + cc * rc];
+      }
+      for (; l < rc; ++l) {
+        const T d = Y[(size_t)(offq + l) * ldy + row0 + i];
+#pragma unroll
+        for (int cc = 0; cc < SM; ++cc) acc[cc] += d * yo[l + cc * rc];
+      }
+    }
+#pragma unroll
+    for (int cc = 0; cc < SM; ++cc) {
+      T v = T(0);
+      if (i < rn && cc < nc) {
+        v = X[(size_t)cc * ldx + row0 + i] - acc[cc];
+        X[(size_t)cc * ldx + row0 + i] = v;
+      }
+      xs[cc * kChunk + i] = v;
+    }
+  }
+  __syncthreads();
+  if (Pout && rp > 0 && rn > 0)
+    unit_products<T, SM>(W, ldy, offp, rp, row0, rn, xs, nc, Pout + ((size_t)c * nch + ch) * rp * nc);
+  else if (Pout && rp > 0)
+    for (int e = t; e < rp * nc; e += nt) Pout[((size_t)c * nch + ch) * rp * nc + e] = T(0);
 }
 
 // ---------------------------------------------------------------------------
@@ -337,9 +579,20 @@ int ensure_work(hodlr_s* h, int ncols) {
   for (int q = 1; q <= t.L; ++q) {
     size_t rq = h->rcols.empty() ? 0 : h->rcols[q - 1];
     size_t offq = h->off.empty() ? 0 : h->off[q - 1];
-    g = std::max(g, (size_t)(1 << q) * rq * std::max<size_t>(offq + rq, ncols));
+    const size_t nch = (t.max_size(q) + kChunk - 1) / kChunk;
+    g = std::max(g, (size_t)(1 << q) * rq * std::max<size_t>(offq + rq, nch * 16));
     y = std::max(y, (size_t)(1 << (q - 1)) * 2 * rq * std::max<size_t>(offq, ncols));
   }
+  // the fused solve keeps two unit buffers of partial products in G
+  size_t units = 1;
+  for (int q = 1; q <= t.L; ++q) {
+    const size_t rq = h->rcols.empty() ? 0 : h->rcols[q - 1];
+    const size_t nu = (q == t.L) ? ((size_t)1 << q)
+                                 : ((size_t)2 << q) * ((t.max_size(q + 1) + kChunk - 1) / kChunk);
+    units = std::max(units, nu * rq * 16);
+  }
+  h->p_half = units;
+  g = std::max(g, 2 * units);
   HODLR_TRY(h->G.ensure(g * h->esize));
   HODLR_TRY(h->Ybuf.ensure(y * h->esize));
   return HODLR_OK;
@@ -427,7 +680,7 @@ constexpr int kCT = 8;  // columns per workgroup in the leaf / Woodbury kernels
 
 template <typename T>
 static int level_solve(hodlr_s* h, int q, T* Z, int ldz, int zcols, const T* G, int gcols,
-                       hipStream_t s) {
+                       int nchunk, hipStream_t s) {
   // y = S^-1 t for every parent, then the corrections of the level-q nodes
   const Tree& t = h->tree;
   const int rq = h->rcols[q - 1], offq = h->off[q - 1];
@@ -436,7 +689,7 @@ static int level_solve(hodlr_s* h, int q, T* Z, int ldz, int zcols, const T* G, 
   {
     ProfScope prof_("schur_apply", s);
     k_schur_apply<T, kCT><<<dim3(1 << (q - 1), cdiv(zcols, kCT)), kBlock, 0, s>>>(
-        G, rq, gcols, zcols, h->d_rank.as<int>(), q, Sinv, Yb);
+        G, rq, gcols, zcols, nchunk, h->d_rank.as<int>(), q, Sinv, Yb);
   }
   HODLR_HIP(hipGetLastError());
   {
@@ -484,7 +737,7 @@ static int factor_t(hodlr_s* h, hipStream_t s) {
           W, n, offq, rq, Y, n, zc, h->d_lo.as<int>(), h->d_hi.as<int>(), node_id(q, 0), G);
     }
     HODLR_HIP(hipGetLastError());
-    const size_t lds_s = (size_t)rq * (rq + 1) * sizeof(T);
+    const size_t lds_s = ((size_t)rq * (rq + 1) + 2 * 32 * 33) * sizeof(T);
     HODLR_TRY(allow_lds(k_schur_form<T>, lds_s));
     {
       ProfScope prof_("schur_form", s);
@@ -493,7 +746,7 @@ static int factor_t(hodlr_s* h, hipStream_t s) {
                                                            h->status.as<int>());
     }
     HODLR_HIP(hipGetLastError());
-    if (offq > 0) HODLR_TRY(level_solve<T>(h, q, Y, n, offq, G, zc, s));
+    if (offq > 0) HODLR_TRY(level_solve<T>(h, q, Y, n, offq, G, zc, 1, s));
   }
   return HODLR_OK;
 }
@@ -502,32 +755,45 @@ int factor_impl(hodlr_s* h, hipStream_t s) {
   return h->precision == 64 ? factor_t<double>(h, s) : factor_t<float>(h, s);
 }
 
-template <typename T>
-static int apply_t(hodlr_s* h, T* X, int ldx, int nrhs, hipStream_t s) {
+template <typename T, int SM>
+static int apply_fused(hodlr_s* h, T* X, int ldx, int nc, hipStream_t s) {
   const Tree& t = h->tree;
   const int n = t.n, L = t.L;
-  for (int c0 = 0; c0 < nrhs; c0 += 64) {
-    const int nc = std::min(64, nrhs - c0);
-    T* Xc = X + (size_t)c0 * ldx;
+  T* P[2] = {h->G.as<T>(), h->G.as<T>() + h->p_half};
+  const int rL = L > 0 ? h->rcols[L - 1] : 0, offL = L > 0 ? h->off[L - 1] : 0;
+  {
+    ProfScope prof_("apply_leaf", s);
+    k_apply_leaf<T, SM><<<h->nleaf, kBlock, 0, s>>>(h->Kinv.as<T>(), h->bmax, h->d_lo.as<int>(),
+                                                   h->d_hi.as<int>(), node_id(L, 0), X, ldx, nc,
+                                                   h->W.as<T>(), n, offL, rL, P[0]);
+  }
+  HODLR_HIP(hipGetLastError());
+  int cur = 0;
+  for (int q = L; q >= 1; --q) {
+    const int rq = h->rcols[q - 1], offq = h->off[q - 1];
+    const int nch = cdiv(t.max_size(q), kChunk);
+    const int upn = (q == L) ? 1 : 2 * cdiv(t.max_size(q + 1), kChunk);
+    const int rp = q > 1 ? h->rcols[q - 2] : 0, offp = q > 1 ? h->off[q - 2] : 0;
+    const T* Sinv = h->Sinv.as<T>() + h->sinv_off[q - 1];
     {
-      ProfScope prof_("leaf_apply", s);
-      k_leaf_apply<T, kCT><<<dim3(h->nleaf, cdiv(nc, kCT)), kBlock, 0, s>>>(
-          h->Kinv.as<T>(), h->bmax, h->d_lo.as<int>(), h->d_hi.as<int>(), node_id(L, 0), Xc, ldx, nc);
+      ProfScope prof_("apply_level", s);
+      k_apply_level<T, SM><<<dim3(1 << q, nch), kBlock, 0, s>>>(
+          q, h->d_lo.as<int>(), h->d_hi.as<int>(), h->d_rank.as<int>(), X, ldx, nc, h->Y.as<T>(), n,
+          offq, rq, Sinv, P[cur], upn, nch, h->W.as<T>(), offp, rp, q > 1 ? P[cur ^ 1] : nullptr);
     }
     HODLR_HIP(hipGetLastError());
-    for (int q = L; q >= 1; --q) {
-      const int rq = h->rcols[q - 1], offq = h->off[q - 1];
-      if (rq == 0) continue;
-      T* G = h->G.as<T>();
-      {
-        ProfScope prof_("panel_tn", s);
-        k_panel_tn<T><<<dim3(1 << q, cdiv(rq, 64), cdiv(nc, 64)), kBlock, 0, s>>>(
-            h->W.as<T>(), n, offq, rq, Xc, ldx, nc, h->d_lo.as<int>(), h->d_hi.as<int>(),
-            node_id(q, 0), G);
-      }
-      HODLR_HIP(hipGetLastError());
-      HODLR_TRY(level_solve<T>(h, q, Xc, ldx, nc, G, nc, s));
-    }
+    cur ^= 1;
+  }
+  return HODLR_OK;
+}
+
+template <typename T>
+static int apply_t(hodlr_s* h, T* X, int ldx, int nrhs, hipStream_t s) {
+  for (int c0 = 0; c0 < nrhs; c0 += 16) {
+    const int nc = std::min(16, nrhs - c0);
+    T* Xc = X + (size_t)c0 * ldx;
+    if (nc <= 8) HODLR_TRY((apply_fused<T, 8>(h, Xc, ldx, nc, s)));
+    else HODLR_TRY((apply_fused<T, 16>(h, Xc, ldx, nc, s)));
   }
   return HODLR_OK;
 }

@@ -89,14 +89,30 @@ __global__ void __launch_bounds__(kRowsPerWG)
   double wi = 0.0;
   if (PASS == 0) {
     if (valid) {
-      for (int sp = 0; sp < nsplit; ++sp) wi += part[((size_t)sp * s + k) * n + i];
+      int sp = 0;
+      for (; sp + 8 <= nsplit; sp += 8) {
+        double pv[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) pv[u] = part[((size_t)(sp + u) * s + k) * n + i];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) wi += pv[u];
+      }
+      for (; sp < nsplit; ++sp) wi += part[((size_t)sp * s + k) * n + i];
       if (b) wi = b[(size_t)k * ldb + i] - wi;
       w[(size_t)k * n + i] = wi;
     }
   } else {
     for (int l = t; l <= j; l += nt) {
       double h = 0.0;
-      for (int c = 0; c < nch; ++c) h += hin[((size_t)c * s + k) * m1 + l];
+      int c = 0;
+      for (; c + 8 <= nch; c += 8) {
+        double hv[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) hv[u] = hin[((size_t)(c + u) * s + k) * m1 + l];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) h += hv[u];
+      }
+      for (; c < nch; ++c) h += hin[((size_t)c * s + k) * m1 + l];
       hs[l] = h;
     }
     __syncthreads();
@@ -108,7 +124,15 @@ __global__ void __launch_bounds__(kRowsPerWG)
     }
     if (valid) {
       wi = w[(size_t)k * n + i];
-      for (int l = 0; l <= j; ++l) wi -= V[((size_t)l * s + k) * n + i] * hs[l];
+      int l = 0;
+      for (; l + 8 <= j + 1; l += 8) {
+        double v[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) v[u] = V[((size_t)(l + u) * s + k) * n + i];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) wi -= v[u] * hs[l + u];
+      }
+      for (; l <= j; ++l) wi -= V[((size_t)l * s + k) * n + i] * hs[l];
       w[(size_t)k * n + i] = wi;
     }
   }
@@ -121,15 +145,29 @@ __global__ void __launch_bounds__(kRowsPerWG)
   __syncthreads();
   const int wave = t >> 6, lane = t & 63, nw = nt >> 6;
   const int r0 = ch * kRowsPerWG;
-  for (int l = wave; l <= j; l += nw) {
-    double d = 0.0;
+  // two basis vectors per wave at a time, all loads issued before reducing
+  for (int l = wave; l <= j; l += 2 * nw) {
+    const int l1 = l + nw;
+    const bool two = l1 <= j;
+    double v0[kRowsPerWG / 64], v1[kRowsPerWG / 64];
 #pragma unroll
     for (int r = 0; r < kRowsPerWG / 64; ++r) {
       const int row = r0 + lane + 64 * r;
-      if (row < n) d += V[((size_t)l * s + k) * n + row] * ws[lane + 64 * r];
+      v0[r] = row < n ? V[((size_t)l * s + k) * n + row] : 0.0;
+      v1[r] = (two && row < n) ? V[((size_t)l1 * s + k) * n + row] : 0.0;
     }
-    d = wave_sum(d);
-    if (lane == 0) hout[((size_t)ch * s + k) * m1 + l] = d;
+    double d0 = 0.0, d1 = 0.0;
+#pragma unroll
+    for (int r = 0; r < kRowsPerWG / 64; ++r) {
+      d0 += v0[r] * ws[lane + 64 * r];
+      d1 += v1[r] * ws[lane + 64 * r];
+    }
+    d0 = wave_sum(d0);
+    d1 = wave_sum(d1);
+    if (lane == 0) {
+      hout[((size_t)ch * s + k) * m1 + l] = d0;
+      if (two) hout[((size_t)ch * s + k) * m1 + l1] = d1;
+    }
   }
 }
 
@@ -260,14 +298,26 @@ __global__ void k_xupdate(int n, int s, int m, double* __restrict__ X, int ldx, 
   const int nk = steps[k];
   if (nk == 0) return;
   double acc = 0.0;
-  for (int l = 0; l < nk; ++l) acc += (double)Z[((size_t)l * s + k) * n + i] * y[(size_t)k * m + l];
+  int l = 0;
+  for (; l + 8 <= nk; l += 8) {
+    double z[8], yy[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      z[u] = (double)Z[((size_t)(l + u) * s + k) * n + i];
+      yy[u] = y[(size_t)k * m + l + u];
+    }
+#pragma unroll
+    for (int u = 0; u < 8; ++u) acc += z[u] * yy[u];
+  }
+  for (; l < nk; ++l) acc += (double)Z[((size_t)l * s + k) * n + i] * y[(size_t)k * m + l];
   X[(size_t)k * ldx + i] += acc;
 }
 
 // ---------------------------------------------------------------------------
 struct GmresWork {
   DevBuf V, Z, w, part, hA, hB, hcol, H, cs, sn, g, y, npart, scal, bnorm, relres, ints;
-  int* host_flags = nullptr;
+  int* host_flags = nullptr;  // pinned: [0, 64) cycle start, [64, 192) two step slots
+  hipEvent_t ev[2] = {nullptr, nullptr};
   std::mutex mu;
 };
 
@@ -321,7 +371,9 @@ static int gmres_t(const double* K, int n, int ldk, hodlr_s* M, const double* B,
   HODLR_TRY(ws.bnorm.ensure(s * sizeof(double)));
   HODLR_TRY(ws.relres.ensure(s * sizeof(double)));
   HODLR_TRY(ws.ints.ensure(3 * 64 * sizeof(int)));
-  if (!ws.host_flags) HODLR_HIP(hipHostMalloc(reinterpret_cast<void**>(&ws.host_flags), 64 * sizeof(int)));
+  if (!ws.host_flags) HODLR_HIP(hipHostMalloc(reinterpret_cast<void**>(&ws.host_flags), 192 * sizeof(int)));
+  for (int e = 0; e < 2; ++e)
+    if (!ws.ev[e]) HODLR_HIP(hipEventCreateWithFlags(&ws.ev[e], hipEventDisableTiming));
   double* V = ws.V.as<double>();
   TP* Z = M ? ws.Z.as<TP>() : nullptr;
   double* w = ws.w.as<double>();
@@ -384,11 +436,20 @@ static int gmres_t(const double* K, int n, int ldk, hodlr_s* M, const double* B,
                                  active, steps, total, tol, maxit);
       k_normalize<TP><<<gvec, kBlock, 0, st>>>(n, s, j + 1, w, ws.scal.as<double>(), active, V, Z);
       HODLR_HIP(hipGetLastError());
-      HODLR_HIP(hipMemcpyAsync(ws.host_flags, active, s * sizeof(int), hipMemcpyDeviceToHost, st));
-      HODLR_HIP(hipStreamSynchronize(st));
-      bool more = false;
-      for (int k = 0; k < s; ++k) more |= ws.host_flags[k] != 0;
-      if (!more) break;
+      // flags of step j go to a pinned slot behind an event; the host waits
+      // for the flags of step j-1 only, so step j is already queued (a step
+      // taken after every column has stopped does no work: the kernels read
+      // the device flags)
+      int* slot = ws.host_flags + 64 + 64 * (j & 1);
+      HODLR_HIP(hipMemcpyAsync(slot, active, s * sizeof(int), hipMemcpyDeviceToHost, st));
+      HODLR_HIP(hipEventRecord(ws.ev[j & 1], st));
+      if (j > 0) {
+        HODLR_HIP(hipEventSynchronize(ws.ev[(j - 1) & 1]));
+        const int* prev = ws.host_flags + 64 + 64 * ((j - 1) & 1);
+        bool more = false;
+        for (int k = 0; k < s; ++k) more |= prev[k] != 0;
+        if (!more) break;
+      }
     }
     k_trisolve<<<1, 64, 0, st>>>(s, m, ws.H.as<double>(), ws.g.as<double>(), steps, ws.y.as<double>());
     if (M)

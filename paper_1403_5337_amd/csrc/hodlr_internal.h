@@ -44,6 +44,8 @@ constexpr int kLeafMax = 256;        // largest leaf block
 constexpr int kMaxN = 1 << 20;
 
 inline int rank_cap(int precision) { return precision == 64 ? kRankCap64 : kRankCap32; }
+// the leaf inverse keeps a leaf in LDS: leaf <= 184 (float) / 128 (double)
+inline int leaf_cap(int precision) { return precision == 64 ? kRankCap64 : kRankCap32; }
 
 // ---------------------------------------------------------------------------
 // Tree: node id of (level p, index i) is (1 << p) - 1 + i.
@@ -60,8 +62,13 @@ struct Tree {
   int max_size(int p) const;
 };
 
+// caching device allocator (api.hip)
+int dev_alloc(size_t nbytes, void** out);
+void dev_free(void* p, size_t nbytes);
+void release_cached_memory();
+
 // ---------------------------------------------------------------------------
-// Device buffer (RAII, hipMalloc / hipFree)
+// Device buffer (RAII over the caching allocator)
 // ---------------------------------------------------------------------------
 struct DevBuf {
   void* p = nullptr;
@@ -70,11 +77,7 @@ struct DevBuf {
   DevBuf(const DevBuf&) = delete;
   DevBuf& operator=(const DevBuf&) = delete;
   ~DevBuf() { release(); }
-  void release() {
-    if (p) (void)hipFree(p);
-    p = nullptr;
-    bytes = 0;
-  }
+  void release();             // back to the allocator cache
   int ensure(size_t nbytes);  // grow-only; contents not preserved
   template <typename T> T* as() const { return static_cast<T*>(p); }
 };
@@ -108,6 +111,7 @@ struct hodlr_s {
   hodlr::DevBuf Sinv;   // per internal node: (2 rq)^2 inverse capacitance
   std::vector<size_t> sinv_off;  // per parent level p = 0..L-1 (elements)
   hodlr::DevBuf G;      // work: per-node panel products
+  size_t p_half = 0;    // elements of one partial-product buffer of the solve
   hodlr::DevBuf Ybuf;   // work: per-node Woodbury solutions
   hodlr::DevBuf status; // int[4]: 0 singular flag, 1 node, 2 abort
   bool factored = false;

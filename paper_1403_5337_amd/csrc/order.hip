@@ -18,8 +18,9 @@
 namespace hodlr {
 
 constexpr int kRcbMax = 16384;
+constexpr int kRcbThreads = 1024;
 
-__global__ void __launch_bounds__(kBlock)
+__global__ void __launch_bounds__(kRcbThreads)
     k_rcb_level(const float* __restrict__ coords, int* __restrict__ perm, const int* __restrict__ lo,
                 const int* __restrict__ hi, int id0) {
   extern __shared__ __align__(16) unsigned char smem[];
@@ -30,7 +31,7 @@ __global__ void __launch_bounds__(kBlock)
   while (P < len) P <<= 1;
   float* key = reinterpret_cast<float*>(smem);
   int* pos = reinterpret_cast<int*>(key + kRcbMax);
-  __shared__ float red[6][kBlock / 64];
+  __shared__ float red[6][kRcbThreads / 64];
   __shared__ int s_axis;
   float mn[3] = {FLT_MAX, FLT_MAX, FLT_MAX}, mx[3] = {-FLT_MAX, -FLT_MAX, -FLT_MAX};
   for (int e = t; e < len; e += nt) {
@@ -127,7 +128,8 @@ int launch_rcb(const float* coords, int n, const Tree& t, int* perm, hipStream_t
   HODLR_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(k_rcb_level),
                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
   for (int p = 0; p < t.L; ++p) {
-    k_rcb_level<<<1 << p, kBlock, lds, s>>>(coords, perm, dlo.as<int>(), dhi.as<int>(), node_id(p, 0));
+    k_rcb_level<<<1 << p, kRcbThreads, lds, s>>>(coords, perm, dlo.as<int>(), dhi.as<int>(),
+                                                 node_id(p, 0));
     HODLR_HIP(hipGetLastError());
   }
   HODLR_HIP(hipStreamSynchronize(s));  // dlo/dhi are released on return

@@ -54,6 +54,7 @@ _SIGNATURES = {
     "hodlr_stats": (ctypes.c_int, [_vp, _c_int_p, _c_int_p, _c_int_p]),
     "hodlr_get_factors": (ctypes.c_int, [_vp, _vp, _vp, _vp]),
     "hodlr_destroy": (ctypes.c_int, [_vp]),
+    "hodlr_release_memory": (ctypes.c_int, []),
     "hodlr_last_error": (ctypes.c_char_p, []),
     "hodlr_prof_enable": (ctypes.c_int, [ctypes.c_int]),
     "hodlr_prof_query": (ctypes.c_int, [ctypes.c_char_p, _c_int_p, _c_dbl_p]),
