@@ -154,6 +154,18 @@ static int init_handle(hodlr_s* h, int n, int leaf, int precision) {
   return HODLR_OK;
 }
 
+// The solve's correction operators: level q's block is 2 r_q wide.
+int alloc_E(hodlr_s* h) {
+  const Tree& t = h->tree;
+  h->offE.assign(t.L, 0);
+  int RE = 0;
+  for (int q = 1; q <= t.L; ++q) {
+    h->offE[q - 1] = RE;
+    RE += 2 * h->rcols[q - 1];
+  }
+  return h->E.ensure((size_t)t.n * std::max(RE, 1) * h->esize);
+}
+
 // Column layout from the per-node ranks: level q's block is as wide as the
 // largest rank at that level.
 int set_layout_from_ranks(hodlr_s* h) {
@@ -171,6 +183,7 @@ int set_layout_from_ranks(hodlr_s* h) {
   h->R = R;
   HODLR_TRY(h->Y.ensure((size_t)t.n * std::max(R, 1) * h->esize));
   HODLR_TRY(h->W.ensure((size_t)t.n * std::max(R, 1) * h->esize));
+  HODLR_TRY(alloc_E(h));
   // inverse capacitance matrices, per parent level p: 2^p nodes of (2 r_{p+1})^2
   h->sinv_off.assign(t.L, 0);
   size_t tot = 0;
@@ -319,6 +332,7 @@ int hodlr_build_from_factors(int n, int leaf, int precision, const double* leave
   h->R = R;
   HODLR_TRY(h->Y.ensure((size_t)n * std::max(R, 1) * h->esize));
   HODLR_TRY(h->W.ensure((size_t)n * std::max(R, 1) * h->esize));
+  HODLR_TRY(alloc_E(h.get()));
   h->sinv_off.assign(t.L, 0);
   size_t tot = 0;
   for (int p = 0; p < t.L; ++p) {

@@ -195,9 +195,6 @@ __global__ void __launch_bounds__(kBlock)
     }
 }
 
-// Rows of a node are cut into chunks of kChunk rows in the fused solve.
-constexpr int kChunk = 256;
-
 // ---------------------------------------------------------------------------
 // Inverse capacitance matrix of every parent of level q (one workgroup each).
 // With A = V_b^T d_a (r_b x r_a) and B = V_a^T d_b (r_a x r_b) read from the
@@ -339,224 +336,28 @@ __global__ void __launch_bounds__(kBlock)
 }
 
 // ---------------------------------------------------------------------------
-// The solve (Sec. 4.3.2) fused into L + 1 launches for few right-hand sides.
-//
-// P^(q) holds partial products W(rows, level-q block)^T x(rows) over "units"
-// of rows: for q = L one unit per leaf; for q < L one unit per (level-(q+1)
-// node, row chunk), so the units of a level-q node are contiguous.
-// Launch "leaf": x_leaf = Kinv_leaf x_leaf, then the units of P^(L).
-// Launch "level q" (one workgroup per level-q node and row chunk): add the
-// units of both siblings into t = [t_a; t_b], form the part of y = S^-1 t
-// that multiplies this node's d, correct the chunk's rows of x, then write
-// the chunk's unit of P^(q-1).
+// E_c = d_c S_P^-1(y rows of c, :) for every node c of level q (the solve's
+// correction operator): one workgroup per node and 256-row chunk.
 // ---------------------------------------------------------------------------
-template <typename T, int SM>
-__device__ void unit_products(const T* __restrict__ W, int ldw, int wcol0, int rp, int row0, int rn,
-                              const T* xs, int nc, T* __restrict__ Pu) {
-  // xs holds kChunk rows per column (zero beyond rn); a wave takes two
-  // columns of W at a time and issues all their loads before reducing
-  constexpr int NR = kChunk / 64;
-  const int t = threadIdx.x, wave = t >> 6, lane = t & 63, nw = blockDim.x >> 6;
-  for (int r0 = wave; r0 < rp; r0 += 2 * nw) {
-    const int r1 = r0 + nw;
-    const bool two = r1 < rp;
-    const T* W0 = W + (size_t)(wcol0 + r0) * ldw + row0;
-    const T* W1 = W + (size_t)(wcol0 + (two ? r1 : r0)) * ldw + row0;
-    T w0[NR], w1[NR];
-#pragma unroll
-    for (int u = 0; u < NR; ++u) {
-      const int i = lane + 64 * u;
-      w0[u] = i < rn ? W0[i] : T(0);
-      w1[u] = i < rn ? W1[i] : T(0);
-    }
-    T a0[SM], a1[SM];
-#pragma unroll
-    for (int c = 0; c < SM; ++c) {
-      a0[c] = T(0);
-      a1[c] = T(0);
-    }
-#pragma unroll
-    for (int u = 0; u < NR; ++u)
-#pragma unroll
-      for (int c = 0; c < SM; ++c) {
-        const T x = xs[c * kChunk + lane + 64 * u];
-        a0[c] += w0[u] * x;
-        a1[c] += w1[u] * x;
-      }
-#pragma unroll
-    for (int c = 0; c < SM; ++c) {
-      a0[c] = wave_sum(a0[c]);
-      a1[c] = wave_sum(a1[c]);
-    }
-    if (lane < nc) {
-      T v0 = a0[0], v1 = a1[0];
-#pragma unroll
-      for (int c = 1; c < SM; ++c)
-        if (lane == c) {
-          v0 = a0[c];
-          v1 = a1[c];
-        }
-      Pu[r0 + (size_t)lane * rp] = v0;
-      if (two) Pu[r1 + (size_t)lane * rp] = v1;
-    }
-  }
-}
-
-template <typename T, int SM>
+template <typename T>
 __global__ void __launch_bounds__(kBlock)
-    k_apply_leaf(const T* __restrict__ Kinv, int bmax, const int* __restrict__ lo,
-                 const int* __restrict__ hi, int idL, T* __restrict__ X, int ldx, int nc,
-                 const T* __restrict__ W, int ldw, int offL, int rL, T* __restrict__ P) {
-  __shared__ T xs[SM * kChunk];
-  __shared__ T ys[SM * kChunk];
-  const int leaf = blockIdx.x, id = idL + leaf, t = threadIdx.x;
-  const int l0 = lo[id], b = hi[id] - l0;
-  const T* Ki = Kinv + (size_t)leaf * bmax * bmax;
-  for (int e = t; e < SM * kChunk; e += blockDim.x) {
-    const int i = e % kChunk, c = e / kChunk;
-    xs[e] = (i < b && c < nc) ? X[(size_t)c * ldx + l0 + i] : T(0);
-  }
-  __syncthreads();
-  for (int i = t; i < b; i += blockDim.x) {
-    T acc[SM];
-#pragma unroll
-    for (int c = 0; c < SM; ++c) acc[c] = T(0);
-    int kk = 0;
-    for (; kk + 8 <= b; kk += 8) {
-      T a[8];
-#pragma unroll
-      for (int u = 0; u < 8; ++u) a[u] = Ki[i + (size_t)(kk + u) * bmax];
-#pragma unroll
-      for (int u = 0; u < 8; ++u)
-#pragma unroll
-        for (int c = 0; c < SM; ++c) acc[c] += a[u] * xs[c * kChunk + kk + u];
-    }
-    for (; kk < b; ++kk) {
-      const T a = Ki[i + (size_t)kk * bmax];
-#pragma unroll
-      for (int c = 0; c < SM; ++c) acc[c] += a * xs[c * kChunk + kk];
-    }
-#pragma unroll
-    for (int c = 0; c < SM; ++c) {
-      ys[c * kChunk + i] = acc[c];
-      if (c < nc) X[(size_t)c * ldx + l0 + i] = acc[c];
-    }
-  }
-  for (int e = t; e < SM * kChunk; e += blockDim.x)
-    if (e % kChunk >= b) ys[e] = T(0);
-  __syncthreads();
-  if (rL > 0) unit_products<T, SM>(W, ldw, offL, rL, l0, b, ys, nc, P + (size_t)leaf * rL * nc);
-}
-
-template <typename T, int SM>
-__global__ void __launch_bounds__(kBlock)
-    k_apply_level(int q, const int* __restrict__ lo, const int* __restrict__ hi,
-                  const int* __restrict__ rank, T* __restrict__ X, int ldx, int nc,
-                  const T* __restrict__ Y, int ldy, int offq, int rq, const T* __restrict__ Sinv,
-                  const T* __restrict__ Pin, int upn, int nch, const T* __restrict__ W, int offp,
-                  int rp, T* __restrict__ Pout) {
-  constexpr int ZT = 32;  // columns of S^-1 staged per LDS tile
-  __shared__ T tcat[2 * kRankCap32 * SM];
-  __shared__ T yo[kRankCap32 * SM];
-  __shared__ T xs[SM * kChunk];
-  __shared__ T Stile[kRankCap32 * ZT];
-  const int c = blockIdx.x, ch = blockIdx.y, t = threadIdx.x, nt = blockDim.x;
-  const int par = c >> 1, left = (c & 1) == 0;
-  const int ia = node_id(q, 2 * par), ib = node_id(q, 2 * par + 1), id = node_id(q, c);
-  const int ra = rank[ia], rb = rank[ib], r = ra + rb;
-  const size_t us = (size_t)rq * nc;  // one unit's products
-  // t_a = V_b^T x_a (r_b x nc) from the units of a, t_b = V_a^T x_b from those of b
-  for (int e = t; e < r * nc; e += nt) {
-    const int z = e % r, cc = e / r;
-    const int node = (z < rb) ? 2 * par : 2 * par + 1;
-    const int zz = (z < rb) ? z : z - rb;
-    const T* P0 = Pin + (size_t)node * upn * us + zz + (size_t)cc * rq;
-    T v = T(0);
-    int u = 0;
-    for (; u + 8 <= upn; u += 8) {
-      T pv[8];
-#pragma unroll
-      for (int x = 0; x < 8; ++x) pv[x] = P0[(u + x) * us];
-#pragma unroll
-      for (int x = 0; x < 8; ++x) v += pv[x];
-    }
-    for (; u < upn; ++u) v += P0[u * us];
-    tcat[z + cc * r] = v;
-  }
-  __syncthreads();
+    k_form_E(const T* __restrict__ Y, int ldy, int offq, int rq, const T* __restrict__ Sinv,
+             const int* __restrict__ lo, const int* __restrict__ hi, const int* __restrict__ rank, int q,
+             T* __restrict__ E, int offE) {
+  __shared__ T As[32 * 33], Bs[32 * 33];
+  const int c = blockIdx.x, par = c >> 1, left = (c & 1) == 0, id = node_id(q, c);
+  const int ra = rank[node_id(q, 2 * par)], rb = rank[node_id(q, 2 * par + 1)], r = ra + rb;
   const int rc = left ? ra : rb, yoff = left ? rb : 0, lds = 2 * rq;
+  const int row0 = lo[id] + blockIdx.y * 256, rn = min(256, hi[id] - row0);
+  if (rn <= 0 || r == 0) return;
   const T* S = Sinv + (size_t)par * lds * lds + yoff;
-  // y_other = S^-1(yoff : yoff + rc, :) t, the rows of S^-1 staged through LDS
-  T yacc[SM];
-#pragma unroll
-  for (int cc = 0; cc < SM; ++cc) yacc[cc] = T(0);
-  for (int z0 = 0; z0 < r; z0 += ZT) {
-    const int zn = min(ZT, r - z0);
-    for (int e0 = 0; e0 < rc * ZT; e0 += 4 * nt) {
-      T sv4[4];
-#pragma unroll
-      for (int u = 0; u < 4; ++u) {
-        const int e = e0 + t + u * nt;
-        const int x = e % rc, zz = e / rc;
-        sv4[u] = (e < rc * ZT && zz < zn) ? S[x + (size_t)(z0 + zz) * lds] : T(0);
-      }
-#pragma unroll
-      for (int u = 0; u < 4; ++u) {
-        const int e = e0 + t + u * nt;
-        if (e < rc * ZT) Stile[e] = sv4[u];
-      }
-    }
-    __syncthreads();
-    if (t < rc) {
-      for (int zz = 0; zz < zn; ++zz) {
-        const T sv = Stile[t + zz * rc];
-#pragma unroll
-        for (int cc = 0; cc < SM; ++cc) yacc[cc] += sv * tcat[z0 + zz + cc * r];
-      }
-    }
-    __syncthreads();
+  if (rc == 0) {
+    for (int e = threadIdx.x; e < rn * r; e += blockDim.x)
+      E[(size_t)(offE + e / rn) * ldy + row0 + e % rn] = T(0);
+    return;
   }
-  if (t < rc)
-#pragma unroll
-    for (int cc = 0; cc < SM; ++cc) yo[t + cc * rc] = yacc[cc];
-  __syncthreads();
-  const int row0 = lo[id] + ch * kChunk, rn = min(kChunk, hi[id] - row0);
-  for (int i = t; i < kChunk; i += nt) {
-    T acc[SM];
-#pragma unroll
-    for (int cc = 0; cc < SM; ++cc) acc[cc] = T(0);
-    if (i < rn) {
-      int l = 0;
-      for (; l + 8 <= rc; l += 8) {
-        T d[8];
-#pragma unroll
-        for (int u = 0; u < 8; ++u) d[u] = Y[(size_t)(offq + l + u) * ldy + row0 + i];
-#pragma unroll
-        for (int u = 0; u < 8; ++u)
-#pragma unroll
-          for (int cc = 0; cc < SM; ++cc) acc[cc] += d[u] * yo[l + u + cc * rc];
-      }
-      for (; l < rc; ++l) {
-        const T d = Y[(size_t)(offq + l) * ldy + row0 + i];
-#pragma unroll
-        for (int cc = 0; cc < SM; ++cc) acc[cc] += d * yo[l + cc * rc];
-      }
-    }
-#pragma unroll
-    for (int cc = 0; cc < SM; ++cc) {
-      T v = T(0);
-      if (i < rn && cc < nc) {
-        v = X[(size_t)cc * ldx + row0 + i] - acc[cc];
-        X[(size_t)cc * ldx + row0 + i] = v;
-      }
-      xs[cc * kChunk + i] = v;
-    }
-  }
-  __syncthreads();
-  if (Pout && rp > 0 && rn > 0)
-    unit_products<T, SM>(W, ldy, offp, rp, row0, rn, xs, nc, Pout + ((size_t)c * nch + ch) * rp * nc);
-  else if (Pout && rp > 0)
-    for (int e = t; e < rp * nc; e += nt) Pout[((size_t)c * nch + ch) * rp * nc + e] = T(0);
+  wg_gemm(rn, r, rc, T(1), Y + (size_t)offq * ldy + row0, ldy, S, lds, T(0),
+          E + (size_t)offE * ldy + row0, ldy, As, Bs);
 }
 
 // ---------------------------------------------------------------------------
@@ -579,20 +380,13 @@ int ensure_work(hodlr_s* h, int ncols) {
   for (int q = 1; q <= t.L; ++q) {
     size_t rq = h->rcols.empty() ? 0 : h->rcols[q - 1];
     size_t offq = h->off.empty() ? 0 : h->off[q - 1];
-    const size_t nch = (t.max_size(q) + kChunk - 1) / kChunk;
-    g = std::max(g, (size_t)(1 << q) * rq * std::max<size_t>(offq + rq, nch * 16));
+    g = std::max(g, (size_t)(1 << q) * rq * (offq + rq));
     y = std::max(y, (size_t)(1 << (q - 1)) * 2 * rq * std::max<size_t>(offq, ncols));
   }
-  // the fused solve keeps two unit buffers of partial products in G
-  size_t units = 1;
-  for (int q = 1; q <= t.L; ++q) {
-    const size_t rq = h->rcols.empty() ? 0 : h->rcols[q - 1];
-    const size_t nu = (q == t.L) ? ((size_t)1 << q)
-                                 : ((size_t)2 << q) * ((t.max_size(q + 1) + kChunk - 1) / kChunk);
-    units = std::max(units, nu * rq * 16);
-  }
-  h->p_half = units;
-  g = std::max(g, 2 * units);
+  // the fused solve keeps two buffers of unit partial products in G
+  h->p_half = solve_partial_elems(h);
+  g = std::max(g, 2 * h->p_half);
+  HODLR_TRY(h->Xtmp.ensure((size_t)t.n * 16 * h->esize));
   HODLR_TRY(h->G.ensure(g * h->esize));
   HODLR_TRY(h->Ybuf.ensure(y * h->esize));
   return HODLR_OK;
@@ -704,7 +498,7 @@ static int level_solve(hodlr_s* h, int q, T* Z, int ldz, int zcols, const T* G, 
 
 template <typename T>
 static int factor_t(hodlr_s* h, hipStream_t s) {
-  const Tree& t = h->tree;
+  const Tree& t = h->tree;  // (tree)
   const int n = t.n, L = t.L;
   HODLR_HIP(hipMemsetAsync(h->status.p, 0, 4 * sizeof(int), s));
   const size_t lds_leaf = (size_t)h->bmax * (h->bmax + 1) * sizeof(T);
@@ -746,6 +540,13 @@ static int factor_t(hodlr_s* h, hipStream_t s) {
                                                            h->status.as<int>());
     }
     HODLR_HIP(hipGetLastError());
+    {
+      ProfScope prof_("form_E", s);
+      k_form_E<T><<<dim3(1 << q, cdiv(t.max_size(q), 256)), kBlock, 0, s>>>(
+          Y, n, offq, rq, h->Sinv.as<T>() + h->sinv_off[q - 1], h->d_lo.as<int>(), h->d_hi.as<int>(),
+          h->d_rank.as<int>(), q, h->E.as<T>(), h->offE[q - 1]);
+    }
+    HODLR_HIP(hipGetLastError());
     if (offq > 0) HODLR_TRY(level_solve<T>(h, q, Y, n, offq, G, zc, 1, s));
   }
   return HODLR_OK;
@@ -753,54 +554,6 @@ static int factor_t(hodlr_s* h, hipStream_t s) {
 
 int factor_impl(hodlr_s* h, hipStream_t s) {
   return h->precision == 64 ? factor_t<double>(h, s) : factor_t<float>(h, s);
-}
-
-template <typename T, int SM>
-static int apply_fused(hodlr_s* h, T* X, int ldx, int nc, hipStream_t s) {
-  const Tree& t = h->tree;
-  const int n = t.n, L = t.L;
-  T* P[2] = {h->G.as<T>(), h->G.as<T>() + h->p_half};
-  const int rL = L > 0 ? h->rcols[L - 1] : 0, offL = L > 0 ? h->off[L - 1] : 0;
-  {
-    ProfScope prof_("apply_leaf", s);
-    k_apply_leaf<T, SM><<<h->nleaf, kBlock, 0, s>>>(h->Kinv.as<T>(), h->bmax, h->d_lo.as<int>(),
-                                                   h->d_hi.as<int>(), node_id(L, 0), X, ldx, nc,
-                                                   h->W.as<T>(), n, offL, rL, P[0]);
-  }
-  HODLR_HIP(hipGetLastError());
-  int cur = 0;
-  for (int q = L; q >= 1; --q) {
-    const int rq = h->rcols[q - 1], offq = h->off[q - 1];
-    const int nch = cdiv(t.max_size(q), kChunk);
-    const int upn = (q == L) ? 1 : 2 * cdiv(t.max_size(q + 1), kChunk);
-    const int rp = q > 1 ? h->rcols[q - 2] : 0, offp = q > 1 ? h->off[q - 2] : 0;
-    const T* Sinv = h->Sinv.as<T>() + h->sinv_off[q - 1];
-    {
-      ProfScope prof_("apply_level", s);
-      k_apply_level<T, SM><<<dim3(1 << q, nch), kBlock, 0, s>>>(
-          q, h->d_lo.as<int>(), h->d_hi.as<int>(), h->d_rank.as<int>(), X, ldx, nc, h->Y.as<T>(), n,
-          offq, rq, Sinv, P[cur], upn, nch, h->W.as<T>(), offp, rp, q > 1 ? P[cur ^ 1] : nullptr);
-    }
-    HODLR_HIP(hipGetLastError());
-    cur ^= 1;
-  }
-  return HODLR_OK;
-}
-
-template <typename T>
-static int apply_t(hodlr_s* h, T* X, int ldx, int nrhs, hipStream_t s) {
-  for (int c0 = 0; c0 < nrhs; c0 += 16) {
-    const int nc = std::min(16, nrhs - c0);
-    T* Xc = X + (size_t)c0 * ldx;
-    if (nc <= 8) HODLR_TRY((apply_fused<T, 8>(h, Xc, ldx, nc, s)));
-    else HODLR_TRY((apply_fused<T, 16>(h, Xc, ldx, nc, s)));
-  }
-  return HODLR_OK;
-}
-
-int apply_impl(hodlr_s* h, void* X, int ldx, int nrhs, hipStream_t s) {
-  return h->precision == 64 ? apply_t<double>(h, static_cast<double*>(X), ldx, nrhs, s)
-                            : apply_t<float>(h, static_cast<float*>(X), ldx, nrhs, s);
 }
 
 }  // namespace hodlr

@@ -107,6 +107,9 @@ struct hodlr_s {
   hodlr::DevBuf d_lo, d_hi, d_rank;
   hodlr::DevBuf Y;      // n x R: U panels, then the factorization (d / c)
   hodlr::DevBuf W;      // n x R: V panels
+  hodlr::DevBuf E;      // n x RE: solve correction operators E_c = d_c S^-1(rows, :)
+  std::vector<int> offE;  // per level q at index q-1: column offset in E (width 2 rq)
+  hodlr::DevBuf Xtmp;   // n x 16: solve work vector
   hodlr::DevBuf Kinv;   // nleaf x bmax x bmax: leaf inverses
   hodlr::DevBuf Sinv;   // per internal node: (2 rq)^2 inverse capacitance
   std::vector<size_t> sinv_off;  // per parent level p = 0..L-1 (elements)
@@ -141,8 +144,11 @@ int launch_repack(hodlr_s* h, const void* Ucap, const void* Vcap, int ldcap,
 int launch_from_f64_panels(hodlr_s* h, const double* Up, const double* Vp, hipStream_t s);
 int launch_to_f64_panels(hodlr_s* h, double* Up, double* Vp, hipStream_t s);
 int factor_impl(hodlr_s* h, hipStream_t s);
-int apply_impl(hodlr_s* h, void* X, int ldx, int nrhs, hipStream_t s);  // in place
 int ensure_work(hodlr_s* h, int ncols);
+
+// solve.hip
+int apply_impl(hodlr_s* h, void* X, int ldx, int nrhs, hipStream_t s);  // in place
+size_t solve_partial_elems(const hodlr_s* h);
 
 // prof.hip: event timing of wrapped launches (hodlr_prof_enable)
 bool prof_on();
