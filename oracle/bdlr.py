@@ -71,19 +71,29 @@ def distance_to_boundary(indptr, indices, own: np.ndarray, sources: np.ndarray) 
     return d
 
 
-def select(indptr, indices, I: np.ndarray, J: np.ndarray, depth: int):
+def _pick(own, d, depth, max_skel):
+    cand = [(d[int(v)], a) for a, v in enumerate(own) if d.get(int(v), depth) < depth]
+    if max_skel is not None and len(cand) > max_skel:
+        cand = sorted(cand)[:max_skel]  # nearest the boundary first, then lowest position
+    return np.array(sorted(a for _, a in cand), dtype=np.int64)
+
+
+def select(indptr, indices, I: np.ndarray, J: np.ndarray, depth: int, max_skel=None):
     """BDLR picks for block (I, J): local positions (into I and into J) of
-    vertices with boundary distance < depth, in increasing vertex order."""
+    vertices with boundary distance < depth, in increasing position order.
+
+    Reading (the skeleton must fit a bounded work space): with ``max_skel``
+    set, at most that many rows (columns) are kept, nearest the boundary
+    first (smaller d), ties to the lower position — the order in which the
+    paper adds rows and columns (d = 0, then d = 1, ...)."""
     BI = boundary(indptr, indices, I, J)
     BJ = boundary(indptr, indices, J, I)
     dI = distance_to_boundary(indptr, indices, I, BI)
     dJ = distance_to_boundary(indptr, indices, J, BJ)
-    rows = [a for a, v in enumerate(I) if dI.get(int(v), depth) < depth]
-    cols = [b for b, v in enumerate(J) if dJ.get(int(v), depth) < depth]
-    return np.array(rows, dtype=np.int64), np.array(cols, dtype=np.int64)
+    return _pick(I, dI, depth, max_skel), _pick(J, dJ, depth, max_skel)
 
 
-def full_pivot_lu(A: np.ndarray, eps: float):
+def full_pivot_lu(A: np.ndarray, eps: float, max_rank=None):
     """Full-pivoting LU with relative pivot truncation.
 
     Returns (prow, pcol, L, U, r): prow/pcol list the rows/columns of A in
@@ -94,7 +104,7 @@ def full_pivot_lu(A: np.ndarray, eps: float):
     m, n = W.shape
     prow = np.arange(m)
     pcol = np.arange(n)
-    kmax = min(m, n)
+    kmax = min(m, n) if max_rank is None else min(m, n, max_rank)
     first = None
     r = 0
     for k in range(kmax):
@@ -120,7 +130,7 @@ def full_pivot_lu(A: np.ndarray, eps: float):
     return prow, pcol, L, U, r
 
 
-def skeleton(B: np.ndarray, rows: np.ndarray, cols: np.ndarray, eps: float):
+def skeleton(B: np.ndarray, rows: np.ndarray, cols: np.ndarray, eps: float, max_rank=None):
     """Pseudo-skeleton of block B from picked local rows/cols (eq. Ahat).
 
     Returns U (m x r), V (n x r) with B ~ U V^T (U = C~, V = R~^T)."""
@@ -128,7 +138,7 @@ def skeleton(B: np.ndarray, rows: np.ndarray, cols: np.ndarray, eps: float):
     if rows.size == 0 or cols.size == 0:
         return np.zeros((m, 0)), np.zeros((n, 0))
     Ahat = B[np.ix_(rows, cols)]
-    prow, pcol, L, U, r = full_pivot_lu(Ahat, eps)
+    prow, pcol, L, U, r = full_pivot_lu(Ahat, eps, max_rank)
     if r == 0:
         return np.zeros((m, 0)), np.zeros((n, 0))
     C = B[:, cols]          # m x |cols|
@@ -144,9 +154,9 @@ def skeleton(B: np.ndarray, rows: np.ndarray, cols: np.ndarray, eps: float):
     return Ct, Rt.T
 
 
-def bdlr(B, indptr, indices, I, J, depth, eps):
-    rows, cols = select(indptr, indices, I, J, depth)
-    return skeleton(B, rows, cols, eps)
+def bdlr(B, indptr, indices, I, J, depth, eps, max_skel=None, max_rank=None):
+    rows, cols = select(indptr, indices, I, J, depth, max_skel)
+    return skeleton(B, rows, cols, eps, max_rank)
 
 
 def sampled_error(B, U, V, rows_avoid, cols_avoid, nsamp, rng):

@@ -67,7 +67,7 @@ def sibling(i: int) -> int:
 
 
 def from_dense(K: np.ndarray, leaf: int, method="aca", eps=1e-8, max_rank=None,
-               graph=None, depth=1, svd_rank=None) -> HODLR:
+               graph=None, depth=1, svd_rank=None, max_skel=None) -> HODLR:
     """Compress every off-diagonal block of K.
 
     method: 'aca' (partial-pivoting ACA), 'bdlr' (needs graph=(indptr, indices)),
@@ -89,7 +89,7 @@ def from_dense(K: np.ndarray, leaf: int, method="aca", eps=1e-8, max_rank=None,
             elif method == "bdlr":
                 indptr, indices = graph
                 U, V = _bdlr.bdlr(B, indptr, indices, np.arange(lo, hi), np.arange(slo, shi),
-                                  depth, eps)
+                                  depth, eps, max_skel, max_rank)
             elif method == "svd":
                 Us, s, Vt = np.linalg.svd(B, full_matrices=False)
                 k = svd_rank if svd_rank is not None else int(np.sum(s > eps * s[0])) if s.size and s[0] > 0 else 0

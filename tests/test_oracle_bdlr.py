@@ -32,6 +32,9 @@ def test_boundary_distance_golden():
     assert [dist[int(v)] for v in I] == d["d_I"]
     rows, cols = bdlr.select(indptr, indices, I, J, d["depth"])
     assert rows.tolist() == d["rows"] and cols.tolist() == d["cols"]
+    c = d["capped"]
+    rows, cols = bdlr.select(indptr, indices, I, J, c["depth"], max_skel=c["max_skel"])
+    assert rows.tolist() == c["rows"] and cols.tolist() == c["cols"]
 
 
 @pytest.mark.parametrize("seed", range(4))
