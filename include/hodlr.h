@@ -52,7 +52,10 @@ typedef struct {
                      (Sec. 7.1). */
   int method;     /* HODLR_ACA or HODLR_BDLR */
   int bdlr_depth; /* BDLR: pick rows/cols at graph distance < depth from the
-                     block boundary (Sec. 5.3) */
+                     block boundary (Sec. 5.3), 1..250.  At most 192
+                     (precision 32) / 128 (precision 64) rows and as many
+                     columns are kept, nearest the boundary first, ties to
+                     the lower index. */
   int max_rank;   /* cap on every off-diagonal rank (0 = library maximum) */
   int precision;  /* 32 or 64: arithmetic of the factorization and solve */
 } hodlr_opts;
@@ -72,8 +75,8 @@ void hodlr_default_opts(hodlr_opts* opts);
  *   opts    host; NULL = defaults.
  *   out     host; receives the new handle.
  * Synchronizes the stream once (to size the factor storage from the ranks
- * found).  Errors: EINVAL (n < 1, ldk < n, NULL K/out, bad opts), ENOMEM,
- * EHIP. */
+ * found).  Errors: EINVAL (n < 1, ldk < n, NULL K/out, bad opts, BDLR with
+ * n > 16384 or without the graph), ENOMEM, EHIP. */
 int hodlr_build(const double* K, int n, int ldk, const int* g_rowptr, const int* g_col,
                 const hodlr_opts* opts, hipStream_t stream, hodlr_t* out);
 
@@ -147,6 +150,23 @@ int hodlr_permute(const double* Kin, int n, int ldi, const int* perm, double* Ko
  * sorted).  Asynchronous. */
 int hodlr_permute_graph(const int* rowptr, const int* col, int n, const int* perm,
                         int* rowptr_out, int* col_out, hipStream_t stream);
+
+/* The row and column picks of BDLR (Sec. 5.3) for every off-diagonal block of
+ * the tree for (n, leaf), as hodlr_build with HODLR_BDLR takes them: for node
+ * c with sibling s, the boundary of c is the set of its indices with a graph
+ * edge into s, distances are breadth-first inside c, and the rows picked are
+ * the positions (0-based, within c) at distance < depth, at most max_skel of
+ * them, nearest the boundary first and ties to the lower position, listed in
+ * increasing position; columns likewise within s.
+ *   g_rowptr, g_col  device CSR of the graph in K's numbering (as hodlr_build).
+ *   picks   device int, (2^(L+1)-2) * 2 * max_skel: for the k-th node below
+ *           the root in level order, rows at k*2*max_skel, columns at
+ *           k*2*max_skel + max_skel.
+ *   counts  device int, 2 per node: number of rows, number of columns.
+ * 2 <= n <= 16384, n > leaf, 1 <= depth <= 250.  Synchronizes the stream.
+ * Errors: EINVAL, ENOMEM, EHIP. */
+int hodlr_bdlr_select(const int* g_rowptr, const int* g_col, int n, int leaf, int depth,
+                      int max_skel, int* picks, int* counts, hipStream_t stream);
 
 /* Introspection (host arrays): number of levels L, ranks of the nodes below
  * the root in level order (capacity 2^(L+1)-2 ints), per-level column widths

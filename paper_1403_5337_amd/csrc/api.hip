@@ -226,8 +226,8 @@ static int check_opts(const hodlr_opts& o) {
     return fail(HODLR_EINVAL, "opts.leaf must be <= " + std::to_string(leaf_cap(o.precision)) +
                                   " at this precision");
   if (o.max_rank < 0) return fail(HODLR_EINVAL, "opts.max_rank must be >= 0");
-  if (o.method == HODLR_BDLR && o.bdlr_depth < 1)
-    return fail(HODLR_EINVAL, "opts.bdlr_depth must be >= 1");
+  if (o.method == HODLR_BDLR && (o.bdlr_depth < 1 || o.bdlr_depth > 250))
+    return fail(HODLR_EINVAL, "opts.bdlr_depth must be in [1, 250]");
   return HODLR_OK;
 }
 
@@ -244,7 +244,7 @@ int hodlr_build(const double* K, int n, int ldk, const int* g_rowptr, const int*
   HODLR_TRY(check_opts(o));
   if (o.method == HODLR_BDLR && (!g_rowptr || !g_col))
     return fail(HODLR_EINVAL, "BDLR needs the separator graph (g_rowptr, g_col)");
-  if (o.method == HODLR_BDLR) return fail(HODLR_EINVAL, "BDLR compression is not built yet");
+  if (o.method == HODLR_BDLR && n > 16384) return fail(HODLR_EINVAL, "BDLR supports n <= 16384");
   std::unique_ptr<hodlr_s> h(new hodlr_s());
   h->method = o.method;
   h->depth = o.bdlr_depth;
@@ -269,8 +269,11 @@ int hodlr_build(const double* K, int n, int ldk, const int* g_rowptr, const int*
     HODLR_TRY(Vcap.ensure((size_t)n * C * h->esize));
     HODLR_HIP(hipMemsetAsync(Ucap.p, 0, (size_t)n * C * h->esize, stream));
     HODLR_HIP(hipMemsetAsync(Vcap.p, 0, (size_t)n * C * h->esize, stream));
-    // a2: compression of every off-diagonal block
-    HODLR_TRY(launch_aca(h.get(), K, ldk, Ucap.p, Vcap.p, capoff, capq, stream));
+    // compression of every off-diagonal block
+    if (o.method == HODLR_BDLR)
+      HODLR_TRY(launch_bdlr(h.get(), K, ldk, g_rowptr, g_col, Ucap.p, Vcap.p, capoff, capq, stream));
+    else
+      HODLR_TRY(launch_aca(h.get(), K, ldk, Ucap.p, Vcap.p, capoff, capq, stream));
     HODLR_HIP(hipMemcpyAsync(h->rank.data(), h->d_rank.p, t.nnodes() * sizeof(int),
                              hipMemcpyDeviceToHost, stream));
     HODLR_HIP(hipStreamSynchronize(stream));

@@ -136,6 +136,10 @@ int launch_permute_graph(const int* rowptr, const int* col, int n, const int* pe
 int launch_aca(hodlr_s* h, const double* K, int ldk, void* Ucap, void* Vcap,
                const std::vector<int>& capoff, const std::vector<int>& cap, hipStream_t s);
 
+// bdlr.hip: boundary-distance skeletons of every off-diagonal block
+int launch_bdlr(hodlr_s* h, const double* K, int ldk, const int* rowptr, const int* col, void* Ucap,
+                void* Vcap, const std::vector<int>& capoff, const std::vector<int>& cap, hipStream_t s);
+
 // factor.hip
 int launch_stage_leaves_from_K(hodlr_s* h, const double* K, int ldk, hipStream_t s);
 int launch_stage_leaves_packed(hodlr_s* h, const double* leaves, hipStream_t s);

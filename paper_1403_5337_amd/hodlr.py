@@ -51,6 +51,8 @@ _SIGNATURES = {
     "hodlr_order_rcb": (ctypes.c_int, [_vp, ctypes.c_int, ctypes.c_int, _vp, _vp]),
     "hodlr_permute": (ctypes.c_int, [_vp, ctypes.c_int, ctypes.c_int, _vp, _vp, ctypes.c_int, _vp]),
     "hodlr_permute_graph": (ctypes.c_int, [_vp, _vp, ctypes.c_int, _vp, _vp, _vp, _vp]),
+    "hodlr_bdlr_select": (ctypes.c_int, [_vp, _vp, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int,
+                                         _vp, _vp, _vp]),
     "hodlr_stats": (ctypes.c_int, [_vp, _c_int_p, _c_int_p, _c_int_p]),
     "hodlr_get_factors": (ctypes.c_int, [_vp, _vp, _vp, _vp]),
     "hodlr_destroy": (ctypes.c_int, [_vp]),
@@ -90,6 +92,11 @@ def _stream(stream=None):
 
 def _ptr(t: Optional[torch.Tensor]):
     return ctypes.c_void_p(0 if t is None else t.data_ptr())
+
+
+def _i32(t: torch.Tensor) -> torch.Tensor:
+    """int32 contiguous view or copy; the caller keeps it alive across the call."""
+    return t.to(torch.int32).contiguous()
 
 
 def _need_gpu(*ts):
@@ -141,7 +148,8 @@ class Hodlr:
         n = Kc.shape[0]
         o = Opts(leaf=leaf, tol=tol, method=HODLR_BDLR if method == "bdlr" else HODLR_ACA,
                  bdlr_depth=depth, max_rank=max_rank, precision=precision)
-        rp, cp = (None, None) if graph is None else graph
+        rp, cp = (None, None) if graph is None else (_i32(graph[0]), _i32(graph[1]))
+        _need_gpu(rp, cp)
         h = ctypes.c_void_p()
         _check(lib().hodlr_build(_ptr(Kc), n, ldk, _ptr(rp), _ptr(cp), ctypes.byref(o), _stream(stream),
                                  ctypes.byref(h)))
@@ -158,7 +166,8 @@ class Hodlr:
         rk = (ctypes.c_int * max(len(ranks), 1))(*ranks)
         rc = (ctypes.c_int * max(len(rcols), 1))(*rcols)
         h = ctypes.c_void_p()
-        _check(lib().hodlr_build_from_factors(n, leaf, precision, _ptr(leaves.contiguous()), _ptr(U),
+        lv = leaves.contiguous()
+        _check(lib().hodlr_build_from_factors(n, leaf, precision, _ptr(lv), _ptr(U),
                                               _ptr(V), rk, rc, len(rcols), _stream(stream), ctypes.byref(h)))
         return cls(h, n, precision)
 
@@ -253,21 +262,40 @@ def hodlr_permute(K: torch.Tensor, perm: torch.Tensor, stream=None) -> torch.Ten
     _need_gpu(K, perm)
     Kc, ldk = colmajor(K, torch.float64)
     n = Kc.shape[0]
+    p32 = _i32(perm)
     out = torch.empty((n, n), dtype=torch.float64, device=K.device).t()
-    _check(lib().hodlr_permute(_ptr(Kc), n, ldk, _ptr(perm.to(torch.int32).contiguous()), _ptr(out), n,
-                               _stream(stream)))
+    _check(lib().hodlr_permute(_ptr(Kc), n, ldk, _ptr(p32), _ptr(out), n, _stream(stream)))
     return out
 
 
 def hodlr_permute_graph(rowptr: torch.Tensor, col: torch.Tensor, perm: torch.Tensor, stream=None):
     _need_gpu(rowptr, col, perm)
     n = rowptr.numel() - 1
-    ro = torch.empty_like(rowptr, dtype=torch.int32)
-    co = torch.empty_like(col, dtype=torch.int32)
-    _check(lib().hodlr_permute_graph(_ptr(rowptr.to(torch.int32).contiguous()), _ptr(col.to(torch.int32).contiguous()),
-                                     n, _ptr(perm.to(torch.int32).contiguous()), _ptr(ro), _ptr(co),
-                                     _stream(stream)))
+    r32, c32, p32 = _i32(rowptr), _i32(col), _i32(perm)
+    ro = torch.empty_like(r32)
+    co = torch.empty_like(c32)
+    _check(lib().hodlr_permute_graph(_ptr(r32), _ptr(c32), n, _ptr(p32), _ptr(ro), _ptr(co), _stream(stream)))
     return ro, co
+
+
+def hodlr_bdlr_select(rowptr: torch.Tensor, col: torch.Tensor, leaf: int, depth: int, max_skel: int,
+                      stream=None):
+    """BDLR picks of every off-diagonal block: list over nodes below the root
+    in level order of (rows, cols), each an int64 CPU tensor of positions."""
+    _need_gpu(rowptr, col)
+    r32, c32 = _i32(rowptr), _i32(col)
+    n = r32.numel() - 1
+    L = 0
+    while -(-n // (1 << L)) > leaf:
+        L += 1
+    nn = (2 << L) - 2
+    picks = torch.zeros(max(nn, 1) * 2 * max_skel, dtype=torch.int32, device=r32.device)
+    counts = torch.zeros(max(nn, 1) * 2, dtype=torch.int32, device=r32.device)
+    _check(lib().hodlr_bdlr_select(_ptr(r32), _ptr(c32), n, leaf, depth, max_skel, _ptr(picks), _ptr(counts),
+                                   _stream(stream)))
+    pk = picks.view(-1, 2, max_skel).cpu().long()
+    ct = counts.view(-1, 2).cpu().long()
+    return [(pk[k, 0, :ct[k, 0]], pk[k, 1, :ct[k, 1]]) for k in range(nn)]
 
 
 def hodlr_prof_enable(on: bool):
