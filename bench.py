@@ -24,7 +24,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
-KERNELS = ["aca", "leaf_inverse", "leaf_apply", "panel_tn", "schur_form", "form_E", "schur_apply", "correct", "apply_leaf", "apply_level",
+KERNELS = ["aca", "bdlr_select", "bdlr_lu", "bdlr_factors", "leaf_inverse", "leaf_apply", "panel_tn", "schur_form", "form_E", "schur_apply", "correct", "apply_leaf", "apply_level",
            "matvec", "orth"]
 
 
@@ -36,6 +36,8 @@ def parse():
     ap.add_argument("--workload", default="tpfa4096")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-lu", action="store_true")
+    ap.add_argument("--method", choices=["aca", "bdlr"], default="aca")
+    ap.add_argument("--depth", type=int, default=2, help="BDLR boundary distance")
     return ap.parse_args()
 
 
@@ -93,6 +95,8 @@ def main():
     n, s, leaf, tol, prec = front.n, w["nrhs"], w["leaf"], w["tol"], w["precision"]
     K = front.K.t().contiguous().t()  # column-major float64 (symmetric front: same values)
     coords = torch.from_numpy(front.coords).to(dev)
+    g_rp = torch.from_numpy(front.indptr).to(dev)
+    g_ci = torch.from_numpy(front.indices).to(dev)
     B = fronts.rhs(n, s, seed=0, device=dev).t().contiguous().t()
     stream = torch.cuda.current_stream()
 
@@ -102,9 +106,11 @@ def main():
             ev[0].record(stream)
         perm = H.hodlr_order_rcb(coords, leaf)
         Kp = H.hodlr_permute(K, perm)
+        graph = H.hodlr_permute_graph(g_rp, g_ci, perm) if args.method == "bdlr" else None
         if ev is not None:
             ev[1].record(stream)
-        h = H.Hodlr.build(Kp, leaf=leaf, tol=tol, precision=prec)
+        h = H.Hodlr.build(Kp, leaf=leaf, tol=tol, precision=prec, method=args.method, depth=args.depth,
+                          graph=graph)
         if ev is not None:
             ev[2].record(stream)
         h.factor()
@@ -130,7 +136,7 @@ def main():
     t1 = time.perf_counter()
     ms_step = (t1 - t0) * 1e3 / args.steps
     stages = np.array([[evs[k][j].elapsed_time(evs[k][j + 1]) for j in range(4)] for k in range(args.steps)])
-    stage_ms = dict(zip(["order_permute", "build_aca", "factor", "gmres"], np.median(stages, axis=0).round(4).tolist()))
+    stage_ms = dict(zip(["order_permute", "build", "factor", "gmres"], np.median(stages, axis=0).round(4).tolist()))
     kern = {}
     for name in KERNELS:
         cnt, tot = H.hodlr_prof_query(name)
@@ -195,16 +201,17 @@ def main():
         "vs_baseline": None,
         "dtype": "f64",
         "data": "synthetic",
-        "config": {"workload": args.workload, "n": n, "nrhs": s, "leaf": leaf, "compression": "aca",
+        "config": {"workload": args.workload, "n": n, "nrhs": s, "leaf": leaf, "compression": args.method,
                    "tol": tol, "hodlr_precision": "f32" if prec == 32 else "f64", "gmres_tol": 1e-12},
         "stage_ms": stage_ms,
+        "bdlr_depth": args.depth if args.method == "bdlr" else None,
         "iters": it,
         "relres_max": max(rr),
         "ranks_max_per_level": [max(r) for r in stats["ranks"]],
         "kernels": kern,
         "gpu_dense_lu_ms": None if lu_ms is None else round(lu_ms, 4),
         "speedup_vs_gpu_dense_lu": None if lu_ms is None else round(lu_ms / ms_step, 3),
-        "factor_ms_vs_lu": {"hodlr_build_plus_factor": round(stage_ms["build_aca"] + stage_ms["factor"], 4),
+        "factor_ms_vs_lu": {"hodlr_build_plus_factor": round(stage_ms["build"] + stage_ms["factor"], 4),
                             "dense_lu_factor_plus_solve": None if lu_ms is None else round(lu_ms, 4)},
         "roofline": roof,
         "cpu_baseline": cpu,

@@ -56,7 +56,8 @@ typedef struct {
                      (precision 32) / 128 (precision 64) rows and as many
                      columns are kept, nearest the boundary first, ties to
                      the lower index. */
-  int max_rank;   /* cap on every off-diagonal rank (0 = library maximum) */
+  int max_rank;   /* cap on every off-diagonal rank (0 = library maximum:
+                     184 at precision 32, 128 at precision 64) */
   int precision;  /* 32 or 64: arithmetic of the factorization and solve */
 } hodlr_opts;
 
@@ -91,8 +92,11 @@ int hodlr_build(const double* K, int n, int ldk, const int* g_rowptr, const int*
  *           U, and in the rows of its sibling, that node's V, so
  *           K(node, sibling) = U V^T.
  *   ranks   host int, one per node below the root in level order
- *           (level 1 left to right, then level 2, ...), each <= rcols[p-1].
- *   rcols   host int[L], width of each level's column block.
+ *           (level 1 left to right, then level 2, ...), each <= rcols[p-1]
+ *           and <= the smaller of the node's and its sibling's sizes.
+ *   rcols   host int[L], width of each level's column block, at most 184
+ *           (precision 32) / 128 (precision 64) and the level's largest
+ *           node.
  * Errors: EINVAL on inconsistent sizes, ENOMEM, EHIP. */
 int hodlr_build_from_factors(int n, int leaf, int precision, const double* leaves,
                              const double* Upanel, const double* Vpanel, const int* ranks,

@@ -260,7 +260,7 @@ int hodlr_build(const double* K, int n, int ldk, const int* g_rowptr, const int*
     std::vector<int> capq(t.L), capoff(t.L);
     int C = 0;
     for (int q = 1; q <= t.L; ++q) {
-      capq[q - 1] = std::min(cap, t.min_size(q));
+      capq[q - 1] = std::min(cap, t.max_size(q));
       capoff[q - 1] = C;
       C += capq[q - 1];
     }
@@ -315,11 +315,11 @@ int hodlr_build_from_factors(int n, int leaf, int precision, const double* leave
   const Tree& t = h->tree;
   int cap = rank_cap(precision);
   for (int q = 1; q <= t.L; ++q) {
-    if (rcols[q - 1] < 0 || rcols[q - 1] > cap || rcols[q - 1] > t.min_size(q))
+    if (rcols[q - 1] < 0 || rcols[q - 1] > cap || rcols[q - 1] > t.max_size(q))
       return fail(HODLR_EINVAL, "rcols out of range at level " + std::to_string(q));
     for (int i = 0; i < (1 << q); ++i) {
       int r = ranks[node_id(q, i) - 1];
-      if (r < 0 || r > rcols[q - 1])
+      if (r < 0 || r > rcols[q - 1] || r > std::min(t.size(node_id(q, i)), t.size(node_id(q, i ^ 1))))
         return fail(HODLR_EINVAL, "rank out of range at node " + std::to_string(node_id(q, i)));
       h->rank[node_id(q, i)] = r;
     }

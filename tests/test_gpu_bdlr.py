@@ -93,7 +93,7 @@ def test_select_rejects_bad_arguments():
 
 
 def _blocks_vs_oracle(g, leaf, depth, tol, precision):
-    K = g.K.numpy()
+    K = g.K.cpu().numpy()
     levs = tree.levels(g.n, leaf)
     graph = (torch.from_numpy(g.indptr).cuda(), torch.from_numpy(g.indices).cuda())
     h = H.Hodlr.build(g.K.cuda(), leaf=leaf, tol=tol, method="bdlr", depth=depth, precision=precision,
