@@ -18,8 +18,10 @@ Sec. 5.3.  For an off-diagonal block K(I, J) of a frontal matrix:
   triangular solves; K(I,J) ~ C~ R~.
 
 Full pivoting takes the entry of largest magnitude of the remaining Schur
-complement, ties to the lowest (row, column) in row-major order.  Rows and
-columns enter Ahat in increasing vertex index.
+complement, ties to the lowest (row, column) of Ahat in its original order,
+row first (the paper fixes no tie rule; this one does not depend on the
+order in which earlier pivots were swapped in).  Rows and columns enter Ahat
+in increasing vertex index.
 
 The optional adaptive loop (Sec. 5.3, monitoring the error on rows/columns
 outside the skeleton) samples rows and columns not picked and adds one
@@ -109,8 +111,11 @@ def full_pivot_lu(A: np.ndarray, eps: float, max_rank=None):
     r = 0
     for k in range(kmax):
         sub = np.abs(W[k:, k:])
-        flat = int(np.argmax(sub))  # row-major first maximum
-        pi, pj = divmod(flat, n - k)
+        top = sub.max()
+        ci, cj = np.nonzero(sub == top)
+        # ties: lowest original row of Ahat, then lowest original column
+        best = min(range(ci.size), key=lambda t: (prow[k + ci[t]], pcol[k + cj[t]]))
+        pi, pj = int(ci[best]), int(cj[best])
         piv = W[k + pi, k + pj]
         if first is None:
             first = abs(piv)

@@ -76,6 +76,18 @@ def test_full_pivot_lu_reconstructs():
         W[k + 1:, k + 1:] -= np.outer(W[k + 1:, k], W[k, k + 1:])
 
 
+def test_full_pivot_ties_go_to_lowest_original_index():
+    """Worked by hand: the first pivot 9 sits at (0, 2); the remaining block
+    then holds two 4s, at original columns 1 and 0 of Ahat.  The tie goes to
+    the lower original column 0 (a rule that compared swapped positions would
+    pick column 1); the last entry left is 0, so the rank is 2."""
+    A = np.array([[0.0, 0.0, 9.0], [4.0, 4.0, 0.0], [0.0, 0.0, 0.0]])
+    prow, pcol, L, U, r = bdlr.full_pivot_lu(A, 0.0)
+    assert r == 2
+    assert list(prow[:2]) == [0, 1] and list(pcol[:2]) == [2, 0]
+    assert np.allclose(U[:2, :2], [[9.0, 0.0], [0.0, 4.0]])
+
+
 @pytest.mark.parametrize("seed", range(5))
 def test_skeleton_identity_exact_low_rank(seed):
     rng = np.random.default_rng(seed)
