@@ -2,20 +2,22 @@
 // every off-diagonal block, all levels at once.
 //
 // For block K(I, J) (I = the node's rows, J = its sibling's, both contiguous
-// index ranges after the ordering) three launches, one workgroup per block:
+// index ranges after the ordering), one workgroup per block in each of:
 //   select  boundary sets (vertices with an edge into the other set), a
 //           level-synchronous breadth-first search inside each set up to
 //           depth-1, and the picked rows/columns: distance < depth, nearest
 //           the boundary first and at most max_skel of them, listed in
 //           increasing position;
-//   lu      Ahat = K(rows, cols) gathered into LDS, LU with full pivoting
+//   lu      Ahat = K(rows, cols) held in registers, LU with full pivoting
 //           (largest |entry| of the remaining Schur complement, ties to the
-//           lowest row-major position), kept while |pivot| >= eps |first
-//           pivot| (Sec. 7.1), giving rank r; then the r x r leading factors
-//           are inverted in place (U11^-1 and L11^-1);
-//   factors C~ = K(I, pivot columns) U11^-1 and R~^T = K(pivot rows, J)^T
-//           L11^-T as gathered panels times the small inverses, written as
-//           U = C~ and V = R~^T into the capped panels.
+//           lowest (row, column) of Ahat), kept while |pivot| >= eps |first
+//           pivot| (Sec. 7.1), giving rank r and the pivot rows and columns;
+//           then G = Ahat11^-1 for the r x r submatrix on them;
+//   gather  C = K(I, pivot columns) and V = K(pivot rows, J)^T;
+//   factors U = C G.
+// U V^T = C Ahat11^-1 R = (C Q)(:, 1:r) U11^-1 L11^-1 (P R)(1:r, :) is the
+// pseudo-skeleton C~ R~ of eq. Ahat; the split between the two factors
+// differs (one r x r inverse and one panel product instead of two of each).
 #include <algorithm>
 #include <climits>
 #include <cstdint>
@@ -167,156 +169,209 @@ __global__ void __launch_bounds__(kBlock)
             buf, s_cut);
 }
 
-template <typename T, int SKEL>
-__global__ void __launch_bounds__(kBlock)
-    k_bdlr_lu(const double* __restrict__ K, int ldk, const BdlrTask* __restrict__ tasks,
-              const int* __restrict__ sel, const int* __restrict__ counts, T eps,
-              int* __restrict__ piv_out, T* __restrict__ inv, int* __restrict__ rank_out,
-              int* __restrict__ rank_task) {
-  extern __shared__ __align__(16) unsigned char smem[];
-  T* A = reinterpret_cast<T*>(smem);
-  __shared__ int prow[SKEL], pcol[SKEL];
-  __shared__ T tmp[SKEL];
-  __shared__ T sv[kBlock / 64];
-  __shared__ int si[kBlock / 64];
-  __shared__ int s_r;
-  const int task = blockIdx.x, t = threadIdx.x;
-  const BdlrTask tk = tasks[task];
-  const int nr = counts[2 * task], nc = counts[2 * task + 1], ld = nr + 1;
-  const int* rows = sel + tk.sel_off;
-  const int* cols = sel + tk.sel_off + SKEL;
-  for (int e0 = 0; e0 < nr * nc; e0 += 8 * kBlock) {
-    T v[8];
+// Full-pivot elimination of Ahat held in registers: thread (lane, w) of the 4
+// waves owns rows lane + 64 a and columns w + 4 b of the tile.  Nothing
+// moves: pivoted rows and columns are retired, and every step applies the
+// rank-1 update of the Schur complement to the active elements only.  A step
+// costs two barriers: one to combine the four waves' candidates, one to
+// publish the pivot column; each wave takes the pivot row straight from the
+// lane that holds it, and the next step's candidate is tracked during the
+// update.  Only the pivot sequence is kept (prow, pcol: positions in Ahat).
+template <typename T, int RA, int CB>
+__device__ int full_pivot_steps(const double* __restrict__ Kb, int ldk, const int* srow, const int* scol,
+                                int nr, int nc, int kmax, T eps, int* prow, int* pcol, T* colv,
+                                T (*sv)[4], int (*si)[4], T* spiv) {
+  const int t = threadIdx.x, lane = t & 63;
+  const int w = __builtin_amdgcn_readfirstlane(t >> 6);
+  unsigned ract = 0;            // per lane: bit a = row lane + 64 a still active
+  unsigned long long cact = 0;  // per wave: bit b = column w + 4 b still active
 #pragma unroll
-    for (int u = 0; u < 8; ++u) {
-      const int e = e0 + t + u * kBlock, i = e % max(nr, 1), j = e / max(nr, 1);
-      v[u] = e < nr * nc ? (T)K[(size_t)(tk.col0 + cols[j]) * ldk + tk.row0 + rows[i]] : T(0);
-    }
+  for (int a = 0; a < RA; ++a) ract |= (lane + 64 * a < nr ? 1u : 0u) << a;
 #pragma unroll
-    for (int u = 0; u < 8; ++u) {
-      const int e = e0 + t + u * kBlock;
-      if (e < nr * nc) A[e % nr + (e / nr) * ld] = v[u];
+  for (int b = 0; b < CB; ++b) cact |= (w + 4 * b < nc ? 1ull : 0ull) << b;
+  T x[RA][CB];
+#pragma unroll
+  for (int a = 0; a < RA; ++a) {
+    const int i = lane + 64 * a;
+    const int ri = srow[i];
+#pragma unroll
+    for (int b = 0; b < CB; ++b) {
+      const int j = w + 4 * b;
+      x[a][b] = (i < nr && j < nc) ? (T)Kb[(size_t)scol[j] * ldk + ri] : T(0);
     }
   }
-  for (int i = t; i < SKEL; i += kBlock) {
-    prow[i] = i;
-    pcol[i] = i;
+  // candidate: the first largest |entry| over active elements in (row,
+  // column) order, encoded 256 i + j
+  T bv;
+  int bi;
+  {
+    T bva[RA];
+    int bba[RA];
+#pragma unroll
+    for (int a = 0; a < RA; ++a) {
+      bva[a] = T(-1);
+      bba[a] = 0;
+      const T rm = ((ract >> a) & 1u) ? T(1) : T(0);
+#pragma unroll
+      for (int b = 0; b < CB; ++b)
+        if ((cact >> b) & 1ull) {
+          const T m = fabs(x[a][b]) * rm;
+          if (m > bva[a]) {
+            bva[a] = m;
+            bba[a] = b;
+          }
+        }
+    }
+    bv = bva[0];
+    bi = lane * 256 + w + 4 * bba[0];
+#pragma unroll
+    for (int a = 1; a < RA; ++a) argmax_merge(bv, bi, bva[a], (lane + 64 * a) * 256 + w + 4 * bba[a]);
   }
-  __syncthreads();
-  const int kmax = min(min(nr, nc), tk.kmax);
   T first = T(0);
   int r = 0;
   for (int k = 0; k < kmax; ++k) {
-    // largest |entry| of the trailing block; ties to the lowest row-major position
-    T bv = T(-1);
-    int bi = INT_MAX;
-    const int w = nc - k, tot = (nr - k) * w;
-    for (int e = t; e < tot; e += kBlock) {
-      const int i = k + e / w, j = k + e % w;
-      argmax_merge(bv, bi, dabs(A[i + j * ld]), e);
+    const int par = k & 1;
+    wave_argmax(bv, bi);
+    if (lane == 0) {
+      sv[par][w] = bv;
+      si[par][w] = bi;
     }
-    T pv;
-    int flat;
-    block_argmax(bv, bi, sv, si, pv, flat);
+    __syncthreads();
+    T pv = sv[par][0];
+    int flat = si[par][0];
+#pragma unroll
+    for (int q = 1; q < 4; ++q) argmax_merge(pv, flat, sv[par][q], si[par][q]);
     if (k == 0) first = pv;
     if (!(pv > T(0)) || pv < eps * first || !(pv < T(INFINITY))) break;
-    const int pi = k + flat / w, pj = k + flat % w;
-    if (pi != k) {
-      for (int j = t; j < nc; j += kBlock) {
-        const T x = A[k + j * ld];
-        A[k + j * ld] = A[pi + j * ld];
-        A[pi + j * ld] = x;
-      }
-      if (t == 0) {
-        const int x = prow[k];
-        prow[k] = prow[pi];
-        prow[pi] = x;
-      }
+    const int pi = __builtin_amdgcn_readfirstlane(flat >> 8);
+    const int pj = __builtin_amdgcn_readfirstlane(flat & 255);
+    const int pl = pi & 63, ap = pi >> 6, wp = pj & 3, bp = pj >> 2;
+    if (t == 0) {
+      prow[k] = pi;
+      pcol[k] = pj;
     }
-    __syncthreads();
-    if (pj != k) {
-      for (int i = t; i < nr; i += kBlock) {
-        const T x = A[i + k * ld];
-        A[i + k * ld] = A[i + pj * ld];
-        A[i + pj * ld] = x;
+    // the pivot column (register column bp of wave wp), pivot entry apart
+    if (w == wp) {
+#pragma unroll
+      for (int a = 0; a < RA; ++a) {
+        T v = x[a][0];
+#pragma unroll
+        for (int b = 1; b < CB; ++b) v = (b == bp) ? x[a][b] : v;
+        const int i = lane + 64 * a;
+        if (i == pi) *spiv = v;  // read after the barrier below, before the next write
+        colv[i] = (((ract >> a) & 1u) && i != pi) ? v : T(0);
       }
-      if (t == 0) {
-        const int x = pcol[k];
-        pcol[k] = pcol[pj];
-        pcol[pj] = x;
+      cact &= ~(1ull << bp);
+    }
+    if (lane == pl) ract &= ~(1u << ap);
+    __syncthreads();
+    const T p = *spiv;
+    T l[RA];
+#pragma unroll
+    for (int a = 0; a < RA; ++a) l[a] = colv[lane + 64 * a] / p;
+    T bva[RA], rm[RA];
+    int bba[RA];
+#pragma unroll
+    for (int a = 0; a < RA; ++a) {
+      bva[a] = T(-1);
+      bba[a] = 0;
+      rm[a] = ((ract >> a) & 1u) ? T(1) : T(0);
+    }
+#pragma unroll
+    for (int b = 0; b < CB; ++b)
+      if ((cact >> b) & 1ull) {
+        T v = x[0][b];
+#pragma unroll
+        for (int a = 1; a < RA; ++a)
+          if (ap == a) v = x[a][b];
+        const T rv = lane_value(v, pl);
+#pragma unroll
+        for (int a = 0; a < RA; ++a) {
+          x[a][b] = fma(-l[a], rv, x[a][b]);
+          const T m = fabs(x[a][b]) * rm[a];
+          if (m > bva[a]) {
+            bva[a] = m;
+            bba[a] = b;
+          }
+        }
       }
-    }
-    __syncthreads();
-    const T rp = T(1) / A[k + k * ld];
-    for (int i = k + 1 + t; i < nr; i += kBlock) A[i + k * ld] *= rp;
-    __syncthreads();
-    const int h = nr - k - 1;
-    for (int e = t; e < h * (nc - k - 1); e += kBlock) {
-      const int i = k + 1 + e % h, j = k + 1 + e / h;
-      A[i + j * ld] -= A[i + k * ld] * A[k + j * ld];
-    }
-    __syncthreads();
+    bv = bva[0];
+    bi = lane * 256 + w + 4 * bba[0];
+#pragma unroll
+    for (int a = 1; a < RA; ++a) argmax_merge(bv, bi, bva[a], (lane + 64 * a) * 256 + w + 4 * bba[a]);
     r = k + 1;
   }
-  if (t == 0) {
-    s_r = r;
-    rank_out[tk.node] = r;
-    rank_task[task] = r;
-  }
-  for (int l = t; l < r; l += kBlock) {
-    piv_out[tk.sel_off + l] = rows[prow[l]];         // picked rows in pivot order
-    piv_out[tk.sel_off + SKEL + l] = cols[pcol[l]];  // picked columns in pivot order
+  return r;
+}
+
+// Pivots and G = Ahat11^-1 of every block: the elimination runs on the
+// smallest register tile (64, 128 or SKEL square) that holds Ahat.
+template <typename T, int SKEL>
+__global__ void __launch_bounds__(kBlock)
+    k_bdlr_lu(const double* __restrict__ K, int ldk, const BdlrTask* __restrict__ tasks,
+              const int* __restrict__ sel, const int* __restrict__ counts, T eps, int rcap,
+              int* __restrict__ piv_out, T* __restrict__ inv, int* __restrict__ rank_out,
+              int* __restrict__ rank_task) {
+  static_assert(SKEL % 64 == 0 && SKEL <= 256, "tile shape");
+  __shared__ int srow[SKEL], scol[SKEL], prow[SKEL], pcol[SKEL];
+  __shared__ T colv[SKEL];
+  __shared__ GjRegScratchAll<T, (sizeof(T) == 8 ? kRankCap64 : kRankCap32)> gw;
+  __shared__ T sv[2][4], spiv;
+  __shared__ int si[2][4];
+  const int task = blockIdx.x, t = threadIdx.x;
+  const BdlrTask tk = tasks[task];
+  const int nr = counts[2 * task], nc = counts[2 * task + 1];
+  for (int x = t; x < SKEL; x += kBlock) {
+    srow[x] = x < nr ? sel[tk.sel_off + x] : 0;
+    scol[x] = x < nc ? sel[tk.sel_off + SKEL + x] : 0;
   }
   __syncthreads();
-  // In-place inverse of U11 (upper), column by column:
-  // Uinv(0:j, j) = -Uinv(0:j, 0:j) U(0:j, j) / U(j, j)
-  for (int j = 0; j < r; ++j) {
-    const T ujj = T(1) / A[j + j * ld];
-    for (int i = t; i < j; i += kBlock) {
-      T s = T(0);
-      for (int l = i; l < j; ++l) s += A[i + l * ld] * A[l + j * ld];
-      tmp[i] = -s * ujj;
-    }
-    __syncthreads();
-    for (int i = t; i < j; i += kBlock) A[i + j * ld] = tmp[i];
-    if (t == 0) A[j + j * ld] = ujj;
-    __syncthreads();
+  const double* Kb = K + (size_t)tk.col0 * ldk + tk.row0;
+  const int kmax = min(min(nr, nc), min(tk.kmax, rcap));
+  const int side = max(nr, nc);
+  int r;
+  if (side <= 64)
+    r = full_pivot_steps<T, 1, 16>(Kb, ldk, srow, scol, nr, nc, kmax, eps, prow, pcol, colv, sv, si, &spiv);
+  else if (side <= 128 || SKEL <= 128)
+    r = full_pivot_steps<T, 2, 32>(Kb, ldk, srow, scol, nr, nc, kmax, eps, prow, pcol, colv, sv, si, &spiv);
+  else
+    r = full_pivot_steps<T, SKEL / 64, SKEL / 4>(Kb, ldk, srow, scol, nr, nc, kmax, eps, prow, pcol, colv, sv,
+                                                 si, &spiv);
+  for (int q = t; q < r; q += kBlock) {
+    piv_out[tk.sel_off + q] = srow[prow[q]];         // picked rows in pivot order
+    piv_out[tk.sel_off + SKEL + q] = scol[pcol[q]];  // picked columns in pivot order
   }
-  // In-place inverse of the unit lower L11, from the last column back:
-  // Linv(j+1:r, j) = -Linv(j+1:r, j+1:r) L(j+1:r, j)
-  for (int j = r - 2; j >= 0; --j) {
-    for (int i = j + 1 + t; i < r; i += kBlock) {
-      T s = A[i + j * ld];
-      for (int l = j + 1; l < i; ++l) s += A[i + l * ld] * A[l + j * ld];
-      tmp[i] = -s;
-    }
-    __syncthreads();
-    for (int i = j + 1 + t; i < r; i += kBlock) A[i + j * ld] = tmp[i];
-    __syncthreads();
-  }
-  T* Ui = inv + tk.inv_off;               // r x r, ld r: U11^-1
-  T* LiT = inv + tk.inv_off + SKEL * SKEL;  // r x r, ld r: (L11^-1)^T
-  for (int e = t; e < r * r; e += kBlock) {
-    const int i = e % r, j = e / r;
-    Ui[i + (size_t)j * r] = (i <= j) ? A[i + j * ld] : T(0);
-    // (L^-1)^T (i, j) = L^-1 (j, i): unit lower -> unit upper
-    LiT[i + (size_t)j * r] = (i < j) ? A[j + i * ld] : (i == j ? T(1) : T(0));
+  // G = Ahat11^-1 with Ahat11 = Ahat(pivot rows, pivot columns), read again
+  // from K; (L11 U11)^-1 = U11^-1 L11^-1, so C(:, pivot columns) G R(pivot
+  // rows, :) is the pseudo-skeleton C~ R~.
+  __syncthreads();
+  T* G = inv + tk.inv_off;  // r x r, ld r
+  const bool ok =
+      r == 0 || gj_invert([&](int i, int j) { return (T)Kb[(size_t)scol[pcol[j]] * ldk + srow[prow[i]]]; },
+                          r, G, r, gw);
+  if (t == 0) {
+    const int rr = ok ? r : 0;  // a numerically singular Ahat11 drops the block
+    rank_out[tk.node] = rr;
+    rank_task[task] = rr;
   }
 }
 
-// Gathers the panels: side 0: C(i, l) = K(row0 + i, pivot column l);
-// side 1: Rt(j, l) = K(pivot row l, col0 + j).
+// Gathers the panels: side 0: C(i, l) = K(row0 + i, pivot column l) into the
+// work panel; side 1: V(j, l) = K(pivot row l, col0 + j) straight into the
+// capped V panel.
 template <typename T, int SKEL>
 __global__ void __launch_bounds__(kBlock)
     k_bdlr_gather(const double* __restrict__ K, int ldk, const BdlrTask* __restrict__ tasks,
-                  const int* __restrict__ piv, const int* __restrict__ rank_task, T* __restrict__ cg) {
+                  const int* __restrict__ piv, const int* __restrict__ rank_task, T* __restrict__ cg,
+                  T* __restrict__ Vcap, int ldu) {
   const int task = blockIdx.x, side = blockIdx.z, t = threadIdx.x;
   const BdlrTask tk = tasks[task];
   const int r = rank_task[task];
   const int len = side == 0 ? tk.m : tk.nc;
   const int i = blockIdx.y * kBlock + t;
   if (i >= len || r == 0) return;
-  T* out = cg + tk.cg_off + (side == 0 ? 0 : (size_t)tk.m * tk.kmax);
+  T* out = side == 0 ? cg + tk.cg_off : Vcap + (size_t)tk.capcol * ldu + tk.col0;
+  const int ldo = side == 0 ? len : ldu;
   const int* pv = piv + tk.sel_off + (side == 0 ? SKEL : 0);
   for (int l0 = 0; l0 < r; l0 += 8) {
     T v[8];
@@ -333,27 +388,23 @@ __global__ void __launch_bounds__(kBlock)
     }
 #pragma unroll
     for (int u = 0; u < 8; ++u)
-      if (l0 + u < r) out[i + (size_t)(l0 + u) * len] = v[u];
+      if (l0 + u < r) out[i + (size_t)(l0 + u) * ldo] = v[u];
   }
 }
 
-// U(rows of I) = C U11^-1 ; V(rows of J) = Rt L11^-T, 256 rows per workgroup.
-template <typename T, int SKEL>
+// U(rows of I) = C G, 256 rows per workgroup.
+template <typename T>
 __global__ void __launch_bounds__(kBlock)
     k_bdlr_factors(const BdlrTask* __restrict__ tasks, const int* __restrict__ rank_task,
-                   const T* __restrict__ cg, const T* __restrict__ inv, T* __restrict__ Ucap,
-                   T* __restrict__ Vcap, int ldu) {
+                   const T* __restrict__ cg, const T* __restrict__ inv, T* __restrict__ Ucap, int ldu) {
   __shared__ T As[32 * 33], Bs[32 * 33];
-  const int task = blockIdx.x, side = blockIdx.z;
+  const int task = blockIdx.x;
   const BdlrTask tk = tasks[task];
   const int r = rank_task[task];
-  const int len = side == 0 ? tk.m : tk.nc;
-  const int i0 = blockIdx.y * 256, rn = min(256, len - i0);
+  const int i0 = blockIdx.y * 256, rn = min(256, tk.m - i0);
   if (rn <= 0 || r == 0) return;
-  const T* P = cg + tk.cg_off + (side == 0 ? 0 : (size_t)tk.m * tk.kmax) + i0;
-  const T* Mi = inv + tk.inv_off + (side == 0 ? 0 : (size_t)SKEL * SKEL);
-  T* out = (side == 0 ? Ucap + tk.row0 : Vcap + tk.col0) + i0 + (size_t)tk.capcol * ldu;
-  wg_gemm(rn, r, r, T(1), P, len, Mi, r, T(0), out, ldu, As, Bs);
+  wg_gemm(rn, r, r, T(1), cg + tk.cg_off + i0, tk.m, inv + tk.inv_off, r, T(0),
+          Ucap + tk.row0 + i0 + (size_t)tk.capcol * ldu, ldu, As, Bs);
 }
 
 // One task per node below the root, in level order (level 1 left to right,
@@ -381,8 +432,8 @@ static std::vector<BdlrTask> make_tasks(const Tree& tr, const std::vector<int>& 
       tk.inv_off = invo;
       tk.cg_off = cgo;
       selo += 2 * skel;
-      invo += 2 * (size_t)skel * skel;
-      cgo += (size_t)(tk.m + tk.nc) * tk.kmax;
+      invo += (size_t)skel * skel;
+      cgo += (size_t)tk.m * tk.kmax;
       tasks.push_back(tk);
     }
   *inv_elems = invo;
@@ -418,24 +469,25 @@ static int bdlr_t(hodlr_s* h, const double* K, int ldk, const int* rowptr, const
                                         d_sel.as<int>(), d_cnt.as<int>());
   }
   HODLR_HIP(hipGetLastError());
-  const size_t lds = (size_t)SKEL * (SKEL + 1) * sizeof(T);
-  HODLR_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(k_bdlr_lu<T, SKEL>),
-                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+  const int rcap = h->precision == 64 ? kRankCap64 : kRankCap32;
   {
     ProfScope prof("bdlr_lu", s);
-    k_bdlr_lu<T, SKEL><<<nt, kBlock, lds, s>>>(K, ldk, d_tasks.as<BdlrTask>(), d_sel.as<int>(),
-                                              d_cnt.as<int>(), (T)h->tol, d_piv.as<int>(), d_inv.as<T>(),
+    k_bdlr_lu<T, SKEL><<<nt, kBlock, 0, s>>>(K, ldk, d_tasks.as<BdlrTask>(), d_sel.as<int>(),
+                                              d_cnt.as<int>(), (T)h->tol, rcap, d_piv.as<int>(), d_inv.as<T>(),
                                               h->d_rank.as<int>(), d_rt.as<int>());
   }
   HODLR_HIP(hipGetLastError());
   const int nch = (maxside + kBlock - 1) / kBlock;
   {
-    ProfScope prof("bdlr_factors", s);
+    ProfScope prof("bdlr_gather", s);
     k_bdlr_gather<T, SKEL><<<dim3(nt, nch, 2), kBlock, 0, s>>>(K, ldk, d_tasks.as<BdlrTask>(), d_piv.as<int>(),
-                                                              d_rt.as<int>(), d_cg.as<T>());
-    k_bdlr_factors<T, SKEL><<<dim3(nt, nch, 2), kBlock, 0, s>>>(d_tasks.as<BdlrTask>(), d_rt.as<int>(),
-                                                               d_cg.as<T>(), d_inv.as<T>(), Ucap, Vcap,
-                                                               tr.n);
+                                                              d_rt.as<int>(), d_cg.as<T>(), Vcap, tr.n);
+  }
+  HODLR_HIP(hipGetLastError());
+  {
+    ProfScope prof("bdlr_factors", s);
+    k_bdlr_factors<T><<<dim3(nt, nch, 1), kBlock, 0, s>>>(d_tasks.as<BdlrTask>(), d_rt.as<int>(), d_cg.as<T>(),
+                                                          d_inv.as<T>(), Ucap, tr.n);
   }
   HODLR_HIP(hipGetLastError());
   HODLR_HIP(hipStreamSynchronize(s));  // scratch goes back to the allocator cache

@@ -74,25 +74,15 @@ template <typename T>
 __global__ void __launch_bounds__(kBlock)
     k_leaf_inverse(T* __restrict__ Kinv, int bmax, const int* __restrict__ lo,
                    const int* __restrict__ hi, int id0, int* __restrict__ status) {
-  extern __shared__ __align__(16) unsigned char smem[];
-  T* A = reinterpret_cast<T*>(smem);
-  __shared__ GjScratch<T> gw;
+  __shared__ GjRegScratchAll<T, (sizeof(T) == 8 ? kRankCap64 : kRankCap32)> gw;
   const int leaf = blockIdx.x, id = id0 + leaf, t = threadIdx.x;
-  const int b = hi[id] - lo[id], ld = b + 1;
+  const int b = hi[id] - lo[id];
   T* Gm = Kinv + (size_t)leaf * bmax * bmax;
-  for (int e = t; e < b * b; e += blockDim.x) A[e % b + (e / b) * ld] = Gm[e % b + (size_t)(e / b) * bmax];
-  __syncthreads();
-  const bool ok = gj_inverse(A, b, ld, gw);
-  if (!ok) {
-    if (t == 0) {
-      atomicExch(status + 0, 1);
-      atomicExch(status + 1, id);
-    }
-    return;
-  }
-  for (int e = t; e < b * b; e += blockDim.x) {
-    const int i = e % b, j = e / b;
-    Gm[i + (size_t)j * bmax] = A[i + gw.src[j] * ld];
+  const bool ok = gj_invert(
+      [&](int i, int j) { return Gm[i + (size_t)j * bmax]; }, b, Gm, bmax, gw);
+  if (!ok && t == 0) {
+    atomicExch(status + 0, 1);
+    atomicExch(status + 1, id);
   }
 }
 
@@ -209,7 +199,7 @@ __global__ void __launch_bounds__(kBlock)
   T* M = reinterpret_cast<T*>(smem);        // rq x (rq + 1)
   T* As = M + (size_t)rq * (rq + 1);        // GEMM tiles
   T* Bs = As + 32 * 33;
-  __shared__ GjScratch<T> gw;
+  __shared__ GjRegScratchAll<T, (sizeof(T) == 8 ? kRankCap64 : kRankCap32)> gw;
   const int i = blockIdx.x, t = threadIdx.x, nt = blockDim.x;
   const int a = node_id(q, 2 * i), b = node_id(q, 2 * i + 1);
   const int ra = rank[a], rb = rank[b], ldm = ra + 1, lds = 2 * rq;
@@ -224,7 +214,7 @@ __global__ void __launch_bounds__(kBlock)
   for (int x = t; x < ra; x += nt) M[x + x * ldm] += T(1);
   __syncthreads();
   if (ra > 0) {
-    const bool ok = gj_inverse(M, ra, ldm, gw);
+    const bool ok = gj_invert([&](int r, int c) { return M[r + c * ldm]; }, ra, S22, lds, gw);
     if (!ok) {
       if (t == 0) {
         atomicExch(status + 0, 2);
@@ -233,8 +223,6 @@ __global__ void __launch_bounds__(kBlock)
       return;
     }
   }
-  for (int y = 0; y < ra; ++y)
-    for (int x = t; x < ra; x += nt) S22[x + (size_t)y * lds] = M[x + gw.src[y] * ldm];
   __syncthreads();
   wg_gemm(ra, rb, ra, T(-1), S22, lds, Bm, rq, T(0), S21, lds, As, Bs);
   wg_gemm(rb, ra, ra, T(-1), Am, rq, S22, lds, T(0), S12, lds, As, Bs);
@@ -501,11 +489,9 @@ static int factor_t(hodlr_s* h, hipStream_t s) {
   const Tree& t = h->tree;  // (tree)
   const int n = t.n, L = t.L;
   HODLR_HIP(hipMemsetAsync(h->status.p, 0, 4 * sizeof(int), s));
-  const size_t lds_leaf = (size_t)h->bmax * (h->bmax + 1) * sizeof(T);
-  HODLR_TRY(allow_lds(k_leaf_inverse<T>, lds_leaf));
   {
     ProfScope prof_("leaf_inverse", s);
-    k_leaf_inverse<T><<<h->nleaf, kBlock, lds_leaf, s>>>(h->Kinv.as<T>(), h->bmax, h->d_lo.as<int>(),
+    k_leaf_inverse<T><<<h->nleaf, kBlock, 0, s>>>(h->Kinv.as<T>(), h->bmax, h->d_lo.as<int>(),
                                                          h->d_hi.as<int>(), node_id(L, 0),
                                                          h->status.as<int>());
   }
