@@ -21,8 +21,10 @@
 // runs the same three kernels on the right-hand side after the leaf solve.
 #include <algorithm>
 #include <string>
+#include <vector>
 
 #include "device_util.h"
+#include "gemm.h"
 #include "hodlr_internal.h"
 
 namespace hodlr {
@@ -125,110 +127,27 @@ __global__ void __launch_bounds__(kBlock)
 }
 
 // ---------------------------------------------------------------------------
-// G_c = W(rows c, wcol0 : wcol0+rq)^T * Z(rows c, 0 : zcols) for every node c
-// of one level; G_c is rq x zcols (ld rq), node stride rq * zcols.
-// ---------------------------------------------------------------------------
-template <typename T>
-__global__ void __launch_bounds__(kBlock)
-    k_panel_tn(const T* __restrict__ W, int ldw, int wcol0, int rq, const T* __restrict__ Z,
-               int ldz, int zcols, const int* __restrict__ lo, const int* __restrict__ hi, int id0,
-               T* __restrict__ G) {
-  constexpr int TR = 64, TM = 64, KC = 16;
-  __shared__ T Ws[KC][TR + 1];
-  __shared__ T Zs[KC][TM + 1];
-  const int node = blockIdx.x, id = id0 + node, r0 = blockIdx.y * TR, m0 = blockIdx.z * TM;
-  const int t = threadIdx.x, tx = t % 16, ty = t / 16;
-  const int l0 = lo[id], len = hi[id] - l0;
-  T acc[4][4];
-#pragma unroll
-  for (int a = 0; a < 4; ++a)
-#pragma unroll
-    for (int c = 0; c < 4; ++c) acc[a][c] = T(0);
-  for (int k0 = 0; k0 < len; k0 += KC) {
-    T wv[KC * TR / kBlock], zv[KC * TR / kBlock];
-#pragma unroll
-    for (int u = 0; u < KC * TR / kBlock; ++u) {
-      const int e = t + u * kBlock;
-      const int kk = e % KC, r = e / KC, row = k0 + kk, col = r0 + r, m = m0 + r;
-      wv[u] = (row < len && col < rq) ? W[(size_t)(wcol0 + col) * ldw + l0 + row] : T(0);
-      zv[u] = (row < len && m < zcols) ? Z[(size_t)m * ldz + l0 + row] : T(0);
-    }
-#pragma unroll
-    for (int u = 0; u < KC * TR / kBlock; ++u) {
-      const int e = t + u * kBlock;
-      Ws[e % KC][e / KC] = wv[u];
-      Zs[e % KC][e / KC] = zv[u];
-    }
-    __syncthreads();
-#pragma unroll
-    for (int kk = 0; kk < KC; ++kk) {
-      T a[4], z[4];
-#pragma unroll
-      for (int u = 0; u < 4; ++u) {
-        a[u] = Ws[kk][tx + 16 * u];
-        z[u] = Zs[kk][ty + 16 * u];
-      }
-#pragma unroll
-      for (int u = 0; u < 4; ++u)
-#pragma unroll
-        for (int v = 0; v < 4; ++v) acc[u][v] += a[u] * z[v];
-    }
-    __syncthreads();
-  }
-  T* Gc = G + (size_t)node * rq * zcols;
-#pragma unroll
-  for (int u = 0; u < 4; ++u)
-#pragma unroll
-    for (int v = 0; v < 4; ++v) {
-      const int r = r0 + tx + 16 * u, m = m0 + ty + 16 * v;
-      if (r < rq && m < zcols) Gc[r + (size_t)m * rq] = acc[u][v];
-    }
-}
-
-// ---------------------------------------------------------------------------
-// Inverse capacitance matrix of every parent of level q (one workgroup each).
-// With A = V_b^T d_a (r_b x r_a) and B = V_a^T d_b (r_a x r_b) read from the
-// d-columns of G, S = [[I, A], [B, I]] and, with M = I - B A,
+// Capacitance inverse per parent of level q.  With A = V_b^T d_a (r_b x r_a)
+// and B = V_a^T d_b (r_a x r_b), S = [[I, A], [B, I]] (eq. SchurSum) and, with
+// M = I - B A,
 //   S^-1 = [[I + A M^-1 B, -A M^-1], [-M^-1 B, M^-1]].
+// M is formed in the S22 block by a batched product; this kernel inverts it
+// in place; the other three blocks follow as batched products.
 // ---------------------------------------------------------------------------
 template <typename T>
 __global__ void __launch_bounds__(kBlock)
-    k_schur_form(const T* __restrict__ G, int rq, int gcols, int offq, const int* __restrict__ rank,
-                 int q, T* __restrict__ Sinv, int* __restrict__ status) {
-  extern __shared__ __align__(16) unsigned char smem[];
-  T* M = reinterpret_cast<T*>(smem);        // rq x (rq + 1)
-  T* As = M + (size_t)rq * (rq + 1);        // GEMM tiles
-  T* Bs = As + 32 * 33;
+    k_capacitance_inverse(const int* __restrict__ rank, int q, int rq, T* __restrict__ Sinv,
+                          int* __restrict__ status) {
   __shared__ GjRegScratchAll<T, (sizeof(T) == 8 ? kRankCap64 : kRankCap32)> gw;
-  const int i = blockIdx.x, t = threadIdx.x, nt = blockDim.x;
-  const int a = node_id(q, 2 * i), b = node_id(q, 2 * i + 1);
-  const int ra = rank[a], rb = rank[b], ldm = ra + 1, lds = 2 * rq;
-  const T* Am = G + (size_t)(2 * i) * rq * gcols + (size_t)offq * rq;      // r_b x r_a, ld rq
-  const T* Bm = G + (size_t)(2 * i + 1) * rq * gcols + (size_t)offq * rq;  // r_a x r_b, ld rq
-  T* S = Sinv + (size_t)i * lds * lds;
-  T* S22 = S + rb + (size_t)rb * lds;  // M^-1      (r_a x r_a)
-  T* S21 = S + rb;                     // -M^-1 B   (r_a x r_b)
-  T* S12 = S + (size_t)rb * lds;       // -A M^-1   (r_b x r_a)
-  // M = I - B A
-  wg_gemm(ra, ra, rb, T(-1), Bm, rq, Am, rq, T(0), M, ldm, As, Bs);
-  for (int x = t; x < ra; x += nt) M[x + x * ldm] += T(1);
-  __syncthreads();
-  if (ra > 0) {
-    const bool ok = gj_invert([&](int r, int c) { return M[r + c * ldm]; }, ra, S22, lds, gw);
-    if (!ok) {
-      if (t == 0) {
-        atomicExch(status + 0, 2);
-        atomicExch(status + 1, node_id(q - 1, i));
-      }
-      return;
-    }
+  const int i = blockIdx.x;
+  const int ra = rank[node_id(q, 2 * i)], rb = rank[node_id(q, 2 * i + 1)], lds = 2 * rq;
+  if (ra == 0) return;
+  T* S22 = Sinv + (size_t)i * lds * lds + rb + (size_t)rb * lds;
+  const bool ok = gj_invert([&](int r, int c) { return S22[r + (size_t)c * lds]; }, ra, S22, lds, gw);
+  if (!ok && threadIdx.x == 0) {
+    atomicExch(status + 0, 2);
+    atomicExch(status + 1, node_id(q - 1, i));
   }
-  __syncthreads();
-  wg_gemm(ra, rb, ra, T(-1), S22, lds, Bm, rq, T(0), S21, lds, As, Bs);
-  wg_gemm(rb, ra, ra, T(-1), Am, rq, S22, lds, T(0), S12, lds, As, Bs);
-  // S11 = I + A M^-1 B = I - A S21
-  wg_gemm(rb, rb, ra, T(-1), Am, rq, S21, lds, T(0), S, lds, As, Bs);
-  for (int x = t; x < rb; x += nt) S[x + (size_t)x * lds] += T(1);
 }
 
 // y = S^-1 [t_a; t_b] for every parent of level q: t_a = G_a(0:r_b, 0:ccols),
@@ -321,31 +240,6 @@ __global__ void __launch_bounds__(kBlock)
     for (int k = 0; k < CT; ++k) acc[k] += d * Yo[l + k * rc];
   }
   for (int k = 0; k < nc; ++k) Z[(size_t)(c0 + k) * ldz + row] -= acc[k];
-}
-
-// ---------------------------------------------------------------------------
-// E_c = d_c S_P^-1(y rows of c, :) for every node c of level q (the solve's
-// correction operator): one workgroup per node and 256-row chunk.
-// ---------------------------------------------------------------------------
-template <typename T>
-__global__ void __launch_bounds__(kBlock)
-    k_form_E(const T* __restrict__ Y, int ldy, int offq, int rq, const T* __restrict__ Sinv,
-             const int* __restrict__ lo, const int* __restrict__ hi, const int* __restrict__ rank, int q,
-             T* __restrict__ E, int offE) {
-  __shared__ T As[32 * 33], Bs[32 * 33];
-  const int c = blockIdx.x, par = c >> 1, left = (c & 1) == 0, id = node_id(q, c);
-  const int ra = rank[node_id(q, 2 * par)], rb = rank[node_id(q, 2 * par + 1)], r = ra + rb;
-  const int rc = left ? ra : rb, yoff = left ? rb : 0, lds = 2 * rq;
-  const int row0 = lo[id] + blockIdx.y * 256, rn = min(256, hi[id] - row0);
-  if (rn <= 0 || r == 0) return;
-  const T* S = Sinv + (size_t)par * lds * lds + yoff;
-  if (rc == 0) {
-    for (int e = threadIdx.x; e < rn * r; e += blockDim.x)
-      E[(size_t)(offE + e / rn) * ldy + row0 + e % rn] = T(0);
-    return;
-  }
-  wg_gemm(rn, r, rc, T(1), Y + (size_t)offq * ldy + row0, ldy, S, lds, T(0),
-          E + (size_t)offE * ldy + row0, ldy, As, Bs);
 }
 
 // ---------------------------------------------------------------------------
@@ -506,33 +400,141 @@ static int factor_t(hodlr_s* h, hipStream_t s) {
         h->Kinv.as<T>(), h->bmax, h->d_lo.as<int>(), h->d_hi.as<int>(), node_id(L, 0), Y, n, h->R);
   }
   HODLR_HIP(hipGetLastError());
+  gemm_reset(h);
   for (int q = L; q >= 1; --q) {
     const int rq = h->rcols[q - 1], offq = h->off[q - 1];
     if (rq == 0) continue;
-    const int zc = offq + rq;
+    const int zc = offq + rq, lds = 2 * rq, np = 1 << (q - 1);
     T* G = h->G.as<T>();
+    T* Sq = h->Sinv.as<T>() + h->sinv_off[q - 1];
+    std::vector<GemmTask> gt;
+    // panel products G_c = V_sib^T Z_c (V of the sibling is stored in c's rows)
     {
+      int tiles = 0, kmax = 1;
+      for (int c = 0; c < (1 << q); ++c) {
+        const int rs = h->rank[node_id(q, c ^ 1)];
+        tiles += ((rs + 63) / 64) * ((zc + 63) / 64);
+        kmax = std::max(kmax, t.size(node_id(q, c)));
+      }
+      const int ks = std::max(1, std::min((256 + tiles - 1) / std::max(tiles, 1), kmax / 128));
+      for (int c = 0; c < (1 << q); ++c) {
+        const int id = node_id(q, c);
+        GemmTask g;
+        g.A = W + (size_t)offq * n + t.lo[id];
+        g.lda = n;
+        g.transA = 1;
+        g.B = Y + t.lo[id];
+        g.ldb = n;
+        g.C = G + (size_t)c * rq * zc;
+        g.ldc = rq;
+        g.m = h->rank[node_id(q, c ^ 1)];
+        g.n = zc;
+        g.k = t.size(id);
+        g.ksplit = ks;
+        gt.push_back(g);
+      }
       ProfScope prof_("panel_tn", s);
-      k_panel_tn<T><<<dim3(1 << q, cdiv(rq, 64), cdiv(zc, 64)), kBlock, 0, s>>>(
-          W, n, offq, rq, Y, n, zc, h->d_lo.as<int>(), h->d_hi.as<int>(), node_id(q, 0), G);
+      HODLR_TRY(gemm_batched(h, gt, s));
     }
-    HODLR_HIP(hipGetLastError());
-    const size_t lds_s = ((size_t)rq * (rq + 1) + 2 * 32 * 33) * sizeof(T);
-    HODLR_TRY(allow_lds(k_schur_form<T>, lds_s));
+    // S22 <- M = I - B A, then M^-1 in place
+    gt.clear();
+    for (int i = 0; i < np; ++i) {
+      const int ra = h->rank[node_id(q, 2 * i)], rb = h->rank[node_id(q, 2 * i + 1)];
+      T* S = Sq + (size_t)i * lds * lds;
+      GemmTask g;
+      g.A = G + (size_t)(2 * i + 1) * rq * zc + (size_t)offq * rq;  // B: r_a x r_b
+      g.lda = rq;
+      g.B = G + (size_t)(2 * i) * rq * zc + (size_t)offq * rq;      // A: r_b x r_a
+      g.ldb = rq;
+      g.C = S + rb + (size_t)rb * lds;
+      g.ldc = lds;
+      g.m = ra;
+      g.n = ra;
+      g.k = rb;
+      g.alpha = -1.0;
+      g.mode = kGemmAddIdentity;
+      gt.push_back(g);
+    }
     {
       ProfScope prof_("schur_form", s);
-      k_schur_form<T><<<1 << (q - 1), kBlock, lds_s, s>>>(G, rq, zc, offq, h->d_rank.as<int>(), q,
-                                                           h->Sinv.as<T>() + h->sinv_off[q - 1],
-                                                           h->status.as<int>());
+      HODLR_TRY(gemm_batched(h, gt, s));
+      k_capacitance_inverse<T><<<np, kBlock, 0, s>>>(h->d_rank.as<int>(), q, rq, Sq, h->status.as<int>());
+      HODLR_HIP(hipGetLastError());
+      // S21 = -M^-1 B, S12 = -A M^-1
+      gt.clear();
+      for (int i = 0; i < np; ++i) {
+        const int ra = h->rank[node_id(q, 2 * i)], rb = h->rank[node_id(q, 2 * i + 1)];
+        T* S = Sq + (size_t)i * lds * lds;
+        const T* Am = G + (size_t)(2 * i) * rq * zc + (size_t)offq * rq;
+        const T* Bm = G + (size_t)(2 * i + 1) * rq * zc + (size_t)offq * rq;
+        const T* S22 = S + rb + (size_t)rb * lds;
+        GemmTask g;
+        g.alpha = -1.0;
+        g.A = S22;
+        g.lda = lds;
+        g.B = Bm;
+        g.ldb = rq;
+        g.C = S + rb;
+        g.ldc = lds;
+        g.m = ra;
+        g.n = rb;
+        g.k = ra;
+        gt.push_back(g);
+        g.A = Am;
+        g.lda = rq;
+        g.B = S22;
+        g.ldb = lds;
+        g.C = S + (size_t)rb * lds;
+        g.m = rb;
+        g.n = ra;
+        g.k = ra;
+        gt.push_back(g);
+      }
+      HODLR_TRY(gemm_batched(h, gt, s));
+      // S11 = I - A S21
+      gt.clear();
+      for (int i = 0; i < np; ++i) {
+        const int ra = h->rank[node_id(q, 2 * i)], rb = h->rank[node_id(q, 2 * i + 1)];
+        T* S = Sq + (size_t)i * lds * lds;
+        GemmTask g;
+        g.alpha = -1.0;
+        g.mode = kGemmAddIdentity;
+        g.A = G + (size_t)(2 * i) * rq * zc + (size_t)offq * rq;
+        g.lda = rq;
+        g.B = S + rb;
+        g.ldb = lds;
+        g.C = S;
+        g.ldc = lds;
+        g.m = rb;
+        g.n = rb;
+        g.k = ra;
+        gt.push_back(g);
+      }
+      HODLR_TRY(gemm_batched(h, gt, s));
     }
-    HODLR_HIP(hipGetLastError());
+    // E_c = d_c S^-1(y rows of c, :): rows r_b.. for a left child, 0.. for a right one
+    gt.clear();
+    for (int c = 0; c < (1 << q); ++c) {
+      const int par = c >> 1, left = (c & 1) == 0, id = node_id(q, c);
+      const int ra = h->rank[node_id(q, 2 * par)], rb = h->rank[node_id(q, 2 * par + 1)];
+      const int rc = left ? ra : rb, yoff = left ? rb : 0;
+      if (ra + rb == 0) continue;
+      GemmTask g;
+      g.A = Y + (size_t)offq * n + t.lo[id];
+      g.lda = n;
+      g.B = Sq + (size_t)par * lds * lds + yoff;
+      g.ldb = lds;
+      g.C = h->E.as<T>() + (size_t)h->offE[q - 1] * n + t.lo[id];
+      g.ldc = n;
+      g.m = t.size(id);
+      g.n = ra + rb;
+      g.k = rc;
+      gt.push_back(g);
+    }
     {
       ProfScope prof_("form_E", s);
-      k_form_E<T><<<dim3(1 << q, cdiv(t.max_size(q), 256)), kBlock, 0, s>>>(
-          Y, n, offq, rq, h->Sinv.as<T>() + h->sinv_off[q - 1], h->d_lo.as<int>(), h->d_hi.as<int>(),
-          h->d_rank.as<int>(), q, h->E.as<T>(), h->offE[q - 1]);
+      HODLR_TRY(gemm_batched(h, gt, s));
     }
-    HODLR_HIP(hipGetLastError());
     if (offq > 0) HODLR_TRY(level_solve<T>(h, q, Y, n, offq, G, zc, 1, s));
   }
   return HODLR_OK;

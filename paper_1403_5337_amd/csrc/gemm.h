@@ -1,0 +1,34 @@
+// Batched small dense products (gemm.hip).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <vector>
+
+struct hodlr_s;
+
+namespace hodlr {
+
+enum { kGemmOverwrite = 0, kGemmAccumulate = 1, kGemmAddIdentity = 2 };
+
+// C (m x n, ld ldc) = alpha op(A) B, then + C (kGemmAccumulate) or + I
+// (kGemmAddIdentity).  op(A) is A (m x k, ld lda) or, with transA, the
+// transpose of A stored k x m (ld lda).  B is k x n (ld ldb).  Column-major,
+// element type of the handle's precision.  ksplit > 1 splits k over that many
+// workgroups per tile and sums the partial tiles afterwards.
+struct GemmTask {
+  const void* A = nullptr;
+  const void* B = nullptr;
+  void* C = nullptr;
+  int m = 0, n = 0, k = 0, lda = 0, ldb = 0, ldc = 0;
+  int transA = 0, mode = kGemmOverwrite, ksplit = 1;
+  double alpha = 1.0;
+};
+
+// All tasks in one launch (plus one for the split sums).  Task tables and
+// split partials live in per-handle arenas that the caller resets (gemm_reset)
+// once the stream has drained.
+int gemm_batched(hodlr_s* h, const std::vector<GemmTask>& tasks, hipStream_t s);
+void gemm_reset(hodlr_s* h);
+
+}  // namespace hodlr

@@ -117,6 +117,8 @@ struct hodlr_s {
   size_t p_half = 0;    // elements of one partial-product buffer of the solve
   hodlr::DevBuf Ybuf;   // work: per-node Woodbury solutions
   hodlr::DevBuf status; // int[4]: 0 singular flag, 1 node, 2 abort
+  hodlr::DevBuf gemm_tab, gemm_work;  // arenas of the batched products
+  size_t gemm_tab_used = 0, gemm_work_used = 0;
   bool factored = false;
 };
 
