@@ -4,10 +4,11 @@ preconditioner, next to GPU dense LU, the dominant kernel's roofline and the
 FP64 oracle timed on the host.
 
 One step = the whole hot path on one front, inputs resident in HBM:
-  recursive-coordinate-bisection order -> permuted front -> ACA compression
-  of every off-diagonal block (float32) -> level-by-level Woodbury
-  factorization (float32) -> flexible GMRES in float64 on 8 right-hand sides
-  to a relative residual of 1e-12.
+  recursive-coordinate-bisection order -> permuted front and separator graph
+  -> compression of every off-diagonal block (BDLR boundary-distance
+  skeletons, depth 2, by default; ACA with --method aca) in float32 ->
+  level-by-level Woodbury factorization (float32) -> flexible GMRES in
+  float64 on 8 right-hand sides to a relative residual of 1e-12.
 value = right-hand sides solved per second of step time.
 
 Workload (synthetic, seeded): Schur complement onto the middle plane of a
@@ -36,43 +37,109 @@ def parse():
     ap.add_argument("--workload", default="tpfa4096")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-lu", action="store_true")
-    ap.add_argument("--method", choices=["aca", "bdlr"], default="aca")
+    ap.add_argument("--method", choices=["aca", "bdlr"], default="bdlr")
     ap.add_argument("--depth", type=int, default=2, help="BDLR boundary distance")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="only run a plain 256 MiB device copy 3 times (reference for HBM counters)")
     return ap.parse_args()
 
 
-def cpu_baseline(front, w, nrhs_sample):
+def cpu_baseline(front, w, nrhs_sample, method, depth):
     """The FP64 oracle, as it stands, on the same front: ordering,
     compression, factorization and GMRES for `nrhs_sample` right-hand sides."""
-    import numpy as np
     from threadpoolctl import threadpool_info
 
     from gen import fronts
     from oracle import gmres, hodlr, ordering
 
-    K = front.K.cpu().numpy()
-    coords = front.coords
+    fc = fronts.Front(K=front.K.cpu(), indptr=front.indptr, indices=front.indices, coords=front.coords,
+                      name=front.name)
     B = fronts.rhs(front.n, nrhs_sample, seed=0).numpy()
-    t0 = time.perf_counter()
-    perm = ordering.rcb_permutation(coords, w["leaf"])
-    Kp = K[np.ix_(perm, perm)]
-    h = hodlr.from_dense(Kp, w["leaf"], method="aca", eps=w["tol"])
-    hodlr.factor(h)
-    X, infos = gmres.fgmres_multi(lambda v: Kp @ v, B, lambda v: hodlr.solve(h, v), tol=1e-12, maxit=1000,
-                                  restart=200)
-    dt = time.perf_counter() - t0
+    # whole pipelines, repeated until about 10 s of host work have been timed
+    reps, t0 = 0, time.perf_counter()
+    while True:
+        perm = ordering.rcb_permutation(fc.coords, w["leaf"])
+        g = fronts.permute_front(fc, perm)
+        Kp = g.K.numpy()
+        if method == "bdlr":
+            h = hodlr.from_dense(Kp, w["leaf"], method="bdlr", eps=w["tol"], graph=(g.indptr, g.indices),
+                                 depth=depth, max_skel=192)
+        else:
+            h = hodlr.from_dense(Kp, w["leaf"], method="aca", eps=w["tol"])
+        hodlr.factor(h)
+        X, infos = gmres.fgmres_multi(lambda v: Kp @ v, B, lambda v: hodlr.solve(h, v), tol=1e-12,
+                                      maxit=1000, restart=200)
+        reps += 1
+        if time.perf_counter() - t0 >= 10.0:
+            break
+    dt = (time.perf_counter() - t0) / reps
     threads = 1
     for p in threadpool_info():
         if p.get("internal_api") in ("openblas", "mkl", "blis"):
             threads = max(threads, int(p.get("num_threads", 1)))
     return dict(value=nrhs_sample / dt, unit="solves/s", cores=threads, kind="oracle",
-                sample=f"full oracle pipeline (RCB order, ACA 1e-4, recursive Woodbury factor, FGMRES to 1e-12) "
-                       f"on the same n={front.n} front for {nrhs_sample} of {w['nrhs']} right-hand sides; "
-                       f"{dt:.1f} s, iterations {[i['iters'] for i in infos]}")
+                sample=f"full oracle pipeline (RCB order, {method.upper()} 1e-4, recursive Woodbury factor, FGMRES to 1e-12) "
+                       f"on the same n={front.n} front for {nrhs_sample} of {w['nrhs']} right-hand sides, "
+                       f"{reps} repetitions, {dt:.2f} s each; iterations {[i['iters'] for i in infos]}")
+
+
+def roofline(name, k, stats, n, s, leaf, ez):
+    """Algorithmic traffic (or flops) of one launch of kernel `name`, from the
+    sizes and the ranks found; achieved = that / average launch time."""
+    ranks = stats["ranks"]  # per level p = 1..L: ranks of its 2^p nodes
+    L = len(ranks)
+    avg_s = k["avg_us"] * 1e-6
+    bound, unit, peak, work, note = "hbm", "GB/s", HBM_PEAK_GBS, None, None
+    if name == "matvec":
+        # K read once in float64 + the iterate (float32 z in the Arnoldi steps) + the float64 output
+        work = 8.0 * n * n + 4.0 * n * s + 8.0 * n * s
+        note = "K (f64) + z (f32) + w (f64) per launch"
+    elif name == "apply_level":
+        # per level q: E_c (|c| x (r_a + r_b)) for every node, the W block of level q-1
+        # (n x r_{q-1}), x read and written; averaged over the L launches of one apply
+        tot = 0.0
+        for q in range(1, L + 1):
+            e = sum((n >> q) * (ranks[q - 1][2 * (c // 2)] + ranks[q - 1][2 * (c // 2) + 1])
+                    for c in range(1 << q))
+            w = n * max(ranks[q - 2]) if q > 1 else 0
+            tot += ez * (e + w + 2 * n * s)
+        work = tot / L
+        note = "E_c, next-level W block, x in/out; mean over the L level launches of one apply"
+    elif name == "apply_leaf":
+        work = ez * (n * leaf + n * max(ranks[-1]) + 2 * n * s) if ranks else ez * (n * leaf + 2 * n * s)
+        note = "leaf inverses, level-L W block, x in/out"
+    elif name == "aca":
+        lv = [(n >> p) for p in range(1, L + 1)]
+        entries = sum(sum(r) * 2 * lv[p] for p, r in enumerate(ranks))
+        work = entries * 8.0 + entries * ez
+        note = "latency-bound chain of dependent pivot steps; bytes = K entries read + U,V written"
+    elif name == "bdlr_lu":
+        # full-pivot elimination on each skeleton (<= r x r active after r steps) + r^3 Gauss-Jordan
+        fl = 0.0
+        for q in range(1, L + 1):
+            for r in ranks[q - 1]:
+                fl += 2.0 * sum((r - i) ** 2 for i in range(r)) + 2.0 * r ** 3
+        bound, unit, peak, work = "alu", "TFLOP/s", 157.3, fl
+        note = "lower bound on flops (active block taken as r x r); one launch per build"
+    if work is None:
+        return dict(kernel=name, bound=bound, achieved=None, peak=peak, unit=unit, frac=None, traffic=None)
+    scale = 1e9 if unit == "GB/s" else 1e12
+    ach = work / avg_s / scale
+    return dict(kernel=name, bound=bound, achieved=round(ach, 3), peak=peak, unit=unit,
+                frac=round(ach / peak, 5), traffic=None, algo_per_launch=work, avg_us=k["avg_us"], note=note)
 
 
 def main():
     args = parse()
+    if args.calibrate_copy:
+        import torch
+        a = torch.ones(64 << 20, device="cuda:0")
+        b = torch.empty_like(a)
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes_read_per_dispatch": 4 * a.numel(), "dispatches": 3}))
+        return
     if args.gpus != 1:
         print(json.dumps({"error": "this benchmark runs on one GPU only; multi-GPU sharding of the HODLR "
                                    "tree is a design note, not an implemented path", "n_gpus": args.gpus}))
@@ -146,28 +213,9 @@ def main():
     H.hodlr_prof_enable(False)
     assert st == H.HODLR_OK and max(rr) <= 1e-12, (st, rr)
 
-    # dominant kernel and its roofline (algorithmic bytes per launch)
+    # dominant kernel and its roofline (algorithmic bytes or flops per launch)
     dom = max(kern, key=lambda k: kern[k]["ms_per_step"])
-    roof = None
-    if dom == "matvec":
-        algo = 8.0 * n * n + 4.0 * n * s + 8.0 * n * s  # K (f64) + z (f32) + w (f64)
-        avg_s = kern[dom]["avg_us"] * 1e-6
-        roof = dict(kernel="matvec", bound="hbm", achieved=round(algo / avg_s / 1e9, 1), peak=HBM_PEAK_GBS,
-                    unit="GB/s", frac=round(algo / avg_s / 1e9 / HBM_PEAK_GBS, 4), traffic=None,
-                    algo_bytes_per_launch=algo, avg_us=kern[dom]["avg_us"])
-    elif dom == "aca":
-        ranks = stats["ranks"]
-        lv = [(n >> p) for p in range(1, len(ranks) + 1)]
-        entries = sum(sum(r) * 2 * lv[p] for p, r in enumerate(ranks))
-        algo = entries * 8.0 + entries * 4.0  # K entries read (f64) + U/V written (f32)
-        avg_s = kern[dom]["avg_us"] * 1e-6
-        roof = dict(kernel="aca", bound="hbm", achieved=round(algo / avg_s / 1e9, 2), peak=HBM_PEAK_GBS,
-                    unit="GB/s", frac=round(algo / avg_s / 1e9 / HBM_PEAK_GBS, 6), traffic=None,
-                    algo_bytes_per_launch=algo, avg_us=kern[dom]["avg_us"],
-                    note="latency-bound chain of dependent pivot steps; bytes = K entries read + U,V written")
-    else:
-        roof = dict(kernel=dom, bound="hbm", achieved=None, peak=HBM_PEAK_GBS, unit="GB/s", frac=None,
-                    traffic=None)
+    roof = roofline(dom, kern[dom], stats, n, s, leaf, 4 if prec == 32 else 8)
 
     # GPU dense FP64 LU comparator (rocSOLVER through torch): factor + solve
     lu_ms = None
@@ -186,7 +234,7 @@ def main():
 
     cpu = None
     if not args.no_cpu_baseline:
-        cpu = cpu_baseline(front, w, 2)
+        cpu = cpu_baseline(front, w, s, args.method, args.depth)
 
     out = {
         "metric": "GMRES-to-1e-12 solves/sec (HODLR-preconditioned, end to end incl. compression and factorization)",
