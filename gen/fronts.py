@@ -107,10 +107,16 @@ def _coupling_update(Apq: sp.spmatrix, Aqp: sp.spmatrix, T: torch.Tensor, device
 
 def separator_graph(A: sp.csr_matrix, m: int, zs: int):
     """CSR pattern of the separator's own diagonal block of the sparse matrix
-    (the interaction graph of Sec. 5.3), self loops removed, int32."""
+    (the interaction graph of Sec. 5.3), self loops removed, int32.
+
+    The pattern is made symmetric (an edge where either S_ij or S_ji is
+    nonzero): the operators are symmetric, and an entry that rounds to an
+    exact zero on one side only must not make the graph directed."""
     S = A[zs * m:(zs + 1) * m, zs * m:(zs + 1) * m].tocoo()
     keep = (S.row != S.col) & (S.data != 0.0)
-    G = sp.csr_matrix((np.ones(int(keep.sum())), (S.row[keep], S.col[keep])), shape=(m, m))
+    r, c = S.row[keep], S.col[keep]
+    G = sp.csr_matrix((np.ones(2 * r.size), (np.concatenate([r, c]), np.concatenate([c, r]))), shape=(m, m))
+    G.data[:] = 1.0
     G.sort_indices()
     return G.indptr.astype(np.int32), G.indices.astype(np.int32)
 

@@ -39,7 +39,7 @@ typedef enum {
   HODLR_EHIP = 5       /* a HIP runtime call or kernel failed */
 } hodlr_status;
 
-enum { HODLR_ACA = 0, HODLR_BDLR = 1 };
+enum { HODLR_ACA = 0, HODLR_BDLR = 1, HODLR_LEARNED = 2 };
 
 typedef struct {
   int leaf;       /* largest leaf block, 1..184 (precision 32) or 1..128
@@ -50,7 +50,8 @@ typedef struct {
                      |u_k||v_k| <= eps |U V^T|_F (Sec. 5.1), or the BDLR
                      relative pivot threshold |pivot| >= eps |first pivot|
                      (Sec. 7.1). */
-  int method;     /* HODLR_ACA or HODLR_BDLR */
+  int method;     /* HODLR_ACA, HODLR_BDLR or HODLR_LEARNED (scorer-proposed
+                     skeletons with ACA fallback, see hodlr_mlp_forward) */
   int bdlr_depth; /* BDLR: pick rows/cols at graph distance < depth from the
                      block boundary (Sec. 5.3), 1..250.  At most 192
                      (precision 32) / 128 (precision 64) rows and as many
@@ -59,10 +60,30 @@ typedef struct {
   int max_rank;   /* cap on every off-diagonal rank (0 = library maximum:
                      184 at precision 32, 128 at precision 64) */
   int precision;  /* 32 or 64: arithmetic of the factorization and solve */
+  /* HODLR_LEARNED only: every block first takes the skel_k best-scoring rows
+     and columns of each side as the skeleton rows/columns of eq. Ahat
+     (Sec. 5.3); its relative Frobenius error is estimated from 16 whole
+     rows and 16 whole columns outside the skeleton (the residual there,
+     scaled by rows outside / rows sampled, over |block|_F^2, the larger of
+     the row and column estimates, float64); a block above skel_tol retries
+     with twice the size, up to 192 (precision 32) / 128 (precision 64),
+     then is compressed by ACA instead. */
+  int skel_k;                /* first skeleton size, >= 1 (default 32) */
+  const float* mlp_params;   /* device float32, 4801 scorer parameters in the
+                                layout of hodlr_mlp_forward; read during the
+                                call only */
+  unsigned long long seed;   /* sample stream of the error check */
+  double skel_tol;           /* HODLR_LEARNED: largest accepted sampled error
+                                (0 = 30 tol: a skeleton truncated at relative
+                                pivot tol has a block error about an order of
+                                magnitude above tol) */
+  int bdlr_max_skel;         /* HODLR_BDLR: cap on the rows (columns) picked
+                                per side, nearest first (0 = 192 / 128) */
 } hodlr_opts;
 
 /* Fill *opts with defaults: leaf 128, tol 1e-4, ACA, depth 1, max_rank 0,
- * precision 32. */
+ * precision 32, skel_k 32, mlp_params NULL, seed 0, skel_tol 0,
+ * bdlr_max_skel 0. */
 void hodlr_default_opts(hodlr_opts* opts);
 
 /* Compress K into a HODLR matrix (Sec. 4.3.1 step 1).
@@ -72,14 +93,18 @@ void hodlr_default_opts(hodlr_opts* opts);
  *   g_rowptr, g_col
  *           device CSR (int32, n+1 and nnz entries) of the separator's
  *           sparse interaction graph in K's numbering (Sec. 5.3); required
- *           for HODLR_BDLR, ignored (may be NULL) for HODLR_ACA.
+ *           for HODLR_BDLR and HODLR_LEARNED, ignored (may be NULL) for
+ *           HODLR_ACA.
+ *   coords  device n x 3 float32 (row-major) dof coordinates in K's
+ *           numbering; required for HODLR_LEARNED, else ignored.
  *   opts    host; NULL = defaults.
  *   out     host; receives the new handle.
  * Synchronizes the stream once (to size the factor storage from the ranks
- * found).  Errors: EINVAL (n < 1, ldk < n, NULL K/out, bad opts, BDLR with
- * n > 16384 or without the graph), ENOMEM, EHIP. */
+ * found; HODLR_LEARNED synchronizes once per size tried).  Errors: EINVAL
+ * (n < 1, ldk < n, NULL K/out, bad opts, BDLR or learned with n > 16384 or
+ * without the graph, learned without coords or parameters), ENOMEM, EHIP. */
 int hodlr_build(const double* K, int n, int ldk, const int* g_rowptr, const int* g_col,
-                const hodlr_opts* opts, hipStream_t stream, hodlr_t* out);
+                const float* coords, const hodlr_opts* opts, hipStream_t stream, hodlr_t* out);
 
 /* Test/benchmark hook: a HODLR matrix given directly by its pieces.
  *   leaves  device float64, the leaf blocks packed leaf after leaf, each
@@ -181,6 +206,62 @@ int hodlr_stats(hodlr_t h, int* nlevels, int* ranks, int* rcols);
  * hodlr_build_from_factors (device, n x R, ld n).  Valid before
  * hodlr_factor (afterwards the U panel holds the factorization). */
 int hodlr_get_factors(hodlr_t h, double* Upanel, double* Vpanel, hipStream_t stream);
+
+/* HODLR_LEARNED handles: per node below the root in level order, the
+ * skeleton size that passed the check, 0 where the block fell back to ACA
+ * (-1 for handles built otherwise).  kused: host, 2^(L+1)-2 ints. */
+int hodlr_skel_info(hodlr_t h, int* kused);
+
+/* Learned skeleton proposer (not in the paper; it proposes the skeleton rows
+ * and columns that BDLR picks by boundary distance, Sec. 5.3).
+ *
+ * Samples: the off-diagonal blocks of the tree for (n, leaf) in level order
+ * (node 1, 2, ...); block of node c: the |c| row vertices, then the |sibling|
+ * column vertices; 2 n L samples in all.  Features, 8 float32 per sample
+ * (row-major), for a vertex v of side S (other side O) of a block:
+ *   d / (dmax + 1), 1 / (1 + d)   d = breadth-first distance inside S from
+ *                                 the vertices of S with an edge into O (a
+ *                                 vertex never reached: dmax + 1), dmax the
+ *                                 largest distance reached on S
+ *   deg(v) / max deg on S         graph degree
+ *   x, y, z scaled to [0, 1] over the bounding box of S (0 on a flat axis)
+ *   |K_vv| / max on S
+ *   min(1, distance from v to the bounding box of O / diagonal of S's box)
+ * g_rowptr/g_col/coords/K as for hodlr_build; feats: device, 2 n L x 8.
+ * Synchronizes.  Errors: EINVAL (2 <= n <= 16384, n > leaf), ENOMEM, EHIP. */
+int hodlr_skel_features(const int* g_rowptr, const int* g_col, const float* coords, const double* K, int n,
+                        int ldk, int leaf, float* feats, hipStream_t stream);
+
+/* Training labels: 1.0 where the sample is a pivot row (row side) or pivot
+ * column (column side) of the block's compression at tol in the given
+ * precision, else 0.0.  source 0: the crosses of ACA (as hodlr_build with
+ * HODLR_ACA); source 1: the pivots of the full-pivot LU of the BDLR skeleton
+ * at the given depth (as HODLR_BDLR; needs the graph).
+ * labels: device, 2 n L float32.  Synchronizes.  Errors: as hodlr_build. */
+int hodlr_skel_labels(const double* K, int n, int ldk, const int* g_rowptr, const int* g_col, int leaf,
+                      double tol, int precision, int source, int depth, float* labels, hipStream_t stream);
+
+/* Scorer: per sample z = w3 . relu(W2 relu(W1 x + b1) + b2) + b3.
+ * params: device float32, 4801 values: W1 (64 x 8 row-major), b1 (64),
+ * W2 (64 x 64 row-major), b2 (64), w3 (64), b3 (1).  bf16 != 0 rounds the
+ * weights to bfloat16 (nearest, ties to even) before use; accumulation is
+ * float32.  feats: device N x 8; logits: device N.  Asynchronous. */
+int hodlr_mlp_forward(const float* feats, int N, const float* params, int bf16, float* logits,
+                      hipStream_t stream);
+
+/* Gradient of the mean weighted logistic loss
+ *   L = mean_i [ p y_i softplus(-z_i) + (1 - y_i) softplus(z_i) ]
+ * (p = pos_weight, y = labels in {0, 1}) with respect to params (same layout),
+ * into grad (device, 4801); loss (device, 1 value) may be NULL.  Partial sums
+ * are combined in a fixed order.  Synchronizes. */
+int hodlr_mlp_grad(const float* feats, const float* labels, int N, const float* params, int bf16,
+                   float pos_weight, float* grad, float* loss, hipStream_t stream);
+
+/* One training step: the gradient above with bfloat16 weights, then Adam
+ * (beta1 0.9, beta2 0.999, eps 1e-8, bias-corrected at step >= 1) on the
+ * float32 params with moments m, v (device, 4801 each).  Synchronizes. */
+int hodlr_mlp_adam_step(const float* feats, const float* labels, int N, float* params, float* m, float* v,
+                        int step, float lr, float pos_weight, float* loss, hipStream_t stream);
 
 /* Frees the handle.  Synchronizes the device first (its device blocks go
  * back to the library's allocator cache for reuse). */

@@ -100,7 +100,7 @@ __global__ void __launch_bounds__(kBlock)
     k_aca(const double* __restrict__ K, int ldk, const AcaTask* __restrict__ tasks,
           const int* __restrict__ wg_task, int wg_base, T* __restrict__ Ucap, T* __restrict__ Vcap,
           int ldu, T* rec, int rec_stride, unsigned* bars,
-          int* __restrict__ rank_out, int* __restrict__ status, T eps) {
+          int* __restrict__ rank_out, int* __restrict__ status, T eps, int* __restrict__ piv_out_rec) {
   constexpr int LD = SLICE + 1;
   extern __shared__ __align__(16) unsigned char smem[];
   T* Us = reinterpret_cast<T*>(smem);           // KCAP x LD: U slice, column l at l*LD
@@ -219,6 +219,10 @@ __global__ void __launch_bounds__(kBlock)
     const int jstar = s_j;
     const T piv = s_piv;
     if (t == 0) colused[jstar >> 5] |= 1u << (jstar & 31);
+    if (piv_out_rec && g == 0 && t == 0) {  // pivot row and column of cross k
+      piv_out_rec[(size_t)(tk.node - 1) * 2 * KCAP + k] = istar;
+      piv_out_rec[(size_t)(tk.node - 1) * 2 * KCAP + KCAP + k] = jstar;
+    }
     if (t < cn) {
       const T v = rown[t] / piv;
       Vs[k * LD + t] = v;
@@ -325,14 +329,19 @@ __global__ void __launch_bounds__(kBlock)
 // Occupancy-limited cooperative launches over contiguous ranges of groups.
 template <typename T, int KCAP, int SLICE>
 static int aca_t(hodlr_s* h, const double* K, int ldk, T* Ucap, T* Vcap,
-                 const std::vector<int>& capoff, const std::vector<int>& cap, hipStream_t s) {
+                 const std::vector<int>& capoff, const std::vector<int>& cap, hipStream_t s,
+                 const std::vector<int>* nodes, int* piv) {
   const Tree& tr = h->tree;
   if (tr.n > 2 * kMaxBlockDim) return fail(HODLR_EINVAL, "ACA supports n <= 16384");
   // blocks, largest first
   std::vector<AcaTask> tasks;
+  std::vector<char> want(tr.nnodes(), nodes ? 0 : 1);
+  if (nodes)
+    for (int c : *nodes) want[c] = 1;
   for (int q = 1; q <= tr.L; ++q)
     for (int i = 0; i < (1 << q); ++i) {
       const int c = node_id(q, i), sib = node_id(q, i ^ 1);
+      if (!want[c]) continue;
       AcaTask tk{};
       tk.node = c;
       tk.row0 = tr.lo[c];
@@ -344,6 +353,7 @@ static int aca_t(hodlr_s* h, const double* K, int ldk, T* Ucap, T* Vcap,
       tk.kmax = std::min(std::min(tk.m, tk.nc), std::min(cap[q - 1], KCAP));
       tasks.push_back(tk);
     }
+  if (tasks.empty()) return HODLR_OK;
   int total = 0;
   for (auto& tk : tasks) {
     tk.g0 = total;
@@ -382,7 +392,7 @@ static int aca_t(hodlr_s* h, const double* K, int ldk, T* Ucap, T* Vcap,
   T* p_rec = static_cast<T*>(uc);
   unsigned* p_bars = reinterpret_cast<unsigned*>(static_cast<char*>(uc) + rec_bytes);
   HODLR_HIP(hipMemsetAsync(p_bars, 0, total * sizeof(unsigned), s));
-  HODLR_HIP(hipMemsetAsync(h->d_rank.p, 0, tr.nnodes() * sizeof(int), s));
+  if (!nodes) HODLR_HIP(hipMemsetAsync(h->d_rank.p, 0, tr.nnodes() * sizeof(int), s));
 
   const AcaTask* p_tasks = d_tasks.as<AcaTask>();
   const int* p_wg = d_wg.as<int>();
@@ -403,7 +413,7 @@ static int aca_t(hodlr_s* h, const double* K, int ldk, T* Ucap, T* Vcap,
     void* args[] = {(void*)&K,     (void*)&ldk,        (void*)&p_tasks, (void*)&p_wg,
                     (void*)&wg_base, (void*)&Ucap,     (void*)&Vcap,    (void*)&ldu,
                     (void*)&p_rec, (void*)&rec_stride, (void*)&p_bars,  (void*)&p_rank,
-                    (void*)&p_status, (void*)&teps};
+                    (void*)&p_status, (void*)&teps,    (void*)&piv};
     HODLR_HIP(hipLaunchCooperativeKernel(reinterpret_cast<const void*>(kern), dim3(cnt),
                                          dim3(kBlock), args, (unsigned)lds, s));
   }
@@ -414,12 +424,13 @@ static int aca_t(hodlr_s* h, const double* K, int ldk, T* Ucap, T* Vcap,
 }
 
 int launch_aca(hodlr_s* h, const double* K, int ldk, void* Ucap, void* Vcap,
-               const std::vector<int>& capoff, const std::vector<int>& cap, hipStream_t s) {
+               const std::vector<int>& capoff, const std::vector<int>& cap, hipStream_t s,
+               const std::vector<int>* nodes, int* piv) {
   if (h->precision == 64)
     return aca_t<double, kRankCap64, kAcaSlice64>(h, K, ldk, static_cast<double*>(Ucap),
-                                                  static_cast<double*>(Vcap), capoff, cap, s);
+                                                  static_cast<double*>(Vcap), capoff, cap, s, nodes, piv);
   return aca_t<float, kRankCap32, kAcaSlice32>(h, K, ldk, static_cast<float*>(Ucap),
-                                               static_cast<float*>(Vcap), capoff, cap, s);
+                                               static_cast<float*>(Vcap), capoff, cap, s, nodes, piv);
 }
 
 }  // namespace hodlr

@@ -210,6 +210,11 @@ void hodlr_default_opts(hodlr_opts* o) {
   o->bdlr_depth = 1;
   o->max_rank = 0;
   o->precision = 32;
+  o->skel_k = 32;
+  o->mlp_params = nullptr;
+  o->seed = 0;
+  o->skel_tol = 0.0;
+  o->bdlr_max_skel = 0;
 }
 
 const char* hodlr_last_error(void) { return g_last_error.c_str(); }
@@ -218,8 +223,12 @@ static int check_opts(const hodlr_opts& o) {
   if (o.leaf < 1 || o.leaf > kLeafMax)
     return fail(HODLR_EINVAL, "opts.leaf must be in [1, " + std::to_string(kLeafMax) + "]");
   if (!(o.tol >= 0.0) || !std::isfinite(o.tol)) return fail(HODLR_EINVAL, "opts.tol must be >= 0");
-  if (o.method != HODLR_ACA && o.method != HODLR_BDLR)
-    return fail(HODLR_EINVAL, "opts.method must be HODLR_ACA or HODLR_BDLR");
+  if (o.method != HODLR_ACA && o.method != HODLR_BDLR && o.method != HODLR_LEARNED)
+    return fail(HODLR_EINVAL, "opts.method must be HODLR_ACA, HODLR_BDLR or HODLR_LEARNED");
+  if (o.method == HODLR_LEARNED && (!o.mlp_params || o.skel_k < 1))
+    return fail(HODLR_EINVAL, "HODLR_LEARNED needs opts.mlp_params and opts.skel_k >= 1");
+  if (!(o.skel_tol >= 0.0) || !std::isfinite(o.skel_tol)) return fail(HODLR_EINVAL, "opts.skel_tol must be >= 0");
+  if (o.bdlr_max_skel < 0) return fail(HODLR_EINVAL, "opts.bdlr_max_skel must be >= 0");
   if (o.precision != 32 && o.precision != 64)
     return fail(HODLR_EINVAL, "opts.precision must be 32 or 64");
   if (o.leaf > leaf_cap(o.precision))
@@ -231,8 +240,9 @@ static int check_opts(const hodlr_opts& o) {
   return HODLR_OK;
 }
 
-int hodlr_build(const double* K, int n, int ldk, const int* g_rowptr, const int* g_col,
-                const hodlr_opts* opts, hipStream_t stream, hodlr_t* out) {
+static int build_impl(const double* K, int n, int ldk, const int* g_rowptr, const int* g_col,
+                      const float* coords, const hodlr_opts* opts, hipStream_t stream, hodlr_t* out,
+                      int* piv_export) {
   if (!out) return fail(HODLR_EINVAL, "out is NULL");
   *out = nullptr;
   hodlr_opts o;
@@ -242,9 +252,10 @@ int hodlr_build(const double* K, int n, int ldk, const int* g_rowptr, const int*
   if (n < 1 || n > kMaxN) return fail(HODLR_EINVAL, "n out of range");
   if (ldk < n) return fail(HODLR_EINVAL, "ldk < n");
   HODLR_TRY(check_opts(o));
-  if (o.method == HODLR_BDLR && (!g_rowptr || !g_col))
-    return fail(HODLR_EINVAL, "BDLR needs the separator graph (g_rowptr, g_col)");
-  if (o.method == HODLR_BDLR && n > 16384) return fail(HODLR_EINVAL, "BDLR supports n <= 16384");
+  if (o.method != HODLR_ACA && (!g_rowptr || !g_col))
+    return fail(HODLR_EINVAL, "BDLR and learned skeletons need the separator graph (g_rowptr, g_col)");
+  if (o.method == HODLR_LEARNED && !coords) return fail(HODLR_EINVAL, "learned skeletons need coords");
+  if (o.method != HODLR_ACA && n > 16384) return fail(HODLR_EINVAL, "BDLR supports n <= 16384");
   std::unique_ptr<hodlr_s> h(new hodlr_s());
   h->method = o.method;
   h->depth = o.bdlr_depth;
@@ -271,9 +282,14 @@ int hodlr_build(const double* K, int n, int ldk, const int* g_rowptr, const int*
     HODLR_HIP(hipMemsetAsync(Vcap.p, 0, (size_t)n * C * h->esize, stream));
     // compression of every off-diagonal block
     if (o.method == HODLR_BDLR)
-      HODLR_TRY(launch_bdlr(h.get(), K, ldk, g_rowptr, g_col, Ucap.p, Vcap.p, capoff, capq, stream));
+      HODLR_TRY(launch_bdlr(h.get(), K, ldk, g_rowptr, g_col, Ucap.p, Vcap.p, capoff, capq, stream,
+                            o.bdlr_max_skel, piv_export));
+    else if (o.method == HODLR_LEARNED)
+      HODLR_TRY(launch_learned(h.get(), K, ldk, g_rowptr, g_col, coords, o.mlp_params, o.skel_k, o.seed,
+                               o.skel_tol > 0.0 ? o.skel_tol : 30.0 * o.tol, Ucap.p, Vcap.p, capoff, capq,
+                               stream));
     else
-      HODLR_TRY(launch_aca(h.get(), K, ldk, Ucap.p, Vcap.p, capoff, capq, stream));
+      HODLR_TRY(launch_aca(h.get(), K, ldk, Ucap.p, Vcap.p, capoff, capq, stream, nullptr, piv_export));
     HODLR_HIP(hipMemcpyAsync(h->rank.data(), h->d_rank.p, t.nnodes() * sizeof(int),
                              hipMemcpyDeviceToHost, stream));
     HODLR_HIP(hipStreamSynchronize(stream));
@@ -289,6 +305,11 @@ int hodlr_build(const double* K, int n, int ldk, const int* g_rowptr, const int*
   }
   *out = h.release();
   return HODLR_OK;
+}
+
+int hodlr_build(const double* K, int n, int ldk, const int* g_rowptr, const int* g_col, const float* coords,
+                const hodlr_opts* opts, hipStream_t stream, hodlr_t* out) {
+  return build_impl(K, n, ldk, g_rowptr, g_col, coords, opts, stream, out, nullptr);
 }
 
 int hodlr_build_from_factors(int n, int leaf, int precision, const double* leaves,
@@ -446,6 +467,75 @@ int hodlr_get_factors(hodlr_t h, double* Upanel, double* Vpanel, hipStream_t str
   if (!Upanel || !Vpanel) return fail(HODLR_EINVAL, "NULL pointer");
   if (h->tree.L == 0 || h->R == 0) return HODLR_OK;
   return launch_to_f64_panels(h, Upanel, Vpanel, stream);
+}
+
+int hodlr_skel_info(hodlr_t h, int* kused) {
+  if (!h) return fail(HODLR_EINVAL, "handle is NULL");
+  if (!kused) return fail(HODLR_EINVAL, "kused is NULL");
+  const Tree& t = h->tree;
+  for (int id = 1; id < t.nnodes(); ++id) kused[id - 1] = h->skel_k.empty() ? -1 : h->skel_k[id];
+  return HODLR_OK;
+}
+
+int hodlr_skel_features(const int* g_rowptr, const int* g_col, const float* coords, const double* K, int n,
+                        int ldk, int leaf, float* feats, hipStream_t stream) {
+  if (!g_rowptr || !g_col || !coords || !K || !feats) return fail(HODLR_EINVAL, "NULL pointer argument");
+  if (n < 2 || n > 16384) return fail(HODLR_EINVAL, "n must be in [2, 16384]");
+  if (ldk < n) return fail(HODLR_EINVAL, "ldk < n");
+  if (leaf < 1 || leaf > kLeafMax) return fail(HODLR_EINVAL, "leaf out of range");
+  Tree t;
+  t.build(n, leaf);
+  if (t.L == 0) return fail(HODLR_EINVAL, "n <= leaf: the tree has no off-diagonal blocks");
+  return launch_skel_features(g_rowptr, g_col, coords, K, ldk, skel_blocks(t), feats, stream);
+}
+
+int hodlr_skel_labels(const double* K, int n, int ldk, const int* g_rowptr, const int* g_col, int leaf,
+                      double tol, int precision, int source, int depth, float* labels, hipStream_t stream) {
+  if (!K || !labels) return fail(HODLR_EINVAL, "NULL pointer argument");
+  if (n < 2 || n > 16384) return fail(HODLR_EINVAL, "n must be in [2, 16384]");
+  if (source != 0 && source != 1) return fail(HODLR_EINVAL, "source must be 0 (ACA) or 1 (skeleton LU)");
+  hodlr_opts o;
+  hodlr_default_opts(&o);
+  o.leaf = leaf;
+  o.tol = tol;
+  o.precision = precision;
+  o.method = source == 0 ? HODLR_ACA : HODLR_BDLR;
+  o.bdlr_depth = depth;
+  HODLR_TRY(check_opts(o));
+  Tree t;
+  t.build(n, leaf);
+  if (t.L == 0) return fail(HODLR_EINVAL, "n <= leaf: the tree has no off-diagonal blocks");
+  const int kcap = source == 0 ? rank_cap(precision) : skel_stride(precision);
+  DevBuf piv;
+  HODLR_TRY(piv.ensure((size_t)t.nnodes() * 2 * kcap * sizeof(int)));
+  hodlr_t h = nullptr;
+  HODLR_TRY(build_impl(K, n, ldk, g_rowptr, g_col, nullptr, &o, stream, &h, piv.as<int>()));
+  std::unique_ptr<hodlr_s> hold(h);
+  return launch_skel_labels(skel_blocks(t), piv.as<int>(), kcap, h->d_rank.as<int>(), labels, stream);
+}
+
+int hodlr_mlp_forward(const float* feats, int N, const float* params, int bf16, float* logits,
+                      hipStream_t stream) {
+  if (!feats || !params || !logits) return fail(HODLR_EINVAL, "NULL pointer argument");
+  if (N < 0) return fail(HODLR_EINVAL, "N < 0");
+  return launch_mlp_forward(feats, N, params, bf16 ? 1 : 0, logits, stream);
+}
+
+int hodlr_mlp_grad(const float* feats, const float* labels, int N, const float* params, int bf16,
+                   float pos_weight, float* grad, float* loss, hipStream_t stream) {
+  if (!feats || !labels || !params || !grad) return fail(HODLR_EINVAL, "NULL pointer argument");
+  if (N < 1) return fail(HODLR_EINVAL, "N must be >= 1");
+  return launch_mlp_grad(feats, labels, N, const_cast<float*>(params), bf16 ? 1 : 0, pos_weight, grad, loss,
+                         nullptr, nullptr, 0, 0.f, 0.f, 0.f, 0.f, stream);
+}
+
+int hodlr_mlp_adam_step(const float* feats, const float* labels, int N, float* params, float* m, float* v,
+                        int step, float lr, float pos_weight, float* loss, hipStream_t stream) {
+  if (!feats || !labels || !params || !m || !v) return fail(HODLR_EINVAL, "NULL pointer argument");
+  if (N < 1) return fail(HODLR_EINVAL, "N must be >= 1");
+  if (step < 1) return fail(HODLR_EINVAL, "step must be >= 1");
+  return launch_mlp_grad(feats, labels, N, params, 1, pos_weight, nullptr, loss, m, v, step, lr, 0.9f, 0.999f,
+                         1e-8f, stream);
 }
 
 int hodlr_destroy(hodlr_t h) {

@@ -33,6 +33,7 @@ constexpr int kSkel64 = 128;
 
 struct BdlrTask {
   int node, row0, m, col0, nc;
+  int samp0;     // first sample of the block in the learned proposer's numbering
   int capcol, kmax;
   int sel_off;   // ints: rows at sel_off, columns at sel_off + max_skel
   size_t inv_off;  // elements: U11^-1 then L11^-T, max_skel^2 each
@@ -105,7 +106,7 @@ __device__ void pick_side(const uint8_t* d, int len, int depth, int max_skel, in
 
 __global__ void __launch_bounds__(kBlock)
     k_bdlr_select(const int* __restrict__ rowptr, const int* __restrict__ col,
-                  const BdlrTask* __restrict__ tasks, int depth, int max_skel, int* __restrict__ sel,
+                  const BdlrTask* __restrict__ tasks, int depth, int max_skel, int stride, int* __restrict__ sel,
                   int* __restrict__ counts) {
   __shared__ uint8_t dI[kBdlrMaxSide], dJ[kBdlrMaxSide];
   __shared__ int cnt[256], buf[kBlock], s_cut[2];
@@ -138,34 +139,30 @@ __global__ void __launch_bounds__(kBlock)
     dJ[j] = dv;
   }
   __syncthreads();
-  // breadth-first layers inside each set
+  // breadth-first layers inside each set: the vertices of layer lvl mark
+  // their unmarked out-neighbours in the same set (benign races: every
+  // writer of a vertex writes the same layer number)
   for (int lvl = 0; lvl + 1 < depth; ++lvl) {
     for (int i = t; i < tk.m; i += kBlock) {
-      if (dI[i] != 255) continue;
+      if (dI[i] != lvl) continue;
       const int v = r0 + i;
       for (int e = rowptr[v]; e < rowptr[v + 1]; ++e) {
         const int u = col[e];
-        if (u >= r0 && u < r1 && dI[u - r0] == lvl) {
-          dI[i] = (uint8_t)(lvl + 1);
-          break;
-        }
+        if (u >= r0 && u < r1 && dI[u - r0] == 255) dI[u - r0] = (uint8_t)(lvl + 1);
       }
     }
     for (int j = t; j < tk.nc; j += kBlock) {
-      if (dJ[j] != 255) continue;
+      if (dJ[j] != lvl) continue;
       const int v = c0 + j;
       for (int e = rowptr[v]; e < rowptr[v + 1]; ++e) {
         const int u = col[e];
-        if (u >= c0 && u < c1 && dJ[u - c0] == lvl) {
-          dJ[j] = (uint8_t)(lvl + 1);
-          break;
-        }
+        if (u >= c0 && u < c1 && dJ[u - c0] == 255) dJ[u - c0] = (uint8_t)(lvl + 1);
       }
     }
     __syncthreads();
   }
   pick_side(dI, tk.m, depth, max_skel, sel + tk.sel_off, counts + 2 * blockIdx.x, cnt, buf, s_cut);
-  pick_side(dJ, tk.nc, depth, max_skel, sel + tk.sel_off + max_skel, counts + 2 * blockIdx.x + 1, cnt,
+  pick_side(dJ, tk.nc, depth, max_skel, sel + tk.sel_off + stride, counts + 2 * blockIdx.x + 1, cnt,
             buf, s_cut);
 }
 
@@ -415,7 +412,7 @@ static std::vector<BdlrTask> make_tasks(const Tree& tr, const std::vector<int>& 
                                         size_t* cg_elems) {
   std::vector<BdlrTask> tasks;
   size_t cgo = 0, invo = 0;
-  int selo = 0;
+  int selo = 0, samp = 0;
   for (int q = 1; q <= tr.L; ++q)
     for (int i = 0; i < (1 << q); ++i) {
       const int c = node_id(q, i), sib = node_id(q, i ^ 1);
@@ -431,6 +428,8 @@ static std::vector<BdlrTask> make_tasks(const Tree& tr, const std::vector<int>& 
       tk.sel_off = selo;
       tk.inv_off = invo;
       tk.cg_off = cgo;
+      tk.samp0 = samp;
+      samp += tk.m + tk.nc;
       selo += 2 * skel;
       invo += (size_t)skel * skel;
       cgo += (size_t)tk.m * tk.kmax;
@@ -443,7 +442,8 @@ static std::vector<BdlrTask> make_tasks(const Tree& tr, const std::vector<int>& 
 
 template <typename T, int SKEL>
 static int bdlr_t(hodlr_s* h, const double* K, int ldk, const int* rowptr, const int* col, T* Ucap,
-                  T* Vcap, const std::vector<int>& capoff, const std::vector<int>& cap, hipStream_t s) {
+                  T* Vcap, const std::vector<int>& capoff, const std::vector<int>& cap, hipStream_t s,
+                  int max_skel, int* piv_export) {
   const Tree& tr = h->tree;
   if (tr.n > 2 * kBdlrMaxSide) return fail(HODLR_EINVAL, "BDLR supports n <= 16384");
   if (h->depth > 250) return fail(HODLR_EINVAL, "bdlr_depth must be <= 250");
@@ -465,7 +465,8 @@ static int bdlr_t(hodlr_s* h, const double* K, int ldk, const int* rowptr, const
   HODLR_HIP(hipMemsetAsync(h->d_rank.p, 0, tr.nnodes() * sizeof(int), s));
   {
     ProfScope prof("bdlr_select", s);
-    k_bdlr_select<<<nt, kBlock, 0, s>>>(rowptr, col, d_tasks.as<BdlrTask>(), h->depth, SKEL,
+    const int ms = max_skel > 0 ? std::min(max_skel, SKEL) : SKEL;
+    k_bdlr_select<<<nt, kBlock, 0, s>>>(rowptr, col, d_tasks.as<BdlrTask>(), h->depth, ms, SKEL,
                                         d_sel.as<int>(), d_cnt.as<int>());
   }
   HODLR_HIP(hipGetLastError());
@@ -490,18 +491,344 @@ static int bdlr_t(hodlr_s* h, const double* K, int ldk, const int* rowptr, const
                                                           d_inv.as<T>(), Ucap, tr.n);
   }
   HODLR_HIP(hipGetLastError());
+  if (piv_export)
+    HODLR_HIP(hipMemcpyAsync(piv_export, d_piv.p, (size_t)selo * sizeof(int), hipMemcpyDeviceToDevice, s));
   HODLR_HIP(hipStreamSynchronize(s));  // scratch goes back to the allocator cache
   return HODLR_OK;
 }
 
+// ---------------------------------------------------------------------------
+// Learned proposals: the k highest-scoring rows and columns of every block
+// replace the boundary-distance picks; the skeleton is formed as above, its
+// error is sampled on rows and columns outside the skeleton, and a block that
+// misses the tolerance retries with twice the k, then falls back to ACA.
+// ---------------------------------------------------------------------------
+
+// larger score -> larger key; NaN lowest
+__device__ __forceinline__ unsigned score_key(float x) {
+  if (x != x) return 0u;
+  const unsigned u = __float_as_uint(x);
+  return (u & 0x80000000u) ? ~u : (u | 0x80000000u);
+}
+
+__device__ int block_count(int v, int* red) {
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  __syncthreads();
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
+  __syncthreads();
+  int r = 0;
+  for (int w = 0; w < kBlock / 64; ++w) r += red[w];
+  __syncthreads();
+  return r;
+}
+
+// The k largest keys of one side (ties to the lower position), listed in
+// increasing position.
+__device__ void topk_side(const unsigned* key, int len, int k, int* out, int* count, int* buf, int* red) {
+  const int t = threadIdx.x;
+  unsigned thr = 0u;  // the k-th largest key (radix select from the top bit)
+  int take = len;     // entries equal to thr that are kept
+  if (k < len) {
+    for (int bit = 31; bit >= 0; --bit) {
+      const unsigned cand = thr | (1u << bit);
+      int c = 0;
+      for (int i = t; i < len; i += kBlock) c += key[i] >= cand;
+      if (block_count(c, red) >= k) thr = cand;
+    }
+    int gt = 0;
+    for (int i = t; i < len; i += kBlock) gt += key[i] > thr;
+    take = k - block_count(gt, red);
+  }
+  const bool all = k >= len;
+  const int seg = (len + kBlock - 1) / kBlock, b0 = min(len, t * seg), b1 = min(len, b0 + seg);
+  int tot;
+  int ne = 0;
+  for (int i = b0; i < b1; ++i) ne += (key[i] == thr);
+  const int eq = block_exclusive_scan(ne, buf, &tot);
+  int ns = 0;
+  for (int i = b0, e = eq; i < b1; ++i) {
+    const bool ise = key[i] == thr;
+    ns += all || key[i] > thr || (ise && e < take);
+    e += ise;
+  }
+  int pos = block_exclusive_scan(ns, buf, &tot);
+  for (int i = b0, e = eq; i < b1; ++i) {
+    const bool ise = key[i] == thr;
+    if (all || key[i] > thr || (ise && e < take)) out[pos++] = i;
+    e += ise;
+  }
+  if (t == 0) *count = tot;
+  __syncthreads();
+}
+
+__global__ void __launch_bounds__(kBlock)
+    k_skel_topk(const float* __restrict__ score, const BdlrTask* __restrict__ tasks, int kk, int skel,
+                int* __restrict__ sel, int* __restrict__ counts) {
+  __shared__ unsigned key[kBdlrMaxSide];
+  __shared__ int buf[kBlock], red[kBlock / 64];
+  const BdlrTask tk = tasks[blockIdx.x];
+  for (int side = 0; side < 2; ++side) {
+    const int len = side == 0 ? tk.m : tk.nc, off = tk.samp0 + (side == 0 ? 0 : tk.m);
+    for (int i = threadIdx.x; i < len; i += kBlock) key[i] = score_key(score[off + i]);
+    __syncthreads();
+    topk_side(key, len, min(kk, min(len, skel)), sel + tk.sel_off + side * skel, counts + 2 * blockIdx.x + side,
+              buf, red);
+  }
+}
+
+// |K(I, J)|_F^2 of every block, in kNormChunks column chunks per block.
+constexpr int kNormChunks = 16;
+__global__ void __launch_bounds__(kBlock)
+    k_block_norm2(const double* __restrict__ K, int ldk, const BdlrTask* __restrict__ tasks,
+                  double* __restrict__ part) {
+  __shared__ double red[kBlock / 64];
+  const BdlrTask tk = tasks[blockIdx.x];
+  const int per = (tk.nc + kNormChunks - 1) / kNormChunks, j0 = blockIdx.y * per, j1 = min(tk.nc, j0 + per);
+  double acc = 0.0;
+  for (int j = j0; j < j1; ++j) {
+    const double* col = K + (size_t)(tk.col0 + j) * ldk + tk.row0;
+    for (int i = threadIdx.x; i < tk.m; i += kBlock) acc += col[i] * col[i];
+  }
+  acc = block_sum(acc, red);
+  if (threadIdx.x == 0) part[(size_t)blockIdx.x * kNormChunks + blockIdx.y] = acc;
+}
+
+// Estimated relative Frobenius error of U V^T on the block: the residual on
+// the sampled rows (whole rows), scaled by (rows outside the skeleton) /
+// (rows sampled), over |K(I, J)|_F^2; the same over columns; the larger of
+// the two (float64).  samp: per task 2 * ns entries (rows, then columns; -1 =
+// unused), ns <= 16; counts: rows and columns picked per task; norm2: per
+// task, kNormChunks partial sums of |K(I, J)|_F^2.
+template <typename T>
+__global__ void __launch_bounds__(kBlock)
+    k_skel_check(const double* __restrict__ K, int ldk, const BdlrTask* __restrict__ tasks,
+                 const int* __restrict__ rank_task, const int* __restrict__ counts, const double* __restrict__ norm2,
+                 const T* __restrict__ Ucap, const T* __restrict__ Vcap, int ldu, const int* __restrict__ samp,
+                 int ns, double* __restrict__ err) {
+  constexpr int RC = sizeof(T) == 8 ? kRankCap64 : kRankCap32, NS = 16;
+  __shared__ T uv[NS][RC];
+  __shared__ int sp[2 * NS];
+  __shared__ double red[kBlock / 64];
+  const BdlrTask tk = tasks[blockIdx.x];
+  const int r = rank_task[blockIdx.x], t = threadIdx.x;
+  if (t < 2 * NS) sp[t] = (t % NS) < ns ? samp[(size_t)blockIdx.x * 2 * ns + (t / NS) * ns + t % NS] : -1;
+  __syncthreads();
+  const T* U = Ucap + (size_t)tk.capcol * ldu;
+  const T* V = Vcap + (size_t)tk.capcol * ldu;
+  double est = 0.0;
+  for (int side = 0; side < 2; ++side) {
+    // the fixed factor's sampled rows: U(row0 + p, :) (side 0) or V(col0 + p, :)
+    const T* F = side == 0 ? U + tk.row0 : V + tk.col0;
+    const T* O = side == 0 ? V + tk.col0 : U + tk.row0;
+    for (int e = t; e < NS * r; e += kBlock) {
+      const int q = e % NS, l = e / NS, p = sp[side * NS + q];
+      uv[q][l] = p >= 0 ? F[(size_t)l * ldu + p] : T(0);
+    }
+    __syncthreads();
+    const int len = side == 0 ? tk.nc : tk.m;
+    double num = 0.0;
+    for (int x = t; x < len; x += kBlock) {
+      double a[NS];
+#pragma unroll
+      for (int q = 0; q < NS; ++q) a[q] = 0.0;
+      for (int l = 0; l < r; ++l) {
+        const double o = (double)O[(size_t)l * ldu + x];
+#pragma unroll
+        for (int q = 0; q < NS; ++q) a[q] += (double)uv[q][l] * o;
+      }
+#pragma unroll
+      for (int q = 0; q < NS; ++q) {
+        const int p = sp[side * NS + q];
+        if (p < 0) continue;
+        const double b = side == 0 ? K[(size_t)(tk.col0 + x) * ldk + tk.row0 + p]
+                                   : K[(size_t)(tk.col0 + p) * ldk + tk.row0 + x];
+        num += (b - a[q]) * (b - a[q]);
+      }
+    }
+    num = block_sum(num, red);
+    int used = 0;
+    for (int q = 0; q < NS; ++q) used += sp[side * NS + q] >= 0;
+    const int outside = (side == 0 ? tk.m : tk.nc) - counts[2 * blockIdx.x + side];
+    if (used > 0) est = fmax(est, num * (double)outside / (double)used);
+    __syncthreads();
+  }
+  if (t == 0) {
+    double nb = 0.0;
+    for (int c = 0; c < kNormChunks; ++c) nb += norm2[(size_t)blockIdx.x * kNormChunks + c];
+    err[blockIdx.x] = nb > 0.0 ? sqrt(est / nb) : sqrt(est);
+  }
+}
+
+// splitmix64 (Steele, Lea & Flood 2014): the sample stream of a block
+static inline unsigned long long splitmix64(unsigned long long& x) {
+  unsigned long long z = (x += 0x9E3779B97F4A7C15ull);
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  return z ^ (z >> 31);
+}
+
+// ns positions of [0, len) outside `picked` (sorted), without replacement
+static void draw_samples(unsigned long long& st, int len, const int* picked, int npick, int ns, int* out) {
+  std::vector<int> avail;
+  avail.reserve(len);
+  int q = 0;
+  for (int i = 0; i < len; ++i) {
+    if (q < npick && picked[q] == i) {
+      ++q;
+      continue;
+    }
+    avail.push_back(i);
+  }
+  for (int x = 0; x < ns; ++x) {
+    const int na = (int)avail.size() - x;
+    if (na <= 0) {
+      out[x] = -1;
+      continue;
+    }
+    const int j = x + (int)(splitmix64(st) % (unsigned long long)na);
+    std::swap(avail[x], avail[j]);
+    out[x] = avail[x];
+  }
+}
+
+constexpr int kSkelSamples = 16;
+
+template <typename T, int SKEL>
+static int learned_t(hodlr_s* h, const double* K, int ldk, const int* rowptr, const int* col, const float* xyz,
+                     const float* params, int kinit, unsigned long long seed, double accept, T* Ucap, T* Vcap,
+                     const std::vector<int>& capoff, const std::vector<int>& cap, hipStream_t s) {
+  const Tree& tr = h->tree;
+  if (tr.n > 2 * kBdlrMaxSide) return fail(HODLR_EINVAL, "learned skeletons support n <= 16384");
+  size_t invo = 0, cgo = 0;
+  const std::vector<BdlrTask> tasks = make_tasks<T>(tr, capoff, cap, SKEL, &invo, &cgo);
+  const int nt = (int)tasks.size(), selo = 2 * SKEL * nt;
+  const std::vector<SkelBlock> blocks = skel_blocks(tr);
+  const int N = 2 * tr.n * tr.L;  // every vertex is a row of one block and a column of another, per level
+  int maxside = 0;
+  for (auto& tk : tasks) maxside = std::max(maxside, std::max(tk.m, tk.nc));
+  DevBuf d_feat, d_score, d_tasks, d_sel, d_piv, d_cnt, d_rt, d_inv, d_cg, d_samp, d_err;
+  HODLR_TRY(d_feat.ensure((size_t)N * 8 * sizeof(float)));
+  HODLR_TRY(d_score.ensure((size_t)N * sizeof(float)));
+  HODLR_TRY(d_tasks.ensure(nt * sizeof(BdlrTask)));
+  HODLR_TRY(d_sel.ensure((size_t)selo * sizeof(int)));
+  HODLR_TRY(d_piv.ensure((size_t)selo * sizeof(int)));
+  HODLR_TRY(d_cnt.ensure((size_t)2 * nt * sizeof(int)));
+  HODLR_TRY(d_rt.ensure((size_t)nt * sizeof(int)));
+  HODLR_TRY(d_inv.ensure(std::max<size_t>(invo, 1) * sizeof(T)));
+  HODLR_TRY(d_cg.ensure(std::max<size_t>(cgo, 1) * sizeof(T)));
+  HODLR_TRY(d_samp.ensure((size_t)nt * 2 * kSkelSamples * sizeof(int)));
+  HODLR_TRY(d_err.ensure((size_t)nt * sizeof(double)));
+  DevBuf d_norm;
+  HODLR_TRY(d_norm.ensure((size_t)nt * kNormChunks * sizeof(double)));
+  {
+    ProfScope prof("skel_features", s);
+    HODLR_TRY(launch_skel_features(rowptr, col, xyz, K, ldk, blocks, d_feat.as<float>(), s));
+  }
+  {
+    ProfScope prof("skel_score", s);
+    HODLR_TRY(launch_mlp_forward(d_feat.as<float>(), N, params, 1, d_score.as<float>(), s));
+  }
+  HODLR_HIP(hipMemsetAsync(h->d_rank.p, 0, tr.nnodes() * sizeof(int), s));
+  const int rcap = h->precision == 64 ? kRankCap64 : kRankCap32;
+  h->skel_k.assign(tr.nnodes(), -1);
+  std::vector<int> pending(nt);
+  for (int x = 0; x < nt; ++x) pending[x] = x;
+  int kk = std::max(1, std::min(kinit, SKEL));
+  for (int attempt = 0;; ++attempt) {
+    std::vector<BdlrTask> sub;
+    for (int x : pending) sub.push_back(tasks[x]);
+    const int ns = (int)sub.size();
+    HODLR_HIP(hipMemcpyAsync(d_tasks.p, sub.data(), ns * sizeof(BdlrTask), hipMemcpyHostToDevice, s));
+    {
+      ProfScope prof("skel_topk", s);
+      k_skel_topk<<<ns, kBlock, 0, s>>>(d_score.as<float>(), d_tasks.as<BdlrTask>(), kk, SKEL, d_sel.as<int>(),
+                                        d_cnt.as<int>());
+    }
+    HODLR_HIP(hipGetLastError());
+    {
+      ProfScope prof("bdlr_lu", s);
+      k_bdlr_lu<T, SKEL><<<ns, kBlock, 0, s>>>(K, ldk, d_tasks.as<BdlrTask>(), d_sel.as<int>(), d_cnt.as<int>(),
+                                               (T)h->tol, rcap, d_piv.as<int>(), d_inv.as<T>(), h->d_rank.as<int>(),
+                                               d_rt.as<int>());
+    }
+    HODLR_HIP(hipGetLastError());
+    const int nch = (maxside + kBlock - 1) / kBlock;
+    {
+      ProfScope prof("bdlr_gather", s);
+      k_bdlr_gather<T, SKEL><<<dim3(ns, nch, 2), kBlock, 0, s>>>(K, ldk, d_tasks.as<BdlrTask>(), d_piv.as<int>(),
+                                                                d_rt.as<int>(), d_cg.as<T>(), Vcap, tr.n);
+      k_bdlr_factors<T><<<dim3(ns, nch, 1), kBlock, 0, s>>>(d_tasks.as<BdlrTask>(), d_rt.as<int>(), d_cg.as<T>(),
+                                                            d_inv.as<T>(), Ucap, tr.n);
+    }
+    HODLR_HIP(hipGetLastError());
+    // the picks come back to draw the samples outside them
+    std::vector<int> cnt(2 * ns), sel(selo);
+    HODLR_HIP(hipMemcpyAsync(cnt.data(), d_cnt.p, 2 * ns * sizeof(int), hipMemcpyDeviceToHost, s));
+    HODLR_HIP(hipMemcpyAsync(sel.data(), d_sel.p, (size_t)selo * sizeof(int), hipMemcpyDeviceToHost, s));
+    HODLR_HIP(hipStreamSynchronize(s));
+    std::vector<int> smp((size_t)ns * 2 * kSkelSamples);
+    for (int x = 0; x < ns; ++x) {
+      const BdlrTask& tk = sub[x];
+      unsigned long long st = seed ^ (0xD1B54A32D192ED03ull * (unsigned long long)tk.node) ^
+                              (0x8CB92BA72F3D8DD7ull * (unsigned long long)(attempt + 1));
+      draw_samples(st, tk.m, sel.data() + tk.sel_off, cnt[2 * x], kSkelSamples, smp.data() + (size_t)x * 2 * kSkelSamples);
+      draw_samples(st, tk.nc, sel.data() + tk.sel_off + SKEL, cnt[2 * x + 1], kSkelSamples,
+                   smp.data() + (size_t)x * 2 * kSkelSamples + kSkelSamples);
+    }
+    HODLR_HIP(hipMemcpyAsync(d_samp.p, smp.data(), smp.size() * sizeof(int), hipMemcpyHostToDevice, s));
+    {
+      ProfScope prof("skel_check", s);
+      k_block_norm2<<<dim3(ns, kNormChunks), kBlock, 0, s>>>(K, ldk, d_tasks.as<BdlrTask>(), d_norm.as<double>());
+      k_skel_check<T><<<ns, kBlock, 0, s>>>(K, ldk, d_tasks.as<BdlrTask>(), d_rt.as<int>(), d_cnt.as<int>(),
+                                            d_norm.as<double>(), Ucap, Vcap, tr.n, d_samp.as<int>(), kSkelSamples,
+                                            d_err.as<double>());
+    }
+    HODLR_HIP(hipGetLastError());
+    std::vector<double> err(ns);
+    HODLR_HIP(hipMemcpyAsync(err.data(), d_err.p, ns * sizeof(double), hipMemcpyDeviceToHost, s));
+    HODLR_HIP(hipStreamSynchronize(s));
+    std::vector<int> next;
+    for (int x = 0; x < ns; ++x) {
+      if (err[x] <= accept) h->skel_k[sub[x].node] = kk;
+      else next.push_back(pending[x]);
+    }
+    pending.swap(next);
+    if (pending.empty() || kk >= SKEL) break;
+    kk = std::min(SKEL, 2 * kk);
+  }
+  if (!pending.empty()) {
+    std::vector<int> nodes;
+    for (int x : pending) {
+      nodes.push_back(tasks[x].node);
+      h->skel_k[tasks[x].node] = 0;
+    }
+    HODLR_TRY(launch_aca(h, K, ldk, Ucap, Vcap, capoff, cap, s, &nodes));
+  }
+  HODLR_HIP(hipStreamSynchronize(s));  // scratch goes back to the allocator cache
+  return HODLR_OK;
+}
+
+int launch_learned(hodlr_s* h, const double* K, int ldk, const int* rowptr, const int* col, const float* xyz,
+                   const float* params, int kinit, unsigned long long seed, double accept, void* Ucap, void* Vcap,
+                   const std::vector<int>& capoff, const std::vector<int>& cap, hipStream_t s) {
+  if (h->precision == 64)
+    return learned_t<double, kSkel64>(h, K, ldk, rowptr, col, xyz, params, kinit, seed, accept,
+                                      static_cast<double*>(Ucap), static_cast<double*>(Vcap), capoff, cap, s);
+  return learned_t<float, kSkel32>(h, K, ldk, rowptr, col, xyz, params, kinit, seed, accept,
+                                   static_cast<float*>(Ucap), static_cast<float*>(Vcap), capoff, cap, s);
+}
+
 int launch_bdlr(hodlr_s* h, const double* K, int ldk, const int* rowptr, const int* col, void* Ucap,
-                void* Vcap, const std::vector<int>& capoff, const std::vector<int>& cap, hipStream_t s) {
+                void* Vcap, const std::vector<int>& capoff, const std::vector<int>& cap, hipStream_t s,
+                int max_skel, int* piv_export) {
   if (h->precision == 64)
     return bdlr_t<double, kSkel64>(h, K, ldk, rowptr, col, static_cast<double*>(Ucap),
-                                   static_cast<double*>(Vcap), capoff, cap, s);
+                                   static_cast<double*>(Vcap), capoff, cap, s, max_skel, piv_export);
   return bdlr_t<float, kSkel32>(h, K, ldk, rowptr, col, static_cast<float*>(Ucap),
-                                static_cast<float*>(Vcap), capoff, cap, s);
+                                static_cast<float*>(Vcap), capoff, cap, s, max_skel, piv_export);
 }
+
+int skel_stride(int precision) { return precision == 64 ? kSkel64 : kSkel32; }
 
 }  // namespace hodlr
 
@@ -523,8 +850,8 @@ extern "C" int hodlr_bdlr_select(const int* g_rowptr, const int* g_col, int n, i
   DevBuf d_tasks;
   HODLR_TRY(d_tasks.ensure(nt * sizeof(BdlrTask)));
   HODLR_HIP(hipMemcpyAsync(d_tasks.p, tasks.data(), nt * sizeof(BdlrTask), hipMemcpyHostToDevice, stream));
-  k_bdlr_select<<<nt, kBlock, 0, stream>>>(g_rowptr, g_col, d_tasks.as<BdlrTask>(), depth, max_skel, picks,
-                                           counts);
+  k_bdlr_select<<<nt, kBlock, 0, stream>>>(g_rowptr, g_col, d_tasks.as<BdlrTask>(), depth, max_skel, max_skel,
+                                           picks, counts);
   HODLR_HIP(hipGetLastError());
   HODLR_HIP(hipStreamSynchronize(stream));  // the task table goes back to the allocator cache
   return HODLR_OK;

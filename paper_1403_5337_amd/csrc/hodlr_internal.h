@@ -118,6 +118,7 @@ struct hodlr_s {
   hodlr::DevBuf Ybuf;   // work: per-node Woodbury solutions
   hodlr::DevBuf status; // int[4]: 0 singular flag, 1 node, 2 abort
   hodlr::DevBuf gemm_tab, gemm_work;  // arenas of the batched products
+  std::vector<int> skel_k;  // learned build, per node: skeleton size kept, 0 = ACA fallback
   size_t gemm_tab_used = 0, gemm_work_used = 0;
   bool factored = false;
 };
@@ -134,13 +135,27 @@ int launch_permute(const double* Kin, int n, int ldi, const int* perm, double* K
 int launch_permute_graph(const int* rowptr, const int* col, int n, const int* perm,
                          int* rowptr_out, int* col_out, hipStream_t s);
 
-// aca.hip: compress every off-diagonal block into capped panels
+// aca.hip: compress every off-diagonal block (or only the blocks of the
+// listed nodes) into capped panels; piv (optional, 2 * rank cap ints per node
+// below the root, level order) receives the pivot rows, then the pivot
+// columns, of every cross.
 int launch_aca(hodlr_s* h, const double* K, int ldk, void* Ucap, void* Vcap,
-               const std::vector<int>& capoff, const std::vector<int>& cap, hipStream_t s);
+               const std::vector<int>& capoff, const std::vector<int>& cap, hipStream_t s,
+               const std::vector<int>* nodes = nullptr, int* piv = nullptr);
 
 // bdlr.hip: boundary-distance skeletons of every off-diagonal block
+// max_skel: cap on picked rows (columns) per side (0 = the library's 192 /
+// 128); piv_export (optional, 2 skel_stride ints per node below the root,
+// level order) receives the skeleton's pivot rows, then columns
 int launch_bdlr(hodlr_s* h, const double* K, int ldk, const int* rowptr, const int* col, void* Ucap,
-                void* Vcap, const std::vector<int>& capoff, const std::vector<int>& cap, hipStream_t s);
+                void* Vcap, const std::vector<int>& capoff, const std::vector<int>& cap, hipStream_t s,
+                int max_skel = 0, int* piv_export = nullptr);
+int skel_stride(int precision);
+
+// bdlr.hip: learned proposals with sampled-error check and ACA fallback
+int launch_learned(hodlr_s* h, const double* K, int ldk, const int* rowptr, const int* col, const float* xyz,
+                   const float* params, int kinit, unsigned long long seed, double accept, void* Ucap, void* Vcap,
+                   const std::vector<int>& capoff, const std::vector<int>& cap, hipStream_t s);
 
 // factor.hip
 int launch_stage_leaves_from_K(hodlr_s* h, const double* K, int ldk, hipStream_t s);
@@ -170,6 +185,22 @@ struct ProfScope {
     if (on) prof_mark(name, s, false);
   }
 };
+
+// skel.hip: learned skeleton proposer (features, labels, scorer)
+constexpr int kMlpParams = 64 * 8 + 64 + 64 * 64 + 64 + 64 + 1;
+struct SkelBlock {
+  int node, row0, m, col0, nc, samp0;  // samp0: first sample (rows, then columns)
+};
+std::vector<SkelBlock> skel_blocks(const Tree& t);  // level order; samples total 2 n L
+int launch_skel_features(const int* rowptr, const int* col, const float* xyz, const double* K, int ldk,
+                         const std::vector<SkelBlock>& blocks, float* feats, hipStream_t s);
+int launch_skel_labels(const std::vector<SkelBlock>& blocks, const int* piv, int kcap, const int* rank,
+                       float* labels, hipStream_t s);
+int launch_mlp_forward(const float* X, int N, const float* P, int bf16, float* z, hipStream_t s);
+// gradient (grad, loss may be NULL); with M, V non-NULL also one Adam step on P
+int launch_mlp_grad(const float* X, const float* Y, int N, float* P, int bf16, float pos_weight, float* grad,
+                    float* loss, float* M, float* V, int step, float lr, float beta1, float beta2, float eps,
+                    hipStream_t s);
 
 // gmres.hip
 int gmres_impl(const double* K, int n, int ldk, hodlr_s* M, const double* B, int nrhs, int ldb,

@@ -1,0 +1,432 @@
+// Learned skeleton proposer: per-vertex block features, their training labels
+// (the pivots ACA picks), and the 8-64-64-1 scorer with its gradient and
+// Adam update.  Not in the paper: it proposes the rows and columns of the
+// pseudo-skeleton of Sec. 5.3 (eq. Ahat) that BDLR picks by boundary
+// distance; a block whose sampled error stays above the tolerance falls back
+// to ACA (Sec. 5.1) in the build.
+//
+// Samples: the blocks of the tree in level order (node 1, 2, ...); for the
+// block of node c (rows I = c, columns J = its sibling) its |I| row vertices,
+// then its |J| column vertices.  Features are 8 floats per sample (row-major).
+//
+// Scorer parameters (float32, kMlpParams values): W1 (64 x 8, row-major),
+// b1 (64), W2 (64 x 64, row-major), b2 (64), w3 (64), b3 (1).  The forward
+// pass and the gradient run with the weights rounded to bfloat16 (nearest,
+// ties to even) unless asked for float32, and always accumulate in float32.
+#include <algorithm>
+#include <climits>
+#include <cstdint>
+#include <vector>
+
+#include "device_util.h"
+#include "hodlr_internal.h"
+
+namespace hodlr {
+
+namespace {
+
+constexpr int NF = 8, HD = 64;
+constexpr int OW1 = 0, OB1 = OW1 + HD * NF, OW2 = OB1 + HD, OB2 = OW2 + HD * HD, OW3 = OB2 + HD,
+              OB3 = OW3 + HD, NP = OB3 + 1;
+static_assert(NP == kMlpParams, "parameter count");
+constexpr int kSideMax = 8192;
+
+__device__ __forceinline__ float bf16_round(float x) {
+  unsigned u = __float_as_uint(x);
+  if ((u & 0x7f800000u) == 0x7f800000u && (u & 0x7fffffu)) return x;  // NaN stays
+  u += 0x7fffu + ((u >> 16) & 1u);
+  return __uint_as_float(u & 0xffff0000u);
+}
+
+// ---------------------------------------------------------------------------
+// Features
+// ---------------------------------------------------------------------------
+__device__ float block_max(float v, float* red) {
+  for (int o = 32; o > 0; o >>= 1) v = fmaxf(v, __shfl_xor(v, o, 64));
+  const int w = threadIdx.x >> 6;
+  __syncthreads();
+  if ((threadIdx.x & 63) == 0) red[w] = v;
+  __syncthreads();
+  float r = red[0];
+  for (int k = 1; k < kBlock / 64; ++k) r = fmaxf(r, red[k]);
+  __syncthreads();
+  return r;
+}
+
+// Breadth-first distances from the boundary of one side, inside that side.
+// dist: LDS, len entries; 0xffff = not reached.  Own side [s0, s0+len), other
+// side [o0, o0+olen) (both contiguous ranges of vertex ids).
+__device__ void side_bfs(const int* __restrict__ rowptr, const int* __restrict__ col, int s0, int len,
+                         int o0, int olen, unsigned short* dist, int* s_changed) {
+  const int t = threadIdx.x;
+  for (int i = t; i < len; i += kBlock) {
+    const int v = s0 + i;
+    unsigned short d = 0xffff;
+    for (int e = rowptr[v]; e < rowptr[v + 1]; ++e) {
+      const int u = col[e];
+      if (u >= o0 && u < o0 + olen) {
+        d = 0;
+        break;
+      }
+    }
+    dist[i] = d;
+  }
+  __syncthreads();
+  // layer lvl marks its unmarked out-neighbours inside the side (benign
+  // races: every writer of a vertex writes the same layer number)
+  for (int lvl = 0; lvl < 0xfffe; ++lvl) {
+    if (t == 0) *s_changed = 0;
+    __syncthreads();
+    int ch = 0;
+    for (int i = t; i < len; i += kBlock) {
+      if (dist[i] != lvl) continue;
+      const int v = s0 + i;
+      for (int e = rowptr[v]; e < rowptr[v + 1]; ++e) {
+        const int u = col[e];
+        if (u >= s0 && u < s0 + len && dist[u - s0] == 0xffff) {
+          dist[u - s0] = (unsigned short)(lvl + 1);
+          ch = 1;
+        }
+      }
+    }
+    if (ch) *s_changed = 1;
+    __syncthreads();
+    const int any = *s_changed;
+    __syncthreads();
+    if (!any) break;
+  }
+}
+
+__global__ void __launch_bounds__(kBlock)
+    k_skel_features(const int* __restrict__ rowptr, const int* __restrict__ col, const float* __restrict__ xyz,
+                    const double* __restrict__ K, int ldk, const SkelBlock* __restrict__ blocks,
+                    float* __restrict__ feats) {
+  __shared__ unsigned short dist[2][kSideMax];
+  __shared__ float red[kBlock / 64];
+  __shared__ int s_changed;
+  const SkelBlock b = blocks[blockIdx.x];
+  const int t = threadIdx.x;
+  side_bfs(rowptr, col, b.row0, b.m, b.col0, b.nc, dist[0], &s_changed);
+  side_bfs(rowptr, col, b.col0, b.nc, b.row0, b.m, dist[1], &s_changed);
+  // per side: dmax, max degree, box, max |K_vv|
+  float st[2][10];
+  for (int sd = 0; sd < 2; ++sd) {
+    const int s0 = sd == 0 ? b.row0 : b.col0, len = sd == 0 ? b.m : b.nc;
+    float dm = 0.f, dg = 0.f, kd = 0.f, lo[3] = {INFINITY, INFINITY, INFINITY},
+          hi[3] = {-INFINITY, -INFINITY, -INFINITY};
+    for (int i = t; i < len; i += kBlock) {
+      const int v = s0 + i;
+      if (dist[sd][i] != 0xffff) dm = fmaxf(dm, (float)dist[sd][i]);
+      dg = fmaxf(dg, (float)(rowptr[v + 1] - rowptr[v]));
+      kd = fmaxf(kd, (float)fabs(K[(size_t)v * ldk + v]));
+      for (int a = 0; a < 3; ++a) {
+        const float x = xyz[3 * v + a];
+        lo[a] = fminf(lo[a], x);
+        hi[a] = fmaxf(hi[a], x);
+      }
+    }
+    st[sd][0] = block_max(dm, red);
+    st[sd][1] = block_max(dg, red);
+    st[sd][2] = block_max(kd, red);
+    for (int a = 0; a < 3; ++a) {
+      st[sd][3 + a] = -block_max(-lo[a], red);
+      st[sd][6 + a] = block_max(hi[a], red);
+    }
+  }
+  for (int sd = 0; sd < 2; ++sd) {
+    const int s0 = sd == 0 ? b.row0 : b.col0, len = sd == 0 ? b.m : b.nc;
+    const int samp = b.samp0 + (sd == 0 ? 0 : b.m);
+    const float* S = st[sd];
+    const float* O = st[sd ^ 1];
+    float ext[3], diag2 = 0.f;
+    for (int a = 0; a < 3; ++a) {
+      ext[a] = S[6 + a] - S[3 + a];
+      diag2 += ext[a] * ext[a];
+    }
+    const float diag = sqrtf(diag2);
+    const int olen = sd == 0 ? b.nc : b.m;
+    for (int i = t; i < len; i += kBlock) {
+      const int v = s0 + i;
+      const float d = dist[sd][i] == 0xffff ? S[0] + 1.f : (float)dist[sd][i];
+      float f[NF];
+      f[0] = d / (S[0] + 1.f);
+      f[1] = 1.f / (1.f + d);
+      f[2] = S[1] > 0.f ? (float)(rowptr[v + 1] - rowptr[v]) / S[1] : 0.f;
+      float g2 = 0.f;
+      for (int a = 0; a < 3; ++a) {
+        const float x = xyz[3 * v + a];
+        f[3 + a] = ext[a] > 0.f ? (x - S[3 + a]) / ext[a] : 0.f;
+        const float gap = fmaxf(0.f, fmaxf(O[3 + a] - x, x - O[6 + a]));
+        g2 += gap * gap;
+      }
+      f[6] = S[2] > 0.f ? (float)fabs(K[(size_t)v * ldk + v]) / S[2] : 0.f;
+      f[7] = (olen > 0 && diag > 0.f) ? fminf(1.f, sqrtf(g2) / diag) : 0.f;
+      for (int a = 0; a < NF; ++a) feats[(size_t)(samp + i) * NF + a] = f[a];
+    }
+  }
+}
+
+// labels of every sample of a block: 1 on the ACA pivot rows / columns
+__global__ void __launch_bounds__(kBlock)
+    k_skel_labels(const SkelBlock* __restrict__ blocks, const int* __restrict__ piv, int kcap,
+                  const int* __restrict__ rank, float* __restrict__ labels) {
+  const SkelBlock b = blocks[blockIdx.x];
+  const int t = threadIdx.x;
+  for (int i = t; i < b.m + b.nc; i += kBlock) labels[b.samp0 + i] = 0.f;
+  __syncthreads();
+  const int r = rank[b.node];
+  const int* p = piv + (size_t)(b.node - 1) * 2 * kcap;
+  for (int l = t; l < r; l += kBlock) {
+    labels[b.samp0 + p[l]] = 1.f;
+    labels[b.samp0 + b.m + p[kcap + l]] = 1.f;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Scorer
+// ---------------------------------------------------------------------------
+__device__ void stage_params(const float* __restrict__ P, int bf16, float* W) {
+  for (int i = threadIdx.x; i < NP; i += blockDim.x) W[i] = bf16 ? bf16_round(P[i]) : P[i];
+  __syncthreads();
+}
+
+// logits of N samples, grid-stride over samples
+__global__ void __launch_bounds__(kBlock)
+    k_mlp_forward(const float* __restrict__ X, int N, const float* __restrict__ P, int bf16,
+                  float* __restrict__ z_out) {
+  __shared__ float W[NP];
+  stage_params(P, bf16, W);
+  for (int s = blockIdx.x * kBlock + threadIdx.x; s < N; s += gridDim.x * kBlock) {
+    float x[NF], h1[HD];
+#pragma unroll
+    for (int a = 0; a < NF; ++a) x[a] = X[(size_t)s * NF + a];
+#pragma unroll
+    for (int o = 0; o < HD; ++o) {
+      float a1 = W[OB1 + o];
+#pragma unroll
+      for (int a = 0; a < NF; ++a) a1 = fmaf(W[OW1 + o * NF + a], x[a], a1);
+      h1[o] = fmaxf(a1, 0.f);
+    }
+    float z = W[OB3];
+    for (int o = 0; o < HD; ++o) {
+      float a2 = W[OB2 + o];
+#pragma unroll
+      for (int i = 0; i < HD; ++i) a2 = fmaf(W[OW2 + o * HD + i], h1[i], a2);
+      z = fmaf(W[OW3 + o], fmaxf(a2, 0.f), z);
+    }
+    z_out[s] = z;
+  }
+}
+
+__device__ __forceinline__ float sigmoidf_(float z) {
+  const float e = expf(-fabsf(z));
+  return z >= 0.f ? 1.f / (1.f + e) : e / (1.f + e);
+}
+__device__ __forceinline__ float softplusf_(float z) { return fmaxf(z, 0.f) + log1pf(expf(-fabsf(z))); }
+
+constexpr int kSB = 128;  // samples per workgroup of the gradient
+
+// Partial gradient (and loss) of the mean weighted logistic loss over the
+// workgroup's 128 samples; partial[wg][0..NP) and partial[wg][NP] = loss sum.
+__global__ void __launch_bounds__(kBlock)
+    k_mlp_grad(const float* __restrict__ X, const float* __restrict__ Y, int N, const float* __restrict__ P,
+               int bf16, float pos_weight, float inv_n, float* __restrict__ partial) {
+  __shared__ float W[NP];
+  __shared__ float Xs[kSB][NF];
+  __shared__ float H1[kSB][HD + 1];  // h1, later dl/da1
+  __shared__ float A2[kSB][HD + 1];  // a2, later dl/da2
+  __shared__ float dz[kSB], lz[kSB];
+  stage_params(P, bf16, W);
+  const int t = threadIdx.x, s0 = blockIdx.x * kSB;
+  float* out = partial + (size_t)blockIdx.x * (NP + 1);
+  if (t < kSB) {
+    const int s = s0 + t;
+    const bool ok = s < N;
+    float x[NF], h1[HD];
+#pragma unroll
+    for (int a = 0; a < NF; ++a) {
+      x[a] = ok ? X[(size_t)s * NF + a] : 0.f;
+      Xs[t][a] = x[a];
+    }
+#pragma unroll
+    for (int o = 0; o < HD; ++o) {
+      float a1 = W[OB1 + o];
+#pragma unroll
+      for (int a = 0; a < NF; ++a) a1 = fmaf(W[OW1 + o * NF + a], x[a], a1);
+      h1[o] = ok ? fmaxf(a1, 0.f) : 0.f;
+      H1[t][o] = h1[o];
+    }
+    float z = W[OB3];
+    for (int o = 0; o < HD; ++o) {
+      float a2 = W[OB2 + o];
+#pragma unroll
+      for (int i = 0; i < HD; ++i) a2 = fmaf(W[OW2 + o * HD + i], h1[i], a2);
+      A2[t][o] = ok ? a2 : 0.f;
+      z = fmaf(W[OW3 + o], fmaxf(a2, 0.f), z);
+    }
+    const float y = ok ? Y[s] : 0.f;
+    dz[t] = ok ? (-pos_weight * y * sigmoidf_(-z) + (1.f - y) * sigmoidf_(z)) * inv_n : 0.f;
+    lz[t] = ok ? (pos_weight * y * softplusf_(-z) + (1.f - y) * softplusf_(z)) * inv_n : 0.f;
+  }
+  __syncthreads();
+  // w3, b3 and the loss
+  if (t < HD) {
+    float g = 0.f;
+    for (int s = 0; s < kSB; ++s) g = fmaf(dz[s], fmaxf(A2[s][t], 0.f), g);
+    out[OW3 + t] = g;
+  } else if (t == HD) {
+    float g = 0.f, l = 0.f;
+    for (int s = 0; s < kSB; ++s) {
+      g += dz[s];
+      l += lz[s];
+    }
+    out[OB3] = g;
+    out[NP] = l;
+  }
+  __syncthreads();
+  for (int e = t; e < kSB * HD; e += kBlock) {
+    const int s = e / HD, o = e % HD;
+    A2[s][o] = A2[s][o] > 0.f ? dz[s] * W[OW3 + o] : 0.f;
+  }
+  __syncthreads();
+  // W2: 16 outputs per thread; b2
+  {
+    const int o = t >> 2, i0 = (t & 3) * 16;
+    float acc[16];
+#pragma unroll
+    for (int u = 0; u < 16; ++u) acc[u] = 0.f;
+    float gb = 0.f;
+    for (int s = 0; s < kSB; ++s) {
+      const float d = A2[s][o];
+      gb += d;
+#pragma unroll
+      for (int u = 0; u < 16; ++u) acc[u] = fmaf(d, H1[s][i0 + u], acc[u]);
+    }
+#pragma unroll
+    for (int u = 0; u < 16; ++u) out[OW2 + o * HD + i0 + u] = acc[u];
+    if ((t & 3) == 0) out[OB2 + o] = gb;
+  }
+  __syncthreads();
+  // dl/da1 = (h1 > 0) * (dl/da2 W2), in place of h1
+  {
+    const int s = t & (kSB - 1), i0 = (t >> 7) * 32;
+    float acc[32];
+#pragma unroll
+    for (int u = 0; u < 32; ++u) acc[u] = 0.f;
+    for (int o = 0; o < HD; ++o) {
+      const float d = A2[s][o];
+#pragma unroll
+      for (int u = 0; u < 32; ++u) acc[u] = fmaf(d, W[OW2 + o * HD + i0 + u], acc[u]);
+    }
+#pragma unroll
+    for (int u = 0; u < 32; ++u) H1[s][i0 + u] = H1[s][i0 + u] > 0.f ? acc[u] : 0.f;
+  }
+  __syncthreads();
+  // W1: 2 outputs per thread; b1
+  {
+    const int o = t >> 2, a0 = (t & 3) * 2;
+    float g0 = 0.f, g1 = 0.f, gb = 0.f;
+    for (int s = 0; s < kSB; ++s) {
+      const float d = H1[s][o];
+      gb += d;
+      g0 = fmaf(d, Xs[s][a0], g0);
+      g1 = fmaf(d, Xs[s][a0 + 1], g1);
+    }
+    out[OW1 + o * NF + a0] = g0;
+    out[OW1 + o * NF + a0 + 1] = g1;
+    if ((t & 3) == 0) out[OB1 + o] = gb;
+  }
+}
+
+// Sums the partial gradients in workgroup order; optionally one Adam step.
+__global__ void __launch_bounds__(kBlock)
+    k_mlp_reduce(const float* __restrict__ partial, int nwg, float* __restrict__ grad, float* __restrict__ loss,
+                 float* __restrict__ P, float* __restrict__ M, float* __restrict__ V, int step, float lr,
+                 float beta1, float beta2, float eps) {
+  const int p = blockIdx.x * kBlock + threadIdx.x;
+  if (p > NP) return;
+  float g = 0.f;
+  for (int w = 0; w < nwg; ++w) g += partial[(size_t)w * (NP + 1) + p];
+  if (p == NP) {
+    if (loss) *loss = g;
+    return;
+  }
+  if (grad) grad[p] = g;
+  if (P) {
+    const float m = beta1 * M[p] + (1.f - beta1) * g;
+    const float v = beta2 * V[p] + (1.f - beta2) * g * g;
+    M[p] = m;
+    V[p] = v;
+    const float mh = m / (1.f - powf(beta1, (float)step));
+    const float vh = v / (1.f - powf(beta2, (float)step));
+    P[p] -= lr * mh / (sqrtf(vh) + eps);
+  }
+}
+
+}  // namespace
+
+std::vector<SkelBlock> skel_blocks(const Tree& t) {
+  std::vector<SkelBlock> out;
+  int samp = 0;
+  for (int q = 1; q <= t.L; ++q)
+    for (int i = 0; i < (1 << q); ++i) {
+      const int c = node_id(q, i), sib = node_id(q, i ^ 1);
+      SkelBlock b{c, t.lo[c], t.size(c), t.lo[sib], t.size(sib), samp};
+      samp += b.m + b.nc;
+      out.push_back(b);
+    }
+  return out;
+}
+
+int launch_skel_features(const int* rowptr, const int* col, const float* xyz, const double* K, int ldk,
+                         const std::vector<SkelBlock>& blocks, float* feats, hipStream_t s) {
+  if (blocks.empty()) return HODLR_OK;
+  for (const SkelBlock& b : blocks)
+    if (b.m > kSideMax || b.nc > kSideMax) return fail(HODLR_EINVAL, "block side above 8192");
+  DevBuf d;
+  HODLR_TRY(d.ensure(blocks.size() * sizeof(SkelBlock)));
+  HODLR_HIP(hipMemcpyAsync(d.p, blocks.data(), blocks.size() * sizeof(SkelBlock), hipMemcpyHostToDevice, s));
+  k_skel_features<<<(unsigned)blocks.size(), kBlock, 0, s>>>(rowptr, col, xyz, K, ldk, d.as<SkelBlock>(), feats);
+  HODLR_HIP(hipGetLastError());
+  HODLR_HIP(hipStreamSynchronize(s));  // the block table goes back to the cache
+  return HODLR_OK;
+}
+
+int launch_skel_labels(const std::vector<SkelBlock>& blocks, const int* piv, int kcap, const int* rank,
+                       float* labels, hipStream_t s) {
+  if (blocks.empty()) return HODLR_OK;
+  DevBuf d;
+  HODLR_TRY(d.ensure(blocks.size() * sizeof(SkelBlock)));
+  HODLR_HIP(hipMemcpyAsync(d.p, blocks.data(), blocks.size() * sizeof(SkelBlock), hipMemcpyHostToDevice, s));
+  k_skel_labels<<<(unsigned)blocks.size(), kBlock, 0, s>>>(d.as<SkelBlock>(), piv, kcap, rank, labels);
+  HODLR_HIP(hipGetLastError());
+  HODLR_HIP(hipStreamSynchronize(s));
+  return HODLR_OK;
+}
+
+int launch_mlp_forward(const float* X, int N, const float* P, int bf16, float* z, hipStream_t s) {
+  if (N <= 0) return HODLR_OK;
+  const int grid = std::min(1024, (N + kBlock - 1) / kBlock);
+  k_mlp_forward<<<grid, kBlock, 0, s>>>(X, N, P, bf16, z);
+  HODLR_HIP(hipGetLastError());
+  return HODLR_OK;
+}
+
+int launch_mlp_grad(const float* X, const float* Y, int N, float* P, int bf16, float pos_weight, float* grad,
+                    float* loss, float* M, float* V, int step, float lr, float beta1, float beta2, float eps,
+                    hipStream_t s) {
+  if (N <= 0) return fail(HODLR_EINVAL, "N must be >= 1");
+  const int nwg = (N + kSB - 1) / kSB;
+  DevBuf part;
+  HODLR_TRY(part.ensure((size_t)nwg * (NP + 1) * sizeof(float)));
+  k_mlp_grad<<<nwg, kBlock, 0, s>>>(X, Y, N, P, bf16, pos_weight, 1.f / (float)N, part.as<float>());
+  HODLR_HIP(hipGetLastError());
+  k_mlp_reduce<<<(NP + 1 + kBlock - 1) / kBlock, kBlock, 0, s>>>(part.as<float>(), nwg, grad, loss,
+                                                                  M ? P : nullptr, M, V, step, lr, beta1,
+                                                                  beta2, eps);
+  HODLR_HIP(hipGetLastError());
+  HODLR_HIP(hipStreamSynchronize(s));  // the partials go back to the cache
+  return HODLR_OK;
+}
+
+}  // namespace hodlr

@@ -17,7 +17,8 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libhodlr.so")
 
 HODLR_OK, HODLR_EINVAL, HODLR_ENOMEM, HODLR_ESINGULAR, HODLR_ENOCONV, HODLR_EHIP = range(6)
-HODLR_ACA, HODLR_BDLR = 0, 1
+HODLR_ACA, HODLR_BDLR, HODLR_LEARNED = 0, 1, 2
+MLP_PARAMS = 64 * 8 + 64 + 64 * 64 + 64 + 64 + 1
 STATUS_NAMES = {0: "OK", 1: "EINVAL", 2: "ENOMEM", 3: "ESINGULAR", 4: "ENOCONV", 5: "EHIP"}
 
 
@@ -29,7 +30,9 @@ class HodlrError(RuntimeError):
 
 class Opts(ctypes.Structure):
     _fields_ = [("leaf", ctypes.c_int), ("tol", ctypes.c_double), ("method", ctypes.c_int),
-                ("bdlr_depth", ctypes.c_int), ("max_rank", ctypes.c_int), ("precision", ctypes.c_int)]
+                ("bdlr_depth", ctypes.c_int), ("max_rank", ctypes.c_int), ("precision", ctypes.c_int),
+                ("skel_k", ctypes.c_int), ("mlp_params", ctypes.c_void_p), ("seed", ctypes.c_ulonglong),
+                ("skel_tol", ctypes.c_double), ("bdlr_max_skel", ctypes.c_int)]
 
 
 _c_int_p = ctypes.POINTER(ctypes.c_int)
@@ -39,8 +42,16 @@ _vp = ctypes.c_void_p
 # name -> (restype, argtypes)
 _SIGNATURES = {
     "hodlr_default_opts": (None, [ctypes.POINTER(Opts)]),
-    "hodlr_build": (ctypes.c_int, [_vp, ctypes.c_int, ctypes.c_int, _vp, _vp, ctypes.POINTER(Opts), _vp,
+    "hodlr_build": (ctypes.c_int, [_vp, ctypes.c_int, ctypes.c_int, _vp, _vp, _vp, ctypes.POINTER(Opts), _vp,
                                    ctypes.POINTER(_vp)]),
+    "hodlr_skel_info": (ctypes.c_int, [_vp, _c_int_p]),
+    "hodlr_skel_features": (ctypes.c_int, [_vp, _vp, _vp, _vp, ctypes.c_int, ctypes.c_int, ctypes.c_int, _vp, _vp]),
+    "hodlr_skel_labels": (ctypes.c_int, [_vp, ctypes.c_int, ctypes.c_int, _vp, _vp, ctypes.c_int, ctypes.c_double,
+                                         ctypes.c_int, ctypes.c_int, ctypes.c_int, _vp, _vp]),
+    "hodlr_mlp_forward": (ctypes.c_int, [_vp, ctypes.c_int, _vp, ctypes.c_int, _vp, _vp]),
+    "hodlr_mlp_grad": (ctypes.c_int, [_vp, _vp, ctypes.c_int, _vp, ctypes.c_int, ctypes.c_float, _vp, _vp, _vp]),
+    "hodlr_mlp_adam_step": (ctypes.c_int, [_vp, _vp, ctypes.c_int, _vp, _vp, _vp, ctypes.c_int, ctypes.c_float,
+                                           ctypes.c_float, _vp, _vp]),
     "hodlr_build_from_factors": (ctypes.c_int, [ctypes.c_int, ctypes.c_int, ctypes.c_int, _vp, _vp, _vp,
                                                 _c_int_p, _c_int_p, ctypes.c_int, _vp, ctypes.POINTER(_vp)]),
     "hodlr_factor": (ctypes.c_int, [_vp, _vp]),
@@ -142,18 +153,39 @@ class Hodlr:
 
     @classmethod
     def build(cls, K: torch.Tensor, leaf=128, tol=1e-4, method="aca", depth=1, max_rank=0,
-              precision=32, graph=None, stream=None) -> "Hodlr":
+              precision=32, graph=None, coords=None, mlp_params=None, skel_k=32, seed=0, skel_tol=0.0,
+              max_skel=0, stream=None) -> "Hodlr":
+        """method: 'aca', 'bdlr' (needs graph = (rowptr, col) device tensors) or
+        'learned' (graph, coords (n, 3) float32 and mlp_params (4801,) float32,
+        all on the device)."""
         _need_gpu(K)
         Kc, ldk = colmajor(K, torch.float64)
         n = Kc.shape[0]
-        o = Opts(leaf=leaf, tol=tol, method=HODLR_BDLR if method == "bdlr" else HODLR_ACA,
-                 bdlr_depth=depth, max_rank=max_rank, precision=precision)
+        mcode = {"aca": HODLR_ACA, "bdlr": HODLR_BDLR, "learned": HODLR_LEARNED}[method]
+        xyz = None if coords is None else coords.to(torch.float32).contiguous()
+        prm = None if mlp_params is None else mlp_params.to(torch.float32).contiguous()
+        _need_gpu(xyz, prm)
+        o = Opts(leaf=leaf, tol=tol, method=mcode, bdlr_depth=depth, max_rank=max_rank, precision=precision,
+                 skel_k=skel_k, mlp_params=None if prm is None else prm.data_ptr(), seed=seed, skel_tol=skel_tol,
+                 bdlr_max_skel=max_skel)
         rp, cp = (None, None) if graph is None else (_i32(graph[0]), _i32(graph[1]))
         _need_gpu(rp, cp)
         h = ctypes.c_void_p()
-        _check(lib().hodlr_build(_ptr(Kc), n, ldk, _ptr(rp), _ptr(cp), ctypes.byref(o), _stream(stream),
-                                 ctypes.byref(h)))
+        _check(lib().hodlr_build(_ptr(Kc), n, ldk, _ptr(rp), _ptr(cp), _ptr(xyz), ctypes.byref(o),
+                                 _stream(stream), ctypes.byref(h)))
         return cls(h, n, precision)
+
+    def skel_info(self):
+        """Learned builds: per level, the skeleton size kept per node (0 = ACA fallback)."""
+        st = self.stats()
+        nn = sum(len(r) for r in st["ranks"])
+        buf = (ctypes.c_int * max(nn, 1))()
+        _check(lib().hodlr_skel_info(self._h, buf))
+        out, o = [], 0
+        for r in st["ranks"]:
+            out.append(list(buf[o:o + len(r)]))
+            o += len(r)
+        return out
 
     @classmethod
     def from_factors(cls, n, leaf, precision, leaves: torch.Tensor, Upanel: torch.Tensor,
@@ -308,3 +340,72 @@ def hodlr_prof_query(name: str):
     ms = ctypes.c_double()
     _check(lib().hodlr_prof_query(name.encode(), ctypes.byref(n), ctypes.byref(ms)))
     return n.value, ms.value
+
+
+def _levels(n: int, leaf: int) -> int:
+    L = 0
+    while -(-n // (1 << L)) > leaf:
+        L += 1
+    return L
+
+
+def hodlr_skel_features(rowptr, col, coords, K, leaf: int, stream=None) -> torch.Tensor:
+    """(2 n L, 8) float32 features of every block side (level order)."""
+    _need_gpu(rowptr, col, coords, K)
+    r32, c32 = _i32(rowptr), _i32(col)
+    xyz = coords.to(torch.float32).contiguous()
+    Kc, ldk = colmajor(K, torch.float64)
+    n = Kc.shape[0]
+    out = torch.empty((2 * n * _levels(n, leaf), 8), dtype=torch.float32, device=Kc.device)
+    _check(lib().hodlr_skel_features(_ptr(r32), _ptr(c32), _ptr(xyz), _ptr(Kc), n, ldk, leaf, _ptr(out),
+                                     _stream(stream)))
+    return out
+
+
+def hodlr_skel_labels(K, leaf: int, tol: float, precision=32, graph=None, source="aca", depth=4,
+                      stream=None) -> torch.Tensor:
+    """(2 n L,) float32: 1 on the pivot rows / columns of every block, from ACA
+    (source 'aca') or from the LU of the BDLR skeleton at `depth` ('lu', needs graph)."""
+    _need_gpu(K)
+    Kc, ldk = colmajor(K, torch.float64)
+    n = Kc.shape[0]
+    rp, cp = (None, None) if graph is None else (_i32(graph[0]), _i32(graph[1]))
+    _need_gpu(rp, cp)
+    out = torch.empty(2 * n * _levels(n, leaf), dtype=torch.float32, device=Kc.device)
+    _check(lib().hodlr_skel_labels(_ptr(Kc), n, ldk, _ptr(rp), _ptr(cp), leaf, tol, precision,
+                                   0 if source == "aca" else 1, depth, _ptr(out), _stream(stream)))
+    return out
+
+
+def hodlr_mlp_forward(feats, params, bf16=True, stream=None) -> torch.Tensor:
+    _need_gpu(feats, params)
+    f = feats.to(torch.float32).contiguous()
+    p = params.to(torch.float32).contiguous()
+    out = torch.empty(f.shape[0], dtype=torch.float32, device=f.device)
+    _check(lib().hodlr_mlp_forward(_ptr(f), f.shape[0], _ptr(p), 1 if bf16 else 0, _ptr(out), _stream(stream)))
+    return out
+
+
+def hodlr_mlp_grad(feats, labels, params, pos_weight: float, bf16=True, stream=None):
+    """(gradient (4801,), mean loss) of the weighted logistic loss."""
+    _need_gpu(feats, labels, params)
+    f = feats.to(torch.float32).contiguous()
+    y = labels.to(torch.float32).contiguous()
+    p = params.to(torch.float32).contiguous()
+    g = torch.empty(MLP_PARAMS, dtype=torch.float32, device=f.device)
+    loss = torch.empty(1, dtype=torch.float32, device=f.device)
+    _check(lib().hodlr_mlp_grad(_ptr(f), _ptr(y), f.shape[0], _ptr(p), 1 if bf16 else 0, pos_weight, _ptr(g),
+                                _ptr(loss), _stream(stream)))
+    return g, float(loss.item())
+
+
+def hodlr_mlp_adam_step(feats, labels, params, m, v, step: int, lr: float, pos_weight: float, stream=None):
+    """In-place Adam step on params (float32, contiguous, on the device); returns the loss."""
+    _need_gpu(feats, labels, params, m, v)
+    for t in (params, m, v):
+        if t.dtype != torch.float32 or not t.is_contiguous():
+            raise HodlrError(HODLR_EINVAL, "params, m, v must be contiguous float32")
+    loss = torch.empty(1, dtype=torch.float32, device=params.device)
+    _check(lib().hodlr_mlp_adam_step(_ptr(feats), _ptr(labels), feats.shape[0], _ptr(params), _ptr(m), _ptr(v),
+                                     step, lr, pos_weight, _ptr(loss), _stream(stream)))
+    return float(loss.item())

@@ -36,23 +36,38 @@ def test_default_opts(L):
     from paper_1403_5337_amd import hodlr
     o = hodlr.default_opts()
     assert (o.leaf, o.tol, o.method, o.bdlr_depth, o.max_rank, o.precision) == (128, 1e-4, 0, 1, 0, 32)
+    assert (o.skel_k, o.mlp_params, o.seed) == (32, None, 0)
 
 
 def test_argument_validation(L):
     from paper_1403_5337_amd import hodlr as H
     out = ctypes.c_void_p()
     o = H.default_opts()
-    st = L.hodlr_build(None, 10, 10, None, None, ctypes.byref(o), None, ctypes.byref(out))
+    st = L.hodlr_build(None, 10, 10, None, None, None, ctypes.byref(o), None, ctypes.byref(out))
     assert st == H.HODLR_EINVAL and b"K is NULL" in L.hodlr_last_error()
-    st = L.hodlr_build(ctypes.c_void_p(16), 10, 5, None, None, ctypes.byref(o), None, ctypes.byref(out))
+    st = L.hodlr_build(ctypes.c_void_p(16), 10, 5, None, None, None, ctypes.byref(o), None, ctypes.byref(out))
     assert st == H.HODLR_EINVAL and b"ldk" in L.hodlr_last_error()
     o.precision = 16
-    st = L.hodlr_build(ctypes.c_void_p(16), 10, 10, None, None, ctypes.byref(o), None, ctypes.byref(out))
+    st = L.hodlr_build(ctypes.c_void_p(16), 10, 10, None, None, None, ctypes.byref(o), None, ctypes.byref(out))
     assert st == H.HODLR_EINVAL and b"precision" in L.hodlr_last_error()
     o = H.default_opts()
     o.method = H.HODLR_BDLR
-    st = L.hodlr_build(ctypes.c_void_p(16), 10, 10, None, None, ctypes.byref(o), None, ctypes.byref(out))
+    st = L.hodlr_build(ctypes.c_void_p(16), 10, 10, None, None, None, ctypes.byref(o), None, ctypes.byref(out))
     assert st == H.HODLR_EINVAL and b"graph" in L.hodlr_last_error()
+    o.method = H.HODLR_LEARNED
+    st = L.hodlr_build(ctypes.c_void_p(16), 10, 10, ctypes.c_void_p(16), ctypes.c_void_p(16), None,
+                       ctypes.byref(o), None, ctypes.byref(out))
+    assert st == H.HODLR_EINVAL and b"mlp_params" in L.hodlr_last_error()
+    o.mlp_params = 16
+    st = L.hodlr_build(ctypes.c_void_p(16), 10, 10, ctypes.c_void_p(16), ctypes.c_void_p(16), None,
+                       ctypes.byref(o), None, ctypes.byref(out))
+    assert st == H.HODLR_EINVAL and b"coords" in L.hodlr_last_error()
+    p = ctypes.c_void_p(16)
+    assert L.hodlr_skel_features(p, p, p, p, 1, 1, 1, p, None) == H.HODLR_EINVAL
+    assert L.hodlr_skel_features(p, p, p, p, 100, 100, 128, p, None) == H.HODLR_EINVAL
+    assert L.hodlr_mlp_grad(p, p, 0, p, 1, 1.0, p, None, None) == H.HODLR_EINVAL
+    assert L.hodlr_mlp_adam_step(p, p, 10, p, p, p, 0, 1e-3, 1.0, None, None) == H.HODLR_EINVAL
+    assert L.hodlr_skel_info(None, None) == H.HODLR_EINVAL
     assert L.hodlr_factor(None, None) == H.HODLR_EINVAL
     assert L.hodlr_solve(None, None, 1, 1, None, 1, None) == H.HODLR_EINVAL
     it = (ctypes.c_int * 1)()

@@ -1,0 +1,260 @@
+"""GPU parity of the learned skeleton proposer against the oracle.
+
+Features: float32 on the GPU vs float64 in the oracle, 1e-5 absolute (they
+are ratios in [0, 1] of float32 coordinates and diagonals; the distances are
+integers and agree exactly).  Labels: the pivots of float64 ACA, compared bit
+for bit with the oracle's ACA on the 1024 Laplacian front.  Scorer: logits and
+gradients within 1e-5 relative (2-norm) of the float64 oracle with float32
+weights, and within 1e-4 with bfloat16 weights rounded the same way on both
+sides (float32 accumulation over 8 + 64 + 64 terms); the bfloat16 gradient is
+within 5 % of the float32-weight gradient; Adam within 1e-5.
+"""
+import sys
+
+import numpy as np
+import pytest
+import torch
+
+from gen import fronts
+from oracle import aca as oaca
+from oracle import dense, features as ofeat, mlp as omlp, ordering, tree
+
+pytestmark = pytest.mark.gpu
+
+H = pytest.importorskip("paper_1403_5337_amd.hodlr")
+S = pytest.importorskip("paper_1403_5337_amd.skeleton")
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    H.lib()
+    yield
+    torch.cuda.synchronize()
+
+
+def _params_dict(flat):
+    out, o = {}, 0
+    for k in omlp.NAMES:
+        sz = int(np.prod(omlp.SHAPES[k]))
+        out[k] = np.asarray(flat[o:o + sz], dtype=np.float64).reshape(omlp.SHAPES[k])
+        o += sz
+    return out
+
+
+def _flat(d):
+    return np.concatenate([np.ravel(d[k]) for k in omlp.NAMES])
+
+
+def _blocks(levs):
+    for p in range(1, len(levs)):
+        for i, (lo, hi) in enumerate(levs[p]):
+            yield lo, hi, levs[p][i ^ 1][0], levs[p][i ^ 1][1]
+
+
+@pytest.mark.parametrize("kind", ["tpfa", "elastic"])
+def test_features_match_oracle(kind):
+    if kind == "tpfa":
+        f, leaf = fronts.tpfa_front((24, 20, 3), zs=1, sigma=1.0, seed=3), 40
+    else:
+        f, leaf = fronts.elasticity_front((7, 6, 3), zs=1, perm_seed=0), 20
+    g = fronts.permute_front(f, ordering.rcb_permutation(f.coords, leaf))
+    say("features", kind, g.n)
+    F = H.hodlr_skel_features(torch.from_numpy(g.indptr).cuda(), torch.from_numpy(g.indices).cuda(),
+                              torch.from_numpy(g.coords).cuda(), g.K.cuda(), leaf).cpu().numpy()
+    K = g.K.numpy()
+    o = 0
+    for lo, hi, slo, shi in _blocks(tree.levels(g.n, leaf)):
+        FI, FJ = ofeat.block_features(g.indptr, g.indices, g.coords, np.diag(K), np.arange(lo, hi),
+                                      np.arange(slo, shi))
+        want = np.vstack([FI, FJ])
+        got = F[o:o + want.shape[0]]
+        np.testing.assert_allclose(got, want, atol=1e-5, rtol=0)
+        o += want.shape[0]
+    assert o == F.shape[0]
+
+
+def test_labels_are_the_aca_pivots_float64():
+    f = fronts.make_workload("laplace1024")
+    g = fronts.permute_front(f, ordering.rcb_permutation(f.coords, 64))
+    say("labels laplace1024")
+    y = H.hodlr_skel_labels(g.K.cuda(), 64, 1e-8, precision=64, source="aca").cpu().numpy()
+    K = g.K.numpy()
+    o = 0
+    for lo, hi, slo, shi in _blocks(tree.levels(g.n, 64)):
+        _, _, info = oaca.aca_pp(K[lo:hi, slo:shi], 1e-8, 128, return_info=True)
+        want = np.zeros((hi - lo) + (shi - slo))
+        want[np.asarray(info["rows"], dtype=int)] = 1
+        want[(hi - lo) + np.asarray(info["cols"], dtype=int)] = 1
+        assert np.array_equal(y[o:o + want.size], want), (lo, hi)
+        o += want.size
+    assert o == y.size
+
+
+def _data(seed, N=3000):
+    rng = np.random.default_rng(seed)
+    X = rng.uniform(0, 1, (N, 8)).astype(np.float32)
+    y = (rng.uniform(size=N) < 0.2).astype(np.float32)
+    return X, y
+
+
+def test_forward_matches_oracle():
+    X, _ = _data(1)
+    P = omlp.random_params(7, scale=0.3)
+    flat = _flat(P).astype(np.float32)
+    Xd, Pd = torch.from_numpy(X).cuda(), torch.from_numpy(flat).cuda()
+    z32 = H.hodlr_mlp_forward(Xd, Pd, bf16=False).cpu().numpy()
+    want, _ = omlp.forward(_params_dict(flat), X)
+    assert np.linalg.norm(z32 - want) <= 1e-5 * np.linalg.norm(want)
+    zb = H.hodlr_mlp_forward(Xd, Pd, bf16=True).cpu().numpy()
+    wantb, _ = omlp.forward(_params_dict(omlp.round_bf16(flat)), X)
+    assert np.linalg.norm(zb - wantb) <= 1e-4 * np.linalg.norm(wantb)
+
+
+@pytest.mark.parametrize("N", [1, 129, 3000])
+def test_gradient_matches_oracle(N):
+    X, y = _data(2, N)
+    P = omlp.random_params(8, scale=0.3)
+    flat = _flat(P).astype(np.float32)
+    Xd, yd, Pd = (torch.from_numpy(a).cuda() for a in (X, y, flat))
+    g32, l32 = H.hodlr_mlp_grad(Xd, yd, Pd, pos_weight=4.0, bf16=False)
+    L, g = omlp.loss_and_grad(_params_dict(flat), X, y, 4.0)
+    a = g32.cpu().numpy()
+    assert np.linalg.norm(a - _flat(g)) <= 1e-5 * np.linalg.norm(_flat(g))
+    assert abs(l32 - L) <= 1e-5 * abs(L)
+    gb, lb = H.hodlr_mlp_grad(Xd, yd, Pd, pos_weight=4.0, bf16=True)
+    Lb, gbw = omlp.loss_and_grad(_params_dict(omlp.round_bf16(flat)), X, y, 4.0)
+    assert np.linalg.norm(gb.cpu().numpy() - _flat(gbw)) <= 1e-4 * np.linalg.norm(_flat(gbw))
+    # against the float32 master weights: bf16 keeps 8 significant bits (relative
+    # rounding <= 2^-9 per weight); through two 64-wide layers with ReLU gates the
+    # gradient moves by a few percent (2.5 % on these draws), so 5 % bounds it
+    assert np.linalg.norm(gb.cpu().numpy() - _flat(g)) <= 5e-2 * np.linalg.norm(_flat(g))
+
+
+def test_adam_step_matches_oracle():
+    X, y = _data(3, 700)
+    P = omlp.random_params(9, scale=0.3)
+    flat = _flat(P).astype(np.float32)
+    rng = np.random.default_rng(4)
+    m0 = (rng.normal(size=flat.size) * 1e-3).astype(np.float32)
+    v0 = (rng.uniform(size=flat.size) * 1e-5).astype(np.float32)
+    Pd, md, vd = (torch.from_numpy(a.copy()).cuda() for a in (flat, m0, v0))
+    Xd, yd = torch.from_numpy(X).cuda(), torch.from_numpy(y).cuda()
+    H.hodlr_mlp_adam_step(Xd, yd, Pd, md, vd, 3, 1e-2, 2.0)
+    _, g = omlp.loss_and_grad(_params_dict(omlp.round_bf16(flat)), X, y, 2.0)
+    P2, M2, V2 = omlp.adam_step(_params_dict(flat), g, _params_dict(m0), _params_dict(v0), 3, lr=1e-2)
+    np.testing.assert_allclose(md.cpu().numpy(), _flat(M2), rtol=1e-4, atol=1e-9)
+    np.testing.assert_allclose(vd.cpu().numpy(), _flat(V2), rtol=1e-4, atol=1e-12)
+    np.testing.assert_allclose(Pd.cpu().numpy(), _flat(P2), rtol=1e-5, atol=1e-6)
+
+
+def _train_fronts(seeds, shape=(40, 40, 9)):
+    return [fronts.tpfa_front(shape, zs=shape[2] // 2, sigma=1.0, seed=s, device="cuda") for s in seeds]
+
+
+def test_training_lowers_the_loss_and_learns_pivots():
+    say("training on 3 small fronts")
+    data = S.concat_samples(S.front_samples(f, 128, 1e-4) for f in _train_fronts([1, 2, 3]))
+    feats, labels = data
+    p0 = S.init_params(0)
+    pos = float(labels.sum())
+    pw = (labels.numel() - pos) / pos
+    _, l0 = H.hodlr_mlp_grad(feats, labels, p0, pw)
+    p, losses = S.train(feats, labels, steps=300, batch=4096, lr=3e-3, pos_weight=pw, seed=0)
+    _, l1 = H.hodlr_mlp_grad(feats, labels, p, pw)
+    say("  loss", l0, "->", l1, "positives", pos / labels.numel())
+    assert l1 < 0.8 * l0
+    # precision at the top: the highest-scoring 5 % of samples hold many more pivots than 5 % would
+    z = H.hodlr_mlp_forward(feats, p)
+    top = torch.topk(z, int(0.05 * z.numel())).indices
+    hit = float(labels[top].mean())
+    say("  pivot rate in the top 5 %:", hit, "overall:", pos / labels.numel())
+    assert hit > 3 * pos / labels.numel()
+
+
+def test_learned_build_end_to_end_with_fallback():
+    """tpfa4096 with a scorer trained on small fronts: every block either
+    passes its sampled check (estimated error <= skel_tol = 30 tol; the true
+    error, computed here, stays within 3x of that: the estimate comes from 16
+    rows and 16 columns) or falls back to ACA; GMRES reaches 1e-12."""
+    say("learned e2e: training")
+    feats, labels = S.concat_samples(S.front_samples(f, 128, 1e-4) for f in _train_fronts([11, 12]))
+    p, _ = S.train(feats, labels, steps=300, batch=4096, seed=1)
+    f = fronts.make_workload("tpfa4096", device="cuda")
+    K, rp, ci, xyz = S.order_front(f, 128)
+    say("learned e2e: build")
+    h = H.Hodlr.build(K, leaf=128, tol=1e-4, method="learned", graph=(rp, ci), coords=xyz, mlp_params=p,
+                      skel_k=32, seed=5)
+    info = h.skel_info()
+    st = h.stats()
+    U, V = h.factors()
+    U, V = U.cpu().numpy(), V.cpu().numpy()
+    Kn = K.cpu().numpy()
+    offs = np.cumsum([0] + st["rcols"])
+    levs = tree.levels(f.n, 128)
+    nfall = 0
+    for p_ in range(1, len(levs)):
+        for i, (lo, hi) in enumerate(levs[p_]):
+            slo, shi = levs[p_][i ^ 1]
+            k = info[p_ - 1][i]
+            r = st["ranks"][p_ - 1][i]
+            assert k >= 0
+            nfall += k == 0
+            if k > 0:
+                B = Kn[lo:hi, slo:shi]
+                A = U[lo:hi, offs[p_ - 1]:offs[p_ - 1] + r] @ V[slo:shi, offs[p_ - 1]:offs[p_ - 1] + r].T
+                e = np.linalg.norm(B - A) / np.linalg.norm(B)
+                assert e <= 3 * 30 * 1e-4, (p_, i, k, e)
+    say("  skeleton sizes", info, "fallbacks", nfall, "ranks", [max(r) for r in st["ranks"]])
+    h.factor()
+    Bv = fronts.rhs(f.n, 8, seed=0).cuda()
+    X, it, rr, status = H.gmres_solve(K, Bv, h, tol=1e-12)
+    say("  iters", it)
+    h.close()
+    assert status == H.HODLR_OK
+    assert np.all(dense.relres(Kn, X.cpu().numpy(), Bv.cpu().numpy()) <= 1e-12)
+
+
+def _block_errors(h, K, n, leaf):
+    st = h.stats()
+    U, V = h.factors()
+    U, V = U.cpu().numpy(), V.cpu().numpy()
+    offs = np.cumsum([0] + st["rcols"])
+    errs = []
+    levs = tree.levels(n, leaf)
+    for p_ in range(1, len(levs)):
+        for i, (lo, hi) in enumerate(levs[p_]):
+            slo, shi = levs[p_][i ^ 1]
+            r = st["ranks"][p_ - 1][i]
+            B = K[lo:hi, slo:shi]
+            A = U[lo:hi, offs[p_ - 1]:offs[p_ - 1] + r] @ V[slo:shi, offs[p_ - 1]:offs[p_ - 1] + r].T
+            errs.append(np.linalg.norm(B - A) / np.linalg.norm(B))
+    return np.array(errs)
+
+
+def test_learned_proposals_beat_boundary_distance_at_equal_size():
+    """What the trained scorer gains over the method without it: with the same
+    skeleton budget (64 rows and 64 columns per block side), the scorer's picks
+    give smaller block errors than BDLR's nearest-64 picks on a held-out front."""
+    feats, labels = S.concat_samples(S.front_samples(f, 128, 1e-4) for f in _train_fronts([21, 22, 23], (48, 48, 9)))
+    p, _ = S.train(feats, labels, steps=600, batch=4096, seed=2)
+    f = fronts.tpfa_front((64, 48, 9), zs=4, sigma=1.0, seed=99, device="cuda")
+    K, rp, ci, xyz = S.order_front(f, 128)
+    Kn = K.cpu().numpy()
+    hl = H.Hodlr.build(K, leaf=128, tol=1e-4, method="learned", graph=(rp, ci), coords=xyz, mlp_params=p,
+                       skel_k=64, skel_tol=1e30)
+    el = _block_errors(hl, Kn, f.n, 128)
+    assert all(k == 64 for lv in hl.skel_info() for k in lv)
+    hl.close()
+    hb = H.Hodlr.build(K, leaf=128, tol=1e-4, method="bdlr", graph=(rp, ci), depth=250, max_skel=64)
+    eb = _block_errors(hb, Kn, f.n, 128)
+    hb.close()
+    gl, gb = np.exp(np.mean(np.log(el))), np.exp(np.mean(np.log(eb)))
+    say("  geometric-mean block error: learned", gl, "boundary distance", gb,
+        "blocks better:", int((el < eb).sum()), "of", el.size)
+    assert gl < gb
