@@ -138,6 +138,62 @@ def permute_front(front: Front, perm: np.ndarray, name=None) -> Front:
 
 
 # ---------------------------------------------------------------------------
+# Nested dissection of a cube: one front per separator
+# ---------------------------------------------------------------------------
+
+def nd_fronts(N=64, levels=6, sigma=1.0, seed=0, device="cpu"):
+    """Fronts of a geometric nested dissection of the N^3 lognormal(0, sigma)
+    TPFA operator (coefficient field seed ``seed``).
+
+    Level l cuts its box at the middle (lo + len//2) across axis z, y, x for
+    l = 0, 1, 2 (mod 3); the two sub-boxes recurse.  Each front is the Schur
+    complement of its box's operator onto its separator, with the box faces
+    (domain boundary or ancestor separators) as Dirichlet faces, i.e. the
+    frontal matrix of the separator in a multifrontal elimination where the
+    ancestors are eliminated last.  Returns the fronts in breadth-first order
+    with meta {level, box, axis}; coords are the cells' (x, y, z).
+    """
+    kap = grids.lognormal_coeff((N, N, N), sigma=sigma, seed=seed).reshape(N, N, N)  # [z][y][x]
+    out = []
+    queue = [(0, (0, N, 0, N, 0, N))]
+    while queue:
+        lev, box = queue.pop(0)
+        x0, x1, y0, y1, z0, z1 = box
+        axis = ("z", "y", "x")[lev % 3]
+        kb = kap[z0:z1, y0:y1, x0:x1]
+        if axis == "z":
+            arr, lo, hi = kb, z0, z1
+            to_xyz = lambda a, b, c: (a + x0, b + y0, c + z0)  # (x', y', z') -> (x, y, z)
+        elif axis == "y":
+            arr, lo, hi = kb.transpose(1, 0, 2), y0, y1  # [y][z][x]
+            to_xyz = lambda a, b, c: (a + x0, c + y0, b + z0)
+        else:
+            arr, lo, hi = kb.transpose(2, 1, 0), x0, x1  # [x][y][z]
+            to_xyz = lambda a, b, c: (c + x0, b + y0, a + z0)
+        nzp, nyp, nxp = arr.shape
+        s = lo + (hi - lo) // 2
+        zs = s - lo
+        A = grids.tpfa_matrix((nxp, nyp, nzp), np.ascontiguousarray(arr).ravel())
+        m = nxp * nyp
+        K = plane_sweep_front(A, m, nzp, zs, device=device)
+        indptr, indices = separator_graph(A, m, zs)
+        yy, xx = np.meshgrid(np.arange(nyp), np.arange(nxp), indexing="ij")
+        X, Y, Z = to_xyz(xx.ravel(), yy.ravel(), np.full(m, zs))
+        coords = np.stack([X, Y, Z], axis=1).astype(np.float32)
+        out.append(Front(K=K, indptr=indptr, indices=indices, coords=coords, name=f"nd{lev}_{len(out)}",
+                         meta=dict(kind="nd", level=lev, box=box, axis=axis, sigma=sigma, seed=seed)))
+        if lev + 1 < levels:
+            for c0, c1 in ((lo, s), (s + 1, hi)):
+                if c1 - c0 < 1:
+                    continue
+                nb = list(box)
+                k = {"x": 0, "y": 2, "z": 4}[axis]
+                nb[k], nb[k + 1] = c0, c1
+                queue.append((lev + 1, tuple(nb)))
+    return out
+
+
+# ---------------------------------------------------------------------------
 # Named generators
 # ---------------------------------------------------------------------------
 

@@ -135,6 +135,15 @@ int hodlr_build_from_factors(int n, int leaf, int precision, const double* leave
  * ESINGULAR (message names the node). */
 int hodlr_factor(hodlr_t h, hipStream_t stream);
 
+/* hodlr_factor for nh handles at once (a batch of fronts, e.g. the
+ * separators of a nested-dissection tree): every front's factorization is
+ * recorded on its own stream into one HIP graph, which is launched once, so
+ * the fronts' level-by-level launches run concurrently.  hs: host array of
+ * nh distinct, not yet factorized handles (any sizes and precisions).
+ * Synchronizes.  Errors: EINVAL, ESINGULAR (the message names the front and
+ * node), ENOMEM, EHIP; on error no handle is marked factorized. */
+int hodlr_factor_batched(hodlr_t* hs, int nh, hipStream_t stream);
+
 /* X = Ktilde^-1 B (Sec. 4.3.2) in the handle's precision.
  *   B, X    device, n x nrhs, leading dimensions ldb, ldx >= n; element
  *           type float (precision 32) or double (precision 64).  X may alias

@@ -7,6 +7,7 @@
 #include <mutex>
 #include <string>
 
+#include "gemm.h"
 #include "hodlr_internal.h"
 
 namespace hodlr {
@@ -387,6 +388,117 @@ int hodlr_factor(hodlr_t h, hipStream_t stream) {
                                                   std::to_string(st[1]));
   }
   h->factored = true;
+  return HODLR_OK;
+}
+
+// one stream per front of a batch (default priority), kept for the process
+static std::mutex g_pool_mu;
+static std::vector<hipStream_t> g_pool;
+
+static int stream_pool(int count, std::vector<hipStream_t>* out) {
+  std::lock_guard<std::mutex> lk(g_pool_mu);
+  while ((int)g_pool.size() < count) {
+    hipStream_t s = nullptr;
+    HODLR_HIP(hipStreamCreateWithFlags(&s, hipStreamNonBlocking));
+    g_pool.push_back(s);
+  }
+  out->assign(g_pool.begin(), g_pool.begin() + count);
+  return HODLR_OK;
+}
+
+int hodlr_factor_batched(hodlr_t* hs, int nh, hipStream_t stream) {
+  if (!hs || nh < 1) return fail(HODLR_EINVAL, "need at least one handle");
+  if (nh > 4096) return fail(HODLR_EINVAL, "at most 4096 handles per batch");
+  for (int f = 0; f < nh; ++f) {
+    if (!hs[f]) return fail(HODLR_EINVAL, "handle " + std::to_string(f) + " is NULL");
+    if (hs[f]->factored) return fail(HODLR_EINVAL, "handle " + std::to_string(f) + " is already factorized");
+    for (int g = 0; g < f; ++g)
+      if (hs[g] == hs[f]) return fail(HODLR_EINVAL, "a handle appears twice in the batch");
+  }
+  // first pass outside the capture: everything is sized, so the captured pass
+  // allocates and synchronizes nothing
+  for (int f = 0; f < nh; ++f) {
+    hodlr_s* h = hs[f];
+    if (h->tree.L > 0 && h->R > 0) {
+      HODLR_TRY(ensure_work(h, 64));
+      size_t tb = 0, wb = 0;
+      for (int q = 1; q <= h->tree.L; ++q) {
+        const size_t rq = h->rcols[q - 1], zc = h->off[q - 1] + rq, nq = (size_t)1 << q;
+        tb += 3 * gemm_table_bound((int)nq) + 2 * gemm_table_bound((int)nq / 2);
+        wb += nq * rq * zc * (size_t)std::max(1, h->tree.max_size(q) / 128) * h->esize + 256;
+      }
+      HODLR_TRY(gemm_prepare(h, tb, wb, stream));
+    }
+  }
+  HODLR_HIP(hipStreamSynchronize(stream));
+  // the graph is recorded on a pool stream (the caller's may be the legacy
+  // default stream, which cannot capture) and launched on the caller's
+  std::vector<hipStream_t> ss;
+  HODLR_TRY(stream_pool(nh + 1, &ss));
+  hipStream_t cs = ss[nh];
+  std::vector<hipEvent_t> ev(nh + 1, nullptr);
+  for (auto& e : ev) HODLR_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+  struct Cleanup {
+    std::vector<hipEvent_t>& ev;
+    hodlr_t* hs;
+    int nh;
+    ~Cleanup() {
+      for (auto e : ev)
+        if (e) (void)hipEventDestroy(e);
+      for (int f = 0; f < nh; ++f) hs[f]->capturing = false;
+      prof_suspend(false);
+    }
+  } cleanup{ev, hs, nh};
+  prof_suspend(true);
+  HODLR_HIP(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
+  int st = HODLR_OK;
+  st = hipEventRecord(ev[nh], cs) == hipSuccess ? HODLR_OK : fail(HODLR_EHIP, "event record");
+  // every front on its own stream: independent branches of one graph
+  for (int f = 0; f < nh && st == HODLR_OK; ++f) {
+    hodlr_s* h = hs[f];
+    if (hipStreamWaitEvent(ss[f], ev[nh], 0) != hipSuccess) {
+      st = fail(HODLR_EHIP, "stream wait");
+      break;
+    }
+    h->capturing = true;
+    st = factor_impl(h, ss[f]);
+    h->capturing = false;
+    if (st != HODLR_OK) break;
+    if (hipEventRecord(ev[f], ss[f]) != hipSuccess || hipStreamWaitEvent(cs, ev[f], 0) != hipSuccess)
+      st = fail(HODLR_EHIP, "event join");
+  }
+  hipGraph_t graph = nullptr;
+  const hipError_t ec = hipStreamEndCapture(cs, &graph);
+  if (st != HODLR_OK) {
+    if (graph) (void)hipGraphDestroy(graph);
+    return st;
+  }
+  if (ec != hipSuccess) return fail(HODLR_EHIP, std::string("hipStreamEndCapture: ") + hipGetErrorString(ec));
+  hipGraphExec_t exec = nullptr;
+  const hipError_t ei = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+  if (ei != hipSuccess) {
+    (void)hipGraphDestroy(graph);
+    return fail(HODLR_EHIP, std::string("hipGraphInstantiate: ") + hipGetErrorString(ei));
+  }
+  {
+    ProfScope prof("factor_graph", stream);
+    const hipError_t el = hipGraphLaunch(exec, stream);
+    if (el != hipSuccess) st = fail(HODLR_EHIP, std::string("hipGraphLaunch: ") + hipGetErrorString(el));
+  }
+  const hipError_t es = hipStreamSynchronize(stream);
+  (void)hipGraphExecDestroy(exec);
+  (void)hipGraphDestroy(graph);
+  if (st != HODLR_OK) return st;
+  if (es != hipSuccess) return fail(HODLR_EHIP, std::string("hipStreamSynchronize: ") + hipGetErrorString(es));
+  for (int f = 0; f < nh; ++f) {
+    int sv[4];
+    HODLR_HIP(hipMemcpy(sv, hs[f]->status.p, sizeof(sv), hipMemcpyDeviceToHost));
+    if (sv[0])
+      return fail(HODLR_ESINGULAR, "front " + std::to_string(f) + ": " +
+                                       (sv[0] == 1 ? "singular leaf block " : "singular capacitance matrix at node ") +
+                                       std::to_string(sv[1]));
+  }
+  for (int f = 0; f < nh; ++f) hs[f]->factored = true;
   return HODLR_OK;
 }
 

@@ -126,6 +126,10 @@ __global__ void __launch_bounds__(kBlock)
   }
 }
 
+__global__ void k_fill_int(int* p, int n, int v) {
+  for (int i = threadIdx.x; i < n; i += blockDim.x) p[i] = v;
+}
+
 // ---------------------------------------------------------------------------
 // Capacitance inverse per parent of level q.  With A = V_b^T d_a (r_b x r_a)
 // and B = V_a^T d_b (r_a x r_b), S = [[I, A], [B, I]] (eq. SchurSum) and, with
@@ -382,7 +386,22 @@ template <typename T>
 static int factor_t(hodlr_s* h, hipStream_t s) {
   const Tree& t = h->tree;  // (tree)
   const int n = t.n, L = t.L;
-  HODLR_HIP(hipMemsetAsync(h->status.p, 0, 4 * sizeof(int), s));
+  // every buffer is sized before the first launch: the sequence below has no
+  // allocation, synchronization or pageable copy, so it can be recorded into
+  // a graph (hodlr_factor_batched)
+  if (L > 0 && h->R > 0) {
+    HODLR_TRY(ensure_work(h, 64));
+    size_t tb = 0, wb = 0;
+    for (int q = 1; q <= L; ++q) {
+      const size_t rq = h->rcols[q - 1], zc = h->off[q - 1] + rq, nq = (size_t)1 << q;
+      tb += 3 * gemm_table_bound((int)nq) + 2 * gemm_table_bound((int)nq / 2);
+      wb += nq * rq * zc * (size_t)std::max(1, t.max_size(q) / 128) * h->esize + 256;
+    }
+    HODLR_TRY(gemm_prepare(h, tb, wb, s));
+  }
+  gemm_reset(h);
+  k_fill_int<<<1, 64, 0, s>>>(h->status.as<int>(), 4, 0);
+  HODLR_HIP(hipGetLastError());
   {
     ProfScope prof_("leaf_inverse", s);
     k_leaf_inverse<T><<<h->nleaf, kBlock, 0, s>>>(h->Kinv.as<T>(), h->bmax, h->d_lo.as<int>(),
@@ -391,7 +410,6 @@ static int factor_t(hodlr_s* h, hipStream_t s) {
   }
   HODLR_HIP(hipGetLastError());
   if (L == 0 || h->R == 0) return HODLR_OK;
-  HODLR_TRY(ensure_work(h, 64));
   T* Y = h->Y.as<T>();
   const T* W = h->W.as<T>();
   {
@@ -400,7 +418,6 @@ static int factor_t(hodlr_s* h, hipStream_t s) {
         h->Kinv.as<T>(), h->bmax, h->d_lo.as<int>(), h->d_hi.as<int>(), node_id(L, 0), Y, n, h->R);
   }
   HODLR_HIP(hipGetLastError());
-  gemm_reset(h);
   for (int q = L; q >= 1; --q) {
     const int rq = h->rcols[q - 1], offq = h->off[q - 1];
     if (rq == 0) continue;

@@ -30,5 +30,9 @@ struct GemmTask {
 // once the stream has drained.
 int gemm_batched(hodlr_s* h, const std::vector<GemmTask>& tasks, hipStream_t s);
 void gemm_reset(hodlr_s* h);
+// sizes the arenas (and the pinned staging of the task tables) up front, so
+// that a factorization needs no growth (required under graph capture)
+int gemm_prepare(hodlr_s* h, size_t tab_bytes, size_t work_bytes, hipStream_t s);
+size_t gemm_table_bound(int ntasks);  // table-arena bytes one call with ntasks tasks may take
 
 }  // namespace hodlr

@@ -5,6 +5,7 @@
 // workgroup, and a long inner dimension can be split over workgroups whose
 // partial tiles are summed by a second launch in a fixed order.
 #include <algorithm>
+#include <cstring>
 #include <vector>
 
 #include "gemm.h"
@@ -157,17 +158,40 @@ __global__ void __launch_bounds__(kBlock)
   }
 }
 
-// Reserves `bytes` (256-aligned) of an arena; growing it first drains the
-// stream, since earlier launches may still read the old block.
-static int arena_take(DevBuf& buf, size_t& used, size_t bytes, hipStream_t s, void** out) {
+// Reserves `bytes` (256-aligned) of an arena.  Growing it first drains the
+// stream, since earlier launches may still read the old block; under stream
+// capture that is impossible, so the arenas must have been sized beforehand
+// (gemm_prepare).
+static int arena_take(hodlr_s* h, DevBuf& buf, size_t& used, size_t bytes, hipStream_t s, void** out) {
   bytes = (bytes + 255) & ~(size_t)255;
   if (used + bytes > buf.bytes) {
+    if (h->capturing) return fail(HODLR_EINVAL, "batched-product arena too small under graph capture");
     HODLR_HIP(hipStreamSynchronize(s));
     HODLR_TRY(buf.ensure(std::max(2 * buf.bytes, used + bytes + (1 << 16))));
     used = 0;
   }
   *out = static_cast<char*>(buf.p) + used;
   used += bytes;
+  return HODLR_OK;
+}
+
+// Task tables are written to pinned host staging at the same offset as their
+// device copy, so an asynchronous (or captured) copy reads memory that stays
+// valid until the next factorization of the handle.
+static int stage_tables(hodlr_s* h, const void* src, size_t bytes, void* dev, hipStream_t s) {
+  const size_t off = static_cast<char*>(dev) - static_cast<char*>(h->gemm_tab.p);
+  if (h->gemm_host_bytes < h->gemm_tab.bytes) {
+    if (h->capturing) return fail(HODLR_EINVAL, "batched-product staging too small under graph capture");
+    HODLR_HIP(hipStreamSynchronize(s));
+    if (h->gemm_host) HODLR_HIP(hipHostFree(h->gemm_host));
+    h->gemm_host = nullptr;
+    h->gemm_host_bytes = 0;
+    HODLR_HIP(hipHostMalloc(&h->gemm_host, h->gemm_tab.bytes));
+    h->gemm_host_bytes = h->gemm_tab.bytes;
+  }
+  char* hp = static_cast<char*>(h->gemm_host) + off;
+  std::memcpy(hp, src, bytes);
+  HODLR_HIP(hipMemcpyAsync(dev, hp, bytes, hipMemcpyHostToDevice, s));
   return HODLR_OK;
 }
 
@@ -212,7 +236,7 @@ int gemm_batched_t(hodlr_s* h, const std::vector<GemmTask>& in, hipStream_t s) {
   std::vector<const void*> parts;
   if (nsplit) {
     void* w = nullptr;
-    HODLR_TRY(arena_take(h->gemm_work, h->gemm_work_used, work_elems * sizeof(T), s, &w));
+    HODLR_TRY(arena_take(h, h->gemm_work, h->gemm_work_used, work_elems * sizeof(T), s, &w));
     T* wp = static_cast<T*>(w);
     for (TaskDev& d : tasks) {
       if (d.ksplit == 1) continue;
@@ -227,14 +251,14 @@ int gemm_batched_t(hodlr_s* h, const std::vector<GemmTask>& in, hipStream_t s) {
   const size_t b0 = tasks.size() * sizeof(TaskDev), b1 = red.size() * sizeof(TaskDev);
   const size_t o1 = (b0 + 255) & ~(size_t)255, o2 = o1 + ((b1 + 255) & ~(size_t)255);
   void* tab = nullptr;
-  HODLR_TRY(arena_take(h->gemm_tab, h->gemm_tab_used, o2 + parts.size() * sizeof(void*), s, &tab));
+  HODLR_TRY(arena_take(h, h->gemm_tab, h->gemm_tab_used, o2 + parts.size() * sizeof(void*), s, &tab));
   char* tb = static_cast<char*>(tab);
-  HODLR_HIP(hipMemcpyAsync(tb, tasks.data(), b0, hipMemcpyHostToDevice, s));
+  HODLR_TRY(stage_tables(h, tasks.data(), b0, tb, s));
   k_gemm_batched<T><<<tiles, kBlock, 0, s>>>(reinterpret_cast<const TaskDev*>(tb), (int)tasks.size());
   HODLR_HIP(hipGetLastError());
   if (nsplit) {
-    HODLR_HIP(hipMemcpyAsync(tb + o1, red.data(), b1, hipMemcpyHostToDevice, s));
-    HODLR_HIP(hipMemcpyAsync(tb + o2, parts.data(), parts.size() * sizeof(void*), hipMemcpyHostToDevice, s));
+    HODLR_TRY(stage_tables(h, red.data(), b1, tb + o1, s));
+    HODLR_TRY(stage_tables(h, parts.data(), parts.size() * sizeof(void*), tb + o2, s));
     k_gemm_reduce<T><<<dim3(std::min(64, (maxmn + kBlock - 1) / kBlock), (unsigned)red.size()), kBlock, 0, s>>>(
         reinterpret_cast<const TaskDev*>(tb + o1), reinterpret_cast<const void* const*>(tb + o2));
     HODLR_HIP(hipGetLastError());
@@ -251,6 +275,27 @@ int gemm_batched(hodlr_s* h, const std::vector<GemmTask>& tasks, hipStream_t s) 
 void gemm_reset(hodlr_s* h) {
   h->gemm_tab_used = 0;
   h->gemm_work_used = 0;
+}
+
+size_t gemm_table_bound(int ntasks) {
+  const size_t t = ((size_t)ntasks * sizeof(TaskDev) + 255) & ~(size_t)255;
+  return 2 * t + (((size_t)ntasks * sizeof(void*) + 255) & ~(size_t)255) + 256;
+}
+
+int gemm_prepare(hodlr_s* h, size_t tab_bytes, size_t work_bytes, hipStream_t s) {
+  if (h->gemm_tab.bytes < tab_bytes || h->gemm_work.bytes < work_bytes || h->gemm_host_bytes < tab_bytes) {
+    HODLR_HIP(hipStreamSynchronize(s));
+    if (h->gemm_tab.bytes < tab_bytes) HODLR_TRY(h->gemm_tab.ensure(tab_bytes));
+    if (h->gemm_work.bytes < work_bytes) HODLR_TRY(h->gemm_work.ensure(work_bytes));
+    if (h->gemm_host_bytes < h->gemm_tab.bytes) {
+      if (h->gemm_host) HODLR_HIP(hipHostFree(h->gemm_host));
+      h->gemm_host = nullptr;
+      h->gemm_host_bytes = 0;
+      HODLR_HIP(hipHostMalloc(&h->gemm_host, h->gemm_tab.bytes));
+      h->gemm_host_bytes = h->gemm_tab.bytes;
+    }
+  }
+  return HODLR_OK;
 }
 
 }  // namespace hodlr

@@ -120,7 +120,16 @@ struct hodlr_s {
   hodlr::DevBuf gemm_tab, gemm_work;  // arenas of the batched products
   std::vector<int> skel_k;  // learned build, per node: skeleton size kept, 0 = ACA fallback
   size_t gemm_tab_used = 0, gemm_work_used = 0;
+  void* gemm_host = nullptr;  // pinned staging of the task tables
+  size_t gemm_host_bytes = 0;
+  bool capturing = false;     // launches are being recorded into a graph
   bool factored = false;
+  hodlr_s() = default;
+  hodlr_s(const hodlr_s&) = delete;
+  hodlr_s& operator=(const hodlr_s&) = delete;
+  ~hodlr_s() {
+    if (gemm_host) (void)hipHostFree(gemm_host);
+  }
 };
 
 namespace hodlr {
@@ -173,6 +182,7 @@ size_t solve_partial_elems(const hodlr_s* h);
 
 // prof.hip: event timing of wrapped launches (hodlr_prof_enable)
 bool prof_on();
+void prof_suspend(bool on);  // this thread records nothing while suspended
 void prof_mark(const char* name, hipStream_t s, bool begin);
 struct ProfScope {
   const char* name;

@@ -39,7 +39,10 @@ void release_all() {
 }
 }  // namespace
 
-bool prof_on() { return g_on; }
+thread_local bool t_suspended = false;
+
+bool prof_on() { return g_on && !t_suspended; }
+void prof_suspend(bool on) { t_suspended = on; }
 
 void prof_mark(const char* name, hipStream_t s, bool begin) {
   std::lock_guard<std::mutex> lk(g_mu);

@@ -55,6 +55,7 @@ _SIGNATURES = {
     "hodlr_build_from_factors": (ctypes.c_int, [ctypes.c_int, ctypes.c_int, ctypes.c_int, _vp, _vp, _vp,
                                                 _c_int_p, _c_int_p, ctypes.c_int, _vp, ctypes.POINTER(_vp)]),
     "hodlr_factor": (ctypes.c_int, [_vp, _vp]),
+    "hodlr_factor_batched": (ctypes.c_int, [ctypes.POINTER(_vp), ctypes.c_int, _vp]),
     "hodlr_solve": (ctypes.c_int, [_vp, _vp, ctypes.c_int, ctypes.c_int, _vp, ctypes.c_int, _vp]),
     "gmres_solve": (ctypes.c_int, [_vp, ctypes.c_int, ctypes.c_int, _vp, _vp, ctypes.c_int, ctypes.c_int,
                                    _vp, ctypes.c_int, ctypes.c_double, ctypes.c_int, ctypes.c_int,
@@ -256,6 +257,13 @@ def hodlr_build(K, **kw) -> Hodlr:
 
 def hodlr_factor(h: Hodlr, stream=None) -> Hodlr:
     return h.factor(stream)
+
+
+def hodlr_factor_batched(handles, stream=None):
+    """Factorize a batch of handles through one captured HIP graph."""
+    arr = (_vp * len(handles))(*[h.handle for h in handles])
+    _check(lib().hodlr_factor_batched(arr, len(handles), _stream(stream)))
+    return handles
 
 
 def hodlr_solve(h: Hodlr, B, stream=None):

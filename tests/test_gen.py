@@ -130,3 +130,32 @@ def test_rhs_deterministic():
     a = fronts.rhs(10, 3, seed=0).numpy()
     b = np.random.default_rng(0).uniform(-1, 1, size=(10, 3))
     assert np.array_equal(a, b)
+
+
+def test_nd_fronts_are_box_schur_complements():
+    """Every nested-dissection front equals the dense Schur complement of its
+    box's operator onto its separator (brute force), and the tree has the
+    expected separators."""
+    import scipy.linalg as sla
+    from gen import grids
+    N = 6
+    fr = fronts.nd_fronts(N, levels=3, sigma=1.0, seed=4)
+    assert [f.meta["level"] for f in fr] == [0, 1, 1, 2, 2, 2, 2]
+    assert fr[0].n == N * N and fr[1].n == N * (N // 2)
+    kap = grids.lognormal_coeff((N, N, N), sigma=1.0, seed=4).reshape(N, N, N)
+    for f in fr:
+        x0, x1, y0, y1, z0, z1 = f.meta["box"]
+        shape = (x1 - x0, y1 - y0, z1 - z0)
+        A = grids.tpfa_matrix(shape, kap[z0:z1, y0:y1, x0:x1].ravel()).toarray()
+        # separator cells in the box's x-fastest numbering
+        c = f.coords.astype(int)
+        sep = (c[:, 0] - x0) + shape[0] * ((c[:, 1] - y0) + shape[1] * (c[:, 2] - z0))
+        rest = np.setdiff1d(np.arange(A.shape[0]), sep)
+        S = A[np.ix_(sep, sep)]
+        if rest.size:
+            S = S - A[np.ix_(sep, rest)] @ sla.solve(A[np.ix_(rest, rest)], A[np.ix_(rest, sep)])
+        np.testing.assert_allclose(f.K.numpy(), S, rtol=1e-10, atol=1e-12)
+        # the separator cuts the box in its middle along the level's axis
+        ax = {"x": 0, "y": 1, "z": 2}[f.meta["axis"]]
+        lo, hi = f.meta["box"][2 * ax], f.meta["box"][2 * ax + 1]
+        assert np.all(c[:, ax] == lo + (hi - lo) // 2)
