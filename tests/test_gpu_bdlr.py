@@ -167,3 +167,23 @@ def test_end_to_end_bdlr_tpfa4096(depth):
     assert st == H.HODLR_OK
     assert np.all(dense.relres(K, Xn, Bn) <= 1e-12)
     assert max(it) <= 20
+
+
+@pytest.mark.parametrize("method", ["aca", "bdlr"])
+def test_end_to_end_elastic4800(method):
+    """Q1 elasticity front (n = 4800, dofs randomly permuted, then RCB order),
+    float32 HODLR at 1e-4 compressed by ACA or BDLR (depth 2), GMRES to 1e-12."""
+    f = fronts.make_workload("elastic4800", device="cuda")
+    say("e2e elastic4800", method)
+    perm = H.hodlr_order_rcb(torch.from_numpy(f.coords).cuda(), 128)
+    Kp = H.hodlr_permute(f.K.cuda(), perm)
+    rp, ci = H.hodlr_permute_graph(torch.from_numpy(f.indptr).cuda(), torch.from_numpy(f.indices).cuda(), perm)
+    B = fronts.rhs(f.n, 1, seed=0).cuda()
+    kw = dict(graph=(rp, ci), depth=2) if method == "bdlr" else {}
+    h = H.Hodlr.build(Kp, leaf=128, tol=1e-4, method=method, precision=32, **kw)
+    h.factor()
+    X, it, rr, st = H.gmres_solve(Kp, B, h, tol=1e-12, maxit=1000, restart=200)
+    say("  iters", it, "relres", rr, "ranks", [max(r) for r in h.stats()["ranks"]])
+    h.close()
+    assert st == H.HODLR_OK
+    assert np.all(dense.relres(Kp.cpu().numpy(), X.cpu().numpy(), B.cpu().numpy()) <= 1e-12)
