@@ -8,13 +8,21 @@
 // (eq. y followed by the back-substitution of Sec. 4.2, applied from the
 // leaves up as in Sec. 4.3.2).
 //
-// Rows are processed in units of kRows = 64 rows.  Launch "leaf" computes
-// x = Kinv_leaf x for one unit and writes the unit's partial products
-// W(unit rows, level-L block)^T x; launch "level q" (one workgroup per
-// level-q node and unit) adds the partial products of both siblings into
-// t_P, applies x -= E t_P to its unit, and writes the unit's partial products
-// for level q-1.  Every operand tile goes through LDS with all its loads in
-// flight together.
+// Rows are processed in units of kRows = 64 rows, one workgroup per unit.
+// Launch "leaf" computes x = Kinv_leaf x for its unit; launch "level q"
+// applies x -= E t_P to its unit.  Both then form the unit's partial products
+// W(unit rows, block of the next level)^T x into one slot per unit.  The next
+// launch reads the slots of its parent's two children along with its other
+// loads.  Where those reads would be large (wide blocks of many units), a
+// small launch in between first adds each node's slots into its first slot
+// (k_sum_units, a fixed summation order), and the next launch reads one slot
+// per child.
+//
+// Every workgroup issues its HBM reads together: the operand columns (E or the
+// leaf inverse, then W) go to LDS by asynchronous global-to-LDS copies while
+// the right-hand side and the group sums are read into registers.  The
+// contraction over the rank splits the rank range across the four waves (one
+// row per lane) and adds the four wave results at the end.
 #include <algorithm>
 
 #include "device_util.h"
@@ -22,184 +30,371 @@
 
 namespace hodlr {
 
-constexpr int kRows = 64;          // rows per unit
-constexpr int kTileC = 64;         // columns per staged tile
-constexpr int kLdT = kRows + 1;    // LDS leading dimension of a tile
-constexpr int kLeafLds = 192;      // >= largest leaf
+constexpr int kRows = 64;        // rows per unit
+constexpr int kLdW = kRows + 1;  // LDS column stride of staged W columns (read across columns)
+// LDS column stride of the staged E / leaf-inverse columns (read 4 rows at a
+// time, so 16-byte aligned)
+template <typename T> constexpr int lda_lds() { return sizeof(T) == 4 ? kRows + 4 : kRows + 2; }
 
-// dst(i, c) = src(i, c) for i < rn, c < cn (zero elsewhere); src column-major
-// with leading dimension ld; dst in LDS with leading dimension kLdT.
+template <typename T> struct SolveCfg;
+// kArena: operand columns staged at once; kT: rows of the right-hand block
+// (>= 2 x rank cap, >= leaf cap, >= 256 for the cross-wave sums)
+template <> struct SolveCfg<float> { static constexpr int kArena = 480, kT = 2 * kRankCap32; };
+template <> struct SolveCfg<double> { static constexpr int kArena = 224, kT = 2 * kRankCap64; };
+
+template <typename T, int SM>
+struct SolveSmem {
+  alignas(16) T arena[SolveCfg<T>::kArena * lda_lds<T>()];  // staged operand columns
+  alignas(16) T tb[SolveCfg<T>::kT * SM];       // right-hand block (z x SM), then wave sums
+  alignas(16) T xs[kRows * SM];                 // x of the unit (i x SM)
+};
+
+typedef __attribute__((address_space(1))) const void* gptr_t;
+typedef __attribute__((address_space(3))) void* lptr_t;
+
+// Asynchronous copy of columns [0, cn) of a 64-row column-major panel (first
+// row at src, leading dimension ld; rows >= rn are not read) into LDS columns
+// dst + c * ldl.  One wave instruction moves 256 bytes of one column; the
+// copies complete at dma_wait().
 template <typename T>
-__device__ __forceinline__ void stage_tile(T* dst, const T* __restrict__ src, size_t ld, int rn, int cn) {
-  constexpr int total = kRows * kTileC;
-  constexpr int per = total / kBlock;  // 16 loads per thread, issued together
-  const int t = threadIdx.x;
-  T v[per];
-#pragma unroll
-  for (int u = 0; u < per; ++u) {
-    const int e = t + u * kBlock, i = e & (kRows - 1), c = e / kRows;
-    v[u] = (i < rn && c < cn) ? src[i + (size_t)c * ld] : T(0);
-  }
-#pragma unroll
-  for (int u = 0; u < per; ++u) {
-    const int e = t + u * kBlock;
-    dst[(e & (kRows - 1)) + (e / kRows) * kLdT] = v[u];
+__device__ __forceinline__ void dma_columns(T* dst, int ldl, const T* __restrict__ src, size_t ld, int rn, int cn) {
+  constexpr int kParts = sizeof(T) / 4;
+  constexpr int kRowsPart = kRows / kParts;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  const int row = lane / kParts;
+  for (int j = wave; j < cn * kParts; j += nw) {
+    const int c = j / kParts, p = j - c * kParts;
+    if (p * kRowsPart + row < rn) {
+      const char* g = reinterpret_cast<const char*>(src + (size_t)c * ld + p * kRowsPart) + lane * 4;
+      __builtin_amdgcn_global_load_lds((gptr_t)g, (lptr_t)(dst + c * ldl + p * kRowsPart), 4, 0, 0);
+    }
   }
 }
 
-// Pu(r, c) = sum_i W(row0 + i, r) xs(i, c) for r < rp, c < nc: the unit's
-// partial products.  Wsrc points at W(row0, first column of the block).
-template <typename T, int SM>
-__device__ void unit_out(T* tile, const T* xs, const T* __restrict__ Wsrc, size_t ldw, int rn, int rp,
-                         int nc, T* __restrict__ Pu) {
-  const int t = threadIdx.x, rr = t & (kRows - 1), cg = t / kRows;
-  for (int r0 = 0; r0 < rp; r0 += kTileC) {
-    const int cn = min(kTileC, rp - r0);
-    stage_tile(tile, Wsrc + (size_t)r0 * ldw, ldw, rn, cn);
-    __syncthreads();
-    if (rr < cn) {
-      T acc[SM / 4];
-#pragma unroll
-      for (int u = 0; u < SM / 4; ++u) acc[u] = T(0);
-      for (int i = 0; i < kRows; ++i) {
-        const T w = tile[i + rr * kLdT];
-#pragma unroll
-        for (int u = 0; u < SM / 4; ++u) acc[u] += w * xs[(cg + 4 * u) * kRows + i];
-      }
-#pragma unroll
-      for (int u = 0; u < SM / 4; ++u) {
-        const int c = cg + 4 * u;
-        if (c < nc) Pu[(r0 + rr) + (size_t)c * rp] = acc[u];
-      }
-    }
-    __syncthreads();
+__device__ __forceinline__ void dma_wait() {
+  __builtin_amdgcn_s_waitcnt(0);
+  __syncthreads();
+}
+
+// Stage operand columns [j0, j0 + jn) of the stream "A columns 0..ra-1, then
+// W columns 0..": A and W are 64-row panels (first row at A / Wp).  In the
+// arena the chunk's A columns come first (stride lda_lds), then its W
+// columns (stride kLdW).
+template <typename T>
+__device__ __forceinline__ void stage_stream(T* arena, const T* A, size_t lda, int ra, const T* Wp, size_t ldw,
+                                             int j0, int jn, int rn) {
+  const int j1 = j0 + jn;
+  if (j0 < ra) dma_columns(arena, lda_lds<T>(), A + (size_t)j0 * lda, lda, rn, min(j1, ra) - j0);
+  if (j1 > ra) {
+    const int w0 = max(j0, ra);
+    dma_columns(arena + (w0 - j0) * lda_lds<T>(), kLdW, Wp + (size_t)(w0 - ra) * ldw, ldw, rn, j1 - w0);
   }
 }
 
+// acc[ri][cj] += sum_z A(4 g + ri, z - a0) B(z, cb + cj) over this wave's
+// share of [z0, z1), with g = lane % 16 and cb = (lane / 16) SM / 4: each lane
+// keeps 4 rows x SM / 4 columns.  A in LDS with column stride lda_lds, B in
+// LDS as [z][SM].  The loads of kU consecutive z are issued together; the sum
+// runs in z order.
 template <typename T, int SM>
-__global__ void __launch_bounds__(kBlock)
-    k_solve_leaf(const T* __restrict__ Kinv, int bmax, const int* __restrict__ lo,
-                 const int* __restrict__ hi, int idL, const T* __restrict__ Xin, int ldxi,
-                 T* __restrict__ Xout, int ldxo, int nc, const T* __restrict__ W, int ldw, int offL,
-                 int rL, int nchL, T* __restrict__ P) {
-  __shared__ T xs[SM * kLeafLds];
-  __shared__ T tile[kLdT * kTileC];
-  __shared__ T ys[SM * kRows];
-  const int leaf = blockIdx.x, ch = blockIdx.y, id = idL + leaf, t = threadIdx.x;
-  const int l0 = lo[id], b = hi[id] - l0, row0 = ch * kRows, rn = min(kRows, b - row0);
-  T* Pu = P + ((size_t)leaf * nchL + ch) * rL * nc;
-  if (rn <= 0) {
-    for (int e = t; e < rL * nc; e += blockDim.x) Pu[e] = T(0);
-    return;
-  }
-  for (int e0 = 0; e0 < SM * kLeafLds; e0 += 8 * kBlock) {
-    T v[8];
+__device__ __forceinline__ void contract(const T* A, int a0, const T* B, int z0, int z1, T (&acc)[4][SM / 4]) {
+  constexpr int kC = SM / 4, kU = 4, kL = lda_lds<T>();
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int g = lane & 15, cb = (lane >> 4) * kC;
+  const int per = (z1 - z0 + 3) >> 2;
+  const int zb = z0 + wave * per, ze = min(z1, zb + per);
+  int z = zb;
+  for (; z + kU <= ze; z += kU) {
+    T a[kU][4], b[kU][kC];
 #pragma unroll
-    for (int u = 0; u < 8; ++u) {
-      const int e = e0 + t + u * kBlock, i = e % kLeafLds, c = e / kLeafLds;
-      v[u] = (e < SM * kLeafLds && i < b && c < nc) ? Xin[(size_t)c * ldxi + l0 + i] : T(0);
+    for (int k = 0; k < kU; ++k) {
+      const T* ap = static_cast<const T*>(__builtin_assume_aligned(A + (z + k - a0) * kL + 4 * g, 16));
+#pragma unroll
+      for (int ri = 0; ri < 4; ++ri) a[k][ri] = ap[ri];
+      const T* bp = static_cast<const T*>(__builtin_assume_aligned(B + (z + k) * SM + cb, 8));
+#pragma unroll
+      for (int cj = 0; cj < kC; ++cj) b[k][cj] = bp[cj];
     }
 #pragma unroll
-    for (int u = 0; u < 8; ++u) {
-      const int e = e0 + t + u * kBlock;
-      if (e < SM * kLeafLds) xs[e] = v[u];
-    }
-  }
-  const T* Ki = Kinv + (size_t)leaf * bmax * bmax + row0;
-  const int ii = t & (kRows - 1), cg = t / kRows;
-  T acc[SM / 4];
+    for (int k = 0; k < kU; ++k)
 #pragma unroll
-  for (int u = 0; u < SM / 4; ++u) acc[u] = T(0);
-  for (int k0 = 0; k0 < b; k0 += kTileC) {
-    const int kn = min(kTileC, b - k0);
-    stage_tile(tile, Ki + (size_t)k0 * bmax, bmax, rn, kn);
-    __syncthreads();
-    for (int kk = 0; kk < kn; ++kk) {
-      const T a = tile[ii + kk * kLdT];
+      for (int ri = 0; ri < 4; ++ri)
 #pragma unroll
-      for (int u = 0; u < SM / 4; ++u) acc[u] += a * xs[(cg + 4 * u) * kLeafLds + k0 + kk];
-    }
-    __syncthreads();
+        for (int cj = 0; cj < kC; ++cj) acc[ri][cj] += a[k][ri] * b[k][cj];
   }
+  for (; z < ze; ++z) {
+    const T* ap = static_cast<const T*>(__builtin_assume_aligned(A + (z - a0) * kL + 4 * g, 16));
+    const T* bp = static_cast<const T*>(__builtin_assume_aligned(B + z * SM + cb, 8));
+#pragma unroll
+    for (int ri = 0; ri < 4; ++ri)
+#pragma unroll
+      for (int cj = 0; cj < kC; ++cj) acc[ri][cj] += ap[ri] * bp[cj];
+  }
+}
+
+// x(i, c) = xr - (sum of the four wave results) (sub) or the sum itself;
+// written to Xout (rows i < rn, c < nc) and to xs (zero elsewhere).
+template <typename T, int SM>
+__device__ __forceinline__ void finalize_x(SolveSmem<T, SM>& sm, const T (&acc)[4][SM / 4], const T (&xr)[SM / 4],
+                                           bool sub, int rn, int nc, T* Xout, size_t ldxo) {
+  constexpr int kC = SM / 4;
+  const int t = threadIdx.x, lane = t & 63, wave = t >> 6, cg = t >> 6;
+  const int g = lane & 15, cb = (lane >> 4) * kC;
+  __syncthreads();  // every wave is done with tb
+#pragma unroll
+  for (int cj = 0; cj < kC; ++cj)
+#pragma unroll
+    for (int ri = 0; ri < 4; ++ri) sm.tb[(wave * SM + cb + cj) * kRows + 4 * g + ri] = acc[ri][cj];
+  __syncthreads();
 #pragma unroll
   for (int u = 0; u < SM / 4; ++u) {
     const int c = cg + 4 * u;
-    const bool ok = ii < rn && c < nc;
-    if (ok) Xout[(size_t)c * ldxo + l0 + row0 + ii] = acc[u];
-    ys[c * kRows + ii] = ok ? acc[u] : T(0);
+    T s = sm.tb[c * kRows + lane];
+#pragma unroll
+    for (int w = 1; w < 4; ++w) s += sm.tb[(w * SM + c) * kRows + lane];
+    const bool ok = lane < rn && c < nc;
+    const T v = ok ? (sub ? xr[u] - s : s) : T(0);
+    if (ok) Xout[(size_t)c * ldxo + lane] = v;
+    sm.xs[lane * SM + c] = v;
   }
   __syncthreads();
-  if (rL > 0) unit_out<T, SM>(tile, ys, W + (size_t)offL * ldw + l0 + row0, ldw, rn, rL, nc, Pu);
+}
+
+// Pu(r0 + r, c) = sum_{i < rn} Wl(i, r) xs(i, c) for r < nw, c < nc (Pu has
+// leading dimension rp); Wl in LDS with column stride kLdW.  Lane = r.  With
+// fewer than four 64-column blocks the rows are split among the waves (S
+// parts per block) and the parts are added in order through red (LDS,
+// 4 x SM x 64).  The loads of kU consecutive rows are issued together.
+template <typename T, int SM>
+__device__ __forceinline__ void unit_partials(const T* Wl, T* red, const T* xs, int rn, int nw, int nc, T* Pu,
+                                              int r0, int rp) {
+  constexpr int kU = SM <= 8 ? 8 : 4;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int nb = (nw + 63) >> 6;
+  const int S = nb == 1 ? 4 : (nb == 2 ? 2 : 1);
+  const int per = ((rn + S - 1) / S + kU - 1) / kU * kU;
+  for (int b0 = 0; b0 < nb; b0 += 4 / S) {
+    const int blk = b0 + wave / S, part = wave % S;
+    const int r = blk * 64 + lane, rc = min(r, nw - 1);
+    const T* wc = Wl + rc * kLdW;
+    T acc[SM];
+#pragma unroll
+    for (int c = 0; c < SM; ++c) acc[c] = T(0);
+    const int i0 = part * per, i1 = blk < nb ? min(rn, i0 + per) : 0;
+    int i = i0;
+    for (; i + kU <= i1; i += kU) {
+      T w[kU], x[kU][SM];
+#pragma unroll
+      for (int k = 0; k < kU; ++k) {
+        w[k] = wc[i + k];
+        const T* xp = static_cast<const T*>(__builtin_assume_aligned(xs + (i + k) * SM, 16));
+#pragma unroll
+        for (int c = 0; c < SM; ++c) x[k][c] = xp[c];
+      }
+#pragma unroll
+      for (int k = 0; k < kU; ++k)
+#pragma unroll
+        for (int c = 0; c < SM; ++c) acc[c] += w[k] * x[k][c];
+    }
+    for (; i < i1; ++i) {
+      const T w = wc[i];
+      const T* xp = static_cast<const T*>(__builtin_assume_aligned(xs + i * SM, 16));
+#pragma unroll
+      for (int c = 0; c < SM; ++c) acc[c] += w * xp[c];
+    }
+    if (S > 1) {
+#pragma unroll
+      for (int c = 0; c < SM; ++c) red[(wave * SM + c) * 64 + lane] = acc[c];
+      __syncthreads();
+      if (part == 0) {
+        for (int p = 1; p < S; ++p)
+#pragma unroll
+          for (int c = 0; c < SM; ++c) acc[c] += red[((wave + p) * SM + c) * 64 + lane];
+      }
+      __syncthreads();
+    }
+    if (part == 0 && blk < nb && r < nw)
+#pragma unroll
+      for (int c = 0; c < SM; ++c)
+        if (c < nc) Pu[(size_t)(r0 + r) + (size_t)c * rp] = acc[c];
+  }
+}
+
+// P holds nnodes x upn slots of usz elements; slot 0 of each node receives
+// the sum of the node's upn slots.  kLanes consecutive lanes share an
+// element: lane j adds units j, j + kLanes, ... in order, then the lanes are
+// combined by a fixed butterfly, so the result does not depend on timing.
+constexpr int kSumLanes = 8;
+
+template <typename T>
+__global__ void __launch_bounds__(kBlock) k_sum_units(T* __restrict__ P, int nnodes, int upn, int usz) {
+  const long gid = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  const long el = gid / kSumLanes;
+  const int j = (int)(gid % kSumLanes);
+  const bool live = el < (long)nnodes * usz;
+  const int node = live ? (int)(el / usz) : 0, e = live ? (int)(el % usz) : 0;
+  T* base = P + (size_t)node * upn * usz + e;
+  T s = T(0);
+  if (live) {
+    int u = j;
+    for (; u + 3 * kSumLanes < upn; u += 4 * kSumLanes) {
+      T v[4];
+#pragma unroll
+      for (int k = 0; k < 4; ++k) v[k] = base[(size_t)(u + k * kSumLanes) * usz];
+#pragma unroll
+      for (int k = 0; k < 4; ++k) s += v[k];
+    }
+    for (; u < upn; u += kSumLanes) s += base[(size_t)u * usz];
+  }
+#pragma unroll
+  for (int o = 1; o < kSumLanes; o <<= 1) s += __shfl_xor(s, o, 64);
+  if (live && j == 0) base[0] = s;
+}
+
+// The unit's pipeline after its right-hand block is in sm.tb: stream the
+// operand columns (A: ra columns, then W: nwc columns), contract, form x, and
+// the partial products of W.
+template <typename T, int SM>
+__device__ __forceinline__ void unit_pipeline(SolveSmem<T, SM>& sm, const T* A, size_t lda, int ra, const T* Wp,
+                                              size_t ldw, int nwc, int rn, int nc, const T (&xr)[SM / 4], bool sub,
+                                              T* Xout, size_t ldxo, T* Pu, int rp, int jn) {
+  constexpr int kA = SolveCfg<T>::kArena;
+  const int total = ra + nwc;
+  T acc[4][SM / 4];
+#pragma unroll
+  for (int ri = 0; ri < 4; ++ri)
+#pragma unroll
+    for (int cj = 0; cj < SM / 4; ++cj) acc[ri][cj] = T(0);
+  bool done = false;
+  for (int j0 = 0;;) {
+    dma_wait();
+    const int j1 = j0 + jn;
+    if (j0 < ra) contract<T, SM>(sm.arena, j0, sm.tb, j0, min(j1, ra), acc);
+    if (!done && ra <= j1) {
+      finalize_x<T, SM>(sm, acc, xr, sub, rn, nc, Xout, ldxo);
+      done = true;
+    }
+    if (j1 > ra) {
+      const int w0 = max(j0, ra);
+      unit_partials<T, SM>(sm.arena + (w0 - j0) * lda_lds<T>(), sm.tb, sm.xs, rn, j1 - w0, nc, Pu, w0 - ra, rp);
+    }
+    if (j1 >= total) break;
+    __syncthreads();  // the arena is reused
+    j0 = j1;
+    jn = min(kA, total - j0);
+    stage_stream(sm.arena, A, lda, ra, Wp, ldw, j0, jn, rn);
+  }
 }
 
 template <typename T, int SM>
 __global__ void __launch_bounds__(kBlock)
-    k_solve_level(int q, const int* __restrict__ lo, const int* __restrict__ hi,
-                  const int* __restrict__ rank, const T* Xin, int ldxi, T* Xout, int ldxo, int nc,
-                  const T* __restrict__ E, int ldE, int offE, int rq, const T* __restrict__ Pin, int upn,
-                  int nch, const T* __restrict__ W, int ldw, int offp, int rp, T* __restrict__ Pout) {
-  constexpr int RC = sizeof(T) == 8 ? kRankCap64 : kRankCap32;
-  __shared__ T tcat[2 * RC * SM];
-  __shared__ T tile[kLdT * kTileC];
-  __shared__ T xs[SM * kRows];
-  const int c = blockIdx.x, ch = blockIdx.y, t = threadIdx.x, nt = blockDim.x;
+    k_solve_leaf(const T* __restrict__ Kinv, int bmax, const int* __restrict__ lo, const int* __restrict__ hi,
+                 int idL, const T* __restrict__ Xin, int ldxi, T* __restrict__ Xout, int ldxo, int nc,
+                 const T* __restrict__ W, int ldw, int offL, int rL, int nchL, T* __restrict__ P) {
+  __shared__ SolveSmem<T, SM> sm;
+  const int leaf = blockIdx.x, ch = blockIdx.y, id = idL + leaf, t = threadIdx.x;
+  const int l0 = lo[id], b = hi[id] - l0, row0 = ch * kRows, rn = min(kRows, b - row0);
+  const int flat = leaf * nchL + ch;
+  T* Pu = P ? P + (size_t)flat * rL * nc : nullptr;
+  if (rn <= 0) {
+    if (Pu)
+      for (int e = t; e < rL * nc; e += blockDim.x) Pu[e] = T(0);
+    return;
+  }
+  const T* Ki = Kinv + (size_t)leaf * bmax * bmax + row0;
+  const T* Wu = W + (size_t)offL * ldw + l0 + row0;
+  const int nwc = Pu ? rL : 0;
+  const int jn = min(SolveCfg<T>::kArena, b + nwc);
+  stage_stream(sm.arena, Ki, (size_t)bmax, b, Wu, (size_t)ldw, 0, jn, rn);
+  // right-hand block: the leaf's rows of x, as [k][SM]
+  for (int e0 = 0; e0 < b * SM; e0 += 8 * kBlock) {
+    T v[8];
+#pragma unroll
+    for (int a = 0; a < 8; ++a) {
+      const int e = e0 + t + a * kBlock, k = e % b, c = e / b;
+      v[a] = (e < b * SM && c < nc) ? Xin[(size_t)c * ldxi + l0 + k] : T(0);
+    }
+#pragma unroll
+    for (int a = 0; a < 8; ++a) {
+      const int e = e0 + t + a * kBlock;
+      if (e < b * SM) sm.tb[(e % b) * SM + e / b] = v[a];
+    }
+  }
+  T xr[SM / 4];
+#pragma unroll
+  for (int u = 0; u < SM / 4; ++u) xr[u] = T(0);
+  unit_pipeline<T, SM>(sm, Ki, (size_t)bmax, b, Wu, (size_t)ldw, nwc, rn, nc, xr, false,
+                       Xout + l0 + row0, (size_t)ldxo, Pu, rL, jn);
+}
+
+template <typename T, int SM>
+__global__ void __launch_bounds__(kBlock)
+    k_solve_level(int q, const int* __restrict__ lo, const int* __restrict__ hi, const int* __restrict__ rank,
+                  const T* Xin, int ldxi, T* Xout, int ldxo, int nc, const T* __restrict__ E, int ldE, int offE,
+                  int rq, const T* __restrict__ Pin, int upn, int gin, int nch, const T* __restrict__ W, int ldw,
+                  int offp, int rp, T* __restrict__ Pout) {
+  __shared__ SolveSmem<T, SM> sm;
+  const int c = blockIdx.x, ch = blockIdx.y, t = threadIdx.x;
   const int par = c >> 1, id = node_id(q, c);
   const int ra = rank[node_id(q, 2 * par)], rb = rank[node_id(q, 2 * par + 1)], r = ra + rb;
   const int row0 = lo[id] + ch * kRows, rn = min(kRows, hi[id] - row0);
-  T* Pu = Pout ? Pout + ((size_t)c * nch + ch) * rp * nc : nullptr;
+  const int flat = c * nch + ch;
+  T* Pu = Pout ? Pout + (size_t)flat * rp * nc : nullptr;
   if (rn <= 0) {
     if (Pu)
-      for (int e = t; e < rp * nc; e += nt) Pu[e] = T(0);
+      for (int e = t; e < rp * nc; e += blockDim.x) Pu[e] = T(0);
     return;
   }
-  // t_P = [W(rows a)^T x_a (r_b entries); W(rows b)^T x_b (r_a entries)]
-  const size_t us = (size_t)rq * nc;
-  for (int e = t; e < r * nc; e += nt) {
-    const int z = e % r, cc = e / r;
-    const int node = (z < rb) ? 2 * par : 2 * par + 1;
-    const int zz = (z < rb) ? z : z - rb;
-    const T* P0 = Pin + (size_t)node * upn * us + zz + (size_t)cc * rq;
-    T v = T(0);
-    int u = 0;
-    for (; u + 8 <= upn; u += 8) {
-      T pv[8];
-#pragma unroll
-      for (int x = 0; x < 8; ++x) pv[x] = P0[(u + x) * us];
-#pragma unroll
-      for (int x = 0; x < 8; ++x) v += pv[x];
-    }
-    for (; u < upn; ++u) v += P0[u * us];
-    tcat[z + cc * r] = v;
-  }
-  // x(unit) -= E(unit, :) t_P
-  const int ii = t & (kRows - 1), cg = t / kRows;
-  T acc[SM / 4];
-#pragma unroll
-  for (int u = 0; u < SM / 4; ++u) acc[u] = T(0);
   const T* Eu = E + (size_t)offE * ldE + row0;
-  for (int z0 = 0; z0 < r; z0 += kTileC) {
-    const int zn = min(kTileC, r - z0);
-    stage_tile(tile, Eu + (size_t)z0 * ldE, ldE, rn, zn);
-    __syncthreads();
-    for (int zz = 0; zz < zn; ++zz) {
-      const T e = tile[ii + zz * kLdT];
-#pragma unroll
-      for (int u = 0; u < SM / 4; ++u) acc[u] += e * tcat[z0 + zz + (cg + 4 * u) * r];
-    }
-    __syncthreads();
-  }
+  const T* Wu = W + (size_t)offp * ldw + row0;
+  const int nwc = Pu ? rp : 0;
+  const int jn = min(SolveCfg<T>::kArena, r + nwc);
+  stage_stream(sm.arena, Eu, (size_t)ldE, r, Wu, (size_t)ldw, 0, jn, rn);
+  // x of the unit
+  const int lane = t & 63, cg = t >> 6;
+  T xr[SM / 4];
 #pragma unroll
   for (int u = 0; u < SM / 4; ++u) {
     const int cc = cg + 4 * u;
-    T v = T(0);
-    if (ii < rn && cc < nc) {
-      v = Xin[(size_t)cc * ldxi + row0 + ii] - acc[u];
-      Xout[(size_t)cc * ldxo + row0 + ii] = v;
-    }
-    xs[cc * kRows + ii] = v;
+    xr[u] = (lane < rn && cc < nc) ? Xin[(size_t)cc * ldxi + row0 + lane] : T(0);
   }
-  __syncthreads();
-  if (Pu && rp > 0) unit_out<T, SM>(tile, xs, W + (size_t)offp * ldw + row0, ldw, rn, rp, nc, Pu);
+  // t_P = [W(rows a)^T x_a (r_b entries); W(rows b)^T x_b (r_a entries)] from
+  // the group sums of both children, as [z][SM]
+  const size_t usz = (size_t)rq * nc, gstride = (size_t)gin * usz;
+  const int ng = upn / gin;
+  constexpr int kE = 4, kJ = 4;
+  for (int e0 = 0; e0 < r * SM; e0 += kE * kBlock) {
+    T s[kE];
+    const T* p0[kE];
+    bool ok[kE];
+#pragma unroll
+    for (int a = 0; a < kE; ++a) {
+      const int e = e0 + t + a * kBlock, z = e % r, cc = e / r;
+      ok[a] = e < r * SM && cc < nc;
+      const int node = (z < rb) ? 2 * par : 2 * par + 1, zz = (z < rb) ? z : z - rb;
+      p0[a] = Pin + (size_t)node * upn * usz + zz + (size_t)cc * rq;
+      s[a] = T(0);
+    }
+    for (int j0 = 0; j0 < ng; j0 += kJ) {
+      T v[kE][kJ];
+#pragma unroll
+      for (int a = 0; a < kE; ++a)
+#pragma unroll
+        for (int j = 0; j < kJ; ++j) v[a][j] = (ok[a] && j0 + j < ng) ? p0[a][(size_t)(j0 + j) * gstride] : T(0);
+#pragma unroll
+      for (int a = 0; a < kE; ++a)
+#pragma unroll
+        for (int j = 0; j < kJ; ++j)
+          if (j0 + j < ng) s[a] += v[a][j];
+    }
+#pragma unroll
+    for (int a = 0; a < kE; ++a) {
+      const int e = e0 + t + a * kBlock;
+      if (e < r * SM) sm.tb[(e % r) * SM + e / r] = s[a];
+    }
+  }
+  unit_pipeline<T, SM>(sm, Eu, (size_t)ldE, r, Wu, (size_t)ldw, nwc, rn, nc, xr, true, Xout + row0,
+                       (size_t)ldxo, Pu, rp, jn);
 }
 
 // ---------------------------------------------------------------------------
@@ -208,6 +403,16 @@ static inline int cdiv(int a, int b) { return (a + b - 1) / b; }
 // Units per level-q node: q = L -> its own units; q < L -> its children's.
 static int units_per_node(const Tree& t, int q) {
   return q == t.L ? cdiv(t.max_size(t.L), kRows) : 2 * cdiv(t.max_size(q + 1), kRows);
+}
+
+// A level-q workgroup reads the upn slots of both children of its parent.
+// While those reads stay within kDirectBytes they ride along with the unit's
+// other loads; beyond that k_sum_units first adds each node's slots (one more
+// launch, one more round trip to memory).
+constexpr size_t kDirectBytes = 96 * 1024;
+
+static bool sum_first(const hodlr_s* h, int q, int nc) {
+  return 2 * (size_t)h->rcols[q - 1] * nc * units_per_node(h->tree, q) * h->esize > kDirectBytes;
 }
 
 size_t solve_partial_elems(const hodlr_s* h) {
@@ -233,7 +438,7 @@ static int solve_t(hodlr_s* h, T* X, int ldx, int nc, hipStream_t s) {
     ProfScope prof_("apply_leaf", s);
     k_solve_leaf<T, SM><<<dim3(h->nleaf, nchL), kBlock, 0, s>>>(
         h->Kinv.as<T>(), h->bmax, h->d_lo.as<int>(), h->d_hi.as<int>(), node_id(L, 0), X, ldx, Xt, n, nc,
-        h->W.as<T>(), n, offL, rL, nchL, P[0]);
+        h->W.as<T>(), n, offL, rL, nchL, L > 0 ? P[0] : nullptr);
   }
   HODLR_HIP(hipGetLastError());
   int cur = 0;
@@ -243,12 +448,22 @@ static int solve_t(hodlr_s* h, T* X, int ldx, int nc, hipStream_t s) {
     const int rp = q > 1 ? h->rcols[q - 2] : 0, offp = q > 1 ? h->off[q - 2] : 0;
     T* Xo = (q == 1) ? X : Xt;
     const int ldo = (q == 1) ? ldx : n;
+    const int upn = units_per_node(t, q);
+    int gin = 1;
+    if (sum_first(h, q, nc)) {
+      const long threads = (long)(1 << q) * rq * nc * kSumLanes;
+      {
+        ProfScope prof_("apply_sum", s);
+        k_sum_units<T><<<(int)((threads + kBlock - 1) / kBlock), kBlock, 0, s>>>(P[cur], 1 << q, upn, rq * nc);
+      }
+      HODLR_HIP(hipGetLastError());
+      gin = upn;
+    }
     {
       ProfScope prof_("apply_level", s);
       k_solve_level<T, SM><<<dim3(1 << q, nch), kBlock, 0, s>>>(
           q, h->d_lo.as<int>(), h->d_hi.as<int>(), h->d_rank.as<int>(), Xt, n, Xo, ldo, nc, h->E.as<T>(), n,
-          h->offE[q - 1], rq, P[cur], units_per_node(t, q), nch, h->W.as<T>(), n, offp, rp,
-          q > 1 ? P[cur ^ 1] : nullptr);
+          h->offE[q - 1], rq, P[cur], upn, gin, nch, h->W.as<T>(), n, offp, rp, q > 1 ? P[cur ^ 1] : nullptr);
     }
     HODLR_HIP(hipGetLastError());
     cur ^= 1;
