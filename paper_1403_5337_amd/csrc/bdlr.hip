@@ -312,7 +312,7 @@ __global__ void __launch_bounds__(kBlock)
   static_assert(SKEL % 64 == 0 && SKEL <= 256, "tile shape");
   __shared__ int srow[SKEL], scol[SKEL], prow[SKEL], pcol[SKEL];
   __shared__ T colv[SKEL];
-  __shared__ GjRegScratchAll<T, (sizeof(T) == 8 ? kRankCap64 : kRankCap32)> gw;
+  __shared__ GjScratch<T, (sizeof(T) == 8 ? kRankCap64 : kRankCap32)> gw;
   __shared__ T sv[2][4], spiv;
   __shared__ int si[2][4];
   const int task = blockIdx.x, t = threadIdx.x;

@@ -10,12 +10,12 @@ namespace hodlr {
 template <typename T> __device__ __forceinline__ T dabs(T x) { return x < T(0) ? -x : x; }
 
 // Keep the larger value; ties go to the lower index.  NaN never wins.
+// Written without branches so that it compiles to compares and selects.
 template <typename T>
 __device__ __forceinline__ void argmax_merge(T& v, int& i, T v2, int i2) {
-  if (v2 > v || (v2 == v && i2 < i)) {
-    v = v2;
-    i = i2;
-  }
+  const bool take = (v2 > v) | ((v2 == v) & (i2 < i));
+  v = take ? v2 : v;
+  i = take ? i2 : i;
 }
 
 template <typename T> __device__ __forceinline__ T wave_sum(T v) {
@@ -64,110 +64,11 @@ template <typename T> __device__ T block_sum(T v, T* sv) {
   return s;
 }
 
-// In-place Gauss-Jordan inversion with partial (row) pivoting of the b x b
-// matrix A (LDS, column-major, leading dimension ld, b <= kGjMax).  On return
-// A holds the inverse of the row-permuted matrix; src[j] names the column of
-// A that is column j of the inverse of the original matrix.  Returns false
-// (uniformly) if a zero or non-finite pivot is met.
-//
-// Each pivot step costs three workgroup barriers: one wave finds the pivot
-// row p of column k; every thread snapshots row p, row k and column k; then
-// every thread rewrites the elements it owns as the row swap, the scaling of
-// the pivot row and the elimination of the other rows at once.
-constexpr int kGjMax = 256;
-
-template <typename T>
-struct GjScratch {
-  int ipiv[kGjMax], src[kGjMax];
-  T colk[kGjMax], prow[kGjMax], krow[kGjMax];
-  T pv;
-  int p;
-};
-
-template <typename T>
-__device__ bool gj_inverse(T* A, int b, int ld, GjScratch<T>& w) {
-  const int t = threadIdx.x, nt = blockDim.x;
-  int lb = 0;
-  while ((1 << lb) < b) ++lb;
-  // thread t owns row (t & (bp-1)) of every (nt/bp)-th column: no div/mod
-  const int bp = 1 << lb, ri = t & (bp - 1), cstep = nt >> lb, c0 = t >> lb;
-  const bool owner = cstep > 0 && ri < b;
-  bool ok = true;
-  for (int k = 0; k < b; ++k) {
-    if (t < 64) {
-      T v = T(-1);
-      int idx = INT_MAX;
-      for (int i = k + t; i < b; i += 64) argmax_merge(v, idx, dabs(A[i + k * ld]), i);
-      for (int o = 32; o > 0; o >>= 1) {
-        const T v2 = __shfl_xor(v, o, 64);
-        const int i2 = __shfl_xor(idx, o, 64);
-        argmax_merge(v, idx, v2, i2);
-      }
-      if (t == 0) {
-        w.pv = v;
-        w.p = idx;
-        w.ipiv[k] = idx;
-      }
-    }
-    __syncthreads();
-    const int p = w.p;
-    const T pv = w.pv;
-    if (!(pv > T(0)) || !(pv < T(INFINITY)) || p >= b) {
-      ok = false;
-      break;
-    }
-    const T inv = T(1) / A[p + k * ld];
-    // snapshot: scaled pivot row, old row k, column k
-    for (int j = t; j < b; j += nt) {
-      w.prow[j] = A[p + j * ld] * inv;
-      w.krow[j] = A[k + j * ld];
-    }
-    for (int i = t; i < b; i += nt) w.colk[i] = A[i + k * ld];
-    __syncthreads();
-    if (owner) {
-      T* Ai = A + ri;
-      const T* pr = w.prow;
-      if (ri == k) {
-#pragma unroll 4
-        for (int j = c0; j < b; j += cstep) Ai[j * ld] = pr[j];
-      } else if (ri == p) {  // old row k lands here
-        const T f = w.krow[k];
-        const T* kr = w.krow;
-#pragma unroll 4
-        for (int j = c0; j < b; j += cstep) Ai[j * ld] = kr[j] - f * pr[j];
-      } else {
-        const T f = w.colk[ri];
-#pragma unroll 4
-        for (int j = c0; j < b; j += cstep) Ai[j * ld] -= f * pr[j];
-      }
-      if (((k - c0) & (cstep - 1)) == 0 && k >= c0) {
-        // column k holds the multipliers: inv on the pivot row, -f * inv elsewhere
-        const T f = (ri == p) ? w.krow[k] : w.colk[ri];
-        Ai[k * ld] = (ri == k) ? inv : -f * inv;
-      }
-    }
-    __syncthreads();
-  }
-  if (ok) {
-    if (t == 0) {
-      for (int j = 0; j < b; ++j) w.src[j] = j;
-      for (int k = b - 1; k >= 0; --k) {
-        const int p = w.ipiv[k];
-        const int x = w.src[k];
-        w.src[k] = w.src[p];
-        w.src[p] = x;
-      }
-    }
-    __syncthreads();
-  }
-  return ok;
-}
-
 // ---------------------------------------------------------------------------
 // Cross-lane moves inside a wavefront through DPP (no LDS round trip).
 // ---------------------------------------------------------------------------
 template <int CTRL> __device__ __forceinline__ int dpp_move(int v) {
-  return __builtin_amdgcn_update_dpp(0, v, CTRL, 0xF, 0xF, false);
+  return __builtin_amdgcn_mov_dpp(v, CTRL, 0xF, 0xF, true);
 }
 template <int CTRL> __device__ __forceinline__ float dpp_move(float v) {
   return __int_as_float(dpp_move<CTRL>(__float_as_int(v)));
@@ -175,6 +76,16 @@ template <int CTRL> __device__ __forceinline__ float dpp_move(float v) {
 template <int CTRL> __device__ __forceinline__ double dpp_move(double v) {
   const long long b = __double_as_longlong(v);
   const int lo = dpp_move<CTRL>((int)(b & 0xffffffffll)), hi = dpp_move<CTRL>((int)(b >> 32));
+  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
+__device__ __forceinline__ float lane_value(float x, int l) {
+  return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(x), l));
+}
+__device__ __forceinline__ double lane_value(double x, int l) {
+  const long long v = __double_as_longlong(x);
+  const int lo = __builtin_amdgcn_readlane((int)(v & 0xffffffffll), l);
+  const int hi = __builtin_amdgcn_readlane((int)(v >> 32), l);
   return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
 }
 
@@ -190,165 +101,284 @@ template <typename T> __device__ __forceinline__ void wave_argmax(T& v, int& i) 
   argmax_merge(v, i, __shfl_xor(v, 32, 64), __shfl_xor(i, 32, 64));
 }
 
-__device__ __forceinline__ float lane_value(float x, int l) {
-  return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(x), l));
+// The same argmax with a wave-uniform result and no LDS traffic: the four DPP
+// stages leave every lane of a 16-lane row holding its row's result, and the
+// four row results are read with readlane and merged in row order.
+template <typename T> __device__ __forceinline__ void wave_argmax_uniform(T& v, int& i) {
+  argmax_merge(v, i, dpp_move<0xB1>(v), dpp_move<0xB1>(i));
+  argmax_merge(v, i, dpp_move<0x4E>(v), dpp_move<0x4E>(i));
+  argmax_merge(v, i, dpp_move<0x141>(v), dpp_move<0x141>(i));
+  argmax_merge(v, i, dpp_move<0x140>(v), dpp_move<0x140>(i));
+  T bv = lane_value(v, 0);
+  int bi = __builtin_amdgcn_readlane(i, 0);
+#pragma unroll
+  for (int r = 1; r < 4; ++r) argmax_merge(bv, bi, lane_value(v, 16 * r), __builtin_amdgcn_readlane(i, 16 * r));
+  v = bv;
+  i = bi;
 }
-__device__ __forceinline__ double lane_value(double x, int l) {
-  const long long v = __double_as_longlong(x);
-  const int lo = __builtin_amdgcn_readlane((int)(v & 0xffffffffll), l);
-  const int hi = __builtin_amdgcn_readlane((int)(v >> 32), l);
-  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+
+// Row of the largest candidate cv[a] (row lane + 64 a), ties to the lowest
+// row, and that candidate (best), both wave-uniform.  The maximum is reduced
+// with DPP inside each 16-lane row and across the four rows by readlane;
+// then the lowest row holding it comes from one ballot per register.  Returns
+// -1 if no candidate equals the maximum (a NaN maximum).
+template <typename T> __device__ __forceinline__ T sel_max(T a, T b) { return b > a ? b : a; }
+
+template <typename T> __device__ __forceinline__ T wave_max(T m) {
+  m = sel_max(m, dpp_move<0xB1>(m));
+  m = sel_max(m, dpp_move<0x4E>(m));
+  m = sel_max(m, dpp_move<0x141>(m));
+  m = sel_max(m, dpp_move<0x140>(m));
+  return sel_max(sel_max(lane_value(m, 0), lane_value(m, 16)), sel_max(lane_value(m, 32), lane_value(m, 48)));
+}
+
+template <typename T, int RA>
+__device__ __forceinline__ int wave_argmax_rows(const T (&cv)[RA], T& best) {
+  T m = cv[0];
+#pragma unroll
+  for (int a = 1; a < RA; ++a) m = sel_max(m, cv[a]);
+  best = wave_max(m);
+#pragma unroll
+  for (int a = 0; a < RA; ++a) {
+    const unsigned long long bal = __ballot(cv[a] == best);
+    if (bal) return 64 * a + __ffsll((long long)bal) - 1;
+  }
+  return -1;
 }
 
 // ---------------------------------------------------------------------------
-// Gauss-Jordan inversion with partial pivoting, matrix held in registers.
+// Blocked Gauss-Jordan inversion with partial pivoting (256 threads).
 //
-// 256 threads (4 waves); thread (lane, w) holds rows lane + 64 a (a < RA) of
-// the columns w + 4 c assigned to its registers, so n <= min(64 RA, 4 CB).
-// Step k eliminates column k: the wave holding it finds the pivot row p
-// (largest |entry| among rows not yet used, ties to the lower row) and
-// publishes the column in LDS; after the one barrier of the step every wave
-// reads the pivot row from lane p & 63 of itself, and every element is
-// updated at once (rows are never swapped; row p is scaled, the others get
-// x -= f * (pivot row) / pivot, and column k receives the multipliers).  With
-// P the row order of the pivots the array ends as (P A)^-1 in place, i.e.
-// A^-1(r, c) = X(p_r, pinv(c)).  The register columns rotate by one after
-// every 4 steps, so the pivot column is always register column 0 of its
-// wave and no register is addressed by a run-time index.
+// The matrix sits in LDS.  Every kGjNb = 8 pivot steps form a block.  Wave 0
+// factors the block's 8 columns (the panel) on its own, without barriers: the
+// pivot of each step is the largest |entry| of the current column among the
+// rows not yet used (ties to the lower row); the pivot row is scaled, the
+// other rows are eliminated, and the column is replaced by the multipliers,
+// which is the in-place Gauss-Jordan step.  The block's steps applied to any
+// other column j amount to X(:, j) += C X_old(P, j), with P the block's pivot
+// rows and C = Z - I(:, P) for the factored panel Z: one rank-8 update.
+//
+// Look-ahead: while waves 1-3 apply block b's update to the other columns
+// (8 x 4 tiles per thread), wave 0 applies it to the next panel's columns in
+// its registers and factors that panel, so the updates run under the chain
+// of pivot steps.  Rows are never swapped: with p_k the pivot row of step k
+// the array ends as (P A)^-1, i.e. A^-1(r, c) = X(p_r, pinv(c)).
 // ---------------------------------------------------------------------------
-template <typename T, int RA, int CB>
-struct GjRegScratch {
-  T colv[2][64 * RA];
-  int p[2];
-  int pinv[64 * RA];  // step at which a row was the pivot row
-  int prow[4 * CB];   // pivot row of each step
+constexpr int kGjNb = 8;
+
+template <typename T, int NMAX>
+struct GjScratch {
+  static constexpr int kLd = (NMAX + 7) / 8 * 8;  // column stride of X and C
+  alignas(16) T X[NMAX * kLd];                    // the matrix, column-major
+  alignas(16) T C[2][kGjNb * kLd];                // C = Z - I(:, P) of two blocks, column-major
+  alignas(16) T R[NMAX * kGjNb];                  // pivot rows of the other columns, [j][s]
+  int p[2][kGjNb];                                // pivot rows of two blocks
+  int pinv[NMAX];                                 // step at which a row was the pivot row
+  int prow[NMAX];                                 // pivot row of each step
+  int bad;
 };
 
-// load(i, j) returns A(i, j) for i, j < n; out (column-major, ld ldo, any
-// address space) receives A^-1 and may hold A itself, since every element is
-// read before the first barrier.  Returns false (uniformly) on a zero or
-// non-finite pivot.
-template <typename T, int RA, int CB, typename Load>
-__device__ bool gj_invert_regs(Load load, int n, T* out, int ldo, GjRegScratch<T, RA, CB>& s) {
-  const int t = threadIdx.x, lane = t & 63;
-  const int w = __builtin_amdgcn_readfirstlane(t >> 6);
-  T x[RA][CB];
+// Wave 0: loads the panel X(:, k0 : k0 + nbk) into registers (rows of lane l
+// are l + 64 a, a < RA), first applying the previous block's update (Cp, with
+// the panel's pivot-row values at R[(jr + j) * kGjNb]) if Cp is not NULL,
+// then runs the panel's pivot steps and stores Z, C and the pivots.  used:
+// per lane, bit a = row used or beyond n.
+template <typename T, int RA, int NMAX>
+__device__ bool gj_panel(GjScratch<T, NMAX>& s, int n, int k0, int nbk, int buf, const T* Cp, int jr,
+                         unsigned& used) {
+  constexpr int ld = GjScratch<T, NMAX>::kLd;
+  const int lane = threadIdx.x & 63;
+  T P[RA][kGjNb];
 #pragma unroll
   for (int a = 0; a < RA; ++a)
 #pragma unroll
-    for (int c = 0; c < CB; ++c) {
-      const int i = lane + 64 * a, j = w + 4 * c;
-      x[a][c] = (i < n && j < n) ? load(i, j) : T(0);
+    for (int j = 0; j < kGjNb; ++j) {
+      const int i = lane + 64 * a;
+      P[a][j] = (i < n && j < nbk) ? s.X[(k0 + j) * ld + i] : T(0);
     }
-  unsigned used = 0;  // rows that were pivots, or lie beyond n
-#pragma unroll
-  for (int a = 0; a < RA; ++a) used |= (lane + 64 * a >= n ? 1u : 0u) << a;
-  bool ok = true;
-  int rot = 0;  // register column c holds column w + 4 ((c + rot) mod CB)
-  for (int k0 = 0; k0 < n && ok; k0 += 4) {
-    for (int wq = 0; wq < 4; ++wq) {
-      const int k = k0 + wq;
-      if (k >= n) break;
-      const int par = k & 1;
-      if (w == wq) {
-        T bv = T(-1);
-        int bi = INT_MAX;
-#pragma unroll
-        for (int a = 0; a < RA; ++a) {
-          const T v = ((used >> a) & 1u) ? T(-1) : fabs(x[a][0]);
-          if (v > bv) {
-            bv = v;
-            bi = lane + 64 * a;
-          }
-        }
-        wave_argmax(bv, bi);
-        if (lane == 0) s.p[par] = bi;
-#pragma unroll
-        for (int a = 0; a < RA; ++a) s.colv[par][lane + 64 * a] = x[a][0];
-      }
-      __syncthreads();
-      const int p = __builtin_amdgcn_readfirstlane(s.p[par]);
-      if (p < 0 || p >= n) {
-        ok = false;
-        break;
-      }
-      const T piv = s.colv[par][p];
-      if (!(fabs(piv) > T(0)) || !(fabs(piv) < T(INFINITY))) {
-        ok = false;
-        break;
-      }
-      const T inv = T(1) / piv;
-      const int pl = p & 63, ap = p >> 6;
-      if (t == 0) {
-        s.pinv[p] = k;
-        s.prow[k] = p;
-      }
-      T f[RA];
-#pragma unroll
-      for (int a = 0; a < RA; ++a) f[a] = (lane + 64 * a == p) ? T(0) : s.colv[par][lane + 64 * a];
-#pragma unroll
-      for (int c = 0; c < CB; ++c) {
-        T v = x[0][c];
-#pragma unroll
-        for (int a = 1; a < RA; ++a)
-          if (ap == a) v = x[a][c];
-        const T rs = lane_value(v, pl) * inv;
-#pragma unroll
-        for (int a = 0; a < RA; ++a) x[a][c] = fma(-f[a], rs, x[a][c]);
-      }
-      // the pivot row is scaled (its f is 0, so the update left it as it was)
-      const T sc = lane == pl ? inv : T(1);
-#pragma unroll
-      for (int a = 0; a < RA; ++a)
-        if (a == ap) {
-#pragma unroll
-          for (int c = 0; c < CB; ++c) x[a][c] *= sc;
-        }
-      // column k: the multipliers
-      if (w == wq) {
-#pragma unroll
-        for (int a = 0; a < RA; ++a)
-          x[a][0] = (lane + 64 * a == p) ? inv : -s.colv[par][lane + 64 * a] * inv;
-      }
-      if (lane == pl) used |= 1u << ap;
-    }
-    // rotate the register columns by one
+  if (Cp) {
 #pragma unroll
     for (int a = 0; a < RA; ++a) {
-      const T x0 = x[a][0];
+      const int i = min(lane + 64 * a, ld - 1);
+      T c[kGjNb];
 #pragma unroll
-      for (int c = 0; c + 1 < CB; ++c) x[a][c] = x[a][c + 1];
-      x[a][CB - 1] = x0;
+      for (int q = 0; q < kGjNb; ++q) c[q] = Cp[q * ld + i];
+#pragma unroll
+      for (int j = 0; j < kGjNb; ++j) {
+        const T* rp = static_cast<const T*>(__builtin_assume_aligned(s.R + (jr + j) * kGjNb, 16));
+#pragma unroll
+        for (int q = 0; q < kGjNb; ++q) P[a][j] = fma(c[q], rp[q], P[a][j]);
+      }
     }
-    ++rot;
   }
-  __syncthreads();
+  int pv[kGjNb];
+  bool ok = true;
+  // pivot candidates of the current column
+  T cv[RA];
+#pragma unroll
+  for (int a = 0; a < RA; ++a) cv[a] = ((used >> a) & 1u) ? T(-1) : fabs(P[a][0]);
+#pragma unroll
+  for (int j = 0; j < kGjNb; ++j) {
+    pv[j] = -1;
+    if (j >= nbk || !ok) continue;
+    T bv;
+    const int pr = __builtin_amdgcn_readfirstlane(wave_argmax_rows<T, RA>(cv, bv));
+    if (pr < 0 || pr >= n || !(bv > T(0)) || !(bv < T(INFINITY))) {
+      ok = false;
+      continue;
+    }
+    const int pl = pr & 63, ap = pr >> 6;
+    T rs[kGjNb];
+#pragma unroll
+    for (int j2 = 0; j2 < kGjNb; ++j2) {
+      T v = P[0][j2];
+#pragma unroll
+      for (int a = 1; a < RA; ++a) v = ap == a ? P[a][j2] : v;
+      rs[j2] = lane_value(v, pl);
+    }
+    const T inv = T(1) / rs[j];
+#pragma unroll
+    for (int j2 = 0; j2 < kGjNb; ++j2) rs[j2] *= inv;
+    if (lane == pl) used |= 1u << ap;
+#pragma unroll
+    for (int a = 0; a < RA; ++a) {
+      const bool isp = lane + 64 * a == pr;
+      const T f = P[a][j];
+#pragma unroll
+      for (int j2 = 0; j2 < kGjNb; ++j2)
+        if (j2 != j) P[a][j2] = isp ? rs[j2] : fma(-f, rs[j2], P[a][j2]);
+      P[a][j] = isp ? inv : -f * inv;
+      if (j + 1 < kGjNb) cv[a] = ((used >> a) & 1u) ? T(-1) : fabs(P[a][j + 1]);
+    }
+    pv[j] = pr;
+    if (lane == 0) {
+      s.p[buf][j] = pr;
+      s.pinv[pr] = k0 + j;
+      s.prow[k0 + j] = pr;
+    }
+  }
   if (!ok) return false;
 #pragma unroll
-  for (int a = 0; a < RA; ++a)
+  for (int a = 0; a < RA; ++a) {
+    const int i = lane + 64 * a;
+    if (i < n)
 #pragma unroll
-    for (int c = 0; c < CB; ++c) {
-      int cc = c + rot;
-      while (cc >= CB) cc -= CB;
-      const int i = lane + 64 * a, j = w + 4 * cc;
-      if (i < n && j < n) out[s.pinv[i] + (size_t)s.prow[j] * ldo] = x[a][c];
-    }
+      for (int j = 0; j < kGjNb; ++j)
+        if (j < nbk) {
+          s.X[(k0 + j) * ld + i] = P[a][j];
+          s.C[buf][j * ld + i] = i == pv[j] ? P[a][j] - T(1) : P[a][j];
+        }
+  }
   return true;
 }
 
-// Size classes of gj_invert_regs for n <= 64, 128 and NMAX (184 or 128).
 template <typename T, int NMAX>
-union GjRegScratchAll {
-  GjRegScratch<T, 1, 16> s1;
-  GjRegScratch<T, 2, 32> s2;
-  GjRegScratch<T, (NMAX + 63) / 64, (NMAX + 3) / 4> s3;
-};
+__device__ __forceinline__ bool gj_panel_any(GjScratch<T, NMAX>& s, int n, int k0, int nbk, int buf, const T* Cp,
+                                             int jr, unsigned& used) {
+  if (n <= 64) return gj_panel<T, 1, NMAX>(s, n, k0, nbk, buf, Cp, jr, used);
+  if (n <= 128) return gj_panel<T, 2, NMAX>(s, n, k0, nbk, buf, Cp, jr, used);
+  return gj_panel<T, 3, NMAX>(s, n, k0, nbk, buf, Cp, jr, used);
+}
 
+// X(0 : n8, j) += C X_old(P, j) for the m columns listed by t' -> jj = t' < k0
+// ? t' : t' + skip (column j = jj < k0 ? jj : jj + nbk, R row jj), in 8 x 4
+// tiles taken by threads tid, tid + nthr, ...
+template <typename T, int NMAX>
+__device__ __forceinline__ void gj_tiles(GjScratch<T, NMAX>& s, const T* Cb, int n8, int m, int k0, int skip,
+                                         int nbk, int tid, int nthr) {
+  constexpr int ld = GjScratch<T, NMAX>::kLd;
+  const int nti = n8 >> 3, ntj = (m + 3) >> 2;
+  for (int tile = tid; tile < nti * ntj; tile += nthr) {
+    const int ti = tile % nti, tj = tile / nti, i0 = ti * 8;
+    T c[8][kGjNb];
+#pragma unroll
+    for (int q = 0; q < kGjNb; ++q) {
+      const T* cp = static_cast<const T*>(__builtin_assume_aligned(Cb + q * ld + i0, 16));
+#pragma unroll
+      for (int r = 0; r < 8; ++r) c[r][q] = cp[r];
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int tp = tj * 4 + u;
+      if (tp >= m) break;
+      const int jj = tp < k0 ? tp : tp + skip, j = jj < k0 ? jj : jj + nbk;
+      const T* rp = static_cast<const T*>(__builtin_assume_aligned(s.R + jj * kGjNb, 16));
+      T rv[kGjNb];
+#pragma unroll
+      for (int q = 0; q < kGjNb; ++q) rv[q] = rp[q];
+      T* xp = static_cast<T*>(__builtin_assume_aligned(s.X + j * ld + i0, 16));
+      T x[8];
+#pragma unroll
+      for (int r = 0; r < 8; ++r) x[r] = xp[r];
+#pragma unroll
+      for (int r = 0; r < 8; ++r)
+#pragma unroll
+        for (int q = 0; q < kGjNb; ++q) x[r] = fma(c[r][q], rv[q], x[r]);
+#pragma unroll
+      for (int r = 0; r < 8; ++r) xp[r] = x[r];
+    }
+  }
+}
+
+// load(i, j) returns A(i, j) for i, j < n <= NMAX; out (column-major, ld ldo,
+// any address space) receives A^-1 and may hold A itself, since every element
+// is read before the first barrier.  Returns false (uniformly) on a zero or
+// non-finite pivot.
 template <typename T, int NMAX, typename Load>
-__device__ bool gj_invert(Load load, int n, T* out, int ldo, GjRegScratchAll<T, NMAX>& s) {
-  if (n <= 64) return gj_invert_regs<T, 1, 16>(load, n, out, ldo, s.s1);
-  if (n <= 128 || NMAX <= 128) return gj_invert_regs<T, 2, 32>(load, n, out, ldo, s.s2);
-  return gj_invert_regs<T, (NMAX + 63) / 64, (NMAX + 3) / 4>(load, n, out, ldo, s.s3);
+__device__ bool gj_invert(Load load, int n, T* out, int ldo, GjScratch<T, NMAX>& s) {
+  static_assert(NMAX <= 192, "three rows per lane at most");
+  constexpr int ld = GjScratch<T, NMAX>::kLd;
+  const int t = threadIdx.x, nt = blockDim.x, lane = t & 63;
+  const int n8 = (n + 7) & ~7;  // rows touched by the 8-row tiles
+  // 32 loads per thread in flight at a time
+  constexpr int kLoads = 32;
+  for (int e0 = 0; e0 < n * n8; e0 += kLoads * nt) {
+    T v[kLoads];
+#pragma unroll
+    for (int u = 0; u < kLoads; ++u) {
+      const int e = e0 + t + u * nt, i = e % n8, j = e / n8;
+      v[u] = (e < n * n8 && i < n) ? load(i, j) : T(0);
+    }
+#pragma unroll
+    for (int u = 0; u < kLoads; ++u) {
+      const int e = e0 + t + u * nt;
+      if (e < n * n8) s.X[(e / n8) * ld + e % n8] = v[u];
+    }
+  }
+  for (int e = t; e < 2 * kGjNb * n8; e += nt) {
+    const int b = e / (kGjNb * n8), r = e % (kGjNb * n8);
+    s.C[b][(r / n8) * ld + r % n8] = T(0);
+  }
+  if (t == 0) s.bad = 0;
+  unsigned used = 0;
+#pragma unroll
+  for (int a = 0; a < 3; ++a) used |= (lane + 64 * a >= n ? 1u : 0u) << a;
+  __syncthreads();
+  if (t < 64 && !gj_panel_any<T, NMAX>(s, n, 0, min(kGjNb, n), 0, nullptr, 0, used) && t == 0) s.bad = 1;
+  for (int k0 = 0, buf = 0;; k0 += kGjNb, buf ^= 1) {
+    __syncthreads();
+    if (s.bad) return false;
+    const int nbk = min(kGjNb, n - k0), ncols = n - nbk;
+    const int k1 = k0 + nbk, nbk1 = k1 < n ? min(kGjNb, n - k1) : 0;
+    // block buf's pivot rows of every other column, before its update
+    for (int e = t; e < ncols * kGjNb; e += nt) {
+      const int jj = e / kGjNb, q = e % kGjNb, j = jj < k0 ? jj : jj + nbk;
+      s.R[e] = q < nbk ? s.X[j * ld + s.p[buf][q]] : T(0);
+    }
+    __syncthreads();
+    if (t < 64) {
+      if (nbk1 > 0 && !gj_panel_any<T, NMAX>(s, n, k1, nbk1, buf ^ 1, s.C[buf], k0, used) && t == 0) s.bad = 1;
+    } else {
+      gj_tiles<T, NMAX>(s, s.C[buf], n8, ncols - nbk1, k0, nbk1, nbk, t - 64, nt - 64);
+    }
+    if (nbk1 == 0) break;
+  }
+  __syncthreads();
+  for (int e = t; e < n * n; e += nt) {
+    const int i = e % n, j = e / n;
+    out[s.pinv[i] + (size_t)s.prow[j] * ldo] = s.X[j * ld + i];
+  }
+  return true;
 }
 
 // C = alpha * A * B + beta * C for column-major operands (any address space)

@@ -76,7 +76,7 @@ template <typename T>
 __global__ void __launch_bounds__(kBlock)
     k_leaf_inverse(T* __restrict__ Kinv, int bmax, const int* __restrict__ lo,
                    const int* __restrict__ hi, int id0, int* __restrict__ status) {
-  __shared__ GjRegScratchAll<T, (sizeof(T) == 8 ? kRankCap64 : kRankCap32)> gw;
+  __shared__ GjScratch<T, (sizeof(T) == 8 ? kRankCap64 : kRankCap32)> gw;
   const int leaf = blockIdx.x, id = id0 + leaf, t = threadIdx.x;
   const int b = hi[id] - lo[id];
   T* Gm = Kinv + (size_t)leaf * bmax * bmax;
@@ -142,7 +142,7 @@ template <typename T>
 __global__ void __launch_bounds__(kBlock)
     k_capacitance_inverse(const int* __restrict__ rank, int q, int rq, T* __restrict__ Sinv,
                           int* __restrict__ status) {
-  __shared__ GjRegScratchAll<T, (sizeof(T) == 8 ? kRankCap64 : kRankCap32)> gw;
+  __shared__ GjScratch<T, (sizeof(T) == 8 ? kRankCap64 : kRankCap32)> gw;
   const int i = blockIdx.x;
   const int ra = rank[node_id(q, 2 * i)], rb = rank[node_id(q, 2 * i + 1)], lds = 2 * rq;
   if (ra == 0) return;
