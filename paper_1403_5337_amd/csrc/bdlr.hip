@@ -166,26 +166,32 @@ __global__ void __launch_bounds__(kBlock)
             buf, s_cut);
 }
 
-// Full-pivot elimination of Ahat held in registers: thread (lane, w) of the 4
-// waves owns rows lane + 64 a and columns w + 4 b of the tile.  Nothing
+// Full-pivot elimination of Ahat held in registers: thread (lane, w) of the
+// NW waves owns rows lane + 64 a and columns w + NW b of the tile.  Nothing
 // moves: pivoted rows and columns are retired, and every step applies the
 // rank-1 update of the Schur complement to the active elements only.  A step
-// costs two barriers: one to combine the four waves' candidates, one to
-// publish the pivot column; each wave takes the pivot row straight from the
-// lane that holds it, and the next step's candidate is tracked during the
-// update.  Only the pivot sequence is kept (prow, pcol: positions in Ahat).
-template <typename T, int RA, int CB>
+// costs two barriers: one to combine the waves' candidates, one to publish the
+// pivot column; each wave takes the pivot row straight from the lane that
+// holds it, and the next step's candidate is tracked during the update.  Only
+// the pivot sequence is kept (prow, pcol: positions in Ahat).  With 16 waves
+// (1024 threads) every SIMD runs four waves, which keeps its VALU busy while
+// each wave waits on its own instruction stream.
+constexpr int kLuWaves = 16;
+constexpr int kLuBlock = 64 * kLuWaves;
+
+template <typename T, int RA, int CB, int NW>
 __device__ int full_pivot_steps(const double* __restrict__ Kb, int ldk, const int* srow, const int* scol,
                                 int nr, int nc, int kmax, T eps, int* prow, int* pcol, T* colv,
-                                T (*sv)[4], int (*si)[4], T* spiv) {
+                                T (*sv)[NW], int (*si)[NW], T* spiv) {
+  static_assert(NW <= 16, "the candidates of the waves are merged inside one 16-lane row");
   const int t = threadIdx.x, lane = t & 63;
   const int w = __builtin_amdgcn_readfirstlane(t >> 6);
   unsigned ract = 0;            // per lane: bit a = row lane + 64 a still active
-  unsigned long long cact = 0;  // per wave: bit b = column w + 4 b still active
+  unsigned long long cact = 0;  // per wave: bit b = column w + NW b still active
 #pragma unroll
   for (int a = 0; a < RA; ++a) ract |= (lane + 64 * a < nr ? 1u : 0u) << a;
 #pragma unroll
-  for (int b = 0; b < CB; ++b) cact |= (w + 4 * b < nc ? 1ull : 0ull) << b;
+  for (int b = 0; b < CB; ++b) cact |= (w + NW * b < nc ? 1ull : 0ull) << b;
   T x[RA][CB];
 #pragma unroll
   for (int a = 0; a < RA; ++a) {
@@ -193,7 +199,7 @@ __device__ int full_pivot_steps(const double* __restrict__ Kb, int ldk, const in
     const int ri = srow[i];
 #pragma unroll
     for (int b = 0; b < CB; ++b) {
-      const int j = w + 4 * b;
+      const int j = w + NW * b;
       x[a][b] = (i < nr && j < nc) ? (T)Kb[(size_t)scol[j] * ldk + ri] : T(0);
     }
   }
@@ -220,9 +226,9 @@ __device__ int full_pivot_steps(const double* __restrict__ Kb, int ldk, const in
         }
     }
     bv = bva[0];
-    bi = lane * 256 + w + 4 * bba[0];
+    bi = lane * 256 + w + NW * bba[0];
 #pragma unroll
-    for (int a = 1; a < RA; ++a) argmax_merge(bv, bi, bva[a], (lane + 64 * a) * 256 + w + 4 * bba[a]);
+    for (int a = 1; a < RA; ++a) argmax_merge(bv, bi, bva[a], (lane + 64 * a) * 256 + w + NW * bba[a]);
   }
   T first = T(0);
   int r = 0;
@@ -234,15 +240,19 @@ __device__ int full_pivot_steps(const double* __restrict__ Kb, int ldk, const in
       si[par][w] = bi;
     }
     __syncthreads();
-    T pv = sv[par][0];
-    int flat = si[par][0];
-#pragma unroll
-    for (int q = 1; q < 4; ++q) argmax_merge(pv, flat, sv[par][q], si[par][q]);
+    // the waves' candidates, merged inside the first 16-lane row
+    T pv = lane < NW ? sv[par][lane] : T(-1);
+    int flat = lane < NW ? si[par][lane] : INT_MAX;
+    argmax_merge(pv, flat, dpp_move<0xB1>(pv), dpp_move<0xB1>(flat));
+    argmax_merge(pv, flat, dpp_move<0x4E>(pv), dpp_move<0x4E>(flat));
+    argmax_merge(pv, flat, dpp_move<0x141>(pv), dpp_move<0x141>(flat));
+    argmax_merge(pv, flat, dpp_move<0x140>(pv), dpp_move<0x140>(flat));
+    pv = lane_value(pv, 0);
+    flat = __builtin_amdgcn_readlane(flat, 0);
     if (k == 0) first = pv;
     if (!(pv > T(0)) || pv < eps * first || !(pv < T(INFINITY))) break;
-    const int pi = __builtin_amdgcn_readfirstlane(flat >> 8);
-    const int pj = __builtin_amdgcn_readfirstlane(flat & 255);
-    const int pl = pi & 63, ap = pi >> 6, wp = pj & 3, bp = pj >> 2;
+    const int pi = flat >> 8, pj = flat & 255;
+    const int pl = pi & 63, ap = pi >> 6, wp = pj % NW, bp = pj / NW;
     if (t == 0) {
       prow[k] = pi;
       pcol[k] = pj;
@@ -279,8 +289,7 @@ __device__ int full_pivot_steps(const double* __restrict__ Kb, int ldk, const in
       if ((cact >> b) & 1ull) {
         T v = x[0][b];
 #pragma unroll
-        for (int a = 1; a < RA; ++a)
-          if (ap == a) v = x[a][b];
+        for (int a = 1; a < RA; ++a) v = (ap == a) ? x[a][b] : v;
         const T rv = lane_value(v, pl);
 #pragma unroll
         for (int a = 0; a < RA; ++a) {
@@ -293,32 +302,31 @@ __device__ int full_pivot_steps(const double* __restrict__ Kb, int ldk, const in
         }
       }
     bv = bva[0];
-    bi = lane * 256 + w + 4 * bba[0];
+    bi = lane * 256 + w + NW * bba[0];
 #pragma unroll
-    for (int a = 1; a < RA; ++a) argmax_merge(bv, bi, bva[a], (lane + 64 * a) * 256 + w + 4 * bba[a]);
+    for (int a = 1; a < RA; ++a) argmax_merge(bv, bi, bva[a], (lane + 64 * a) * 256 + w + NW * bba[a]);
     r = k + 1;
   }
   return r;
 }
 
-// Pivots and G = Ahat11^-1 of every block: the elimination runs on the
-// smallest register tile (64, 128 or SKEL square) that holds Ahat.
+// Pivots of every block: the elimination runs on the smallest register tile
+// (64, 128 or SKEL square) that holds Ahat.  rank_out / rank_task receive the
+// number of pivots; k_bdlr_ginv follows.
 template <typename T, int SKEL>
-__global__ void __launch_bounds__(kBlock)
+__global__ void __launch_bounds__(kLuBlock)
     k_bdlr_lu(const double* __restrict__ K, int ldk, const BdlrTask* __restrict__ tasks,
               const int* __restrict__ sel, const int* __restrict__ counts, T eps, int rcap,
-              int* __restrict__ piv_out, T* __restrict__ inv, int* __restrict__ rank_out,
-              int* __restrict__ rank_task) {
-  static_assert(SKEL % 64 == 0 && SKEL <= 256, "tile shape");
+              int* __restrict__ piv_out, int* __restrict__ rank_out, int* __restrict__ rank_task) {
+  static_assert(SKEL % 64 == 0 && SKEL <= 256 && SKEL % kLuWaves == 0, "tile shape");
   __shared__ int srow[SKEL], scol[SKEL], prow[SKEL], pcol[SKEL];
   __shared__ T colv[SKEL];
-  __shared__ GjScratch<T, (sizeof(T) == 8 ? kRankCap64 : kRankCap32)> gw;
-  __shared__ T sv[2][4], spiv;
-  __shared__ int si[2][4];
+  __shared__ T sv[2][kLuWaves], spiv;
+  __shared__ int si[2][kLuWaves];
   const int task = blockIdx.x, t = threadIdx.x;
   const BdlrTask tk = tasks[task];
   const int nr = counts[2 * task], nc = counts[2 * task + 1];
-  for (int x = t; x < SKEL; x += kBlock) {
+  for (int x = t; x < SKEL; x += blockDim.x) {
     srow[x] = x < nr ? sel[tk.sel_off + x] : 0;
     scol[x] = x < nc ? sel[tk.sel_off + SKEL + x] : 0;
   }
@@ -326,31 +334,61 @@ __global__ void __launch_bounds__(kBlock)
   const double* Kb = K + (size_t)tk.col0 * ldk + tk.row0;
   const int kmax = min(min(nr, nc), min(tk.kmax, rcap));
   const int side = max(nr, nc);
+  constexpr int NW = kLuWaves;
   int r;
   if (side <= 64)
-    r = full_pivot_steps<T, 1, 16>(Kb, ldk, srow, scol, nr, nc, kmax, eps, prow, pcol, colv, sv, si, &spiv);
+    r = full_pivot_steps<T, 1, 64 / NW, NW>(Kb, ldk, srow, scol, nr, nc, kmax, eps, prow, pcol, colv, sv, si, &spiv);
   else if (side <= 128 || SKEL <= 128)
-    r = full_pivot_steps<T, 2, 32>(Kb, ldk, srow, scol, nr, nc, kmax, eps, prow, pcol, colv, sv, si, &spiv);
+    r = full_pivot_steps<T, 2, 128 / NW, NW>(Kb, ldk, srow, scol, nr, nc, kmax, eps, prow, pcol, colv, sv, si,
+                                             &spiv);
   else
-    r = full_pivot_steps<T, SKEL / 64, SKEL / 4>(Kb, ldk, srow, scol, nr, nc, kmax, eps, prow, pcol, colv, sv,
-                                                 si, &spiv);
-  for (int q = t; q < r; q += kBlock) {
+    r = full_pivot_steps<T, SKEL / 64, SKEL / NW, NW>(Kb, ldk, srow, scol, nr, nc, kmax, eps, prow, pcol, colv, sv,
+                                                      si, &spiv);
+  __syncthreads();
+  for (int q = t; q < r; q += blockDim.x) {
     piv_out[tk.sel_off + q] = srow[prow[q]];         // picked rows in pivot order
     piv_out[tk.sel_off + SKEL + q] = scol[pcol[q]];  // picked columns in pivot order
   }
-  // G = Ahat11^-1 with Ahat11 = Ahat(pivot rows, pivot columns), read again
-  // from K; (L11 U11)^-1 = U11^-1 L11^-1, so C(:, pivot columns) G R(pivot
-  // rows, :) is the pseudo-skeleton C~ R~.
-  __syncthreads();
-  T* G = inv + tk.inv_off;  // r x r, ld r
-  const bool ok =
-      r == 0 || gj_invert([&](int i, int j) { return (T)Kb[(size_t)scol[pcol[j]] * ldk + srow[prow[i]]]; },
-                          r, G, r, gw);
   if (t == 0) {
-    const int rr = ok ? r : 0;  // a numerically singular Ahat11 drops the block
-    rank_out[tk.node] = rr;
-    rank_task[task] = rr;
+    rank_out[tk.node] = r;
+    rank_task[task] = r;
   }
+}
+
+// G = Ahat11^-1 with Ahat11 = Ahat(pivot rows, pivot columns), read again
+// from K; (L11 U11)^-1 = U11^-1 L11^-1, so C(:, pivot columns) G R(pivot
+// rows, :) is the pseudo-skeleton C~ R~.  A numerically singular Ahat11 drops
+// the block (rank 0).
+template <typename T, int SKEL>
+__global__ void __launch_bounds__(kBlock)
+    k_bdlr_ginv(const double* __restrict__ K, int ldk, const BdlrTask* __restrict__ tasks,
+                const int* __restrict__ piv, T* __restrict__ inv, int* __restrict__ rank_out,
+                int* __restrict__ rank_task) {
+  __shared__ GjScratch<T, (sizeof(T) == 8 ? kRankCap64 : kRankCap32)> gw;
+  const int task = blockIdx.x, t = threadIdx.x;
+  const BdlrTask tk = tasks[task];
+  const int r = rank_task[task];
+  if (r == 0) return;
+  const double* Kb = K + (size_t)tk.col0 * ldk + tk.row0;
+  const int* pr = piv + tk.sel_off;
+  const int* pc = piv + tk.sel_off + SKEL;
+  T* G = inv + tk.inv_off;  // r x r, ld r
+  const bool ok = gj_invert([&](int i, int j) { return (T)Kb[(size_t)pc[j] * ldk + pr[i]]; }, r, G, r, gw);
+  if (!ok && t == 0) {
+    rank_out[tk.node] = 0;
+    rank_task[task] = 0;
+  }
+}
+
+// The pivots, then G, of ns blocks.
+template <typename T, int SKEL>
+static int launch_bdlr_lu(const double* K, int ldk, const BdlrTask* tasks, int ns, const int* sel, const int* cnt,
+                          T eps, int rcap, int* piv, T* inv, int* rank_out, int* rank_task, hipStream_t s) {
+  k_bdlr_lu<T, SKEL><<<ns, kLuBlock, 0, s>>>(K, ldk, tasks, sel, cnt, eps, rcap, piv, rank_out, rank_task);
+  HODLR_HIP(hipGetLastError());
+  k_bdlr_ginv<T, SKEL><<<ns, kBlock, 0, s>>>(K, ldk, tasks, piv, inv, rank_out, rank_task);
+  HODLR_HIP(hipGetLastError());
+  return HODLR_OK;
 }
 
 // Gathers the panels: side 0: C(i, l) = K(row0 + i, pivot column l) into the
@@ -473,11 +511,10 @@ static int bdlr_t(hodlr_s* h, const double* K, int ldk, const int* rowptr, const
   const int rcap = h->precision == 64 ? kRankCap64 : kRankCap32;
   {
     ProfScope prof("bdlr_lu", s);
-    k_bdlr_lu<T, SKEL><<<nt, kBlock, 0, s>>>(K, ldk, d_tasks.as<BdlrTask>(), d_sel.as<int>(),
-                                              d_cnt.as<int>(), (T)h->tol, rcap, d_piv.as<int>(), d_inv.as<T>(),
-                                              h->d_rank.as<int>(), d_rt.as<int>());
+    HODLR_TRY((launch_bdlr_lu<T, SKEL>(K, ldk, d_tasks.as<BdlrTask>(), nt, d_sel.as<int>(), d_cnt.as<int>(),
+                                       (T)h->tol, rcap, d_piv.as<int>(), d_inv.as<T>(), h->d_rank.as<int>(),
+                                       d_rt.as<int>(), s)));
   }
-  HODLR_HIP(hipGetLastError());
   const int nch = (maxside + kBlock - 1) / kBlock;
   {
     ProfScope prof("bdlr_gather", s);
@@ -747,11 +784,10 @@ static int learned_t(hodlr_s* h, const double* K, int ldk, const int* rowptr, co
     HODLR_HIP(hipGetLastError());
     {
       ProfScope prof("bdlr_lu", s);
-      k_bdlr_lu<T, SKEL><<<ns, kBlock, 0, s>>>(K, ldk, d_tasks.as<BdlrTask>(), d_sel.as<int>(), d_cnt.as<int>(),
-                                               (T)h->tol, rcap, d_piv.as<int>(), d_inv.as<T>(), h->d_rank.as<int>(),
-                                               d_rt.as<int>());
+      HODLR_TRY((launch_bdlr_lu<T, SKEL>(K, ldk, d_tasks.as<BdlrTask>(), ns, d_sel.as<int>(), d_cnt.as<int>(),
+                                         (T)h->tol, rcap, d_piv.as<int>(), d_inv.as<T>(), h->d_rank.as<int>(),
+                                         d_rt.as<int>(), s)));
     }
-    HODLR_HIP(hipGetLastError());
     const int nch = (maxside + kBlock - 1) / kBlock;
     {
       ProfScope prof("bdlr_gather", s);
