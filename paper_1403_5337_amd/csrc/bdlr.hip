@@ -428,18 +428,92 @@ __global__ void __launch_bounds__(kBlock)
 }
 
 // U(rows of I) = C G, 256 rows per workgroup.
+// U(rows of the block, 0:r) = C G, one 64 x 64 tile of U per workgroup
+// (blockIdx.y: row tile, blockIdx.z: column tile), on the matrix cores: each
+// wave owns a 32 x 32 quarter.  The tile's 64 rows of C (all r columns) and
+// 64 columns of G go to LDS in one round of asynchronous copies; the inner
+// dimension is padded with zeros to the MFMA depth.
+template <typename T> constexpr int mfma_depth() { return sizeof(T) == 4 ? 2 : 4; }
+template <typename T> constexpr int factors_kmax() { return sizeof(T) == 4 ? kRankCap32 : kRankCap64; }
+
+template <typename T>
+struct FactorsSmem {
+  static constexpr int kK = (factors_kmax<T>() + 3) / 4 * 4;  // padded inner dimension
+  static constexpr int kLdA = 65, kLdB = kK + 1;
+  T A[kK * kLdA];   // C(i0 + i, k) at A[k kLdA + i]
+  T B[64 * kLdB];   // G(k, j0 + j) at B[j kLdB + k]
+};
+
+typedef float f32x16 __attribute__((ext_vector_type(16)));
+typedef double f64x4 __attribute__((ext_vector_type(4)));
+
 template <typename T>
 __global__ void __launch_bounds__(kBlock)
     k_bdlr_factors(const BdlrTask* __restrict__ tasks, const int* __restrict__ rank_task,
                    const T* __restrict__ cg, const T* __restrict__ inv, T* __restrict__ Ucap, int ldu) {
-  __shared__ T As[32 * 33], Bs[32 * 33];
-  const int task = blockIdx.x;
+  using S = FactorsSmem<T>;
+  __shared__ S sm;
+  const int task = blockIdx.x, t = threadIdx.x, lane = t & 63, w = t >> 6;
   const BdlrTask tk = tasks[task];
   const int r = rank_task[task];
-  const int i0 = blockIdx.y * 256, rn = min(256, tk.m - i0);
-  if (rn <= 0 || r == 0) return;
-  wg_gemm(rn, r, r, T(1), cg + tk.cg_off + i0, tk.m, inv + tk.inv_off, r, T(0),
-          Ucap + tk.row0 + i0 + (size_t)tk.capcol * ldu, ldu, As, Bs);
+  const int i0 = blockIdx.y * 64, j0 = blockIdx.z * 64;
+  const int rn = min(64, tk.m - i0), cn = min(64, r - j0);
+  if (rn <= 0 || cn <= 0) return;
+  constexpr int D = mfma_depth<T>();
+  const int kp = (r + D - 1) / D * D;
+  // zero the padding of the inner dimension
+  for (int e = t; e < (kp - r) * 64; e += kBlock) {
+    const int k = r + e / 64, i = e % 64;
+    sm.A[k * S::kLdA + i] = T(0);
+    sm.B[i * S::kLdB + k] = T(0);
+  }
+  const T* C = cg + tk.cg_off + i0;  // column k at C + k m
+  const T* G = inv + tk.inv_off + (size_t)j0 * r;
+  for (int k = w; k < r; k += kBlock / 64) dma_span(sm.A + k * S::kLdA, C + (size_t)k * tk.m, rn);
+  for (int j = w; j < cn; j += kBlock / 64) dma_span(sm.B + j * S::kLdB, G + (size_t)j * r, r);
+  dma_wait();
+  const int wm = (w & 1) * 32, wn = (w >> 1) * 32;
+  T* U = Ucap + tk.row0 + i0 + (size_t)(tk.capcol + j0) * ldu;
+  if constexpr (sizeof(T) == 4) {
+    f32x16 acc = {};
+    const int am = wm + (lane & 31), bn = wn + (lane & 31), kl = lane >> 5;
+    for (int k = 0; k < kp; k += 2) {
+      const float a = sm.A[(k + kl) * S::kLdA + am];
+      const float b = sm.B[bn * S::kLdB + k + kl];
+      acc = __builtin_amdgcn_mfma_f32_32x32x2f32(a, b, acc, 0, 0, 0);
+    }
+    // D(v) at lane l: row 8 (v / 4) + 4 (l / 32) + v % 4, column l % 32
+#pragma unroll
+    for (int v = 0; v < 16; ++v) {
+      const int i = wm + 8 * (v >> 2) + 4 * (lane >> 5) + (v & 3), j = wn + (lane & 31);
+      if (i < rn && j < cn) U[i + (size_t)j * ldu] = acc[v];
+    }
+  } else {
+    f64x4 acc[2][2] = {};
+    const int ml = lane & 15, kl = lane >> 4;
+    for (int k = 0; k < kp; k += 4) {
+      double a[2], b[2];
+#pragma unroll
+      for (int x = 0; x < 2; ++x) {
+        a[x] = sm.A[(k + kl) * S::kLdA + wm + 16 * x + ml];
+        b[x] = sm.B[(wn + 16 * x + ml) * S::kLdB + k + kl];
+      }
+#pragma unroll
+      for (int x = 0; x < 2; ++x)
+#pragma unroll
+        for (int y = 0; y < 2; ++y) acc[x][y] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[x], b[y], acc[x][y], 0, 0, 0);
+    }
+    // D(v) at lane l: row l / 16 + 4 v, column l % 16
+#pragma unroll
+    for (int x = 0; x < 2; ++x)
+#pragma unroll
+      for (int y = 0; y < 2; ++y)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int i = wm + 16 * x + (lane >> 4) + 4 * v, j = wn + 16 * y + (lane & 15);
+          if (i < rn && j < cn) U[i + (size_t)j * ldu] = acc[x][y][v];
+        }
+  }
 }
 
 // One task per node below the root, in level order (level 1 left to right,
@@ -524,8 +598,8 @@ static int bdlr_t(hodlr_s* h, const double* K, int ldk, const int* rowptr, const
   HODLR_HIP(hipGetLastError());
   {
     ProfScope prof("bdlr_factors", s);
-    k_bdlr_factors<T><<<dim3(nt, nch, 1), kBlock, 0, s>>>(d_tasks.as<BdlrTask>(), d_rt.as<int>(), d_cg.as<T>(),
-                                                          d_inv.as<T>(), Ucap, tr.n);
+    k_bdlr_factors<T><<<dim3(nt, (maxside + 63) / 64, (rcap + 63) / 64), kBlock, 0, s>>>(
+        d_tasks.as<BdlrTask>(), d_rt.as<int>(), d_cg.as<T>(), d_inv.as<T>(), Ucap, tr.n);
   }
   HODLR_HIP(hipGetLastError());
   if (piv_export)
@@ -793,8 +867,8 @@ static int learned_t(hodlr_s* h, const double* K, int ldk, const int* rowptr, co
       ProfScope prof("bdlr_gather", s);
       k_bdlr_gather<T, SKEL><<<dim3(ns, nch, 2), kBlock, 0, s>>>(K, ldk, d_tasks.as<BdlrTask>(), d_piv.as<int>(),
                                                                 d_rt.as<int>(), d_cg.as<T>(), Vcap, tr.n);
-      k_bdlr_factors<T><<<dim3(ns, nch, 1), kBlock, 0, s>>>(d_tasks.as<BdlrTask>(), d_rt.as<int>(), d_cg.as<T>(),
-                                                            d_inv.as<T>(), Ucap, tr.n);
+      k_bdlr_factors<T><<<dim3(ns, (maxside + 63) / 64, (rcap + 63) / 64), kBlock, 0, s>>>(
+          d_tasks.as<BdlrTask>(), d_rt.as<int>(), d_cg.as<T>(), d_inv.as<T>(), Ucap, tr.n);
     }
     HODLR_HIP(hipGetLastError());
     // the picks come back to draw the samples outside them

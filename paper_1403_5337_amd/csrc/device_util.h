@@ -65,6 +65,30 @@ template <typename T> __device__ T block_sum(T v, T* sv) {
 }
 
 // ---------------------------------------------------------------------------
+// Asynchronous global-to-LDS copies: each wave instruction moves 64 dwords
+// (lane l takes dword l) to consecutive LDS addresses from a wave-uniform
+// base.  They complete at dma_wait().
+// ---------------------------------------------------------------------------
+typedef __attribute__((address_space(1))) const void* gptr_t;
+typedef __attribute__((address_space(3))) void* lptr_t;
+
+// The calling wave copies count contiguous elements from src to LDS dst.
+template <typename T>
+__device__ __forceinline__ void dma_span(T* dst, const T* __restrict__ src, int count) {
+  const int lane = threadIdx.x & 63;
+  const int nd = count * (int)(sizeof(T) / 4);
+  for (int d0 = 0; d0 < nd; d0 += 64)
+    if (d0 + lane < nd)
+      __builtin_amdgcn_global_load_lds((gptr_t)(reinterpret_cast<const char*>(src) + 4 * (d0 + lane)),
+                                       (lptr_t)(reinterpret_cast<char*>(dst) + 4 * d0), 4, 0, 0);
+}
+
+__device__ __forceinline__ void dma_wait() {
+  __builtin_amdgcn_s_waitcnt(0);
+  __syncthreads();
+}
+
+// ---------------------------------------------------------------------------
 // Cross-lane moves inside a wavefront through DPP (no LDS round trip).
 // ---------------------------------------------------------------------------
 template <int CTRL> __device__ __forceinline__ int dpp_move(int v) {
@@ -379,65 +403,6 @@ __device__ bool gj_invert(Load load, int n, T* out, int ldo, GjScratch<T, NMAX>&
     out[s.pinv[i] + (size_t)s.prow[j] * ldo] = s.X[j * ld + i];
   }
   return true;
-}
-
-// C = alpha * A * B + beta * C for column-major operands (any address space)
-// computed by the whole workgroup through 32 x 32 LDS tiles.  As, Bs: LDS,
-// 32 * 33 elements each.  beta == 0 does not read C.  C must not alias A, B.
-template <typename T>
-__device__ void wg_gemm(int m, int n, int k, T alpha, const T* A, int lda, const T* B, int ldb, T beta,
-                        T* C, int ldc, T* As, T* Bs) {
-  const int t = threadIdx.x, nt = blockDim.x, tx = t & 15, ty = (t >> 4) & 15;
-  const bool active = t < 256;
-  for (int i0 = 0; i0 < m; i0 += 32)
-    for (int j0 = 0; j0 < n; j0 += 32) {
-      T acc[2][2] = {{T(0), T(0)}, {T(0), T(0)}};
-      for (int k0 = 0; k0 < k; k0 += 32) {
-        // all loads of the two tiles are issued before any is stored
-        T av[4], bv[4];
-#pragma unroll
-        for (int u = 0; u < 4; ++u) {
-          const int e = t + u * 256;
-          const int ii = e & 31, kk = e >> 5;
-          av[u] = (e < 1024 && i0 + ii < m && k0 + kk < k) ? A[(i0 + ii) + (size_t)(k0 + kk) * lda] : T(0);
-          bv[u] = (e < 1024 && k0 + ii < k && j0 + kk < n) ? B[(k0 + ii) + (size_t)(j0 + kk) * ldb] : T(0);
-        }
-#pragma unroll
-        for (int u = 0; u < 4; ++u) {
-          const int e = t + u * 256;
-          if (e < 1024 && t < 256) {
-            As[(e >> 5) * 33 + (e & 31)] = av[u];
-            Bs[(e >> 5) * 33 + (e & 31)] = bv[u];
-          }
-        }
-        __syncthreads();
-        if (active) {
-#pragma unroll 8
-          for (int kk = 0; kk < 32; ++kk) {
-            const T a0 = As[kk * 33 + tx], a1 = As[kk * 33 + tx + 16];
-            const T b0 = Bs[ty * 33 + kk], b1 = Bs[(ty + 16) * 33 + kk];
-            acc[0][0] += a0 * b0;
-            acc[0][1] += a0 * b1;
-            acc[1][0] += a1 * b0;
-            acc[1][1] += a1 * b1;
-          }
-        }
-        __syncthreads();
-      }
-      if (active) {
-#pragma unroll
-        for (int a = 0; a < 2; ++a)
-#pragma unroll
-          for (int c = 0; c < 2; ++c) {
-            const int i = i0 + tx + 16 * a, j = j0 + ty + 16 * c;
-            if (i < m && j < n) {
-              T* cp = C + i + (size_t)j * ldc;
-              *cp = (beta == T(0) ? T(0) : beta * *cp) + alpha * acc[a][c];
-            }
-          }
-      }
-      __syncthreads();
-    }
 }
 
 }  // namespace hodlr

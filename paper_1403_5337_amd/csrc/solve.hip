@@ -49,9 +49,6 @@ struct SolveSmem {
   alignas(16) T xs[kRows * SM];                 // x of the unit (i x SM)
 };
 
-typedef __attribute__((address_space(1))) const void* gptr_t;
-typedef __attribute__((address_space(3))) void* lptr_t;
-
 // Asynchronous copy of columns [0, cn) of a 64-row column-major panel (first
 // row at src, leading dimension ld; rows >= rn are not read) into LDS columns
 // dst + c * ldl.  One wave instruction moves 256 bytes of one column; the
@@ -69,11 +66,6 @@ __device__ __forceinline__ void dma_columns(T* dst, int ldl, const T* __restrict
       __builtin_amdgcn_global_load_lds((gptr_t)g, (lptr_t)(dst + c * ldl + p * kRowsPart), 4, 0, 0);
     }
   }
-}
-
-__device__ __forceinline__ void dma_wait() {
-  __builtin_amdgcn_s_waitcnt(0);
-  __syncthreads();
 }
 
 // Stage operand columns [j0, j0 + jn) of the stream "A columns 0..ra-1, then
