@@ -30,9 +30,70 @@ struct TaskDev {
   int tile0;
 };
 
-// C tile (64 x 64) = alpha op(A) B over k in [kb, ke); thread (tx, ty) owns
-// rows tx + 16 u and columns ty + 16 v.  The next K chunk is loaded into
-// registers while the current one is multiplied out of LDS.
+typedef float f32x16 __attribute__((ext_vector_type(16)));
+typedef double f64x4 __attribute__((ext_vector_type(4)));
+
+// A wave's 32 x 32 accumulator on the matrix cores.  step() multiplies the
+// LDS chunks A(k, i) = As[k ld + i] and B(k, j) = Bs[k ld + j] (k < KC) into
+// rows wm.., columns wn.. of the tile; coord() names the (row, column) within
+// the quarter of accumulator slot q of a lane.
+template <typename T> struct MfmaAcc;
+
+template <> struct MfmaAcc<float> {
+  static constexpr int kN = 16;
+  f32x16 d;
+  __device__ void zero() { d = f32x16{}; }
+  template <int KC>
+  __device__ __forceinline__ void step(const float* As, const float* Bs, int ld, int wm, int wn, int lane) {
+    const int ml = lane & 31, kl = lane >> 5;
+#pragma unroll
+    for (int k = 0; k < KC; k += 2)  // v_mfma_f32_32x32x2f32: A(m = l % 32, k = l / 32), B(k = l / 32, n = l % 32)
+      d = __builtin_amdgcn_mfma_f32_32x32x2f32(As[(k + kl) * ld + wm + ml], Bs[(k + kl) * ld + wn + ml], d, 0, 0, 0);
+  }
+  // slot q of lane l: row 8 (q / 4) + 4 (l / 32) + q % 4, column l % 32
+  __device__ static void coord(int q, int lane, int& i, int& j) {
+    i = 8 * (q >> 2) + 4 * (lane >> 5) + (q & 3);
+    j = lane & 31;
+  }
+  __device__ float get(int q) const { return d[q]; }
+};
+
+template <> struct MfmaAcc<double> {
+  static constexpr int kN = 16;
+  f64x4 d[2][2];
+  __device__ void zero() {
+    for (int x = 0; x < 2; ++x)
+      for (int y = 0; y < 2; ++y) d[x][y] = f64x4{};
+  }
+  template <int KC>
+  __device__ __forceinline__ void step(const double* As, const double* Bs, int ld, int wm, int wn, int lane) {
+    const int ml = lane & 15, kl = lane >> 4;
+#pragma unroll
+    for (int k = 0; k < KC; k += 4) {  // v_mfma_f64_16x16x4f64: A(m = l % 16, k = l / 16), B(k = l / 16, n = l % 16)
+      double a[2], b[2];
+#pragma unroll
+      for (int x = 0; x < 2; ++x) {
+        a[x] = As[(k + kl) * ld + wm + 16 * x + ml];
+        b[x] = Bs[(k + kl) * ld + wn + 16 * x + ml];
+      }
+#pragma unroll
+      for (int x = 0; x < 2; ++x)
+#pragma unroll
+        for (int y = 0; y < 2; ++y) d[x][y] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[x], b[y], d[x][y], 0, 0, 0);
+    }
+  }
+  // slot q = 8 x + 4 y + v of lane l: block (x, y), row l / 16 + 4 v, column l % 16
+  __device__ static void coord(int q, int lane, int& i, int& j) {
+    const int x = q >> 3, y = (q >> 2) & 1, v = q & 3;
+    i = 16 * x + (lane >> 4) + 4 * v;
+    j = 16 * y + (lane & 15);
+  }
+  __device__ double get(int q) const { return d[q >> 3][(q >> 2) & 1][q & 3]; }
+};
+
+// C tile (64 x 64) = alpha op(A) B over k in [kb, ke), each wave a 32 x 32
+// quarter on the matrix cores.  The next K chunk is loaded into registers
+// while the current one is multiplied out of LDS.
 template <typename T>
 __global__ void __launch_bounds__(kBlock)
     k_gemm_batched(const TaskDev* __restrict__ tasks, int ntask) {
@@ -40,7 +101,7 @@ __global__ void __launch_bounds__(kBlock)
   __shared__ T As[2][KC][kTile + 1];
   __shared__ T Bs[2][KC][kTile + 1];
   __shared__ int s_task;
-  const int t = threadIdx.x, tx = t & 15, ty = t >> 4;
+  const int t = threadIdx.x;
   if (t == 0) {
     int lo = 0, hi = ntask - 1;
     while (lo < hi) {  // last task with tile0 <= blockIdx.x
@@ -88,11 +149,10 @@ __global__ void __launch_bounds__(kBlock)
       Bs[buf][e % KC][e / KC] = bv[u];
     }
   };
-  T acc[4][4];
-#pragma unroll
-  for (int u = 0; u < 4; ++u)
-#pragma unroll
-    for (int v = 0; v < 4; ++v) acc[u][v] = T(0);
+  // each wave owns a 32 x 32 quarter of the tile, on the matrix cores
+  const int lane = t & 63, wv = t >> 6, wm = (wv & 1) * 32, wn = (wv >> 1) * 32;
+  MfmaAcc<T> acc;
+  acc.zero();
   int buf = 0;
   if (kb < ke) {
     load(kb);
@@ -102,40 +162,24 @@ __global__ void __launch_bounds__(kBlock)
   for (int k0 = kb; k0 < ke; k0 += KC) {
     const bool more = k0 + KC < ke;
     if (more) load(k0 + KC);
-#pragma unroll 8
-    for (int kk = 0; kk < KC; ++kk) {
-      T a[4], b[4];
-#pragma unroll
-      for (int u = 0; u < 4; ++u) {
-        a[u] = As[buf][kk][tx + 16 * u];
-        b[u] = Bs[buf][kk][ty + 16 * u];
-      }
-#pragma unroll
-      for (int u = 0; u < 4; ++u)
-#pragma unroll
-        for (int v = 0; v < 4; ++v) acc[u][v] = fma(a[u], b[v], acc[u][v]);
-    }
+    acc.template step<KC>(&As[buf][0][0], &Bs[buf][0][0], kTile + 1, wm, wn, lane);
     if (more) store(buf ^ 1);
     __syncthreads();
     buf ^= 1;
   }
   const T alpha = (T)tk.alpha;
-#pragma unroll
-  for (int v = 0; v < 4; ++v) {
-    const int j = j0 + ty + 16 * v;
-    if (j >= tk.n) continue;
-#pragma unroll
-    for (int u = 0; u < 4; ++u) {
-      const int i = i0 + tx + 16 * u;
-      if (i >= tk.m) continue;
-      T* cp = C + i + (size_t)j * tk.ldc;
-      T val = alpha * acc[u][v];
-      if (tk.ksplit == 1) {
-        if (tk.mode == kGemmAccumulate) val += *cp;
-        else if (tk.mode == kGemmAddIdentity && i == j) val += T(1);
-      }
-      *cp = val;
+  for (int q = 0; q < MfmaAcc<T>::kN; ++q) {
+    int ii, jj;
+    MfmaAcc<T>::coord(q, lane, ii, jj);
+    const int i = i0 + wm + ii, j = j0 + wn + jj;
+    if (i >= tk.m || j >= tk.n) continue;
+    T* cp = C + i + (size_t)j * tk.ldc;
+    T val = alpha * acc.get(q);
+    if (tk.ksplit == 1) {
+      if (tk.mode == kGemmAccumulate) val += *cp;
+      else if (tk.mode == kGemmAddIdentity && i == j) val += T(1);
     }
+    *cp = val;
   }
 }
 

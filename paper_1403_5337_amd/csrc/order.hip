@@ -6,8 +6,9 @@
 // from the root down, its dofs are sorted by the coordinate of largest
 // extent (first axis on ties; equal keys keep their current order) and the
 // left child takes the first floor(len/2).  One workgroup sorts one node with
-// a bitonic sort of (key, position) pairs in LDS, which is stable by
-// construction because positions break ties.
+// a bitonic sort of (key, position) pairs, which is stable by construction
+// because positions break ties; the pairs stay in registers except for the
+// strides that cross waves.
 #include <algorithm>
 #include <cfloat>
 #include <climits>
@@ -20,19 +21,111 @@ namespace hodlr {
 constexpr int kRcbMax = 16384;
 constexpr int kRcbThreads = 1024;
 
+// (k, p) becomes the smaller (take_min) or the larger of itself and (ko, po)
+// in the order "key, then position".
+__device__ __forceinline__ void rcb_pick(float& k, int& p, float ko, int po, bool take_min) {
+  const bool o_less = (ko < k) | ((ko == k) & (po < p));
+  const bool take = take_min ? o_less : !o_less;
+  k = take ? ko : k;
+  p = take ? po : p;
+}
+
+// Bitonic sort of P (a power of two, <= 1024 E) (key, position) pairs held
+// E per thread: element e = t E + r.  Strides below E stay in registers,
+// strides below 64 E pair lanes of one wave, larger strides go through LDS.
+template <int E>
+__device__ void rcb_sort(float (&key)[E], int (&pos)[E], int P, float* skey, int* spos) {
+  const int t = threadIdx.x;
+  const bool live = t * E < P;
+  for (int k = 2; k <= P; k <<= 1) {
+    for (int j = k >> 1; j > 0; j >>= 1) {
+      if (j < E) {
+#pragma unroll
+        for (int jj = E / 2; jj >= 1; jj >>= 1) {
+          if (jj != j) continue;
+#pragma unroll
+          for (int r = 0; r < E; ++r) {
+            const int rr = r ^ jj;
+            if (rr < r) continue;
+            const bool up = (((t * E + r) & k) == 0);
+            const float ka = key[r], kb = key[rr];
+            const int pa = pos[r], pb = pos[rr];
+            const bool a_gt_b = (ka > kb) | ((ka == kb) & (pa > pb));
+            if (a_gt_b == up) {
+              key[r] = kb;
+              key[rr] = ka;
+              pos[r] = pb;
+              pos[rr] = pa;
+            }
+          }
+        }
+      } else if (j < 64 * E) {
+        const int m = j / E;  // partner lane: t ^ m
+        const bool lower = (t & m) == 0;
+#pragma unroll
+        for (int r = 0; r < E; ++r) {
+          const float ko = __shfl_xor(key[r], m, 64);
+          const int po = __shfl_xor(pos[r], m, 64);
+          const bool up = (((t * E + r) & k) == 0);
+          rcb_pick(key[r], pos[r], ko, po, lower == up);
+        }
+      } else {
+        if (live)
+#pragma unroll
+          for (int r = 0; r < E; ++r) {
+            skey[t * E + r] = key[r];
+            spos[t * E + r] = pos[r];
+          }
+        __syncthreads();
+        if (live)
+#pragma unroll
+          for (int r = 0; r < E; ++r) {
+            const int e = t * E + r, x = e ^ j;
+            const bool up = ((e & k) == 0);
+            rcb_pick(key[r], pos[r], skey[x], spos[x], ((e & j) == 0) == up);
+          }
+        __syncthreads();
+      }
+    }
+  }
+}
+
+template <int E>
+__device__ void rcb_node(const float* __restrict__ coords, int* __restrict__ perm, int l0, int len, int P,
+                         int ax, float* skey, int* spos) {
+  const int t = threadIdx.x;
+  float key[E];
+  int pos[E];
+#pragma unroll
+  for (int r = 0; r < E; ++r) {
+    const int e = t * E + r;
+    pos[r] = e < len ? e : INT_MAX;
+    key[r] = e < len ? coords[3 * (size_t)perm[l0 + e] + ax] : INFINITY;
+  }
+  rcb_sort<E>(key, pos, P, skey, spos);
+  // perm(l0 + e) <- perm(l0 + pos(e)); the old entries go through LDS
+  int* old = spos;
+  for (int e = t; e < len; e += blockDim.x) old[e] = perm[l0 + e];
+  __syncthreads();
+#pragma unroll
+  for (int r = 0; r < E; ++r) {
+    const int e = t * E + r;
+    if (e < len && pos[r] < len) perm[l0 + e] = old[pos[r]];
+  }
+}
+
 __global__ void __launch_bounds__(kRcbThreads)
     k_rcb_level(const float* __restrict__ coords, int* __restrict__ perm, const int* __restrict__ lo,
                 const int* __restrict__ hi, int id0) {
-  extern __shared__ __align__(16) unsigned char smem[];
+  __shared__ float skey[kRcbMax];
+  __shared__ int spos[kRcbMax];
+  __shared__ float red[6][kRcbThreads / 64];
+  __shared__ int s_axis;
   const int node = blockIdx.x, id = id0 + node, t = threadIdx.x, nt = blockDim.x;
   const int l0 = lo[id], len = hi[id] - l0;
   if (len <= 1) return;
   int P = 1;
   while (P < len) P <<= 1;
-  float* key = reinterpret_cast<float*>(smem);
-  int* pos = reinterpret_cast<int*>(key + kRcbMax);
-  __shared__ float red[6][kRcbThreads / 64];
-  __shared__ int s_axis;
   float mn[3] = {FLT_MAX, FLT_MAX, FLT_MAX}, mx[3] = {-FLT_MAX, -FLT_MAX, -FLT_MAX};
   for (int e = t; e < len; e += nt) {
     const int v = perm[l0 + e];
@@ -73,40 +166,11 @@ __global__ void __launch_bounds__(kRcbThreads)
   }
   __syncthreads();
   const int ax = s_axis;
-  for (int e = t; e < P; e += nt) {
-    if (e < len) {
-      key[e] = coords[3 * (size_t)perm[l0 + e] + ax];
-      pos[e] = e;
-    } else {
-      key[e] = INFINITY;
-      pos[e] = INT_MAX;
-    }
-  }
-  __syncthreads();
-  for (int k = 2; k <= P; k <<= 1) {
-    for (int j = k >> 1; j > 0; j >>= 1) {
-      for (int e = t; e < P; e += nt) {
-        const int x = e ^ j;
-        if (x > e) {
-          const float ka = key[e], kb = key[x];
-          const int pa = pos[e], pb = pos[x];
-          const bool a_gt_b = (ka > kb) || (ka == kb && pa > pb);
-          const bool up = (e & k) == 0;
-          if (a_gt_b == up) {
-            key[e] = kb;
-            key[x] = ka;
-            pos[e] = pb;
-            pos[x] = pa;
-          }
-        }
-      }
-      __syncthreads();
-    }
-  }
-  int* old = reinterpret_cast<int*>(key);  // keys are no longer needed
-  for (int e = t; e < len; e += nt) old[e] = perm[l0 + e];
-  __syncthreads();
-  for (int e = t; e < len; e += nt) perm[l0 + e] = old[pos[e]];
+  if (P <= kRcbThreads) rcb_node<1>(coords, perm, l0, len, P, ax, skey, spos);
+  else if (P <= 2 * kRcbThreads) rcb_node<2>(coords, perm, l0, len, P, ax, skey, spos);
+  else if (P <= 4 * kRcbThreads) rcb_node<4>(coords, perm, l0, len, P, ax, skey, spos);
+  else if (P <= 8 * kRcbThreads) rcb_node<8>(coords, perm, l0, len, P, ax, skey, spos);
+  else rcb_node<16>(coords, perm, l0, len, P, ax, skey, spos);
 }
 
 __global__ void k_iota(int* p, int n) {
@@ -124,12 +188,8 @@ int launch_rcb(const float* coords, int n, const Tree& t, int* perm, hipStream_t
   HODLR_TRY(dhi.ensure(nn * sizeof(int)));
   HODLR_HIP(hipMemcpyAsync(dlo.p, t.lo.data(), nn * sizeof(int), hipMemcpyHostToDevice, s));
   HODLR_HIP(hipMemcpyAsync(dhi.p, t.hi.data(), nn * sizeof(int), hipMemcpyHostToDevice, s));
-  const size_t lds = (size_t)kRcbMax * (sizeof(float) + sizeof(int));
-  HODLR_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(k_rcb_level),
-                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
   for (int p = 0; p < t.L; ++p) {
-    k_rcb_level<<<1 << p, kRcbThreads, lds, s>>>(coords, perm, dlo.as<int>(), dhi.as<int>(),
-                                                 node_id(p, 0));
+    k_rcb_level<<<1 << p, kRcbThreads, 0, s>>>(coords, perm, dlo.as<int>(), dhi.as<int>(), node_id(p, 0));
     HODLR_HIP(hipGetLastError());
   }
   HODLR_HIP(hipStreamSynchronize(s));  // dlo/dhi are released on return
@@ -146,9 +206,49 @@ __global__ void k_permute(const double* __restrict__ Kin, int n, int ldi, const 
   Kout[(size_t)j * ldo + i] = Kin[(size_t)pj * ldi + perm[i]];
 }
 
+// Column j of the output through LDS: input column perm[j] arrives with
+// contiguous asynchronous copies, rows are gathered inside LDS, and the
+// output column is written contiguously (n <= kPermLds).
+constexpr int kPermLds = 16384;
+
+__global__ void __launch_bounds__(kBlock)
+    k_permute_lds(const double* __restrict__ Kin, int n, int ldi, const int* __restrict__ perm,
+                  double* __restrict__ Kout, int ldo) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  double* col = reinterpret_cast<double*>(smem);
+  const int j = blockIdx.x, t = threadIdx.x, w = t >> 6, nw = blockDim.x >> 6;
+  const double* src = Kin + (size_t)perm[j] * ldi;
+  const int part = (n + nw - 1) / nw;
+  const int c0 = min(n, w * part), c1 = min(n, c0 + part);
+  dma_span(col + c0, src + c0, c1 - c0);
+  dma_wait();
+  double* dst = Kout + (size_t)j * ldo;
+  for (int i0 = 0; i0 < n; i0 += 4 * kBlock) {
+    int p[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int i = i0 + t + u * kBlock;
+      p[u] = i < n ? perm[i] : 0;
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int i = i0 + t + u * kBlock;
+      if (i < n) dst[i] = col[p[u]];
+    }
+  }
+}
+
 int launch_permute(const double* Kin, int n, int ldi, const int* perm, double* Kout, int ldo,
                    hipStream_t s) {
-  k_permute<<<dim3((n + kBlock - 1) / kBlock, n), kBlock, 0, s>>>(Kin, n, ldi, perm, Kout, ldo);
+  if (n <= kPermLds) {
+    const size_t lds = (size_t)n * sizeof(double);
+    if (lds > 64 * 1024)
+      HODLR_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(k_permute_lds),
+                                    hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+    k_permute_lds<<<n, kBlock, lds, s>>>(Kin, n, ldi, perm, Kout, ldo);
+  } else {
+    k_permute<<<dim3((n + kBlock - 1) / kBlock, n), kBlock, 0, s>>>(Kin, n, ldi, perm, Kout, ldo);
+  }
   HODLR_HIP(hipGetLastError());
   return HODLR_OK;
 }
