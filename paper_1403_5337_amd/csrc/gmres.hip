@@ -28,43 +28,69 @@ constexpr int kRowsPerWG = 256;
 constexpr int kMatvecCols = 128;  // columns of K per workgroup (split-K)
 constexpr int kMaxRestart = 512;
 
-// part[(sp s + k) n + i] = sum over the columns c of split sp of K(i, c) src(c, k)
-template <typename TZ, int SMAX>
+// part[(sp s + k) n + i] = sum over the columns c of split sp of K(i, c)
+// src(c, k), with the matrix cores doing the multiply-adds.  Wave w of
+// workgroup (x, sp) takes rows 64 x + 16 w .. + 16 and the 128 columns of
+// split sp; its 32 loads of K (one 16 x 4 block each, 128 contiguous bytes
+// per column) are all in flight at once, z (as float64, zero-padded to 16 NB
+// columns) comes from LDS, and v_mfma_f64_16x16x4f64 accumulates the
+// 16 x 16 NB block.  The product stays bound by the K traffic; the matrix
+// cores only keep the instruction count per byte low.
+typedef double f64x4 __attribute__((ext_vector_type(4)));
+
+template <typename TZ, int NB>
 __global__ void __launch_bounds__(kRowsPerWG)
-    k_matvec(const double* __restrict__ K, int ldk, int n, const TZ* __restrict__ src, int lds, int s,
-             double* __restrict__ part) {
-  __shared__ double zs[kMatvecCols * SMAX];
-  const int t = threadIdx.x, sp = blockIdx.y;
+    k_matvec_mfma(const double* __restrict__ K, int ldk, int n, const TZ* __restrict__ src, int lds, int s,
+                  double* __restrict__ part) {
+  constexpr int kQ = kMatvecCols / 4;
+  __shared__ double zs[kMatvecCols * 16 * NB];  // z(c, k) at zs[c 16 NB + k]
+  const int t = threadIdx.x, lane = t & 63, w = t >> 6, sp = blockIdx.y;
   const int c0 = sp * kMatvecCols, cn = min(kMatvecCols, n - c0);
-  for (int e = t; e < cn * s; e += blockDim.x) {
-    const int c = e % cn, k = e / cn;
-    zs[c * SMAX + k] = (double)src[(size_t)k * lds + c0 + c];
+  const int m = lane & 15, kl = lane >> 4;
+  const int row = blockIdx.x * 64 + 16 * w + m;
+  // z first: its loads precede those of K in the (in-order) load queue, so
+  // staging it waits for z alone, and the products below start on the first
+  // blocks of K while the later ones are still arriving
+  constexpr int kZ = kMatvecCols * 16 * NB / kRowsPerWG;
+  double zv[kZ];
+  // (addresses are clamped into range so that no load sits behind a branch;
+  // the entries outside become zero afterwards)
+#pragma unroll
+  for (int u = 0; u < kZ; ++u) {
+    const int e = t + u * kRowsPerWG, c = e / (16 * NB), k = e % (16 * NB);
+    zv[u] = (double)src[(size_t)min(k, s - 1) * lds + c0 + min(c, cn - 1)];
+  }
+  double a[kQ];
+  const int rowc = min(row, n - 1);
+#pragma unroll
+  for (int q = 0; q < kQ; ++q) {
+    const int c = min(4 * q + kl, cn - 1);
+    a[q] = __builtin_nontemporal_load(K + (size_t)(c0 + c) * ldk + rowc);
+  }
+  __builtin_amdgcn_sched_barrier(0);  // every load is issued before the wait for z
+#pragma unroll
+  for (int u = 0; u < kZ; ++u) {
+    const int e = t + u * kRowsPerWG, c = e / (16 * NB), k = e % (16 * NB);
+    zs[e] = (c < cn && k < s) ? zv[u] : 0.0;
   }
   __syncthreads();
-  const int i = blockIdx.x * kRowsPerWG + t;
-  if (i >= n) return;
-  double acc[SMAX];
+  f64x4 acc[NB];
 #pragma unroll
-  for (int k = 0; k < SMAX; ++k) acc[k] = 0.0;
-  const double* Kc = K + (size_t)c0 * ldk + i;
-  int c = 0;
-  for (; c + 8 <= cn; c += 8) {
-    double a[8];
+  for (int b = 0; b < NB; ++b) acc[b] = f64x4{};
 #pragma unroll
-    for (int u = 0; u < 8; ++u) a[u] = __builtin_nontemporal_load(Kc + (size_t)(c + u) * ldk);
+  for (int q = 0; q < kQ; ++q)
 #pragma unroll
-    for (int u = 0; u < 8; ++u)
+    for (int b = 0; b < NB; ++b)  // A(m = l % 16, k = l / 16), B(k = l / 16, n = l % 16)
+      acc[b] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[q], zs[(4 * q + kl) * 16 * NB + 16 * b + m], acc[b], 0, 0, 0);
+  // slot v of lane l: row l / 16 + 4 v, column l % 16
+  const int r0 = blockIdx.x * 64 + 16 * w + (lane >> 4);
 #pragma unroll
-      for (int k = 0; k < SMAX; ++k) acc[k] += a[u] * zs[(c + u) * SMAX + k];
-  }
-  for (; c < cn; ++c) {
-    const double a = Kc[(size_t)c * ldk];
+  for (int b = 0; b < NB; ++b)
 #pragma unroll
-    for (int k = 0; k < SMAX; ++k) acc[k] += a * zs[c * SMAX + k];
-  }
-#pragma unroll
-  for (int k = 0; k < SMAX; ++k)
-    if (k < s) part[((size_t)sp * s + k) * n + i] = acc[k];
+    for (int v = 0; v < 4; ++v) {
+      const int r = r0 + 4 * v, k = 16 * b + m;
+      if (r < n && k < s) part[((size_t)sp * s + k) * n + r] = acc[b][v];
+    }
 }
 
 // PASS 0: w = sum of the split-K partials (minus b when residual != 0), dots
@@ -329,16 +355,12 @@ static GmresWork& work() {
 template <typename TZ>
 static int launch_matvec(const double* K, int ldk, int n, const TZ* src, int lds, int s, double* part,
                          hipStream_t st) {
-  const dim3 grid((n + kRowsPerWG - 1) / kRowsPerWG, (n + kMatvecCols - 1) / kMatvecCols);
+  const dim3 grid((n + 63) / 64, (n + kMatvecCols - 1) / kMatvecCols);
   ProfScope prof("matvec", st);
-#define HODLR_MV(SM) k_matvec<TZ, SM><<<grid, kRowsPerWG, 0, st>>>(K, ldk, n, src, lds, s, part)
-  if (s <= 1) HODLR_MV(1);
-  else if (s <= 2) HODLR_MV(2);
-  else if (s <= 4) HODLR_MV(4);
-  else if (s <= 8) HODLR_MV(8);
-  else if (s <= 16) HODLR_MV(16);
-  else if (s <= 32) HODLR_MV(32);
-  else HODLR_MV(64);
+#define HODLR_MV(NB) k_matvec_mfma<TZ, NB><<<grid, kRowsPerWG, 0, st>>>(K, ldk, n, src, lds, s, part)
+  if (s <= 16) HODLR_MV(1);
+  else if (s <= 32) HODLR_MV(2);
+  else HODLR_MV(4);
 #undef HODLR_MV
   HODLR_HIP(hipGetLastError());
   return HODLR_OK;
