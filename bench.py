@@ -83,7 +83,35 @@ def cpu_baseline(front, w, nrhs_sample, method, depth):
                        f"{reps} repetitions, {dt:.2f} s each; iterations {[i['iters'] for i in infos]}")
 
 
-def roofline(name, k, stats, n, s, leaf, ez):
+# HBM bytes per launch from rocprofv3 FETCH_SIZE / WRITE_SIZE runs of this
+# bench (profiles/tpfa4096_hbm_counters.md), calibrated by a 256 MiB copy
+# (FETCH_SIZE reads half the bytes moved, WRITE_SIZE all of them).  The
+# figures belong to the kernel source they were taken with: a changed source
+# reports traffic = null until the counters are taken again.
+TRAFFIC = {
+    "apply_level": {"source": "paper_1403_5337_amd/csrc/solve.hip",
+                    "sha256": "e45fc5870d4753f32880a6c8f64f7d4e54254a7a79216c3341c26272ef414b8a",
+                    "workload": "tpfa4096", "fetch_kib": 1617.5, "write_kib": 236.0,
+                    "fetch_factor": 2.0, "write_factor": 1.0, "rocprof_avg_us": 9.40},
+}
+
+
+def measured_traffic(name, workload):
+    import hashlib
+    t = TRAFFIC.get(name)
+    if not t or t["workload"] != workload:
+        return None, None
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), t["source"])
+    try:
+        digest = hashlib.sha256(open(path, "rb").read()).hexdigest()
+    except OSError:
+        return None, None
+    if digest != t["sha256"]:
+        return None, None
+    return (t["fetch_kib"] * t["fetch_factor"] + t["write_kib"] * t["write_factor"]) * 1024.0, t["rocprof_avg_us"]
+
+
+def roofline(name, k, stats, n, s, leaf, ez, workload):
     """Algorithmic traffic (or flops) of one launch of kernel `name`, from the
     sizes and the ranks found; achieved = that / average launch time."""
     ranks = stats["ranks"]  # per level p = 1..L: ranks of its 2^p nodes
@@ -125,8 +153,10 @@ def roofline(name, k, stats, n, s, leaf, ez):
         return dict(kernel=name, bound=bound, achieved=None, peak=peak, unit=unit, frac=None, traffic=None)
     scale = 1e9 if unit == "GB/s" else 1e12
     ach = work / avg_s / scale
+    traffic, rp_us = measured_traffic(name, workload)
     return dict(kernel=name, bound=bound, achieved=round(ach, 3), peak=peak, unit=unit,
-                frac=round(ach / peak, 5), traffic=None, algo_per_launch=work, avg_us=k["avg_us"], note=note)
+                frac=round(ach / peak, 5), traffic=None if traffic is None else round(traffic),
+                algo_per_launch=round(work), avg_us=k["avg_us"], rocprof_avg_us=rp_us, note=note)
 
 
 def main_batch(args):
@@ -316,7 +346,7 @@ def main():
 
     # dominant kernel and its roofline (algorithmic bytes or flops per launch)
     dom = max(kern, key=lambda k: kern[k]["ms_per_step"])
-    roof = roofline(dom, kern[dom], stats, n, s, leaf, 4 if prec == 32 else 8)
+    roof = roofline(dom, kern[dom], stats, n, s, leaf, 4 if prec == 32 else 8, args.workload)
 
     # GPU dense FP64 LU comparator (rocSOLVER through torch): factor + solve
     lu_ms = None

@@ -26,7 +26,9 @@ hipEvent_t get_event() {
     return e;
   }
   hipEvent_t e = nullptr;
-  if (hipEventCreate(&e) != hipSuccess) return nullptr;
+  // no system-scope release at the marker: the timed kernels write device
+  // memory only, and the fence would add to every measured interval
+  if (hipEventCreateWithFlags(&e, hipEventDisableSystemFence) != hipSuccess) return nullptr;
   return e;
 }
 
