@@ -19,6 +19,7 @@ HIP_FLAGS = [
     "-O3", "-std=c++17", "--offload-arch=gfx950", "-fPIC", "-shared",
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-Wno-unused-command-line-argument",
+    "-Wl,--no-undefined",  # a missing definition fails the build, not the first load
 ]
 
 

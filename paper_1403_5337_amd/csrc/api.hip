@@ -197,6 +197,16 @@ int set_layout_from_ranks(hodlr_s* h) {
   return ensure_work(h, 8);
 }
 
+int side_stream(int which, hipStream_t* out) {
+  static std::mutex mu;
+  static hipStream_t streams[2] = {nullptr, nullptr};
+  if (which < 0 || which > 1) return fail(HODLR_EINVAL, "side stream index");
+  std::lock_guard<std::mutex> lk(mu);
+  if (!streams[which]) HODLR_HIP(hipStreamCreateWithFlags(&streams[which], hipStreamNonBlocking));
+  *out = streams[which];
+  return HODLR_OK;
+}
+
 }  // namespace hodlr
 
 using namespace hodlr;
@@ -266,6 +276,28 @@ static int build_impl(const double* K, int n, int ldk, const int* g_rowptr, cons
   const Tree& t = h->tree;
   // a1: leaf blocks to the factorization precision
   HODLR_TRY(launch_stage_leaves_from_K(h.get(), K, ldk, stream));
+  // The leaf inverses need only the staged diagonal blocks: they run on a
+  // second stream beside the compression (not beside ACA, whose cooperative
+  // launch wants every compute unit).  The guard joins that stream before any
+  // return, so no kernel outlives the handle's buffers.
+  struct Fork {
+    hipStream_t side = nullptr;
+    hipEvent_t ev[2] = {nullptr, nullptr};
+    ~Fork() {
+      if (side) (void)hipStreamSynchronize(side);
+      for (auto e : ev)
+        if (e) (void)hipEventDestroy(e);
+    }
+  } fork;
+  if (o.method != HODLR_ACA) {
+    HODLR_TRY(side_stream(0, &fork.side));
+    for (auto& e : fork.ev) HODLR_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+    HODLR_HIP(hipEventRecord(fork.ev[0], stream));
+    HODLR_HIP(hipStreamWaitEvent(fork.side, fork.ev[0], 0));
+    HODLR_TRY(h->lstatus.ensure(4 * sizeof(int)));
+    HODLR_TRY(launch_leaf_inverse(h.get(), h->lstatus.as<int>(), fork.side));
+    HODLR_HIP(hipEventRecord(fork.ev[1], fork.side));
+  }
   if (t.L > 0) {
     int cap = rank_cap(o.precision);
     if (o.max_rank > 0) cap = std::min(cap, o.max_rank);
@@ -303,6 +335,14 @@ static int build_impl(const double* K, int n, int ldk, const int* g_rowptr, cons
     HODLR_HIP(hipStreamSynchronize(stream));  // Ucap/Vcap are freed on return
   } else {
     HODLR_TRY(set_layout_from_ranks(h.get()));
+  }
+  if (fork.side) {
+    HODLR_HIP(hipStreamWaitEvent(stream, fork.ev[1], 0));
+    HODLR_HIP(hipStreamSynchronize(stream));
+    int ls[4];
+    HODLR_HIP(hipMemcpy(ls, h->lstatus.p, sizeof(ls), hipMemcpyDeviceToHost));
+    h->leaves_inverted = true;
+    if (ls[0]) h->leaf_singular = ls[1];
   }
   *out = h.release();
   return HODLR_OK;
@@ -378,6 +418,7 @@ int hodlr_build_from_factors(int n, int leaf, int precision, const double* leave
 int hodlr_factor(hodlr_t h, hipStream_t stream) {
   if (!h) return fail(HODLR_EINVAL, "handle is NULL");
   if (h->factored) return fail(HODLR_EINVAL, "handle is already factorized");
+  if (h->leaf_singular >= 0) return fail(HODLR_ESINGULAR, "singular leaf block " + std::to_string(h->leaf_singular));
   HODLR_TRY(factor_impl(h, stream));
   HODLR_HIP(hipStreamSynchronize(stream));
   int st[4];
@@ -412,6 +453,9 @@ int hodlr_factor_batched(hodlr_t* hs, int nh, hipStream_t stream) {
   for (int f = 0; f < nh; ++f) {
     if (!hs[f]) return fail(HODLR_EINVAL, "handle " + std::to_string(f) + " is NULL");
     if (hs[f]->factored) return fail(HODLR_EINVAL, "handle " + std::to_string(f) + " is already factorized");
+    if (hs[f]->leaf_singular >= 0)
+      return fail(HODLR_ESINGULAR, "front " + std::to_string(f) + ": singular leaf block " +
+                                       std::to_string(hs[f]->leaf_singular));
     for (int g = 0; g < f; ++g)
       if (hs[g] == hs[f]) return fail(HODLR_EINVAL, "a handle appears twice in the batch");
   }

@@ -585,17 +585,43 @@ static int bdlr_t(hodlr_s* h, const double* K, int ldk, const int* rowptr, const
   const int rcap = h->precision == 64 ? kRankCap64 : kRankCap32;
   {
     ProfScope prof("bdlr_lu", s);
-    HODLR_TRY((launch_bdlr_lu<T, SKEL>(K, ldk, d_tasks.as<BdlrTask>(), nt, d_sel.as<int>(), d_cnt.as<int>(),
-                                       (T)h->tol, rcap, d_piv.as<int>(), d_inv.as<T>(), h->d_rank.as<int>(),
-                                       d_rt.as<int>(), s)));
-  }
-  const int nch = (maxside + kBlock - 1) / kBlock;
-  {
-    ProfScope prof("bdlr_gather", s);
-    k_bdlr_gather<T, SKEL><<<dim3(nt, nch, 2), kBlock, 0, s>>>(K, ldk, d_tasks.as<BdlrTask>(), d_piv.as<int>(),
-                                                              d_rt.as<int>(), d_cg.as<T>(), Vcap, tr.n);
+    k_bdlr_lu<T, SKEL><<<nt, kLuBlock, 0, s>>>(K, ldk, d_tasks.as<BdlrTask>(), d_sel.as<int>(), d_cnt.as<int>(),
+                                                (T)h->tol, rcap, d_piv.as<int>(), h->d_rank.as<int>(), d_rt.as<int>());
   }
   HODLR_HIP(hipGetLastError());
+  // the gather needs only the pivots: it runs on a second stream beside the
+  // inverses of the pivot blocks (a block the inverse finds singular gets
+  // rank 0, and its gathered columns are never read)
+  const int nch = (maxside + kBlock - 1) / kBlock;
+  hipStream_t side = nullptr;
+  HODLR_TRY(side_stream(1, &side));
+  struct Events {  // joins the side stream on every return (the scratch above outlives it)
+    hipStream_t side = nullptr;
+    hipEvent_t e[2] = {nullptr, nullptr};
+    ~Events() {
+      if (side) (void)hipStreamSynchronize(side);
+      for (auto x : e)
+        if (x) (void)hipEventDestroy(x);
+    }
+  } ev;
+  ev.side = side;
+  for (auto& x : ev.e) HODLR_HIP(hipEventCreateWithFlags(&x, hipEventDisableTiming));
+  HODLR_HIP(hipEventRecord(ev.e[0], s));
+  HODLR_HIP(hipStreamWaitEvent(side, ev.e[0], 0));
+  {
+    ProfScope prof("bdlr_gather", side);
+    k_bdlr_gather<T, SKEL><<<dim3(nt, nch, 2), kBlock, 0, side>>>(K, ldk, d_tasks.as<BdlrTask>(), d_piv.as<int>(),
+                                                                 d_rt.as<int>(), d_cg.as<T>(), Vcap, tr.n);
+  }
+  HODLR_HIP(hipGetLastError());
+  HODLR_HIP(hipEventRecord(ev.e[1], side));
+  {
+    ProfScope prof("bdlr_lu", s);
+    k_bdlr_ginv<T, SKEL><<<nt, kBlock, 0, s>>>(K, ldk, d_tasks.as<BdlrTask>(), d_piv.as<int>(), d_inv.as<T>(),
+                                               h->d_rank.as<int>(), d_rt.as<int>());
+  }
+  HODLR_HIP(hipGetLastError());
+  HODLR_HIP(hipStreamWaitEvent(s, ev.e[1], 0));
   {
     ProfScope prof("bdlr_factors", s);
     k_bdlr_factors<T><<<dim3(nt, (maxside + 63) / 64, (rcap + 63) / 64), kBlock, 0, s>>>(

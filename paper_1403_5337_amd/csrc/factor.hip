@@ -278,6 +278,21 @@ int ensure_work(hodlr_s* h, int ncols) {
   return HODLR_OK;
 }
 
+int launch_leaf_inverse(hodlr_s* h, int* status, hipStream_t s) {
+  const Tree& t = h->tree;
+  k_fill_int<<<1, 64, 0, s>>>(status, 4, 0);
+  HODLR_HIP(hipGetLastError());
+  ProfScope prof_("leaf_inverse", s);
+  if (h->precision == 64)
+    k_leaf_inverse<double><<<h->nleaf, kBlock, 0, s>>>(h->Kinv.as<double>(), h->bmax, h->d_lo.as<int>(),
+                                                       h->d_hi.as<int>(), node_id(t.L, 0), status);
+  else
+    k_leaf_inverse<float><<<h->nleaf, kBlock, 0, s>>>(h->Kinv.as<float>(), h->bmax, h->d_lo.as<int>(),
+                                                      h->d_hi.as<int>(), node_id(t.L, 0), status);
+  HODLR_HIP(hipGetLastError());
+  return HODLR_OK;
+}
+
 template <typename T>
 static int stage_from_K(hodlr_s* h, const double* K, int ldk, hipStream_t s) {
   const Tree& t = h->tree;
@@ -402,7 +417,7 @@ static int factor_t(hodlr_s* h, hipStream_t s) {
   gemm_reset(h);
   k_fill_int<<<1, 64, 0, s>>>(h->status.as<int>(), 4, 0);
   HODLR_HIP(hipGetLastError());
-  {
+  if (!h->leaves_inverted) {  // (the build may have run them beside the compression)
     ProfScope prof_("leaf_inverse", s);
     k_leaf_inverse<T><<<h->nleaf, kBlock, 0, s>>>(h->Kinv.as<T>(), h->bmax, h->d_lo.as<int>(),
                                                          h->d_hi.as<int>(), node_id(L, 0),

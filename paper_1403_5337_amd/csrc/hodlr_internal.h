@@ -123,6 +123,9 @@ struct hodlr_s {
   void* gemm_host = nullptr;  // pinned staging of the task tables
   size_t gemm_host_bytes = 0;
   bool capturing = false;     // launches are being recorded into a graph
+  hodlr::DevBuf lstatus;      // int[4]: status of the leaf inverses run by the build
+  bool leaves_inverted = false;  // the build already inverted the leaf blocks
+  int leaf_singular = -1;        // node id of a singular leaf found by the build
   bool factored = false;
   hodlr_s() = default;
   hodlr_s(const hodlr_s&) = delete;
@@ -174,11 +177,18 @@ int launch_repack(hodlr_s* h, const void* Ucap, const void* Vcap, int ldcap,
 int launch_from_f64_panels(hodlr_s* h, const double* Up, const double* Vp, hipStream_t s);
 int launch_to_f64_panels(hodlr_s* h, double* Up, double* Vp, hipStream_t s);
 int factor_impl(hodlr_s* h, hipStream_t s);
+// leaf inverses in place (status: int[4], zeroed here; [0] = 1 and [1] = node
+// id for a singular leaf)
+int launch_leaf_inverse(hodlr_s* h, int* status, hipStream_t s);
 int ensure_work(hodlr_s* h, int ncols);
 
 // solve.hip
 int apply_impl(hodlr_s* h, void* X, int ldx, int nrhs, hipStream_t s);  // in place
 size_t solve_partial_elems(const hodlr_s* h);
+
+// api.hip: streams for work that runs beside the caller's stream (default
+// priority, one pair per process, created on first use)
+int side_stream(int which, hipStream_t* out);
 
 // prof.hip: event timing of wrapped launches (hodlr_prof_enable)
 bool prof_on();
