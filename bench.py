@@ -25,7 +25,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
-KERNELS = ["aca", "bdlr_select", "bdlr_lu", "bdlr_gather", "bdlr_factors", "leaf_inverse", "leaf_apply", "panel_tn", "schur_form", "form_E", "schur_apply", "correct", "apply_leaf", "apply_level", "apply_sum",
+KERNELS = ["aca", "bdlr_select", "bdlr_lu", "bdlr_gather", "bdlr_factors", "leaf_inverse", "leaf_apply", "panel_tn", "schur_form", "cap_inverse", "form_E", "schur_apply", "correct", "apply_leaf", "apply_level", "apply_sum",
            "matvec", "orth"]
 
 

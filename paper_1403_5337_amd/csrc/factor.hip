@@ -488,10 +488,16 @@ static int factor_t(hodlr_s* h, hipStream_t s) {
       gt.push_back(g);
     }
     {
-      ProfScope prof_("schur_form", s);
-      HODLR_TRY(gemm_batched(h, gt, s));
-      k_capacitance_inverse<T><<<np, kBlock, 0, s>>>(h->d_rank.as<int>(), q, rq, Sq, h->status.as<int>());
+      {
+        ProfScope prof_("schur_form", s);
+        HODLR_TRY(gemm_batched(h, gt, s));
+      }
+      {
+        ProfScope prof_("cap_inverse", s);
+        k_capacitance_inverse<T><<<np, kBlock, 0, s>>>(h->d_rank.as<int>(), q, rq, Sq, h->status.as<int>());
+      }
       HODLR_HIP(hipGetLastError());
+      ProfScope prof_("schur_form", s);
       // S21 = -M^-1 B, S12 = -A M^-1
       gt.clear();
       for (int i = 0; i < np; ++i) {

@@ -31,6 +31,8 @@
 namespace hodlr {
 
 constexpr int kRows = 64;        // rows per unit
+constexpr int kSolveThreads = 1024;  // 16 waves: four per SIMD
+constexpr int kZParts = 4;       // the rank range of a contraction splits in 4 (x 4 column groups)
 constexpr int kLdW = kRows + 1;  // LDS column stride of staged W columns (read across columns)
 // LDS column stride of the staged E / leaf-inverse columns (read 4 rows at a
 // time, so 16-byte aligned)
@@ -83,26 +85,24 @@ __device__ __forceinline__ void stage_stream(T* arena, const T* A, size_t lda, i
   }
 }
 
-// acc[ri][cj] += sum_z A(4 g + ri, z - a0) B(z, cb + cj) over this wave's
-// share of [z0, z1), with g = lane % 16 and cb = (lane / 16) SM / 4: each lane
-// keeps 4 rows x SM / 4 columns.  A in LDS with column stride lda_lds, B in
-// LDS as [z][SM].  The loads of kU consecutive z are issued together; the sum
-// runs in z order.
+// acc[cj] += sum_z A(lane, z - a0) B(z, cb + cj) over this wave's share of
+// [z0, z1): wave w takes the quarter w % 4 of the range and the column group
+// cb = (w / 4) SM / 4.  A in LDS with column stride lda_lds, B in LDS as
+// [z][SM].  The loads of kU consecutive z are issued together; the sum runs
+// in z order.
 template <typename T, int SM>
-__device__ __forceinline__ void contract(const T* A, int a0, const T* B, int z0, int z1, T (&acc)[4][SM / 4]) {
-  constexpr int kC = SM / 4, kU = 4, kL = lda_lds<T>();
+__device__ __forceinline__ void contract(const T* A, int a0, const T* B, int z0, int z1, T (&acc)[SM / 4]) {
+  constexpr int kC = SM / 4, kU = 8, kL = lda_lds<T>();
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int g = lane & 15, cb = (lane >> 4) * kC;
-  const int per = (z1 - z0 + 3) >> 2;
-  const int zb = z0 + wave * per, ze = min(z1, zb + per);
+  const int zp = wave % kZParts, cb = (wave / kZParts) * kC;
+  const int per = (z1 - z0 + kZParts - 1) / kZParts;
+  const int zb = z0 + zp * per, ze = min(z1, zb + per);
   int z = zb;
   for (; z + kU <= ze; z += kU) {
-    T a[kU][4], b[kU][kC];
+    T a[kU], b[kU][kC];
 #pragma unroll
     for (int k = 0; k < kU; ++k) {
-      const T* ap = static_cast<const T*>(__builtin_assume_aligned(A + (z + k - a0) * kL + 4 * g, 16));
-#pragma unroll
-      for (int ri = 0; ri < 4; ++ri) a[k][ri] = ap[ri];
+      a[k] = A[(z + k - a0) * kL + lane];
       const T* bp = static_cast<const T*>(__builtin_assume_aligned(B + (z + k) * SM + cb, 8));
 #pragma unroll
       for (int cj = 0; cj < kC; ++cj) b[k][cj] = bp[cj];
@@ -110,42 +110,36 @@ __device__ __forceinline__ void contract(const T* A, int a0, const T* B, int z0,
 #pragma unroll
     for (int k = 0; k < kU; ++k)
 #pragma unroll
-      for (int ri = 0; ri < 4; ++ri)
-#pragma unroll
-        for (int cj = 0; cj < kC; ++cj) acc[ri][cj] += a[k][ri] * b[k][cj];
+      for (int cj = 0; cj < kC; ++cj) acc[cj] += a[k] * b[k][cj];
   }
   for (; z < ze; ++z) {
-    const T* ap = static_cast<const T*>(__builtin_assume_aligned(A + (z - a0) * kL + 4 * g, 16));
+    const T a = A[(z - a0) * kL + lane];
     const T* bp = static_cast<const T*>(__builtin_assume_aligned(B + z * SM + cb, 8));
 #pragma unroll
-    for (int ri = 0; ri < 4; ++ri)
-#pragma unroll
-      for (int cj = 0; cj < kC; ++cj) acc[ri][cj] += ap[ri] * bp[cj];
+    for (int cj = 0; cj < kC; ++cj) acc[cj] += a * bp[cj];
   }
 }
 
-// x(i, c) = xr - (sum of the four wave results) (sub) or the sum itself;
-// written to Xout (rows i < rn, c < nc) and to xs (zero elsewhere).
+// x(i, c) = xr - (sum of the four rank quarters) (sub) or the sum itself;
+// written to Xout (rows i < rn, c < nc) and to xs (zero elsewhere).  Thread
+// (lane, wave) finishes row lane of column wave (waves >= SM idle here).
 template <typename T, int SM>
-__device__ __forceinline__ void finalize_x(SolveSmem<T, SM>& sm, const T (&acc)[4][SM / 4], const T (&xr)[SM / 4],
-                                           bool sub, int rn, int nc, T* Xout, size_t ldxo) {
+__device__ __forceinline__ void finalize_x(SolveSmem<T, SM>& sm, const T (&acc)[SM / 4], T xr, bool sub, int rn,
+                                           int nc, T* Xout, size_t ldxo) {
   constexpr int kC = SM / 4;
-  const int t = threadIdx.x, lane = t & 63, wave = t >> 6, cg = t >> 6;
-  const int g = lane & 15, cb = (lane >> 4) * kC;
+  const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+  const int zp = wave % kZParts, cb = (wave / kZParts) * kC;
   __syncthreads();  // every wave is done with tb
 #pragma unroll
-  for (int cj = 0; cj < kC; ++cj)
-#pragma unroll
-    for (int ri = 0; ri < 4; ++ri) sm.tb[(wave * SM + cb + cj) * kRows + 4 * g + ri] = acc[ri][cj];
+  for (int cj = 0; cj < kC; ++cj) sm.tb[(zp * SM + cb + cj) * kRows + lane] = acc[cj];
   __syncthreads();
-#pragma unroll
-  for (int u = 0; u < SM / 4; ++u) {
-    const int c = cg + 4 * u;
+  if (wave < SM) {
+    const int c = wave;
     T s = sm.tb[c * kRows + lane];
 #pragma unroll
-    for (int w = 1; w < 4; ++w) s += sm.tb[(w * SM + c) * kRows + lane];
+    for (int p = 1; p < kZParts; ++p) s += sm.tb[(p * SM + c) * kRows + lane];
     const bool ok = lane < rn && c < nc;
-    const T v = ok ? (sub ? xr[u] - s : s) : T(0);
+    const T v = ok ? (sub ? xr - s : s) : T(0);
     if (ok) Xout[(size_t)c * ldxo + lane] = v;
     sm.xs[lane * SM + c] = v;
   }
@@ -153,62 +147,56 @@ __device__ __forceinline__ void finalize_x(SolveSmem<T, SM>& sm, const T (&acc)[
 }
 
 // Pu(r0 + r, c) = sum_{i < rn} Wl(i, r) xs(i, c) for r < nw, c < nc (Pu has
-// leading dimension rp); Wl in LDS with column stride kLdW.  Lane = r.  With
-// fewer than four 64-column blocks the rows are split among the waves (S
-// parts per block) and the parts are added in order through red (LDS,
-// 4 x SM x 64).  The loads of kU consecutive rows are issued together.
+// leading dimension rp); Wl in LDS with column stride kLdW.  Lane = r.  Per
+// 64-column block of Wl the 16 waves split as 4 row quarters x 4 column
+// groups of SM / 4; the quarters are added in order through red (LDS,
+// 4 x SM x 64).
 template <typename T, int SM>
 __device__ __forceinline__ void unit_partials(const T* Wl, T* red, const T* xs, int rn, int nw, int nc, T* Pu,
                                               int r0, int rp) {
-  constexpr int kU = SM <= 8 ? 8 : 4;
+  constexpr int kC = SM / 4, kU = 4;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int nb = (nw + 63) >> 6;
-  const int S = nb == 1 ? 4 : (nb == 2 ? 2 : 1);
-  const int per = ((rn + S - 1) / S + kU - 1) / kU * kU;
-  for (int b0 = 0; b0 < nb; b0 += 4 / S) {
-    const int blk = b0 + wave / S, part = wave % S;
-    const int r = blk * 64 + lane, rc = min(r, nw - 1);
+  const int part = wave % kZParts, cb = (wave / kZParts) * kC;
+  const int per = ((rn + kZParts - 1) / kZParts + kU - 1) / kU * kU;
+  const int i0 = part * per, i1 = min(rn, i0 + per);
+  for (int b0 = 0; b0 < nw; b0 += 64) {
+    const int r = b0 + lane, rc = min(r, nw - 1);
     const T* wc = Wl + rc * kLdW;
-    T acc[SM];
+    T acc[kC];
 #pragma unroll
-    for (int c = 0; c < SM; ++c) acc[c] = T(0);
-    const int i0 = part * per, i1 = blk < nb ? min(rn, i0 + per) : 0;
+    for (int cj = 0; cj < kC; ++cj) acc[cj] = T(0);
     int i = i0;
     for (; i + kU <= i1; i += kU) {
-      T w[kU], x[kU][SM];
+      T w[kU], x[kU][kC];
 #pragma unroll
       for (int k = 0; k < kU; ++k) {
         w[k] = wc[i + k];
-        const T* xp = static_cast<const T*>(__builtin_assume_aligned(xs + (i + k) * SM, 16));
+        const T* xp = static_cast<const T*>(__builtin_assume_aligned(xs + (i + k) * SM + cb, 8));
 #pragma unroll
-        for (int c = 0; c < SM; ++c) x[k][c] = xp[c];
+        for (int cj = 0; cj < kC; ++cj) x[k][cj] = xp[cj];
       }
 #pragma unroll
       for (int k = 0; k < kU; ++k)
 #pragma unroll
-        for (int c = 0; c < SM; ++c) acc[c] += w[k] * x[k][c];
+        for (int cj = 0; cj < kC; ++cj) acc[cj] += w[k] * x[k][cj];
     }
     for (; i < i1; ++i) {
       const T w = wc[i];
-      const T* xp = static_cast<const T*>(__builtin_assume_aligned(xs + i * SM, 16));
+      const T* xp = static_cast<const T*>(__builtin_assume_aligned(xs + i * SM + cb, 8));
 #pragma unroll
-      for (int c = 0; c < SM; ++c) acc[c] += w * xp[c];
+      for (int cj = 0; cj < kC; ++cj) acc[cj] += w * xp[cj];
     }
-    if (S > 1) {
 #pragma unroll
-      for (int c = 0; c < SM; ++c) red[(wave * SM + c) * 64 + lane] = acc[c];
-      __syncthreads();
-      if (part == 0) {
-        for (int p = 1; p < S; ++p)
+    for (int cj = 0; cj < kC; ++cj) red[(part * SM + cb + cj) * 64 + lane] = acc[cj];
+    __syncthreads();
+    if (wave < SM) {
+      const int c = wave;
+      T v = red[c * 64 + lane];
 #pragma unroll
-          for (int c = 0; c < SM; ++c) acc[c] += red[((wave + p) * SM + c) * 64 + lane];
-      }
-      __syncthreads();
+      for (int p = 1; p < kZParts; ++p) v += red[(p * SM + c) * 64 + lane];
+      if (r < nw && c < nc) Pu[(size_t)(r0 + r) + (size_t)c * rp] = v;
     }
-    if (part == 0 && blk < nb && r < nw)
-#pragma unroll
-      for (int c = 0; c < SM; ++c)
-        if (c < nc) Pu[(size_t)(r0 + r) + (size_t)c * rp] = acc[c];
+    __syncthreads();
   }
 }
 
@@ -248,15 +236,13 @@ __global__ void __launch_bounds__(kBlock) k_sum_units(T* __restrict__ P, int nno
 // the partial products of W.
 template <typename T, int SM>
 __device__ __forceinline__ void unit_pipeline(SolveSmem<T, SM>& sm, const T* A, size_t lda, int ra, const T* Wp,
-                                              size_t ldw, int nwc, int rn, int nc, const T (&xr)[SM / 4], bool sub,
+                                              size_t ldw, int nwc, int rn, int nc, T xr, bool sub,
                                               T* Xout, size_t ldxo, T* Pu, int rp, int jn) {
   constexpr int kA = SolveCfg<T>::kArena;
   const int total = ra + nwc;
-  T acc[4][SM / 4];
+  T acc[SM / 4];
 #pragma unroll
-  for (int ri = 0; ri < 4; ++ri)
-#pragma unroll
-    for (int cj = 0; cj < SM / 4; ++cj) acc[ri][cj] = T(0);
+  for (int cj = 0; cj < SM / 4; ++cj) acc[cj] = T(0);
   bool done = false;
   for (int j0 = 0;;) {
     dma_wait();
@@ -279,7 +265,7 @@ __device__ __forceinline__ void unit_pipeline(SolveSmem<T, SM>& sm, const T* A, 
 }
 
 template <typename T, int SM>
-__global__ void __launch_bounds__(kBlock)
+__global__ void __launch_bounds__(kSolveThreads)
     k_solve_leaf(const T* __restrict__ Kinv, int bmax, const int* __restrict__ lo, const int* __restrict__ hi,
                  int idL, const T* __restrict__ Xin, int ldxi, T* __restrict__ Xout, int ldxo, int nc,
                  const T* __restrict__ W, int ldw, int offL, int rL, int nchL, T* __restrict__ P) {
@@ -299,28 +285,25 @@ __global__ void __launch_bounds__(kBlock)
   const int jn = min(SolveCfg<T>::kArena, b + nwc);
   stage_stream(sm.arena, Ki, (size_t)bmax, b, Wu, (size_t)ldw, 0, jn, rn);
   // right-hand block: the leaf's rows of x, as [k][SM]
-  for (int e0 = 0; e0 < b * SM; e0 += 8 * kBlock) {
-    T v[8];
+  for (int e0 = 0; e0 < b * SM; e0 += 4 * kSolveThreads) {
+    T v[4];
 #pragma unroll
-    for (int a = 0; a < 8; ++a) {
-      const int e = e0 + t + a * kBlock, k = e % b, c = e / b;
+    for (int a = 0; a < 4; ++a) {
+      const int e = e0 + t + a * kSolveThreads, k = e % b, c = e / b;
       v[a] = (e < b * SM && c < nc) ? Xin[(size_t)c * ldxi + l0 + k] : T(0);
     }
 #pragma unroll
-    for (int a = 0; a < 8; ++a) {
-      const int e = e0 + t + a * kBlock;
+    for (int a = 0; a < 4; ++a) {
+      const int e = e0 + t + a * kSolveThreads;
       if (e < b * SM) sm.tb[(e % b) * SM + e / b] = v[a];
     }
   }
-  T xr[SM / 4];
-#pragma unroll
-  for (int u = 0; u < SM / 4; ++u) xr[u] = T(0);
-  unit_pipeline<T, SM>(sm, Ki, (size_t)bmax, b, Wu, (size_t)ldw, nwc, rn, nc, xr, false,
+  unit_pipeline<T, SM>(sm, Ki, (size_t)bmax, b, Wu, (size_t)ldw, nwc, rn, nc, T(0), false,
                        Xout + l0 + row0, (size_t)ldxo, Pu, rL, jn);
 }
 
 template <typename T, int SM>
-__global__ void __launch_bounds__(kBlock)
+__global__ void __launch_bounds__(kSolveThreads)
     k_solve_level(int q, const int* __restrict__ lo, const int* __restrict__ hi, const int* __restrict__ rank,
                   const T* Xin, int ldxi, T* Xout, int ldxo, int nc, const T* __restrict__ E, int ldE, int offE,
                   int rq, const T* __restrict__ Pin, int upn, int gin, int nch, const T* __restrict__ W, int ldw,
@@ -342,26 +325,21 @@ __global__ void __launch_bounds__(kBlock)
   const int nwc = Pu ? rp : 0;
   const int jn = min(SolveCfg<T>::kArena, r + nwc);
   stage_stream(sm.arena, Eu, (size_t)ldE, r, Wu, (size_t)ldw, 0, jn, rn);
-  // x of the unit
-  const int lane = t & 63, cg = t >> 6;
-  T xr[SM / 4];
-#pragma unroll
-  for (int u = 0; u < SM / 4; ++u) {
-    const int cc = cg + 4 * u;
-    xr[u] = (lane < rn && cc < nc) ? Xin[(size_t)cc * ldxi + row0 + lane] : T(0);
-  }
+  // x of the unit: thread (lane, wave) holds row lane of column wave
+  const int lane = t & 63, cw = t >> 6;
+  const T xr = (lane < rn && cw < nc) ? Xin[(size_t)cw * ldxi + row0 + lane] : T(0);
   // t_P = [W(rows a)^T x_a (r_b entries); W(rows b)^T x_b (r_a entries)] from
   // the group sums of both children, as [z][SM]
   const size_t usz = (size_t)rq * nc, gstride = (size_t)gin * usz;
   const int ng = upn / gin;
-  constexpr int kE = 4, kJ = 4;
-  for (int e0 = 0; e0 < r * SM; e0 += kE * kBlock) {
+  constexpr int kE = 2, kJ = 4;
+  for (int e0 = 0; e0 < r * SM; e0 += kE * kSolveThreads) {
     T s[kE];
     const T* p0[kE];
     bool ok[kE];
 #pragma unroll
     for (int a = 0; a < kE; ++a) {
-      const int e = e0 + t + a * kBlock, z = e % r, cc = e / r;
+      const int e = e0 + t + a * kSolveThreads, z = e % r, cc = e / r;
       ok[a] = e < r * SM && cc < nc;
       const int node = (z < rb) ? 2 * par : 2 * par + 1, zz = (z < rb) ? z : z - rb;
       p0[a] = Pin + (size_t)node * upn * usz + zz + (size_t)cc * rq;
@@ -381,7 +359,7 @@ __global__ void __launch_bounds__(kBlock)
     }
 #pragma unroll
     for (int a = 0; a < kE; ++a) {
-      const int e = e0 + t + a * kBlock;
+      const int e = e0 + t + a * kSolveThreads;
       if (e < r * SM) sm.tb[(e % r) * SM + e / r] = s[a];
     }
   }
@@ -428,7 +406,7 @@ static int solve_t(hodlr_s* h, T* X, int ldx, int nc, hipStream_t s) {
   const int nchL = cdiv(h->bmax, kRows);
   {
     ProfScope prof_("apply_leaf", s);
-    k_solve_leaf<T, SM><<<dim3(h->nleaf, nchL), kBlock, 0, s>>>(
+    k_solve_leaf<T, SM><<<dim3(h->nleaf, nchL), kSolveThreads, 0, s>>>(
         h->Kinv.as<T>(), h->bmax, h->d_lo.as<int>(), h->d_hi.as<int>(), node_id(L, 0), X, ldx, Xt, n, nc,
         h->W.as<T>(), n, offL, rL, nchL, L > 0 ? P[0] : nullptr);
   }
@@ -453,7 +431,7 @@ static int solve_t(hodlr_s* h, T* X, int ldx, int nc, hipStream_t s) {
     }
     {
       ProfScope prof_("apply_level", s);
-      k_solve_level<T, SM><<<dim3(1 << q, nch), kBlock, 0, s>>>(
+      k_solve_level<T, SM><<<dim3(1 << q, nch), kSolveThreads, 0, s>>>(
           q, h->d_lo.as<int>(), h->d_hi.as<int>(), h->d_rank.as<int>(), Xt, n, Xo, ldo, nc, h->E.as<T>(), n,
           h->offE[q - 1], rq, P[cur], upn, gin, nch, h->W.as<T>(), n, offp, rp, q > 1 ? P[cur ^ 1] : nullptr);
     }
