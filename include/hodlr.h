@@ -170,6 +170,32 @@ int gmres_solve(const double* K, int n, int ldk, hodlr_t precond, const double* 
                 int ldb, double* X, int ldx, double tol, int maxit, int restart, int* iters,
                 double* relres, hipStream_t stream);
 
+/* Batches of fronts (the separators of a nested-dissection tree, solved
+ * independently; Sec. 2): the library runs the fronts side by side on a pool
+ * of host worker threads, each issuing its fronts' calls on its own stream
+ * (default priority), ordered after the work already queued on `stream`.
+ * The worker count is 8, or HODLR_THREADS (1..64) from the environment when
+ * the pool starts.  Pointer arguments are host arrays of nf entries; each
+ * front follows the rules of the single-front call.  Both calls synchronize
+ * and return the error of the lowest-numbered failing front (the message
+ * names it); every front runs even if another fails.  Concurrent calls of
+ * either function on one process share the pool.
+ *
+ * hodlr_build_batched: out[f] receives front f's handle; on any error every
+ * handle built by the call is destroyed and out[] is all NULL.
+ * g_rowptr, g_col, coords may be NULL (all fronts) or arrays whose entries
+ * follow hodlr_build.  One opts for all fronts. */
+int hodlr_build_batched(int nf, const double* const* K, const int* n, const int* ldk,
+                        const int* const* g_rowptr, const int* const* g_col, const float* const* coords,
+                        const hodlr_opts* opts, hipStream_t stream, hodlr_t* out);
+
+/* gmres_solve_batched: front f solves K[f] X[f] = B[f] with preconditioner
+ * precond[f] (precond may be NULL for none); iters and relres are host
+ * arrays of nf * nrhs entries, front f at f * nrhs. */
+int gmres_solve_batched(int nf, const double* const* K, const int* n, const int* ldk, const hodlr_t* precond,
+                        const double* const* B, int nrhs, const int* ldb, double* const* X, const int* ldx,
+                        double tol, int maxit, int restart, int* iters, double* relres, hipStream_t stream);
+
 /* Recursive coordinate bisection order of n dofs for the HODLR tree of
  * (n, leaf): for every node from the root down, sort its dofs by the
  * coordinate of largest extent (first axis on ties, stable) and give the

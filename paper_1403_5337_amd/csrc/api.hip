@@ -4,7 +4,11 @@
 #include <cstring>
 #include <map>
 #include <memory>
+#include <condition_variable>
+#include <cstdlib>
+#include <functional>
 #include <mutex>
+#include <thread>
 #include <string>
 
 #include "gemm.h"
@@ -198,14 +202,123 @@ int set_layout_from_ranks(hodlr_s* h) {
 }
 
 int side_stream(int which, hipStream_t* out) {
-  static std::mutex mu;
-  static hipStream_t streams[2] = {nullptr, nullptr};
+  // per host thread, so concurrent builds do not queue behind each other
+  static thread_local hipStream_t streams[2] = {nullptr, nullptr};
   if (which < 0 || which > 1) return fail(HODLR_EINVAL, "side stream index");
-  std::lock_guard<std::mutex> lk(mu);
   if (!streams[which]) HODLR_HIP(hipStreamCreateWithFlags(&streams[which], hipStreamNonBlocking));
   *out = streams[which];
   return HODLR_OK;
 }
+
+// ---------------------------------------------------------------------------
+// Worker pool of the batched calls: threads started on first use and kept for
+// the process, each with its own stream; a call hands out its items through
+// a shared counter and waits for all of them.
+// ---------------------------------------------------------------------------
+class Workers {
+ public:
+  static Workers& get() {
+    static Workers* w = new Workers();  // kept for the process
+    return *w;
+  }
+  // fn(item, stream) for every item in [0, nitems); returns the code of the
+  // lowest failing item and its message in *msg
+  int run(int nitems, const std::function<int(int, hipStream_t)>& fn, hipStream_t caller, std::string* msg) {
+    std::lock_guard<std::mutex> serial(call_mu_);  // one batched call at a time
+    int dev = 0;
+    HODLR_HIP(hipGetDevice(&dev));
+    hipEvent_t start = nullptr;
+    HODLR_HIP(hipEventCreateWithFlags(&start, hipEventDisableTiming));
+    const hipError_t er = hipEventRecord(start, caller);
+    if (er != hipSuccess) {
+      (void)hipEventDestroy(start);
+      return fail(HODLR_EHIP, std::string("hipEventRecord: ") + hipGetErrorString(er));
+    }
+    std::vector<int> codes(nitems, HODLR_OK);
+    std::vector<std::string> msgs(nitems);
+    {
+      std::unique_lock<std::mutex> lk(mu_);
+      job_ = [&, dev, start](int i) {
+        hipStream_t s = nullptr;
+        int st = worker_stream(dev, &s);
+        if (st == HODLR_OK) {
+          const hipError_t e = hipStreamWaitEvent(s, start, 0);
+          st = e == hipSuccess ? fn(i, s) : fail(HODLR_EHIP, std::string("hipStreamWaitEvent: ") +
+                                                                 hipGetErrorString(e));
+          if (s) {
+            const hipError_t e2 = hipStreamSynchronize(s);
+            if (st == HODLR_OK && e2 != hipSuccess)
+              st = fail(HODLR_EHIP, std::string("hipStreamSynchronize: ") + hipGetErrorString(e2));
+          }
+        }
+        codes[i] = st;
+        if (st != HODLR_OK) msgs[i] = hodlr_last_error();
+      };
+      next_ = 0;
+      count_ = nitems;
+      remaining_ = nitems;
+      ++generation_;
+      start_threads();
+    }
+    cv_.notify_all();
+    {
+      std::unique_lock<std::mutex> lk(mu_);
+      done_cv_.wait(lk, [&] { return remaining_ == 0; });
+      job_ = nullptr;
+    }
+    (void)hipEventDestroy(start);
+    for (int i = 0; i < nitems; ++i)
+      if (codes[i] != HODLR_OK) {
+        *msg = msgs[i];
+        return codes[i];
+      }
+    return HODLR_OK;
+  }
+
+ private:
+  static int worker_stream(int dev, hipStream_t* out) {
+    static thread_local hipStream_t s = nullptr;
+    static thread_local int sdev = -1;
+    HODLR_HIP(hipSetDevice(dev));
+    if (!s || sdev != dev) {
+      HODLR_HIP(hipStreamCreateWithFlags(&s, hipStreamNonBlocking));
+      sdev = dev;
+    }
+    *out = s;
+    return HODLR_OK;
+  }
+  void start_threads() {  // under mu_
+    if (!threads_.empty()) return;
+    int nt = 8;
+    if (const char* e = std::getenv("HODLR_THREADS")) nt = std::max(1, std::min(64, std::atoi(e)));
+    for (int k = 0; k < nt; ++k) threads_.emplace_back([this] { loop(); });
+  }
+  void loop() {
+    unsigned long long seen = 0;
+    for (;;) {
+      std::function<void(int)> job;
+      int i = -1;
+      {
+        std::unique_lock<std::mutex> lk(mu_);
+        cv_.wait(lk, [&] { return generation_ != seen && next_ < count_; });
+        i = next_++;
+        if (next_ >= count_) seen = generation_;
+        job = job_;
+      }
+      job(i);
+      {
+        std::lock_guard<std::mutex> lk(mu_);
+        if (--remaining_ == 0) done_cv_.notify_all();
+      }
+    }
+  }
+  std::mutex call_mu_, mu_;
+  std::condition_variable cv_, done_cv_;
+  std::vector<std::thread> threads_;
+  std::function<void(int)> job_;
+  int next_ = 0, count_ = 0, remaining_ = 0;
+  unsigned long long generation_ = 0;
+};
 
 }  // namespace hodlr
 
@@ -580,6 +693,48 @@ int gmres_solve(const double* K, int n, int ldk, hodlr_t precond, const double* 
   }
   return gmres_impl(K, n, ldk, precond, B, nrhs, ldb, X, ldx, tol, maxit, restart, iters, relres,
                     stream);
+}
+
+int hodlr_build_batched(int nf, const double* const* K, const int* n, const int* ldk,
+                        const int* const* g_rowptr, const int* const* g_col, const float* const* coords,
+                        const hodlr_opts* opts, hipStream_t stream, hodlr_t* out) {
+  if (nf < 1 || nf > 65536) return fail(HODLR_EINVAL, "nf must be in [1, 65536]");
+  if (!K || !n || !ldk || !out) return fail(HODLR_EINVAL, "K, n, ldk or out is NULL");
+  for (int f = 0; f < nf; ++f) out[f] = nullptr;
+  std::string msg;
+  const int st = Workers::get().run(
+      nf,
+      [&](int f, hipStream_t s) {
+        return hodlr_build(K[f], n[f], ldk[f], g_rowptr ? g_rowptr[f] : nullptr, g_col ? g_col[f] : nullptr,
+                           coords ? coords[f] : nullptr, opts, s, &out[f]);
+      },
+      stream, &msg);
+  if (st != HODLR_OK) {
+    for (int f = 0; f < nf; ++f) {
+      if (out[f]) hodlr_destroy(out[f]);
+      out[f] = nullptr;
+    }
+    return fail(st, msg);
+  }
+  return HODLR_OK;
+}
+
+int gmres_solve_batched(int nf, const double* const* K, const int* n, const int* ldk, const hodlr_t* precond,
+                        const double* const* B, int nrhs, const int* ldb, double* const* X, const int* ldx,
+                        double tol, int maxit, int restart, int* iters, double* relres, hipStream_t stream) {
+  if (nf < 1 || nf > 65536) return fail(HODLR_EINVAL, "nf must be in [1, 65536]");
+  if (!K || !n || !ldk || !B || !ldb || !X || !ldx || !iters || !relres)
+    return fail(HODLR_EINVAL, "NULL argument array");
+  std::string msg;
+  const int st = Workers::get().run(
+      nf,
+      [&](int f, hipStream_t s) {
+        return gmres_solve(K[f], n[f], ldk[f], precond ? precond[f] : nullptr, B[f], nrhs, ldb[f], X[f], ldx[f],
+                           tol, maxit, restart, iters + (size_t)f * nrhs, relres + (size_t)f * nrhs, s);
+      },
+      stream, &msg);
+  if (st != HODLR_OK) return fail(st, msg);
+  return HODLR_OK;
 }
 
 int hodlr_order_rcb(const float* coords, int n, int leaf, int* perm, hipStream_t stream) {

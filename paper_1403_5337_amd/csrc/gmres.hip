@@ -344,11 +344,12 @@ struct GmresWork {
   DevBuf V, Z, w, part, hA, hB, hcol, H, cs, sn, g, y, npart, scal, bnorm, relres, ints;
   int* host_flags = nullptr;  // pinned: [0, 64) cycle start, [64, 192) two step slots
   hipEvent_t ev[2] = {nullptr, nullptr};
-  std::mutex mu;
 };
 
+// One workspace per host thread, so solves on different threads (each on its
+// own stream) run side by side; it lives as long as its thread.
 static GmresWork& work() {
-  static GmresWork* ws = new GmresWork();  // lives until the process ends
+  static thread_local GmresWork* ws = new GmresWork();
   return *ws;
 }
 
@@ -371,7 +372,6 @@ static int gmres_t(const double* K, int n, int ldk, hodlr_s* M, const double* B,
                    double* X, int ldx, double tol, int maxit, int m, int* iters, double* relres,
                    hipStream_t st) {
   GmresWork& ws = work();
-  std::lock_guard<std::mutex> lock(ws.mu);
   const int m1 = m + 1;
   const int nch = (n + kRowsPerWG - 1) / kRowsPerWG;
   const int nsplit = (n + kMatvecCols - 1) / kMatvecCols;

@@ -187,7 +187,7 @@ int apply_impl(hodlr_s* h, void* X, int ldx, int nrhs, hipStream_t s);  // in pl
 size_t solve_partial_elems(const hodlr_s* h);
 
 // api.hip: streams for work that runs beside the caller's stream (default
-// priority, one pair per process, created on first use)
+// priority, one pair per host thread, created on first use)
 int side_stream(int which, hipStream_t* out);
 
 // prof.hip: event timing of wrapped launches (hodlr_prof_enable)

@@ -12,6 +12,10 @@
 #include <algorithm>
 #include <cfloat>
 #include <climits>
+#include <map>
+#include <mutex>
+#include <tuple>
+#include <vector>
 
 #include "device_util.h"
 #include "hodlr_internal.h"
@@ -178,21 +182,46 @@ __global__ void k_iota(int* p, int n) {
   if (i < n) p[i] = i;
 }
 
+// Node ranges of the tree of (n, leaf) on the current device, uploaded once
+// and kept for the process (a few KB each), so the ordering never waits for
+// the stream to drain before releasing them.
+static int tree_ranges(const Tree& t, const int** lo, const int** hi) {
+  static std::mutex mu;
+  static std::map<std::tuple<int, int, int>, std::pair<int*, int*>> cache;
+  int dev = 0;
+  HODLR_HIP(hipGetDevice(&dev));
+  std::lock_guard<std::mutex> lk(mu);
+  auto key = std::make_tuple(dev, t.n, t.leaf);
+  auto it = cache.find(key);
+  if (it == cache.end()) {
+    const size_t nn = t.nnodes();
+    int* d = nullptr;
+    HODLR_HIP(hipMalloc(&d, 2 * nn * sizeof(int)));
+    std::vector<int> h(2 * nn);
+    std::copy(t.lo.begin(), t.lo.end(), h.begin());
+    std::copy(t.hi.begin(), t.hi.end(), h.begin() + nn);
+    const hipError_t e = hipMemcpy(d, h.data(), 2 * nn * sizeof(int), hipMemcpyHostToDevice);
+    if (e != hipSuccess) {
+      (void)hipFree(d);
+      return fail(HODLR_EHIP, std::string("hipMemcpy: ") + hipGetErrorString(e));
+    }
+    it = cache.emplace(key, std::make_pair(d, d + nn)).first;
+  }
+  *lo = it->second.first;
+  *hi = it->second.second;
+  return HODLR_OK;
+}
+
 int launch_rcb(const float* coords, int n, const Tree& t, int* perm, hipStream_t s) {
   k_iota<<<(n + kBlock - 1) / kBlock, kBlock, 0, s>>>(perm, n);
   HODLR_HIP(hipGetLastError());
   if (t.L == 0) return HODLR_OK;
-  DevBuf dlo, dhi;
-  const int nn = t.nnodes();
-  HODLR_TRY(dlo.ensure(nn * sizeof(int)));
-  HODLR_TRY(dhi.ensure(nn * sizeof(int)));
-  HODLR_HIP(hipMemcpyAsync(dlo.p, t.lo.data(), nn * sizeof(int), hipMemcpyHostToDevice, s));
-  HODLR_HIP(hipMemcpyAsync(dhi.p, t.hi.data(), nn * sizeof(int), hipMemcpyHostToDevice, s));
+  const int *dlo = nullptr, *dhi = nullptr;
+  HODLR_TRY(tree_ranges(t, &dlo, &dhi));
   for (int p = 0; p < t.L; ++p) {
-    k_rcb_level<<<1 << p, kRcbThreads, 0, s>>>(coords, perm, dlo.as<int>(), dhi.as<int>(), node_id(p, 0));
+    k_rcb_level<<<1 << p, kRcbThreads, 0, s>>>(coords, perm, dlo, dhi, node_id(p, 0));
     HODLR_HIP(hipGetLastError());
   }
-  HODLR_HIP(hipStreamSynchronize(s));  // dlo/dhi are released on return
   return HODLR_OK;
 }
 
@@ -266,30 +295,31 @@ __global__ void k_new_degree(const int* __restrict__ rowptr, const int* __restri
   if (i < n) deg[i] = rowptr[perm[i] + 1] - rowptr[perm[i]];
 }
 
-// Exclusive scan of deg into rowptr_out[0..n] by one workgroup.
+// Exclusive scan of deg into rowptr_out[0..n] by one workgroup: thread t sums
+// its contiguous chunk, the 256 chunk sums are scanned in LDS, and each
+// thread writes its chunk's running sums.
 __global__ void __launch_bounds__(kBlock) k_scan(const int* __restrict__ deg, int* __restrict__ out, int n) {
   __shared__ int part[kBlock];
-  __shared__ int carry;
   const int t = threadIdx.x;
-  if (t == 0) carry = 0;
+  const int per = (n + kBlock - 1) / kBlock;
+  const int b = min(n, t * per), e = min(n, b + per);
+  int sum = 0;
+#pragma unroll 8
+  for (int i = b; i < e; ++i) sum += deg[i];
+  part[t] = sum;
   __syncthreads();
-  for (int base = 0; base < n; base += kBlock) {
-    const int i = base + t;
-    const int v = i < n ? deg[i] : 0;
-    part[t] = v;
+  for (int o = 1; o < kBlock; o <<= 1) {
+    const int add = t >= o ? part[t - o] : 0;
     __syncthreads();
-    for (int o = 1; o < kBlock; o <<= 1) {
-      const int add = t >= o ? part[t - o] : 0;
-      __syncthreads();
-      part[t] += add;
-      __syncthreads();
-    }
-    if (i < n) out[i] = carry + part[t] - v;
-    __syncthreads();
-    if (t == kBlock - 1) carry += part[t];
+    part[t] += add;
     __syncthreads();
   }
-  if (t == 0) out[n] = carry;
+  int run = t > 0 ? part[t - 1] : 0;
+  for (int i = b; i < e; ++i) {
+    out[i] = run;
+    run += deg[i];
+  }
+  if (t == kBlock - 1) out[n] = part[kBlock - 1];
 }
 
 __global__ void k_fill_sorted(const int* __restrict__ rowptr, const int* __restrict__ col,
@@ -311,16 +341,20 @@ __global__ void k_fill_sorted(const int* __restrict__ rowptr, const int* __restr
 
 int launch_permute_graph(const int* rowptr, const int* col, int n, const int* perm,
                          int* rowptr_out, int* col_out, hipStream_t s) {
-  DevBuf inv, deg;
-  HODLR_TRY(inv.ensure(n * sizeof(int)));
-  HODLR_TRY(deg.ensure(n * sizeof(int)));
+  // the two scratch arrays are allocated and freed in stream order, so the
+  // call returns without waiting for its kernels
+  int* scratch = nullptr;
+  HODLR_HIP(hipMallocAsync(reinterpret_cast<void**>(&scratch), 2 * (size_t)n * sizeof(int), s));
+  int* inv = scratch;
+  int* deg = scratch + n;
   const int g = (n + kBlock - 1) / kBlock;
-  k_inverse_perm<<<g, kBlock, 0, s>>>(perm, inv.as<int>(), n);
-  k_new_degree<<<g, kBlock, 0, s>>>(rowptr, perm, deg.as<int>(), n);
-  k_scan<<<1, kBlock, 0, s>>>(deg.as<int>(), rowptr_out, n);
-  k_fill_sorted<<<g, kBlock, 0, s>>>(rowptr, col, perm, inv.as<int>(), rowptr_out, col_out, n);
-  HODLR_HIP(hipGetLastError());
-  HODLR_HIP(hipStreamSynchronize(s));
+  k_inverse_perm<<<g, kBlock, 0, s>>>(perm, inv, n);
+  k_new_degree<<<g, kBlock, 0, s>>>(rowptr, perm, deg, n);
+  k_scan<<<1, kBlock, 0, s>>>(deg, rowptr_out, n);
+  k_fill_sorted<<<g, kBlock, 0, s>>>(rowptr, col, perm, inv, rowptr_out, col_out, n);
+  const hipError_t le = hipGetLastError();
+  HODLR_HIP(hipFreeAsync(scratch, s));
+  if (le != hipSuccess) return fail(HODLR_EHIP, std::string("graph permutation launch: ") + hipGetErrorString(le));
   return HODLR_OK;
 }
 

@@ -60,6 +60,13 @@ _SIGNATURES = {
     "gmres_solve": (ctypes.c_int, [_vp, ctypes.c_int, ctypes.c_int, _vp, _vp, ctypes.c_int, ctypes.c_int,
                                    _vp, ctypes.c_int, ctypes.c_double, ctypes.c_int, ctypes.c_int,
                                    _c_int_p, _c_dbl_p, _vp]),
+    "hodlr_build_batched": (ctypes.c_int, [ctypes.c_int, ctypes.POINTER(_vp), _c_int_p, _c_int_p,
+                                           ctypes.POINTER(_vp), ctypes.POINTER(_vp), ctypes.POINTER(_vp),
+                                           ctypes.POINTER(Opts), _vp, ctypes.POINTER(_vp)]),
+    "gmres_solve_batched": (ctypes.c_int, [ctypes.c_int, ctypes.POINTER(_vp), _c_int_p, _c_int_p,
+                                           ctypes.POINTER(_vp), ctypes.POINTER(_vp), ctypes.c_int, _c_int_p,
+                                           ctypes.POINTER(_vp), _c_int_p, ctypes.c_double, ctypes.c_int,
+                                           ctypes.c_int, _c_int_p, _c_dbl_p, _vp]),
     "hodlr_order_rcb": (ctypes.c_int, [_vp, ctypes.c_int, ctypes.c_int, _vp, _vp]),
     "hodlr_permute": (ctypes.c_int, [_vp, ctypes.c_int, ctypes.c_int, _vp, _vp, ctypes.c_int, _vp]),
     "hodlr_permute_graph": (ctypes.c_int, [_vp, _vp, ctypes.c_int, _vp, _vp, _vp, _vp]),
@@ -176,6 +183,47 @@ class Hodlr:
                                  _stream(stream), ctypes.byref(h)))
         return cls(h, n, precision)
 
+    @classmethod
+    def build_batched(cls, Ks, graphs=None, coords=None, leaf=128, tol=1e-4, method="aca", depth=1, max_rank=0,
+                      precision=32, mlp_params=None, skel_k=32, seed=0, skel_tol=0.0, max_skel=0,
+                      stream=None) -> list:
+        """hodlr_build for every front of Ks side by side (hodlr_build_batched);
+        graphs: list of (rowptr, col) or None; coords: list of (n, 3) or None."""
+        nf = len(Ks)
+        keep = []
+        Kp = (_vp * nf)()
+        ns = (ctypes.c_int * nf)()
+        lds = (ctypes.c_int * nf)()
+        for f, K in enumerate(Ks):
+            _need_gpu(K)
+            Kc, ldk = colmajor(K, torch.float64)
+            keep.append(Kc)
+            Kp[f], ns[f], lds[f] = Kc.data_ptr(), Kc.shape[0], ldk
+        rps = cps = xyzs = None
+        if graphs is not None:
+            rps, cps = (_vp * nf)(), (_vp * nf)()
+            for f, g in enumerate(graphs):
+                rp, cp = _i32(g[0]), _i32(g[1])
+                _need_gpu(rp, cp)
+                keep += [rp, cp]
+                rps[f], cps[f] = rp.data_ptr(), cp.data_ptr()
+        if coords is not None:
+            xyzs = (_vp * nf)()
+            for f, c in enumerate(coords):
+                x = c.to(torch.float32).contiguous()
+                _need_gpu(x)
+                keep.append(x)
+                xyzs[f] = x.data_ptr()
+        mcode = {"aca": HODLR_ACA, "bdlr": HODLR_BDLR, "learned": HODLR_LEARNED}[method]
+        prm = None if mlp_params is None else mlp_params.to(torch.float32).contiguous()
+        _need_gpu(prm)
+        o = Opts(leaf=leaf, tol=tol, method=mcode, bdlr_depth=depth, max_rank=max_rank, precision=precision,
+                 skel_k=skel_k, mlp_params=None if prm is None else prm.data_ptr(), seed=seed, skel_tol=skel_tol,
+                 bdlr_max_skel=max_skel)
+        out = (_vp * nf)()
+        _check(lib().hodlr_build_batched(nf, Kp, ns, lds, rps, cps, xyzs, ctypes.byref(o), _stream(stream), out))
+        return [cls(ctypes.c_void_p(out[f]), ns[f], precision) for f in range(nf)]
+
     def skel_info(self):
         """Learned builds: per level, the skeleton size kept per node (0 = ACA fallback)."""
         st = self.stats()
@@ -287,6 +335,48 @@ def gmres_solve(K: torch.Tensor, B: torch.Tensor, precond: Optional[Hodlr] = Non
     if st not in (HODLR_OK, HODLR_ENOCONV) or (raise_on_noconv and st == HODLR_ENOCONV):
         _check(st)
     return X, list(it), list(rr), st
+
+
+def gmres_solve_batched(Ks, Bs, preconds=None, X0s=None, tol=1e-12, maxit=1000, restart=200, stream=None,
+                        raise_on_noconv=False):
+    """gmres_solve for every front side by side (gmres_solve_batched); all
+    Bs have the same number of columns.  Returns (Xs, iters[f][k],
+    relres[f][k], status)."""
+    nf = len(Ks)
+    keep, Xs = [], []
+    Kp, Bp, Xp = (_vp * nf)(), (_vp * nf)(), (_vp * nf)()
+    ns, ldk, ldb, ldx = ((ctypes.c_int * nf)() for _ in range(4))
+    s = None
+    for f in range(nf):
+        _need_gpu(Ks[f], Bs[f])
+        Kc, lk = colmajor(Ks[f], torch.float64)
+        Bc, lb = colmajor(Bs[f], torch.float64)
+        n, sf = Bc.shape
+        if s is None:
+            s = sf
+        elif sf != s:
+            raise HodlrError(HODLR_EINVAL, "every front needs the same number of right-hand sides")
+        X = torch.zeros((s, n), dtype=torch.float64, device=Bs[f].device).t()
+        if X0s is not None and X0s[f] is not None:
+            X.copy_(X0s[f].reshape(n, s))
+        keep += [Kc, Bc]
+        Xs.append(X)
+        Kp[f], Bp[f], Xp[f] = Kc.data_ptr(), Bc.data_ptr(), X.data_ptr()
+        ns[f], ldk[f], ldb[f], ldx[f] = n, lk, lb, n
+    pp = None
+    if preconds is not None:
+        pp = (_vp * nf)()
+        for f, h in enumerate(preconds):
+            pp[f] = None if h is None else h.handle
+    it = (ctypes.c_int * (nf * s))()
+    rr = (ctypes.c_double * (nf * s))()
+    st = lib().gmres_solve_batched(nf, Kp, ns, ldk, pp, Bp, s, ldb, Xp, ldx, tol, maxit, restart, it, rr,
+                                   _stream(stream))
+    if st not in (HODLR_OK, HODLR_ENOCONV) or (raise_on_noconv and st == HODLR_ENOCONV):
+        _check(st)
+    its = [list(it[f * s:(f + 1) * s]) for f in range(nf)]
+    rrs = [list(rr[f * s:(f + 1) * s]) for f in range(nf)]
+    return Xs, its, rrs, st
 
 
 def hodlr_order_rcb(coords: torch.Tensor, leaf: int, stream=None) -> torch.Tensor:

@@ -97,3 +97,64 @@ def test_nested_dissection_batch_end_to_end():
         assert st == H.HODLR_OK
         assert np.all(dense.relres(K.cpu().numpy(), X.cpu().numpy(), B.cpu().numpy()) <= 1e-12)
         h.close()
+
+
+def _small_fronts():
+    out = []
+    for shape, seed, leaf in (((24, 20, 3), 11, 40), ((32, 16, 5), 12, 48), ((20, 20, 3), 13, 40),
+                              ((28, 24, 3), 14, 64)):
+        f = fronts.tpfa_front(shape, zs=shape[2] // 2, sigma=1.0, seed=seed, device="cuda")
+        K, rp, ci, xyz = S.order_front(f, leaf)
+        out.append((K, rp, ci, leaf))
+    return out
+
+
+def test_batched_build_and_gmres_match_single_calls_bitwise():
+    fr = _small_fronts()
+    # one leaf size per call: group by leaf
+    for leaf in sorted({x[3] for x in fr}):
+        grp = [x for x in fr if x[3] == leaf]
+        say("batched build + GMRES, leaf", leaf, "sizes", [x[0].shape[0] for x in grp])
+        single = [H.Hodlr.build(K, leaf=leaf, tol=1e-4, method="bdlr", depth=2, graph=(rp, ci))
+                  for K, rp, ci, _ in grp]
+        batch = H.Hodlr.build_batched([x[0] for x in grp], graphs=[(x[1], x[2]) for x in grp], leaf=leaf,
+                                      tol=1e-4, method="bdlr", depth=2)
+        for a, b in zip(single, batch):
+            assert a.stats() == b.stats()
+            a.factor()
+        H.hodlr_factor_batched(batch)
+        Bs = [fronts.rhs(x[0].shape[0], 3, seed=7).cuda() for x in grp]
+        res = [H.gmres_solve(x[0], B, h, tol=1e-12) for x, B, h in zip(grp, Bs, single)]
+        Xs, its, rrs, st = H.gmres_solve_batched([x[0] for x in grp], Bs, batch, tol=1e-12)
+        assert st == H.HODLR_OK
+        for (X1, it1, rr1, st1), X2, it2, rr2 in zip(res, Xs, its, rrs):
+            assert st1 == H.HODLR_OK and it1 == it2 and rr1 == rr2
+            assert torch.equal(X1, X2)
+            assert max(rr2) <= 1e-12
+        for h in single + batch:
+            h.close()
+
+
+def test_batched_gmres_reports_lowest_failing_front_and_runs_all():
+    fr = _small_fronts()[:2]
+    Ks = [x[0] for x in fr]
+    Bs = [fronts.rhs(K.shape[0], 2, seed=9).cuda() for K in Ks]
+    # no preconditioner and a tiny maxit: every front stops above tol
+    Xs, its, rrs, st = H.gmres_solve_batched(Ks, Bs, None, tol=1e-12, maxit=3, restart=3)
+    assert st == H.HODLR_ENOCONV
+    assert all(max(i) == 3 for i in its) and all(min(r) > 1e-12 for r in rrs)
+    with pytest.raises(H.HodlrError) as ei:
+        H.gmres_solve_batched(Ks, Bs, None, tol=1e-12, maxit=3, restart=3, raise_on_noconv=True)
+    assert "front 0" in str(ei.value) or "maxit" in str(ei.value)
+
+
+def test_bdlr_build_reports_a_singular_leaf_at_factor_time():
+    K, rp, ci, leaf = _small_fronts()[0]
+    K = K.clone()
+    K[5, :] = 0.0
+    K[:, 5] = 0.0  # dof 5 decouples: its leaf block is singular
+    h = H.Hodlr.build(K, leaf=leaf, tol=1e-4, method="bdlr", depth=2, graph=(rp, ci))
+    with pytest.raises(H.HodlrError) as ei:
+        h.factor()
+    assert ei.value.status == H.HODLR_ESINGULAR and "leaf" in str(ei.value)
+    h.close()
