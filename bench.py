@@ -245,7 +245,7 @@ def main_batch(args):
         "config": {"workload": "nd64", "fronts": len(fr), "sizes": sorted({f.n for f in fr}), "nrhs_per_front": s,
                    "leaf": 128, "compression": "bdlr", "bdlr_depth": 2, "tol": 1e-4, "hodlr_precision": "f32",
                    "gmres_tol": 1e-12},
-        "stage_ms": stage, "iters_max_per_front": its, "relres_max": max(rrs),
+        "stage_ms": stage, "tuned": H.hodlr_tune_report(), "iters_max_per_front": its, "relres_max": max(rrs),
         "gpu_dense_lu_ms": None if lu_ms is None else round(lu_ms, 3),
         "speedup_vs_gpu_dense_lu": None if lu_ms is None else round(lu_ms / ms, 3),
     }), flush=True)
@@ -389,6 +389,7 @@ def main():
                    "tol": tol, "hodlr_precision": "f32" if prec == 32 else "f64", "gmres_tol": 1e-12},
         "stage_ms": stage_timed,
         "stage_ms_profiled": stage_ms,
+        "tuned": H.hodlr_tune_report(),
         "profiled_steps": nprof,
         "bdlr_depth": args.depth if args.method == "bdlr" else None,
         "iters": it,

@@ -306,6 +306,14 @@ int hodlr_destroy(hodlr_t h);
  * device).  The library keeps freed device memory for reuse otherwise. */
 int hodlr_release_memory(void);
 
+/* Launch variants chosen by the library's autotuner: the split width of the
+ * float64 matvec is picked per (n, right-hand-side block, type of z) by timing
+ * each width on the first product of that shape (HODLR_TUNE=0 in the
+ * environment keeps the default).  Writes one "key=choice" line per tuned
+ * shape into buf (NUL-terminated, at most len bytes).  Errors: EINVAL if buf
+ * is NULL or too short. */
+int hodlr_tune_report(char* buf, int len);
+
 /* Kernel timing for benchmarks.  hodlr_prof_enable(1) clears earlier records
  * and makes the library record a HIP event pair around each launch of its
  * main kernels, on the launch stream; hodlr_prof_enable(0) stops recording.

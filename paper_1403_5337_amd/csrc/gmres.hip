@@ -25,7 +25,8 @@
 namespace hodlr {
 
 constexpr int kRowsPerWG = 256;
-constexpr int kMatvecCols = 128;  // columns of K per workgroup (split-K)
+constexpr int kMatvecCols = 128;     // default columns of K per workgroup (split-K)
+constexpr int kMatvecColsMin = 64;   // narrowest split the tuner tries (sizes the partial sums)
 constexpr int kMaxRestart = 512;
 
 // part[(sp s + k) n + i] = sum over the columns c of split sp of K(i, c)
@@ -38,20 +39,20 @@ constexpr int kMaxRestart = 512;
 // cores only keep the instruction count per byte low.
 typedef double f64x4 __attribute__((ext_vector_type(4)));
 
-template <typename TZ, int NB>
+template <typename TZ, int NB, int COLS>
 __global__ void __launch_bounds__(kRowsPerWG)
     k_matvec_mfma(const double* __restrict__ K, int ldk, int n, const TZ* __restrict__ src, int lds, int s,
                   double* __restrict__ part) {
-  constexpr int kQ = kMatvecCols / 4;
-  __shared__ double zs[kMatvecCols * 16 * NB];  // z(c, k) at zs[c 16 NB + k]
+  constexpr int kQ = COLS / 4;
+  __shared__ double zs[COLS * 16 * NB];  // z(c, k) at zs[c 16 NB + k]
   const int t = threadIdx.x, lane = t & 63, w = t >> 6, sp = blockIdx.y;
-  const int c0 = sp * kMatvecCols, cn = min(kMatvecCols, n - c0);
+  const int c0 = sp * COLS, cn = min(COLS, n - c0);
   const int m = lane & 15, kl = lane >> 4;
   const int row = blockIdx.x * 64 + 16 * w + m;
   // z first: its loads precede those of K in the (in-order) load queue, so
   // staging it waits for z alone, and the products below start on the first
   // blocks of K while the later ones are still arriving
-  constexpr int kZ = kMatvecCols * 16 * NB / kRowsPerWG;
+  constexpr int kZ = COLS * 16 * NB / kRowsPerWG;
   double zv[kZ];
   // (addresses are clamped into range so that no load sits behind a branch;
   // the entries outside become zero afterwards)
@@ -353,17 +354,46 @@ static GmresWork& work() {
   return *ws;
 }
 
-template <typename TZ>
-static int launch_matvec(const double* K, int ldk, int n, const TZ* src, int lds, int s, double* part,
-                         hipStream_t st) {
-  const dim3 grid((n + 63) / 64, (n + kMatvecCols - 1) / kMatvecCols);
-  ProfScope prof("matvec", st);
-#define HODLR_MV(NB) k_matvec_mfma<TZ, NB><<<grid, kRowsPerWG, 0, st>>>(K, ldk, n, src, lds, s, part)
+template <typename TZ, int COLS>
+static int launch_matvec_cols(const double* K, int ldk, int n, const TZ* src, int lds, int s, double* part,
+                              hipStream_t st) {
+  const dim3 grid((n + 63) / 64, (n + COLS - 1) / COLS);
+#define HODLR_MV(NB) k_matvec_mfma<TZ, NB, COLS><<<grid, kRowsPerWG, 0, st>>>(K, ldk, n, src, lds, s, part)
   if (s <= 16) HODLR_MV(1);
   else if (s <= 32) HODLR_MV(2);
   else HODLR_MV(4);
 #undef HODLR_MV
   HODLR_HIP(hipGetLastError());
+  return HODLR_OK;
+}
+
+// Split widths the tuner chooses from (columns of K per workgroup): a
+// narrower split gives more workgroups and more loads in flight, a wider one
+// writes fewer partial sums.
+constexpr int kMatvecChoices[3] = {64, 128, 256};
+
+template <typename TZ>
+static int launch_matvec(const double* K, int ldk, int n, const TZ* src, int lds, int s, double* part, int cols,
+                         hipStream_t st) {
+  ProfScope prof("matvec", st);
+  if (cols == 64) return launch_matvec_cols<TZ, 64>(K, ldk, n, src, lds, s, part, st);
+  if (cols == 256) return launch_matvec_cols<TZ, 256>(K, ldk, n, src, lds, s, part, st);
+  return launch_matvec_cols<TZ, 128>(K, ldk, n, src, lds, s, part, st);
+}
+
+// The split width for (n, right-hand-side block, type of z): chosen on the
+// first product of that shape by timing each width (tune_choice), kept for
+// the process.
+template <typename TZ>
+static int matvec_cols(const double* K, int ldk, int n, const TZ* src, int lds, int s, double* part,
+                       hipStream_t st, int* cols) {
+  const std::string key = "matvec:" + std::to_string(n) + ":" + std::to_string((s + 15) / 16) + ":" +
+                          std::to_string(sizeof(TZ));
+  int pick = 1;
+  HODLR_TRY(tune_choice(key, 3, 1, [&](int c) {
+    return launch_matvec<TZ>(K, ldk, n, src, lds, s, part, kMatvecChoices[c], st);
+  }, st, &pick));
+  *cols = kMatvecChoices[pick];
   return HODLR_OK;
 }
 
@@ -374,12 +404,15 @@ static int gmres_t(const double* K, int n, int ldk, hodlr_s* M, const double* B,
   GmresWork& ws = work();
   const int m1 = m + 1;
   const int nch = (n + kRowsPerWG - 1) / kRowsPerWG;
-  const int nsplit = (n + kMatvecCols - 1) / kMatvecCols;
+  // partial sums sized for the narrowest split; the width itself is tuned on
+  // the first products
+  const int nsplit_max = (n + kMatvecColsMin - 1) / kMatvecColsMin;
+  int cols_d = kMatvecCols, cols_p = kMatvecCols;
   const size_t ns = (size_t)n * s;
   HODLR_TRY(ws.V.ensure(ns * m1 * sizeof(double)));
   if (M) HODLR_TRY(ws.Z.ensure(ns * m1 * sizeof(TP)));
   HODLR_TRY(ws.w.ensure(ns * sizeof(double)));
-  HODLR_TRY(ws.part.ensure(ns * nsplit * sizeof(double)));
+  HODLR_TRY(ws.part.ensure(ns * nsplit_max * sizeof(double)));
   HODLR_TRY(ws.hA.ensure((size_t)nch * s * m1 * sizeof(double)));
   HODLR_TRY(ws.hB.ensure((size_t)nch * s * m1 * sizeof(double)));
   HODLR_TRY(ws.hcol.ensure((size_t)s * m1 * sizeof(double)));
@@ -412,9 +445,9 @@ static int gmres_t(const double* K, int n, int ldk, hodlr_s* M, const double* B,
 
   while (true) {
     // true residual of the current x, start of a cycle
-    HODLR_TRY(launch_matvec<double>(K, ldk, n, X, ldx, s, part, st));
+    HODLR_TRY(matvec_cols<double>(K, ldk, n, X, ldx, s, part, st, &cols_d));
     HODLR_HIP(hipMemsetAsync(active, 0xff, s * sizeof(int), st));  // nonzero: every column
-    k_orth<0><<<gch, kRowsPerWG, 0, st>>>(n, s, 0, m1, V, w, part, nsplit, B, ldb, nullptr, nullptr,
+    k_orth<0><<<gch, kRowsPerWG, 0, st>>>(n, s, 0, m1, V, w, part, (n + cols_d - 1) / cols_d, B, ldb, nullptr, nullptr,
                                           nullptr, ws.npart.as<double>(), active);
     k_cycle_init<<<1, 64, 0, st>>>(s, m, nch, ws.npart.as<double>(), ws.bnorm.as<double>(),
                                    ws.scal.as<double>(), ws.g.as<double>(), ws.relres.as<double>(),
@@ -431,10 +464,11 @@ static int gmres_t(const double* K, int n, int ldk, hodlr_s* M, const double* B,
       if (M) {
         TP* zj = Z + (size_t)j * ns;
         HODLR_TRY(apply_impl(M, zj, n, s, st));
-        HODLR_TRY(launch_matvec<TP>(K, ldk, n, zj, n, s, part, st));
+        HODLR_TRY(matvec_cols<TP>(K, ldk, n, zj, n, s, part, st, &cols_p));
       } else {
-        HODLR_TRY(launch_matvec<double>(K, ldk, n, src_d, n, s, part, st));
+        HODLR_TRY(matvec_cols<double>(K, ldk, n, src_d, n, s, part, st, &cols_p));
       }
+      const int nsplit = (n + cols_p - 1) / cols_p;
       {
         ProfScope po("orth", st);
         k_orth<0><<<gch, kRowsPerWG, 0, st>>>(n, s, j, m1, V, w, part, nsplit, nullptr, 0, nullptr,

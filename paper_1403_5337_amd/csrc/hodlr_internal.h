@@ -5,6 +5,7 @@
 
 #include <cstddef>
 #include <cstdint>
+#include <functional>
 #include <string>
 #include <vector>
 
@@ -194,6 +195,11 @@ int side_stream(int which, hipStream_t* out);
 bool prof_on();
 void prof_suspend(bool on);  // this thread records nothing while suspended
 void prof_mark(const char* name, hipStream_t s, bool begin);
+// launch(c) for candidate c < ncand, the choice for `key` found by timing on
+// first use (see prof.hip); *pick receives it
+int tune_choice(const std::string& key, int ncand, int fallback, const std::function<int(int)>& launch,
+                hipStream_t s, int* pick);
+std::string tune_report();
 struct ProfScope {
   const char* name;
   hipStream_t s;

@@ -1,6 +1,10 @@
 // Optional per-kernel timing with HIP events recorded on the launch stream.
 // Off by default; when on, every wrapped launch records an event pair, and
 // hodlr_prof_query sums the elapsed times of one kernel name.
+#include <cstdlib>
+#include <cstring>
+#include <functional>
+#include <map>
 #include <mutex>
 #include <string>
 #include <vector>
@@ -64,6 +68,80 @@ void prof_mark(const char* name, hipStream_t s, bool begin) {
   }
 }
 
+// ---------------------------------------------------------------------------
+// Autotuning of launch variants (tune_choice): the first call for a key times
+// every candidate on the caller's stream (one warm launch, then kTuneReps
+// timed launches each, the profiler suspended), keeps the fastest for the
+// process and launches it once more, so the call's outputs are the chosen
+// variant's.  Later calls launch the kept choice; other threads asking while
+// a key is being tuned wait for it.  Under stream capture, or with
+// HODLR_TUNE=0 in the environment, the fallback runs untimed.  A choice
+// changes only how work is split (e.g. the order of partial sums).
+// ---------------------------------------------------------------------------
+namespace {
+constexpr int kTuneReps = 3;
+std::mutex g_tune_mu;
+std::map<std::string, int> g_tune;
+}  // namespace
+
+int tune_choice(const std::string& key, int ncand, int fallback, const std::function<int(int)>& launch,
+                hipStream_t s, int* pick) {
+  // one thread tunes a key while the others wait for its choice
+  std::unique_lock<std::mutex> lk(g_tune_mu);
+  auto it = g_tune.find(key);
+  if (it != g_tune.end()) {
+    *pick = it->second;
+    lk.unlock();
+    return launch(*pick);
+  }
+  const char* env = std::getenv("HODLR_TUNE");
+  hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+  HODLR_HIP(hipStreamIsCapturing(s, &cs));
+  if ((env && env[0] == '0') || cs != hipStreamCaptureStatusNone || ncand < 2) {
+    lk.unlock();
+    *pick = fallback;
+    return launch(fallback);
+  }
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  HODLR_HIP(hipEventCreate(&e0));
+  HODLR_HIP(hipEventCreate(&e1));
+  const bool was = t_suspended;
+  t_suspended = true;
+  int best = fallback, st = HODLR_OK;
+  float best_ms = 0.f;
+  for (int c = 0; c < ncand && st == HODLR_OK; ++c) {
+    st = launch(c);
+    if (st == HODLR_OK && hipEventRecord(e0, s) != hipSuccess) st = fail(HODLR_EHIP, "hipEventRecord");
+    for (int r = 0; r < kTuneReps && st == HODLR_OK; ++r) st = launch(c);
+    if (st != HODLR_OK) break;
+    if (hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess) {
+      st = fail(HODLR_EHIP, "tuning events");
+      break;
+    }
+    float ms = 0.f;
+    (void)hipEventElapsedTime(&ms, e0, e1);
+    if (c == 0 || ms < best_ms) {
+      best_ms = ms;
+      best = c;
+    }
+  }
+  t_suspended = was;
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (st != HODLR_OK) return st;
+  g_tune[key] = best;
+  lk.unlock();
+  *pick = best;
+  return launch(best);
+}
+
+std::string tune_report() {
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  std::string out;
+  for (auto& kv : g_tune) out += kv.first + "=" + std::to_string(kv.second) + "\n";
+  return out;
+}
+
 }  // namespace hodlr
 
 extern "C" {
@@ -94,3 +172,12 @@ int hodlr_prof_query(const char* name, int* launches, double* total_ms) {
 }
 
 }  // extern "C"
+
+extern "C" int hodlr_tune_report(char* buf, int len) {
+  if (!buf || len < 1) return hodlr::fail(HODLR_EINVAL, "buf is NULL or len < 1");
+  const std::string r = hodlr::tune_report();
+  const size_t k = std::min((size_t)len - 1, r.size());
+  std::memcpy(buf, r.data(), k);
+  buf[k] = 0;
+  return r.size() < (size_t)len ? HODLR_OK : hodlr::fail(HODLR_EINVAL, "buffer too short for the report");
+}

@@ -77,6 +77,7 @@ _SIGNATURES = {
     "hodlr_destroy": (ctypes.c_int, [_vp]),
     "hodlr_release_memory": (ctypes.c_int, []),
     "hodlr_last_error": (ctypes.c_char_p, []),
+    "hodlr_tune_report": (ctypes.c_int, [ctypes.c_char_p, ctypes.c_int]),
     "hodlr_prof_enable": (ctypes.c_int, [ctypes.c_int]),
     "hodlr_prof_query": (ctypes.c_int, [ctypes.c_char_p, _c_int_p, _c_dbl_p]),
 }
@@ -507,3 +508,14 @@ def hodlr_mlp_adam_step(feats, labels, params, m, v, step: int, lr: float, pos_w
     _check(lib().hodlr_mlp_adam_step(_ptr(feats), _ptr(labels), feats.shape[0], _ptr(params), _ptr(m), _ptr(v),
                                      step, lr, pos_weight, _ptr(loss), _stream(stream)))
     return float(loss.item())
+
+
+def hodlr_tune_report() -> dict:
+    """The autotuner's choices so far: {key: choice}."""
+    buf = ctypes.create_string_buffer(1 << 16)
+    _check(lib().hodlr_tune_report(buf, len(buf)))
+    out = {}
+    for line in buf.value.decode().splitlines():
+        k, v = line.split("=")
+        out[k] = int(v)
+    return out

@@ -158,3 +158,21 @@ def test_bdlr_build_reports_a_singular_leaf_at_factor_time():
         h.factor()
     assert ei.value.status == H.HODLR_ESINGULAR and "leaf" in str(ei.value)
     h.close()
+
+
+def test_matvec_split_width_is_tuned_once_per_shape():
+    K, rp, ci, leaf = _small_fronts()[1]
+    n = K.shape[0]
+    h = H.Hodlr.build(K, leaf=leaf, tol=1e-4, method="bdlr", depth=2, graph=(rp, ci))
+    h.factor()
+    B = fronts.rhs(n, 5, seed=21).cuda()
+    X1, it1, rr1, st1 = H.gmres_solve(K, B, h, tol=1e-12)
+    rep = H.hodlr_tune_report()
+    keys = [k for k in rep if k.startswith(f"matvec:{n}:")]
+    say("tuned", {k: rep[k] for k in keys})
+    assert len(keys) == 2  # float64 residual products and float32 preconditioned products
+    assert all(rep[k] in (0, 1, 2) for k in keys)
+    X2, it2, rr2, st2 = H.gmres_solve(K, B, h, tol=1e-12)  # the kept choice: the same result
+    assert st1 == st2 == H.HODLR_OK and it1 == it2 and torch.equal(X1, X2)
+    assert H.hodlr_tune_report() == rep
+    h.close()
