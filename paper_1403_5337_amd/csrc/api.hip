@@ -71,6 +71,36 @@ int dev_alloc(size_t nbytes, void** out) {
   return HODLR_OK;
 }
 
+namespace {
+std::mutex g_pin_mu;
+std::multimap<size_t, void*> g_pin_free;  // size -> block
+}  // namespace
+
+int pinned_alloc(size_t nbytes, void** out, size_t* got) {
+  nbytes = std::max<size_t>(4096, (nbytes + 4095) / 4096 * 4096);
+  {
+    std::lock_guard<std::mutex> lk(g_pin_mu);
+    auto it = g_pin_free.lower_bound(nbytes);
+    if (it != g_pin_free.end() && it->first <= 4 * nbytes) {
+      *out = it->second;
+      *got = it->first;
+      g_pin_free.erase(it);
+      return HODLR_OK;
+    }
+  }
+  void* p = nullptr;
+  HODLR_HIP(hipHostMalloc(&p, nbytes));
+  *out = p;
+  *got = nbytes;
+  return HODLR_OK;
+}
+
+void pinned_free(void* p, size_t nbytes) {
+  if (!p) return;
+  std::lock_guard<std::mutex> lk(g_pin_mu);
+  g_pin_free.emplace(nbytes, p);
+}
+
 void dev_free(void* p, size_t nbytes) {
   if (!p) return;
   nbytes = (nbytes + 255) / 256 * 256;

@@ -227,11 +227,10 @@ static int stage_tables(hodlr_s* h, const void* src, size_t bytes, void* dev, hi
   if (h->gemm_host_bytes < h->gemm_tab.bytes) {
     if (h->capturing) return fail(HODLR_EINVAL, "batched-product staging too small under graph capture");
     HODLR_HIP(hipStreamSynchronize(s));
-    if (h->gemm_host) HODLR_HIP(hipHostFree(h->gemm_host));
+    if (h->gemm_host) pinned_free(h->gemm_host, h->gemm_host_bytes);
     h->gemm_host = nullptr;
     h->gemm_host_bytes = 0;
-    HODLR_HIP(hipHostMalloc(&h->gemm_host, h->gemm_tab.bytes));
-    h->gemm_host_bytes = h->gemm_tab.bytes;
+    HODLR_TRY(pinned_alloc(h->gemm_tab.bytes, &h->gemm_host, &h->gemm_host_bytes));
   }
   char* hp = static_cast<char*>(h->gemm_host) + off;
   std::memcpy(hp, src, bytes);
@@ -332,11 +331,10 @@ int gemm_prepare(hodlr_s* h, size_t tab_bytes, size_t work_bytes, hipStream_t s)
     if (h->gemm_tab.bytes < tab_bytes) HODLR_TRY(h->gemm_tab.ensure(tab_bytes));
     if (h->gemm_work.bytes < work_bytes) HODLR_TRY(h->gemm_work.ensure(work_bytes));
     if (h->gemm_host_bytes < h->gemm_tab.bytes) {
-      if (h->gemm_host) HODLR_HIP(hipHostFree(h->gemm_host));
+      if (h->gemm_host) pinned_free(h->gemm_host, h->gemm_host_bytes);
       h->gemm_host = nullptr;
       h->gemm_host_bytes = 0;
-      HODLR_HIP(hipHostMalloc(&h->gemm_host, h->gemm_tab.bytes));
-      h->gemm_host_bytes = h->gemm_tab.bytes;
+      HODLR_TRY(pinned_alloc(h->gemm_tab.bytes, &h->gemm_host, &h->gemm_host_bytes));
     }
   }
   return HODLR_OK;

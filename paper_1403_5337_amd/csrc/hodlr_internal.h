@@ -67,6 +67,11 @@ struct Tree {
 int dev_alloc(size_t nbytes, void** out);
 void dev_free(void* p, size_t nbytes);
 void release_cached_memory();
+// pinned host blocks, kept in a process-wide cache (api.hip): pinning and
+// unpinning memory are slow driver calls, so freed blocks are reused.  A block
+// must not be returned while a copy from it may still be pending.
+int pinned_alloc(size_t nbytes, void** out, size_t* got);
+void pinned_free(void* p, size_t nbytes);
 
 // ---------------------------------------------------------------------------
 // Device buffer (RAII over the caching allocator)
@@ -132,7 +137,7 @@ struct hodlr_s {
   hodlr_s(const hodlr_s&) = delete;
   hodlr_s& operator=(const hodlr_s&) = delete;
   ~hodlr_s() {
-    if (gemm_host) (void)hipHostFree(gemm_host);
+    if (gemm_host) hodlr::pinned_free(gemm_host, gemm_host_bytes);
   }
 };
 
