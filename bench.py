@@ -90,9 +90,9 @@ def cpu_baseline(front, w, nrhs_sample, method, depth):
 # reports traffic = null until the counters are taken again.
 TRAFFIC = {
     "apply_level": {"source": "paper_1403_5337_amd/csrc/solve.hip",
-                    "sha256": "e45fc5870d4753f32880a6c8f64f7d4e54254a7a79216c3341c26272ef414b8a",
-                    "workload": "tpfa4096", "fetch_kib": 1617.5, "write_kib": 236.0,
-                    "fetch_factor": 2.0, "write_factor": 1.0, "rocprof_avg_us": 9.40},
+                    "sha256": "1d82d45c2b8b6ead97b0bd7d0293e05faaff676d5dab2c1218497abfcd6f6c5b",
+                    "workload": "tpfa4096", "fetch_kib": 1595.5, "write_kib": 236.0,
+                    "fetch_factor": 2.0, "write_factor": 1.0, "rocprof_avg_us": 7.86},
 }
 
 
