@@ -168,30 +168,62 @@ __global__ void __launch_bounds__(kBlock)
 
 // Full-pivot elimination of Ahat held in registers: thread (lane, w) of the
 // NW waves owns rows lane + 64 a and columns w + NW b of the tile.  Nothing
-// moves: pivoted rows and columns are retired, and every step applies the
-// rank-1 update of the Schur complement to the active elements only.  A step
-// costs two barriers: one to combine the waves' candidates, one to publish the
-// pivot column; each wave takes the pivot row straight from the lane that
-// holds it, and the next step's candidate is tracked during the update.  Only
+// moves: a pivot column is retired (skipped from then on, a wave-uniform
+// bit), and a pivot row is zeroed by its own update (its multiplier is p/p =
+// 1, so each entry becomes x - x = 0) and stays zero, so the largest |entry|
+// over the active columns is the pivot search over the Schur complement with
+// no row mask.  A step tracks only the per-row maxima during the update; the
+// waves' maxima are combined across one barrier, then the one wave holding
+// the maximum finds its position (lowest row, then lowest column, by ballots)
+// and publishes the pivot column before the second barrier.  Equal maxima in
+// several waves take a third barrier to agree on the lowest position.  Only
 // the pivot sequence is kept (prow, pcol: positions in Ahat).  With 16 waves
 // (1024 threads) every SIMD runs four waves, which keeps its VALU busy while
 // each wave waits on its own instruction stream.
 constexpr int kLuWaves = 16;
 constexpr int kLuBlock = 64 * kLuWaves;
 
+// Position 256 i + j of the first entry (lowest row i, then lowest column j)
+// of this wave with |x| == M over the active columns; M must be the wave's
+// own maximum, so some row maximum ma[a] equals it.
+template <typename T, int RA, int CB, int NW>
+__device__ __forceinline__ int first_position(const T (&x)[RA][CB], const T (&ma)[RA], T M, unsigned cact,
+                                              int w) {
+  int as = -1, ls = 0;
+#pragma unroll
+  for (int a = 0; a < RA; ++a) {
+    const unsigned long long bal = __ballot(ma[a] == M);
+    if (as < 0 && bal) {
+      as = a;
+      ls = __ffsll((long long)bal) - 1;
+    }
+  }
+  as = __builtin_amdgcn_readfirstlane(as);
+  ls = __builtin_amdgcn_readfirstlane(ls);
+  unsigned m = 0;
+#pragma unroll
+  for (int a = 0; a < RA; ++a)
+    if (a == as) {
+#pragma unroll
+      for (int b = 0; b < CB; ++b)
+        if ((cact >> b) & 1u) m |= (fabs(x[a][b]) == M ? 1u : 0u) << b;
+    }
+  const unsigned mb = (unsigned)__builtin_amdgcn_readlane((int)m, ls);
+  const int bs = mb ? __ffs(mb) - 1 : 0;
+  return ((ls + 64 * max(as, 0)) << 8) + w + NW * bs;
+}
+
 template <typename T, int RA, int CB, int NW>
 __device__ int full_pivot_steps(const double* __restrict__ Kb, int ldk, const int* srow, const int* scol,
                                 int nr, int nc, int kmax, T eps, int* prow, int* pcol, T* colv,
-                                T (*sv)[NW], int (*si)[NW], T* spiv) {
-  static_assert(NW <= 16, "the candidates of the waves are merged inside one 16-lane row");
+                                T (*sv)[NW], int (*si)[NW], int* spos) {
+  static_assert(NW <= 16, "the maxima of the waves are combined inside one 16-lane row");
+  static_assert(CB <= 32, "one bit per register column");
   const int t = threadIdx.x, lane = t & 63;
   const int w = __builtin_amdgcn_readfirstlane(t >> 6);
-  unsigned ract = 0;            // per lane: bit a = row lane + 64 a still active
-  unsigned long long cact = 0;  // per wave: bit b = column w + NW b still active
+  unsigned cact = 0;  // per wave: bit b = column w + NW b still active
 #pragma unroll
-  for (int a = 0; a < RA; ++a) ract |= (lane + 64 * a < nr ? 1u : 0u) << a;
-#pragma unroll
-  for (int b = 0; b < CB; ++b) cact |= (w + NW * b < nc ? 1ull : 0ull) << b;
+  for (int b = 0; b < CB; ++b) cact |= (w + NW * b < nc ? 1u : 0u) << b;
   T x[RA][CB];
 #pragma unroll
   for (int a = 0; a < RA; ++a) {
@@ -203,108 +235,95 @@ __device__ int full_pivot_steps(const double* __restrict__ Kb, int ldk, const in
       x[a][b] = (i < nr && j < nc) ? (T)Kb[(size_t)scol[j] * ldk + ri] : T(0);
     }
   }
-  // candidate: the first largest |entry| over active elements in (row,
-  // column) order, encoded 256 i + j
-  T bv;
-  int bi;
-  {
-    T bva[RA];
-    int bba[RA];
+  T ma[RA];  // per register row: largest |entry| over the active columns
 #pragma unroll
-    for (int a = 0; a < RA; ++a) {
-      bva[a] = T(-1);
-      bba[a] = 0;
-      const T rm = ((ract >> a) & 1u) ? T(1) : T(0);
+  for (int a = 0; a < RA; ++a) {
+    ma[a] = T(0);
 #pragma unroll
-      for (int b = 0; b < CB; ++b)
-        if ((cact >> b) & 1ull) {
-          const T m = fabs(x[a][b]) * rm;
-          if (m > bva[a]) {
-            bva[a] = m;
-            bba[a] = b;
-          }
-        }
-    }
-    bv = bva[0];
-    bi = lane * 256 + w + NW * bba[0];
-#pragma unroll
-    for (int a = 1; a < RA; ++a) argmax_merge(bv, bi, bva[a], (lane + 64 * a) * 256 + w + NW * bba[a]);
+    for (int b = 0; b < CB; ++b)
+      if ((cact >> b) & 1u) ma[a] = fmax(ma[a], fabs(x[a][b]));
   }
   T first = T(0);
   int r = 0;
   for (int k = 0; k < kmax; ++k) {
     const int par = k & 1;
-    wave_argmax(bv, bi);
-    if (lane == 0) {
-      sv[par][w] = bv;
-      si[par][w] = bi;
-    }
+    T lm = ma[0];
+#pragma unroll
+    for (int a = 1; a < RA; ++a) lm = fmax(lm, ma[a]);
+    const T wm = wave_max(lm);
+    if (lane == 0) sv[par][w] = wm;
     __syncthreads();
-    // the waves' candidates, merged inside the first 16-lane row
-    T pv = lane < NW ? sv[par][lane] : T(-1);
-    int flat = lane < NW ? si[par][lane] : INT_MAX;
-    argmax_merge(pv, flat, dpp_move<0xB1>(pv), dpp_move<0xB1>(flat));
-    argmax_merge(pv, flat, dpp_move<0x4E>(pv), dpp_move<0x4E>(flat));
-    argmax_merge(pv, flat, dpp_move<0x141>(pv), dpp_move<0x141>(flat));
-    argmax_merge(pv, flat, dpp_move<0x140>(pv), dpp_move<0x140>(flat));
-    pv = lane_value(pv, 0);
-    flat = __builtin_amdgcn_readlane(flat, 0);
-    if (k == 0) first = pv;
-    if (!(pv > T(0)) || pv < eps * first || !(pv < T(INFINITY))) break;
-    const int pi = flat >> 8, pj = flat & 255;
-    const int pl = pi & 63, ap = pi >> 6, wp = pj % NW, bp = pj / NW;
-    if (t == 0) {
-      prow[k] = pi;
-      pcol[k] = pj;
-    }
-    // the pivot column (register column bp of wave wp), pivot entry apart
-    if (w == wp) {
-#pragma unroll
-      for (int a = 0; a < RA; ++a) {
-        T v = x[a][0];
-#pragma unroll
-        for (int b = 1; b < CB; ++b) v = (b == bp) ? x[a][b] : v;
-        const int i = lane + 64 * a;
-        if (i == pi) *spiv = v;  // read after the barrier below, before the next write
-        colv[i] = (((ract >> a) & 1u) && i != pi) ? v : T(0);
+    // the waves' maxima, combined inside the first 16-lane row
+    const T pv = lane < NW ? sv[par][lane] : T(-1);
+    T M = pv;
+    M = sel_max(M, dpp_move<0xB1>(M));
+    M = sel_max(M, dpp_move<0x4E>(M));
+    M = sel_max(M, dpp_move<0x141>(M));
+    M = sel_max(M, dpp_move<0x140>(M));
+    M = lane_value(M, 0);
+    if (k == 0) first = M;
+    if (!(M > T(0)) || M < eps * first || !(M < T(INFINITY))) break;
+    const unsigned long long who = __ballot(lane < NW && pv == M);  // waves holding the maximum
+    int enc = -1;  // the pivot position, in the wave that holds its column
+    if (__popcll(who) == 1) {
+      if (w == __ffsll((long long)who) - 1) enc = first_position<T, RA, CB, NW>(x, ma, M, cact, w);
+    } else {
+      if ((who >> w) & 1ull) {
+        const int e = first_position<T, RA, CB, NW>(x, ma, M, cact, w);
+        if (lane == 0) si[par][w] = e;
       }
-      cact &= ~(1ull << bp);
+      __syncthreads();
+      int e = (lane < NW && ((who >> lane) & 1ull)) ? si[par][lane] : INT_MAX;
+      e = min(e, dpp_move<0xB1>(e));
+      e = min(e, dpp_move<0x4E>(e));
+      e = min(e, dpp_move<0x141>(e));
+      e = min(e, dpp_move<0x140>(e));
+      e = __builtin_amdgcn_readlane(e, 0);
+      if ((e & 255) % NW == w) enc = e;
     }
-    if (lane == pl) ract &= ~(1u << ap);
+    enc = __builtin_amdgcn_readfirstlane(enc);
+    if (enc >= 0) {
+      // publish the pivot column (the pivot row included: its multiplier is 1)
+      const int bs = (enc & 255) / NW;
+#pragma unroll
+      for (int b = 0; b < CB; ++b)
+        if (b == bs) {
+#pragma unroll
+          for (int a = 0; a < RA; ++a) colv[lane + 64 * a] = x[a][b];
+        }
+      cact &= ~(1u << bs);
+      if (lane == 0) {
+        spos[par] = enc;
+        prow[k] = enc >> 8;
+        pcol[k] = enc & 255;
+      }
+    }
     __syncthreads();
-    const T p = *spiv;
+    const int pi = spos[par], pr = pi >> 8;
+    const int pl = pr & 63, ap = pr >> 6;
+    const T p = colv[pr];
     T l[RA];
 #pragma unroll
     for (int a = 0; a < RA; ++a) l[a] = colv[lane + 64 * a] / p;
-    T bva[RA], rm[RA];
-    int bba[RA];
+    // the pivot row's entries, from the lane that holds them
+    T rv[CB];
 #pragma unroll
-    for (int a = 0; a < RA; ++a) {
-      bva[a] = T(-1);
-      bba[a] = 0;
-      rm[a] = ((ract >> a) & 1u) ? T(1) : T(0);
-    }
+    for (int a = 0; a < RA; ++a)
+      if (a == ap) {
+#pragma unroll
+        for (int b = 0; b < CB; ++b) rv[b] = lane_value(x[a][b], pl);
+      }
+#pragma unroll
+    for (int a = 0; a < RA; ++a) ma[a] = T(0);
 #pragma unroll
     for (int b = 0; b < CB; ++b)
-      if ((cact >> b) & 1ull) {
-        T v = x[0][b];
-#pragma unroll
-        for (int a = 1; a < RA; ++a) v = (ap == a) ? x[a][b] : v;
-        const T rv = lane_value(v, pl);
+      if ((cact >> b) & 1u) {
 #pragma unroll
         for (int a = 0; a < RA; ++a) {
-          x[a][b] = fma(-l[a], rv, x[a][b]);
-          const T m = fabs(x[a][b]) * rm[a];
-          if (m > bva[a]) {
-            bva[a] = m;
-            bba[a] = b;
-          }
+          x[a][b] = fma(-l[a], rv[b], x[a][b]);
+          ma[a] = fmax(ma[a], fabs(x[a][b]));
         }
       }
-    bv = bva[0];
-    bi = lane * 256 + w + NW * bba[0];
-#pragma unroll
-    for (int a = 1; a < RA; ++a) argmax_merge(bv, bi, bva[a], (lane + 64 * a) * 256 + w + NW * bba[a]);
     r = k + 1;
   }
   return r;
@@ -321,8 +340,8 @@ __global__ void __launch_bounds__(kLuBlock)
   static_assert(SKEL % 64 == 0 && SKEL <= 256 && SKEL % kLuWaves == 0, "tile shape");
   __shared__ int srow[SKEL], scol[SKEL], prow[SKEL], pcol[SKEL];
   __shared__ T colv[SKEL];
-  __shared__ T sv[2][kLuWaves], spiv;
-  __shared__ int si[2][kLuWaves];
+  __shared__ T sv[2][kLuWaves];
+  __shared__ int si[2][kLuWaves], spos[2];
   const int task = blockIdx.x, t = threadIdx.x;
   const BdlrTask tk = tasks[task];
   const int nr = counts[2 * task], nc = counts[2 * task + 1];
@@ -337,13 +356,13 @@ __global__ void __launch_bounds__(kLuBlock)
   constexpr int NW = kLuWaves;
   int r;
   if (side <= 64)
-    r = full_pivot_steps<T, 1, 64 / NW, NW>(Kb, ldk, srow, scol, nr, nc, kmax, eps, prow, pcol, colv, sv, si, &spiv);
+    r = full_pivot_steps<T, 1, 64 / NW, NW>(Kb, ldk, srow, scol, nr, nc, kmax, eps, prow, pcol, colv, sv, si, spos);
   else if (side <= 128 || SKEL <= 128)
     r = full_pivot_steps<T, 2, 128 / NW, NW>(Kb, ldk, srow, scol, nr, nc, kmax, eps, prow, pcol, colv, sv, si,
-                                             &spiv);
+                                             spos);
   else
     r = full_pivot_steps<T, SKEL / 64, SKEL / NW, NW>(Kb, ldk, srow, scol, nr, nc, kmax, eps, prow, pcol, colv, sv,
-                                                      si, &spiv);
+                                                      si, spos);
   __syncthreads();
   for (int q = t; q < r; q += blockDim.x) {
     piv_out[tk.sel_off + q] = srow[prow[q]];         // picked rows in pivot order
@@ -360,7 +379,7 @@ __global__ void __launch_bounds__(kLuBlock)
 // rows, :) is the pseudo-skeleton C~ R~.  A numerically singular Ahat11 drops
 // the block (rank 0).
 template <typename T, int SKEL>
-__global__ void __launch_bounds__(kBlock)
+__global__ void __launch_bounds__(gj_threads<T>())
     k_bdlr_ginv(const double* __restrict__ K, int ldk, const BdlrTask* __restrict__ tasks,
                 const int* __restrict__ piv, T* __restrict__ inv, int* __restrict__ rank_out,
                 int* __restrict__ rank_task) {
@@ -386,7 +405,7 @@ static int launch_bdlr_lu(const double* K, int ldk, const BdlrTask* tasks, int n
                           T eps, int rcap, int* piv, T* inv, int* rank_out, int* rank_task, hipStream_t s) {
   k_bdlr_lu<T, SKEL><<<ns, kLuBlock, 0, s>>>(K, ldk, tasks, sel, cnt, eps, rcap, piv, rank_out, rank_task);
   HODLR_HIP(hipGetLastError());
-  k_bdlr_ginv<T, SKEL><<<ns, kBlock, 0, s>>>(K, ldk, tasks, piv, inv, rank_out, rank_task);
+  k_bdlr_ginv<T, SKEL><<<ns, gj_threads<T>(), 0, s>>>(K, ldk, tasks, piv, inv, rank_out, rank_task);
   HODLR_HIP(hipGetLastError());
   return HODLR_OK;
 }
@@ -617,7 +636,7 @@ static int bdlr_t(hodlr_s* h, const double* K, int ldk, const int* rowptr, const
   HODLR_HIP(hipEventRecord(ev.e[1], side));
   {
     ProfScope prof("bdlr_lu", s);
-    k_bdlr_ginv<T, SKEL><<<nt, kBlock, 0, s>>>(K, ldk, d_tasks.as<BdlrTask>(), d_piv.as<int>(), d_inv.as<T>(),
+    k_bdlr_ginv<T, SKEL><<<nt, gj_threads<T>(), 0, s>>>(K, ldk, d_tasks.as<BdlrTask>(), d_piv.as<int>(), d_inv.as<T>(),
                                                h->d_rank.as<int>(), d_rt.as<int>());
   }
   HODLR_HIP(hipGetLastError());

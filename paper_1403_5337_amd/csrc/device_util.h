@@ -171,7 +171,7 @@ __device__ __forceinline__ int wave_argmax_rows(const T (&cv)[RA], T& best) {
 }
 
 // ---------------------------------------------------------------------------
-// Blocked Gauss-Jordan inversion with partial pivoting (256 threads).
+// Blocked Gauss-Jordan inversion with partial pivoting (gj_threads<T>() threads).
 //
 // The matrix sits in LDS.  Every kGjNb = 8 pivot steps form a block.  Wave 0
 // factors the block's 8 columns (the panel) on its own, without barriers: the
@@ -182,13 +182,21 @@ __device__ __forceinline__ int wave_argmax_rows(const T (&cv)[RA], T& best) {
 // other column j amount to X(:, j) += C X_old(P, j), with P the block's pivot
 // rows and C = Z - I(:, P) for the factored panel Z: one rank-8 update.
 //
-// Look-ahead: while waves 1-3 apply block b's update to the other columns
-// (8 x 4 tiles per thread), wave 0 applies it to the next panel's columns in
+// Look-ahead: while waves 1-15 apply block b's update to the other columns
+// (small tiles per thread), wave 0 applies it to the next panel's columns in
 // its registers and factors that panel, so the updates run under the chain
 // of pivot steps.  Rows are never swapped: with p_k the pivot row of step k
 // the array ends as (P A)^-1, i.e. A^-1(r, c) = X(p_r, pinv(c)).
 // ---------------------------------------------------------------------------
 constexpr int kGjNb = 8;
+// A single wave issues a VALU op only every ~8 cycles, so the tile updates
+// need as many waves as a workgroup can hold to keep up with the panel wave;
+// the kernels that invert hold the whole CU (LDS) anyway.  Double precision
+// takes 8 waves, which leaves it 256 registers per lane.
+template <typename T>
+constexpr int gj_threads() {
+  return sizeof(T) == 8 ? 512 : 1024;
+}
 
 template <typename T, int NMAX>
 struct GjScratch {
@@ -300,30 +308,32 @@ template <typename T, int NMAX>
 __device__ __forceinline__ bool gj_panel_any(GjScratch<T, NMAX>& s, int n, int k0, int nbk, int buf, const T* Cp,
                                              int jr, unsigned& used) {
   if (n <= 64) return gj_panel<T, 1, NMAX>(s, n, k0, nbk, buf, Cp, jr, used);
-  if (n <= 128) return gj_panel<T, 2, NMAX>(s, n, k0, nbk, buf, Cp, jr, used);
-  return gj_panel<T, 3, NMAX>(s, n, k0, nbk, buf, Cp, jr, used);
+  if (NMAX <= 128 || n <= 128) return gj_panel<T, 2, NMAX>(s, n, k0, nbk, buf, Cp, jr, used);
+  return gj_panel<T, (NMAX + 63) / 64, NMAX>(s, n, k0, nbk, buf, Cp, jr, used);
 }
 
 // X(0 : n8, j) += C X_old(P, j) for the m columns listed by t' -> jj = t' < k0
-// ? t' : t' + skip (column j = jj < k0 ? jj : jj + nbk, R row jj), in 8 x 4
-// tiles taken by threads tid, tid + nthr, ...
+// ? t' : t' + skip (column j = jj < k0 ? jj : jj + nbk, R row jj), in TR x 2
+// tiles taken by threads tid, tid + nthr, ... (TR = 8 rows for float, 4 for
+// double, so the C tile stays in 64 registers).
 template <typename T, int NMAX>
 __device__ __forceinline__ void gj_tiles(GjScratch<T, NMAX>& s, const T* Cb, int n8, int m, int k0, int skip,
                                          int nbk, int tid, int nthr) {
   constexpr int ld = GjScratch<T, NMAX>::kLd;
-  const int nti = n8 >> 3, ntj = (m + 3) >> 2;
+  constexpr int TR = sizeof(T) == 8 ? 4 : 8, TC = 2;
+  const int nti = n8 / TR, ntj = (m + TC - 1) / TC;
   for (int tile = tid; tile < nti * ntj; tile += nthr) {
-    const int ti = tile % nti, tj = tile / nti, i0 = ti * 8;
-    T c[8][kGjNb];
+    const int ti = tile % nti, tj = tile / nti, i0 = ti * TR;
+    T c[TR][kGjNb];
 #pragma unroll
     for (int q = 0; q < kGjNb; ++q) {
       const T* cp = static_cast<const T*>(__builtin_assume_aligned(Cb + q * ld + i0, 16));
 #pragma unroll
-      for (int r = 0; r < 8; ++r) c[r][q] = cp[r];
+      for (int r = 0; r < TR; ++r) c[r][q] = cp[r];
     }
 #pragma unroll
-    for (int u = 0; u < 4; ++u) {
-      const int tp = tj * 4 + u;
+    for (int u = 0; u < TC; ++u) {
+      const int tp = tj * TC + u;
       if (tp >= m) break;
       const int jj = tp < k0 ? tp : tp + skip, j = jj < k0 ? jj : jj + nbk;
       const T* rp = static_cast<const T*>(__builtin_assume_aligned(s.R + jj * kGjNb, 16));
@@ -331,15 +341,15 @@ __device__ __forceinline__ void gj_tiles(GjScratch<T, NMAX>& s, const T* Cb, int
 #pragma unroll
       for (int q = 0; q < kGjNb; ++q) rv[q] = rp[q];
       T* xp = static_cast<T*>(__builtin_assume_aligned(s.X + j * ld + i0, 16));
-      T x[8];
+      T x[TR];
 #pragma unroll
-      for (int r = 0; r < 8; ++r) x[r] = xp[r];
+      for (int r = 0; r < TR; ++r) x[r] = xp[r];
 #pragma unroll
-      for (int r = 0; r < 8; ++r)
+      for (int r = 0; r < TR; ++r)
 #pragma unroll
         for (int q = 0; q < kGjNb; ++q) x[r] = fma(c[r][q], rv[q], x[r]);
 #pragma unroll
-      for (int r = 0; r < 8; ++r) xp[r] = x[r];
+      for (int r = 0; r < TR; ++r) xp[r] = x[r];
     }
   }
 }
@@ -354,8 +364,8 @@ __device__ bool gj_invert(Load load, int n, T* out, int ldo, GjScratch<T, NMAX>&
   constexpr int ld = GjScratch<T, NMAX>::kLd;
   const int t = threadIdx.x, nt = blockDim.x, lane = t & 63;
   const int n8 = (n + 7) & ~7;  // rows touched by the 8-row tiles
-  // 32 loads per thread in flight at a time
-  constexpr int kLoads = 32;
+  // 16 loads per thread in flight at a time
+  constexpr int kLoads = 16;
   for (int e0 = 0; e0 < n * n8; e0 += kLoads * nt) {
     T v[kLoads];
 #pragma unroll

@@ -73,7 +73,7 @@ __global__ void k_convert(const S* __restrict__ src, D* __restrict__ dst, size_t
 // Leaf LU (partial pivoting) kept as the explicit inverse
 // ---------------------------------------------------------------------------
 template <typename T>
-__global__ void __launch_bounds__(kBlock)
+__global__ void __launch_bounds__(gj_threads<T>())
     k_leaf_inverse(T* __restrict__ Kinv, int bmax, const int* __restrict__ lo,
                    const int* __restrict__ hi, int id0, int* __restrict__ status) {
   __shared__ GjScratch<T, (sizeof(T) == 8 ? kRankCap64 : kRankCap32)> gw;
@@ -139,7 +139,7 @@ __global__ void k_fill_int(int* p, int n, int v) {
 // in place; the other three blocks follow as batched products.
 // ---------------------------------------------------------------------------
 template <typename T>
-__global__ void __launch_bounds__(kBlock)
+__global__ void __launch_bounds__(gj_threads<T>())
     k_capacitance_inverse(const int* __restrict__ rank, int q, int rq, T* __restrict__ Sinv,
                           int* __restrict__ status) {
   __shared__ GjScratch<T, (sizeof(T) == 8 ? kRankCap64 : kRankCap32)> gw;
@@ -284,10 +284,10 @@ int launch_leaf_inverse(hodlr_s* h, int* status, hipStream_t s) {
   HODLR_HIP(hipGetLastError());
   ProfScope prof_("leaf_inverse", s);
   if (h->precision == 64)
-    k_leaf_inverse<double><<<h->nleaf, kBlock, 0, s>>>(h->Kinv.as<double>(), h->bmax, h->d_lo.as<int>(),
+    k_leaf_inverse<double><<<h->nleaf, gj_threads<double>(), 0, s>>>(h->Kinv.as<double>(), h->bmax, h->d_lo.as<int>(),
                                                        h->d_hi.as<int>(), node_id(t.L, 0), status);
   else
-    k_leaf_inverse<float><<<h->nleaf, kBlock, 0, s>>>(h->Kinv.as<float>(), h->bmax, h->d_lo.as<int>(),
+    k_leaf_inverse<float><<<h->nleaf, gj_threads<float>(), 0, s>>>(h->Kinv.as<float>(), h->bmax, h->d_lo.as<int>(),
                                                       h->d_hi.as<int>(), node_id(t.L, 0), status);
   HODLR_HIP(hipGetLastError());
   return HODLR_OK;
@@ -419,7 +419,7 @@ static int factor_t(hodlr_s* h, hipStream_t s) {
   HODLR_HIP(hipGetLastError());
   if (!h->leaves_inverted) {  // (the build may have run them beside the compression)
     ProfScope prof_("leaf_inverse", s);
-    k_leaf_inverse<T><<<h->nleaf, kBlock, 0, s>>>(h->Kinv.as<T>(), h->bmax, h->d_lo.as<int>(),
+    k_leaf_inverse<T><<<h->nleaf, gj_threads<T>(), 0, s>>>(h->Kinv.as<T>(), h->bmax, h->d_lo.as<int>(),
                                                          h->d_hi.as<int>(), node_id(L, 0),
                                                          h->status.as<int>());
   }
@@ -494,7 +494,7 @@ static int factor_t(hodlr_s* h, hipStream_t s) {
       }
       {
         ProfScope prof_("cap_inverse", s);
-        k_capacitance_inverse<T><<<np, kBlock, 0, s>>>(h->d_rank.as<int>(), q, rq, Sq, h->status.as<int>());
+        k_capacitance_inverse<T><<<np, gj_threads<T>(), 0, s>>>(h->d_rank.as<int>(), q, rq, Sq, h->status.as<int>());
       }
       HODLR_HIP(hipGetLastError());
       ProfScope prof_("schur_form", s);
