@@ -397,42 +397,15 @@ static int level_solve(hodlr_s* h, int q, T* Z, int ldz, int zcols, const T* G, 
   return HODLR_OK;
 }
 
+// The Woodbury steps of every level, leaves up (Sec. 4.2-4.3).  With rec the
+// pass only records the batched products (their task tables), launching
+// nothing; the launching pass then replays them in the same order.
 template <typename T>
-static int factor_t(hodlr_s* h, hipStream_t s) {
-  const Tree& t = h->tree;  // (tree)
+static int factor_levels(hodlr_s* h, hipStream_t s, bool rec) {
+  const Tree& t = h->tree;
   const int n = t.n, L = t.L;
-  // every buffer is sized before the first launch: the sequence below has no
-  // allocation, synchronization or pageable copy, so it can be recorded into
-  // a graph (hodlr_factor_batched)
-  if (L > 0 && h->R > 0) {
-    HODLR_TRY(ensure_work(h, 64));
-    size_t tb = 0, wb = 0;
-    for (int q = 1; q <= L; ++q) {
-      const size_t rq = h->rcols[q - 1], zc = h->off[q - 1] + rq, nq = (size_t)1 << q;
-      tb += 3 * gemm_table_bound((int)nq) + 2 * gemm_table_bound((int)nq / 2);
-      wb += nq * rq * zc * (size_t)std::max(1, t.max_size(q) / 128) * h->esize + 256;
-    }
-    HODLR_TRY(gemm_prepare(h, tb, wb, s));
-  }
-  gemm_reset(h);
-  k_fill_int<<<1, 64, 0, s>>>(h->status.as<int>(), 4, 0);
-  HODLR_HIP(hipGetLastError());
-  if (!h->leaves_inverted) {  // (the build may have run them beside the compression)
-    ProfScope prof_("leaf_inverse", s);
-    k_leaf_inverse<T><<<h->nleaf, gj_threads<T>(), 0, s>>>(h->Kinv.as<T>(), h->bmax, h->d_lo.as<int>(),
-                                                         h->d_hi.as<int>(), node_id(L, 0),
-                                                         h->status.as<int>());
-  }
-  HODLR_HIP(hipGetLastError());
-  if (L == 0 || h->R == 0) return HODLR_OK;
   T* Y = h->Y.as<T>();
   const T* W = h->W.as<T>();
-  {
-    ProfScope prof_("leaf_apply", s);
-    k_leaf_apply<T, kCT><<<dim3(h->nleaf, cdiv(h->R, kCT)), kBlock, 0, s>>>(
-        h->Kinv.as<T>(), h->bmax, h->d_lo.as<int>(), h->d_hi.as<int>(), node_id(L, 0), Y, n, h->R);
-  }
-  HODLR_HIP(hipGetLastError());
   for (int q = L; q >= 1; --q) {
     const int rq = h->rcols[q - 1], offq = h->off[q - 1];
     if (rq == 0) continue;
@@ -465,7 +438,7 @@ static int factor_t(hodlr_s* h, hipStream_t s) {
         g.ksplit = ks;
         gt.push_back(g);
       }
-      ProfScope prof_("panel_tn", s);
+      ProfScope prof_("panel_tn", s, !rec);
       HODLR_TRY(gemm_batched(h, gt, s));
     }
     // S22 <- M = I - B A, then M^-1 in place
@@ -489,15 +462,15 @@ static int factor_t(hodlr_s* h, hipStream_t s) {
     }
     {
       {
-        ProfScope prof_("schur_form", s);
+        ProfScope prof_("schur_form", s, !rec);
         HODLR_TRY(gemm_batched(h, gt, s));
       }
-      {
+      if (!rec) {
         ProfScope prof_("cap_inverse", s);
         k_capacitance_inverse<T><<<np, gj_threads<T>(), 0, s>>>(h->d_rank.as<int>(), q, rq, Sq, h->status.as<int>());
+        HODLR_HIP(hipGetLastError());
       }
-      HODLR_HIP(hipGetLastError());
-      ProfScope prof_("schur_form", s);
+      ProfScope prof_("schur_form", s, !rec);
       // S21 = -M^-1 B, S12 = -A M^-1
       gt.clear();
       for (int i = 0; i < np; ++i) {
@@ -570,11 +543,77 @@ static int factor_t(hodlr_s* h, hipStream_t s) {
       gt.push_back(g);
     }
     {
-      ProfScope prof_("form_E", s);
+      ProfScope prof_("form_E", s, !rec);
       HODLR_TRY(gemm_batched(h, gt, s));
     }
-    if (offq > 0) HODLR_TRY(level_solve<T>(h, q, Y, n, offq, G, zc, 1, s));
+    if (offq > 0 && !rec) HODLR_TRY(level_solve<T>(h, q, Y, n, offq, G, zc, 1, s));
   }
+  return HODLR_OK;
+}
+
+// Restores direct batched products when a factorization ends, also on error.
+struct GemmModeGuard {
+  hodlr_s* h;
+  ~GemmModeGuard() {
+    h->gemm_mode = kGemmDirect;
+    h->gemm_recs.clear();
+    h->gemm_rec_pos = 0;
+    h->gemm_staged = 0;
+  }
+};
+
+template <typename T>
+static int factor_t(hodlr_s* h, hipStream_t s) {
+  const Tree& t = h->tree;  // (tree)
+  const int n = t.n, L = t.L;
+  // every buffer is sized before the first launch: the sequence below has no
+  // allocation, synchronization or pageable copy, so it can be recorded into
+  // a graph (hodlr_factor_batched)
+  if (L > 0 && h->R > 0) {
+    HODLR_TRY(ensure_work(h, 64));
+    size_t tb = 0, wb = 0;
+    for (int q = 1; q <= L; ++q) {
+      const size_t rq = h->rcols[q - 1], zc = h->off[q - 1] + rq, nq = (size_t)1 << q;
+      tb += 3 * gemm_table_bound((int)nq) + 2 * gemm_table_bound((int)nq / 2);
+      wb += nq * rq * zc * (size_t)std::max(1, t.max_size(q) / 128) * h->esize + 256;
+    }
+    HODLR_TRY(gemm_prepare(h, tb, wb, s));
+  }
+  GemmModeGuard guard_{h};
+  // record every batched product of the factorization, then move all their
+  // task tables with one copy
+  for (int attempt = 0;; ++attempt) {
+    gemm_reset(h);
+    h->gemm_recs.clear();
+    h->gemm_staged = 0;
+    h->gemm_replan = false;
+    h->gemm_mode = kGemmRecord;
+    if (L > 0 && h->R > 0) HODLR_TRY(factor_levels<T>(h, s, true));
+    if (!h->gemm_replan) break;
+    if (attempt >= 3) return fail(HODLR_EINVAL, "batched-product arenas keep growing");
+  }
+  HODLR_TRY(gemm_upload(h, s));
+  h->gemm_mode = kGemmReplay;
+  h->gemm_rec_pos = 0;
+  k_fill_int<<<1, 64, 0, s>>>(h->status.as<int>(), 4, 0);
+  HODLR_HIP(hipGetLastError());
+  if (!h->leaves_inverted) {  // (the build may have run them beside the compression)
+    ProfScope prof_("leaf_inverse", s);
+    k_leaf_inverse<T><<<h->nleaf, gj_threads<T>(), 0, s>>>(h->Kinv.as<T>(), h->bmax, h->d_lo.as<int>(),
+                                                         h->d_hi.as<int>(), node_id(L, 0),
+                                                         h->status.as<int>());
+  }
+  HODLR_HIP(hipGetLastError());
+  if (L == 0 || h->R == 0) return HODLR_OK;
+  T* Y = h->Y.as<T>();
+  {
+    ProfScope prof_("leaf_apply", s);
+    k_leaf_apply<T, kCT><<<dim3(h->nleaf, cdiv(h->R, kCT)), kBlock, 0, s>>>(
+        h->Kinv.as<T>(), h->bmax, h->d_lo.as<int>(), h->d_hi.as<int>(), node_id(L, 0), Y, n, h->R);
+  }
+  HODLR_HIP(hipGetLastError());
+  HODLR_TRY(factor_levels<T>(h, s, false));
+  if (h->gemm_rec_pos != h->gemm_recs.size()) return fail(HODLR_EINVAL, "batched products replayed out of step");
   return HODLR_OK;
 }
 

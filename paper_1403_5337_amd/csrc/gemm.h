@@ -29,6 +29,20 @@ struct GemmTask {
 // split partials live in per-handle arenas that the caller resets (gemm_reset)
 // once the stream has drained.
 int gemm_batched(hodlr_s* h, const std::vector<GemmTask>& tasks, hipStream_t s);
+
+// Recording.  In kGemmRecord mode a call only writes its task tables to the
+// handle's pinned staging (no copy, no launch) and keeps what its launches
+// need; gemm_upload then moves every recorded table to the device with one
+// copy, and in kGemmReplay mode each call launches the next recorded product
+// (its task list is not looked at again).  A factorization records its whole
+// product sequence first, so its tables cost one copy instead of one per call.
+enum { kGemmDirect = 0, kGemmRecord = 1, kGemmReplay = 2 };
+struct GemmRec {
+  const char* tb = nullptr;  // device table block: tasks, then the sums' tasks (o1) and parts (o2)
+  int ntasks = 0, tiles = 0, nred = 0, maxmn = 0;
+  size_t o1 = 0, o2 = 0;
+};
+int gemm_upload(hodlr_s* h, hipStream_t s);
 void gemm_reset(hodlr_s* h);
 // sizes the arenas (and the pinned staging of the task tables) up front, so
 // that a factorization needs no growth (required under graph capture)

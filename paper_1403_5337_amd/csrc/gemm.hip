@@ -213,6 +213,7 @@ static int arena_take(hodlr_s* h, DevBuf& buf, size_t& used, size_t bytes, hipSt
     HODLR_HIP(hipStreamSynchronize(s));
     HODLR_TRY(buf.ensure(std::max(2 * buf.bytes, used + bytes + (1 << 16))));
     used = 0;
+    if (h->gemm_mode == kGemmRecord) h->gemm_replan = true;  // earlier records point into the old block
   }
   *out = static_cast<char*>(buf.p) + used;
   used += bytes;
@@ -221,7 +222,8 @@ static int arena_take(hodlr_s* h, DevBuf& buf, size_t& used, size_t bytes, hipSt
 
 // Task tables are written to pinned host staging at the same offset as their
 // device copy, so an asynchronous (or captured) copy reads memory that stays
-// valid until the next factorization of the handle.
+// valid until the next factorization of the handle.  In record mode the copy
+// is left to gemm_upload.
 static int stage_tables(hodlr_s* h, const void* src, size_t bytes, void* dev, hipStream_t s) {
   const size_t off = static_cast<char*>(dev) - static_cast<char*>(h->gemm_tab.p);
   if (h->gemm_host_bytes < h->gemm_tab.bytes) {
@@ -231,15 +233,45 @@ static int stage_tables(hodlr_s* h, const void* src, size_t bytes, void* dev, hi
     h->gemm_host = nullptr;
     h->gemm_host_bytes = 0;
     HODLR_TRY(pinned_alloc(h->gemm_tab.bytes, &h->gemm_host, &h->gemm_host_bytes));
+    if (h->gemm_mode == kGemmRecord) h->gemm_replan = true;  // the tables staged so far are gone
   }
   char* hp = static_cast<char*>(h->gemm_host) + off;
   std::memcpy(hp, src, bytes);
+  if (h->gemm_mode == kGemmRecord) {
+    h->gemm_staged = std::max(h->gemm_staged, off + bytes);
+    return HODLR_OK;
+  }
   HODLR_HIP(hipMemcpyAsync(dev, hp, bytes, hipMemcpyHostToDevice, s));
+  return HODLR_OK;
+}
+
+}  // namespace
+
+int gemm_upload(hodlr_s* h, hipStream_t s) {
+  if (h->gemm_staged > 0)
+    HODLR_HIP(hipMemcpyAsync(h->gemm_tab.p, h->gemm_host, h->gemm_staged, hipMemcpyHostToDevice, s));
+  h->gemm_staged = 0;
+  return HODLR_OK;
+}
+
+template <typename T>
+static int gemm_launch(const GemmRec& r, hipStream_t s) {
+  k_gemm_batched<T><<<r.tiles, kBlock, 0, s>>>(reinterpret_cast<const TaskDev*>(r.tb), r.ntasks);
+  HODLR_HIP(hipGetLastError());
+  if (r.nred) {
+    k_gemm_reduce<T><<<dim3(std::min(64, (r.maxmn + kBlock - 1) / kBlock), (unsigned)r.nred), kBlock, 0, s>>>(
+        reinterpret_cast<const TaskDev*>(r.tb + r.o1), reinterpret_cast<const void* const*>(r.tb + r.o2));
+    HODLR_HIP(hipGetLastError());
+  }
   return HODLR_OK;
 }
 
 template <typename T>
 int gemm_batched_t(hodlr_s* h, const std::vector<GemmTask>& in, hipStream_t s) {
+  if (h->gemm_mode == kGemmReplay) {
+    if (h->gemm_rec_pos >= h->gemm_recs.size()) return fail(HODLR_EINVAL, "batched product beyond the recorded sequence");
+    return gemm_launch<T>(h->gemm_recs[h->gemm_rec_pos++], s);
+  }
   std::vector<TaskDev> tasks;
   int tiles = 0, maxmn = 0, nsplit = 0;
   size_t work_elems = 0;
@@ -290,26 +322,34 @@ int gemm_batched_t(hodlr_s* h, const std::vector<GemmTask>& in, hipStream_t s) {
       wp += (size_t)d.cstride * d.ksplit;
     }
   }
-  // one block of the table arena: tasks, then the sums' tasks and their parts
+  // one block of the table arena: tasks, then the sums' tasks and their parts,
+  // staged with one copy
   const size_t b0 = tasks.size() * sizeof(TaskDev), b1 = red.size() * sizeof(TaskDev);
   const size_t o1 = (b0 + 255) & ~(size_t)255, o2 = o1 + ((b1 + 255) & ~(size_t)255);
+  const size_t nb = nsplit ? o2 + parts.size() * sizeof(void*) : b0;
   void* tab = nullptr;
   HODLR_TRY(arena_take(h, h->gemm_tab, h->gemm_tab_used, o2 + parts.size() * sizeof(void*), s, &tab));
-  char* tb = static_cast<char*>(tab);
-  HODLR_TRY(stage_tables(h, tasks.data(), b0, tb, s));
-  k_gemm_batched<T><<<tiles, kBlock, 0, s>>>(reinterpret_cast<const TaskDev*>(tb), (int)tasks.size());
-  HODLR_HIP(hipGetLastError());
+  std::vector<char> blk(nb, 0);
+  std::memcpy(blk.data(), tasks.data(), b0);
   if (nsplit) {
-    HODLR_TRY(stage_tables(h, red.data(), b1, tb + o1, s));
-    HODLR_TRY(stage_tables(h, parts.data(), parts.size() * sizeof(void*), tb + o2, s));
-    k_gemm_reduce<T><<<dim3(std::min(64, (maxmn + kBlock - 1) / kBlock), (unsigned)red.size()), kBlock, 0, s>>>(
-        reinterpret_cast<const TaskDev*>(tb + o1), reinterpret_cast<const void* const*>(tb + o2));
-    HODLR_HIP(hipGetLastError());
+    std::memcpy(blk.data() + o1, red.data(), b1);
+    std::memcpy(blk.data() + o2, parts.data(), parts.size() * sizeof(void*));
   }
-  return HODLR_OK;
+  HODLR_TRY(stage_tables(h, blk.data(), nb, tab, s));
+  GemmRec r;
+  r.tb = static_cast<const char*>(tab);
+  r.ntasks = (int)tasks.size();
+  r.tiles = tiles;
+  r.nred = (int)red.size();
+  r.maxmn = maxmn;
+  r.o1 = o1;
+  r.o2 = o2;
+  if (h->gemm_mode == kGemmRecord) {
+    h->gemm_recs.push_back(r);
+    return HODLR_OK;
+  }
+  return gemm_launch<T>(r, s);
 }
-
-}  // namespace
 
 int gemm_batched(hodlr_s* h, const std::vector<GemmTask>& tasks, hipStream_t s) {
   return h->precision == 64 ? gemm_batched_t<double>(h, tasks, s) : gemm_batched_t<float>(h, tasks, s);

@@ -10,6 +10,7 @@
 #include <vector>
 
 #include "hodlr.h"
+#include "gemm.h"
 
 namespace hodlr {
 
@@ -128,6 +129,11 @@ struct hodlr_s {
   size_t gemm_tab_used = 0, gemm_work_used = 0;
   void* gemm_host = nullptr;  // pinned staging of the task tables
   size_t gemm_host_bytes = 0;
+  int gemm_mode = hodlr::kGemmDirect;    // direct, record or replay (gemm.h)
+  std::vector<hodlr::GemmRec> gemm_recs;  // the recorded products, in call order
+  size_t gemm_rec_pos = 0;               // next product to replay
+  size_t gemm_staged = 0;                // bytes of recorded tables in the staging
+  bool gemm_replan = false;              // an arena grew while recording: record again
   bool capturing = false;     // launches are being recorded into a graph
   hodlr::DevBuf lstatus;      // int[4]: status of the leaf inverses run by the build
   bool leaves_inverted = false;  // the build already inverted the leaf blocks
@@ -209,7 +215,7 @@ struct ProfScope {
   const char* name;
   hipStream_t s;
   bool on;
-  ProfScope(const char* n, hipStream_t st) : name(n), s(st), on(prof_on()) {
+  ProfScope(const char* n, hipStream_t st, bool enabled = true) : name(n), s(st), on(enabled && prof_on()) {
     if (on) prof_mark(name, s, true);
   }
   ~ProfScope() {
