@@ -309,7 +309,9 @@ int hodlr_release_memory(void);
 /* Launch variants chosen by the library's autotuner: the split width of the
  * float64 matvec is picked per (n, right-hand-side block, type of z) by timing
  * each width on the first product of that shape (HODLR_TUNE=0 in the
- * environment keeps the default).  Writes one "key=choice" line per tuned
+ * environment keeps the default, choice 1).  Choice c sums 64 << c columns of
+ * K per partial (64, 128, 256, or 512 as four chunks of 128 per workgroup,
+ * the last for up to 32 right-hand sides).  Writes one "key=choice" line per tuned
  * shape into buf (NUL-terminated, at most len bytes).  Errors: EINVAL if buf
  * is NULL or too short. */
 int hodlr_tune_report(char* buf, int len);

@@ -94,6 +94,68 @@ __global__ void __launch_bounds__(kRowsPerWG)
     }
 }
 
+// The same product with CH consecutive 128-column chunks per workgroup:
+// workgroup (x, sp) loads chunk c + 1 of its row block while chunk c goes
+// through the matrix cores, and writes one partial for all CH chunks, so
+// the partial sums shrink CH-fold and the grid fits the chip in one round.
+// z for all chunks is staged in LDS first (CH * 128 * 16 NB doubles).
+template <typename TZ, int NB, int CH>
+__global__ void __launch_bounds__(kRowsPerWG)
+    k_matvec_chunks(const double* __restrict__ K, int ldk, int n, const TZ* __restrict__ src, int lds, int s,
+                    double* __restrict__ part) {
+  constexpr int COLS = 128, kQ = COLS / 4, WD = CH * COLS;
+  __shared__ double zs[WD * 16 * NB];  // z(c, k) at zs[c 16 NB + k]
+  const int t = threadIdx.x, lane = t & 63, w = t >> 6, sp = blockIdx.y;
+  const int c0 = sp * WD, cn = min(WD, n - c0);
+  const int m = lane & 15, kl = lane >> 4;
+  const int row = blockIdx.x * 64 + 16 * w + m;
+  const int rowc = min(row, n - 1);
+  constexpr int kZ = WD * 16 * NB / kRowsPerWG;
+  double zv[kZ];
+#pragma unroll
+  for (int u = 0; u < kZ; ++u) {
+    const int e = t + u * kRowsPerWG, c = e / (16 * NB), k = e % (16 * NB);
+    zv[u] = (double)src[(size_t)min(k, s - 1) * lds + c0 + min(c, cn - 1)];
+  }
+  double a[2][kQ];
+#pragma unroll
+  for (int q = 0; q < kQ; ++q)
+    a[0][q] = __builtin_nontemporal_load(K + (size_t)(c0 + min(4 * q + kl, cn - 1)) * ldk + rowc);
+  __builtin_amdgcn_sched_barrier(0);  // every load is issued before the wait for z
+#pragma unroll
+  for (int u = 0; u < kZ; ++u) {
+    const int e = t + u * kRowsPerWG, c = e / (16 * NB), k = e % (16 * NB);
+    zs[e] = (c < cn && k < s) ? zv[u] : 0.0;
+  }
+  __syncthreads();
+  f64x4 acc[NB];
+#pragma unroll
+  for (int b = 0; b < NB; ++b) acc[b] = f64x4{};
+#pragma unroll
+  for (int c = 0; c < CH; ++c) {
+    if (c + 1 < CH) {
+#pragma unroll
+      for (int q = 0; q < kQ; ++q)
+        a[(c + 1) & 1][q] = __builtin_nontemporal_load(
+            K + (size_t)(c0 + min((c + 1) * COLS + 4 * q + kl, cn - 1)) * ldk + rowc);
+    }
+#pragma unroll
+    for (int q = 0; q < kQ; ++q)
+#pragma unroll
+      for (int b = 0; b < NB; ++b)  // A(m = l % 16, k = l / 16), B(k = l / 16, n = l % 16)
+        acc[b] = __builtin_amdgcn_mfma_f64_16x16x4f64(
+            a[c & 1][q], zs[(c * COLS + 4 * q + kl) * 16 * NB + 16 * b + m], acc[b], 0, 0, 0);
+  }
+  const int r0 = blockIdx.x * 64 + 16 * w + (lane >> 4);
+#pragma unroll
+  for (int b = 0; b < NB; ++b)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int r = r0 + 4 * v, k = 16 * b + m;
+      if (r < n && k < s) part[((size_t)sp * s + k) * n + r] = acc[b][v];
+    }
+}
+
 // PASS 0: w = sum of the split-K partials (minus b when residual != 0), dots
 //         of w with v_0..v_j into hout
 // PASS 1: h = sum of hin over chunks; w -= V h; hcol = h; dots into hout
@@ -367,10 +429,27 @@ static int launch_matvec_cols(const double* K, int ldk, int n, const TZ* src, in
   return HODLR_OK;
 }
 
-// Split widths the tuner chooses from (columns of K per workgroup): a
+template <typename TZ, int CH>
+static int launch_matvec_chunks(const double* K, int ldk, int n, const TZ* src, int lds, int s, double* part,
+                                hipStream_t st) {
+  const dim3 grid((n + 63) / 64, (n + 128 * CH - 1) / (128 * CH));
+  if (s <= 16)
+    k_matvec_chunks<TZ, 1, CH><<<grid, kRowsPerWG, 0, st>>>(K, ldk, n, src, lds, s, part);
+  else if (s <= 32)
+    k_matvec_chunks<TZ, 2, CH><<<grid, kRowsPerWG, 0, st>>>(K, ldk, n, src, lds, s, part);
+  else
+    return fail(HODLR_EINVAL, "chunked product: too many right-hand sides for the staged z");
+  HODLR_HIP(hipGetLastError());
+  return HODLR_OK;
+}
+
+// Split widths the tuner chooses from (columns of K per partial sum): a
 // narrower split gives more workgroups and more loads in flight, a wider one
-// writes fewer partial sums.
-constexpr int kMatvecChoices[3] = {64, 128, 256};
+// writes fewer partial sums; 512 walks 4 chunks of 128 columns per
+// workgroup, with z staged for all of them (up to 32 right-hand sides).
+constexpr int kMatvecChoices[4] = {64, 128, 256, 512};
+
+static int matvec_choices(int s) { return s <= 32 ? 4 : 3; }
 
 template <typename TZ>
 static int launch_matvec(const double* K, int ldk, int n, const TZ* src, int lds, int s, double* part, int cols,
@@ -378,6 +457,7 @@ static int launch_matvec(const double* K, int ldk, int n, const TZ* src, int lds
   ProfScope prof("matvec", st);
   if (cols == 64) return launch_matvec_cols<TZ, 64>(K, ldk, n, src, lds, s, part, st);
   if (cols == 256) return launch_matvec_cols<TZ, 256>(K, ldk, n, src, lds, s, part, st);
+  if (cols == 512) return launch_matvec_chunks<TZ, 4>(K, ldk, n, src, lds, s, part, st);
   return launch_matvec_cols<TZ, 128>(K, ldk, n, src, lds, s, part, st);
 }
 
@@ -390,7 +470,7 @@ static int matvec_cols(const double* K, int ldk, int n, const TZ* src, int lds, 
   const std::string key = "matvec:" + std::to_string(n) + ":" + std::to_string((s + 15) / 16) + ":" +
                           std::to_string(sizeof(TZ));
   int pick = 1;
-  HODLR_TRY(tune_choice(key, 3, 1, [&](int c) {
+  HODLR_TRY(tune_choice(key, matvec_choices(s), 1, [&](int c) {
     return launch_matvec<TZ>(K, ldk, n, src, lds, s, part, kMatvecChoices[c], st);
   }, st, &pick));
   *cols = kMatvecChoices[pick];

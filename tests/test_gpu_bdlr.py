@@ -137,6 +137,59 @@ def test_bdlr_float64_matches_oracle_ragged_elastic():
         assert np.linalg.norm(approx - Uo @ Vo.T) <= 1e-9 * np.linalg.norm(B), (p, i)
 
 
+def _signed_permutation_blocks(g, leaf, depth, max_skel, seed):
+    """K = 4 I plus, in every off-diagonal block of the tree, a signed partial
+    permutation between the block's picked rows and columns (the selection,
+    which is compared bit for bit above): each row and each column holds at
+    most one nonzero, +-1 mostly and +-2 for a few, so Ahat is one too."""
+    rng = np.random.default_rng(seed)
+    K = 4.0 * np.eye(g.n)
+    for p, i, lo, hi, slo, shi in _nodes(tree.levels(g.n, leaf)):
+        rows, cols = obdlr.select(g.indptr, g.indices, np.arange(lo, hi), np.arange(slo, shi), depth, max_skel)
+        rows = np.asarray(rows) % (hi - lo)  # positions inside the block
+        cols = np.asarray(cols) % (shi - slo)
+        q = min(rows.size, cols.size)
+        rs, cs = rng.permutation(rows)[:q], rng.permutation(cols)[:q]
+        keep = rng.random(q) < 0.8
+        val = rng.choice([-1.0, 1.0], size=q) * np.where(rng.random(q) < 0.05, 2.0, 1.0)
+        B = np.zeros((hi - lo, shi - slo))
+        B[rs[keep], cs[keep]] = val[keep]
+        K[lo:hi, slo:shi] = B
+    return K
+
+
+@pytest.mark.parametrize("precision", [64, 32])
+def test_bdlr_pivot_ties_take_the_lowest_position(precision):
+    """Entries of equal magnitude at every pivot step, spread over the waves
+    of the elimination (signed partial permutations): the elimination is
+    exact and L11 = I, so the factors equal the oracle's exactly, column by
+    column in pivot order; another choice among the tied entries would
+    permute or change their columns."""
+    f = fronts.make_workload("laplace1024")
+    g = fronts.permute_front(f, ordering.rcb_permutation(f.coords, 64))
+    K = _signed_permutation_blocks(g, 64, 2, SKEL[precision], seed=4)
+    graph = (torch.from_numpy(g.indptr).cuda(), torch.from_numpy(g.indices).cuda())
+    say("bdlr pivot ties, precision", precision)
+    h = H.Hodlr.build(torch.from_numpy(K).cuda(), leaf=64, tol=1e-8, method="bdlr", depth=2, precision=precision,
+                      graph=graph)
+    st = h.stats()
+    U, V = h.factors()
+    h.close()
+    U, V = U.double().cpu().numpy(), V.double().cpu().numpy()
+    offs = np.cumsum([0] + st["rcols"])
+    total = 0
+    for p, i, lo, hi, slo, shi in _nodes(tree.levels(g.n, 64)):
+        cap = min(RCAP[precision], hi - lo, shi - slo)
+        Uo, Vo = obdlr.bdlr(K[lo:hi, slo:shi], g.indptr, g.indices, np.arange(lo, hi), np.arange(slo, shi), 2,
+                            1e-8, SKEL[precision], cap)
+        r, c0 = st["ranks"][p - 1][i], offs[p - 1]
+        assert r == Uo.shape[1], (p, i, r, Uo.shape[1])
+        assert np.array_equal(U[lo:hi, c0:c0 + r], Uo), (p, i)
+        assert np.array_equal(V[slo:shi, c0:c0 + r], Vo), (p, i)
+        total += r
+    assert total > 100
+
+
 def test_bdlr_float32_quality_tpfa4096():
     f = fronts.make_workload("tpfa4096", device="cuda")
     g = fronts.permute_front(f, ordering.rcb_permutation(f.coords, 128))
