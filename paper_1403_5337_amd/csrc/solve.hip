@@ -332,15 +332,18 @@ __global__ void __launch_bounds__(kSolveThreads)
   // the group sums of both children, as [z][SM]
   const size_t usz = (size_t)rq * nc, gstride = (size_t)gin * usz;
   const int ng = upn / gin;
-  constexpr int kE = 2, kJ = 4;
+  // up to kJ slots per element in one round trip, issued in batches of 4
+  // (a batch past the last slot is skipped); the addresses are clamped into
+  // range and the entries outside the block are masked afterwards
+  constexpr int kE = 2, kJ = 16;
   for (int e0 = 0; e0 < r * SM; e0 += kE * kSolveThreads) {
     T s[kE];
     const T* p0[kE];
     bool ok[kE];
 #pragma unroll
     for (int a = 0; a < kE; ++a) {
-      const int e = e0 + t + a * kSolveThreads, z = e % r, cc = e / r;
-      ok[a] = e < r * SM && cc < nc;
+      const int e = e0 + t + a * kSolveThreads, z = e % r, cc = min(e / r, nc - 1);
+      ok[a] = e < r * SM && e / r < nc;
       const int node = (z < rb) ? 2 * par : 2 * par + 1, zz = (z < rb) ? z : z - rb;
       p0[a] = Pin + (size_t)node * upn * usz + zz + (size_t)cc * rq;
       s[a] = T(0);
@@ -348,9 +351,13 @@ __global__ void __launch_bounds__(kSolveThreads)
     for (int j0 = 0; j0 < ng; j0 += kJ) {
       T v[kE][kJ];
 #pragma unroll
-      for (int a = 0; a < kE; ++a)
+      for (int bq = 0; bq < kJ; bq += 4)
+        if (j0 + bq < ng) {
 #pragma unroll
-        for (int j = 0; j < kJ; ++j) v[a][j] = (ok[a] && j0 + j < ng) ? p0[a][(size_t)(j0 + j) * gstride] : T(0);
+          for (int a = 0; a < kE; ++a)
+#pragma unroll
+            for (int j = bq; j < bq + 4; ++j) v[a][j] = p0[a][(size_t)min(j0 + j, ng - 1) * gstride];
+        }
 #pragma unroll
       for (int a = 0; a < kE; ++a)
 #pragma unroll
@@ -360,7 +367,7 @@ __global__ void __launch_bounds__(kSolveThreads)
 #pragma unroll
     for (int a = 0; a < kE; ++a) {
       const int e = e0 + t + a * kSolveThreads;
-      if (e < r * SM) sm.tb[(e % r) * SM + e / r] = s[a];
+      if (e < r * SM) sm.tb[(e % r) * SM + e / r] = ok[a] ? s[a] : T(0);
     }
   }
   unit_pipeline<T, SM>(sm, Eu, (size_t)ldE, r, Wu, (size_t)ldw, nwc, rn, nc, xr, true, Xout + row0,
