@@ -260,62 +260,102 @@ __global__ void __launch_bounds__(kRowsPerWG)
   }
 }
 
-// One thread per right-hand side: Hessenberg column j, Givens rotation,
-// residual estimate, convergence.
-__global__ void k_givens(int s, int j, int m, int nch, const double* __restrict__ hcol,
-                         const double* __restrict__ npart, double* __restrict__ H,
-                         double* __restrict__ cs, double* __restrict__ sn, double* __restrict__ g,
-                         double* __restrict__ scal, const double* __restrict__ bnorm,
-                         int* __restrict__ active, int* __restrict__ steps, int* __restrict__ total,
-                         double tol, int maxit) {
-  const int k = threadIdx.x;
-  if (k >= s || !active[k]) return;
-  const int m1 = m + 1;
-  double hn2 = 0.0;
-  for (int c = 0; c < nch; ++c) hn2 += npart[(size_t)c * s + k];
-  const double hn = sqrt(hn2);
-  double* Hk = H + (size_t)k * m1 * m + (size_t)j * m1;
-  for (int l = 0; l <= j; ++l) Hk[l] = hcol[(size_t)k * m1 + l];
-  Hk[j + 1] = hn;
-  double* ck = cs + (size_t)k * m;
-  double* sk = sn + (size_t)k * m;
-  for (int l = 0; l < j; ++l) {
-    const double a = Hk[l], bb = Hk[l + 1];
-    Hk[l] = ck[l] * a + sk[l] * bb;
-    Hk[l + 1] = -sk[l] * a + ck[l] * bb;
+// End of step j, one launch: the Hessenberg column j, its Givens rotation,
+// the residual estimate and the convergence decision per right-hand side,
+// then v_{j+1} = w / |w| (and its copy, rounded to TP, as the next
+// preconditioner input; zero for a column that stops).  Every workgroup of
+// column k works the rotation out itself from data no workgroup writes in
+// this step (the earlier rotations, the running residual grun_in, the flags
+// act_in, the cycle's starting count tstart), so they all take the same
+// decision; workgroup 0 alone writes the results: H, the rotation, g, the
+// next running residual, the counts, the next flags act_out, and the flags
+// into host memory (pinned, read by the host after the stream event).
+template <typename TP>
+__global__ void __launch_bounds__(kBlock)
+    k_step_end(int n, int s, int j, int m, int nch, const double* __restrict__ hcol,
+               const double* __restrict__ npart, double* __restrict__ H, double* __restrict__ cs,
+               double* __restrict__ sn, double* __restrict__ g, const double* __restrict__ grun_in,
+               double* __restrict__ grun_out, double* __restrict__ scal, const double* __restrict__ bnorm,
+               const int* __restrict__ act_in, int* __restrict__ act_out, int* __restrict__ steps,
+               int* __restrict__ total, const int* __restrict__ tstart, double tol, int maxit,
+               const double* __restrict__ w, double* __restrict__ V, TP* __restrict__ Z, int* host_slot) {
+  __shared__ double s_hn;
+  __shared__ int s_go;
+  const int k = blockIdx.y, lead = blockIdx.x == 0;
+  if (threadIdx.x == 0) {
+    int go = 0;
+    double hn = 1.0;
+    if (act_in[k]) {
+      const int m1 = m + 1;
+      double hn2 = 0.0;
+      for (int c = 0; c < nch; ++c) hn2 += npart[(size_t)c * s + k];
+      hn = sqrt(hn2);
+      const double* hc = hcol + (size_t)k * m1;
+      const double* ck = cs + (size_t)k * m;
+      const double* sk = sn + (size_t)k * m;
+      double* Hk = H + (size_t)k * m1 * m + (size_t)j * m1;
+      // the earlier rotations applied down the column, one running entry
+      double cur = hc[0];
+      for (int l = 0; l < j; ++l) {
+        const double b = hc[l + 1];
+        const double o = ck[l] * cur + sk[l] * b;
+        cur = -sk[l] * cur + ck[l] * b;
+        if (lead) Hk[l] = o;
+      }
+      double c = 1.0, sv = 0.0;
+      if (hn != 0.0) {
+        const double r = hypot(cur, hn);
+        c = cur / r;
+        sv = hn / r;
+      }
+      const double g0 = grun_in[k], g1 = -sv * g0;
+      const int tot = tstart[k] + j + 1;
+      const bool conv = fabs(g1) <= tol * bnorm[k];
+      go = !(conv || tot >= maxit || !(hn > 0.0) || j + 1 >= m);
+      if (lead) {
+        cs[(size_t)k * m + j] = c;
+        sn[(size_t)k * m + j] = sv;
+        Hk[j] = c * cur + sv * hn;
+        Hk[j + 1] = 0.0;
+        g[(size_t)k * m1 + j] = c * g0;
+        g[(size_t)k * m1 + j + 1] = g1;
+        grun_out[k] = g1;
+        scal[k] = hn;
+        steps[k] = j + 1;
+        total[k] = tot;
+      }
+    }
+    if (lead) {
+      act_out[k] = go;
+      host_slot[k] = go;
+      __threadfence_system();
+    }
+    s_hn = hn;
+    s_go = go;
   }
-  double c = 1.0, sv = 0.0;
-  const double a = Hk[j], bb = Hk[j + 1];
-  if (bb != 0.0) {
-    const double r = hypot(a, bb);
-    c = a / r;
-    sv = bb / r;
+  __syncthreads();
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const size_t o = ((size_t)(j + 1) * s + k) * n + i;
+  if (s_go) {
+    const double v = w[(size_t)k * n + i] / s_hn;
+    V[o] = v;
+    if (Z) Z[o] = (TP)v;
+  } else if (Z) {
+    Z[o] = TP(0);
   }
-  ck[j] = c;
-  sk[j] = sv;
-  Hk[j] = c * a + sv * bb;
-  Hk[j + 1] = 0.0;
-  double* gk = g + (size_t)k * m1;
-  gk[j + 1] = -sv * gk[j];
-  gk[j] = c * gk[j];
-  scal[k] = hn;
-  steps[k] = j + 1;
-  total[k] += 1;
-  const bool conv = fabs(gk[j + 1]) <= tol * bnorm[k];
-  if (conv || total[k] >= maxit || !(hn > 0.0) || j + 1 >= m) active[k] = 0;
 }
 
-// v_{slot}(k) = w(k) / scal(k) for active k, copied (rounded to TP) into the
-// z slot as the next preconditioner input.  Inactive columns of the z slot
+// v_0(k) = w(k) / scal(k) for active k, copied (rounded to TP) into the z
+// slot 0 as the first preconditioner input.  Inactive columns of the z slot
 // are zeroed.
 template <typename TP>
-__global__ void k_normalize(int n, int s, int slot, const double* __restrict__ w,
-                            const double* __restrict__ scal, const int* __restrict__ active,
-                            double* __restrict__ V, TP* __restrict__ Z) {
+__global__ void k_normalize(int n, int s, const double* __restrict__ w, const double* __restrict__ scal,
+                            const int* __restrict__ active, double* __restrict__ V, TP* __restrict__ Z) {
   const int k = blockIdx.y;
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
-  const size_t o = ((size_t)slot * s + k) * n + i;
+  const size_t o = (size_t)k * n + i;
   if (active[k]) {
     const double v = w[(size_t)k * n + i] / scal[k];
     V[o] = v;
@@ -325,12 +365,15 @@ __global__ void k_normalize(int n, int s, int slot, const double* __restrict__ w
   }
 }
 
-// Start of a cycle: true residual norms, decide who iterates, g = beta e_1.
+// Start of a cycle: true residual norms, decide who iterates, g = beta e_1
+// (and the running residual), the count at the start; the flags also go to
+// host memory (pinned).
 __global__ void k_cycle_init(int s, int m, int nch, const double* __restrict__ npart,
                              const double* __restrict__ bnorm, double* __restrict__ scal,
-                             double* __restrict__ g, double* __restrict__ relres,
+                             double* __restrict__ g, double* __restrict__ grun, double* __restrict__ relres,
                              int* __restrict__ active, int* __restrict__ steps,
-                             const int* __restrict__ total, double tol, int maxit) {
+                             const int* __restrict__ total, int* __restrict__ tstart, double tol, int maxit,
+                             int* host_slot) {
   const int k = threadIdx.x;
   if (k >= s) return;
   double r2 = 0.0;
@@ -341,9 +384,13 @@ __global__ void k_cycle_init(int s, int m, int nch, const double* __restrict__ n
   const int go = (bnorm[k] > 0.0) && (rr > tol) && (total[k] < maxit) && (beta > 0.0);
   active[k] = go;
   steps[k] = 0;
+  tstart[k] = total[k];
   scal[k] = go ? beta : 1.0;
   for (int l = 0; l <= m; ++l) g[(size_t)k * (m + 1) + l] = 0.0;
   g[(size_t)k * (m + 1)] = beta;
+  grun[k] = beta;
+  host_slot[k] = go;
+  __threadfence_system();
 }
 
 __global__ void k_bnorm(int s, int nch, const double* __restrict__ npart, double* __restrict__ bnorm) {
@@ -404,8 +451,9 @@ __global__ void k_xupdate(int n, int s, int m, double* __restrict__ X, int ldx, 
 
 // ---------------------------------------------------------------------------
 struct GmresWork {
-  DevBuf V, Z, w, part, hA, hB, hcol, H, cs, sn, g, y, npart, scal, bnorm, relres, ints;
+  DevBuf V, Z, w, part, hA, hB, hcol, H, cs, sn, g, grun, y, npart, scal, bnorm, relres, ints;
   int* host_flags = nullptr;  // pinned: [0, 64) cycle start, [64, 192) two step slots
+  int* dev_flags = nullptr;   // the same memory as the device addresses it
   hipEvent_t ev[2] = {nullptr, nullptr};
 };
 
@@ -500,22 +548,31 @@ static int gmres_t(const double* K, int n, int ldk, hodlr_s* M, const double* B,
   HODLR_TRY(ws.cs.ensure((size_t)s * m * sizeof(double)));
   HODLR_TRY(ws.sn.ensure((size_t)s * m * sizeof(double)));
   HODLR_TRY(ws.g.ensure((size_t)s * m1 * sizeof(double)));
+  HODLR_TRY(ws.grun.ensure(2 * 64 * sizeof(double)));
   HODLR_TRY(ws.y.ensure((size_t)s * m * sizeof(double)));
   HODLR_TRY(ws.npart.ensure((size_t)nch * s * sizeof(double)));
   HODLR_TRY(ws.scal.ensure(s * sizeof(double)));
   HODLR_TRY(ws.bnorm.ensure(s * sizeof(double)));
   HODLR_TRY(ws.relres.ensure(s * sizeof(double)));
-  HODLR_TRY(ws.ints.ensure(3 * 64 * sizeof(int)));
-  if (!ws.host_flags) HODLR_HIP(hipHostMalloc(reinterpret_cast<void**>(&ws.host_flags), 192 * sizeof(int)));
+  HODLR_TRY(ws.ints.ensure(5 * 64 * sizeof(int)));
+  if (!ws.host_flags) {
+    HODLR_HIP(hipHostMalloc(reinterpret_cast<void**>(&ws.host_flags), 192 * sizeof(int)));
+    HODLR_HIP(hipHostGetDevicePointer(reinterpret_cast<void**>(&ws.dev_flags), ws.host_flags, 0));
+  }
   for (int e = 0; e < 2; ++e)
     if (!ws.ev[e]) HODLR_HIP(hipEventCreateWithFlags(&ws.ev[e], hipEventDisableTiming));
   double* V = ws.V.as<double>();
   TP* Z = M ? ws.Z.as<TP>() : nullptr;
   double* w = ws.w.as<double>();
   double* part = ws.part.as<double>();
-  int* active = ws.ints.as<int>();
-  int* steps = active + 64;
-  int* total = active + 128;
+  // flags of the columns still iterating, two arrays: step j reads act[j & 1]
+  // and its last kernel writes act[(j + 1) & 1]
+  int* act[2] = {ws.ints.as<int>(), ws.ints.as<int>() + 64};
+  int* active = act[0];
+  int* steps = act[0] + 128;
+  int* total = act[0] + 192;
+  int* tstart = act[0] + 256;
+  double* grun[2] = {ws.grun.as<double>(), ws.grun.as<double>() + 64};
   HODLR_HIP(hipMemsetAsync(total, 0, s * sizeof(int), st));
 
   const dim3 gch(nch, s), gvec((n + kBlock - 1) / kBlock, s);
@@ -530,15 +587,14 @@ static int gmres_t(const double* K, int n, int ldk, hodlr_s* M, const double* B,
     k_orth<0><<<gch, kRowsPerWG, 0, st>>>(n, s, 0, m1, V, w, part, (n + cols_d - 1) / cols_d, B, ldb, nullptr, nullptr,
                                           nullptr, ws.npart.as<double>(), active);
     k_cycle_init<<<1, 64, 0, st>>>(s, m, nch, ws.npart.as<double>(), ws.bnorm.as<double>(),
-                                   ws.scal.as<double>(), ws.g.as<double>(), ws.relres.as<double>(),
-                                   active, steps, total, tol, maxit);
+                                   ws.scal.as<double>(), ws.g.as<double>(), grun[0], ws.relres.as<double>(),
+                                   active, steps, total, tstart, tol, maxit, ws.dev_flags);
     HODLR_HIP(hipGetLastError());
-    HODLR_HIP(hipMemcpyAsync(ws.host_flags, active, s * sizeof(int), hipMemcpyDeviceToHost, st));
     HODLR_HIP(hipStreamSynchronize(st));
     bool any = false;
     for (int k = 0; k < s; ++k) any |= ws.host_flags[k] != 0;
     if (!any) break;
-    k_normalize<TP><<<gvec, kBlock, 0, st>>>(n, s, 0, w, ws.scal.as<double>(), active, V, Z);
+    k_normalize<TP><<<gvec, kBlock, 0, st>>>(n, s, w, ws.scal.as<double>(), active, V, Z);
     for (int j = 0; j < m; ++j) {
       const double* src_d = V + (size_t)j * ns;
       if (M) {
@@ -552,32 +608,31 @@ static int gmres_t(const double* K, int n, int ldk, hodlr_s* M, const double* B,
       {
         ProfScope po("orth", st);
         k_orth<0><<<gch, kRowsPerWG, 0, st>>>(n, s, j, m1, V, w, part, nsplit, nullptr, 0, nullptr,
-                                              ws.hA.as<double>(), nullptr, nullptr, active);
+                                              ws.hA.as<double>(), nullptr, nullptr, act[j & 1]);
       }
       {
         ProfScope po("orth", st);
         k_orth<1><<<gch, kRowsPerWG, 0, st>>>(n, s, j, m1, V, w, part, nsplit, nullptr, 0,
                                               ws.hA.as<double>(), ws.hB.as<double>(),
-                                              ws.hcol.as<double>(), nullptr, active);
+                                              ws.hcol.as<double>(), nullptr, act[j & 1]);
       }
       {
         ProfScope po("orth", st);
         k_orth<2><<<gch, kRowsPerWG, 0, st>>>(n, s, j, m1, V, w, part, nsplit, nullptr, 0,
                                               ws.hB.as<double>(), nullptr, ws.hcol.as<double>(),
-                                              ws.npart.as<double>(), active);
+                                              ws.npart.as<double>(), act[j & 1]);
       }
-      k_givens<<<1, 64, 0, st>>>(s, j, m, nch, ws.hcol.as<double>(), ws.npart.as<double>(),
-                                 ws.H.as<double>(), ws.cs.as<double>(), ws.sn.as<double>(),
-                                 ws.g.as<double>(), ws.scal.as<double>(), ws.bnorm.as<double>(),
-                                 active, steps, total, tol, maxit);
-      k_normalize<TP><<<gvec, kBlock, 0, st>>>(n, s, j + 1, w, ws.scal.as<double>(), active, V, Z);
+      // flags of step j go straight to a pinned slot, read after the event;
+      // the host waits for the flags of step j-1 only, so step j is already
+      // queued (a step taken after every column has stopped does no work:
+      // the kernels read the device flags)
+      k_step_end<TP><<<gvec, kBlock, 0, st>>>(n, s, j, m, nch, ws.hcol.as<double>(), ws.npart.as<double>(),
+                                              ws.H.as<double>(), ws.cs.as<double>(), ws.sn.as<double>(),
+                                              ws.g.as<double>(), grun[j & 1], grun[(j + 1) & 1],
+                                              ws.scal.as<double>(), ws.bnorm.as<double>(), act[j & 1],
+                                              act[(j + 1) & 1], steps, total, tstart, tol, maxit, w, V, Z,
+                                              ws.dev_flags + 64 + 64 * (j & 1));
       HODLR_HIP(hipGetLastError());
-      // flags of step j go to a pinned slot behind an event; the host waits
-      // for the flags of step j-1 only, so step j is already queued (a step
-      // taken after every column has stopped does no work: the kernels read
-      // the device flags)
-      int* slot = ws.host_flags + 64 + 64 * (j & 1);
-      HODLR_HIP(hipMemcpyAsync(slot, active, s * sizeof(int), hipMemcpyDeviceToHost, st));
       HODLR_HIP(hipEventRecord(ws.ev[j & 1], st));
       if (j > 0) {
         HODLR_HIP(hipEventSynchronize(ws.ev[(j - 1) & 1]));
