@@ -418,8 +418,8 @@ static int aca_t(hodlr_s* h, const double* K, int ldk, T* Ucap, T* Vcap,
                                          dim3(kBlock), args, (unsigned)lds, s));
   }
   }
-  // the scratch buffers are released on return: wait for the kernels
-  HODLR_HIP(hipStreamSynchronize(s));
+  // the scratch goes back to the allocator once s is past the kernels
+  for (DevBuf* b : {&d_tasks, &d_wg, &d_rec}) b->release_after(s);
   return HODLR_OK;
 }
 

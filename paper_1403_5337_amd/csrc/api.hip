@@ -31,16 +31,43 @@ int fail(int code, const std::string& msg) {
 // so repeated builds and solves do not call hipMalloc / hipFree (which also
 // synchronizes the device).  Blocks are returned only by
 // hodlr_release_memory().  A block is reused by later work on any stream, so
-// every internal temporary is released only after the work that used it has
-// been synchronized.
+// a temporary is released either after the work that used it has been
+// synchronized, or behind an event on the stream of that work
+// (dev_free_after): such a block joins the free list only once its event has
+// completed, which allocations check without waiting.
 // ---------------------------------------------------------------------------
 namespace {
 std::mutex g_alloc_mu;
 std::multimap<size_t, void*> g_free[64];
+struct PendingBlock {
+  size_t bytes;
+  void* p;
+  hipEvent_t ev;
+  int dev;
+};
+std::vector<PendingBlock> g_pending;  // released behind an event, not yet reusable
+std::vector<hipEvent_t> g_event_pool;
 int cur_device() {
   int d = 0;
   (void)hipGetDevice(&d);
   return d < 0 ? 0 : (d > 63 ? 63 : d);
+}
+// moves the pending blocks whose event has completed (all of them with
+// wait) to the free lists; g_alloc_mu held
+void collect_pending(bool wait) {
+  size_t keep = 0;
+  for (size_t i = 0; i < g_pending.size(); ++i) {
+    PendingBlock& b = g_pending[i];
+    const bool done = wait ? hipEventSynchronize(b.ev) == hipSuccess : hipEventQuery(b.ev) == hipSuccess;
+    if (done || wait) {
+      g_free[b.dev].emplace(b.bytes, b.p);
+      g_event_pool.push_back(b.ev);
+    } else {
+      g_pending[keep++] = b;
+    }
+  }
+  g_pending.resize(keep);
+  (void)hipGetLastError();  // a not-ready query leaves no error behind
 }
 }  // namespace
 
@@ -48,6 +75,7 @@ int dev_alloc(size_t nbytes, void** out) {
   nbytes = (nbytes + 255) / 256 * 256;
   {
     std::lock_guard<std::mutex> lk(g_alloc_mu);
+    if (!g_pending.empty()) collect_pending(false);
     auto& fl = g_free[cur_device()];
     auto it = fl.lower_bound(nbytes);
     if (it != fl.end() && it->first <= 2 * nbytes) {
@@ -108,16 +136,50 @@ void dev_free(void* p, size_t nbytes) {
   g_free[cur_device()].emplace(nbytes, p);
 }
 
+void dev_free_after(void* p, size_t nbytes, hipStream_t s) {
+  if (!p) return;
+  nbytes = (nbytes + 255) / 256 * 256;
+  hipEvent_t ev = nullptr;
+  {
+    std::lock_guard<std::mutex> lk(g_alloc_mu);
+    if (!g_event_pool.empty()) {
+      ev = g_event_pool.back();
+      g_event_pool.pop_back();
+    }
+  }
+  if (!ev && hipEventCreateWithFlags(&ev, hipEventDisableTiming) != hipSuccess) ev = nullptr;
+  if (!ev || hipEventRecord(ev, s) != hipSuccess) {
+    // no event: fall back to waiting for the stream
+    (void)hipGetLastError();
+    (void)hipStreamSynchronize(s);
+    dev_free(p, nbytes);
+    if (ev) {
+      std::lock_guard<std::mutex> lk(g_alloc_mu);
+      g_event_pool.push_back(ev);
+    }
+    return;
+  }
+  std::lock_guard<std::mutex> lk(g_alloc_mu);
+  g_pending.push_back({nbytes, p, ev, cur_device()});
+}
+
 void release_cached_memory() {
   std::lock_guard<std::mutex> lk(g_alloc_mu);
   int dev = cur_device();
   (void)hipDeviceSynchronize();
+  collect_pending(true);
   for (auto& kv : g_free[dev]) (void)hipFree(kv.second);
   g_free[dev].clear();
 }
 
 void DevBuf::release() {
   if (p) dev_free(p, bytes);
+  p = nullptr;
+  bytes = 0;
+}
+
+void DevBuf::release_after(hipStream_t s) {
+  if (p) dev_free_after(p, bytes, s);
   p = nullptr;
   bytes = 0;
 }
@@ -394,6 +456,21 @@ static int check_opts(const hodlr_opts& o) {
   return HODLR_OK;
 }
 
+// dst[0, na) = a, dst[na, na + 4) = b, dst[na + 4, na + 8) = c (zeros if c
+// is NULL); dst is pinned host memory, made visible to the host before the
+// kernel ends.
+__global__ void k_export_ints(const int* __restrict__ a, int na, const int* __restrict__ b,
+                              const int* __restrict__ c, int* dst) {
+  for (int i = threadIdx.x; i < na + 8; i += blockDim.x) {
+    int v = 0;
+    if (i < na) v = a[i];
+    else if (i < na + 4) v = b[i - na];
+    else if (c) v = c[i - na - 4];
+    dst[i] = v;
+  }
+  __threadfence_system();
+}
+
 static int build_impl(const double* K, int n, int ldk, const int* g_rowptr, const int* g_col,
                       const float* coords, const hodlr_opts* opts, hipStream_t stream, hodlr_t* out,
                       int* piv_export) {
@@ -466,19 +543,42 @@ static int build_impl(const double* K, int n, int ldk, const int* g_rowptr, cons
                                stream));
     else
       HODLR_TRY(launch_aca(h.get(), K, ldk, Ucap.p, Vcap.p, capoff, capq, stream, nullptr, piv_export));
-    HODLR_HIP(hipMemcpyAsync(h->rank.data(), h->d_rank.p, t.nnodes() * sizeof(int),
-                             hipMemcpyDeviceToHost, stream));
+    // the ranks, the compression's status words and those of the leaf
+    // inverses come back together, written into pinned host memory by one
+    // kernel, behind the build's one synchronization
+    if (fork.side) HODLR_HIP(hipStreamWaitEvent(stream, fork.ev[1], 0));
+    const int nn = t.nnodes();
+    void* pin = nullptr;
+    size_t pin_bytes = 0;
+    HODLR_TRY(pinned_alloc((size_t)(nn + 8) * sizeof(int), &pin, &pin_bytes));
+    struct PinGuard {
+      void* p;
+      size_t b;
+      ~PinGuard() { pinned_free(p, b); }
+    } pin_guard{pin, pin_bytes};
+    int* dpin = nullptr;
+    HODLR_HIP(hipHostGetDevicePointer(reinterpret_cast<void**>(&dpin), pin, 0));
+    k_export_ints<<<1, kBlock, 0, stream>>>(h->d_rank.as<int>(), nn, h->status.as<int>(),
+                                            fork.side ? h->lstatus.as<int>() : nullptr, dpin);
+    HODLR_HIP(hipGetLastError());
     HODLR_HIP(hipStreamSynchronize(stream));
-    int st[4];
-    HODLR_HIP(hipMemcpy(st, h->status.p, sizeof(st), hipMemcpyDeviceToHost));
-    if (st[2]) return fail(HODLR_EHIP, "ACA workgroup barrier timed out");
+    const int* hp = static_cast<const int*>(pin);
+    std::copy(hp, hp + nn, h->rank.begin());
+    if (hp[nn + 2]) return fail(HODLR_EHIP, "ACA workgroup barrier timed out");
+    if (fork.side) {
+      h->leaves_inverted = true;
+      if (hp[nn + 4]) h->leaf_singular = hp[nn + 5];
+    }
     h->rank[0] = 0;
     HODLR_TRY(set_layout_from_ranks(h.get()));
     HODLR_TRY(launch_repack(h.get(), Ucap.p, Vcap.p, n, capoff, stream));
-    HODLR_HIP(hipStreamSynchronize(stream));  // Ucap/Vcap are freed on return
-  } else {
-    HODLR_TRY(set_layout_from_ranks(h.get()));
+    // the capped panels go back to the allocator once the repack has run
+    Ucap.release_after(stream);
+    Vcap.release_after(stream);
+    *out = h.release();
+    return HODLR_OK;
   }
+  HODLR_TRY(set_layout_from_ranks(h.get()));
   if (fork.side) {
     HODLR_HIP(hipStreamWaitEvent(stream, fork.ev[1], 0));
     HODLR_HIP(hipStreamSynchronize(stream));
@@ -563,9 +663,22 @@ int hodlr_factor(hodlr_t h, hipStream_t stream) {
   if (h->factored) return fail(HODLR_EINVAL, "handle is already factorized");
   if (h->leaf_singular >= 0) return fail(HODLR_ESINGULAR, "singular leaf block " + std::to_string(h->leaf_singular));
   HODLR_TRY(factor_impl(h, stream));
+  // the status words come back through pinned host memory, written by a
+  // kernel behind the factorization, with one synchronization
+  void* pin = nullptr;
+  size_t pin_bytes = 0;
+  HODLR_TRY(pinned_alloc(16 * sizeof(int), &pin, &pin_bytes));
+  struct PinGuard {
+    void* p;
+    size_t b;
+    ~PinGuard() { pinned_free(p, b); }
+  } pin_guard{pin, pin_bytes};
+  int* dpin = nullptr;
+  HODLR_HIP(hipHostGetDevicePointer(reinterpret_cast<void**>(&dpin), pin, 0));
+  k_export_ints<<<1, 64, 0, stream>>>(h->status.as<int>(), 4, h->status.as<int>(), nullptr, dpin);
+  HODLR_HIP(hipGetLastError());
   HODLR_HIP(hipStreamSynchronize(stream));
-  int st[4];
-  HODLR_HIP(hipMemcpy(st, h->status.p, sizeof(st), hipMemcpyDeviceToHost));
+  const int* st = static_cast<const int*>(pin);
   if (st[0]) {
     return fail(HODLR_ESINGULAR, st[0] == 1 ? "singular leaf block " + std::to_string(st[1])
                                             : "singular capacitance matrix at node " +

@@ -649,7 +649,10 @@ static int bdlr_t(hodlr_s* h, const double* K, int ldk, const int* rowptr, const
   HODLR_HIP(hipGetLastError());
   if (piv_export)
     HODLR_HIP(hipMemcpyAsync(piv_export, d_piv.p, (size_t)selo * sizeof(int), hipMemcpyDeviceToDevice, s));
-  HODLR_HIP(hipStreamSynchronize(s));  // scratch goes back to the allocator cache
+  // the scratch goes back to the allocator once s is past its last reader
+  // (s has waited for the side stream's gather)
+  for (DevBuf* b : {&d_tasks, &d_sel, &d_piv, &d_cnt, &d_rt, &d_inv, &d_cg}) b->release_after(s);
+  ev.side = nullptr;
   return HODLR_OK;
 }
 

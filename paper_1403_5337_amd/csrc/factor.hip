@@ -321,22 +321,47 @@ int launch_stage_leaves_packed(hodlr_s* h, const double* leaves, hipStream_t s) 
   return h->precision == 64 ? stage_packed<double>(h, leaves, s) : stage_packed<float>(h, leaves, s);
 }
 
+// Copies every level's rq columns of the capped panels (column block capoff,
+// leading dimension ldcap) into the packed panels Y / W (column block off,
+// leading dimension n): workgroup row y is packed column y, z picks U or V.
+constexpr int kRepackLevels = 32;
+struct RepackCols {
+  int L;
+  int off[kRepackLevels], cap[kRepackLevels];
+};
+
+template <typename T>
+__global__ void __launch_bounds__(kBlock)
+    k_repack(const T* __restrict__ Ucap, const T* __restrict__ Vcap, int ldcap, T* __restrict__ Y,
+             T* __restrict__ W, int n, const RepackCols rc) {
+  const int j = blockIdx.y;
+  int q = 0;
+  while (q + 1 < rc.L && j >= rc.off[q + 1]) ++q;
+  const size_t src = (size_t)(rc.cap[q] + j - rc.off[q]) * ldcap;
+  const T* sp = blockIdx.z ? Vcap : Ucap;
+  T* dp = (blockIdx.z ? W : Y) + (size_t)j * n;
+  for (int i = blockIdx.x * kBlock + threadIdx.x; i < n; i += gridDim.x * kBlock) dp[i] = sp[src + i];
+}
+
 int launch_repack(hodlr_s* h, const void* Ucap, const void* Vcap, int ldcap,
                   const std::vector<int>& capoff, hipStream_t s) {
   const Tree& t = h->tree;
-  const size_t n = t.n, es = h->esize;
+  if (t.L > kRepackLevels) return fail(HODLR_EINVAL, "tree deeper than the repack supports");
+  if (h->R == 0) return HODLR_OK;
+  RepackCols rc{};
+  rc.L = t.L;
   for (int q = 1; q <= t.L; ++q) {
-    const size_t rq = h->rcols[q - 1];
-    if (rq == 0) continue;
-    const char* us = static_cast<const char*>(Ucap) + (size_t)capoff[q - 1] * ldcap * es;
-    const char* vs = static_cast<const char*>(Vcap) + (size_t)capoff[q - 1] * ldcap * es;
-    char* ud = static_cast<char*>(h->Y.p) + (size_t)h->off[q - 1] * n * es;
-    char* vd = static_cast<char*>(h->W.p) + (size_t)h->off[q - 1] * n * es;
-    HODLR_HIP(hipMemcpy2DAsync(ud, n * es, us, (size_t)ldcap * es, n * es, rq,
-                               hipMemcpyDeviceToDevice, s));
-    HODLR_HIP(hipMemcpy2DAsync(vd, n * es, vs, (size_t)ldcap * es, n * es, rq,
-                               hipMemcpyDeviceToDevice, s));
+    rc.off[q - 1] = h->off[q - 1];
+    rc.cap[q - 1] = capoff[q - 1];
   }
+  const dim3 grid(std::min(cdiv(t.n, kBlock), 16), h->R, 2);
+  if (h->precision == 64)
+    k_repack<double><<<grid, kBlock, 0, s>>>(static_cast<const double*>(Ucap), static_cast<const double*>(Vcap),
+                                            ldcap, h->Y.as<double>(), h->W.as<double>(), t.n, rc);
+  else
+    k_repack<float><<<grid, kBlock, 0, s>>>(static_cast<const float*>(Ucap), static_cast<const float*>(Vcap), ldcap,
+                                           h->Y.as<float>(), h->W.as<float>(), t.n, rc);
+  HODLR_HIP(hipGetLastError());
   return HODLR_OK;
 }
 

@@ -67,6 +67,8 @@ struct Tree {
 // caching device allocator (api.hip)
 int dev_alloc(size_t nbytes, void** out);
 void dev_free(void* p, size_t nbytes);
+// released once the work queued so far on stream s is done, without waiting
+void dev_free_after(void* p, size_t nbytes, hipStream_t s);
 void release_cached_memory();
 // pinned host blocks, kept in a process-wide cache (api.hip): pinning and
 // unpinning memory are slow driver calls, so freed blocks are reused.  A block
@@ -85,6 +87,7 @@ struct DevBuf {
   DevBuf& operator=(const DevBuf&) = delete;
   ~DevBuf() { release(); }
   void release();             // back to the allocator cache
+  void release_after(hipStream_t s);  // back to the cache once s's queued work is done
   int ensure(size_t nbytes);  // grow-only; contents not preserved
   template <typename T> T* as() const { return static_cast<T*>(p); }
 };
