@@ -36,7 +36,9 @@ constexpr int kMaxRestart = 512;
 // per column) are all in flight at once, z (as float64, zero-padded to 16 NB
 // columns) comes from LDS, and v_mfma_f64_16x16x4f64 accumulates the
 // 16 x 16 NB block.  The product stays bound by the K traffic; the matrix
-// cores only keep the instruction count per byte low.
+// cores only keep the instruction count per byte low.  K is read with
+// ordinary (cached) loads: the 256 MB last-level cache then keeps much of a
+// 134 MB K between the products of one solve.
 typedef double f64x4 __attribute__((ext_vector_type(4)));
 
 template <typename TZ, int NB, int COLS>
@@ -66,7 +68,7 @@ __global__ void __launch_bounds__(kRowsPerWG)
 #pragma unroll
   for (int q = 0; q < kQ; ++q) {
     const int c = min(4 * q + kl, cn - 1);
-    a[q] = __builtin_nontemporal_load(K + (size_t)(c0 + c) * ldk + rowc);
+    a[q] = K[(size_t)(c0 + c) * ldk + rowc];
   }
   __builtin_amdgcn_sched_barrier(0);  // every load is issued before the wait for z
 #pragma unroll
@@ -120,7 +122,7 @@ __global__ void __launch_bounds__(kRowsPerWG)
   double a[2][kQ];
 #pragma unroll
   for (int q = 0; q < kQ; ++q)
-    a[0][q] = __builtin_nontemporal_load(K + (size_t)(c0 + min(4 * q + kl, cn - 1)) * ldk + rowc);
+    a[0][q] = K[(size_t)(c0 + min(4 * q + kl, cn - 1)) * ldk + rowc];
   __builtin_amdgcn_sched_barrier(0);  // every load is issued before the wait for z
 #pragma unroll
   for (int u = 0; u < kZ; ++u) {
@@ -136,8 +138,7 @@ __global__ void __launch_bounds__(kRowsPerWG)
     if (c + 1 < CH) {
 #pragma unroll
       for (int q = 0; q < kQ; ++q)
-        a[(c + 1) & 1][q] = __builtin_nontemporal_load(
-            K + (size_t)(c0 + min((c + 1) * COLS + 4 * q + kl, cn - 1)) * ldk + rowc);
+        a[(c + 1) & 1][q] = K[(size_t)(c0 + min((c + 1) * COLS + 4 * q + kl, cn - 1)) * ldk + rowc];
     }
 #pragma unroll
     for (int q = 0; q < kQ; ++q)
