@@ -90,9 +90,9 @@ def cpu_baseline(front, w, nrhs_sample, method, depth):
 # reports traffic = null until the counters are taken again.
 TRAFFIC = {
     "apply_level": {"source": "paper_1403_5337_amd/csrc/solve.hip",
-                    "sha256": "1d82d45c2b8b6ead97b0bd7d0293e05faaff676d5dab2c1218497abfcd6f6c5b",
-                    "workload": "tpfa4096", "fetch_kib": 1595.5, "write_kib": 236.0,
-                    "fetch_factor": 2.0, "write_factor": 1.0, "rocprof_avg_us": 7.86},
+                    "sha256": "792a556e9f24caac7c69b9f5dd5185421785192b1fc8398ea7f456996596c677",
+                    "workload": "tpfa4096", "fetch_kib": 1598.0, "write_kib": 236.0,
+                    "fetch_factor": 2.0, "write_factor": 1.0, "rocprof_avg_us": 7.91},
 }
 
 
