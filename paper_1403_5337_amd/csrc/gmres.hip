@@ -282,25 +282,38 @@ __global__ void __launch_bounds__(kBlock)
                const double* __restrict__ w, double* __restrict__ V, TP* __restrict__ Z, int* host_slot) {
   __shared__ double s_hn;
   __shared__ int s_go;
-  const int k = blockIdx.y, lead = blockIdx.x == 0;
-  if (threadIdx.x == 0) {
+  __shared__ double s_col[kMaxRestart + 1], s_c[kMaxRestart], s_s[kMaxRestart], s_n2;
+  const int k = blockIdx.y, lead = blockIdx.x == 0, t = threadIdx.x;
+  const bool live = act_in[k] != 0;
+  const int m1 = m + 1;
+  if (live) {
+    // the column, the earlier rotations and the norm partials, all loaded at
+    // once by the workgroup
+    for (int l = t; l <= j; l += blockDim.x) s_col[l] = hcol[(size_t)k * m1 + l];
+    for (int l = t; l < j; l += blockDim.x) {
+      s_c[l] = cs[(size_t)k * m + l];
+      s_s[l] = sn[(size_t)k * m + l];
+    }
+    if (t < 64) {
+      double v = 0.0;
+      for (int c = t; c < nch; c += 64) v += npart[(size_t)c * s + k];
+      v = wave_sum(v);
+      if (t == 0) s_n2 = v;
+    }
+  }
+  __syncthreads();
+  if (t == 0) {
     int go = 0;
     double hn = 1.0;
-    if (act_in[k]) {
-      const int m1 = m + 1;
-      double hn2 = 0.0;
-      for (int c = 0; c < nch; ++c) hn2 += npart[(size_t)c * s + k];
-      hn = sqrt(hn2);
-      const double* hc = hcol + (size_t)k * m1;
-      const double* ck = cs + (size_t)k * m;
-      const double* sk = sn + (size_t)k * m;
+    if (live) {
+      hn = sqrt(s_n2);
       double* Hk = H + (size_t)k * m1 * m + (size_t)j * m1;
       // the earlier rotations applied down the column, one running entry
-      double cur = hc[0];
+      double cur = s_col[0];
       for (int l = 0; l < j; ++l) {
-        const double b = hc[l + 1];
-        const double o = ck[l] * cur + sk[l] * b;
-        cur = -sk[l] * cur + ck[l] * b;
+        const double b = s_col[l + 1];
+        const double o = s_c[l] * cur + s_s[l] * b;
+        cur = -s_s[l] * cur + s_c[l] * b;
         if (lead) Hk[l] = o;
       }
       double c = 1.0, sv = 0.0;
