@@ -16,6 +16,7 @@ Modules
   bdlr      boundary-distance pseudo-skeleton (Sec. 5.3, eq. Ahat)
   hodlr     HODLR assembly, Woodbury factorization and solve (Sec. 4.2-4.3)
   gmres     flexible right-preconditioned GMRES (Sec. 3)
+  cg        preconditioned conjugate gradients for the symmetric fronts (Sec. 3)
   dense     dense LU reference solve
   cost      flop counter of the factorization (Sec. 4.4, eq. cost)
 

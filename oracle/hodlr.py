@@ -67,12 +67,18 @@ def sibling(i: int) -> int:
 
 
 def from_dense(K: np.ndarray, leaf: int, method="aca", eps=1e-8, max_rank=None,
-               graph=None, depth=1, svd_rank=None, max_skel=None) -> HODLR:
+               graph=None, depth=1, svd_rank=None, max_skel=None, symmetric=False) -> HODLR:
     """Compress every off-diagonal block of K.
 
     method: 'aca' (partial-pivoting ACA), 'bdlr' (needs graph=(indptr, indices)),
     'svd' (truncated SVD at relative 2-norm eps, or fixed ``svd_rank``),
-    'full' (exact, U = block, V = I)."""
+    'full' (exact, U = block, V = I).
+
+    symmetric: K is symmetric, so only the block of each left child is
+    compressed, K(c, s) ~ U_c V_c^T, and its sibling's block is its transpose,
+    K(s, c) = K(c, s)^T ~ V_c U_c^T: U_s = V_c, V_s = U_c (the symmetric case
+    of eq. HODLR2, where the two off-diagonal blocks of a node are each
+    other's transposes)."""
     K = np.asarray(K, dtype=np.float64)
     n = K.shape[0]
     levs = _tree.levels(n, leaf)
@@ -82,6 +88,10 @@ def from_dense(K: np.ndarray, leaf: int, method="aca", eps=1e-8, max_rank=None,
         h.leaves[(L, i)] = K[lo:hi, lo:hi].copy()
     for p in range(1, L + 1):
         for i, (lo, hi) in enumerate(levs[p]):
+            if symmetric and i % 2 == 1:
+                h.U[(p, i)] = h.V[(p, i - 1)].copy()
+                h.V[(p, i)] = h.U[(p, i - 1)].copy()
+                continue
             slo, shi = levs[p][sibling(i)]
             B = K[lo:hi, slo:shi]
             if method == "aca":
