@@ -16,7 +16,8 @@ applies.  Readings (the paper fixes none of these):
   operator.  For a fixed symmetric M, r'^T z = 0 in exact arithmetic and
   beta equals the classical r'^T z' / (r^T z);
 * a step with p^T q <= 0 or r'^T z' <= 0 (M or K not positive definite in
-  floating point) ends the cycle; the true residual then decides;
+  floating point) ends the cycle; the true residual then decides, and a
+  cycle that took no step ends the solve;
 * at most ``maxit`` steps in total; each right-hand side separately.
 
 Pinned in tests: M = K^-1 converges in one step; M = I on a small SPD
@@ -43,12 +44,13 @@ def pcg(matvec, b: np.ndarray, precond=None, tol=1e-12, maxit=1000, x0=None, his
     if bnorm == 0.0:
         return np.zeros(n), dict(iters=0, relres=0.0, converged=True, iterates=[])
     its = [x.copy()] if history else []
-    total = 0
+    total, start = 0, -1
     while True:
         r = b - matvec(x)
         relres = float(np.linalg.norm(r)) / bnorm
-        if relres <= tol or total >= maxit:
+        if relres <= tol or total >= maxit or total == start:
             return x, dict(iters=total, relres=relres, converged=relres <= tol, iterates=its)
+        start = total
         z = np.asarray(M(r), dtype=np.float64)
         rz = float(r @ z)
         if not rz > 0.0:

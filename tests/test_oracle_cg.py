@@ -124,3 +124,11 @@ def test_hodlr_preconditioned_cg_end_to_end():
     assert np.linalg.norm(X - np.linalg.solve(K, b)) <= 1e-10 * np.linalg.norm(X)
     for a, c in zip(infos, infos0):
         assert a["converged"] and a["iters"] <= 10 and a["iters"] * 3 < c["iters"]
+
+
+def test_indefinite_matrix_stops():
+    """A cycle that cannot take a step (p^T q <= 0 at once) ends the solve."""
+    K = np.diag([1.0, -1.0])
+    b = np.array([1.0, 1.0])
+    x, info = cg.pcg(lambda v: K @ v, b, None, tol=1e-12, maxit=100)
+    assert not info["converged"] and info["iters"] == 0
