@@ -26,7 +26,7 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
 KERNELS = ["aca", "bdlr_select", "bdlr_lu", "bdlr_gather", "bdlr_factors", "leaf_inverse", "leaf_apply", "panel_tn", "schur_form", "cap_inverse", "form_E", "schur_apply", "correct", "apply_leaf", "apply_level", "apply_sum",
-           "matvec", "orth"]
+           "matvec", "orth", "cg_vec"]
 
 
 def parse():
@@ -39,18 +39,21 @@ def parse():
     ap.add_argument("--no-lu", action="store_true")
     ap.add_argument("--method", choices=["aca", "bdlr"], default="bdlr")
     ap.add_argument("--depth", type=int, default=2, help="BDLR boundary distance")
+    ap.add_argument("--solver", choices=["gmres", "cg"], default="gmres",
+                    help="cg: symmetric HODLR build and preconditioned CG instead of GMRES")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain 256 MiB device copy 3 times (reference for HBM counters)")
     return ap.parse_args()
 
 
-def cpu_baseline(front, w, nrhs_sample, method, depth):
+def cpu_baseline(front, w, nrhs_sample, method, depth, solver="gmres"):
     """The FP64 oracle, as it stands, on the same front: ordering,
-    compression, factorization and GMRES for `nrhs_sample` right-hand sides."""
+    compression, factorization and GMRES (or CG) for `nrhs_sample`
+    right-hand sides."""
     from threadpoolctl import threadpool_info
 
     from gen import fronts
-    from oracle import gmres, hodlr, ordering
+    from oracle import cg, gmres, hodlr, ordering
 
     fc = fronts.Front(K=front.K.cpu(), indptr=front.indptr, indices=front.indices, coords=front.coords,
                       name=front.name)
@@ -61,14 +64,18 @@ def cpu_baseline(front, w, nrhs_sample, method, depth):
         perm = ordering.rcb_permutation(fc.coords, w["leaf"])
         g = fronts.permute_front(fc, perm)
         Kp = g.K.numpy()
+        sym = solver == "cg"
         if method == "bdlr":
             h = hodlr.from_dense(Kp, w["leaf"], method="bdlr", eps=w["tol"], graph=(g.indptr, g.indices),
-                                 depth=depth, max_skel=192)
+                                 depth=depth, max_skel=192, symmetric=sym)
         else:
-            h = hodlr.from_dense(Kp, w["leaf"], method="aca", eps=w["tol"])
+            h = hodlr.from_dense(Kp, w["leaf"], method="aca", eps=w["tol"], symmetric=sym)
         hodlr.factor(h)
-        X, infos = gmres.fgmres_multi(lambda v: Kp @ v, B, lambda v: hodlr.solve(h, v), tol=1e-12,
-                                      maxit=1000, restart=200)
+        if sym:
+            X, infos = cg.pcg_multi(lambda v: Kp @ v, B, lambda v: hodlr.solve(h, v), tol=1e-12, maxit=1000)
+        else:
+            X, infos = gmres.fgmres_multi(lambda v: Kp @ v, B, lambda v: hodlr.solve(h, v), tol=1e-12,
+                                          maxit=1000, restart=200)
         reps += 1
         if time.perf_counter() - t0 >= 10.0:
             break
@@ -78,7 +85,8 @@ def cpu_baseline(front, w, nrhs_sample, method, depth):
         if p.get("internal_api") in ("openblas", "mkl", "blis"):
             threads = max(threads, int(p.get("num_threads", 1)))
     return dict(value=nrhs_sample / dt, unit="solves/s", cores=threads, kind="oracle",
-                sample=f"full oracle pipeline (RCB order, {method.upper()} 1e-4, recursive Woodbury factor, FGMRES to 1e-12) "
+                sample=f"full oracle pipeline (RCB order, {method.upper()} 1e-4, recursive Woodbury factor, "
+                       f"{'symmetric build, PCG' if solver == 'cg' else 'FGMRES'} to 1e-12) "
                        f"on the same n={front.n} front for {nrhs_sample} of {w['nrhs']} right-hand sides, "
                        f"{reps} repetitions, {dt:.2f} s each; iterations {[i['iters'] for i in infos]}")
 
@@ -301,13 +309,16 @@ def main():
         if ev is not None:
             ev[1].record(stream)
         h = H.Hodlr.build(Kp, leaf=leaf, tol=tol, precision=prec, method=args.method, depth=args.depth,
-                          graph=graph)
+                          graph=graph, symmetric=args.solver == "cg")
         if ev is not None:
             ev[2].record(stream)
         h.factor()
         if ev is not None:
             ev[3].record(stream)
-        X, it, rr, st = H.gmres_solve(Kp, B, h, tol=1e-12, maxit=1000, restart=200)
+        if args.solver == "cg":
+            X, it, rr, st = H.cg_solve(Kp, B, h, tol=1e-12, maxit=1000)
+        else:
+            X, it, rr, st = H.gmres_solve(Kp, B, h, tol=1e-12, maxit=1000, restart=200)
         if ev is not None:
             ev[4].record(stream)
         stats = h.stats()
@@ -328,7 +339,7 @@ def main():
     t1 = time.perf_counter()
     ms_step = (t1 - t0) * 1e3 / args.steps
     tstages = np.array([[tev[k][j].elapsed_time(tev[k][j + 1]) for j in range(4)] for k in range(args.steps)])
-    stage_timed = dict(zip(["order_permute", "build", "factor", "gmres"], np.median(tstages, axis=0).round(4).tolist()))
+    stage_timed = dict(zip(["order_permute", "build", "factor", args.solver], np.median(tstages, axis=0).round(4).tolist()))
     assert st == H.HODLR_OK and max(rr) <= 1e-12, (st, rr)
     # separate profiled pass: stage events and per-launch event pairs (these
     # add gaps between launches, so they are kept out of the timed region)
@@ -340,7 +351,7 @@ def main():
         step(evs[k])
     torch.cuda.synchronize()
     stages = np.array([[evs[k][j].elapsed_time(evs[k][j + 1]) for j in range(4)] for k in range(nprof)])
-    stage_ms = dict(zip(["order_permute", "build", "factor", "gmres"], np.median(stages, axis=0).round(4).tolist()))
+    stage_ms = dict(zip(["order_permute", "build", "factor", args.solver], np.median(stages, axis=0).round(4).tolist()))
     kern = {}
     for name in KERNELS:
         cnt, tot = H.hodlr_prof_query(name)
@@ -370,10 +381,13 @@ def main():
 
     cpu = None
     if not args.no_cpu_baseline:
-        cpu = cpu_baseline(front, w, s, args.method, args.depth)
+        cpu = cpu_baseline(front, w, s, args.method, args.depth, args.solver)
 
     out = {
-        "metric": "GMRES-to-1e-12 solves/sec (HODLR-preconditioned, end to end incl. compression and factorization)",
+        "metric": ("GMRES-to-1e-12 solves/sec (HODLR-preconditioned, end to end incl. compression and factorization)"
+                   if args.solver == "gmres" else
+                   "CG-to-1e-12 solves/sec (symmetric HODLR-preconditioned, end to end incl. compression and "
+                   "factorization)"),
         "value": round(s * 1e3 / ms_step, 3),
         "unit": "solves/s",
         "n_gpus": 1,
@@ -386,7 +400,8 @@ def main():
         "dtype": "f64",
         "data": "synthetic",
         "config": {"workload": args.workload, "n": n, "nrhs": s, "leaf": leaf, "compression": args.method,
-                   "tol": tol, "hodlr_precision": "f32" if prec == 32 else "f64", "gmres_tol": 1e-12},
+                   "tol": tol, "hodlr_precision": "f32" if prec == 32 else "f64", "solver": args.solver,
+                   "symmetric_build": args.solver == "cg", "solver_tol": 1e-12},
         "stage_ms": stage_timed,
         "stage_ms_profiled": stage_ms,
         "tuned": H.hodlr_tune_report(),

@@ -79,11 +79,20 @@ typedef struct {
                                 magnitude above tol) */
   int bdlr_max_skel;         /* HODLR_BDLR: cap on the rows (columns) picked
                                 per side, nearest first (0 = 192 / 128) */
+  int symmetric;             /* 1: K is symmetric (the symmetric case of eq.
+                                HODLR2: a node's two off-diagonal blocks are
+                                each other's transposes).  Only the block of
+                                each left child c is compressed, K(c, s) ~
+                                U_c V_c^T; its sibling takes U_s = V_c,
+                                V_s = U_c, so Ktilde is symmetric.  ACA then
+                                compresses half the blocks; BDLR and learned
+                                skeletons compress all and keep the left
+                                ones.  0 (default): every block on its own. */
 } hodlr_opts;
 
 /* Fill *opts with defaults: leaf 128, tol 1e-4, ACA, depth 1, max_rank 0,
  * precision 32, skel_k 32, mlp_params NULL, seed 0, skel_tol 0,
- * bdlr_max_skel 0. */
+ * bdlr_max_skel 0, symmetric 0. */
 void hodlr_default_opts(hodlr_opts* opts);
 
 /* Compress K into a HODLR matrix (Sec. 4.3.1 step 1).
@@ -169,6 +178,26 @@ int hodlr_solve(hodlr_t h, const void* B, int nrhs, int ldb, void* X, int ldx,
 int gmres_solve(const double* K, int n, int ldk, hodlr_t precond, const double* B, int nrhs,
                 int ldb, double* X, int ldx, double tol, int maxit, int restart, int* iters,
                 double* relres, hipStream_t stream);
+
+/* Preconditioned conjugate gradients in float64 for symmetric positive
+ * definite K (Sec. 3: the HODLR solve preconditions any Krylov method,
+ * conjugate gradients included).  Arguments as gmres_solve, without restart.
+ * precond is NULL (plain CG) or a factorized handle, best built with
+ * opts.symmetric = 1.  Per right-hand side: x0 = X on entry, r = b - K x0,
+ * z = M r, p = z; a step takes alpha = r^T z / p^T q (q = K p), updates x
+ * and r, and stops the cycle when |r| <= tol |b|; otherwise z' = M r and
+ * p = z' + beta p with the flexible beta = r^T (z' - z) / (r^T z), which is
+ * the classical coefficient when M is a fixed symmetric operator and keeps
+ * CG converging with a float32 M.  A cycle also ends when p^T q <= 0 or
+ * r^T z' <= 0 (not positive definite in floating point).  When every
+ * column's cycle has ended the true residual |b - K x| / |b| decides who
+ * restarts (a column whose last cycle took no step stops).  iters[k] counts
+ * the steps, at most maxit in total; relres[k] is the last true relative
+ * residual.  Synchronizes the stream.  Returns ENOCONV if any right-hand
+ * side ends above tol (X holds the last iterates).  Scratch is per host
+ * thread, so calls on different threads (and streams) run side by side. */
+int cg_solve(const double* K, int n, int ldk, hodlr_t precond, const double* B, int nrhs, int ldb,
+             double* X, int ldx, double tol, int maxit, int* iters, double* relres, hipStream_t stream);
 
 /* Batches of fronts (the separators of a nested-dissection tree, solved
  * independently; Sec. 2): the library runs the fronts side by side on a pool

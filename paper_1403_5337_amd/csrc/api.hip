@@ -431,6 +431,7 @@ void hodlr_default_opts(hodlr_opts* o) {
   o->seed = 0;
   o->skel_tol = 0.0;
   o->bdlr_max_skel = 0;
+  o->symmetric = 0;
 }
 
 const char* hodlr_last_error(void) { return g_last_error.c_str(); }
@@ -445,6 +446,7 @@ static int check_opts(const hodlr_opts& o) {
     return fail(HODLR_EINVAL, "HODLR_LEARNED needs opts.mlp_params and opts.skel_k >= 1");
   if (!(o.skel_tol >= 0.0) || !std::isfinite(o.skel_tol)) return fail(HODLR_EINVAL, "opts.skel_tol must be >= 0");
   if (o.bdlr_max_skel < 0) return fail(HODLR_EINVAL, "opts.bdlr_max_skel must be >= 0");
+  if (o.symmetric != 0 && o.symmetric != 1) return fail(HODLR_EINVAL, "opts.symmetric must be 0 or 1");
   if (o.precision != 32 && o.precision != 64)
     return fail(HODLR_EINVAL, "opts.precision must be 32 or 64");
   if (o.leaf > leaf_cap(o.precision))
@@ -541,8 +543,15 @@ static int build_impl(const double* K, int n, int ldk, const int* g_rowptr, cons
       HODLR_TRY(launch_learned(h.get(), K, ldk, g_rowptr, g_col, coords, o.mlp_params, o.skel_k, o.seed,
                                o.skel_tol > 0.0 ? o.skel_tol : 30.0 * o.tol, Ucap.p, Vcap.p, capoff, capq,
                                stream));
-    else
+    else if (o.symmetric) {
+      // only the left children's blocks; their siblings' are their transposes
+      std::vector<int> left;
+      for (int q = 1; q <= t.L; ++q)
+        for (int i = 0; i < (1 << q); i += 2) left.push_back(node_id(q, i));
+      HODLR_TRY(launch_aca(h.get(), K, ldk, Ucap.p, Vcap.p, capoff, capq, stream, &left, piv_export));
+    } else {
       HODLR_TRY(launch_aca(h.get(), K, ldk, Ucap.p, Vcap.p, capoff, capq, stream, nullptr, piv_export));
+    }
     // the ranks, the compression's status words and those of the leaf
     // inverses come back together, written into pinned host memory by one
     // kernel, behind the build's one synchronization
@@ -570,8 +579,11 @@ static int build_impl(const double* K, int n, int ldk, const int* g_rowptr, cons
       if (hp[nn + 4]) h->leaf_singular = hp[nn + 5];
     }
     h->rank[0] = 0;
+    if (o.symmetric)  // a right child (even id >= 2) takes its left sibling's rank
+      for (int id = 2; id < nn; id += 2) h->rank[id] = h->rank[id - 1];
     HODLR_TRY(set_layout_from_ranks(h.get()));
     HODLR_TRY(launch_repack(h.get(), Ucap.p, Vcap.p, n, capoff, stream));
+    if (o.symmetric) HODLR_TRY(launch_mirror(h.get(), stream));
     // the capped panels go back to the allocator once the repack has run
     Ucap.release_after(stream);
     Vcap.release_after(stream);
@@ -836,6 +848,22 @@ int gmres_solve(const double* K, int n, int ldk, hodlr_t precond, const double* 
   }
   return gmres_impl(K, n, ldk, precond, B, nrhs, ldb, X, ldx, tol, maxit, restart, iters, relres,
                     stream);
+}
+
+int cg_solve(const double* K, int n, int ldk, hodlr_t precond, const double* B, int nrhs, int ldb, double* X,
+             int ldx, double tol, int maxit, int* iters, double* relres, hipStream_t stream) {
+  if (!K || !B || !X) return fail(HODLR_EINVAL, "K, B or X is NULL");
+  if (n < 1 || n > kMaxN) return fail(HODLR_EINVAL, "n out of range");
+  if (ldk < n || ldb < n || ldx < n) return fail(HODLR_EINVAL, "leading dimension < n");
+  if (nrhs < 1 || nrhs > 64) return fail(HODLR_EINVAL, "nrhs must be in [1, 64]");
+  if (!(tol > 0.0)) return fail(HODLR_EINVAL, "tol must be > 0");
+  if (maxit < 1) return fail(HODLR_EINVAL, "maxit must be >= 1");
+  if (!iters || !relres) return fail(HODLR_EINVAL, "iters or relres is NULL");
+  if (precond) {
+    if (!precond->factored) return fail(HODLR_EINVAL, "preconditioner is not factorized");
+    if (precond->tree.n != n) return fail(HODLR_EINVAL, "preconditioner size differs from n");
+  }
+  return cg_impl(K, n, ldk, precond, B, nrhs, ldb, X, ldx, tol, maxit, iters, relres, stream);
 }
 
 int hodlr_build_batched(int nf, const double* const* K, const int* n, const int* ldk,

@@ -365,6 +365,57 @@ int launch_repack(hodlr_s* h, const void* Ucap, const void* Vcap, int ldcap,
   return HODLR_OK;
 }
 
+// Symmetric build: the block of every right child s is the transpose of its
+// left sibling c's, K(s, c) = K(c, s)^T ~ V_c U_c^T, so U_s = V_c and
+// V_s = U_c.  In the panels U_s sits in Y and V_c in W at the rows of s, V_s
+// in W and U_c in Y at the rows of c.  For column j of level p: rows of a
+// right child take Y(i, j) = W(i, j), rows of a left child W(i, j) = Y(i, j),
+// for j - off_p < rank(c); the level's other columns become zero there.  The
+// first workgroup also gives every right child its sibling's rank.
+template <typename T>
+__global__ void __launch_bounds__(kBlock)
+    k_mirror(T* __restrict__ Y, T* __restrict__ W, int n, const int* __restrict__ lo, int* __restrict__ rank,
+             int nnodes, const RepackCols rc) {
+  const int j = blockIdx.y;
+  if (j == 0 && blockIdx.x == 0)
+    for (int id = 2 + 2 * threadIdx.x; id < nnodes; id += 2 * kBlock) rank[id] = rank[id - 1];
+  int q = 0;
+  while (q + 1 < rc.L && j >= rc.off[q + 1]) ++q;
+  const int p = q + 1, jj = j - rc.off[q];
+  const int first = node_id(p, 0), cnt = 1 << p;
+  for (int i = blockIdx.x * kBlock + threadIdx.x; i < n; i += gridDim.x * kBlock) {
+    // the node of level p holding row i: the last one with lo <= i
+    int a = 0, b = cnt - 1;
+    while (a < b) {
+      const int m = (a + b + 1) >> 1;
+      if (lo[first + m] <= i) a = m;
+      else b = m - 1;
+    }
+    const bool keep = jj < rank[first + (a & ~1)];
+    const size_t e = (size_t)j * n + i;
+    if (a & 1) Y[e] = keep ? W[e] : T(0);
+    else W[e] = keep ? Y[e] : T(0);
+  }
+}
+
+int launch_mirror(hodlr_s* h, hipStream_t s) {
+  const Tree& t = h->tree;
+  if (t.L > kRepackLevels) return fail(HODLR_EINVAL, "tree deeper than the repack supports");
+  if (h->R == 0) return HODLR_OK;
+  RepackCols rc{};
+  rc.L = t.L;
+  for (int q = 1; q <= t.L; ++q) rc.off[q - 1] = h->off[q - 1];
+  const dim3 grid(std::min(cdiv(t.n, kBlock), 16), h->R);
+  if (h->precision == 64)
+    k_mirror<double><<<grid, kBlock, 0, s>>>(h->Y.as<double>(), h->W.as<double>(), t.n, h->d_lo.as<int>(),
+                                            h->d_rank.as<int>(), t.nnodes(), rc);
+  else
+    k_mirror<float><<<grid, kBlock, 0, s>>>(h->Y.as<float>(), h->W.as<float>(), t.n, h->d_lo.as<int>(),
+                                           h->d_rank.as<int>(), t.nnodes(), rc);
+  HODLR_HIP(hipGetLastError());
+  return HODLR_OK;
+}
+
 template <typename S, typename D>
 static int convert(const S* src, D* dst, size_t count, hipStream_t s) {
   if (count == 0) return HODLR_OK;

@@ -685,3 +685,22 @@ int gmres_impl(const double* K, int n, int ldk, hodlr_s* M, const double* B, int
 }
 
 }  // namespace hodlr
+
+namespace hodlr {
+
+// The float64 product K src (s columns, leading dimension lds) as split-K
+// partial sums, with the tuned split width; *nsplit receives the number of
+// partials per element (part[(sp s + k) n + i]).
+int matvec_partials(const double* K, int ldk, int n, const double* src, int lds, int s, double* part,
+                    hipStream_t st, int* nsplit) {
+  int cols = kMatvecCols;
+  HODLR_TRY(matvec_cols<double>(K, ldk, n, src, lds, s, part, st, &cols));
+  *nsplit = (n + cols - 1) / cols;
+  return HODLR_OK;
+}
+
+size_t matvec_partial_elems(int n, int s) {
+  return (size_t)n * s * ((n + kMatvecColsMin - 1) / kMatvecColsMin);
+}
+
+}  // namespace hodlr

@@ -189,6 +189,8 @@ int launch_stage_leaves_from_K(hodlr_s* h, const double* K, int ldk, hipStream_t
 int launch_stage_leaves_packed(hodlr_s* h, const double* leaves, hipStream_t s);
 int launch_repack(hodlr_s* h, const void* Ucap, const void* Vcap, int ldcap,
                   const std::vector<int>& capoff, hipStream_t s);
+// symmetric build: right children's panels and ranks from their left siblings
+int launch_mirror(hodlr_s* h, hipStream_t s);
 int launch_from_f64_panels(hodlr_s* h, const double* Up, const double* Vp, hipStream_t s);
 int launch_to_f64_panels(hodlr_s* h, double* Up, double* Vp, hipStream_t s);
 int factor_impl(hodlr_s* h, hipStream_t s);
@@ -241,6 +243,15 @@ int launch_mlp_forward(const float* X, int N, const float* P, int bf16, float* z
 int launch_mlp_grad(const float* X, const float* Y, int N, float* P, int bf16, float pos_weight, float* grad,
                     float* loss, float* M, float* V, int step, float lr, float beta1, float beta2, float eps,
                     hipStream_t s);
+
+// gmres.hip: the float64 product of GMRES, as split-K partial sums
+int matvec_partials(const double* K, int ldk, int n, const double* src, int lds, int s, double* part,
+                    hipStream_t st, int* nsplit);
+size_t matvec_partial_elems(int n, int s);  // elements of part for (n, s)
+
+// cg.hip
+int cg_impl(const double* K, int n, int ldk, hodlr_s* M, const double* B, int nrhs, int ldb, double* X, int ldx,
+            double tol, int maxit, int* iters, double* relres, hipStream_t s);
 
 // gmres.hip
 int gmres_impl(const double* K, int n, int ldk, hodlr_s* M, const double* B, int nrhs, int ldb,

@@ -32,7 +32,7 @@ class Opts(ctypes.Structure):
     _fields_ = [("leaf", ctypes.c_int), ("tol", ctypes.c_double), ("method", ctypes.c_int),
                 ("bdlr_depth", ctypes.c_int), ("max_rank", ctypes.c_int), ("precision", ctypes.c_int),
                 ("skel_k", ctypes.c_int), ("mlp_params", ctypes.c_void_p), ("seed", ctypes.c_ulonglong),
-                ("skel_tol", ctypes.c_double), ("bdlr_max_skel", ctypes.c_int)]
+                ("skel_tol", ctypes.c_double), ("bdlr_max_skel", ctypes.c_int), ("symmetric", ctypes.c_int)]
 
 
 _c_int_p = ctypes.POINTER(ctypes.c_int)
@@ -60,6 +60,8 @@ _SIGNATURES = {
     "gmres_solve": (ctypes.c_int, [_vp, ctypes.c_int, ctypes.c_int, _vp, _vp, ctypes.c_int, ctypes.c_int,
                                    _vp, ctypes.c_int, ctypes.c_double, ctypes.c_int, ctypes.c_int,
                                    _c_int_p, _c_dbl_p, _vp]),
+    "cg_solve": (ctypes.c_int, [_vp, ctypes.c_int, ctypes.c_int, _vp, _vp, ctypes.c_int, ctypes.c_int,
+                                _vp, ctypes.c_int, ctypes.c_double, ctypes.c_int, _c_int_p, _c_dbl_p, _vp]),
     "hodlr_build_batched": (ctypes.c_int, [ctypes.c_int, ctypes.POINTER(_vp), _c_int_p, _c_int_p,
                                            ctypes.POINTER(_vp), ctypes.POINTER(_vp), ctypes.POINTER(_vp),
                                            ctypes.POINTER(Opts), _vp, ctypes.POINTER(_vp)]),
@@ -163,10 +165,11 @@ class Hodlr:
     @classmethod
     def build(cls, K: torch.Tensor, leaf=128, tol=1e-4, method="aca", depth=1, max_rank=0,
               precision=32, graph=None, coords=None, mlp_params=None, skel_k=32, seed=0, skel_tol=0.0,
-              max_skel=0, stream=None) -> "Hodlr":
+              max_skel=0, symmetric=False, stream=None) -> "Hodlr":
         """method: 'aca', 'bdlr' (needs graph = (rowptr, col) device tensors) or
         'learned' (graph, coords (n, 3) float32 and mlp_params (4801,) float32,
-        all on the device)."""
+        all on the device).  symmetric: K is symmetric; only the left
+        children's blocks are compressed and mirrored."""
         _need_gpu(K)
         Kc, ldk = colmajor(K, torch.float64)
         n = Kc.shape[0]
@@ -176,7 +179,7 @@ class Hodlr:
         _need_gpu(xyz, prm)
         o = Opts(leaf=leaf, tol=tol, method=mcode, bdlr_depth=depth, max_rank=max_rank, precision=precision,
                  skel_k=skel_k, mlp_params=None if prm is None else prm.data_ptr(), seed=seed, skel_tol=skel_tol,
-                 bdlr_max_skel=max_skel)
+                 bdlr_max_skel=max_skel, symmetric=1 if symmetric else 0)
         rp, cp = (None, None) if graph is None else (_i32(graph[0]), _i32(graph[1]))
         _need_gpu(rp, cp)
         h = ctypes.c_void_p()
@@ -187,7 +190,7 @@ class Hodlr:
     @classmethod
     def build_batched(cls, Ks, graphs=None, coords=None, leaf=128, tol=1e-4, method="aca", depth=1, max_rank=0,
                       precision=32, mlp_params=None, skel_k=32, seed=0, skel_tol=0.0, max_skel=0,
-                      stream=None) -> list:
+                      symmetric=False, stream=None) -> list:
         """hodlr_build for every front of Ks side by side (hodlr_build_batched);
         graphs: list of (rowptr, col) or None; coords: list of (n, 3) or None."""
         nf = len(Ks)
@@ -220,7 +223,7 @@ class Hodlr:
         _need_gpu(prm)
         o = Opts(leaf=leaf, tol=tol, method=mcode, bdlr_depth=depth, max_rank=max_rank, precision=precision,
                  skel_k=skel_k, mlp_params=None if prm is None else prm.data_ptr(), seed=seed, skel_tol=skel_tol,
-                 bdlr_max_skel=max_skel)
+                 bdlr_max_skel=max_skel, symmetric=1 if symmetric else 0)
         out = (_vp * nf)()
         _check(lib().hodlr_build_batched(nf, Kp, ns, lds, rps, cps, xyzs, ctypes.byref(o), _stream(stream), out))
         return [cls(ctypes.c_void_p(out[f]), ns[f], precision) for f in range(nf)]
@@ -333,6 +336,26 @@ def gmres_solve(K: torch.Tensor, B: torch.Tensor, precond: Optional[Hodlr] = Non
     rr = (ctypes.c_double * s)()
     st = lib().gmres_solve(_ptr(Kc), n, ldk, None if precond is None else precond.handle, _ptr(Bc), s, ldb,
                            _ptr(X), n, tol, maxit, restart, it, rr, _stream(stream))
+    if st not in (HODLR_OK, HODLR_ENOCONV) or (raise_on_noconv and st == HODLR_ENOCONV):
+        _check(st)
+    return X, list(it), list(rr), st
+
+
+def cg_solve(K: torch.Tensor, B: torch.Tensor, precond: Optional[Hodlr] = None, X0=None, tol=1e-12, maxit=1000,
+             stream=None, raise_on_noconv=False):
+    """Preconditioned CG (cg_solve) for symmetric positive definite K.
+    Returns (X (n, s) float64, iters list, relres list, status)."""
+    _need_gpu(K, B)
+    Kc, ldk = colmajor(K, torch.float64)
+    Bc, ldb = colmajor(B, torch.float64)
+    n, s = Bc.shape
+    X = torch.zeros((s, n), dtype=torch.float64, device=B.device).t()
+    if X0 is not None:
+        X.copy_(X0.reshape(n, s))
+    it = (ctypes.c_int * s)()
+    rr = (ctypes.c_double * s)()
+    st = lib().cg_solve(_ptr(Kc), n, ldk, None if precond is None else precond.handle, _ptr(Bc), s, ldb, _ptr(X), n,
+                        tol, maxit, it, rr, _stream(stream))
     if st not in (HODLR_OK, HODLR_ENOCONV) or (raise_on_noconv and st == HODLR_ENOCONV):
         _check(st)
     return X, list(it), list(rr), st

@@ -37,6 +37,7 @@ def test_default_opts(L):
     o = hodlr.default_opts()
     assert (o.leaf, o.tol, o.method, o.bdlr_depth, o.max_rank, o.precision) == (128, 1e-4, 0, 1, 0, 32)
     assert (o.skel_k, o.mlp_params, o.seed) == (32, None, 0)
+    assert (o.skel_tol, o.bdlr_max_skel, o.symmetric) == (0.0, 0, 0)
 
 
 def test_argument_validation(L):
@@ -76,6 +77,14 @@ def test_argument_validation(L):
     assert L.gmres_solve(p, 10, 10, None, p, 1, 10, p, 10, 0.0, 10, 10, it, rr, None) == H.HODLR_EINVAL
     assert L.gmres_solve(p, 10, 10, None, p, 0, 10, p, 10, 1e-12, 10, 10, it, rr, None) == H.HODLR_EINVAL
     assert L.gmres_solve(p, 10, 9, None, p, 1, 10, p, 10, 1e-12, 10, 10, it, rr, None) == H.HODLR_EINVAL
+    assert L.cg_solve(p, 10, 10, None, p, 1, 10, p, 10, 0.0, 10, it, rr, None) == H.HODLR_EINVAL
+    assert L.cg_solve(p, 10, 10, None, p, 65, 10, p, 10, 1e-12, 10, it, rr, None) == H.HODLR_EINVAL
+    assert L.cg_solve(p, 10, 10, None, p, 1, 10, p, 10, 1e-12, 0, it, rr, None) == H.HODLR_EINVAL
+    assert L.cg_solve(p, 10, 10, None, p, 1, 10, p, 9, 1e-12, 10, it, rr, None) == H.HODLR_EINVAL
+    o = H.default_opts()
+    o.symmetric = 2
+    st = L.hodlr_build(ctypes.c_void_p(16), 10, 10, None, None, None, ctypes.byref(o), None, ctypes.byref(out))
+    assert st == H.HODLR_EINVAL and b"symmetric" in L.hodlr_last_error()
     assert L.hodlr_order_rcb(p, 0, 4, p, None) == H.HODLR_EINVAL
     assert L.hodlr_order_rcb(p, 20000, 4, p, None) == H.HODLR_EINVAL
     assert L.hodlr_permute(p, 10, 10, p, p, 10, None) == H.HODLR_EINVAL  # in place
