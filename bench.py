@@ -41,6 +41,9 @@ def parse():
     ap.add_argument("--depth", type=int, default=2, help="BDLR boundary distance")
     ap.add_argument("--solver", choices=["gmres", "cg"], default="gmres",
                     help="cg: symmetric HODLR build and preconditioned CG instead of GMRES")
+    ap.add_argument("--study", choices=["sweep"], default=None,
+                    help="sweep: the tolerance table (ACA and BDLR at 1e-1, 1e-3, 1e-5, plus a float64 "
+                         "high-accuracy HODLR used alone) on the TPFA and elasticity fronts")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain 256 MiB device copy 3 times (reference for HBM counters)")
     return ap.parse_args()
@@ -259,6 +262,92 @@ def main_batch(args):
     }), flush=True)
 
 
+def main_sweep(args):
+    """The analogue of the paper's timing table (Sec. 7, Table 3): for each
+    front, compression method and tolerance eps in {1e-1, 1e-3, 1e-5}
+    (BDLR depth 1, 3, 5 with them), the end-to-end time T (ordering,
+    permutation, compression, factorization and GMRES to 1e-12; median of
+    `--steps` runs after a warm-up) and the GMRES steps I, against the
+    GPU dense FP64 LU (factor + solve).  One more row per front: a float64
+    HODLR at eps = 1e-8 used as a direct solver (one solve, no GMRES) with
+    its relative residual, the high-accuracy mode the paper compares
+    against.  The float32 factorization is used for eps >= 1e-5."""
+    import numpy as np
+    import torch
+
+    import paper_1403_5337_amd.hodlr as H
+    from gen import fronts
+
+    dev = torch.device("cuda:0")
+    H.lib()
+    out = []
+    for wname in ("tpfa4096", "elastic4800"):
+        w = fronts.WORKLOADS[wname]
+        front = fronts.make_workload(wname, device=dev)
+        n, leaf = front.n, w["leaf"]
+        K = front.K.t().contiguous().t()
+        coords = torch.from_numpy(front.coords).to(dev)
+        g_rp = torch.from_numpy(front.indptr).to(dev)
+        g_ci = torch.from_numpy(front.indices).to(dev)
+        B = fronts.rhs(n, 1, seed=0, device=dev).t().contiguous().t()
+
+        def run(method, eps, depth, prec, direct=False):
+            perm = H.hodlr_order_rcb(coords, leaf)
+            Kp = H.hodlr_permute(K, perm)
+            graph = H.hodlr_permute_graph(g_rp, g_ci, perm) if method == "bdlr" else None
+            h = H.Hodlr.build(Kp, leaf=leaf, tol=eps, precision=prec, method=method, depth=depth, graph=graph)
+            h.factor()
+            if direct:
+                X = h.solve(B)
+                r = (B - Kp @ X.double()).norm() / B.norm()
+                res = (X, [0], [float(r)], H.HODLR_OK)
+            else:
+                res = H.gmres_solve(Kp, B, h, tol=1e-12, maxit=1000, restart=200)
+            ranks = [max(r) for r in h.stats()["ranks"]]
+            h.close()
+            return res, ranks
+
+        def timed(*a, **k):
+            run(*a, **k)
+            ts = []
+            for _ in range(max(1, args.steps)):
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                (X, it, rr, st), ranks = run(*a, **k)
+                torch.cuda.synchronize()
+                ts.append((time.perf_counter() - t0) * 1e3)
+            return float(np.median(ts)), it, rr, st, ranks
+
+        rows = []
+        for method in ("aca", "bdlr"):
+            for eps, depth in ((1e-1, 1), (1e-3, 3), (1e-5, 5)):
+                ms, it, rr, st, ranks = timed(method, eps, depth, 32)
+                rows.append(dict(method=method, eps=eps, depth=depth if method == "bdlr" else None,
+                                 precision=32, T_ms=round(ms, 3), I=max(it), relres=max(rr),
+                                 converged=st == H.HODLR_OK, ranks_max=ranks))
+                print(f"# {wname} {method} {eps:g}: T {ms:.2f} ms, I {max(it)}, relres {max(rr):.2e}",
+                      file=sys.stderr, flush=True)
+        ms, it, rr, st, ranks = timed("aca", 1e-8, 1, 64, direct=True)
+        rows.append(dict(method="aca", eps=1e-8, depth=None, precision=64, direct=True, T_ms=round(ms, 3),
+                         I=0, relres=max(rr), converged=max(rr) <= 1e-12, ranks_max=ranks))
+        print(f"# {wname} direct f64 1e-8: T {ms:.2f} ms, relres {max(rr):.2e}", file=sys.stderr, flush=True)
+        LU, piv = torch.linalg.lu_factor(K)
+        torch.linalg.lu_solve(LU, piv, B)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(3):
+            LU, piv = torch.linalg.lu_factor(K)
+            torch.linalg.lu_solve(LU, piv, B)
+        torch.cuda.synchronize()
+        lu_ms = (time.perf_counter() - t0) * 1e3 / 3
+        best = {m: min((r["T_ms"] for r in rows if r["method"] == m and r["converged"] and not r.get("direct")),
+                       default=None) for m in ("aca", "bdlr")}
+        out.append(dict(workload=wname, n=n, nrhs=1, leaf=leaf, rows=rows, gpu_dense_lu_ms=round(lu_ms, 3),
+                        speedup_vs_lu={m: None if v is None else round(lu_ms / v, 3) for m, v in best.items()}))
+    print(json.dumps({"study": "tolerance sweep (paper Table 3 analogue)", "gmres_tol": 1e-12, "fronts": out}),
+          flush=True)
+
+
 def main():
     args = parse()
     if args.calibrate_copy:
@@ -282,6 +371,8 @@ def main():
 
     if args.workload == "nd64":
         return main_batch(args)
+    if args.study == "sweep":
+        return main_sweep(args)
     w = dict(fronts.WORKLOADS[args.workload])
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     dev = torch.device("cuda:0")

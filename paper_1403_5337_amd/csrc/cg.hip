@@ -33,10 +33,26 @@ namespace hodlr {
 constexpr int kCgThreads = 1024;
 constexpr int kCgMaxRhs = 64;
 
-// q(i) of column k: the sum of the nsplit partial products of K p
+// Each thread takes elements t, t + kCgThreads, ... of its column, kE of them
+// per round with all their loads issued together; the sums run in element
+// order, so the result does not depend on the batching.
+constexpr int kE = 4;
+
+// q(i) of column k: the sum of the nsplit partial products of K p, in split
+// order, loaded 8 at a time
 __device__ __forceinline__ double cg_q(const double* __restrict__ part, int nsplit, int s, int n, int k, int i) {
+  const double* pp = part + (size_t)k * n + i;
+  const size_t st = (size_t)s * n;
   double q = 0.0;
-  for (int sp = 0; sp < nsplit; ++sp) q += part[((size_t)sp * s + k) * n + i];
+  int sp = 0;
+  for (; sp + 8 <= nsplit; sp += 8) {
+    double v[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) v[u] = pp[(size_t)(sp + u) * st];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) q += v[u];
+  }
+  for (; sp < nsplit; ++sp) q += pp[(size_t)sp * st];
   return q;
 }
 
@@ -66,11 +82,22 @@ __global__ void __launch_bounds__(kCgThreads)
   __shared__ double red[kCgThreads / 64];
   const int k = blockIdx.x, t = threadIdx.x;
   double v = 0.0;
-  for (int i = t; i < n; i += kCgThreads) {
-    const double r = B[(size_t)k * ldb + i] - cg_q(part, nsplit, s, n, k, i);
-    R[(size_t)k * n + i] = r;
-    Z[(size_t)k * n + i] = (TP)r;
-    v += r * r;
+  for (int i0 = t; i0 < n; i0 += kE * kCgThreads) {
+    double r[kE];
+#pragma unroll
+    for (int e = 0; e < kE; ++e) {
+      const int i = i0 + e * kCgThreads;
+      r[e] = i < n ? B[(size_t)k * ldb + i] - cg_q(part, nsplit, s, n, k, i) : 0.0;
+    }
+#pragma unroll
+    for (int e = 0; e < kE; ++e) {
+      const int i = i0 + e * kCgThreads;
+      if (i < n) {
+        R[(size_t)k * n + i] = r[e];
+        Z[(size_t)k * n + i] = (TP)r[e];
+      }
+      v += r[e] * r[e];
+    }
   }
   v = block_sum(v, red);
   const double bn = bnorm[k], rel = bn > 0.0 ? sqrt(v) / bn : 0.0;
@@ -104,9 +131,21 @@ __global__ void __launch_bounds__(kCgThreads)
   const double rz_old = rz[k];
   const bool first = rz_old == 0.0;
   double a = 0.0, b = 0.0;
-  for (int i = t; i < n; i += kCgThreads) {
-    a += r[i] * (double)z[i];
-    if (!first) b += r[i] * (double)zo[i];
+  for (int i0 = t; i0 < n; i0 += kE * kCgThreads) {
+    double rv[kE], zv[kE], ov[kE];
+#pragma unroll
+    for (int e = 0; e < kE; ++e) {
+      const int i = i0 + e * kCgThreads;
+      const bool in = i < n;
+      rv[e] = in ? r[i] : 0.0;
+      zv[e] = in ? (double)z[i] : 0.0;
+      ov[e] = (in && !first) ? (double)zo[i] : 0.0;
+    }
+#pragma unroll
+    for (int e = 0; e < kE; ++e) {
+      a += rv[e] * zv[e];
+      b += rv[e] * ov[e];
+    }
   }
   const double rzn = block_sum(a, red);
   const double rzo = first ? 0.0 : block_sum(b, red);
@@ -115,10 +154,24 @@ __global__ void __launch_bounds__(kCgThreads)
     return;
   }
   const double beta = first ? 0.0 : (rzn - rzo) / rz_old;
-  for (int i = t; i < n; i += kCgThreads) {
-    const TP zi = z[i];
-    p[i] = first ? (double)zi : (double)zi + beta * p[i];
-    zo[i] = zi;
+  for (int i0 = t; i0 < n; i0 += kE * kCgThreads) {
+    TP zv[kE];
+    double pv[kE];
+#pragma unroll
+    for (int e = 0; e < kE; ++e) {
+      const int i = i0 + e * kCgThreads;
+      const bool in = i < n;
+      zv[e] = in ? z[i] : TP(0);
+      pv[e] = (in && !first) ? p[i] : 0.0;
+    }
+#pragma unroll
+    for (int e = 0; e < kE; ++e) {
+      const int i = i0 + e * kCgThreads;
+      if (i < n) {
+        p[i] = first ? (double)zv[e] : (double)zv[e] + beta * pv[e];
+        zo[i] = zv[e];
+      }
+    }
   }
   if (t == 0) rz[k] = rzn;
 }
@@ -137,8 +190,30 @@ __global__ void __launch_bounds__(kCgThreads)
   int go = act[k];
   if (go) {
     const double* p = P + (size_t)k * n;
+    // q kept in registers for the update when the column is short enough
+    constexpr int kKeep = 4;
+    double qk[kKeep][kE];
+    const bool keep = n <= kKeep * kE * kCgThreads;
     double v = 0.0;
-    for (int i = t; i < n; i += kCgThreads) v += p[i] * cg_q(part, nsplit, s, n, k, i);
+    for (int i0 = t, c = 0; i0 < n; i0 += kE * kCgThreads, ++c) {
+      double pv[kE], qv[kE];
+#pragma unroll
+      for (int e = 0; e < kE; ++e) {
+        const int i = i0 + e * kCgThreads;
+        const bool in = i < n;
+        pv[e] = in ? p[i] : 0.0;
+        qv[e] = in ? cg_q(part, nsplit, s, n, k, i) : 0.0;
+      }
+#pragma unroll
+      for (int e = 0; e < kE; ++e) {
+        v += pv[e] * qv[e];
+        if (keep) {
+#pragma unroll
+          for (int cc = 0; cc < kKeep; ++cc)
+            if (cc == c) qk[cc][e] = qv[e];
+        }
+      }
+    }
     const double pq = block_sum(v, red);
     if (!(pq > 0.0)) {
       go = 0;  // K not positive definite along p: end the cycle
@@ -148,13 +223,36 @@ __global__ void __launch_bounds__(kCgThreads)
       double* r = R + (size_t)k * n;
       TP* z = Z + (size_t)k * n;
       double w = 0.0;
-      for (int i = t; i < n; i += kCgThreads) {
-        const double q = cg_q(part, nsplit, s, n, k, i);
-        x[i] += alpha * p[i];
-        const double ri = r[i] - alpha * q;
-        r[i] = ri;
-        z[i] = (TP)ri;
-        w += ri * ri;
+      for (int i0 = t, c = 0; i0 < n; i0 += kE * kCgThreads, ++c) {
+        double pv[kE], qv[kE], xv[kE], rv[kE];
+#pragma unroll
+        for (int e = 0; e < kE; ++e) {
+          const int i = i0 + e * kCgThreads;
+          const bool in = i < n;
+          double qq = 0.0;
+          if (keep) {
+#pragma unroll
+            for (int cc = 0; cc < kKeep; ++cc)
+              if (cc == c) qq = qk[cc][e];
+          } else if (in) {
+            qq = cg_q(part, nsplit, s, n, k, i);
+          }
+          qv[e] = in ? qq : 0.0;
+          pv[e] = in ? p[i] : 0.0;
+          xv[e] = in ? x[i] : 0.0;
+          rv[e] = in ? r[i] : 0.0;
+        }
+#pragma unroll
+        for (int e = 0; e < kE; ++e) {
+          const int i = i0 + e * kCgThreads;
+          const double ri = rv[e] - alpha * qv[e];
+          if (i < n) {
+            x[i] = xv[e] + alpha * pv[e];
+            r[i] = ri;
+            z[i] = (TP)ri;
+          }
+          w += (i < n) ? ri * ri : 0.0;
+        }
       }
       const double rr = block_sum(w, red);
       const int tot = total[k] + 1;
