@@ -281,7 +281,7 @@ def main_sweep(args):
     dev = torch.device("cuda:0")
     H.lib()
     out = []
-    for wname in ("tpfa4096", "elastic4800"):
+    for wname in ("tpfa4096", "elastic4800", "tet64k"):
         w = fronts.WORKLOADS[wname]
         front = fronts.make_workload(wname, device=dev)
         n, leaf = front.n, w["leaf"]

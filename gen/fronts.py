@@ -258,6 +258,9 @@ WORKLOADS = {
                      leaf=128, tol=1e-4, precision=32, nrhs=8),
     "elastic4800": dict(gen="q1", free_shape=(40, 40, 39), zs=19, perm_seed=0,
                         leaf=128, tol=1e-4, precision=32, nrhs=1),
+    # unstructured: P1 Laplacian on a Delaunay mesh of 64000 seeded points,
+    # mid-plane vertex separator (n about 2000)
+    "tet64k": dict(gen="tet", npoints=64000, seed=0, leaf=128, tol=1e-4, precision=32, nrhs=1),
 }
 
 
@@ -269,4 +272,7 @@ def make_workload(name: str, device="cpu") -> Front:
     if w["gen"] == "q1":
         return elasticity_front(w["free_shape"], zs=w["zs"], perm_seed=w["perm_seed"],
                                 device=device, name=name)
+    if w["gen"] == "tet":
+        from .meshes import tet_front
+        return tet_front(w["npoints"], seed=w["seed"], device=device, name=name)
     raise KeyError(name)

@@ -159,3 +159,54 @@ def test_nd_fronts_are_box_schur_complements():
         ax = {"x": 0, "y": 1, "z": 2}[f.meta["axis"]]
         lo, hi = f.meta["box"][2 * ax], f.meta["box"][2 * ax + 1]
         assert np.all(c[:, ax] == lo + (hi - lo) // 2)
+
+
+# ---------------------------------------------------------------------------
+# unstructured tetrahedral meshes (gen/meshes.py)
+# ---------------------------------------------------------------------------
+def test_p1_reference_element():
+    """The P1 stiffness of the unit right tetrahedron, by hand: |T| = 1/6 and
+    the basis gradients (-1,-1,-1), e_x, e_y, e_z."""
+    from gen import meshes
+    pts = np.array([[0.0, 0, 0], [1, 0, 0], [0, 1, 0], [0, 0, 1]])
+    A = meshes.p1_laplacian(pts, np.array([[0, 1, 2, 3]])).toarray()
+    want = np.array([[3, -1, -1, -1], [-1, 1, 0, 0], [-1, 0, 1, 0], [-1, 0, 0, 1]]) / 6.0
+    assert np.allclose(A, want, atol=1e-15)
+
+
+def test_p1_constants_and_linear_patch():
+    """Rows sum to zero (constants are harmonic) and a linear function is
+    discretely harmonic at every vertex off the boundary."""
+    from gen import meshes
+    pts, tets = meshes.tet_mesh(1500, seed=3)
+    A = meshes.p1_laplacian(pts, tets)
+    scale = abs(A).max()
+    assert np.abs(A @ np.ones(pts.shape[0])).max() <= 1e-12 * scale
+    u = pts @ np.array([0.3, -1.2, 0.7]) + 2.0
+    inner = np.setdiff1d(np.arange(pts.shape[0]), meshes.hull_vertices(pts))
+    assert np.abs((A @ u)[inner]).max() <= 1e-11 * scale
+
+
+def test_tet_front_is_the_schur_complement_and_spd():
+    from gen import meshes
+    f = meshes.tet_front(1500, seed=4)
+    pts, tets = meshes.tet_mesh(1500, seed=4)
+    A = meshes.p1_laplacian(pts, tets)
+    free = np.setdiff1d(np.arange(pts.shape[0]), meshes.hull_vertices(pts))
+    S = meshes.mid_separator(pts, A, free)
+    I = np.setdiff1d(free, S)
+    D = A.toarray()
+    want = D[np.ix_(S, S)] - D[np.ix_(S, I)] @ np.linalg.solve(D[np.ix_(I, I)], D[np.ix_(I, S)])
+    K = f.K.numpy()
+    assert np.abs(K - want).max() <= 1e-11 * np.abs(want).max()
+    assert np.linalg.eigvalsh(K).min() > 0
+    # the separator disconnects the two halves: no edge joins I below to I above
+    below = pts[I, 2] < 0.5
+    C = A[I][:, I].tocoo()
+    assert not np.any((below[C.row] != below[C.col]) & (C.data != 0.0))
+    # graph = pattern of A_SS, symmetric, no self loops
+    G = sp.csr_matrix((np.ones(f.indices.size), f.indices, f.indptr), shape=(f.n, f.n)).toarray()
+    P = (np.abs(D[np.ix_(S, S)]) > 0).astype(float)
+    np.fill_diagonal(P, 0)
+    assert np.array_equal(G, P) and np.array_equal(G, G.T)
+    assert np.allclose(f.coords, pts[S].astype(np.float32))
