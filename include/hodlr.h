@@ -110,8 +110,9 @@ void hodlr_default_opts(hodlr_opts* opts);
  *   out     host; receives the new handle.
  * Synchronizes the stream once (to size the factor storage from the ranks
  * found; HODLR_LEARNED synchronizes once per size tried).  Errors: EINVAL
- * (n < 1, ldk < n, NULL K/out, bad opts, BDLR or learned with n > 16384 or
- * without the graph, learned without coords or parameters), ENOMEM, EHIP. */
+ * (n < 1, n > 16384 (every compression keeps a block side <= 8192), ldk < n,
+ * NULL K/out, bad opts, BDLR or learned without the graph, learned without
+ * coords or parameters), ENOMEM, EHIP. */
 int hodlr_build(const double* K, int n, int ldk, const int* g_rowptr, const int* g_col,
                 const float* coords, const hodlr_opts* opts, hipStream_t stream, hodlr_t* out);
 

@@ -488,7 +488,7 @@ static int build_impl(const double* K, int n, int ldk, const int* g_rowptr, cons
   if (o.method != HODLR_ACA && (!g_rowptr || !g_col))
     return fail(HODLR_EINVAL, "BDLR and learned skeletons need the separator graph (g_rowptr, g_col)");
   if (o.method == HODLR_LEARNED && !coords) return fail(HODLR_EINVAL, "learned skeletons need coords");
-  if (o.method != HODLR_ACA && n > 16384) return fail(HODLR_EINVAL, "BDLR supports n <= 16384");
+  if (n > 16384) return fail(HODLR_EINVAL, "hodlr_build supports n <= 16384 (block sides <= 8192)");
   std::unique_ptr<hodlr_s> h(new hodlr_s());
   h->method = o.method;
   h->depth = o.bdlr_depth;

@@ -82,6 +82,8 @@ def test_argument_validation(L):
     assert L.cg_solve(p, 10, 10, None, p, 1, 10, p, 10, 1e-12, 0, it, rr, None) == H.HODLR_EINVAL
     assert L.cg_solve(p, 10, 10, None, p, 1, 10, p, 9, 1e-12, 10, it, rr, None) == H.HODLR_EINVAL
     o = H.default_opts()
+    st = L.hodlr_build(ctypes.c_void_p(16), 16385, 16385, None, None, None, ctypes.byref(o), None, ctypes.byref(out))
+    assert st == H.HODLR_EINVAL and b"16384" in L.hodlr_last_error()
     o.symmetric = 2
     st = L.hodlr_build(ctypes.c_void_p(16), 10, 10, None, None, None, ctypes.byref(o), None, ctypes.byref(out))
     assert st == H.HODLR_EINVAL and b"symmetric" in L.hodlr_last_error()
