@@ -205,20 +205,22 @@ def main_batch(args):
             perm = H.hodlr_order_rcb(xyz, 128)
             Ks.append(H.hodlr_permute(K, perm))
             gs.append(H.hodlr_permute_graph(rp, ci, perm))
+        if ev is not None:
+            ev[1].record()
         # the fronts are compressed side by side (hodlr_build_batched)
         hs = H.Hodlr.build_batched(Ks, graphs=gs, leaf=128, tol=1e-4, method="bdlr", depth=2)
         if ev is not None:
-            ev[1].record()
+            ev[2].record()
         H.hodlr_factor_batched(hs)
         if ev is not None:
-            ev[2].record()
+            ev[3].record()
         # and solved side by side (gmres_solve_batched)
         Xs, it, rr, st = H.gmres_solve_batched(Ks, [d[4] for d in data], hs, tol=1e-12, maxit=1000, restart=200)
         assert st == H.HODLR_OK, st
         its = [max(i) for i in it]
         rrs = [max(r) for r in rr]
         if ev is not None:
-            ev[3].record()
+            ev[4].record()
         for h in hs:
             h.close()
         return its, rrs
@@ -226,14 +228,14 @@ def main_batch(args):
     for _ in range(args.warmup):
         step()
     torch.cuda.synchronize()
-    evs = [[torch.cuda.Event(enable_timing=True) for _ in range(4)] for _ in range(args.steps)]
+    evs = [[torch.cuda.Event(enable_timing=True) for _ in range(5)] for _ in range(args.steps)]
     t1 = time.perf_counter()
     for k in range(args.steps):
         its, rrs = step(evs[k])
     torch.cuda.synchronize()
     ms = (time.perf_counter() - t1) * 1e3 / args.steps
-    st = np.array([[evs[k][j].elapsed_time(evs[k][j + 1]) for j in range(3)] for k in range(args.steps)])
-    stage = dict(zip(["order_build", "factor_graph", "gmres"], np.median(st, axis=0).round(3).tolist()))
+    st = np.array([[evs[k][j].elapsed_time(evs[k][j + 1]) for j in range(4)] for k in range(args.steps)])
+    stage = dict(zip(["order", "build", "factor_graph", "gmres"], np.median(st, axis=0).round(3).tolist()))
     lu_ms = None
     if not args.no_lu:
         def lu_all():
