@@ -139,3 +139,53 @@ def test_bdlr_on_front_depth_improves():
         errs.append(np.linalg.norm(B - U @ V.T) / np.linalg.norm(B))
     assert errs[0] < 1e-1
     assert errs[-1] < errs[0] and errs[-1] < 1e-3
+
+
+# ---------------------------------------------------------------------------
+# the error monitor and the adaptive depth (Sec. 5.3)
+# ---------------------------------------------------------------------------
+def test_sampled_error_hand_cases():
+    B = np.diag([1.0, 2.0, 3.0, 4.0])
+    rng = np.random.default_rng(0)
+    avoid = np.array([0, 1, 2])
+    # exact: zero; nothing: one; diag(1,2,3,2): row 3 and column 3 each miss by 2,
+    # so sqrt((4 + 4) / (16 + 16)) = 1/2
+    assert bdlr.sampled_error(B, B.copy(), np.eye(4), avoid, avoid, 1, rng) == 0.0
+    assert bdlr.sampled_error(B, np.zeros((4, 1)), np.zeros((4, 1)), avoid, avoid, 1, rng) == 1.0
+    e = bdlr.sampled_error(B, np.diag([1.0, 2.0, 3.0, 2.0]), np.eye(4), avoid, avoid, 1, rng)
+    assert abs(e - 0.5) < 1e-15
+
+
+def three_scale_block(n):
+    """Rows I = 0..n-1 and columns J = n..2n-1 of a path graph with edge
+    (n-1, n); B(i, j) = sum of three exponentials of the graph distance
+    j - i: exactly rank 3, each term reaching one layer further from the
+    boundary, so the skeleton needs the first three distance layers."""
+    indptr, indices = path_graph(2 * n)
+    I, J = np.arange(n), np.arange(n, 2 * n)
+    D = (J[None, :] - I[:, None]).astype(float)
+    B = np.exp(-0.3 * D) + 0.5 * np.exp(-1.0 * D) + 0.25 * np.exp(-2.0 * D)
+    return indptr, indices, I, J, B
+
+
+def test_adaptive_depth_deepens_until_the_error_meets_eps():
+    indptr, indices, I, J, B = three_scale_block(40)
+    eps = 1e-10
+    U, V, depth, err = bdlr.bdlr_adaptive(B, indptr, indices, I, J, 1, eps, max_depth=40, seed=1)
+    assert depth == 3 and err <= eps and U.shape[1] == 3
+    # the factors are the fixed-depth skeleton at the depth reached
+    U2, V2 = bdlr.bdlr(B, indptr, indices, I, J, depth, eps)
+    assert np.array_equal(U, U2) and np.array_equal(V, V2)
+    assert np.linalg.norm(B - U @ V.T) <= 1e-14 * np.linalg.norm(B)
+    # one layer fewer leaves a term out
+    U1, V1 = bdlr.bdlr(B, indptr, indices, I, J, depth - 1, eps)
+    assert np.linalg.norm(B - U1 @ V1.T) > 1e-4 * np.linalg.norm(B)
+    # a start that already passes is kept
+    _, _, d2, _ = bdlr.bdlr_adaptive(B, indptr, indices, I, J, 5, eps, max_depth=40, seed=1)
+    assert d2 == 5
+
+
+def test_adaptive_depth_stops_at_the_maximum():
+    indptr, indices, I, J, B = three_scale_block(30)
+    _, _, depth, err = bdlr.bdlr_adaptive(B, indptr, indices, I, J, 1, 1e-10, max_depth=2, seed=2)
+    assert depth == 2 and err > 1e-10
