@@ -177,7 +177,8 @@ def main_batch(args):
     2, hodlr_build_batched), the 63 factorizations run as one captured HIP
     graph, then FP64 GMRES solves 32 right-hand sides per front to 1e-12, the
     fronts side by side (gmres_solve_batched).  value = right-hand sides
-    solved per second."""
+    solved per second.  The ordering and relabelling of all fronts is one
+    call as well (hodlr_order_batched)."""
     import numpy as np
     import torch
 
@@ -194,17 +195,16 @@ def main_batch(args):
     data = []
     for f in fr:
         K = f.K.t().contiguous().t()
-        data.append((K, torch.from_numpy(f.coords).to(dev), torch.from_numpy(f.indptr).to(dev),
-                     torch.from_numpy(f.indices).to(dev), fronts.rhs(f.n, s, seed=f.n, device=dev)))
+        data.append((K, torch.from_numpy(f.coords).to(dev).contiguous(),
+                     torch.from_numpy(f.indptr).to(dev).to(torch.int32), torch.from_numpy(f.indices).to(dev).to(torch.int32),
+                     fronts.rhs(f.n, s, seed=f.n, device=dev)))
 
     def step(ev=None):
         if ev is not None:
             ev[0].record()
-        Ks, gs = [], []
-        for K, xyz, rp, ci, _ in data:
-            perm = H.hodlr_order_rcb(xyz, 128)
-            Ks.append(H.hodlr_permute(K, perm))
-            gs.append(H.hodlr_permute_graph(rp, ci, perm))
+        # every front ordered and relabelled side by side (hodlr_order_batched)
+        _, Ks, gs = H.hodlr_order_batched([d[1] for d in data], [d[0] for d in data],
+                                          graphs=[(d[2], d[3]) for d in data], leaf=128)
         if ev is not None:
             ev[1].record()
         # the fronts are compressed side by side (hodlr_build_batched)

@@ -79,6 +79,17 @@ typedef struct {
                                 magnitude above tol) */
   int bdlr_max_skel;         /* HODLR_BDLR: cap on the rows (columns) picked
                                 per side, nearest first (0 = 192 / 128) */
+  int bdlr_max_depth;        /* HODLR_BDLR: 0 (default) = every block at
+                                bdlr_depth.  Otherwise the error monitor of
+                                Sec. 5.3: a block whose sampled error (the
+                                estimate of HODLR_LEARNED, seed opts.seed) is
+                                above skel_tol (0 = 30 tol) takes one more
+                                distance layer, up to bdlr_max_depth
+                                (bdlr_depth..250) or until a layer adds no
+                                pick; a block that never passes keeps its
+                                deepest skeleton.  hodlr_skel_info gives the
+                                depth each block ended at.  One stream
+                                synchronization per layer tried. */
   int symmetric;             /* 1: K is symmetric (the symmetric case of eq.
                                 HODLR2: a node's two off-diagonal blocks are
                                 each other's transposes).  Only the block of
@@ -92,7 +103,7 @@ typedef struct {
 
 /* Fill *opts with defaults: leaf 128, tol 1e-4, ACA, depth 1, max_rank 0,
  * precision 32, skel_k 32, mlp_params NULL, seed 0, skel_tol 0,
- * bdlr_max_skel 0, symmetric 0. */
+ * bdlr_max_skel 0, bdlr_max_depth 0, symmetric 0. */
 void hodlr_default_opts(hodlr_opts* opts);
 
 /* Compress K into a HODLR matrix (Sec. 4.3.1 step 1).
@@ -219,6 +230,18 @@ int hodlr_build_batched(int nf, const double* const* K, const int* n, const int*
                         const int* const* g_rowptr, const int* const* g_col, const float* const* coords,
                         const hodlr_opts* opts, hipStream_t stream, hodlr_t* out);
 
+/* hodlr_order_batched: for every front f, hodlr_order_rcb(coords[f], n[f],
+ * leaf, perm[f]), then hodlr_permute(K[f], n[f], ldk[f], perm[f], Kout[f],
+ * ldo[f]), then (if g_rowptr is not NULL) hodlr_permute_graph(g_rowptr[f],
+ * g_col[f], n[f], perm[f], rowptr_out[f], col_out[f]); every output array is
+ * caller-owned device memory sized as for the single calls.  The fronts'
+ * ordering and relabelling are the first step of the path (the index-halving
+ * tree of Sec. 4.1 needs a bisection order of each separator). */
+int hodlr_order_batched(int nf, const float* const* coords, const int* n, int leaf, const double* const* K,
+                        const int* ldk, const int* const* g_rowptr, const int* const* g_col, int* const* perm,
+                        double* const* Kout, const int* ldo, int* const* rowptr_out, int* const* col_out,
+                        hipStream_t stream);
+
 /* gmres_solve_batched: front f solves K[f] X[f] = B[f] with preconditioner
  * precond[f] (precond may be NULL for none); iters and relres are host
  * arrays of nf * nrhs entries, front f at f * nrhs. */
@@ -273,8 +296,9 @@ int hodlr_stats(hodlr_t h, int* nlevels, int* ranks, int* rcols);
 int hodlr_get_factors(hodlr_t h, double* Upanel, double* Vpanel, hipStream_t stream);
 
 /* HODLR_LEARNED handles: per node below the root in level order, the
- * skeleton size that passed the check, 0 where the block fell back to ACA
- * (-1 for handles built otherwise).  kused: host, 2^(L+1)-2 ints. */
+ * skeleton size that passed the check, 0 where the block fell back to ACA.
+ * Adaptive BDLR handles (bdlr_max_depth > 0): the depth each block ended at.
+ * -1 for handles built otherwise.  kused: host, 2^(L+1)-2 ints. */
 int hodlr_skel_info(hodlr_t h, int* kused);
 
 /* Learned skeleton proposer (not in the paper; it proposes the skeleton rows

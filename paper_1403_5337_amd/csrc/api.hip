@@ -432,6 +432,7 @@ void hodlr_default_opts(hodlr_opts* o) {
   o->skel_tol = 0.0;
   o->bdlr_max_skel = 0;
   o->symmetric = 0;
+  o->bdlr_max_depth = 0;
 }
 
 const char* hodlr_last_error(void) { return g_last_error.c_str(); }
@@ -447,6 +448,8 @@ static int check_opts(const hodlr_opts& o) {
   if (!(o.skel_tol >= 0.0) || !std::isfinite(o.skel_tol)) return fail(HODLR_EINVAL, "opts.skel_tol must be >= 0");
   if (o.bdlr_max_skel < 0) return fail(HODLR_EINVAL, "opts.bdlr_max_skel must be >= 0");
   if (o.symmetric != 0 && o.symmetric != 1) return fail(HODLR_EINVAL, "opts.symmetric must be 0 or 1");
+  if (o.bdlr_max_depth != 0 && (o.bdlr_max_depth < o.bdlr_depth || o.bdlr_max_depth > 250))
+    return fail(HODLR_EINVAL, "opts.bdlr_max_depth must be 0 or in [bdlr_depth, 250]");
   if (o.precision != 32 && o.precision != 64)
     return fail(HODLR_EINVAL, "opts.precision must be 32 or 64");
   if (o.leaf > leaf_cap(o.precision))
@@ -536,7 +539,11 @@ static int build_impl(const double* K, int n, int ldk, const int* g_rowptr, cons
     HODLR_HIP(hipMemsetAsync(Ucap.p, 0, (size_t)n * C * h->esize, stream));
     HODLR_HIP(hipMemsetAsync(Vcap.p, 0, (size_t)n * C * h->esize, stream));
     // compression of every off-diagonal block
-    if (o.method == HODLR_BDLR)
+    if (o.method == HODLR_BDLR && o.bdlr_max_depth > 0)
+      HODLR_TRY(launch_bdlr_adaptive(h.get(), K, ldk, g_rowptr, g_col, o.bdlr_max_depth, o.bdlr_max_skel, o.seed,
+                                     o.skel_tol > 0.0 ? o.skel_tol : 30.0 * o.tol, Ucap.p, Vcap.p, capoff, capq,
+                                     stream));
+    else if (o.method == HODLR_BDLR)
       HODLR_TRY(launch_bdlr(h.get(), K, ldk, g_rowptr, g_col, Ucap.p, Vcap.p, capoff, capq, stream,
                             o.bdlr_max_skel, piv_export));
     else if (o.method == HODLR_LEARNED)
@@ -887,6 +894,28 @@ int hodlr_build_batched(int nf, const double* const* K, const int* n, const int*
     }
     return fail(st, msg);
   }
+  return HODLR_OK;
+}
+
+int hodlr_order_batched(int nf, const float* const* coords, const int* n, int leaf, const double* const* K,
+                        const int* ldk, const int* const* g_rowptr, const int* const* g_col, int* const* perm,
+                        double* const* Kout, const int* ldo, int* const* rowptr_out, int* const* col_out,
+                        hipStream_t stream) {
+  if (nf < 1 || nf > 65536) return fail(HODLR_EINVAL, "nf must be in [1, 65536]");
+  if (!coords || !n || !K || !ldk || !perm || !Kout || !ldo) return fail(HODLR_EINVAL, "NULL argument array");
+  if (g_rowptr && (!g_col || !rowptr_out || !col_out)) return fail(HODLR_EINVAL, "graph arrays incomplete");
+  std::string msg;
+  const int st = Workers::get().run(
+      nf,
+      [&](int f, hipStream_t s) -> int {
+        HODLR_TRY(hodlr_order_rcb(coords[f], n[f], leaf, perm[f], s));
+        HODLR_TRY(hodlr_permute(K[f], n[f], ldk[f], perm[f], Kout[f], ldo[f], s));
+        if (g_rowptr)
+          HODLR_TRY(hodlr_permute_graph(g_rowptr[f], g_col[f], n[f], perm[f], rowptr_out[f], col_out[f], s));
+        return HODLR_OK;
+      },
+      stream, &msg);
+  if (st != HODLR_OK) return fail(st, msg);
   return HODLR_OK;
 }
 

@@ -852,6 +852,83 @@ static void draw_samples(unsigned long long& st, int len, const int* picked, int
 
 constexpr int kSkelSamples = 16;
 
+// Scratch of the attempt loops (learned proposals, adaptive BDLR depth).
+struct SkelScratch {
+  DevBuf tasks, sel, piv, cnt, rt, inv, cg, samp, err, norm;
+  int ensure(int nt, int selo, size_t invo, size_t cgo, size_t esize) {
+    HODLR_TRY(tasks.ensure(nt * sizeof(BdlrTask)));
+    HODLR_TRY(sel.ensure((size_t)selo * sizeof(int)));
+    HODLR_TRY(piv.ensure((size_t)selo * sizeof(int)));
+    HODLR_TRY(cnt.ensure((size_t)2 * nt * sizeof(int)));
+    HODLR_TRY(rt.ensure((size_t)nt * sizeof(int)));
+    HODLR_TRY(inv.ensure(std::max<size_t>(invo, 1) * esize));
+    HODLR_TRY(cg.ensure(std::max<size_t>(cgo, 1) * esize));
+    HODLR_TRY(samp.ensure((size_t)nt * 2 * kSkelSamples * sizeof(int)));
+    HODLR_TRY(err.ensure((size_t)nt * sizeof(double)));
+    return norm.ensure((size_t)nt * kNormChunks * sizeof(double));
+  }
+};
+
+// One attempt over the ns blocks of sub, whose picks are in sc.sel / sc.cnt
+// and whose tasks are in sc.tasks: the pivot-block LU and inverse, the
+// factors into Ucap / Vcap, then the sampled error of every block (samples
+// drawn outside its picks from a stream seeded by the block and the attempt)
+// into err; the pick counts (rows, columns per block) into cnt.  Synchronizes
+// the stream twice (the picks come back to draw the samples; the errors come
+// back to decide).
+template <typename T, int SKEL>
+static int skel_attempt(hodlr_s* h, const double* K, int ldk, const std::vector<BdlrTask>& sub, int maxside,
+                        int selo, SkelScratch& sc, T* Ucap, T* Vcap, unsigned long long seed, int attempt,
+                        std::vector<double>& err, std::vector<int>& cnt, hipStream_t s) {
+  const Tree& tr = h->tree;
+  const int ns = (int)sub.size();
+  const int rcap = h->precision == 64 ? kRankCap64 : kRankCap32;
+  {
+    ProfScope prof("bdlr_lu", s);
+    HODLR_TRY((launch_bdlr_lu<T, SKEL>(K, ldk, sc.tasks.as<BdlrTask>(), ns, sc.sel.as<int>(), sc.cnt.as<int>(),
+                                       (T)h->tol, rcap, sc.piv.as<int>(), sc.inv.as<T>(), h->d_rank.as<int>(),
+                                       sc.rt.as<int>(), s)));
+  }
+  const int nch = (maxside + kBlock - 1) / kBlock;
+  {
+    ProfScope prof("bdlr_gather", s);
+    k_bdlr_gather<T, SKEL><<<dim3(ns, nch, 2), kBlock, 0, s>>>(K, ldk, sc.tasks.as<BdlrTask>(), sc.piv.as<int>(),
+                                                              sc.rt.as<int>(), sc.cg.as<T>(), Vcap, tr.n);
+    k_bdlr_factors<T><<<dim3(ns, (maxside + 63) / 64, (rcap + 63) / 64), kBlock, 0, s>>>(
+        sc.tasks.as<BdlrTask>(), sc.rt.as<int>(), sc.cg.as<T>(), sc.inv.as<T>(), Ucap, tr.n);
+  }
+  HODLR_HIP(hipGetLastError());
+  // the picks come back to draw the samples outside them
+  cnt.assign(2 * ns, 0);
+  std::vector<int> sel(selo);
+  HODLR_HIP(hipMemcpyAsync(cnt.data(), sc.cnt.p, 2 * ns * sizeof(int), hipMemcpyDeviceToHost, s));
+  HODLR_HIP(hipMemcpyAsync(sel.data(), sc.sel.p, (size_t)selo * sizeof(int), hipMemcpyDeviceToHost, s));
+  HODLR_HIP(hipStreamSynchronize(s));
+  std::vector<int> smp((size_t)ns * 2 * kSkelSamples);
+  for (int x = 0; x < ns; ++x) {
+    const BdlrTask& tk = sub[x];
+    unsigned long long st = seed ^ (0xD1B54A32D192ED03ull * (unsigned long long)tk.node) ^
+                            (0x8CB92BA72F3D8DD7ull * (unsigned long long)(attempt + 1));
+    draw_samples(st, tk.m, sel.data() + tk.sel_off, cnt[2 * x], kSkelSamples,
+                 smp.data() + (size_t)x * 2 * kSkelSamples);
+    draw_samples(st, tk.nc, sel.data() + tk.sel_off + SKEL, cnt[2 * x + 1], kSkelSamples,
+                 smp.data() + (size_t)x * 2 * kSkelSamples + kSkelSamples);
+  }
+  HODLR_HIP(hipMemcpyAsync(sc.samp.p, smp.data(), smp.size() * sizeof(int), hipMemcpyHostToDevice, s));
+  {
+    ProfScope prof("skel_check", s);
+    k_block_norm2<<<dim3(ns, kNormChunks), kBlock, 0, s>>>(K, ldk, sc.tasks.as<BdlrTask>(), sc.norm.as<double>());
+    k_skel_check<T><<<ns, kBlock, 0, s>>>(K, ldk, sc.tasks.as<BdlrTask>(), sc.rt.as<int>(), sc.cnt.as<int>(),
+                                          sc.norm.as<double>(), Ucap, Vcap, tr.n, sc.samp.as<int>(), kSkelSamples,
+                                          sc.err.as<double>());
+  }
+  HODLR_HIP(hipGetLastError());
+  err.assign(ns, 0.0);
+  HODLR_HIP(hipMemcpyAsync(err.data(), sc.err.p, ns * sizeof(double), hipMemcpyDeviceToHost, s));
+  HODLR_HIP(hipStreamSynchronize(s));
+  return HODLR_OK;
+}
+
 template <typename T, int SKEL>
 static int learned_t(hodlr_s* h, const double* K, int ldk, const int* rowptr, const int* col, const float* xyz,
                      const float* params, int kinit, unsigned long long seed, double accept, T* Ucap, T* Vcap,
@@ -865,20 +942,11 @@ static int learned_t(hodlr_s* h, const double* K, int ldk, const int* rowptr, co
   const int N = 2 * tr.n * tr.L;  // every vertex is a row of one block and a column of another, per level
   int maxside = 0;
   for (auto& tk : tasks) maxside = std::max(maxside, std::max(tk.m, tk.nc));
-  DevBuf d_feat, d_score, d_tasks, d_sel, d_piv, d_cnt, d_rt, d_inv, d_cg, d_samp, d_err;
+  DevBuf d_feat, d_score;
   HODLR_TRY(d_feat.ensure((size_t)N * 8 * sizeof(float)));
   HODLR_TRY(d_score.ensure((size_t)N * sizeof(float)));
-  HODLR_TRY(d_tasks.ensure(nt * sizeof(BdlrTask)));
-  HODLR_TRY(d_sel.ensure((size_t)selo * sizeof(int)));
-  HODLR_TRY(d_piv.ensure((size_t)selo * sizeof(int)));
-  HODLR_TRY(d_cnt.ensure((size_t)2 * nt * sizeof(int)));
-  HODLR_TRY(d_rt.ensure((size_t)nt * sizeof(int)));
-  HODLR_TRY(d_inv.ensure(std::max<size_t>(invo, 1) * sizeof(T)));
-  HODLR_TRY(d_cg.ensure(std::max<size_t>(cgo, 1) * sizeof(T)));
-  HODLR_TRY(d_samp.ensure((size_t)nt * 2 * kSkelSamples * sizeof(int)));
-  HODLR_TRY(d_err.ensure((size_t)nt * sizeof(double)));
-  DevBuf d_norm;
-  HODLR_TRY(d_norm.ensure((size_t)nt * kNormChunks * sizeof(double)));
+  SkelScratch sc;
+  HODLR_TRY(sc.ensure(nt, selo, invo, cgo, sizeof(T)));
   {
     ProfScope prof("skel_features", s);
     HODLR_TRY(launch_skel_features(rowptr, col, xyz, K, ldk, blocks, d_feat.as<float>(), s));
@@ -888,63 +956,24 @@ static int learned_t(hodlr_s* h, const double* K, int ldk, const int* rowptr, co
     HODLR_TRY(launch_mlp_forward(d_feat.as<float>(), N, params, 1, d_score.as<float>(), s));
   }
   HODLR_HIP(hipMemsetAsync(h->d_rank.p, 0, tr.nnodes() * sizeof(int), s));
-  const int rcap = h->precision == 64 ? kRankCap64 : kRankCap32;
   h->skel_k.assign(tr.nnodes(), -1);
   std::vector<int> pending(nt);
   for (int x = 0; x < nt; ++x) pending[x] = x;
   int kk = std::max(1, std::min(kinit, SKEL));
+  std::vector<double> err;
+  std::vector<int> cnt;
   for (int attempt = 0;; ++attempt) {
     std::vector<BdlrTask> sub;
     for (int x : pending) sub.push_back(tasks[x]);
     const int ns = (int)sub.size();
-    HODLR_HIP(hipMemcpyAsync(d_tasks.p, sub.data(), ns * sizeof(BdlrTask), hipMemcpyHostToDevice, s));
+    HODLR_HIP(hipMemcpyAsync(sc.tasks.p, sub.data(), ns * sizeof(BdlrTask), hipMemcpyHostToDevice, s));
     {
       ProfScope prof("skel_topk", s);
-      k_skel_topk<<<ns, kBlock, 0, s>>>(d_score.as<float>(), d_tasks.as<BdlrTask>(), kk, SKEL, d_sel.as<int>(),
-                                        d_cnt.as<int>());
+      k_skel_topk<<<ns, kBlock, 0, s>>>(d_score.as<float>(), sc.tasks.as<BdlrTask>(), kk, SKEL, sc.sel.as<int>(),
+                                        sc.cnt.as<int>());
     }
     HODLR_HIP(hipGetLastError());
-    {
-      ProfScope prof("bdlr_lu", s);
-      HODLR_TRY((launch_bdlr_lu<T, SKEL>(K, ldk, d_tasks.as<BdlrTask>(), ns, d_sel.as<int>(), d_cnt.as<int>(),
-                                         (T)h->tol, rcap, d_piv.as<int>(), d_inv.as<T>(), h->d_rank.as<int>(),
-                                         d_rt.as<int>(), s)));
-    }
-    const int nch = (maxside + kBlock - 1) / kBlock;
-    {
-      ProfScope prof("bdlr_gather", s);
-      k_bdlr_gather<T, SKEL><<<dim3(ns, nch, 2), kBlock, 0, s>>>(K, ldk, d_tasks.as<BdlrTask>(), d_piv.as<int>(),
-                                                                d_rt.as<int>(), d_cg.as<T>(), Vcap, tr.n);
-      k_bdlr_factors<T><<<dim3(ns, (maxside + 63) / 64, (rcap + 63) / 64), kBlock, 0, s>>>(
-          d_tasks.as<BdlrTask>(), d_rt.as<int>(), d_cg.as<T>(), d_inv.as<T>(), Ucap, tr.n);
-    }
-    HODLR_HIP(hipGetLastError());
-    // the picks come back to draw the samples outside them
-    std::vector<int> cnt(2 * ns), sel(selo);
-    HODLR_HIP(hipMemcpyAsync(cnt.data(), d_cnt.p, 2 * ns * sizeof(int), hipMemcpyDeviceToHost, s));
-    HODLR_HIP(hipMemcpyAsync(sel.data(), d_sel.p, (size_t)selo * sizeof(int), hipMemcpyDeviceToHost, s));
-    HODLR_HIP(hipStreamSynchronize(s));
-    std::vector<int> smp((size_t)ns * 2 * kSkelSamples);
-    for (int x = 0; x < ns; ++x) {
-      const BdlrTask& tk = sub[x];
-      unsigned long long st = seed ^ (0xD1B54A32D192ED03ull * (unsigned long long)tk.node) ^
-                              (0x8CB92BA72F3D8DD7ull * (unsigned long long)(attempt + 1));
-      draw_samples(st, tk.m, sel.data() + tk.sel_off, cnt[2 * x], kSkelSamples, smp.data() + (size_t)x * 2 * kSkelSamples);
-      draw_samples(st, tk.nc, sel.data() + tk.sel_off + SKEL, cnt[2 * x + 1], kSkelSamples,
-                   smp.data() + (size_t)x * 2 * kSkelSamples + kSkelSamples);
-    }
-    HODLR_HIP(hipMemcpyAsync(d_samp.p, smp.data(), smp.size() * sizeof(int), hipMemcpyHostToDevice, s));
-    {
-      ProfScope prof("skel_check", s);
-      k_block_norm2<<<dim3(ns, kNormChunks), kBlock, 0, s>>>(K, ldk, d_tasks.as<BdlrTask>(), d_norm.as<double>());
-      k_skel_check<T><<<ns, kBlock, 0, s>>>(K, ldk, d_tasks.as<BdlrTask>(), d_rt.as<int>(), d_cnt.as<int>(),
-                                            d_norm.as<double>(), Ucap, Vcap, tr.n, d_samp.as<int>(), kSkelSamples,
-                                            d_err.as<double>());
-    }
-    HODLR_HIP(hipGetLastError());
-    std::vector<double> err(ns);
-    HODLR_HIP(hipMemcpyAsync(err.data(), d_err.p, ns * sizeof(double), hipMemcpyDeviceToHost, s));
-    HODLR_HIP(hipStreamSynchronize(s));
+    HODLR_TRY((skel_attempt<T, SKEL>(h, K, ldk, sub, maxside, selo, sc, Ucap, Vcap, seed, attempt, err, cnt, s)));
     std::vector<int> next;
     for (int x = 0; x < ns; ++x) {
       if (err[x] <= accept) h->skel_k[sub[x].node] = kk;
@@ -964,6 +993,69 @@ static int learned_t(hodlr_s* h, const double* K, int ldk, const int* rowptr, co
   }
   HODLR_HIP(hipStreamSynchronize(s));  // scratch goes back to the allocator cache
   return HODLR_OK;
+}
+
+// BDLR with the error monitor of Sec. 5.3: every block starts at the handle's
+// depth; a block whose sampled error is above accept takes one more distance
+// layer, up to max_depth (or until its picks stop growing).  A block that
+// never passes keeps its deepest skeleton.  h->skel_k receives the depth each
+// block ended at.
+template <typename T, int SKEL>
+static int adaptive_t(hodlr_s* h, const double* K, int ldk, const int* rowptr, const int* col, int max_depth,
+                      int max_skel, unsigned long long seed, double accept, T* Ucap, T* Vcap,
+                      const std::vector<int>& capoff, const std::vector<int>& cap, hipStream_t s) {
+  const Tree& tr = h->tree;
+  if (tr.n > 2 * kBdlrMaxSide) return fail(HODLR_EINVAL, "BDLR supports n <= 16384");
+  size_t invo = 0, cgo = 0;
+  const std::vector<BdlrTask> tasks = make_tasks<T>(tr, capoff, cap, SKEL, &invo, &cgo);
+  const int nt = (int)tasks.size(), selo = 2 * SKEL * nt;
+  int maxside = 0;
+  for (auto& tk : tasks) maxside = std::max(maxside, std::max(tk.m, tk.nc));
+  SkelScratch sc;
+  HODLR_TRY(sc.ensure(nt, selo, invo, cgo, sizeof(T)));
+  HODLR_HIP(hipMemsetAsync(h->d_rank.p, 0, tr.nnodes() * sizeof(int), s));
+  h->skel_k.assign(tr.nnodes(), -1);
+  const int ms = max_skel > 0 ? std::min(max_skel, SKEL) : SKEL;
+  std::vector<int> pending(nt), last(nt, -1);  // picks (rows + columns) of a block's previous attempt
+  for (int x = 0; x < nt; ++x) pending[x] = x;
+  std::vector<double> err;
+  std::vector<int> cnt;
+  for (int depth = h->depth, attempt = 0;; ++depth, ++attempt) {
+    std::vector<BdlrTask> sub;
+    for (int x : pending) sub.push_back(tasks[x]);
+    const int ns = (int)sub.size();
+    HODLR_HIP(hipMemcpyAsync(sc.tasks.p, sub.data(), ns * sizeof(BdlrTask), hipMemcpyHostToDevice, s));
+    {
+      ProfScope prof("bdlr_select", s);
+      k_bdlr_select<<<ns, kBlock, 0, s>>>(rowptr, col, sc.tasks.as<BdlrTask>(), depth, ms, SKEL, sc.sel.as<int>(),
+                                          sc.cnt.as<int>());
+    }
+    HODLR_HIP(hipGetLastError());
+    HODLR_TRY((skel_attempt<T, SKEL>(h, K, ldk, sub, maxside, selo, sc, Ucap, Vcap, seed, attempt, err, cnt, s)));
+    std::vector<int> next;
+    for (int x = 0; x < ns; ++x) {
+      const int b = pending[x], picks = cnt[2 * x] + cnt[2 * x + 1];
+      h->skel_k[sub[x].node] = depth;
+      // a block stops when it passes, or when one more layer added no pick
+      // (its picks are capped or cover both sides)
+      if (err[x] > accept && picks > last[b]) next.push_back(b);
+      last[b] = picks;
+    }
+    pending.swap(next);
+    if (pending.empty() || depth >= max_depth) break;
+  }
+  HODLR_HIP(hipStreamSynchronize(s));  // scratch goes back to the allocator cache
+  return HODLR_OK;
+}
+
+int launch_bdlr_adaptive(hodlr_s* h, const double* K, int ldk, const int* rowptr, const int* col, int max_depth,
+                         int max_skel, unsigned long long seed, double accept, void* Ucap, void* Vcap,
+                         const std::vector<int>& capoff, const std::vector<int>& cap, hipStream_t s) {
+  if (h->precision == 64)
+    return adaptive_t<double, kSkel64>(h, K, ldk, rowptr, col, max_depth, max_skel, seed, accept,
+                                       static_cast<double*>(Ucap), static_cast<double*>(Vcap), capoff, cap, s);
+  return adaptive_t<float, kSkel32>(h, K, ldk, rowptr, col, max_depth, max_skel, seed, accept,
+                                    static_cast<float*>(Ucap), static_cast<float*>(Vcap), capoff, cap, s);
 }
 
 int launch_learned(hodlr_s* h, const double* K, int ldk, const int* rowptr, const int* col, const float* xyz,

@@ -179,6 +179,12 @@ int launch_bdlr(hodlr_s* h, const double* K, int ldk, const int* rowptr, const i
                 int max_skel = 0, int* piv_export = nullptr);
 int skel_stride(int precision);
 
+// bdlr.hip: BDLR with the sampled error monitor of Sec. 5.3: blocks above
+// accept take one more distance layer, up to max_depth
+int launch_bdlr_adaptive(hodlr_s* h, const double* K, int ldk, const int* rowptr, const int* col, int max_depth,
+                         int max_skel, unsigned long long seed, double accept, void* Ucap, void* Vcap,
+                         const std::vector<int>& capoff, const std::vector<int>& cap, hipStream_t s);
+
 // bdlr.hip: learned proposals with sampled-error check and ACA fallback
 int launch_learned(hodlr_s* h, const double* K, int ldk, const int* rowptr, const int* col, const float* xyz,
                    const float* params, int kinit, unsigned long long seed, double accept, void* Ucap, void* Vcap,

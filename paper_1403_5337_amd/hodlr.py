@@ -32,7 +32,8 @@ class Opts(ctypes.Structure):
     _fields_ = [("leaf", ctypes.c_int), ("tol", ctypes.c_double), ("method", ctypes.c_int),
                 ("bdlr_depth", ctypes.c_int), ("max_rank", ctypes.c_int), ("precision", ctypes.c_int),
                 ("skel_k", ctypes.c_int), ("mlp_params", ctypes.c_void_p), ("seed", ctypes.c_ulonglong),
-                ("skel_tol", ctypes.c_double), ("bdlr_max_skel", ctypes.c_int), ("symmetric", ctypes.c_int)]
+                ("skel_tol", ctypes.c_double), ("bdlr_max_skel", ctypes.c_int), ("bdlr_max_depth", ctypes.c_int),
+                ("symmetric", ctypes.c_int)]
 
 
 _c_int_p = ctypes.POINTER(ctypes.c_int)
@@ -70,6 +71,10 @@ _SIGNATURES = {
                                            ctypes.POINTER(_vp), _c_int_p, ctypes.c_double, ctypes.c_int,
                                            ctypes.c_int, _c_int_p, _c_dbl_p, _vp]),
     "hodlr_order_rcb": (ctypes.c_int, [_vp, ctypes.c_int, ctypes.c_int, _vp, _vp]),
+    "hodlr_order_batched": (ctypes.c_int, [ctypes.c_int, ctypes.POINTER(_vp), _c_int_p, ctypes.c_int,
+                                           ctypes.POINTER(_vp), _c_int_p, ctypes.POINTER(_vp), ctypes.POINTER(_vp),
+                                           ctypes.POINTER(_vp), ctypes.POINTER(_vp), _c_int_p, ctypes.POINTER(_vp),
+                                           ctypes.POINTER(_vp), _vp]),
     "hodlr_permute": (ctypes.c_int, [_vp, ctypes.c_int, ctypes.c_int, _vp, _vp, ctypes.c_int, _vp]),
     "hodlr_permute_graph": (ctypes.c_int, [_vp, _vp, ctypes.c_int, _vp, _vp, _vp, _vp]),
     "hodlr_bdlr_select": (ctypes.c_int, [_vp, _vp, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int,
@@ -165,11 +170,12 @@ class Hodlr:
     @classmethod
     def build(cls, K: torch.Tensor, leaf=128, tol=1e-4, method="aca", depth=1, max_rank=0,
               precision=32, graph=None, coords=None, mlp_params=None, skel_k=32, seed=0, skel_tol=0.0,
-              max_skel=0, symmetric=False, stream=None) -> "Hodlr":
+              max_skel=0, symmetric=False, max_depth=0, stream=None) -> "Hodlr":
         """method: 'aca', 'bdlr' (needs graph = (rowptr, col) device tensors) or
         'learned' (graph, coords (n, 3) float32 and mlp_params (4801,) float32,
         all on the device).  symmetric: K is symmetric; only the left
-        children's blocks are compressed and mirrored."""
+        children's blocks are compressed and mirrored.  max_depth (BDLR):
+        blocks above the sampled error tolerance deepen up to it."""
         _need_gpu(K)
         Kc, ldk = colmajor(K, torch.float64)
         n = Kc.shape[0]
@@ -179,7 +185,7 @@ class Hodlr:
         _need_gpu(xyz, prm)
         o = Opts(leaf=leaf, tol=tol, method=mcode, bdlr_depth=depth, max_rank=max_rank, precision=precision,
                  skel_k=skel_k, mlp_params=None if prm is None else prm.data_ptr(), seed=seed, skel_tol=skel_tol,
-                 bdlr_max_skel=max_skel, symmetric=1 if symmetric else 0)
+                 bdlr_max_skel=max_skel, symmetric=1 if symmetric else 0, bdlr_max_depth=max_depth)
         rp, cp = (None, None) if graph is None else (_i32(graph[0]), _i32(graph[1]))
         _need_gpu(rp, cp)
         h = ctypes.c_void_p()
@@ -430,6 +436,41 @@ def hodlr_permute_graph(rowptr: torch.Tensor, col: torch.Tensor, perm: torch.Ten
     co = torch.empty_like(c32)
     _check(lib().hodlr_permute_graph(_ptr(r32), _ptr(c32), n, _ptr(p32), _ptr(ro), _ptr(co), _stream(stream)))
     return ro, co
+
+
+def hodlr_order_batched(coords, Ks, graphs=None, leaf=128, stream=None):
+    """hodlr_order_rcb, hodlr_permute and (with graphs) hodlr_permute_graph
+    for every front side by side (hodlr_order_batched).  Returns (perms,
+    permuted Ks, permuted graphs or None)."""
+    nf = len(Ks)
+    arr = lambda: (_vp * nf)()
+    cp, Kp, pp, Kop = arr(), arr(), arr(), arr()
+    ns, ldk, ldo = ((ctypes.c_int * nf)() for _ in range(3))
+    rpi = cpi = rpo = cpo = None
+    if graphs is not None:
+        rpi, cpi, rpo, cpo = arr(), arr(), arr(), arr()
+    keep, perms, Kouts, gouts = [], [], [], []
+    for f in range(nf):
+        c = coords[f].to(torch.float32).contiguous()
+        Kc, lk = colmajor(Ks[f], torch.float64)
+        _need_gpu(c, Kc)
+        n = Kc.shape[0]
+        perm = torch.empty(n, dtype=torch.int32, device=Kc.device)
+        Ko = torch.empty((n, n), dtype=torch.float64, device=Kc.device).t()
+        keep += [c, Kc]
+        perms.append(perm)
+        Kouts.append(Ko)
+        cp[f], Kp[f], pp[f], Kop[f] = c.data_ptr(), Kc.data_ptr(), perm.data_ptr(), Ko.data_ptr()
+        ns[f], ldk[f], ldo[f] = n, lk, n
+        if graphs is not None:
+            r32, c32 = _i32(graphs[f][0]), _i32(graphs[f][1])
+            _need_gpu(r32, c32)
+            ro, co = torch.empty_like(r32), torch.empty_like(c32)
+            keep += [r32, c32]
+            gouts.append((ro, co))
+            rpi[f], cpi[f], rpo[f], cpo[f] = r32.data_ptr(), c32.data_ptr(), ro.data_ptr(), co.data_ptr()
+    _check(lib().hodlr_order_batched(nf, cp, ns, leaf, Kp, ldk, rpi, cpi, pp, Kop, ldo, rpo, cpo, _stream(stream)))
+    return perms, Kouts, (gouts if graphs is not None else None)
 
 
 def hodlr_bdlr_select(rowptr: torch.Tensor, col: torch.Tensor, leaf: int, depth: int, max_skel: int,

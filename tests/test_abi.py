@@ -37,7 +37,7 @@ def test_default_opts(L):
     o = hodlr.default_opts()
     assert (o.leaf, o.tol, o.method, o.bdlr_depth, o.max_rank, o.precision) == (128, 1e-4, 0, 1, 0, 32)
     assert (o.skel_k, o.mlp_params, o.seed) == (32, None, 0)
-    assert (o.skel_tol, o.bdlr_max_skel, o.symmetric) == (0.0, 0, 0)
+    assert (o.skel_tol, o.bdlr_max_skel, o.bdlr_max_depth, o.symmetric) == (0.0, 0, 0, 0)
 
 
 def test_argument_validation(L):
@@ -81,6 +81,17 @@ def test_argument_validation(L):
     assert L.cg_solve(p, 10, 10, None, p, 65, 10, p, 10, 1e-12, 10, it, rr, None) == H.HODLR_EINVAL
     assert L.cg_solve(p, 10, 10, None, p, 1, 10, p, 10, 1e-12, 0, it, rr, None) == H.HODLR_EINVAL
     assert L.cg_solve(p, 10, 10, None, p, 1, 10, p, 9, 1e-12, 10, it, rr, None) == H.HODLR_EINVAL
+    arr = (ctypes.c_void_p * 1)(16)
+    ni = (ctypes.c_int * 1)(10)
+    assert L.hodlr_order_batched(0, arr, ni, 4, arr, ni, None, None, arr, arr, ni, None, None, None) == H.HODLR_EINVAL
+    assert L.hodlr_order_batched(1, None, ni, 4, arr, ni, None, None, arr, arr, ni, None, None, None) == H.HODLR_EINVAL
+    assert L.hodlr_order_batched(1, arr, ni, 4, arr, ni, arr, None, arr, arr, ni, None, None, None) == H.HODLR_EINVAL
+    assert b"graph" in L.hodlr_last_error()
+    o = H.default_opts()
+    o.method, o.bdlr_depth, o.bdlr_max_depth = H.HODLR_BDLR, 3, 2
+    st = L.hodlr_build(ctypes.c_void_p(16), 10, 10, ctypes.c_void_p(16), ctypes.c_void_p(16), None,
+                       ctypes.byref(o), None, ctypes.byref(out))
+    assert st == H.HODLR_EINVAL and b"bdlr_max_depth" in L.hodlr_last_error()
     o = H.default_opts()
     st = L.hodlr_build(ctypes.c_void_p(16), 16385, 16385, None, None, None, ctypes.byref(o), None, ctypes.byref(out))
     assert st == H.HODLR_EINVAL and b"16384" in L.hodlr_last_error()

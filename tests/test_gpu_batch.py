@@ -99,6 +99,26 @@ def test_nested_dissection_batch_end_to_end():
         h.close()
 
 
+def test_batched_ordering_matches_single_calls_bitwise():
+    """hodlr_order_batched gives, front by front, exactly what the three
+    single calls give (the same kernels on the same inputs)."""
+    fr = fronts.nd_fronts(24, levels=4, sigma=1.0, seed=0, device="cuda")
+    say("batched ordering of", len(fr), "fronts")
+    xyz = [torch.from_numpy(f.coords).cuda() for f in fr]
+    Ks = [f.K.t().contiguous().t() for f in fr]
+    gs = [(torch.from_numpy(f.indptr).cuda(), torch.from_numpy(f.indices).cuda()) for f in fr]
+    perms, Kps, gps = H.hodlr_order_batched(xyz, Ks, graphs=gs, leaf=128)
+    torch.cuda.synchronize()
+    for f, c, K, g, p, Kp, gp in zip(fr, xyz, Ks, gs, perms, Kps, gps):
+        p1 = H.hodlr_order_rcb(c, 128)
+        K1 = H.hodlr_permute(K, p1)
+        r1, c1 = H.hodlr_permute_graph(g[0], g[1], p1)
+        assert torch.equal(p, p1) and torch.equal(Kp, K1)
+        assert torch.equal(gp[0], r1) and torch.equal(gp[1], c1)
+    _, Kq, gq = H.hodlr_order_batched(xyz[:2], Ks[:2], leaf=128)  # without graphs
+    assert gq is None and torch.equal(Kq[1], Kps[1])
+
+
 def _small_fronts():
     out = []
     for shape, seed, leaf in (((24, 20, 3), 11, 40), ((32, 16, 5), 12, 48), ((20, 20, 3), 13, 40),

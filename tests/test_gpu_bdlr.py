@@ -240,3 +240,77 @@ def test_end_to_end_elastic4800(method):
     h.close()
     assert st == H.HODLR_OK
     assert np.all(dense.relres(Kp.cpu().numpy(), X.cpu().numpy(), B.cpu().numpy()) <= 1e-12)
+
+
+# ---------------------------------------------------------------------------
+# the error monitor of Sec. 5.3: adaptive depth (opts.bdlr_max_depth)
+# ---------------------------------------------------------------------------
+def _ordered(name):
+    f = fronts.make_workload(name, device="cuda")
+    perm = H.hodlr_order_rcb(torch.from_numpy(f.coords).cuda(), 128)
+    Kp = H.hodlr_permute(f.K.cuda(), perm)
+    rp, ci = H.hodlr_permute_graph(torch.from_numpy(f.indptr).cuda(), torch.from_numpy(f.indices).cuda(), perm)
+    return Kp, (rp, ci)
+
+
+def _exact_block_errors(h, K, n, leaf):
+    st = h.stats()
+    U, V = (a.cpu().numpy() for a in h.factors())
+    offs = np.cumsum([0] + st["rcols"])
+    levs = tree.levels(n, leaf)
+    out = []
+    for p in range(1, len(levs)):
+        for i, (lo, hi) in enumerate(levs[p]):
+            slo, shi = levs[p][i ^ 1]
+            r = st["ranks"][p - 1][i]
+            B = K[lo:hi, slo:shi]
+            A = U[lo:hi, offs[p - 1]:offs[p - 1] + r] @ V[slo:shi, offs[p - 1]:offs[p - 1] + r].T
+            out.append(np.linalg.norm(B - A) / np.linalg.norm(B))
+    return np.array(out)
+
+
+def test_adaptive_depth_at_its_start_is_the_fixed_depth():
+    """With bdlr_max_depth = bdlr_depth the monitor takes one attempt: the
+    factors are bit for bit those of the fixed-depth build."""
+    Kp, g = _ordered("tpfa4096")
+    a = H.Hodlr.build(Kp, leaf=128, tol=1e-4, method="bdlr", depth=2, graph=g)
+    b = H.Hodlr.build(Kp, leaf=128, tol=1e-4, method="bdlr", depth=2, graph=g, max_depth=2)
+    assert a.stats() == b.stats()
+    assert all(k == 2 for k in b.skel_info() for k in k) and all(k == -1 for k in a.skel_info() for k in k)
+    for x, y in zip(a.factors(), b.factors()):
+        assert torch.equal(x, y)
+    a.close()
+    b.close()
+
+
+@pytest.mark.parametrize("name", ["tpfa4096", "elastic4800"])
+def test_adaptive_depth_meets_the_monitor(name):
+    """From depth 1 up to 6 at tol 1e-4 (accept 3e-3): the blocks that
+    stopped early passed the monitor or ran out of picks (the 192-pick cap),
+    so nearly all of them have a whole-block error within a factor 3 of
+    accept (the monitor sees 16 rows and 16 columns); the depths are in
+    range, and the preconditioner takes no more GMRES steps than depth 1."""
+    Kp, g = _ordered(name)
+    n = Kp.shape[0]
+    K = Kp.cpu().numpy()
+    h1 = H.Hodlr.build(Kp, leaf=128, tol=1e-4, method="bdlr", depth=1, graph=g)
+    ha = H.Hodlr.build(Kp, leaf=128, tol=1e-4, method="bdlr", depth=1, graph=g, max_depth=6, seed=3)
+    depths = np.array([k for lv in ha.skel_info() for k in lv])
+    errs = _exact_block_errors(ha, K, n, 128)
+    errs1 = _exact_block_errors(h1, K, n, 128)
+    say(" ", name, "depths", np.bincount(depths).tolist(), "max err", errs.max(), "depth-1 max err", errs1.max())
+    assert depths.min() >= 1 and depths.max() <= 6 and depths.max() > 1
+    early = depths < 6
+    assert np.mean(errs[early] <= 3 * 30 * 1e-4) >= 0.9
+    assert errs.max() <= errs1.max()
+    B = fronts.rhs(n, 1, seed=0).cuda()
+    its = []
+    for h in (h1, ha):
+        h.factor()
+        X, it, rr, st = H.gmres_solve(Kp, B, h, tol=1e-12)
+        assert st == H.HODLR_OK
+        assert np.all(dense.relres(K, X.cpu().numpy(), B.cpu().numpy()) <= 1e-12)
+        its.append(it[0])
+        h.close()
+    say("  iterations depth 1:", its[0], "adaptive:", its[1])
+    assert its[1] <= its[0]
