@@ -103,7 +103,7 @@ TRAFFIC = {
     "apply_level": {"source": "paper_1403_5337_amd/csrc/solve.hip",
                     "sha256": "792a556e9f24caac7c69b9f5dd5185421785192b1fc8398ea7f456996596c677",
                     "workload": "tpfa4096", "fetch_kib": 1598.0, "write_kib": 236.0,
-                    "fetch_factor": 2.0, "write_factor": 1.0, "rocprof_avg_us": 7.91},
+                    "fetch_factor": 2.0, "write_factor": 1.0, "rocprof_avg_us": 7.94},
 }
 
 
