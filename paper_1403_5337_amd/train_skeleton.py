@@ -1,6 +1,6 @@
 """Train the learned skeleton proposer on generated fronts and evaluate it.
 
-    python -m paper_1403_5337_amd.train_skeleton [--fronts 64] [--steps 3000]
+    python -m paper_1403_5337_amd.train_skeleton [--fronts 2000] [--steps 12000]
 
 Training fronts: Schur complements of lognormal(0, 1) TPFA diffusion onto the
 middle plane of nx x ny x 17 cell grids (8 planes on each side of the
@@ -88,8 +88,8 @@ def evaluate(params, fr, leaf=128, tol=1e-4, skel_k=32, seed=0):
 
 def main(argv=None):
     ap = argparse.ArgumentParser()
-    ap.add_argument("--fronts", type=int, default=64)
-    ap.add_argument("--steps", type=int, default=3000)
+    ap.add_argument("--fronts", type=int, default=2000)
+    ap.add_argument("--steps", type=int, default=12000)
     ap.add_argument("--batch", type=int, default=8192)
     ap.add_argument("--lr", type=float, default=3e-3)
     ap.add_argument("--eval", type=int, default=3)
