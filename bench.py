@@ -44,6 +44,8 @@ def parse():
     ap.add_argument("--study", choices=["sweep"], default=None,
                     help="sweep: the tolerance table (ACA and BDLR at 1e-1, 1e-3, 1e-5, plus a float64 "
                          "high-accuracy HODLR used alone) on the TPFA and elasticity fronts")
+    ap.add_argument("--fronts", default="laplace1024,tpfa4096,elastic4800,tet64k",
+                    help="workloads of the sweep, comma separated")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain 256 MiB device copy 3 times (reference for HBM counters)")
     return ap.parse_args()
@@ -270,10 +272,11 @@ def main_sweep(args):
     (BDLR depth 1, 3, 5 with them), the end-to-end time T (ordering,
     permutation, compression, factorization and GMRES to 1e-12; median of
     `--steps` runs after a warm-up) and the GMRES steps I, against the
-    GPU dense FP64 LU (factor + solve).  One more row per front: a float64
-    HODLR at eps = 1e-8 used as a direct solver (one solve, no GMRES) with
-    its relative residual, the high-accuracy mode the paper compares
-    against.  The float32 factorization is used for eps >= 1e-5."""
+    GPU dense FP64 LU (factor + solve).  Three more rows per front: a
+    float64 HODLR at eps = 1e-8 with GMRES, and float64 HODLRs at 1e-8 and
+    1e-10 used as direct solvers (one solve, no GMRES) with their relative
+    residuals, the high-accuracy mode the paper compares against.  The
+    float32 factorization is used for eps >= 1e-5."""
     import numpy as np
     import torch
 
@@ -283,7 +286,7 @@ def main_sweep(args):
     dev = torch.device("cuda:0")
     H.lib()
     out = []
-    for wname in ("tpfa4096", "elastic4800", "tet64k"):
+    for wname in args.fronts.split(","):
         w = fronts.WORKLOADS[wname]
         front = fronts.make_workload(wname, device=dev)
         n, leaf = front.n, w["leaf"]
@@ -329,10 +332,16 @@ def main_sweep(args):
                                  converged=st == H.HODLR_OK, ranks_max=ranks))
                 print(f"# {wname} {method} {eps:g}: T {ms:.2f} ms, I {max(it)}, relres {max(rr):.2e}",
                       file=sys.stderr, flush=True)
-        ms, it, rr, st, ranks = timed("aca", 1e-8, 1, 64, direct=True)
-        rows.append(dict(method="aca", eps=1e-8, depth=None, precision=64, direct=True, T_ms=round(ms, 3),
-                         I=0, relres=max(rr), converged=max(rr) <= 1e-12, ranks_max=ranks))
-        print(f"# {wname} direct f64 1e-8: T {ms:.2f} ms, relres {max(rr):.2e}", file=sys.stderr, flush=True)
+        # the high-accuracy float64 HODLR: with GMRES, and alone as a direct solver
+        ms, it, rr, st, ranks = timed("aca", 1e-8, 1, 64)
+        rows.append(dict(method="aca", eps=1e-8, depth=None, precision=64, T_ms=round(ms, 3), I=max(it),
+                         relres=max(rr), converged=st == H.HODLR_OK, ranks_max=ranks))
+        for eps in (1e-8, 1e-10):
+            ms, it, rr, st, ranks = timed("aca", eps, 1, 64, direct=True)
+            rows.append(dict(method="aca", eps=eps, depth=None, precision=64, direct=True, T_ms=round(ms, 3),
+                             I=0, relres=max(rr), converged=max(rr) <= 1e-12, ranks_max=ranks))
+            print(f"# {wname} direct f64 {eps:g}: T {ms:.2f} ms, relres {max(rr):.2e}, ranks {ranks}",
+                  file=sys.stderr, flush=True)
         LU, piv = torch.linalg.lu_factor(K)
         torch.linalg.lu_solve(LU, piv, B)
         torch.cuda.synchronize()
