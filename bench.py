@@ -26,7 +26,8 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
 KERNELS = ["aca", "bdlr_select", "bdlr_lu", "bdlr_gather", "bdlr_factors", "leaf_inverse", "leaf_apply", "panel_tn", "schur_form", "cap_inverse", "form_E", "schur_apply", "correct", "apply_leaf", "apply_level", "apply_sum",
-           "matvec", "orth", "cg_vec"]
+           "matvec", "orth", "cg_vec",
+           "skel_features", "skel_score", "skel_topk", "skel_check"]
 
 
 def parse():
@@ -37,7 +38,8 @@ def parse():
     ap.add_argument("--workload", default="tpfa4096")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-lu", action="store_true")
-    ap.add_argument("--method", choices=["aca", "bdlr"], default="bdlr")
+    ap.add_argument("--method", choices=["aca", "bdlr", "learned"], default="bdlr",
+                    help="learned: scorer-proposed skeletons (committed parameters) with ACA fallback")
     ap.add_argument("--depth", type=int, default=2, help="BDLR boundary distance")
     ap.add_argument("--solver", choices=["gmres", "cg"], default="gmres",
                     help="cg: symmetric HODLR build and preconditioned CG instead of GMRES")
@@ -400,6 +402,10 @@ def main():
     g_ci = torch.from_numpy(front.indices).to(dev)
     B = fronts.rhs(n, s, seed=0, device=dev).t().contiguous().t()
     stream = torch.cuda.current_stream()
+    params = None
+    if args.method == "learned":
+        from paper_1403_5337_amd import skeleton as S
+        params = S.load(device=dev)
 
     def step(stage_events=None):
         ev = stage_events
@@ -407,11 +413,12 @@ def main():
             ev[0].record(stream)
         perm = H.hodlr_order_rcb(coords, leaf)
         Kp = H.hodlr_permute(K, perm)
-        graph = H.hodlr_permute_graph(g_rp, g_ci, perm) if args.method == "bdlr" else None
+        graph = H.hodlr_permute_graph(g_rp, g_ci, perm) if args.method != "aca" else None
+        xyz = H.hodlr_permute_rows(coords, perm) if args.method == "learned" else None
         if ev is not None:
             ev[1].record(stream)
         h = H.Hodlr.build(Kp, leaf=leaf, tol=tol, precision=prec, method=args.method, depth=args.depth,
-                          graph=graph, symmetric=args.solver == "cg")
+                          graph=graph, coords=xyz, mlp_params=params, symmetric=args.solver == "cg")
         if ev is not None:
             ev[2].record(stream)
         h.factor()
@@ -483,7 +490,10 @@ def main():
 
     cpu = None
     if not args.no_cpu_baseline:
-        cpu = cpu_baseline(front, w, s, args.method, args.depth, args.solver)
+        # the oracle has no learned build: a learned run is set beside the
+        # oracle's BDLR pipeline, and the sample says so
+        cpu = cpu_baseline(front, w, s, "bdlr" if args.method == "learned" else args.method, args.depth,
+                           args.solver)
 
     out = {
         "metric": ("GMRES-to-1e-12 solves/sec (HODLR-preconditioned, end to end incl. compression and factorization)"

@@ -262,6 +262,12 @@ int hodlr_order_rcb(const float* coords, int n, int leaf, int* perm, hipStream_t
 int hodlr_permute(const double* Kin, int n, int ldi, const int* perm, double* Kout, int ldo,
                   hipStream_t stream);
 
+/* out(i, :) = in(perm[i], :): device float32 row-major n x width arrays
+ * (width 1..16), e.g. the dof coordinates a learned build takes in K's
+ * permuted numbering; in and out must not overlap; perm device int32[n].
+ * Asynchronous.  Errors: EINVAL. */
+int hodlr_permute_rows(const float* in, int n, int width, const int* perm, float* out, hipStream_t stream);
+
 /* Relabel a CSR graph: new vertex i = old vertex perm[i].  All device int32:
  * rowptr[n+1], col[nnz] in; rowptr_out[n+1], col_out[nnz] out (neighbours
  * sorted).  Asynchronous. */

@@ -954,6 +954,13 @@ int hodlr_permute(const double* Kin, int n, int ldi, const int* perm, double* Ko
   return launch_permute(Kin, n, ldi, perm, Kout, ldo, stream);
 }
 
+int hodlr_permute_rows(const float* in, int n, int width, const int* perm, float* out, hipStream_t stream) {
+  if (!in || !perm || !out) return fail(HODLR_EINVAL, "NULL pointer");
+  if (n < 1 || width < 1 || width > 16) return fail(HODLR_EINVAL, "n < 1 or width not in [1, 16]");
+  if (in == out) return fail(HODLR_EINVAL, "in and out must not overlap");
+  return launch_permute_rows(in, n, width, perm, out, stream);
+}
+
 int hodlr_permute_graph(const int* rowptr, const int* col, int n, const int* perm,
                         int* rowptr_out, int* col_out, hipStream_t stream) {
   if (!rowptr || !col || !perm || !rowptr_out || !col_out) return fail(HODLR_EINVAL, "NULL pointer");

@@ -159,6 +159,7 @@ namespace hodlr {
 int launch_rcb(const float* coords, int n, const Tree& t, int* perm, hipStream_t s);
 int launch_permute(const double* Kin, int n, int ldi, const int* perm, double* Kout, int ldo,
                    hipStream_t s);
+int launch_permute_rows(const float* in, int n, int width, const int* perm, float* out, hipStream_t s);
 int launch_permute_graph(const int* rowptr, const int* col, int n, const int* perm,
                          int* rowptr_out, int* col_out, hipStream_t s);
 

@@ -358,4 +358,22 @@ int launch_permute_graph(const int* rowptr, const int* col, int n, const int* pe
   return HODLR_OK;
 }
 
+// ---------------------------------------------------------------------------
+// out(i, :) = in(perm[i], :) for row-major n x width float arrays (dof
+// coordinates follow the dofs into the new order).
+__global__ void k_permute_rows(const float* __restrict__ in, int n, int width, const int* __restrict__ perm,
+                               float* __restrict__ out) {
+  const long e = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= (long)n * width) return;
+  const int i = (int)(e / width), c = (int)(e % width);
+  out[e] = in[(size_t)perm[i] * width + c];
+}
+
+int launch_permute_rows(const float* in, int n, int width, const int* perm, float* out, hipStream_t s) {
+  const long total = (long)n * width;
+  k_permute_rows<<<(int)((total + kBlock - 1) / kBlock), kBlock, 0, s>>>(in, n, width, perm, out);
+  HODLR_HIP(hipGetLastError());
+  return HODLR_OK;
+}
+
 }  // namespace hodlr

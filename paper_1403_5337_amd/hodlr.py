@@ -77,6 +77,7 @@ _SIGNATURES = {
                                            ctypes.POINTER(_vp), _vp]),
     "hodlr_permute": (ctypes.c_int, [_vp, ctypes.c_int, ctypes.c_int, _vp, _vp, ctypes.c_int, _vp]),
     "hodlr_permute_graph": (ctypes.c_int, [_vp, _vp, ctypes.c_int, _vp, _vp, _vp, _vp]),
+    "hodlr_permute_rows": (ctypes.c_int, [_vp, ctypes.c_int, ctypes.c_int, _vp, _vp, _vp]),
     "hodlr_bdlr_select": (ctypes.c_int, [_vp, _vp, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int,
                                          _vp, _vp, _vp]),
     "hodlr_stats": (ctypes.c_int, [_vp, _c_int_p, _c_int_p, _c_int_p]),
@@ -425,6 +426,17 @@ def hodlr_permute(K: torch.Tensor, perm: torch.Tensor, stream=None) -> torch.Ten
     p32 = _i32(perm)
     out = torch.empty((n, n), dtype=torch.float64, device=K.device).t()
     _check(lib().hodlr_permute(_ptr(Kc), n, ldk, _ptr(p32), _ptr(out), n, _stream(stream)))
+    return out
+
+
+def hodlr_permute_rows(x: torch.Tensor, perm: torch.Tensor, stream=None) -> torch.Tensor:
+    """out[i] = x[perm[i]] for an (n, width) float32 array (hodlr_permute_rows)."""
+    _need_gpu(x, perm)
+    xc = x.to(torch.float32).contiguous()
+    n, w = xc.shape
+    p32 = _i32(perm)
+    out = torch.empty_like(xc)
+    _check(lib().hodlr_permute_rows(_ptr(xc), n, w, _ptr(p32), _ptr(out), _stream(stream)))
     return out
 
 

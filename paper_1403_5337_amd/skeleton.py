@@ -33,7 +33,7 @@ def order_front(front, leaf: int, device="cuda"):
     K = H.hodlr_permute(front.K.to(dev), perm)
     rp, ci = H.hodlr_permute_graph(torch.from_numpy(front.indptr).to(dev), torch.from_numpy(front.indices).to(dev),
                                    perm)
-    coords = xyz.index_select(0, perm.long())
+    coords = H.hodlr_permute_rows(xyz, perm)
     return K, rp, ci, coords
 
 

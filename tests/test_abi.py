@@ -81,6 +81,9 @@ def test_argument_validation(L):
     assert L.cg_solve(p, 10, 10, None, p, 65, 10, p, 10, 1e-12, 10, it, rr, None) == H.HODLR_EINVAL
     assert L.cg_solve(p, 10, 10, None, p, 1, 10, p, 10, 1e-12, 0, it, rr, None) == H.HODLR_EINVAL
     assert L.cg_solve(p, 10, 10, None, p, 1, 10, p, 9, 1e-12, 10, it, rr, None) == H.HODLR_EINVAL
+    assert L.hodlr_permute_rows(p, 10, 17, p, ctypes.c_void_p(32), None) == H.HODLR_EINVAL
+    assert L.hodlr_permute_rows(p, 10, 3, p, p, None) == H.HODLR_EINVAL  # in place
+    assert L.hodlr_permute_rows(None, 10, 3, p, p, None) == H.HODLR_EINVAL
     arr = (ctypes.c_void_p * 1)(16)
     ni = (ctypes.c_int * 1)(10)
     assert L.hodlr_order_batched(0, arr, ni, 4, arr, ni, None, None, arr, arr, ni, None, None, None) == H.HODLR_EINVAL

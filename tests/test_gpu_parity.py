@@ -62,6 +62,15 @@ def test_rcb_bit_exact(case):
     assert np.array_equal(got, want)
 
 
+def test_permute_rows_bit_exact():
+    rng = np.random.default_rng(3)
+    for n, w in ((1, 3), (1000, 3), (517, 8), (64, 16)):
+        x = torch.from_numpy(rng.standard_normal((n, w)).astype(np.float32)).cuda()
+        perm = torch.from_numpy(rng.permutation(n).astype(np.int32)).cuda()
+        got = H.hodlr_permute_rows(x, perm)
+        assert torch.equal(got, x[perm.long()])
+
+
 def test_permute_front_and_graph():
     f = fronts.elasticity_front((5, 4, 3), zs=1)
     perm = np.random.default_rng(3).permutation(f.n)
