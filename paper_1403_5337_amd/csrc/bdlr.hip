@@ -38,6 +38,7 @@ struct BdlrTask {
   int sel_off;   // ints: rows at sel_off, columns at sel_off + max_skel
   size_t inv_off;  // elements: U11^-1 then L11^-T, max_skel^2 each
   size_t cg_off;   // elements: C panel (m x kmax) then R^T panel (nc x kmax)
+  int task;        // position in the build's whole task list (attempt loops)
 };
 
 // exclusive prefix over the 256 per-thread values v; returns this thread's
@@ -735,18 +736,27 @@ __global__ void __launch_bounds__(kBlock)
   }
 }
 
-// |K(I, J)|_F^2 of every block, in kNormChunks column chunks per block.
-constexpr int kNormChunks = 16;
+// |K(I, J)|_F^2 of every block, in kNormChunks column chunks per block; a
+// thread keeps four loads in flight (a chunk is read as one flat range of
+// column-major entries).
+constexpr int kNormChunks = 64;
 __global__ void __launch_bounds__(kBlock)
     k_block_norm2(const double* __restrict__ K, int ldk, const BdlrTask* __restrict__ tasks,
                   double* __restrict__ part) {
   __shared__ double red[kBlock / 64];
   const BdlrTask tk = tasks[blockIdx.x];
   const int per = (tk.nc + kNormChunks - 1) / kNormChunks, j0 = blockIdx.y * per, j1 = min(tk.nc, j0 + per);
+  const long tot = j1 > j0 ? (long)tk.m * (j1 - j0) : 0;
   double acc = 0.0;
-  for (int j = j0; j < j1; ++j) {
-    const double* col = K + (size_t)(tk.col0 + j) * ldk + tk.row0;
-    for (int i = threadIdx.x; i < tk.m; i += kBlock) acc += col[i] * col[i];
+  for (long e0 = threadIdx.x; e0 < tot; e0 += 4 * kBlock) {
+    double v[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const long e = e0 + (long)u * kBlock;
+      v[u] = e < tot ? K[(size_t)(tk.col0 + j0 + e / tk.m) * ldk + tk.row0 + e % tk.m] : 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) acc += v[u] * v[u];
   }
   acc = block_sum(acc, red);
   if (threadIdx.x == 0) part[(size_t)blockIdx.x * kNormChunks + blockIdx.y] = acc;
@@ -757,14 +767,22 @@ __global__ void __launch_bounds__(kBlock)
 // (rows sampled), over |K(I, J)|_F^2; the same over columns; the larger of
 // the two (float64).  samp: per task 2 * ns entries (rows, then columns; -1 =
 // unused), ns <= 16; counts: rows and columns picked per task; norm2: per
-// task, kNormChunks partial sums of |K(I, J)|_F^2.
+// task of the whole list (BdlrTask::task), kNormChunks partial sums of
+// |K(I, J)|_F^2.
+//
+// k_skel_check: workgroup (task, chunk) sums the squared residual of the
+// sampled rows over its chunk of the columns (and of the sampled columns
+// over its chunk of the rows) into part; the other factor's entries are
+// loaded 8 at a time.  k_skel_err then adds a task's chunks in order and
+// forms the estimate, so the result does not depend on timing.
+constexpr int kCheckChunks = 16;
+
 template <typename T>
 __global__ void __launch_bounds__(kBlock)
     k_skel_check(const double* __restrict__ K, int ldk, const BdlrTask* __restrict__ tasks,
-                 const int* __restrict__ rank_task, const int* __restrict__ counts, const double* __restrict__ norm2,
-                 const T* __restrict__ Ucap, const T* __restrict__ Vcap, int ldu, const int* __restrict__ samp,
-                 int ns, double* __restrict__ err) {
-  constexpr int RC = sizeof(T) == 8 ? kRankCap64 : kRankCap32, NS = 16;
+                 const int* __restrict__ rank_task, const T* __restrict__ Ucap, const T* __restrict__ Vcap,
+                 int ldu, const int* __restrict__ samp, int ns, double* __restrict__ part) {
+  constexpr int RC = sizeof(T) == 8 ? kRankCap64 : kRankCap32, NS = 16, kL = 8;
   __shared__ T uv[NS][RC];
   __shared__ int sp[2 * NS];
   __shared__ double red[kBlock / 64];
@@ -774,7 +792,6 @@ __global__ void __launch_bounds__(kBlock)
   __syncthreads();
   const T* U = Ucap + (size_t)tk.capcol * ldu;
   const T* V = Vcap + (size_t)tk.capcol * ldu;
-  double est = 0.0;
   for (int side = 0; side < 2; ++side) {
     // the fixed factor's sampled rows: U(row0 + p, :) (side 0) or V(col0 + p, :)
     const T* F = side == 0 ? U + tk.row0 : V + tk.col0;
@@ -785,37 +802,64 @@ __global__ void __launch_bounds__(kBlock)
     }
     __syncthreads();
     const int len = side == 0 ? tk.nc : tk.m;
+    const int per = (len + kCheckChunks - 1) / kCheckChunks;
+    const int x0 = blockIdx.y * per, x1 = min(len, x0 + per);
     double num = 0.0;
-    for (int x = t; x < len; x += kBlock) {
+    for (int x = x0 + t; x < x1; x += kBlock) {
       double a[NS];
 #pragma unroll
       for (int q = 0; q < NS; ++q) a[q] = 0.0;
-      for (int l = 0; l < r; ++l) {
+      int l = 0;
+      for (; l + kL <= r; l += kL) {
+        double o[kL];
+#pragma unroll
+        for (int u = 0; u < kL; ++u) o[u] = (double)O[(size_t)(l + u) * ldu + x];
+#pragma unroll
+        for (int u = 0; u < kL; ++u)
+#pragma unroll
+          for (int q = 0; q < NS; ++q) a[q] += (double)uv[q][l + u] * o[u];
+      }
+      for (; l < r; ++l) {
         const double o = (double)O[(size_t)l * ldu + x];
 #pragma unroll
         for (int q = 0; q < NS; ++q) a[q] += (double)uv[q][l] * o;
       }
+      double b[NS];
 #pragma unroll
       for (int q = 0; q < NS; ++q) {
         const int p = sp[side * NS + q];
-        if (p < 0) continue;
-        const double b = side == 0 ? K[(size_t)(tk.col0 + x) * ldk + tk.row0 + p]
-                                   : K[(size_t)(tk.col0 + p) * ldk + tk.row0 + x];
-        num += (b - a[q]) * (b - a[q]);
+        b[q] = p < 0 ? 0.0
+                     : side == 0 ? K[(size_t)(tk.col0 + x) * ldk + tk.row0 + p]
+                                 : K[(size_t)(tk.col0 + p) * ldk + tk.row0 + x];
       }
+#pragma unroll
+      for (int q = 0; q < NS; ++q)
+        if (sp[side * NS + q] >= 0) num += (b[q] - a[q]) * (b[q] - a[q]);
     }
     num = block_sum(num, red);
-    int used = 0;
-    for (int q = 0; q < NS; ++q) used += sp[side * NS + q] >= 0;
-    const int outside = (side == 0 ? tk.m : tk.nc) - counts[2 * blockIdx.x + side];
-    if (used > 0) est = fmax(est, num * (double)outside / (double)used);
+    if (t == 0) part[((size_t)blockIdx.x * kCheckChunks + blockIdx.y) * 2 + side] = num;
     __syncthreads();
   }
-  if (t == 0) {
-    double nb = 0.0;
-    for (int c = 0; c < kNormChunks; ++c) nb += norm2[(size_t)blockIdx.x * kNormChunks + c];
-    err[blockIdx.x] = nb > 0.0 ? sqrt(est / nb) : sqrt(est);
+}
+
+__global__ void k_skel_err(const BdlrTask* __restrict__ tasks, int ntask, const int* __restrict__ counts,
+                           const double* __restrict__ norm2, const int* __restrict__ samp, int ns,
+                           const double* __restrict__ part, double* __restrict__ err) {
+  const int x = blockIdx.x * blockDim.x + threadIdx.x;
+  if (x >= ntask) return;
+  const BdlrTask tk = tasks[x];
+  double est = 0.0;
+  for (int side = 0; side < 2; ++side) {
+    double num = 0.0;
+    for (int c = 0; c < kCheckChunks; ++c) num += part[((size_t)x * kCheckChunks + c) * 2 + side];
+    int used = 0;
+    for (int q = 0; q < ns; ++q) used += samp[(size_t)x * 2 * ns + side * ns + q] >= 0;
+    const int outside = (side == 0 ? tk.m : tk.nc) - counts[2 * x + side];
+    if (used > 0) est = fmax(est, num * (double)outside / (double)used);
   }
+  double nb = 0.0;
+  for (int c = 0; c < kNormChunks; ++c) nb += norm2[(size_t)tk.task * kNormChunks + c];
+  err[x] = nb > 0.0 ? sqrt(est / nb) : sqrt(est);
 }
 
 // splitmix64 (Steele, Lea & Flood 2014): the sample stream of a block
@@ -854,7 +898,7 @@ constexpr int kSkelSamples = 16;
 
 // Scratch of the attempt loops (learned proposals, adaptive BDLR depth).
 struct SkelScratch {
-  DevBuf tasks, sel, piv, cnt, rt, inv, cg, samp, err, norm;
+  DevBuf tasks, sel, piv, cnt, rt, inv, cg, samp, err, norm, part;
   int ensure(int nt, int selo, size_t invo, size_t cgo, size_t esize) {
     HODLR_TRY(tasks.ensure(nt * sizeof(BdlrTask)));
     HODLR_TRY(sel.ensure((size_t)selo * sizeof(int)));
@@ -865,9 +909,22 @@ struct SkelScratch {
     HODLR_TRY(cg.ensure(std::max<size_t>(cgo, 1) * esize));
     HODLR_TRY(samp.ensure((size_t)nt * 2 * kSkelSamples * sizeof(int)));
     HODLR_TRY(err.ensure((size_t)nt * sizeof(double)));
+    HODLR_TRY(part.ensure((size_t)nt * kCheckChunks * 2 * sizeof(double)));
     return norm.ensure((size_t)nt * kNormChunks * sizeof(double));
   }
 };
+
+// |K(I, J)|_F^2 of every block of the build, once (the attempts read them by
+// BdlrTask::task); the task list goes through sc.tasks, which each attempt
+// then overwrites with its own.
+static int block_norms(const double* K, int ldk, const std::vector<BdlrTask>& tasks, SkelScratch& sc, hipStream_t s) {
+  const int nt = (int)tasks.size();
+  HODLR_HIP(hipMemcpyAsync(sc.tasks.p, tasks.data(), nt * sizeof(BdlrTask), hipMemcpyHostToDevice, s));
+  ProfScope prof("skel_check", s);
+  k_block_norm2<<<dim3(nt, kNormChunks), kBlock, 0, s>>>(K, ldk, sc.tasks.as<BdlrTask>(), sc.norm.as<double>());
+  HODLR_HIP(hipGetLastError());
+  return HODLR_OK;
+}
 
 // One attempt over the ns blocks of sub, whose picks are in sc.sel / sc.cnt
 // and whose tasks are in sc.tasks: the pivot-block LU and inverse, the
@@ -917,10 +974,12 @@ static int skel_attempt(hodlr_s* h, const double* K, int ldk, const std::vector<
   HODLR_HIP(hipMemcpyAsync(sc.samp.p, smp.data(), smp.size() * sizeof(int), hipMemcpyHostToDevice, s));
   {
     ProfScope prof("skel_check", s);
-    k_block_norm2<<<dim3(ns, kNormChunks), kBlock, 0, s>>>(K, ldk, sc.tasks.as<BdlrTask>(), sc.norm.as<double>());
-    k_skel_check<T><<<ns, kBlock, 0, s>>>(K, ldk, sc.tasks.as<BdlrTask>(), sc.rt.as<int>(), sc.cnt.as<int>(),
-                                          sc.norm.as<double>(), Ucap, Vcap, tr.n, sc.samp.as<int>(), kSkelSamples,
-                                          sc.err.as<double>());
+    k_skel_check<T><<<dim3(ns, kCheckChunks), kBlock, 0, s>>>(K, ldk, sc.tasks.as<BdlrTask>(), sc.rt.as<int>(),
+                                                               Ucap, Vcap, tr.n, sc.samp.as<int>(), kSkelSamples,
+                                                               sc.part.as<double>());
+    k_skel_err<<<(ns + kBlock - 1) / kBlock, kBlock, 0, s>>>(sc.tasks.as<BdlrTask>(), ns, sc.cnt.as<int>(),
+                                                            sc.norm.as<double>(), sc.samp.as<int>(), kSkelSamples,
+                                                            sc.part.as<double>(), sc.err.as<double>());
   }
   HODLR_HIP(hipGetLastError());
   err.assign(ns, 0.0);
@@ -936,8 +995,9 @@ static int learned_t(hodlr_s* h, const double* K, int ldk, const int* rowptr, co
   const Tree& tr = h->tree;
   if (tr.n > 2 * kBdlrMaxSide) return fail(HODLR_EINVAL, "learned skeletons support n <= 16384");
   size_t invo = 0, cgo = 0;
-  const std::vector<BdlrTask> tasks = make_tasks<T>(tr, capoff, cap, SKEL, &invo, &cgo);
+  std::vector<BdlrTask> tasks = make_tasks<T>(tr, capoff, cap, SKEL, &invo, &cgo);
   const int nt = (int)tasks.size(), selo = 2 * SKEL * nt;
+  for (int x = 0; x < nt; ++x) tasks[x].task = x;
   const std::vector<SkelBlock> blocks = skel_blocks(tr);
   const int N = 2 * tr.n * tr.L;  // every vertex is a row of one block and a column of another, per level
   int maxside = 0;
@@ -947,6 +1007,7 @@ static int learned_t(hodlr_s* h, const double* K, int ldk, const int* rowptr, co
   HODLR_TRY(d_score.ensure((size_t)N * sizeof(float)));
   SkelScratch sc;
   HODLR_TRY(sc.ensure(nt, selo, invo, cgo, sizeof(T)));
+  HODLR_TRY(block_norms(K, ldk, tasks, sc, s));
   {
     ProfScope prof("skel_features", s);
     HODLR_TRY(launch_skel_features(rowptr, col, xyz, K, ldk, blocks, d_feat.as<float>(), s));
@@ -1007,12 +1068,14 @@ static int adaptive_t(hodlr_s* h, const double* K, int ldk, const int* rowptr, c
   const Tree& tr = h->tree;
   if (tr.n > 2 * kBdlrMaxSide) return fail(HODLR_EINVAL, "BDLR supports n <= 16384");
   size_t invo = 0, cgo = 0;
-  const std::vector<BdlrTask> tasks = make_tasks<T>(tr, capoff, cap, SKEL, &invo, &cgo);
+  std::vector<BdlrTask> tasks = make_tasks<T>(tr, capoff, cap, SKEL, &invo, &cgo);
   const int nt = (int)tasks.size(), selo = 2 * SKEL * nt;
+  for (int x = 0; x < nt; ++x) tasks[x].task = x;
   int maxside = 0;
   for (auto& tk : tasks) maxside = std::max(maxside, std::max(tk.m, tk.nc));
   SkelScratch sc;
   HODLR_TRY(sc.ensure(nt, selo, invo, cgo, sizeof(T)));
+  HODLR_TRY(block_norms(K, ldk, tasks, sc, s));
   HODLR_HIP(hipMemsetAsync(h->d_rank.p, 0, tr.nnodes() * sizeof(int), s));
   h->skel_k.assign(tr.nnodes(), -1);
   const int ms = max_skel > 0 ? std::min(max_skel, SKEL) : SKEL;
