@@ -217,10 +217,11 @@ int cg_solve(const double* K, int n, int ldk, hodlr_t precond, const double* B, 
  * (default priority), ordered after the work already queued on `stream`.
  * The worker count is 8, or HODLR_THREADS (1..64) from the environment when
  * the pool starts.  Pointer arguments are host arrays of nf entries; each
- * front follows the rules of the single-front call.  Both calls synchronize
- * and return the error of the lowest-numbered failing front (the message
- * names it); every front runs even if another fails.  Concurrent calls of
- * either function on one process share the pool.
+ * front follows the rules of the single-front call.  The batched calls
+ * (hodlr_order_batched, hodlr_build_batched, gmres_solve_batched)
+ * synchronize and return the error of the lowest-numbered failing front (the
+ * message names it); every front runs even if another fails.  Concurrent
+ * batched calls on one process share the pool and run one after another.
  *
  * hodlr_build_batched: out[f] receives front f's handle; on any error every
  * handle built by the call is destroyed and out[] is all NULL.
