@@ -53,39 +53,48 @@ __device__ float block_max(float v, float* red) {
   return r;
 }
 
-// Breadth-first distances from the boundary of one side, inside that side.
-// dist: LDS, len entries; 0xffff = not reached.  Own side [s0, s0+len), other
-// side [o0, o0+olen) (both contiguous ranges of vertex ids).
-__device__ void side_bfs(const int* __restrict__ rowptr, const int* __restrict__ col, int s0, int len,
-                         int o0, int olen, unsigned short* dist, int* s_changed) {
+// Breadth-first distances from the boundary of each side of a block, inside
+// that side, both sides in one level loop.  dist[sd]: LDS, len entries;
+// 0xffff = not reached.  Side 0 is [a0, a0+alen), side 1 [b0, b0+blen)
+// (contiguous ranges of vertex ids); the boundary of a side is its vertices
+// with an edge into the other side.
+__device__ void block_bfs(const int* __restrict__ rowptr, const int* __restrict__ col, int a0, int alen, int b0,
+                          int blen, unsigned short (*dist)[kSideMax], int* s_changed) {
   const int t = threadIdx.x;
-  for (int i = t; i < len; i += kBlock) {
-    const int v = s0 + i;
-    unsigned short d = 0xffff;
-    for (int e = rowptr[v]; e < rowptr[v + 1]; ++e) {
-      const int u = col[e];
-      if (u >= o0 && u < o0 + olen) {
-        d = 0;
-        break;
+  for (int sd = 0; sd < 2; ++sd) {
+    const int s0 = sd == 0 ? a0 : b0, len = sd == 0 ? alen : blen;
+    const int o0 = sd == 0 ? b0 : a0, olen = sd == 0 ? blen : alen;
+    for (int i = t; i < len; i += kBlock) {
+      const int v = s0 + i;
+      unsigned short d = 0xffff;
+      for (int e = rowptr[v]; e < rowptr[v + 1]; ++e) {
+        const int u = col[e];
+        if (u >= o0 && u < o0 + olen) {
+          d = 0;
+          break;
+        }
       }
+      dist[sd][i] = d;
     }
-    dist[i] = d;
   }
   __syncthreads();
-  // layer lvl marks its unmarked out-neighbours inside the side (benign
+  // layer lvl marks its unmarked out-neighbours inside its side (benign
   // races: every writer of a vertex writes the same layer number)
   for (int lvl = 0; lvl < 0xfffe; ++lvl) {
     if (t == 0) *s_changed = 0;
     __syncthreads();
     int ch = 0;
-    for (int i = t; i < len; i += kBlock) {
-      if (dist[i] != lvl) continue;
-      const int v = s0 + i;
-      for (int e = rowptr[v]; e < rowptr[v + 1]; ++e) {
-        const int u = col[e];
-        if (u >= s0 && u < s0 + len && dist[u - s0] == 0xffff) {
-          dist[u - s0] = (unsigned short)(lvl + 1);
-          ch = 1;
+    for (int sd = 0; sd < 2; ++sd) {
+      const int s0 = sd == 0 ? a0 : b0, len = sd == 0 ? alen : blen;
+      for (int i = t; i < len; i += kBlock) {
+        if (dist[sd][i] != lvl) continue;
+        const int v = s0 + i;
+        for (int e = rowptr[v]; e < rowptr[v + 1]; ++e) {
+          const int u = col[e];
+          if (u >= s0 && u < s0 + len && dist[sd][u - s0] == 0xffff) {
+            dist[sd][u - s0] = (unsigned short)(lvl + 1);
+            ch = 1;
+          }
         }
       }
     }
@@ -106,8 +115,7 @@ __global__ void __launch_bounds__(kBlock)
   __shared__ int s_changed;
   const SkelBlock b = blocks[blockIdx.x];
   const int t = threadIdx.x;
-  side_bfs(rowptr, col, b.row0, b.m, b.col0, b.nc, dist[0], &s_changed);
-  side_bfs(rowptr, col, b.col0, b.nc, b.row0, b.m, dist[1], &s_changed);
+  block_bfs(rowptr, col, b.row0, b.m, b.col0, b.nc, dist, &s_changed);
   // per side: dmax, max degree, box, max |K_vv|
   float st[2][10];
   for (int sd = 0; sd < 2; ++sd) {
