@@ -120,7 +120,8 @@ void hodlr_default_opts(hodlr_opts* opts);
  *   opts    host; NULL = defaults.
  *   out     host; receives the new handle.
  * Synchronizes the stream once (to size the factor storage from the ranks
- * found; HODLR_LEARNED synchronizes once per size tried).  Errors: EINVAL
+ * found; HODLR_LEARNED and the adaptive BDLR depth synchronize once more per
+ * size or depth tried).  Errors: EINVAL
  * (n < 1, n > 16384 (every compression keeps a block side <= 8192), ldk < n,
  * NULL K/out, bad opts, BDLR or learned without the graph, learned without
  * coords or parameters), ENOMEM, EHIP. */

@@ -863,38 +863,85 @@ __global__ void k_skel_err(const BdlrTask* __restrict__ tasks, int ntask, const 
 }
 
 // splitmix64 (Steele, Lea & Flood 2014): the sample stream of a block
-static inline unsigned long long splitmix64(unsigned long long& x) {
+__device__ __forceinline__ unsigned long long splitmix64(unsigned long long& x) {
   unsigned long long z = (x += 0x9E3779B97F4A7C15ull);
   z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
   z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
   return z ^ (z >> 31);
 }
 
-// ns positions of [0, len) outside `picked` (sorted), without replacement
-static void draw_samples(unsigned long long& st, int len, const int* picked, int npick, int ns, int* out) {
-  std::vector<int> avail;
-  avail.reserve(len);
-  int q = 0;
-  for (int i = 0; i < len; ++i) {
-    if (q < npick && picked[q] == i) {
-      ++q;
-      continue;
-    }
-    avail.push_back(i);
+// Position p of the list of [0, len) without the picks (sorted ascending,
+// distinct): p + k, k = the number of picks below the answer = the number of
+// i with picked[i] - i <= p (non-decreasing in i), by binary search.
+__device__ __forceinline__ int avail_at(const int* picked, int npick, int p) {
+  int lo = 0, hi = npick;  // first i with picked[i] - i > p
+  while (lo < hi) {
+    const int mid = (lo + hi) >> 1;
+    if (picked[mid] - mid <= p) lo = mid + 1;
+    else hi = mid;
   }
-  for (int x = 0; x < ns; ++x) {
-    const int na = (int)avail.size() - x;
+  return p + lo;
+}
+
+constexpr int kSkelSamples = 16;  // sampled rows (columns) per block side
+
+// NS positions of [0, len) outside the picks, without replacement: the first
+// NS steps of a Fisher-Yates shuffle of the unpicked positions, taken from
+// the stream st.  The list itself is never built: its entries are computed
+// on demand (avail_at), and the entries the swaps moved are kept in fixed
+// register slots, 2x for position x and 2x + 1 for the position j swapped
+// with it at step x; a lookup takes the latest slot holding the position.
+// Every loop is unrolled, so the slots stay in registers.
+template <int NS>
+__device__ void draw_side(unsigned long long& st, int len, const int* picked, int npick, int* out) {
+  int opos[2 * NS], oval[2 * NS];
+#pragma unroll
+  for (int k = 0; k < 2 * NS; ++k) opos[k] = -1;
+  const int navail = len - npick;
+#pragma unroll
+  for (int x = 0; x < NS; ++x) {
+    const int na = navail - x;
     if (na <= 0) {
       out[x] = -1;
       continue;
     }
     const int j = x + (int)(splitmix64(st) % (unsigned long long)na);
-    std::swap(avail[x], avail[j]);
-    out[x] = avail[x];
+    int vx = -1, vj = -1;
+#pragma unroll
+    for (int k = 2 * x - 1; k >= 0; --k) {  // latest first
+      if (vx < 0 && opos[k] == x) vx = oval[k];
+      if (vj < 0 && opos[k] == j) vj = oval[k];
+    }
+    if (vx < 0) vx = avail_at(picked, npick, x);
+    if (vj < 0) vj = avail_at(picked, npick, j);
+    opos[2 * x] = x;
+    oval[2 * x] = vj;
+    opos[2 * x + 1] = j;
+    oval[2 * x + 1] = (j == x) ? vj : vx;
+    out[x] = vj;
   }
 }
 
-constexpr int kSkelSamples = 16;
+// One wave per block of the attempt: the picks go to LDS, then one lane
+// draws the row samples and then the column samples, from one stream seeded
+// by the block's node and the attempt.
+constexpr int kDrawPicks = 256;  // >= the largest skeleton (192 / 128)
+__global__ void __launch_bounds__(64)
+    k_draw_samples(const BdlrTask* __restrict__ tasks, const int* __restrict__ sel, const int* __restrict__ cnt,
+                   int skel, unsigned long long seed, int attempt, int ns, int* __restrict__ samp) {
+  __shared__ int pk[2][kDrawPicks];
+  const int x = blockIdx.x, t = threadIdx.x;
+  const BdlrTask tk = tasks[x];
+  const int nr = min(cnt[2 * x], kDrawPicks), nc = min(cnt[2 * x + 1], kDrawPicks);
+  for (int i = t; i < nr; i += 64) pk[0][i] = sel[tk.sel_off + i];
+  for (int i = t; i < nc; i += 64) pk[1][i] = sel[tk.sel_off + skel + i];
+  __syncthreads();
+  if (t != 0) return;
+  unsigned long long st = seed ^ (0xD1B54A32D192ED03ull * (unsigned long long)tk.node) ^
+                          (0x8CB92BA72F3D8DD7ull * (unsigned long long)(attempt + 1));
+  draw_side<kSkelSamples>(st, tk.m, pk[0], nr, samp + (size_t)x * 2 * ns);
+  draw_side<kSkelSamples>(st, tk.nc, pk[1], nc, samp + (size_t)x * 2 * ns + ns);
+}
 
 // Scratch of the attempt loops (learned proposals, adaptive BDLR depth).
 struct SkelScratch {
@@ -930,12 +977,12 @@ static int block_norms(const double* K, int ldk, const std::vector<BdlrTask>& ta
 // and whose tasks are in sc.tasks: the pivot-block LU and inverse, the
 // factors into Ucap / Vcap, then the sampled error of every block (samples
 // drawn outside its picks from a stream seeded by the block and the attempt)
-// into err; the pick counts (rows, columns per block) into cnt.  Synchronizes
-// the stream twice (the picks come back to draw the samples; the errors come
-// back to decide).
+// into err; the pick counts (rows, columns per block) into cnt.  The samples
+// are drawn on the device; the stream is synchronized once, for the errors
+// and counts that decide the next attempt.
 template <typename T, int SKEL>
 static int skel_attempt(hodlr_s* h, const double* K, int ldk, const std::vector<BdlrTask>& sub, int maxside,
-                        int selo, SkelScratch& sc, T* Ucap, T* Vcap, unsigned long long seed, int attempt,
+                        SkelScratch& sc, T* Ucap, T* Vcap, unsigned long long seed, int attempt,
                         std::vector<double>& err, std::vector<int>& cnt, hipStream_t s) {
   const Tree& tr = h->tree;
   const int ns = (int)sub.size();
@@ -955,23 +1002,11 @@ static int skel_attempt(hodlr_s* h, const double* K, int ldk, const std::vector<
         sc.tasks.as<BdlrTask>(), sc.rt.as<int>(), sc.cg.as<T>(), sc.inv.as<T>(), Ucap, tr.n);
   }
   HODLR_HIP(hipGetLastError());
-  // the picks come back to draw the samples outside them
-  cnt.assign(2 * ns, 0);
-  std::vector<int> sel(selo);
-  HODLR_HIP(hipMemcpyAsync(cnt.data(), sc.cnt.p, 2 * ns * sizeof(int), hipMemcpyDeviceToHost, s));
-  HODLR_HIP(hipMemcpyAsync(sel.data(), sc.sel.p, (size_t)selo * sizeof(int), hipMemcpyDeviceToHost, s));
-  HODLR_HIP(hipStreamSynchronize(s));
-  std::vector<int> smp((size_t)ns * 2 * kSkelSamples);
-  for (int x = 0; x < ns; ++x) {
-    const BdlrTask& tk = sub[x];
-    unsigned long long st = seed ^ (0xD1B54A32D192ED03ull * (unsigned long long)tk.node) ^
-                            (0x8CB92BA72F3D8DD7ull * (unsigned long long)(attempt + 1));
-    draw_samples(st, tk.m, sel.data() + tk.sel_off, cnt[2 * x], kSkelSamples,
-                 smp.data() + (size_t)x * 2 * kSkelSamples);
-    draw_samples(st, tk.nc, sel.data() + tk.sel_off + SKEL, cnt[2 * x + 1], kSkelSamples,
-                 smp.data() + (size_t)x * 2 * kSkelSamples + kSkelSamples);
-  }
-  HODLR_HIP(hipMemcpyAsync(sc.samp.p, smp.data(), smp.size() * sizeof(int), hipMemcpyHostToDevice, s));
+  // the samples outside the picks, drawn on the device
+  static_assert(SKEL <= kDrawPicks, "the picks of a side must fit the sampler's LDS");
+  k_draw_samples<<<ns, 64, 0, s>>>(sc.tasks.as<BdlrTask>(), sc.sel.as<int>(), sc.cnt.as<int>(), SKEL, seed, attempt,
+                                   kSkelSamples, sc.samp.as<int>());
+  HODLR_HIP(hipGetLastError());
   {
     ProfScope prof("skel_check", s);
     k_skel_check<T><<<dim3(ns, kCheckChunks), kBlock, 0, s>>>(K, ldk, sc.tasks.as<BdlrTask>(), sc.rt.as<int>(),
@@ -983,7 +1018,9 @@ static int skel_attempt(hodlr_s* h, const double* K, int ldk, const std::vector<
   }
   HODLR_HIP(hipGetLastError());
   err.assign(ns, 0.0);
+  cnt.assign(2 * ns, 0);
   HODLR_HIP(hipMemcpyAsync(err.data(), sc.err.p, ns * sizeof(double), hipMemcpyDeviceToHost, s));
+  HODLR_HIP(hipMemcpyAsync(cnt.data(), sc.cnt.p, 2 * ns * sizeof(int), hipMemcpyDeviceToHost, s));
   HODLR_HIP(hipStreamSynchronize(s));
   return HODLR_OK;
 }
@@ -1034,7 +1071,7 @@ static int learned_t(hodlr_s* h, const double* K, int ldk, const int* rowptr, co
                                         sc.cnt.as<int>());
     }
     HODLR_HIP(hipGetLastError());
-    HODLR_TRY((skel_attempt<T, SKEL>(h, K, ldk, sub, maxside, selo, sc, Ucap, Vcap, seed, attempt, err, cnt, s)));
+    HODLR_TRY((skel_attempt<T, SKEL>(h, K, ldk, sub, maxside, sc, Ucap, Vcap, seed, attempt, err, cnt, s)));
     std::vector<int> next;
     for (int x = 0; x < ns; ++x) {
       if (err[x] <= accept) h->skel_k[sub[x].node] = kk;
@@ -1094,7 +1131,7 @@ static int adaptive_t(hodlr_s* h, const double* K, int ldk, const int* rowptr, c
                                           sc.cnt.as<int>());
     }
     HODLR_HIP(hipGetLastError());
-    HODLR_TRY((skel_attempt<T, SKEL>(h, K, ldk, sub, maxside, selo, sc, Ucap, Vcap, seed, attempt, err, cnt, s)));
+    HODLR_TRY((skel_attempt<T, SKEL>(h, K, ldk, sub, maxside, sc, Ucap, Vcap, seed, attempt, err, cnt, s)));
     std::vector<int> next;
     for (int x = 0; x < ns; ++x) {
       const int b = pending[x], picks = cnt[2 * x] + cnt[2 * x + 1];
