@@ -472,6 +472,9 @@ def main():
     # dominant kernel and its roofline (algorithmic bytes or flops per launch)
     dom = max(kern, key=lambda k: kern[k]["ms_per_step"])
     roof = roofline(dom, kern[dom], stats, n, s, leaf, 4 if prec == 32 else 8, args.workload)
+    # the bandwidth-bound float64 product beside it (the dominant kernel is latency-bound)
+    roof_mv = roofline("matvec", kern["matvec"], stats, n, s, leaf, 4 if prec == 32 else 8, args.workload) \
+        if "matvec" in kern and dom != "matvec" else None
 
     # GPU dense FP64 LU comparator (rocSOLVER through torch): factor + solve
     lu_ms = None
@@ -528,6 +531,7 @@ def main():
         "factor_ms_vs_lu": {"hodlr_build_plus_factor": round(stage_timed["build"] + stage_timed["factor"], 4),
                             "dense_lu_factor_plus_solve": None if lu_ms is None else round(lu_ms, 4)},
         "roofline": roof,
+        "roofline_matvec": roof_mv,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)
