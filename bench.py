@@ -108,6 +108,11 @@ TRAFFIC = {
                     "sha256": "792a556e9f24caac7c69b9f5dd5185421785192b1fc8398ea7f456996596c677",
                     "workload": "tpfa4096", "fetch_kib": 1598.0, "write_kib": 236.0,
                     "fetch_factor": 2.0, "write_factor": 1.0, "rocprof_avg_us": 7.94},
+    # the float64 product on float32 z, the width the tuner keeps on this front (512 columns as 4 chunks)
+    "matvec": {"source": "paper_1403_5337_amd/csrc/gmres.hip",
+               "sha256": "195835287e5149775f5607f87b5b079ae0d7a402d704c836da93e604c71ba018",
+               "workload": "tpfa4096", "fetch_kib": 66135.0, "write_kib": 2048.0,
+               "fetch_factor": 2.0, "write_factor": 1.0, "rocprof_avg_us": 23.95},
 }
 
 
