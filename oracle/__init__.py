@@ -18,7 +18,8 @@ Modules
   gmres     flexible right-preconditioned GMRES (Sec. 3)
   cg        preconditioned conjugate gradients for the symmetric fronts (Sec. 3)
   dense     dense LU reference solve
-  cost      flop counter of the factorization (Sec. 4.4, eq. cost)
+  mlp       the skeleton scorer's network, loss, gradient and Adam (float64)
+  features  the scorer's per-vertex features and training labels
 
 Parity status of each function is stated in its module docstring.
 """

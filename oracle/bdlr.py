@@ -25,7 +25,9 @@ in increasing vertex index.
 
 The optional adaptive loop (Sec. 5.3, monitoring the error on rows/columns
 outside the skeleton) samples rows and columns not picked and adds one
-distance layer while the sampled relative Frobenius error exceeds eps.
+distance layer while the sampled relative Frobenius error exceeds the
+acceptance; the learned proposals (top-k of a scorer) use the same check and
+double k instead.
 
 Pinned in tests: boundary sets and distances against brute force
 (all-pairs shortest paths), the skeleton identity for exactly low-rank
@@ -164,26 +166,143 @@ def bdlr(B, indptr, indices, I, J, depth, eps, max_skel=None, max_rank=None):
     return skeleton(B, rows, cols, eps, max_rank)
 
 
-def sampled_error(B, U, V, rows_avoid, cols_avoid, nsamp, rng):
-    """Relative Frobenius error of U V^T on sampled rows and columns outside
-    the skeleton (the monitor of Sec. 5.3)."""
+# ---------------------------------------------------------------------------
+# The error monitor of Sec. 5.3: the block error is measured on rows and
+# columns outside the skeleton.  Reading: 16 whole rows and 16 whole columns
+# are drawn without replacement from those outside the picks; the squared
+# residual of the sampled rows, scaled by (rows outside) / (rows sampled),
+# estimates the residual over all rows outside (the picked rows contribute
+# little: a pseudo-skeleton reproduces its own rows where Ahat has full
+# rank); likewise for columns; the estimate is the larger of the two, over
+# the exact |B|_F^2.  A block passes at estimate <= accept.
+#
+# Draws come from splitmix64 (Steele, Lea & Flood, "Fast splittable
+# pseudorandom number generators", OOPSLA 2014), one stream per block and
+# attempt: state0 = seed xor (0xD1B54A32D192ED03 * node) xor
+# (0x8CB92BA72F3D8DD7 * (attempt + 1)) modulo 2^64; the samples are the first
+# 16 steps of a Fisher-Yates shuffle of the unpicked positions (ascending),
+# step x swapping position x with x + (next() mod (count - x)); rows first,
+# then columns from the same stream.
+# ---------------------------------------------------------------------------
+MASK64 = (1 << 64) - 1
+NSAMP = 16
+
+
+class SplitMix64:
+    """splitmix64: add the golden gamma to the state, then mix."""
+
+    def __init__(self, state: int):
+        self.state = state & MASK64
+
+    def next(self) -> int:
+        self.state = (self.state + 0x9E3779B97F4A7C15) & MASK64
+        z = self.state
+        z = ((z ^ (z >> 30)) * 0xBF58476D1CE4E5B9) & MASK64
+        z = ((z ^ (z >> 27)) * 0x94D049BB133111EB) & MASK64
+        return z ^ (z >> 31)
+
+
+def block_stream(seed: int, node: int, attempt: int) -> SplitMix64:
+    """The sample stream of block ``node`` (tree node id 2^p - 1 + i) at
+    attempt ``attempt`` (0 = first)."""
+    s = (seed & MASK64) ^ ((0xD1B54A32D192ED03 * node) & MASK64) ^ ((0x8CB92BA72F3D8DD7 * (attempt + 1)) & MASK64)
+    return SplitMix64(s)
+
+
+def draw_outside(rng: SplitMix64, length: int, picks, ns: int = NSAMP):
+    """``ns`` positions of range(length) outside ``picks``, without
+    replacement: the first ``ns`` steps of a Fisher-Yates shuffle of the
+    unpicked positions; -1 where fewer than ``ns`` are left."""
+    taken = set(int(p) for p in picks)
+    avail = [p for p in range(length) if p not in taken]
+    out = []
+    for x in range(ns):
+        left = len(avail) - x
+        if left <= 0:
+            out.append(-1)
+            continue
+        j = x + rng.next() % left
+        avail[x], avail[j] = avail[j], avail[x]
+        out.append(avail[x])
+    return out
+
+
+def sampled_error(B, U, V, nrows_picked, ncols_picked, rs, cs):
+    """Estimated relative Frobenius error of U V^T on B from the sampled whole
+    rows ``rs`` and columns ``cs`` (positions; -1 entries ignored)."""
     m, n = B.shape
-    rfree = np.setdiff1d(np.arange(m), rows_avoid)
-    cfree = np.setdiff1d(np.arange(n), cols_avoid)
-    rs = rng.choice(rfree, size=min(nsamp, rfree.size), replace=False) if rfree.size else rfree
-    cs = rng.choice(cfree, size=min(nsamp, cfree.size), replace=False) if cfree.size else cfree
-    num = np.linalg.norm(B[rs, :] - U[rs, :] @ V.T) ** 2 + np.linalg.norm(B[:, cs] - U @ V[cs, :].T) ** 2
-    den = np.linalg.norm(B[rs, :]) ** 2 + np.linalg.norm(B[:, cs]) ** 2
-    return float(np.sqrt(num / den)) if den > 0 else float(np.sqrt(num))
+    est = 0.0
+    rs = [int(r) for r in rs if r >= 0]
+    cs = [int(c) for c in cs if c >= 0]
+    if rs:
+        R = B[rs, :] - U[rs, :] @ V.T
+        est = max(est, float(np.sum(R * R)) * (m - nrows_picked) / len(rs))
+    if cs:
+        C = B[:, cs] - U @ V[cs, :].T
+        est = max(est, float(np.sum(C * C)) * (n - ncols_picked) / len(cs))
+    nb = float(np.sum(B * B))
+    return float(np.sqrt(est / nb)) if nb > 0 else float(np.sqrt(est))
 
 
-def bdlr_adaptive(B, indptr, indices, I, J, depth, eps, max_depth=10, nsamp=16, seed=0):
-    """Grow the depth while the sampled error exceeds eps (Sec. 5.3)."""
-    rng = np.random.default_rng(seed)
+def check_skeleton(B, U, V, rows, cols, seed, node, attempt, ns=NSAMP):
+    """Draw the samples of (node, attempt) outside ``rows``/``cols`` and
+    return (estimate, row samples, column samples)."""
+    m, n = B.shape
+    rng = block_stream(seed, node, attempt)
+    rs = draw_outside(rng, m, rows, ns)
+    cs = draw_outside(rng, n, cols, ns)
+    return sampled_error(B, U, V, len(rows), len(cols), rs, cs), rs, cs
+
+
+def bdlr_adaptive(B, indptr, indices, I, J, depth, eps, max_depth, accept, seed=0, node=1,
+                  max_skel=None, max_rank=None):
+    """Grow the boundary distance of one block while its sampled error is
+    above ``accept`` (Sec. 5.3).  Attempt a uses depth + a; the block stops
+    when it passes, when one more layer adds no pick, or at ``max_depth``,
+    keeping the skeleton of its last attempt.  Returns (U, V, depth reached,
+    trace), trace = one dict per attempt (depth, picks, samples, err)."""
+    last, attempt, trace = -1, 0, []
     while True:
-        rows, cols = select(indptr, indices, I, J, depth)
-        U, V = skeleton(B, rows, cols, eps)
-        err = sampled_error(B, U, V, rows, cols, nsamp, rng)
-        if err <= eps or depth >= max_depth:
-            return U, V, depth, err
+        rows, cols = select(indptr, indices, I, J, depth, max_skel)
+        U, V = skeleton(B, rows, cols, eps, max_rank)
+        err, rs, cs = check_skeleton(B, U, V, rows, cols, seed, node, attempt)
+        trace.append(dict(depth=depth, nrows=len(rows), ncols=len(cols), rows_s=rs, cols_s=cs, err=err))
+        picks = len(rows) + len(cols)
+        if not (err > accept and picks > last) or depth >= max_depth:
+            return U, V, depth, trace
+        last = picks
         depth += 1
+        attempt += 1
+
+
+def top_k(scores, k):
+    """Positions of the k largest scores (ties to the lower position), in
+    increasing position order."""
+    s = np.asarray(scores)
+    k = min(k, s.size)
+    order = sorted(range(s.size), key=lambda i: (-s[i], i))
+    return np.array(sorted(order[:k]), dtype=np.int64)
+
+
+def learned_block(B, row_scores, col_scores, k_first, max_skel, eps, accept, seed=0, node=1,
+                  max_rank=None):
+    """Learned proposals for one block (the task's scorer replaces Sec. 5.3's
+    pick by distance): the k best-scoring rows and columns form the skeleton
+    of eq. Ahat; a block above ``accept`` retries with twice k, up to
+    ``max_skel``; attempt a uses k_first * 2^a (capped).  Returns (U, V, k
+    kept, trace); k kept = 0 and U, V = None when no size passed (the caller
+    compresses the block by ACA instead)."""
+    k = max(1, min(k_first, max_skel))
+    attempt, trace = 0, []
+    while True:
+        rows = top_k(row_scores, min(k, max_skel))
+        cols = top_k(col_scores, min(k, max_skel))
+        U, V = skeleton(B, rows, cols, eps, max_rank)
+        err, rs, cs = check_skeleton(B, U, V, rows, cols, seed, node, attempt)
+        trace.append(dict(k=k, nrows=len(rows), ncols=len(cols), rows_s=rs, cols_s=cs, err=err))
+        if err <= accept:
+            return U, V, k, trace
+        if k >= max_skel:
+            return None, None, 0, trace
+        k = min(max_skel, 2 * k)
+        attempt += 1

@@ -19,7 +19,10 @@ with O = I) gets 8 features:
                             the diagonal is 0)
 
 Labels (training): 1 if v is a pivot row (S = I) or pivot column (S = J) of
-the block's ACA cross approximation, else 0.
+the block's compression, else 0; two sources: the rows and columns the
+full-pivot LU keeps from the depth-D BDLR skeleton (``lu_labels``; the source
+the committed scorer is trained on) or the crosses of ACA (oracle.aca with
+return_info).
 
 Pinned in tests: a hand-worked 6-vertex path graph.
 """
@@ -67,3 +70,16 @@ def block_features(indptr, indices, coords, kdiag, I, J):
     """(features of the rows I, features of the columns J)."""
     return (side_features(indptr, indices, coords, kdiag, I, J),
             side_features(indptr, indices, coords, kdiag, J, I))
+
+
+def lu_labels(B, indptr, indices, I, J, depth, eps, max_skel=None, max_rank=None):
+    """(row labels, column labels) of block B = K(I, J): 1 on the rows and
+    columns of Ahat that the full-pivot LU of the depth-``depth`` BDLR
+    skeleton keeps as pivots (Sec. 5.3, eq. Ahat), else 0."""
+    rows, cols = _bdlr.select(indptr, indices, I, J, depth, max_skel)
+    yr, yc = np.zeros(len(I)), np.zeros(len(J))
+    if rows.size and cols.size:
+        prow, pcol, _, _, r = _bdlr.full_pivot_lu(B[np.ix_(rows, cols)], eps, max_rank)
+        yr[rows[prow[:r]]] = 1.0
+        yc[cols[pcol[:r]]] = 1.0
+    return yr, yc

@@ -144,16 +144,87 @@ def test_bdlr_on_front_depth_improves():
 # ---------------------------------------------------------------------------
 # the error monitor and the adaptive depth (Sec. 5.3)
 # ---------------------------------------------------------------------------
+def test_splitmix64_published_outputs():
+    # the generator's published reference outputs (Steele, Lea & Flood 2014;
+    # the splitmix64 reference code): state 0 and state 1234567
+    r = bdlr.SplitMix64(0)
+    assert [r.next() for _ in range(4)] == [0xE220A8397B1DCDAF, 0x6E789E6AA1B965F4, 0x06C45D188009454F,
+                                            0xF88BB8A8724C81EC]
+    r = bdlr.SplitMix64(1234567)
+    assert [r.next() for _ in range(3)] == [6457827717110365317, 3203168211198807973, 9817491932198370423]
+
+
+def test_block_stream_seeding():
+    # state0 = seed ^ (0xD1B54A32D192ED03 * node) ^ (0x8CB92BA72F3D8DD7 * (attempt + 1)) mod 2^64;
+    # node 0, attempt -1 leaves the seed itself
+    assert bdlr.block_stream(1234567, 0, -1).next() == 6457827717110365317
+    a = bdlr.block_stream(5, 3, 0).state
+    assert a == (5 ^ ((0xD1B54A32D192ED03 * 3) % 2 ** 64) ^ 0x8CB92BA72F3D8DD7)
+
+
+def test_draw_outside_hand_worked():
+    # positions 0..2 with 1 picked: the unpicked list is [0, 2].  State 0's
+    # first output is odd, so step 0 swaps position 0 with 0 + (odd mod 2) = 1
+    # and draws 2; step 1 has one position left (a draw is still consumed)
+    # and takes 0; the rest are empty.
+    r = bdlr.SplitMix64(0)
+    assert bdlr.draw_outside(r, 3, [1], 4) == [2, 0, -1, -1]
+    assert r.next() == 0x06C45D188009454F  # two outputs were consumed: the third is next
+
+
+@pytest.mark.parametrize("length,npick", [(200, 0), (200, 37), (20, 10), (17, 0), (5, 5), (0, 0)])
+def test_draw_outside_properties(length, npick):
+    rng = np.random.default_rng(length + npick)
+    picks = np.sort(rng.choice(length, npick, replace=False)) if npick else np.array([], int)
+    s = bdlr.draw_outside(bdlr.SplitMix64(99), length, picks, 16)
+    got = [x for x in s if x >= 0]
+    left = length - npick
+    assert len(s) == 16 and len(got) == min(16, left) and all(x == -1 for x in s[len(got):])
+    assert len(set(got)) == len(got) and not set(got) & set(picks.tolist())
+    assert all(0 <= x < length for x in got)
+    if left <= 16:
+        assert sorted(got) == sorted(set(range(length)) - set(picks.tolist()))
+
+
+def test_draw_outside_is_uniform():
+    # first draw over 5 unpicked positions, 5000 streams: each about 1/5
+    counts = np.zeros(8, int)
+    for node in range(5000):
+        counts[bdlr.draw_outside(bdlr.block_stream(0, node, 0), 8, [1, 4, 6], 1)[0]] += 1
+    assert counts[[1, 4, 6]].sum() == 0
+    assert np.all(np.abs(counts[[0, 2, 3, 5, 7]] - 1000) < 4.5 * np.sqrt(5000 * 0.2 * 0.8))
+
+
 def test_sampled_error_hand_cases():
     B = np.diag([1.0, 2.0, 3.0, 4.0])
-    rng = np.random.default_rng(0)
-    avoid = np.array([0, 1, 2])
-    # exact: zero; nothing: one; diag(1,2,3,2): row 3 and column 3 each miss by 2,
-    # so sqrt((4 + 4) / (16 + 16)) = 1/2
-    assert bdlr.sampled_error(B, B.copy(), np.eye(4), avoid, avoid, 1, rng) == 0.0
-    assert bdlr.sampled_error(B, np.zeros((4, 1)), np.zeros((4, 1)), avoid, avoid, 1, rng) == 1.0
-    e = bdlr.sampled_error(B, np.diag([1.0, 2.0, 3.0, 2.0]), np.eye(4), avoid, avoid, 1, rng)
-    assert abs(e - 0.5) < 1e-15
+    U, V = np.diag([1.0, 2.0, 3.0, 2.0]), np.eye(4)
+    # rows 0, 1 and columns 0, 1 picked: 2 rows and 2 columns outside.  Row 3
+    # misses by 2 (squared residual 4), column 2 is exact: one sampled row
+    # stands for 2 outside rows, so the estimate is sqrt(8 / |B|^2) with
+    # |B|^2 = 30; both outside rows sampled: sqrt(4 / 30)
+    assert bdlr.sampled_error(B, U, V, 2, 2, [3], [2]) == pytest.approx(np.sqrt(8 / 30), rel=1e-15)
+    assert bdlr.sampled_error(B, U, V, 2, 2, [2, 3, -1], [-1]) == pytest.approx(np.sqrt(4 / 30), rel=1e-15)
+    # the larger side wins: column 3 also misses by 2
+    assert bdlr.sampled_error(B, U, V, 3, 1, [3], [3]) == pytest.approx(np.sqrt(4 * 3 / 30), rel=1e-15)
+    assert bdlr.sampled_error(B, B.copy(), np.eye(4), 2, 2, [2, 3], [2, 3]) == 0.0
+    assert bdlr.sampled_error(B, U, V, 2, 2, [-1], []) == 0.0
+    # nothing kept: every row misses its whole norm; all 4 rows sampled gives 1
+    assert bdlr.sampled_error(B, np.zeros((4, 1)), np.zeros((4, 1)), 0, 0, [0, 1, 2, 3], []) == 1.0
+
+
+def test_sampled_error_equals_the_true_error_when_every_outside_row_is_sampled():
+    # a pseudo-skeleton reproduces its picked rows and columns where Ahat has
+    # full rank, so sampling every outside row (and column) measures the whole
+    # residual: the estimate is the exact relative error
+    rng = np.random.default_rng(4)
+    B = rng.standard_normal((12, 5)) @ rng.standard_normal((5, 10)) + 1e-3 * rng.standard_normal((12, 10))
+    rows, cols = np.arange(5), np.arange(5)
+    U, V = bdlr.skeleton(B, rows, cols, 1e-14)
+    exact = np.linalg.norm(B - U @ V.T) / np.linalg.norm(B)
+    est = bdlr.sampled_error(B, U, V, 5, 5, list(range(5, 12)), list(range(5, 10)))
+    assert est == pytest.approx(exact, rel=1e-9)
+    err, rs, cs = bdlr.check_skeleton(B, U, V, rows, cols, seed=3, node=2, attempt=0)
+    assert sorted(x for x in rs if x >= 0) == list(range(5, 12)) and err == pytest.approx(exact, rel=1e-9)
 
 
 def three_scale_block(n):
@@ -168,11 +239,12 @@ def three_scale_block(n):
     return indptr, indices, I, J, B
 
 
-def test_adaptive_depth_deepens_until_the_error_meets_eps():
+def test_adaptive_depth_deepens_until_the_error_meets_the_acceptance():
     indptr, indices, I, J, B = three_scale_block(40)
     eps = 1e-10
-    U, V, depth, err = bdlr.bdlr_adaptive(B, indptr, indices, I, J, 1, eps, max_depth=40, seed=1)
-    assert depth == 3 and err <= eps and U.shape[1] == 3
+    U, V, depth, trace = bdlr.bdlr_adaptive(B, indptr, indices, I, J, 1, eps, max_depth=40, accept=1e-10, seed=1)
+    assert depth == 3 and U.shape[1] == 3 and [t["depth"] for t in trace] == [1, 2, 3]
+    assert trace[-1]["err"] <= 1e-10 and all(t["err"] > 1e-10 for t in trace[:-1])
     # the factors are the fixed-depth skeleton at the depth reached
     U2, V2 = bdlr.bdlr(B, indptr, indices, I, J, depth, eps)
     assert np.array_equal(U, U2) and np.array_equal(V, V2)
@@ -181,11 +253,53 @@ def test_adaptive_depth_deepens_until_the_error_meets_eps():
     U1, V1 = bdlr.bdlr(B, indptr, indices, I, J, depth - 1, eps)
     assert np.linalg.norm(B - U1 @ V1.T) > 1e-4 * np.linalg.norm(B)
     # a start that already passes is kept
-    _, _, d2, _ = bdlr.bdlr_adaptive(B, indptr, indices, I, J, 5, eps, max_depth=40, seed=1)
-    assert d2 == 5
+    _, _, d2, t2 = bdlr.bdlr_adaptive(B, indptr, indices, I, J, 5, eps, max_depth=40, accept=1e-10, seed=1)
+    assert d2 == 5 and len(t2) == 1
+    # attempt a draws from the stream of (node, a)
+    r0 = bdlr.block_stream(1, 1, 2)
+    rows, cols = bdlr.select(indptr, indices, I, J, 3)
+    assert trace[2]["rows_s"] == bdlr.draw_outside(r0, 40, rows)
 
 
 def test_adaptive_depth_stops_at_the_maximum():
     indptr, indices, I, J, B = three_scale_block(30)
-    _, _, depth, err = bdlr.bdlr_adaptive(B, indptr, indices, I, J, 1, 1e-10, max_depth=2, seed=2)
-    assert depth == 2 and err > 1e-10
+    _, _, depth, trace = bdlr.bdlr_adaptive(B, indptr, indices, I, J, 1, 1e-10, max_depth=2, accept=1e-10, seed=2)
+    assert depth == 2 and len(trace) == 2 and trace[-1]["err"] > 1e-10
+
+
+def test_adaptive_depth_stops_when_a_layer_adds_no_pick():
+    # path 1-2-3-4-5 with vertex 0 isolated; rows {0,1,2}, columns {3,4,5}:
+    # row 0 is never reached, so from depth 3 on a layer adds nothing; eps 0.5
+    # keeps one pivot and the sampled row 0 keeps the error above acceptance
+    rows = [1, 2, 2, 3, 3, 4, 4, 5]
+    cols = [2, 1, 3, 2, 4, 3, 5, 4]
+    G = sp.csr_matrix((np.ones(len(rows)), (rows, cols)), shape=(6, 6))
+    G.sort_indices()
+    _, _, _, _, B = three_scale_block(3)
+    I, J = np.arange(3), np.arange(3, 6)
+    _, _, depth, trace = bdlr.bdlr_adaptive(B, G.indptr, G.indices, I, J, 1, 0.5, max_depth=40, accept=1e-14, seed=0)
+    assert [t["nrows"] + t["ncols"] for t in trace] == [2, 4, 5, 5] and depth == 4
+    assert trace[-1]["err"] > 1e-14 and trace[-1]["rows_s"][:2] == [0, -1]
+
+
+def test_top_k_ties_to_the_lower_position():
+    assert bdlr.top_k([0.5, 2.0, 0.5, 1.0, 0.5], 3).tolist() == [0, 1, 3]
+    assert bdlr.top_k([0.5, 2.0, 0.5, 1.0, 0.5], 4).tolist() == [0, 1, 2, 3]
+    assert bdlr.top_k([1.0], 5).tolist() == [0]
+
+
+def test_learned_block_doubles_k_until_the_check_passes():
+    # scores that prefer the boundary: the k nearest rows / columns; the block
+    # needs the first three distance layers (k = 4 covers them, k = 2 does not)
+    indptr, indices, I, J, B = three_scale_block(40)
+    sr = -np.abs(np.arange(40) - 39.0)   # row 39 touches the columns
+    sc = -np.arange(40, dtype=float)     # column 0 touches the rows
+    U, V, k, trace = bdlr.learned_block(B, sr, sc, 1, 192, 1e-10, 1e-10, seed=0, node=1)
+    assert k == 4 and [t["k"] for t in trace] == [1, 2, 4]
+    Ur, Vr = bdlr.skeleton(B, np.arange(36, 40), np.arange(4), 1e-10)
+    assert np.array_equal(U, Ur) and np.array_equal(V, Vr)
+    # with at most 2 picks per side no size passes: fallback
+    U, V, k, trace = bdlr.learned_block(B, sr, sc, 1, 2, 1e-10, 1e-10, seed=0, node=1)
+    assert U is None and k == 0 and [t["k"] for t in trace] == [1, 2]
+
+

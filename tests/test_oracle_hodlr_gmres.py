@@ -4,7 +4,7 @@ import pytest
 import scipy.linalg as sla
 
 from gen import factors, fronts
-from oracle import cost, dense, gmres, hodlr, ordering
+from oracle import dense, gmres, hodlr, ordering
 
 
 def oracle_from_factors(fac):
@@ -89,17 +89,6 @@ def test_extended_system_matches():
     xh = np.linalg.solve(Kh, np.r_[F, np.zeros(r21 + r12)])
     hodlr.factor(h)
     assert np.allclose(hodlr.solve(h, F), xh[:n], rtol=0, atol=1e-12)
-
-
-def test_cost_count_matches_recurrence():
-    n, L, r, s = 1024, 4, 6, 2
-    sizes = [[n / 2 ** p] * 2 ** p for p in range(L + 1)]
-    ranks = [[0]] + [[r] * 2 ** p for p in range(1, L + 1)]
-    assert np.isclose(cost.count(sizes, ranks, s), cost.recurrence(n, r, s, L), rtol=1e-12)
-    # decaying ranks r_p = r1 / 2^{p/2}: cost grows like n r1^2 (Sec. 4.4), not n r^2 log^2 n
-    c1 = cost.count([[4096 / 2 ** p] * 2 ** p for p in range(6)],
-                    [[0]] + [[int(64 / 2 ** ((p - 1) / 2))] * 2 ** p for p in range(1, 6)], 1)
-    assert c1 < cost.recurrence(4096, 64, 1, 5)
 
 
 # --------------------------------------------------------------------------

@@ -125,3 +125,24 @@ def test_features_unreached_vertex():
     np.testing.assert_allclose(FI[:, 1], [0.5, 1, 1 / 3])
     np.testing.assert_allclose(FI[:, 3:6], 0)
     np.testing.assert_allclose(FI[:, 7], 0)
+
+
+def test_lu_labels_mark_the_kept_pivots():
+    # path graph 0..2n-1, rows 0..n-1, columns n..2n-1; B exactly rank 3 in
+    # three distance layers (three exponentials of the distance): depth 4
+    # picks 4 rows and 4 columns, the full-pivot LU keeps 3 of each, all
+    # inside the picks; at depth 1 one row and one column
+    import scipy.sparse as sp
+    n = 12
+    r_ = np.r_[np.arange(2 * n - 1), np.arange(1, 2 * n)]
+    c_ = np.r_[np.arange(1, 2 * n), np.arange(2 * n - 1)]
+    G = sp.csr_matrix((np.ones(r_.size), (r_, c_)), shape=(2 * n, 2 * n))
+    G.sort_indices()
+    I, J = np.arange(n), np.arange(n, 2 * n)
+    D = (J[None, :] - I[:, None]).astype(float)
+    B = np.exp(-0.3 * D) + 0.5 * np.exp(-1.0 * D) + 0.25 * np.exp(-2.0 * D)
+    yr, yc = ofeat.lu_labels(B, G.indptr, G.indices, I, J, 4, 1e-10)
+    assert yr.sum() == 3 and yc.sum() == 3
+    assert set(np.nonzero(yr)[0]) <= {8, 9, 10, 11} and set(np.nonzero(yc)[0]) <= {0, 1, 2, 3}
+    yr, yc = ofeat.lu_labels(B, G.indptr, G.indices, I, J, 1, 1e-10)
+    assert np.nonzero(yr)[0].tolist() == [11] and np.nonzero(yc)[0].tolist() == [0]
