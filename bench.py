@@ -4,16 +4,21 @@ preconditioner, next to GPU dense LU, the dominant kernel's roofline and the
 FP64 oracle timed on the host.
 
 One step = the whole hot path on one front, inputs resident in HBM:
-  recursive-coordinate-bisection order -> permuted front and separator graph
-  -> compression of every off-diagonal block (BDLR boundary-distance
-  skeletons, depth 2, by default; ACA with --method aca) in float32 ->
+  recursive-coordinate-bisection order -> permuted front, separator graph
+  and dof coordinates -> compression of every off-diagonal block in float32
+  (default: the learned skeleton proposer with the committed scorer, each
+  side's first budget its BDLR pick count at depth 2, ACA fallback) ->
   level-by-level Woodbury factorization (float32) -> flexible GMRES in
-  float64 on 8 right-hand sides to a relative residual of 1e-12.
+  float64 to a relative residual of 1e-12.
 value = right-hand sides solved per second of step time.
 
-Workload (synthetic, seeded): Schur complement onto the middle plane of a
-7-point lognormal(0,1) diffusion operator on a 64x64x63 grid (n = 4096),
-HODLR leaf 128, tolerance 1e-4.
+Default workload (synthetic, seeded): a held-out evaluation front of the
+learned proposer, the Schur complement of clamped Q1 hex elasticity (E = 1,
+nu = 0.3, 3 dof per node) on a 64 x 32 x 63 free-node grid onto its middle
+node plane (64 x 32 nodes, n = 6144), separator dofs permuted by seed
+10001; HODLR leaf 128, tolerance 1e-4, one right-hand side.  Other
+workloads: --workload tpfa4096 (8 right-hand sides), elastic4800, laplace1024,
+tet64k, nd64 (the nested-dissection batch); --method bdlr / aca.
 """
 import argparse
 import json
@@ -35,12 +40,13 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="tpfa4096")
+    ap.add_argument("--workload", default="elastic6144")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-lu", action="store_true")
-    ap.add_argument("--method", choices=["aca", "bdlr", "learned"], default="bdlr",
+    ap.add_argument("--method", choices=["aca", "bdlr", "learned"], default="learned",
                     help="learned: scorer-proposed skeletons (committed parameters) with ACA fallback")
-    ap.add_argument("--depth", type=int, default=2, help="BDLR boundary distance")
+    ap.add_argument("--depth", type=int, default=2,
+                    help="BDLR boundary distance; for learned, the depth whose pick counts size the first budgets")
     ap.add_argument("--solver", choices=["gmres", "cg"], default="gmres",
                     help="cg: symmetric HODLR build and preconditioned CG instead of GMRES")
     ap.add_argument("--study", choices=["sweep"], default=None,
@@ -53,11 +59,31 @@ def parse():
     return ap.parse_args()
 
 
-def cpu_baseline(front, w, nrhs_sample, method, depth, solver="gmres"):
+def _oracle_params():
+    """The committed scorer parameters as the oracle's dictionary, weights
+    rounded to bfloat16 as the library uses them."""
+    import numpy as np
+
+    from oracle import mlp
+    flat = mlp.round_bf16(np.load(os.path.join(ROOT, "paper_1403_5337_amd", "skel_mlp.npy"), allow_pickle=False))
+    P, o = {}, 0
+    for k in mlp.NAMES:
+        sz = int(np.prod(mlp.SHAPES[k]))
+        P[k] = np.asarray(flat[o:o + sz], dtype=np.float64).reshape(mlp.SHAPES[k])
+        o += sz
+    return P
+
+
+def cpu_baseline(front, w, nrhs_sample, method, depth, solver="gmres", budget_s=10.0):
     """The FP64 oracle, as it stands, on the same front: ordering,
-    compression, factorization and GMRES (or CG) for `nrhs_sample`
-    right-hand sides."""
-    from threadpoolctl import threadpool_info
+    compression (the same method: ACA, BDLR, or the learned proposals with
+    ACA fallback), recursive Woodbury factorization and FGMRES (or CG) for
+    `nrhs_sample` right-hand sides; whole pipelines repeated until
+    `budget_s` of host time, first with the BLAS pool's threads, then with
+    one thread.  Returns (the JSON entry, the oracle's solution in the
+    permuted numbering)."""
+    import numpy as np
+    from threadpoolctl import threadpool_info, threadpool_limits
 
     from gen import fronts
     from oracle import cg, gmres, hodlr, ordering
@@ -65,14 +91,17 @@ def cpu_baseline(front, w, nrhs_sample, method, depth, solver="gmres"):
     fc = fronts.Front(K=front.K.cpu(), indptr=front.indptr, indices=front.indices, coords=front.coords,
                       name=front.name)
     B = fronts.rhs(front.n, nrhs_sample, seed=0).numpy()
-    # whole pipelines, repeated until about 10 s of host work have been timed
-    reps, t0 = 0, time.perf_counter()
-    while True:
+    params = _oracle_params() if method == "learned" else None
+    sym = solver == "cg"
+
+    def pipeline():
         perm = ordering.rcb_permutation(fc.coords, w["leaf"])
         g = fronts.permute_front(fc, perm)
         Kp = g.K.numpy()
-        sym = solver == "cg"
-        if method == "bdlr":
+        if method == "learned":
+            h = hodlr.from_dense(Kp, w["leaf"], method="learned", eps=w["tol"], graph=(g.indptr, g.indices),
+                                 depth=depth, max_skel=192, max_rank=184, coords=g.coords, mlp_params=params)
+        elif method == "bdlr":
             h = hodlr.from_dense(Kp, w["leaf"], method="bdlr", eps=w["tol"], graph=(g.indptr, g.indices),
                                  depth=depth, max_skel=192, symmetric=sym)
         else:
@@ -83,19 +112,36 @@ def cpu_baseline(front, w, nrhs_sample, method, depth, solver="gmres"):
         else:
             X, infos = gmres.fgmres_multi(lambda v: Kp @ v, B, lambda v: hodlr.solve(h, v), tol=1e-12,
                                           maxit=1000, restart=200)
-        reps += 1
-        if time.perf_counter() - t0 >= 10.0:
-            break
-    dt = (time.perf_counter() - t0) / reps
+        return X, infos
+
+    def timed():
+        reps, t0 = 0, time.perf_counter()
+        while True:
+            X, infos = pipeline()
+            reps += 1
+            if time.perf_counter() - t0 >= budget_s:
+                break
+        return (time.perf_counter() - t0) / reps, reps, X, infos
+
     threads = 1
     for p in threadpool_info():
         if p.get("internal_api") in ("openblas", "mkl", "blis"):
             threads = max(threads, int(p.get("num_threads", 1)))
-    return dict(value=nrhs_sample / dt, unit="solves/s", cores=threads, kind="oracle",
-                sample=f"full oracle pipeline (RCB order, {method.upper()} 1e-4, recursive Woodbury factor, "
-                       f"{'symmetric build, PCG' if solver == 'cg' else 'FGMRES'} to 1e-12) "
-                       f"on the same n={front.n} front for {nrhs_sample} of {w['nrhs']} right-hand sides, "
-                       f"{reps} repetitions, {dt:.2f} s each; iterations {[i['iters'] for i in infos]}")
+    dt, reps, X, infos = timed()
+    with threadpool_limits(limits=1):
+        dt1, reps1, _, _ = timed()
+    what = {"learned": "learned proposals by mesh node (committed scorer, first budgets the depth-"
+                       f"{depth} BDLR pick counts) with ACA fallback",
+            "bdlr": f"BDLR depth {depth}", "aca": "ACA"}[method]
+    entry = dict(value=nrhs_sample / dt, unit="solves/s", cores=threads, kind="oracle",
+                 sample=f"full oracle pipeline (RCB order, {what} at {w['tol']:g}, recursive Woodbury factor, "
+                        f"{'symmetric build, PCG' if sym else 'FGMRES'} to 1e-12) on the same n={front.n} front "
+                        f"for {nrhs_sample} of {w['nrhs']} right-hand sides, {reps} repetitions of "
+                        f"{dt:.2f} s each; iterations {[i['iters'] for i in infos]}",
+                 one_thread=dict(value=nrhs_sample / dt1, unit="solves/s", cores=1,
+                                 sample=f"the same pipeline with the BLAS pool limited to one thread, {reps1} "
+                                        f"repetitions of {dt1:.2f} s each"))
+    return entry, X
 
 
 # HBM bytes per launch from rocprofv3 FETCH_SIZE / WRITE_SIZE runs of this
@@ -143,16 +189,13 @@ def roofline(name, k, stats, n, s, leaf, ez, workload):
         work = 8.0 * n * n + 4.0 * n * s + 8.0 * n * s
         note = "K (f64) + z (f32) + w (f64) per launch"
     elif name == "apply_level":
-        # per level q: E_c (|c| x (r_a + r_b)) for every node, the W block of level q-1
-        # (n x r_{q-1}), x read and written; averaged over the L launches of one apply
-        tot = 0.0
-        for q in range(1, L + 1):
-            e = sum((n >> q) * (ranks[q - 1][2 * (c // 2)] + ranks[q - 1][2 * (c // 2) + 1])
-                    for c in range(1 << q))
-            w = n * max(ranks[q - 2]) if q > 1 else 0
-            tot += ez * (e + w + 2 * n * s)
-        work = tot / L
-        note = "E_c, next-level W block, x in/out; mean over the L level launches of one apply"
+        # the apply's algorithmic bytes 4 n (b + 2 R) (float32 elements; R =
+        # the sum over levels of the level's rank): its level part, the two
+        # n x R panels, spread over the L level launches, plus x read and
+        # written per launch
+        R = sum(max(r) for r in ranks)
+        work = ez * 2.0 * n * R / L + 2.0 * ez * n * s
+        note = "apply bytes 4n(b + 2R): the 2nR panel part over the L level launches, plus x in/out"
     elif name == "apply_leaf":
         work = ez * (n * leaf + n * max(ranks[-1]) + 2 * n * s) if ranks else ez * (n * leaf + 2 * n * s)
         note = "leaf inverses, level-L W block, x in/out"
@@ -436,6 +479,8 @@ def main():
         if ev is not None:
             ev[4].record(stream)
         stats = h.stats()
+        if args.method == "learned":
+            stats["kused"] = h.skel_info()
         h.close()
         return X, it, rr, st, stats, Kp
 
@@ -481,27 +526,50 @@ def main():
     roof_mv = roofline("matvec", kern["matvec"], stats, n, s, leaf, 4 if prec == 32 else 8, args.workload) \
         if "matvec" in kern and dom != "matvec" else None
 
-    # GPU dense FP64 LU comparator (rocSOLVER through torch): factor + solve
-    lu_ms = None
+    # GPU dense FP64 LU comparators on the same permuted front and right-hand
+    # sides: torch's default linear-algebra backend and the one it names
+    # "cusolver" (rocSOLVER / hipSOLVER on ROCm), each timed for factor +
+    # solve, with its achieved float64 rate (2/3 n^3 + 2 n^2 s flops)
+    lu = {}
+    Xlu = None
     if not args.no_lu:
-        Kr = front.K
-        for _ in range(2):
-            LU, piv = torch.linalg.lu_factor(Kr)
-            torch.linalg.lu_solve(LU, piv, B)
-        torch.cuda.synchronize()
-        t2 = time.perf_counter()
-        for _ in range(max(3, args.steps // 2)):
-            LU, piv = torch.linalg.lu_factor(Kr)
-            Xlu = torch.linalg.lu_solve(LU, piv, B)
-        torch.cuda.synchronize()
-        lu_ms = (time.perf_counter() - t2) * 1e3 / max(3, args.steps // 2)
+        lu_flops = 2.0 / 3.0 * n ** 3 + 2.0 * n * n * s
+        prev = torch.backends.cuda.preferred_linalg_library()
+        for backend in ("default", "cusolver"):
+            try:
+                torch.backends.cuda.preferred_linalg_library(backend)
+                for _ in range(2):
+                    LU, piv = torch.linalg.lu_factor(Kp)
+                    Xl = torch.linalg.lu_solve(LU, piv, B)
+                torch.cuda.synchronize()
+                reps = max(3, args.steps // 2)
+                t2 = time.perf_counter()
+                for _ in range(reps):
+                    LU, piv = torch.linalg.lu_factor(Kp)
+                    Xl = torch.linalg.lu_solve(LU, piv, B)
+                torch.cuda.synchronize()
+                ms_lu = (time.perf_counter() - t2) * 1e3 / reps
+                lu[backend] = dict(ms=round(ms_lu, 4), tflops_f64=round(lu_flops / ms_lu * 1e-9, 3))
+                Xlu = Xl
+            except RuntimeError as e:  # a backend this build of torch lacks
+                lu[backend] = dict(error=str(e)[:120])
+        torch.backends.cuda.preferred_linalg_library(prev)
+    lu_ok = [v["ms"] for v in lu.values() if "ms" in v]
+    lu_ms = min(lu_ok) if lu_ok else None
+
+    def col_err(Xa, Xb):
+        Xa, Xb = np.asarray(Xa, dtype=np.float64), np.asarray(Xb, dtype=np.float64)
+        return float(max(np.linalg.norm(Xa[:, j] - Xb[:, j]) / np.linalg.norm(Xb[:, j]) for j in range(Xb.shape[1])))
+
+    Xn = X.double().cpu().numpy()
+    x_err = {}
+    if Xlu is not None:
+        x_err["vs_gpu_dense_lu"] = col_err(Xn, Xlu.cpu().numpy())
 
     cpu = None
     if not args.no_cpu_baseline:
-        # the oracle has no learned build: a learned run is set beside the
-        # oracle's BDLR pipeline, and the sample says so
-        cpu = cpu_baseline(front, w, s, "bdlr" if args.method == "learned" else args.method, args.depth,
-                           args.solver)
+        cpu, Xo = cpu_baseline(front, w, s, args.method, args.depth, args.solver)
+        x_err["vs_oracle"] = col_err(Xn, Xo)
 
     out = {
         "metric": ("GMRES-to-1e-12 solves/sec (HODLR-preconditioned, end to end incl. compression and factorization)"
@@ -530,7 +598,13 @@ def main():
         "iters": it,
         "relres_max": max(rr),
         "ranks_max_per_level": [max(r) for r in stats["ranks"]],
+        "learned_blocks": None if "kused" not in stats else {
+            "passed": sum(k > 0 for lv in stats["kused"] for k in lv),
+            "aca_kept": sum(k == 0 for lv in stats["kused"] for k in lv),
+            "failed_skeleton_kept": sum(k < 0 for lv in stats["kused"] for k in lv)},
         "kernels": kern,
+        "x_rel_err_max": x_err,
+        "gpu_dense_lu": lu,
         "gpu_dense_lu_ms": None if lu_ms is None else round(lu_ms, 4),
         "speedup_vs_gpu_dense_lu": None if lu_ms is None else round(lu_ms / ms_step, 3),
         "factor_ms_vs_lu": {"hodlr_build_plus_factor": round(stage_timed["build"] + stage_timed["factor"], 4),

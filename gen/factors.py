@@ -62,3 +62,30 @@ def random_hodlr(n, leaf, ranks, seed=0, scale=0.5, ragged=False):
             Up[p][lo:hi, :r] = u
             Vp[p][slo:shi, :r] = v
     return dict(levels=levs, leaves=leaves, U=U, V=V, Upanel=Up, Vpanel=Vp, rmax=rmax)
+
+
+def random_picks(n, leaf, max_skel, seed=0):
+    """Seeded pick lists for every off-diagonal block of the halving tree, in
+    level order (node 1, 2, ...): per block (rows, cols), each a sorted list
+    of distinct positions within its side, of a random count in [0,
+    min(max_skel, side)], with the extremes (none picked, and the side
+    picked up to at most 15 positions left) drawn as well."""
+    rng = np.random.default_rng(seed)
+    levs = halving_levels(n, leaf)
+    out = []
+    for p in range(1, len(levs)):
+        for i, (lo, hi) in enumerate(levs[p]):
+            slo, shi = levs[p][i ^ 1]
+            pair = []
+            for length in (hi - lo, shi - slo):
+                cap = min(max_skel, length)
+                kind = rng.integers(0, 6)
+                if kind == 0:
+                    k = 0
+                elif kind == 1:
+                    k = max(0, min(cap, length - int(rng.integers(0, 16))))
+                else:
+                    k = int(rng.integers(0, cap + 1))
+                pair.append(sorted(int(x) for x in rng.choice(length, size=k, replace=False)))
+            out.append(tuple(pair))
+    return out

@@ -258,6 +258,11 @@ WORKLOADS = {
                      leaf=128, tol=1e-4, precision=32, nrhs=8),
     "elastic4800": dict(gen="q1", free_shape=(40, 40, 39), zs=19, perm_seed=0,
                         leaf=128, tol=1e-4, precision=32, nrhs=1),
+    # held-out evaluation fronts of the learned skeleton proposer: Q1
+    # elasticity with 64 x 32 separator nodes (n = 6144) in a 64 x 32 x 63
+    # free-node box, dofs permuted by seeds 10001, 10002, ...
+    "elastic6144": dict(gen="q1", free_shape=(64, 32, 63), zs=31, perm_seed=10001,
+                        leaf=128, tol=1e-4, precision=32, nrhs=1),
     # unstructured: P1 Laplacian on a Delaunay mesh of 64000 seeded points,
     # mid-plane vertex separator (n about 2000)
     "tet64k": dict(gen="tet", npoints=64000, seed=0, leaf=128, tol=1e-4, precision=32, nrhs=1),

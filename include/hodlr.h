@@ -60,15 +60,21 @@ typedef struct {
   int max_rank;   /* cap on every off-diagonal rank (0 = library maximum:
                      184 at precision 32, 128 at precision 64) */
   int precision;  /* 32 or 64: arithmetic of the factorization and solve */
-  /* HODLR_LEARNED only: every block first takes the skel_k best-scoring rows
-     and columns of each side as the skeleton rows/columns of eq. Ahat
-     (Sec. 5.3); its relative Frobenius error is estimated from 16 whole
-     rows and 16 whole columns outside the skeleton (the residual there,
-     scaled by rows outside / rows sampled, over |block|_F^2, the larger of
-     the row and column estimates, float64); a block above skel_tol retries
-     with twice the size, up to 192 (precision 32) / 128 (precision 64),
-     then is compressed by ACA instead. */
-  int skel_k;                /* first skeleton size, >= 1 (default 32) */
+  /* HODLR_LEARNED only: the scorer proposes the skeleton rows/columns of
+     eq. Ahat (Sec. 5.3) by mesh node.  On each side of a block, dofs at
+     consecutive positions with equal coordinates form one node (at most 8
+     dofs); a node scores the best score of its dofs; with a budget of k
+     picks and longest node g, the side takes the k / g best nodes (at least
+     one, ties to the lower position) with all their dofs.  The skeleton's
+     relative Frobenius error is estimated from 16 whole rows and 16 whole
+     columns outside it (hodlr_sampled_error); a block above skel_tol
+     retries with both budgets doubled, up to 192 (precision 32) / 128
+     (precision 64) picks and at most 4 attempts, all decided on the device.
+     A block that still fails is also compressed by ACA, whose error is
+     estimated on the same samples, and keeps the smaller of the two
+     (hodlr_skel_info). */
+  int skel_k;                /* first budget per side, >= 0; 0 (default) =
+                                the side's BDLR pick count at bdlr_depth */
   const float* mlp_params;   /* device float32, 4801 scorer parameters in the
                                 layout of hodlr_mlp_forward; read during the
                                 call only */
@@ -102,7 +108,7 @@ typedef struct {
 } hodlr_opts;
 
 /* Fill *opts with defaults: leaf 128, tol 1e-4, ACA, depth 1, max_rank 0,
- * precision 32, skel_k 32, mlp_params NULL, seed 0, skel_tol 0,
+ * precision 32, skel_k 0, mlp_params NULL, seed 0, skel_tol 0,
  * bdlr_max_skel 0, bdlr_max_depth 0, symmetric 0. */
 void hodlr_default_opts(hodlr_opts* opts);
 
@@ -120,8 +126,8 @@ void hodlr_default_opts(hodlr_opts* opts);
  *   opts    host; NULL = defaults.
  *   out     host; receives the new handle.
  * Synchronizes the stream once (to size the factor storage from the ranks
- * found; HODLR_LEARNED and the adaptive BDLR depth synchronize once more per
- * size or depth tried).  Errors: EINVAL
+ * found; HODLR_LEARNED synchronizes once more, and twice when a block falls
+ * back; the adaptive BDLR depth once per depth tried).  Errors: EINVAL
  * (n < 1, n > 16384 (every compression keeps a block side <= 8192), ldk < n,
  * NULL K/out, bad opts, BDLR or learned without the graph, learned without
  * coords or parameters), ENOMEM, EHIP. */
@@ -293,6 +299,37 @@ int hodlr_permute_graph(const int* rowptr, const int* col, int n, const int* per
 int hodlr_bdlr_select(const int* g_rowptr, const int* g_col, int n, int leaf, int depth,
                       int max_skel, int* picks, int* counts, hipStream_t stream);
 
+/* Test hook: the sampled error check that HODLR_LEARNED and the adaptive
+ * BDLR depth apply to every block (the error monitor of Sec. 5.3, measured on
+ * rows and columns outside the skeleton), run on given factors and picks.
+ * For the k-th node below the root (level order; node id c = 2^p - 1 + i,
+ * block K(c, sibling), m x nc):
+ *   draws   splitmix64 (Steele, Lea & Flood 2014) from the state
+ *           seed ^ (0xD1B54A32D192ED03 * c) ^ (0x8CB92BA72F3D8DD7 * (attempt+1))
+ *           (mod 2^64); 16 row positions, then 16 column positions, each the
+ *           first 16 steps of a Fisher-Yates shuffle of the side's positions
+ *           outside its picks (ascending), step x swapping entries x and
+ *           x + (next() mod (left - x)); -1 once fewer are left;
+ *   err     sqrt(max(e_r, e_c) / |K(c, sibling)|_F^2), e_r = the squared
+ *           residual of U V^T on the sampled whole rows times (m - rows
+ *           picked) / (rows sampled), e_c likewise over columns; float64.
+ *   K       device n x n float64 (ld ldk).
+ *   Upanel, Vpanel
+ *           device n x R, ld n, float (precision 32) or double (64), in the
+ *           layout of hodlr_build_from_factors; ranks (host, one per node
+ *           below the root) and rcols (host, per level) as there.
+ *   picks, counts
+ *           device, the layout of hodlr_bdlr_select for max_skel (at most
+ *           192 / 128): ascending distinct positions, counts <= max_skel
+ *           and <= the side's length.
+ *   samples device int, 32 per node: 16 rows then 16 columns (out).
+ *   err     device double, one per node (out).
+ * Synchronizes the stream.  Errors: EINVAL, ENOMEM, EHIP. */
+int hodlr_sampled_error(const double* K, int n, int ldk, int leaf, int precision, const void* Upanel,
+                        const void* Vpanel, const int* ranks, const int* rcols, const int* picks,
+                        const int* counts, int max_skel, unsigned long long seed, int attempt, int* samples,
+                        double* err, hipStream_t stream);
+
 /* Introspection (host arrays): number of levels L, ranks of the nodes below
  * the root in level order (capacity 2^(L+1)-2 ints), per-level column widths
  * (capacity L ints).  Any pointer may be NULL. */
@@ -304,7 +341,9 @@ int hodlr_stats(hodlr_t h, int* nlevels, int* ranks, int* rcols);
 int hodlr_get_factors(hodlr_t h, double* Upanel, double* Vpanel, hipStream_t stream);
 
 /* HODLR_LEARNED handles: per node below the root in level order, the
- * skeleton size that passed the check, 0 where the block fell back to ACA.
+ * budget (picks per side, the larger of rows and columns) that passed the
+ * check; for a block that failed at its last budget k, 0 if the ACA
+ * fallback was kept, -k if its own skeleton was (the smaller estimate).
  * Adaptive BDLR handles (bdlr_max_depth > 0): the depth each block ended at.
  * -1 for handles built otherwise.  kused: host, 2^(L+1)-2 ints. */
 int hodlr_skel_info(hodlr_t h, int* kused);
@@ -325,7 +364,7 @@ int hodlr_skel_info(hodlr_t h, int* kused);
  *   |K_vv| / max on S
  *   min(1, distance from v to the bounding box of O / diagonal of S's box)
  * g_rowptr/g_col/coords/K as for hodlr_build; feats: device, 2 n L x 8.
- * Synchronizes.  Errors: EINVAL (2 <= n <= 16384, n > leaf), ENOMEM, EHIP. */
+ * Asynchronous.  Errors: EINVAL (2 <= n <= 16384, n > leaf), ENOMEM, EHIP. */
 int hodlr_skel_features(const int* g_rowptr, const int* g_col, const float* coords, const double* K, int n,
                         int ldk, int leaf, float* feats, hipStream_t stream);
 

@@ -284,25 +284,129 @@ def top_k(scores, k):
     return np.array(sorted(order[:k]), dtype=np.int64)
 
 
-def learned_block(B, row_scores, col_scores, k_first, max_skel, eps, accept, seed=0, node=1,
-                  max_rank=None):
+RUN_MAX = 8
+
+
+def node_runs(coords):
+    """Mesh nodes of one block side: maximal runs of consecutive positions
+    with equal coordinates, at most RUN_MAX positions each (a position with
+    RUN_MAX equal predecessors starts a node of its own).  Returns the list
+    of (first position, length)."""
+    X = np.asarray(coords)
+    m = X.shape[0]
+    runs = []
+    i = 0
+    while i < m:
+        g = 1
+        if i >= RUN_MAX and all(np.array_equal(X[i], X[i - b]) for b in range(1, RUN_MAX + 1)):
+            runs.append((i, 1))  # beyond a full node of equal points
+            i += 1
+            continue
+        while g < RUN_MAX and i + g < m and np.array_equal(X[i + g], X[i]):
+            g += 1
+        runs.append((i, g))
+        i += g
+    return runs
+
+
+def node_picks(scores, coords, budget):
+    """Learned picks of one side by mesh node: a node scores the largest score
+    of its positions; with longest node g the budget // g best nodes (at
+    least one; ties to the lower first position) give all their positions,
+    listed in increasing order."""
+    runs = node_runs(coords)
+    if not runs:
+        return np.zeros(0, dtype=np.int64)
+    longest = max(g for _, g in runs)
+    knode = min(len(runs), max(1, budget // longest))
+    best = [max(scores[p:p + g]) for p, g in runs]
+    order = sorted(range(len(runs)), key=lambda r: (-best[r], runs[r][0]))[:knode]
+    out = []
+    for r in order:
+        p, g = runs[r]
+        out.extend(range(p, p + g))
+    return np.array(sorted(out), dtype=np.int64)
+
+
+def depth_count(indptr, indices, own, other, depth):
+    """Vertices of ``own`` at boundary distance < depth (BDLR's picks at that
+    depth before any cap)."""
+    d = distance_to_boundary(indptr, indices, own, boundary(indptr, indices, own, other))
+    return sum(1 for v in own if d.get(int(v), depth) < depth)
+
+
+LEARNED_ATTEMPTS = 4
+
+
+def learned_block(B, row_scores, col_scores, row_coords, col_coords, budgets, max_skel, eps, accept, seed=0, node=1,
+                  max_rank=None, attempts=LEARNED_ATTEMPTS, fallback=None):
     """Learned proposals for one block (the task's scorer replaces Sec. 5.3's
-    pick by distance): the k best-scoring rows and columns form the skeleton
-    of eq. Ahat; a block above ``accept`` retries with twice k, up to
-    ``max_skel``; attempt a uses k_first * 2^a (capped).  Returns (U, V, k
-    kept, trace); k kept = 0 and U, V = None when no size passed (the caller
-    compresses the block by ACA instead)."""
-    k = max(1, min(k_first, max_skel))
-    attempt, trace = 0, []
-    while True:
-        rows = top_k(row_scores, min(k, max_skel))
-        cols = top_k(col_scores, min(k, max_skel))
+    pick by distance; the error monitor of Sec. 5.3 judges them).
+
+    ``budgets`` = (rows, columns): the first skeleton size per side (capped
+    to [1, min(max_skel, side)]).  Attempt a picks whole mesh nodes by score
+    (node_picks) within the budgets, forms the skeleton of eq. Ahat and
+    checks it (check_skeleton, attempt a); a block at or below ``accept``
+    passes; otherwise both budgets double (capped) and the block retries, and
+    it fails when they cannot grow or after ``attempts`` attempts.  A failed
+    block is compressed by ``fallback(B)`` -> (U, V) (ACA) as well; both
+    approximations are then measured by candidate_error on the skeleton's
+    last picks (exactly) and 16 fresh rows and columns outside them (stream
+    attempt ``attempts``), and the block keeps the smaller.  (A sample of the
+    whole block alone would favour ACA: its error gathers near the boundary,
+    where the picks are.)
+
+    Returns (U, V, kused, trace): kused = the budget that passed, 0 when the
+    fallback is kept, minus the last budget when the failed skeleton is kept.
+    """
+    m, n = B.shape
+    br = max(1, min(budgets[0], max_skel, m))
+    bc = max(1, min(budgets[1], max_skel, n))
+    trace = []
+    for attempt in range(attempts):
+        rows = node_picks(row_scores, row_coords, br)
+        cols = node_picks(col_scores, col_coords, bc)
         U, V = skeleton(B, rows, cols, eps, max_rank)
         err, rs, cs = check_skeleton(B, U, V, rows, cols, seed, node, attempt)
-        trace.append(dict(k=k, nrows=len(rows), ncols=len(cols), rows_s=rs, cols_s=cs, err=err))
+        trace.append(dict(br=br, bc=bc, nrows=len(rows), ncols=len(cols), rows=rows, cols=cols, rows_s=rs,
+                          cols_s=cs, err=err))
         if err <= accept:
-            return U, V, k, trace
-        if k >= max_skel:
-            return None, None, 0, trace
-        k = min(max_skel, 2 * k)
-        attempt += 1
+            return U, V, max(br, bc), trace
+        nr, nc = min(2 * br, max_skel, m), min(2 * bc, max_skel, n)
+        if attempt == attempts - 1 or (nr == br and nc == bc):
+            break
+        br, bc = nr, nc
+    if fallback is None:
+        return U, V, -max(br, bc), trace
+    Uf, Vf = fallback(B)
+    # both candidates on the same positions: the skeleton's last picks,
+    # exactly, and 16 fresh samples per side outside them (stream attempt
+    # ``attempts``), scaled by (outside / sampled)
+    rows, cols = trace[-1]["rows"], trace[-1]["cols"]
+    rng = block_stream(seed, node, attempts)
+    rs = draw_outside(rng, m, rows)
+    cs = draw_outside(rng, n, cols)
+    errs = candidate_error(B, U, V, rows, cols, rs, cs)
+    errf = candidate_error(B, Uf, Vf, rows, cols, rs, cs)
+    trace.append(dict(fallback=True, err=errf, err_skeleton=errs, rows_s=rs, cols_s=cs))
+    if errf < errs:
+        return Uf, Vf, 0, trace
+    return U, V, -max(br, bc), trace
+
+
+def candidate_error(B, U, V, rows, cols, rs, cs):
+    """Relative Frobenius error of U V^T on B estimated from the picked rows
+    and columns (exactly) and the sampled rows and columns outside them
+    (-1 entries ignored; scaled by outside / sampled): the larger side."""
+    m, n = B.shape
+    est = 0.0
+    for picks, samp, length, res in ((rows, rs, m, lambda P: B[P, :] - U[P, :] @ V.T),
+                                     (cols, cs, n, lambda P: B[:, P] - U @ V[P, :].T)):
+        P = [int(x) for x in picks]
+        S = [int(x) for x in samp if x >= 0]
+        e = float(np.sum(res(P) ** 2)) if P else 0.0
+        if S:
+            e += float(np.sum(res(S) ** 2)) * (length - len(P)) / len(S)
+        est = max(est, e)
+    nb = float(np.sum(B * B))
+    return float(np.sqrt(est / nb)) if nb > 0 else float(np.sqrt(est))

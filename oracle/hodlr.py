@@ -46,6 +46,7 @@ class HODLR:
     leaf_lu: dict = field(default_factory=dict)
     d: dict = field(default_factory=dict)        # (p, i) -> K_node^-1 U_node
     S_lu: dict = field(default_factory=dict)     # (p, i) internal node -> lu_factor(S)
+    kused: dict = field(default_factory=dict)    # learned build: (p, i) -> oracle.bdlr.learned_block decision
 
     @property
     def L(self):
@@ -67,12 +68,18 @@ def sibling(i: int) -> int:
 
 
 def from_dense(K: np.ndarray, leaf: int, method="aca", eps=1e-8, max_rank=None,
-               graph=None, depth=1, svd_rank=None, max_skel=None, symmetric=False) -> HODLR:
+               graph=None, depth=1, svd_rank=None, max_skel=None, symmetric=False, coords=None,
+               mlp_params=None, accept=None, seed=0) -> HODLR:
     """Compress every off-diagonal block of K.
 
     method: 'aca' (partial-pivoting ACA), 'bdlr' (needs graph=(indptr, indices)),
     'svd' (truncated SVD at relative 2-norm eps, or fixed ``svd_rank``),
-    'full' (exact, U = block, V = I).
+    'full' (exact, U = block, V = I), 'learned' (the scorer's proposals by
+    mesh node, oracle.bdlr.learned_block: needs graph, coords (n x 3) and
+    mlp_params (the oracle.mlp dictionary); first budgets = the BDLR pick
+    counts at ``depth``, acceptance ``accept`` (default 30 eps), at most
+    ``max_skel`` picks per side, ACA fallback; h.kused records the
+    decisions per node (p, i)).
 
     symmetric: K is symmetric, so only the block of each left child is
     compressed, K(c, s) ~ U_c V_c^T, and its sibling's block is its transpose,
@@ -106,6 +113,23 @@ def from_dense(K: np.ndarray, leaf: int, method="aca", eps=1e-8, max_rank=None,
                 U, V = Us[:, :k] * s[:k], Vt[:k].T
             elif method == "full":
                 U, V = B.copy(), np.eye(shi - slo)
+            elif method == "learned":
+                from . import features as _feat
+                from . import mlp as _mlp
+                indptr, indices = graph
+                I, J = np.arange(lo, hi), np.arange(slo, shi)
+                FI, FJ = _feat.block_features(indptr, indices, coords, np.diag(K), I, J)
+                sr, _ = _mlp.forward(mlp_params, FI)
+                sc, _ = _mlp.forward(mlp_params, FJ)
+                budgets = (_bdlr.depth_count(indptr, indices, I, J, depth),
+                           _bdlr.depth_count(indptr, indices, J, I, depth))
+                cap = min(hi - lo, shi - slo) if max_rank is None else min(max_rank, hi - lo, shi - slo)
+                ms = max(hi - lo, shi - slo) if max_skel is None else max_skel
+                U, V, k, _ = _bdlr.learned_block(B, sr, sc, np.asarray(coords)[I], np.asarray(coords)[J], budgets,
+                                                 ms, eps, 30 * eps if accept is None else accept, seed=seed,
+                                                 node=(1 << p) - 1 + i, max_rank=cap,
+                                                 fallback=lambda A, c=cap: _aca.aca_pp(A, eps, c)[:2])
+                h.kused[(p, i)] = k
             else:
                 raise ValueError(method)
             h.U[(p, i)] = U

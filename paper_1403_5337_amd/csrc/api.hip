@@ -426,7 +426,7 @@ void hodlr_default_opts(hodlr_opts* o) {
   o->bdlr_depth = 1;
   o->max_rank = 0;
   o->precision = 32;
-  o->skel_k = 32;
+  o->skel_k = 0;
   o->mlp_params = nullptr;
   o->seed = 0;
   o->skel_tol = 0.0;
@@ -443,8 +443,10 @@ static int check_opts(const hodlr_opts& o) {
   if (!(o.tol >= 0.0) || !std::isfinite(o.tol)) return fail(HODLR_EINVAL, "opts.tol must be >= 0");
   if (o.method != HODLR_ACA && o.method != HODLR_BDLR && o.method != HODLR_LEARNED)
     return fail(HODLR_EINVAL, "opts.method must be HODLR_ACA, HODLR_BDLR or HODLR_LEARNED");
-  if (o.method == HODLR_LEARNED && (!o.mlp_params || o.skel_k < 1))
-    return fail(HODLR_EINVAL, "HODLR_LEARNED needs opts.mlp_params and opts.skel_k >= 1");
+  if (o.method == HODLR_LEARNED && (!o.mlp_params || o.skel_k < 0))
+    return fail(HODLR_EINVAL, "HODLR_LEARNED needs opts.mlp_params and opts.skel_k >= 0");
+  if (o.method == HODLR_LEARNED && o.skel_k == 0 && (o.bdlr_depth < 1 || o.bdlr_depth > 250))
+    return fail(HODLR_EINVAL, "HODLR_LEARNED with skel_k 0 sizes by opts.bdlr_depth, which must be in [1, 250]");
   if (!(o.skel_tol >= 0.0) || !std::isfinite(o.skel_tol)) return fail(HODLR_EINVAL, "opts.skel_tol must be >= 0");
   if (o.bdlr_max_skel < 0) return fail(HODLR_EINVAL, "opts.bdlr_max_skel must be >= 0");
   if (o.symmetric != 0 && o.symmetric != 1) return fail(HODLR_EINVAL, "opts.symmetric must be 0 or 1");

@@ -337,13 +337,15 @@ template <typename T, int SKEL>
 __global__ void __launch_bounds__(kLuBlock)
     k_bdlr_lu(const double* __restrict__ K, int ldk, const BdlrTask* __restrict__ tasks,
               const int* __restrict__ sel, const int* __restrict__ counts, T eps, int rcap,
-              int* __restrict__ piv_out, int* __restrict__ rank_out, int* __restrict__ rank_task) {
+              int* __restrict__ piv_out, int* __restrict__ rank_out, int* __restrict__ rank_task,
+              const int* __restrict__ skip) {
   static_assert(SKEL % 64 == 0 && SKEL <= 256 && SKEL % kLuWaves == 0, "tile shape");
   __shared__ int srow[SKEL], scol[SKEL], prow[SKEL], pcol[SKEL];
   __shared__ T colv[SKEL];
   __shared__ T sv[2][kLuWaves];
   __shared__ int si[2][kLuWaves], spos[2];
   const int task = blockIdx.x, t = threadIdx.x;
+  if (skip && skip[task]) return;
   const BdlrTask tk = tasks[task];
   const int nr = counts[2 * task], nc = counts[2 * task + 1];
   for (int x = t; x < SKEL; x += blockDim.x) {
@@ -383,9 +385,10 @@ template <typename T, int SKEL>
 __global__ void __launch_bounds__(gj_threads<T>())
     k_bdlr_ginv(const double* __restrict__ K, int ldk, const BdlrTask* __restrict__ tasks,
                 const int* __restrict__ piv, T* __restrict__ inv, int* __restrict__ rank_out,
-                int* __restrict__ rank_task) {
+                int* __restrict__ rank_task, const int* __restrict__ skip) {
   __shared__ GjScratch<T, (sizeof(T) == 8 ? kRankCap64 : kRankCap32)> gw;
   const int task = blockIdx.x, t = threadIdx.x;
+  if (skip && skip[task]) return;
   const BdlrTask tk = tasks[task];
   const int r = rank_task[task];
   if (r == 0) return;
@@ -403,10 +406,11 @@ __global__ void __launch_bounds__(gj_threads<T>())
 // The pivots, then G, of ns blocks.
 template <typename T, int SKEL>
 static int launch_bdlr_lu(const double* K, int ldk, const BdlrTask* tasks, int ns, const int* sel, const int* cnt,
-                          T eps, int rcap, int* piv, T* inv, int* rank_out, int* rank_task, hipStream_t s) {
-  k_bdlr_lu<T, SKEL><<<ns, kLuBlock, 0, s>>>(K, ldk, tasks, sel, cnt, eps, rcap, piv, rank_out, rank_task);
+                          T eps, int rcap, int* piv, T* inv, int* rank_out, int* rank_task, hipStream_t s,
+                          const int* skip = nullptr) {
+  k_bdlr_lu<T, SKEL><<<ns, kLuBlock, 0, s>>>(K, ldk, tasks, sel, cnt, eps, rcap, piv, rank_out, rank_task, skip);
   HODLR_HIP(hipGetLastError());
-  k_bdlr_ginv<T, SKEL><<<ns, gj_threads<T>(), 0, s>>>(K, ldk, tasks, piv, inv, rank_out, rank_task);
+  k_bdlr_ginv<T, SKEL><<<ns, gj_threads<T>(), 0, s>>>(K, ldk, tasks, piv, inv, rank_out, rank_task, skip);
   HODLR_HIP(hipGetLastError());
   return HODLR_OK;
 }
@@ -418,13 +422,19 @@ template <typename T, int SKEL>
 __global__ void __launch_bounds__(kBlock)
     k_bdlr_gather(const double* __restrict__ K, int ldk, const BdlrTask* __restrict__ tasks,
                   const int* __restrict__ piv, const int* __restrict__ rank_task, T* __restrict__ cg,
-                  T* __restrict__ Vcap, int ldu) {
+                  T* __restrict__ Ucap, T* __restrict__ Vcap, int ldu, const int* __restrict__ skip) {
   const int task = blockIdx.x, side = blockIdx.z, t = threadIdx.x;
+  if (skip && skip[task]) return;
   const BdlrTask tk = tasks[task];
   const int r = rank_task[task];
   const int len = side == 0 ? tk.m : tk.nc;
   const int i = blockIdx.y * kBlock + t;
-  if (i >= len || r == 0) return;
+  if (i >= len) return;
+  {  // the factor columns past the rank are zero (an earlier attempt may have written them)
+    T* z = (side == 0 ? Ucap + tk.row0 : Vcap + tk.col0) + (size_t)tk.capcol * ldu + i;
+    for (int l = r; l < tk.kmax; ++l) z[(size_t)l * ldu] = T(0);
+  }
+  if (r == 0) return;
   T* out = side == 0 ? cg + tk.cg_off : Vcap + (size_t)tk.capcol * ldu + tk.col0;
   const int ldo = side == 0 ? len : ldu;
   const int* pv = piv + tk.sel_off + (side == 0 ? SKEL : 0);
@@ -470,10 +480,12 @@ typedef double f64x4 __attribute__((ext_vector_type(4)));
 template <typename T>
 __global__ void __launch_bounds__(kBlock)
     k_bdlr_factors(const BdlrTask* __restrict__ tasks, const int* __restrict__ rank_task,
-                   const T* __restrict__ cg, const T* __restrict__ inv, T* __restrict__ Ucap, int ldu) {
+                   const T* __restrict__ cg, const T* __restrict__ inv, T* __restrict__ Ucap, int ldu,
+                   const int* __restrict__ skip) {
   using S = FactorsSmem<T>;
   __shared__ S sm;
   const int task = blockIdx.x, t = threadIdx.x, lane = t & 63, w = t >> 6;
+  if (skip && skip[task]) return;
   const BdlrTask tk = tasks[task];
   const int r = rank_task[task];
   const int i0 = blockIdx.y * 64, j0 = blockIdx.z * 64;
@@ -606,7 +618,8 @@ static int bdlr_t(hodlr_s* h, const double* K, int ldk, const int* rowptr, const
   {
     ProfScope prof("bdlr_lu", s);
     k_bdlr_lu<T, SKEL><<<nt, kLuBlock, 0, s>>>(K, ldk, d_tasks.as<BdlrTask>(), d_sel.as<int>(), d_cnt.as<int>(),
-                                                (T)h->tol, rcap, d_piv.as<int>(), h->d_rank.as<int>(), d_rt.as<int>());
+                                                (T)h->tol, rcap, d_piv.as<int>(), h->d_rank.as<int>(), d_rt.as<int>(),
+                                                nullptr);
   }
   HODLR_HIP(hipGetLastError());
   // the gather needs only the pivots: it runs on a second stream beside the
@@ -631,21 +644,22 @@ static int bdlr_t(hodlr_s* h, const double* K, int ldk, const int* rowptr, const
   {
     ProfScope prof("bdlr_gather", side);
     k_bdlr_gather<T, SKEL><<<dim3(nt, nch, 2), kBlock, 0, side>>>(K, ldk, d_tasks.as<BdlrTask>(), d_piv.as<int>(),
-                                                                 d_rt.as<int>(), d_cg.as<T>(), Vcap, tr.n);
+                                                                 d_rt.as<int>(), d_cg.as<T>(), Ucap, Vcap, tr.n,
+                                                                 nullptr);
   }
   HODLR_HIP(hipGetLastError());
   HODLR_HIP(hipEventRecord(ev.e[1], side));
   {
     ProfScope prof("bdlr_lu", s);
     k_bdlr_ginv<T, SKEL><<<nt, gj_threads<T>(), 0, s>>>(K, ldk, d_tasks.as<BdlrTask>(), d_piv.as<int>(), d_inv.as<T>(),
-                                               h->d_rank.as<int>(), d_rt.as<int>());
+                                               h->d_rank.as<int>(), d_rt.as<int>(), nullptr);
   }
   HODLR_HIP(hipGetLastError());
   HODLR_HIP(hipStreamWaitEvent(s, ev.e[1], 0));
   {
     ProfScope prof("bdlr_factors", s);
     k_bdlr_factors<T><<<dim3(nt, (maxside + 63) / 64, (rcap + 63) / 64), kBlock, 0, s>>>(
-        d_tasks.as<BdlrTask>(), d_rt.as<int>(), d_cg.as<T>(), d_inv.as<T>(), Ucap, tr.n);
+        d_tasks.as<BdlrTask>(), d_rt.as<int>(), d_cg.as<T>(), d_inv.as<T>(), Ucap, tr.n, nullptr);
   }
   HODLR_HIP(hipGetLastError());
   if (piv_export)
@@ -721,21 +735,6 @@ __device__ void topk_side(const unsigned* key, int len, int k, int* out, int* co
   __syncthreads();
 }
 
-__global__ void __launch_bounds__(kBlock)
-    k_skel_topk(const float* __restrict__ score, const BdlrTask* __restrict__ tasks, int kk, int skel,
-                int* __restrict__ sel, int* __restrict__ counts) {
-  __shared__ unsigned key[kBdlrMaxSide];
-  __shared__ int buf[kBlock], red[kBlock / 64];
-  const BdlrTask tk = tasks[blockIdx.x];
-  for (int side = 0; side < 2; ++side) {
-    const int len = side == 0 ? tk.m : tk.nc, off = tk.samp0 + (side == 0 ? 0 : tk.m);
-    for (int i = threadIdx.x; i < len; i += kBlock) key[i] = score_key(score[off + i]);
-    __syncthreads();
-    topk_side(key, len, min(kk, min(len, skel)), sel + tk.sel_off + side * skel, counts + 2 * blockIdx.x + side,
-              buf, red);
-  }
-}
-
 // |K(I, J)|_F^2 of every block, in kNormChunks column chunks per block; a
 // thread keeps four loads in flight (a chunk is read as one flat range of
 // column-major entries).
@@ -770,10 +769,11 @@ __global__ void __launch_bounds__(kBlock)
 // task of the whole list (BdlrTask::task), kNormChunks partial sums of
 // |K(I, J)|_F^2.
 //
-// k_skel_check: workgroup (task, chunk) sums the squared residual of the
-// sampled rows over its chunk of the columns (and of the sampled columns
+// k_skel_check: workgroup (task, chunk, group) sums the squared residual of
+// the group's rows over its chunk of the columns (and of the group's columns
 // over its chunk of the rows) into part; the other factor's entries are
-// loaded 8 at a time.  k_skel_err then adds a task's chunks in order and
+// loaded 8 at a time.  A task has gridDim.z groups of 2 ns positions (one
+// group: the samples).  k_skel_err then adds a task's chunks in order and
 // forms the estimate, so the result does not depend on timing.
 constexpr int kCheckChunks = 16;
 
@@ -781,14 +781,17 @@ template <typename T>
 __global__ void __launch_bounds__(kBlock)
     k_skel_check(const double* __restrict__ K, int ldk, const BdlrTask* __restrict__ tasks,
                  const int* __restrict__ rank_task, const T* __restrict__ Ucap, const T* __restrict__ Vcap,
-                 int ldu, const int* __restrict__ samp, int ns, double* __restrict__ part) {
+                 int ldu, const int* __restrict__ samp, int ns, double* __restrict__ part,
+                 const int* __restrict__ skip) {
   constexpr int RC = sizeof(T) == 8 ? kRankCap64 : kRankCap32, NS = 16, kL = 8;
   __shared__ T uv[NS][RC];
   __shared__ int sp[2 * NS];
   __shared__ double red[kBlock / 64];
+  if (skip && skip[blockIdx.x]) return;
   const BdlrTask tk = tasks[blockIdx.x];
   const int r = rank_task[blockIdx.x], t = threadIdx.x;
-  if (t < 2 * NS) sp[t] = (t % NS) < ns ? samp[(size_t)blockIdx.x * 2 * ns + (t / NS) * ns + t % NS] : -1;
+  const size_t grp = (size_t)blockIdx.x * gridDim.z + blockIdx.z;  // position group of this task
+  if (t < 2 * NS) sp[t] = (t % NS) < ns ? samp[grp * 2 * ns + (t / NS) * ns + t % NS] : -1;
   __syncthreads();
   const T* U = Ucap + (size_t)tk.capcol * ldu;
   const T* V = Vcap + (size_t)tk.capcol * ldu;
@@ -837,16 +840,17 @@ __global__ void __launch_bounds__(kBlock)
         if (sp[side * NS + q] >= 0) num += (b[q] - a[q]) * (b[q] - a[q]);
     }
     num = block_sum(num, red);
-    if (t == 0) part[((size_t)blockIdx.x * kCheckChunks + blockIdx.y) * 2 + side] = num;
+    if (t == 0) part[(grp * kCheckChunks + blockIdx.y) * 2 + side] = num;
     __syncthreads();
   }
 }
 
 __global__ void k_skel_err(const BdlrTask* __restrict__ tasks, int ntask, const int* __restrict__ counts,
                            const double* __restrict__ norm2, const int* __restrict__ samp, int ns,
-                           const double* __restrict__ part, double* __restrict__ err) {
+                           const double* __restrict__ part, double* __restrict__ err,
+                           const int* __restrict__ skip) {
   const int x = blockIdx.x * blockDim.x + threadIdx.x;
-  if (x >= ntask) return;
+  if (x >= ntask || (skip && skip[x])) return;
   const BdlrTask tk = tasks[x];
   double est = 0.0;
   for (int side = 0; side < 2; ++side) {
@@ -928,9 +932,11 @@ __device__ void draw_side(unsigned long long& st, int len, const int* picked, in
 constexpr int kDrawPicks = 256;  // >= the largest skeleton (192 / 128)
 __global__ void __launch_bounds__(64)
     k_draw_samples(const BdlrTask* __restrict__ tasks, const int* __restrict__ sel, const int* __restrict__ cnt,
-                   int skel, unsigned long long seed, int attempt, int ns, int* __restrict__ samp) {
+                   int skel, unsigned long long seed, int attempt, int ns, int* __restrict__ samp,
+                   const int* __restrict__ skip) {
   __shared__ int pk[2][kDrawPicks];
   const int x = blockIdx.x, t = threadIdx.x;
+  if (skip && skip[x]) return;
   const BdlrTask tk = tasks[x];
   const int nr = min(cnt[2 * x], kDrawPicks), nc = min(cnt[2 * x + 1], kDrawPicks);
   for (int i = t; i < nr; i += 64) pk[0][i] = sel[tk.sel_off + i];
@@ -973,56 +979,286 @@ static int block_norms(const double* K, int ldk, const std::vector<BdlrTask>& ta
   return HODLR_OK;
 }
 
-// One attempt over the ns blocks of sub, whose picks are in sc.sel / sc.cnt
-// and whose tasks are in sc.tasks: the pivot-block LU and inverse, the
-// factors into Ucap / Vcap, then the sampled error of every block (samples
-// drawn outside its picks from a stream seeded by the block and the attempt)
-// into err; the pick counts (rows, columns per block) into cnt.  The samples
-// are drawn on the device; the stream is synchronized once, for the errors
-// and counts that decide the next attempt.
+// One attempt over the ns blocks whose tasks are in sc.tasks and picks in
+// sc.sel / sc.cnt: the pivot-block LU and inverse, the factors into Ucap /
+// Vcap, then the sampled error of every block (samples drawn on the device
+// outside its picks, from a stream seeded by the block and the attempt) into
+// sc.err.  Blocks with skip[x] != 0 (skip may be NULL) are left untouched.
 template <typename T, int SKEL>
-static int skel_attempt(hodlr_s* h, const double* K, int ldk, const std::vector<BdlrTask>& sub, int maxside,
-                        SkelScratch& sc, T* Ucap, T* Vcap, unsigned long long seed, int attempt,
-                        std::vector<double>& err, std::vector<int>& cnt, hipStream_t s) {
+static int skel_attempt_launch(hodlr_s* h, const double* K, int ldk, int ns, int maxside, SkelScratch& sc, T* Ucap,
+                               T* Vcap, unsigned long long seed, int attempt, const int* skip, hipStream_t s) {
   const Tree& tr = h->tree;
-  const int ns = (int)sub.size();
   const int rcap = h->precision == 64 ? kRankCap64 : kRankCap32;
   {
     ProfScope prof("bdlr_lu", s);
     HODLR_TRY((launch_bdlr_lu<T, SKEL>(K, ldk, sc.tasks.as<BdlrTask>(), ns, sc.sel.as<int>(), sc.cnt.as<int>(),
                                        (T)h->tol, rcap, sc.piv.as<int>(), sc.inv.as<T>(), h->d_rank.as<int>(),
-                                       sc.rt.as<int>(), s)));
+                                       sc.rt.as<int>(), s, skip)));
   }
   const int nch = (maxside + kBlock - 1) / kBlock;
   {
     ProfScope prof("bdlr_gather", s);
     k_bdlr_gather<T, SKEL><<<dim3(ns, nch, 2), kBlock, 0, s>>>(K, ldk, sc.tasks.as<BdlrTask>(), sc.piv.as<int>(),
-                                                              sc.rt.as<int>(), sc.cg.as<T>(), Vcap, tr.n);
+                                                              sc.rt.as<int>(), sc.cg.as<T>(), Ucap, Vcap, tr.n, skip);
     k_bdlr_factors<T><<<dim3(ns, (maxside + 63) / 64, (rcap + 63) / 64), kBlock, 0, s>>>(
-        sc.tasks.as<BdlrTask>(), sc.rt.as<int>(), sc.cg.as<T>(), sc.inv.as<T>(), Ucap, tr.n);
+        sc.tasks.as<BdlrTask>(), sc.rt.as<int>(), sc.cg.as<T>(), sc.inv.as<T>(), Ucap, tr.n, skip);
   }
   HODLR_HIP(hipGetLastError());
-  // the samples outside the picks, drawn on the device
   static_assert(SKEL <= kDrawPicks, "the picks of a side must fit the sampler's LDS");
   k_draw_samples<<<ns, 64, 0, s>>>(sc.tasks.as<BdlrTask>(), sc.sel.as<int>(), sc.cnt.as<int>(), SKEL, seed, attempt,
-                                   kSkelSamples, sc.samp.as<int>());
+                                   kSkelSamples, sc.samp.as<int>(), skip);
   HODLR_HIP(hipGetLastError());
   {
     ProfScope prof("skel_check", s);
     k_skel_check<T><<<dim3(ns, kCheckChunks), kBlock, 0, s>>>(K, ldk, sc.tasks.as<BdlrTask>(), sc.rt.as<int>(),
                                                                Ucap, Vcap, tr.n, sc.samp.as<int>(), kSkelSamples,
-                                                               sc.part.as<double>());
+                                                               sc.part.as<double>(), skip);
     k_skel_err<<<(ns + kBlock - 1) / kBlock, kBlock, 0, s>>>(sc.tasks.as<BdlrTask>(), ns, sc.cnt.as<int>(),
                                                             sc.norm.as<double>(), sc.samp.as<int>(), kSkelSamples,
-                                                            sc.part.as<double>(), sc.err.as<double>());
+                                                            sc.part.as<double>(), sc.err.as<double>(), skip);
   }
   HODLR_HIP(hipGetLastError());
+  return HODLR_OK;
+}
+
+// skel_attempt_launch for every block of sub, then the errors and pick counts
+// (rows, columns per block) to the host: one stream synchronization.
+template <typename T, int SKEL>
+static int skel_attempt(hodlr_s* h, const double* K, int ldk, const std::vector<BdlrTask>& sub, int maxside,
+                        SkelScratch& sc, T* Ucap, T* Vcap, unsigned long long seed, int attempt,
+                        std::vector<double>& err, std::vector<int>& cnt, hipStream_t s) {
+  const int ns = (int)sub.size();
+  HODLR_TRY((skel_attempt_launch<T, SKEL>(h, K, ldk, ns, maxside, sc, Ucap, Vcap, seed, attempt, nullptr, s)));
   err.assign(ns, 0.0);
   cnt.assign(2 * ns, 0);
   HODLR_HIP(hipMemcpyAsync(err.data(), sc.err.p, ns * sizeof(double), hipMemcpyDeviceToHost, s));
   HODLR_HIP(hipMemcpyAsync(cnt.data(), sc.cnt.p, 2 * ns * sizeof(int), hipMemcpyDeviceToHost, s));
   HODLR_HIP(hipStreamSynchronize(s));
   return HODLR_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Learned proposals, decided on the device.  State per block: 0 pending, 1
+// accepted, 2 failed (the largest size tried is above the acceptance); the
+// per-side budgets (rows, columns) double after every failing attempt, up to
+// the skeleton cap; kused: the budget that passed.
+// ---------------------------------------------------------------------------
+constexpr int kLearnedAttempts = 4;
+
+// First budgets: kinit per side, or (kinit == 0) the side's BDLR pick count
+// at the build's depth (dcount), at least 1 and at most the cap and the side.
+__global__ void k_learned_init(const BdlrTask* __restrict__ tasks, int nt, const int* __restrict__ dcount, int kinit,
+                               int skel, int* __restrict__ budget, int* __restrict__ state,
+                               int* __restrict__ kused) {
+  const int x = blockIdx.x * blockDim.x + threadIdx.x;
+  if (x >= nt) return;
+  const BdlrTask tk = tasks[x];
+  for (int sd = 0; sd < 2; ++sd) {
+    const int len = sd == 0 ? tk.m : tk.nc;
+    const int k0 = kinit > 0 ? kinit : dcount[2 * x + sd];
+    budget[2 * x + sd] = max(1, min(k0, min(skel, len)));
+  }
+  state[x] = 0;
+  kused[x] = 0;
+}
+
+// After an attempt: a pending block passes at err <= accept; otherwise its
+// budgets double (capped), and it fails when they cannot grow or on the last
+// attempt.
+__global__ void k_learned_decide(const BdlrTask* __restrict__ tasks, int nt, const double* __restrict__ err,
+                                 double accept, int skel, int last, int* __restrict__ budget, int* __restrict__ state,
+                                 int* __restrict__ kused) {
+  const int x = blockIdx.x * blockDim.x + threadIdx.x;
+  if (x >= nt || state[x] != 0) return;
+  const BdlrTask tk = tasks[x];
+  const int br = budget[2 * x], bc = budget[2 * x + 1];
+  if (err[x] <= accept) {
+    state[x] = 1;
+    kused[x] = max(br, bc);
+    return;
+  }
+  const int nr = min(2 * br, min(skel, tk.m)), nc = min(2 * bc, min(skel, tk.nc));
+  if (last || (nr == br && nc == bc)) {
+    state[x] = 2;
+    kused[x] = -max(br, bc);
+    return;
+  }
+  budget[2 * x] = nr;
+  budget[2 * x + 1] = nc;
+}
+
+// Learned picks by mesh node.  On each side, dofs at consecutive positions
+// with equal coordinates form one node (at most kRunMax dofs: later equal
+// positions count as nodes of their own); a node scores the largest score of
+// its dofs.  A side with budget k and longest node of g dofs takes the k / g
+// best nodes (ties to the lower first position) and lists all their dofs in
+// increasing position, so at most k picks.
+constexpr int kRunMax = 8;
+
+__device__ __forceinline__ bool same_point(const float* __restrict__ xyz, int u, int v) {
+  return xyz[3 * u] == xyz[3 * v] && xyz[3 * u + 1] == xyz[3 * v + 1] && xyz[3 * u + 2] == xyz[3 * v + 2];
+}
+
+__global__ void __launch_bounds__(kBlock)
+    k_skel_topk_nodes(const float* __restrict__ score, const float* __restrict__ xyz,
+                      const BdlrTask* __restrict__ tasks, const int* __restrict__ budget,
+                      const int* __restrict__ skip, int skel, int* __restrict__ sel, int* __restrict__ counts) {
+  __shared__ unsigned key[kBdlrMaxSide];
+  __shared__ unsigned char run[kBdlrMaxSide];  // dofs of the node starting here, 0 elsewhere
+  __shared__ unsigned char flag[kBdlrMaxSide];
+  __shared__ int chosen[kDrawPicks];
+  __shared__ int buf[kBlock], red[kBlock / 64];
+  __shared__ int s_nchosen;
+  const int x = blockIdx.x, t = threadIdx.x;
+  if (skip && skip[x]) return;
+  const BdlrTask tk = tasks[x];
+  for (int side = 0; side < 2; ++side) {
+    const int len = side == 0 ? tk.m : tk.nc, v0 = side == 0 ? tk.row0 : tk.col0;
+    const int off = tk.samp0 + (side == 0 ? 0 : tk.m);
+    int longest = 0, nstart = 0;
+    for (int i = t; i < len; i += kBlock) {
+      int back = 0;  // equal predecessors, counted up to kRunMax
+      while (back < kRunMax && i - back - 1 >= 0 && same_point(xyz, v0 + i, v0 + i - back - 1)) ++back;
+      const bool start = back == 0 || back >= kRunMax;
+      int g = 0;
+      float best = -INFINITY;
+      if (start) {
+        g = 1;
+        best = score[off + i];
+        while (g < kRunMax && i + g < len && same_point(xyz, v0 + i, v0 + i + g)) {
+          // a dof with kRunMax equal predecessors starts a node of its own
+          int b2 = 0;
+          while (b2 < kRunMax && i + g - b2 - 1 >= 0 && same_point(xyz, v0 + i + g, v0 + i + g - b2 - 1)) ++b2;
+          if (b2 >= kRunMax) break;
+          best = fmaxf(best, score[off + i + g]);
+          ++g;
+        }
+      }
+      run[i] = (unsigned char)g;
+      flag[i] = 0;
+      key[i] = start ? max(score_key(best), 1u) : 0u;
+      longest = max(longest, g);
+      nstart += start ? 1 : 0;
+    }
+    for (int o = 32; o > 0; o >>= 1) longest = max(longest, __shfl_xor(longest, o, 64));
+    __syncthreads();
+    if ((t & 63) == 0) red[t >> 6] = longest;
+    __syncthreads();
+    longest = 0;
+    for (int w = 0; w < kBlock / 64; ++w) longest = max(longest, red[w]);
+    nstart = block_count(nstart, red);  // (block_count ends with a barrier)
+    const int k = min(budget[2 * x + side], min(skel, len));
+    const int knode = min(nstart, max(1, k / max(1, longest)));
+    topk_side(key, len, knode, chosen, &s_nchosen, buf, red);
+    const int nch = s_nchosen;
+    for (int c = t; c < nch; c += kBlock) {
+      const int p = chosen[c];
+      for (int j = 0; j < run[p]; ++j) flag[p + j] = 1;
+    }
+    __syncthreads();
+    // the flagged positions in increasing order
+    const int seg = (len + kBlock - 1) / kBlock, b0 = min(len, t * seg), b1 = min(len, b0 + seg);
+    int nf = 0, tot;
+    for (int i = b0; i < b1; ++i) nf += flag[i];
+    int pos = block_exclusive_scan(nf, buf, &tot);
+    int* out = sel + tk.sel_off + side * skel;
+    for (int i = b0; i < b1; ++i)
+      if (flag[i]) out[pos++] = i;
+    if (t == 0) counts[2 * x + side] = tot;
+    __syncthreads();
+  }
+}
+
+// The per-task rank of the fallback (ACA) approximation of failed blocks,
+// and the skip mask of the blocks that did not fail.
+__global__ void k_fallback_prep(const BdlrTask* __restrict__ tasks, int nt, const int* __restrict__ state,
+                                const int* __restrict__ rank, int* __restrict__ rank2, int* __restrict__ skip2) {
+  const int x = blockIdx.x * blockDim.x + threadIdx.x;
+  if (x >= nt) return;
+  const bool failed = state[x] == 2;
+  skip2[x] = failed ? 0 : 1;
+  rank2[x] = failed ? rank[tasks[x].node] : 0;
+}
+
+// A failed block keeps the approximation with the smaller sampled error: the
+// fallback's (its factors copied from U2 / V2, the rank it wrote) or its own
+// last skeleton (whose rank is restored); kused then is 0 or minus the size.
+template <typename T>
+__global__ void __launch_bounds__(kBlock)
+    k_fallback_choose(const BdlrTask* __restrict__ tasks, const int* __restrict__ state,
+                      const double* __restrict__ err, const double* __restrict__ err2,
+                      const int* __restrict__ rank_task, const T* __restrict__ U2, const T* __restrict__ V2,
+                      T* __restrict__ Ucap, T* __restrict__ Vcap, int ldu, int* __restrict__ rank,
+                      int* __restrict__ kused) {
+  const int x = blockIdx.x, t = threadIdx.x;
+  if (state[x] != 2) return;
+  const BdlrTask tk = tasks[x];
+  const bool aca = err2[x] < err[x];
+  if (!aca) {
+    if (t == 0) rank[tk.node] = rank_task[x];
+    return;
+  }
+  if (t == 0) kused[x] = 0;
+  for (int side = 0; side < 2; ++side) {
+    const int len = side == 0 ? tk.m : tk.nc, r0 = side == 0 ? tk.row0 : tk.col0;
+    const T* src = (side == 0 ? U2 : V2) + (size_t)tk.capcol * ldu + r0;
+    T* dst = (side == 0 ? Ucap : Vcap) + (size_t)tk.capcol * ldu + r0;
+    for (int e = blockIdx.y * kBlock + t; e < len * tk.kmax; e += gridDim.y * kBlock) {
+      const int i = e % len, l = e / len;
+      dst[i + (size_t)l * ldu] = src[i + (size_t)l * ldu];
+    }
+  }
+}
+
+// The fallback's comparison: each candidate's squared residual, exact on the
+// rows (columns) the skeleton picked plus the sampled rows (columns) outside
+// them scaled by (outside / sampled), over |K(I, J)|_F^2, the larger of the
+// two sides.  Positions per task: G groups of 2 x 16 (rows, then columns):
+// groups 0 .. G-2 hold the picks 16 at a time, group G-1 the samples.
+__global__ void k_cand_positions(const BdlrTask* __restrict__ tasks, int nt, const int* __restrict__ sel,
+                                 const int* __restrict__ cnt, int skel, const int* __restrict__ samp, int G,
+                                 const int* __restrict__ skip, int* __restrict__ pos) {
+  const int x = blockIdx.x, t = threadIdx.x;
+  if (x >= nt || (skip && skip[x])) return;
+  const BdlrTask tk = tasks[x];
+  for (int e = t; e < G * 2 * kSkelSamples; e += blockDim.x) {
+    const int g = e / (2 * kSkelSamples), side = (e / kSkelSamples) & 1, q = e % kSkelSamples;
+    int v;
+    if (g == G - 1) {
+      v = samp[(size_t)x * 2 * kSkelSamples + side * kSkelSamples + q];
+    } else {
+      const int k = 16 * g + q;
+      v = k < cnt[2 * x + side] ? sel[tk.sel_off + side * skel + k] : -1;
+    }
+    pos[(size_t)x * G * 2 * kSkelSamples + e] = v;
+  }
+}
+
+__global__ void k_cand_err(const BdlrTask* __restrict__ tasks, int nt, const int* __restrict__ cnt,
+                           const double* __restrict__ norm2, const int* __restrict__ pos, int G,
+                           const double* __restrict__ part, const int* __restrict__ skip, double* __restrict__ err) {
+  const int x = blockIdx.x * blockDim.x + threadIdx.x;
+  if (x >= nt || (skip && skip[x])) return;
+  const BdlrTask tk = tasks[x];
+  double est = 0.0;
+  for (int side = 0; side < 2; ++side) {
+    double exact = 0.0, sampled = 0.0;
+    for (int g = 0; g < G; ++g)
+      for (int c = 0; c < kCheckChunks; ++c) {
+        const double v = part[(((size_t)x * G + g) * kCheckChunks + c) * 2 + side];
+        if (g == G - 1) sampled += v;
+        else exact += v;
+      }
+    int used = 0;
+    for (int q = 0; q < kSkelSamples; ++q)
+      used += pos[((size_t)x * G + G - 1) * 2 * kSkelSamples + side * kSkelSamples + q] >= 0;
+    const int outside = (side == 0 ? tk.m : tk.nc) - cnt[2 * x + side];
+    const double e = exact + (used > 0 ? sampled * (double)outside / (double)used : 0.0);
+    est = fmax(est, e);
+  }
+  double nb = 0.0;
+  for (int c = 0; c < kNormChunks; ++c) nb += norm2[(size_t)tk.task * kNormChunks + c];
+  err[x] = nb > 0.0 ? sqrt(est / nb) : sqrt(est);
 }
 
 template <typename T, int SKEL>
@@ -1039,57 +1275,112 @@ static int learned_t(hodlr_s* h, const double* K, int ldk, const int* rowptr, co
   const int N = 2 * tr.n * tr.L;  // every vertex is a row of one block and a column of another, per level
   int maxside = 0;
   for (auto& tk : tasks) maxside = std::max(maxside, std::max(tk.m, tk.nc));
-  DevBuf d_feat, d_score;
+  DevBuf d_feat, d_score, d_dcnt, d_budget, d_state, d_kused;
   HODLR_TRY(d_feat.ensure((size_t)N * 8 * sizeof(float)));
   HODLR_TRY(d_score.ensure((size_t)N * sizeof(float)));
+  HODLR_TRY(d_dcnt.ensure((size_t)2 * nt * sizeof(int)));
+  HODLR_TRY(d_budget.ensure((size_t)2 * nt * sizeof(int)));
+  HODLR_TRY(d_state.ensure((size_t)nt * sizeof(int)));
+  HODLR_TRY(d_kused.ensure((size_t)nt * sizeof(int)));
   SkelScratch sc;
   HODLR_TRY(sc.ensure(nt, selo, invo, cgo, sizeof(T)));
-  HODLR_TRY(block_norms(K, ldk, tasks, sc, s));
+  HODLR_TRY(block_norms(K, ldk, tasks, sc, s));  // also uploads the task table to sc.tasks
   {
     ProfScope prof("skel_features", s);
-    HODLR_TRY(launch_skel_features(rowptr, col, xyz, K, ldk, blocks, d_feat.as<float>(), s));
+    HODLR_TRY(launch_skel_features(rowptr, col, xyz, K, ldk, blocks, d_feat.as<float>(), s, h->depth,
+                                   d_dcnt.as<int>()));
   }
   {
     ProfScope prof("skel_score", s);
     HODLR_TRY(launch_mlp_forward(d_feat.as<float>(), N, params, 1, d_score.as<float>(), s));
   }
   HODLR_HIP(hipMemsetAsync(h->d_rank.p, 0, tr.nnodes() * sizeof(int), s));
-  h->skel_k.assign(tr.nnodes(), -1);
-  std::vector<int> pending(nt);
-  for (int x = 0; x < nt; ++x) pending[x] = x;
-  int kk = std::max(1, std::min(kinit, SKEL));
-  std::vector<double> err;
-  std::vector<int> cnt;
-  for (int attempt = 0;; ++attempt) {
-    std::vector<BdlrTask> sub;
-    for (int x : pending) sub.push_back(tasks[x]);
-    const int ns = (int)sub.size();
-    HODLR_HIP(hipMemcpyAsync(sc.tasks.p, sub.data(), ns * sizeof(BdlrTask), hipMemcpyHostToDevice, s));
+  const int g1 = (nt + kBlock - 1) / kBlock;
+  k_learned_init<<<g1, kBlock, 0, s>>>(sc.tasks.as<BdlrTask>(), nt, d_dcnt.as<int>(), kinit, SKEL,
+                                       d_budget.as<int>(), d_state.as<int>(), d_kused.as<int>());
+  HODLR_HIP(hipGetLastError());
+  // every attempt is queued at once; blocks already decided skip its kernels
+  for (int attempt = 0; attempt < kLearnedAttempts; ++attempt) {
     {
       ProfScope prof("skel_topk", s);
-      k_skel_topk<<<ns, kBlock, 0, s>>>(d_score.as<float>(), sc.tasks.as<BdlrTask>(), kk, SKEL, sc.sel.as<int>(),
-                                        sc.cnt.as<int>());
+      k_skel_topk_nodes<<<nt, kBlock, 0, s>>>(d_score.as<float>(), xyz, sc.tasks.as<BdlrTask>(), d_budget.as<int>(),
+                                              d_state.as<int>(), SKEL, sc.sel.as<int>(), sc.cnt.as<int>());
     }
     HODLR_HIP(hipGetLastError());
-    HODLR_TRY((skel_attempt<T, SKEL>(h, K, ldk, sub, maxside, sc, Ucap, Vcap, seed, attempt, err, cnt, s)));
-    std::vector<int> next;
-    for (int x = 0; x < ns; ++x) {
-      if (err[x] <= accept) h->skel_k[sub[x].node] = kk;
-      else next.push_back(pending[x]);
-    }
-    pending.swap(next);
-    if (pending.empty() || kk >= SKEL) break;
-    kk = std::min(SKEL, 2 * kk);
+    HODLR_TRY((skel_attempt_launch<T, SKEL>(h, K, ldk, nt, maxside, sc, Ucap, Vcap, seed, attempt,
+                                            d_state.as<int>(), s)));
+    k_learned_decide<<<g1, kBlock, 0, s>>>(sc.tasks.as<BdlrTask>(), nt, sc.err.as<double>(), accept, SKEL,
+                                           attempt == kLearnedAttempts - 1 ? 1 : 0, d_budget.as<int>(),
+                                           d_state.as<int>(), d_kused.as<int>());
+    HODLR_HIP(hipGetLastError());
   }
-  if (!pending.empty()) {
-    std::vector<int> nodes;
-    for (int x : pending) {
-      nodes.push_back(tasks[x].node);
-      h->skel_k[tasks[x].node] = 0;
+  std::vector<int> state(nt), kused(nt);
+  HODLR_HIP(hipMemcpyAsync(state.data(), d_state.p, nt * sizeof(int), hipMemcpyDeviceToHost, s));
+  HODLR_HIP(hipMemcpyAsync(kused.data(), d_kused.p, nt * sizeof(int), hipMemcpyDeviceToHost, s));
+  HODLR_HIP(hipStreamSynchronize(s));
+  std::vector<int> nodes;
+  for (int x = 0; x < nt; ++x)
+    if (state[x] == 2) nodes.push_back(tasks[x].node);
+  if (!nodes.empty()) {
+    // fallback: ACA on the failed blocks into panels of their own; the block
+    // keeps whichever of the two approximations has the smaller estimate
+    int C = 0;
+    for (int q = 0; q < tr.L; ++q) C = std::max(C, capoff[q] + cap[q]);
+    DevBuf U2, V2, rank2, skip2, err2, pos2, part2;
+    {
+      constexpr int G = (SKEL + kSkelSamples - 1) / kSkelSamples + 1;
+      HODLR_TRY(pos2.ensure((size_t)nt * G * 2 * kSkelSamples * sizeof(int)));
+      HODLR_TRY(part2.ensure((size_t)nt * G * kCheckChunks * 2 * sizeof(double)));
     }
-    HODLR_TRY(launch_aca(h, K, ldk, Ucap, Vcap, capoff, cap, s, &nodes));
+    HODLR_TRY(U2.ensure((size_t)tr.n * C * sizeof(T)));
+    HODLR_TRY(V2.ensure((size_t)tr.n * C * sizeof(T)));
+    HODLR_TRY(rank2.ensure((size_t)nt * sizeof(int)));
+    HODLR_TRY(skip2.ensure((size_t)nt * sizeof(int)));
+    HODLR_TRY(err2.ensure((size_t)nt * sizeof(double)));
+    HODLR_HIP(hipMemsetAsync(U2.p, 0, (size_t)tr.n * C * sizeof(T), s));
+    HODLR_HIP(hipMemsetAsync(V2.p, 0, (size_t)tr.n * C * sizeof(T), s));
+    HODLR_TRY(launch_aca(h, K, ldk, U2.p, V2.p, capoff, cap, s, &nodes));
+    k_fallback_prep<<<g1, kBlock, 0, s>>>(sc.tasks.as<BdlrTask>(), nt, d_state.as<int>(), h->d_rank.as<int>(),
+                                          rank2.as<int>(), skip2.as<int>());
+    HODLR_HIP(hipGetLastError());
+    // both candidates measured on the same positions: the skeleton's last
+    // picks (exactly) and 16 fresh samples per side outside them (stream
+    // attempt kLearnedAttempts, scaled); a sample of the whole block alone
+    // would favour ACA, whose error gathers near the boundary the picks cover
+    k_draw_samples<<<nt, 64, 0, s>>>(sc.tasks.as<BdlrTask>(), sc.sel.as<int>(), sc.cnt.as<int>(), SKEL, seed,
+                                     kLearnedAttempts, kSkelSamples, sc.samp.as<int>(), skip2.as<int>());
+    HODLR_HIP(hipGetLastError());
+    constexpr int G = (SKEL + kSkelSamples - 1) / kSkelSamples + 1;
+    k_cand_positions<<<nt, 256, 0, s>>>(sc.tasks.as<BdlrTask>(), nt, sc.sel.as<int>(), sc.cnt.as<int>(), SKEL,
+                                        sc.samp.as<int>(), G, skip2.as<int>(), pos2.as<int>());
+    HODLR_HIP(hipGetLastError());
+    {
+      ProfScope prof("skel_check", s);
+      for (int cand = 0; cand < 2; ++cand) {
+        k_skel_check<T><<<dim3(nt, kCheckChunks, G), kBlock, 0, s>>>(
+            K, ldk, sc.tasks.as<BdlrTask>(), cand ? rank2.as<int>() : sc.rt.as<int>(), cand ? U2.as<T>() : Ucap,
+            cand ? V2.as<T>() : Vcap, tr.n, pos2.as<int>(), kSkelSamples, part2.as<double>(), skip2.as<int>());
+        k_cand_err<<<g1, kBlock, 0, s>>>(sc.tasks.as<BdlrTask>(), nt, sc.cnt.as<int>(), sc.norm.as<double>(),
+                                         pos2.as<int>(), G, part2.as<double>(), skip2.as<int>(),
+                                         cand ? err2.as<double>() : sc.err.as<double>());
+      }
+    }
+    HODLR_HIP(hipGetLastError());
+    k_fallback_choose<T><<<dim3(nt, 8), kBlock, 0, s>>>(sc.tasks.as<BdlrTask>(), d_state.as<int>(),
+                                                        sc.err.as<double>(), err2.as<double>(), sc.rt.as<int>(),
+                                                        U2.as<T>(), V2.as<T>(), Ucap, Vcap, tr.n,
+                                                        h->d_rank.as<int>(), d_kused.as<int>());
+    HODLR_HIP(hipGetLastError());
+    HODLR_HIP(hipMemcpyAsync(kused.data(), d_kused.p, nt * sizeof(int), hipMemcpyDeviceToHost, s));
+    HODLR_HIP(hipStreamSynchronize(s));
   }
-  HODLR_HIP(hipStreamSynchronize(s));  // scratch goes back to the allocator cache
+  h->skel_k.assign(tr.nnodes(), -1);
+  for (int x = 0; x < nt; ++x) h->skel_k[tasks[x].node] = kused[x];
+  // the scratch goes back to the allocator once the stream is past its readers
+  for (DevBuf* b : {&d_feat, &d_score, &d_dcnt, &d_budget, &d_state, &d_kused}) b->release_after(s);
+  for (DevBuf* b : {&sc.tasks, &sc.sel, &sc.piv, &sc.cnt, &sc.rt, &sc.inv, &sc.cg, &sc.samp, &sc.err, &sc.norm,
+                    &sc.part})
+    b->release_after(s);
   return HODLR_OK;
 }
 
@@ -1205,4 +1496,70 @@ extern "C" int hodlr_bdlr_select(const int* g_rowptr, const int* g_col, int n, i
   HODLR_HIP(hipGetLastError());
   HODLR_HIP(hipStreamSynchronize(stream));  // the task table goes back to the allocator cache
   return HODLR_OK;
+}
+
+namespace {
+// The sampled error check of the learned and adaptive builds on given
+// factors (hodlr_sampled_error): block norms, draws, residuals, estimates.
+template <typename T>
+int sampled_error_t(const double* K, int ldk, const Tree& tr, const T* U, const T* V, const int* ranks,
+                    const int* rcols, const int* picks, const int* counts, int max_skel, unsigned long long seed,
+                    int attempt, int* samples, double* err, hipStream_t s) {
+  std::vector<int> capoff(tr.L), cap(rcols, rcols + tr.L);
+  for (int q = 0, o = 0; q < tr.L; o += rcols[q], ++q) capoff[q] = o;
+  size_t invo = 0, cgo = 0;
+  std::vector<BdlrTask> tasks = make_tasks<T>(tr, capoff, cap, max_skel, &invo, &cgo);
+  const int nt = (int)tasks.size();
+  for (int x = 0; x < nt; ++x) tasks[x].task = x;
+  SkelScratch sc;
+  HODLR_TRY(sc.tasks.ensure(nt * sizeof(BdlrTask)));
+  HODLR_TRY(sc.rt.ensure(nt * sizeof(int)));
+  HODLR_TRY(sc.norm.ensure((size_t)nt * kNormChunks * sizeof(double)));
+  HODLR_TRY(sc.part.ensure((size_t)nt * kCheckChunks * 2 * sizeof(double)));
+  HODLR_HIP(hipMemcpyAsync(sc.rt.p, ranks, nt * sizeof(int), hipMemcpyHostToDevice, s));
+  HODLR_TRY(block_norms(K, ldk, tasks, sc, s));
+  k_draw_samples<<<nt, 64, 0, s>>>(sc.tasks.as<BdlrTask>(), picks, counts, max_skel, seed, attempt, kSkelSamples,
+                                   samples, nullptr);
+  HODLR_HIP(hipGetLastError());
+  k_skel_check<T><<<dim3(nt, kCheckChunks), kBlock, 0, s>>>(K, ldk, sc.tasks.as<BdlrTask>(), sc.rt.as<int>(), U, V,
+                                                             tr.n, samples, kSkelSamples, sc.part.as<double>(),
+                                                             nullptr);
+  HODLR_HIP(hipGetLastError());
+  k_skel_err<<<(nt + kBlock - 1) / kBlock, kBlock, 0, s>>>(sc.tasks.as<BdlrTask>(), nt, counts, sc.norm.as<double>(),
+                                                          samples, kSkelSamples, sc.part.as<double>(), err,
+                                                          nullptr);
+  HODLR_HIP(hipGetLastError());
+  HODLR_HIP(hipStreamSynchronize(s));  // the scratch goes back to the allocator cache
+  return HODLR_OK;
+}
+}  // namespace
+
+extern "C" int hodlr_sampled_error(const double* K, int n, int ldk, int leaf, int precision, const void* Upanel,
+                                   const void* Vpanel, const int* ranks, const int* rcols, const int* picks,
+                                   const int* counts, int max_skel, unsigned long long seed, int attempt,
+                                   int* samples, double* err, hipStream_t stream) {
+  if (n < 2 || n > 2 * kBdlrMaxSide) return fail(HODLR_EINVAL, "n must be in [2, 16384]");
+  if (leaf < 1 || leaf > kLeafMax) return fail(HODLR_EINVAL, "leaf out of range");
+  if (ldk < n) return fail(HODLR_EINVAL, "ldk < n");
+  if (precision != 32 && precision != 64) return fail(HODLR_EINVAL, "precision must be 32 or 64");
+  if (!K || !Upanel || !Vpanel || !ranks || !rcols || !picks || !counts || !samples || !err)
+    return fail(HODLR_EINVAL, "NULL pointer argument");
+  if (attempt < 0) return fail(HODLR_EINVAL, "attempt must be >= 0");
+  const int skel = skel_stride(precision);
+  if (max_skel < 1 || max_skel > skel) return fail(HODLR_EINVAL, "max_skel must be in [1, 192 / 128]");
+  Tree tr;
+  tr.build(n, leaf);
+  if (tr.L == 0) return fail(HODLR_EINVAL, "n <= leaf: the tree has no off-diagonal blocks");
+  const int rc = rank_cap(precision);
+  for (int q = 1, x = 0; q <= tr.L; ++q) {
+    if (rcols[q - 1] < 0 || rcols[q - 1] > rc) return fail(HODLR_EINVAL, "rcols out of range");
+    for (int i = 0; i < (1 << q); ++i, ++x)
+      if (ranks[x] < 0 || ranks[x] > rcols[q - 1]) return fail(HODLR_EINVAL, "rank above its level's width");
+  }
+  if (precision == 64)
+    return sampled_error_t<double>(K, ldk, tr, static_cast<const double*>(Upanel),
+                                   static_cast<const double*>(Vpanel), ranks, rcols, picks, counts, max_skel, seed,
+                                   attempt, samples, err, stream);
+  return sampled_error_t<float>(K, ldk, tr, static_cast<const float*>(Upanel), static_cast<const float*>(Vpanel),
+                                ranks, rcols, picks, counts, max_skel, seed, attempt, samples, err, stream);
 }

@@ -241,8 +241,10 @@ struct SkelBlock {
   int node, row0, m, col0, nc, samp0;  // samp0: first sample (rows, then columns)
 };
 std::vector<SkelBlock> skel_blocks(const Tree& t);  // level order; samples total 2 n L
+// dcount (optional, 2 ints per block): row and column vertices at distance < cnt_depth
 int launch_skel_features(const int* rowptr, const int* col, const float* xyz, const double* K, int ldk,
-                         const std::vector<SkelBlock>& blocks, float* feats, hipStream_t s);
+                         const std::vector<SkelBlock>& blocks, float* feats, hipStream_t s, int cnt_depth = 0,
+                         int* dcount = nullptr);
 int launch_skel_labels(const std::vector<SkelBlock>& blocks, const int* piv, int kcap, const int* rank,
                        float* labels, hipStream_t s);
 int launch_mlp_forward(const float* X, int N, const float* P, int bf16, float* z, hipStream_t s);

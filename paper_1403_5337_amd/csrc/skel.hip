@@ -106,16 +106,32 @@ __device__ void block_bfs(const int* __restrict__ rowptr, const int* __restrict_
   }
 }
 
+// dcount (optional): per block, the number of row and of column vertices at
+// distance < cnt_depth (the picks of BDLR at that depth before any cap).
 __global__ void __launch_bounds__(kBlock)
     k_skel_features(const int* __restrict__ rowptr, const int* __restrict__ col, const float* __restrict__ xyz,
                     const double* __restrict__ K, int ldk, const SkelBlock* __restrict__ blocks,
-                    float* __restrict__ feats) {
+                    float* __restrict__ feats, int cnt_depth, int* __restrict__ dcount) {
   __shared__ unsigned short dist[2][kSideMax];
   __shared__ float red[kBlock / 64];
   __shared__ int s_changed;
   const SkelBlock b = blocks[blockIdx.x];
   const int t = threadIdx.x;
   block_bfs(rowptr, col, b.row0, b.m, b.col0, b.nc, dist, &s_changed);
+  if (dcount) {
+    __shared__ int cnt[2];
+    if (t < 2) cnt[t] = 0;
+    __syncthreads();
+    for (int sd = 0; sd < 2; ++sd) {
+      const int len = sd == 0 ? b.m : b.nc;
+      int c = 0;
+      for (int i = t; i < len; i += kBlock) c += dist[sd][i] < cnt_depth ? 1 : 0;
+      for (int o = 32; o > 0; o >>= 1) c += __shfl_xor(c, o, 64);
+      if ((t & 63) == 0 && c) atomicAdd(&cnt[sd], c);
+    }
+    __syncthreads();
+    if (t < 2) dcount[2 * blockIdx.x + t] = cnt[t];
+  }
   // per side: dmax, max degree, box, max |K_vv|
   float st[2][10];
   for (int sd = 0; sd < 2; ++sd) {
@@ -387,16 +403,18 @@ std::vector<SkelBlock> skel_blocks(const Tree& t) {
 }
 
 int launch_skel_features(const int* rowptr, const int* col, const float* xyz, const double* K, int ldk,
-                         const std::vector<SkelBlock>& blocks, float* feats, hipStream_t s) {
+                         const std::vector<SkelBlock>& blocks, float* feats, hipStream_t s, int cnt_depth,
+                         int* dcount) {
   if (blocks.empty()) return HODLR_OK;
   for (const SkelBlock& b : blocks)
     if (b.m > kSideMax || b.nc > kSideMax) return fail(HODLR_EINVAL, "block side above 8192");
   DevBuf d;
   HODLR_TRY(d.ensure(blocks.size() * sizeof(SkelBlock)));
   HODLR_HIP(hipMemcpyAsync(d.p, blocks.data(), blocks.size() * sizeof(SkelBlock), hipMemcpyHostToDevice, s));
-  k_skel_features<<<(unsigned)blocks.size(), kBlock, 0, s>>>(rowptr, col, xyz, K, ldk, d.as<SkelBlock>(), feats);
+  k_skel_features<<<(unsigned)blocks.size(), kBlock, 0, s>>>(rowptr, col, xyz, K, ldk, d.as<SkelBlock>(), feats,
+                                                            cnt_depth, dcount);
   HODLR_HIP(hipGetLastError());
-  HODLR_HIP(hipStreamSynchronize(s));  // the block table goes back to the cache
+  d.release_after(s);  // the block table goes back to the cache once the kernel has read it
   return HODLR_OK;
 }
 

@@ -80,6 +80,9 @@ _SIGNATURES = {
     "hodlr_permute_rows": (ctypes.c_int, [_vp, ctypes.c_int, ctypes.c_int, _vp, _vp, _vp]),
     "hodlr_bdlr_select": (ctypes.c_int, [_vp, _vp, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int,
                                          _vp, _vp, _vp]),
+    "hodlr_sampled_error": (ctypes.c_int, [_vp, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int, _vp, _vp,
+                                           _c_int_p, _c_int_p, _vp, _vp, ctypes.c_int, ctypes.c_ulonglong,
+                                           ctypes.c_int, _vp, _vp, _vp]),
     "hodlr_stats": (ctypes.c_int, [_vp, _c_int_p, _c_int_p, _c_int_p]),
     "hodlr_get_factors": (ctypes.c_int, [_vp, _vp, _vp, _vp]),
     "hodlr_destroy": (ctypes.c_int, [_vp]),
@@ -170,7 +173,7 @@ class Hodlr:
 
     @classmethod
     def build(cls, K: torch.Tensor, leaf=128, tol=1e-4, method="aca", depth=1, max_rank=0,
-              precision=32, graph=None, coords=None, mlp_params=None, skel_k=32, seed=0, skel_tol=0.0,
+              precision=32, graph=None, coords=None, mlp_params=None, skel_k=0, seed=0, skel_tol=0.0,
               max_skel=0, symmetric=False, max_depth=0, stream=None) -> "Hodlr":
         """method: 'aca', 'bdlr' (needs graph = (rowptr, col) device tensors) or
         'learned' (graph, coords (n, 3) float32 and mlp_params (4801,) float32,
@@ -196,7 +199,7 @@ class Hodlr:
 
     @classmethod
     def build_batched(cls, Ks, graphs=None, coords=None, leaf=128, tol=1e-4, method="aca", depth=1, max_rank=0,
-                      precision=32, mlp_params=None, skel_k=32, seed=0, skel_tol=0.0, max_skel=0,
+                      precision=32, mlp_params=None, skel_k=0, seed=0, skel_tol=0.0, max_skel=0,
                       symmetric=False, stream=None) -> list:
         """hodlr_build for every front of Ks side by side (hodlr_build_batched);
         graphs: list of (rowptr, col) or None; coords: list of (n, 3) or None."""
@@ -503,6 +506,39 @@ def hodlr_bdlr_select(rowptr: torch.Tensor, col: torch.Tensor, leaf: int, depth:
     pk = picks.view(-1, 2, max_skel).cpu().long()
     ct = counts.view(-1, 2).cpu().long()
     return [(pk[k, 0, :ct[k, 0]], pk[k, 1, :ct[k, 1]]) for k in range(nn)]
+
+
+def hodlr_sampled_error(K, leaf: int, precision: int, Upanel, Vpanel, ranks, rcols, picks, max_skel: int,
+                        seed: int, attempt: int, stream=None):
+    """The build's sampled error check on given factors (hodlr_sampled_error).
+    Upanel/Vpanel: (n, R) device panels (made column-major in the handle's
+    precision); ranks/rcols: host ints; picks: list over nodes below the root
+    of (rows, cols) position sequences.  Returns (samples (nodes, 2, 16) int64
+    CPU tensor, err (nodes,) float64 CPU tensor)."""
+    _need_gpu(K, Upanel, Vpanel)
+    Kc, ldk = colmajor(K, torch.float64)
+    n = Kc.shape[0]
+    dt = torch.float64 if precision == 64 else torch.float32
+    U = Upanel.to(dt).t().contiguous().t()
+    V = Vpanel.to(dt).t().contiguous().t()
+    if U.shape[1] == 0:
+        U = torch.zeros((1, n), dtype=dt, device=K.device).t()
+        V = torch.zeros_like(U)
+    nn = len(picks)
+    pk = torch.zeros((max(nn, 1), 2, max_skel), dtype=torch.int32)
+    ct = torch.zeros((max(nn, 1), 2), dtype=torch.int32)
+    for k, (r, c) in enumerate(picks):
+        pk[k, 0, :len(r)] = torch.as_tensor(r, dtype=torch.int32)
+        pk[k, 1, :len(c)] = torch.as_tensor(c, dtype=torch.int32)
+        ct[k, 0], ct[k, 1] = len(r), len(c)
+    pk, ct = pk.to(K.device), ct.to(K.device)
+    samples = torch.empty((max(nn, 1), 2, 16), dtype=torch.int32, device=K.device)
+    err = torch.empty(max(nn, 1), dtype=torch.float64, device=K.device)
+    rk = (ctypes.c_int * max(len(ranks), 1))(*ranks)
+    rc = (ctypes.c_int * max(len(rcols), 1))(*rcols)
+    _check(lib().hodlr_sampled_error(_ptr(Kc), n, ldk, leaf, precision, _ptr(U), _ptr(V), rk, rc, _ptr(pk),
+                                     _ptr(ct), max_skel, seed, attempt, _ptr(samples), _ptr(err), _stream(stream)))
+    return samples[:nn].cpu().long(), err[:nn].cpu()
 
 
 def hodlr_prof_enable(on: bool):

@@ -36,7 +36,7 @@ def test_default_opts(L):
     from paper_1403_5337_amd import hodlr
     o = hodlr.default_opts()
     assert (o.leaf, o.tol, o.method, o.bdlr_depth, o.max_rank, o.precision) == (128, 1e-4, 0, 1, 0, 32)
-    assert (o.skel_k, o.mlp_params, o.seed) == (32, None, 0)
+    assert (o.skel_k, o.mlp_params, o.seed) == (0, None, 0)
     assert (o.skel_tol, o.bdlr_max_skel, o.bdlr_max_depth, o.symmetric) == (0.0, 0, 0, 0)
 
 

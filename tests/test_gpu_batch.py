@@ -196,3 +196,72 @@ def test_matvec_split_width_is_tuned_once_per_shape():
     assert st1 == st2 == H.HODLR_OK and it1 == it2 and torch.equal(X1, X2)
     assert H.hodlr_tune_report() == rep
     h.close()
+
+
+def test_nested_dissection_64_cube_stated_size():
+    """The batch at its stated size: levels 0-5 of the 64^3 lognormal TPFA
+    cube (63 fronts, n 4096 down to 225), 32 right-hand sides per front, BDLR
+    depth 2 at 1e-4 in float32: ordered, compressed and solved through the
+    batched calls, factorized through one graph.  Every front's relative
+    residual is recomputed in float64 on the CPU.  On three fronts of
+    different sizes, the factorization and solve of the oracle's own BDLR
+    factors (oracle.bdlr, recursive Woodbury in float64) agree with the
+    library's on the same factors (hodlr_build_from_factors) to the float32
+    bar of the factor parity tests."""
+    from oracle import bdlr as obdlr, hodlr as ohodlr, ordering, tree
+
+    fr = fronts.nd_fronts(64, levels=6, sigma=1.0, seed=0, device="cuda")
+    sizes = [f.n for f in fr]
+    say("nd64 batch:", len(fr), "fronts, n", max(sizes), "..", min(sizes))
+    assert len(fr) == 63 and max(sizes) == 4096 and min(sizes) >= 200
+    xyz = [torch.from_numpy(f.coords).cuda() for f in fr]
+    Ks = [f.K.t().contiguous().t() for f in fr]
+    gs = [(torch.from_numpy(f.indptr).cuda(), torch.from_numpy(f.indices).cuda()) for f in fr]
+    perms, Kps, gps = H.hodlr_order_batched(xyz, Ks, graphs=gs, leaf=128)
+    hs = H.Hodlr.build_batched(Kps, graphs=gps, leaf=128, tol=1e-4, method="bdlr", depth=2)
+    H.hodlr_factor_batched(hs)
+    Bs = [fronts.rhs(f.n, 32, seed=f.n).cuda() for f in fr]
+    Xs, its, rrs, st = H.gmres_solve_batched(Kps, Bs, hs, tol=1e-12, maxit=1000, restart=200)
+    assert st == H.HODLR_OK
+    worst = 0.0
+    for Kp, B, X in zip(Kps, Bs, Xs):
+        rr = dense.relres(Kp.cpu().numpy(), X.cpu().numpy(), B.cpu().numpy())
+        worst = max(worst, float(rr.max()))
+    say("  iterations max per front", [max(i) for i in its][:8], "... worst relres", worst)
+    assert worst <= 1e-12
+    for h in hs:
+        h.close()
+    # factor / solve parity on shared (oracle-built) factors
+    pick = sorted(range(len(fr)), key=lambda k: -fr[k].n)
+    for k in (pick[0], pick[len(pick) // 2], pick[-1]):
+        f = fr[k]
+        perm = ordering.rcb_permutation(f.coords, 128)
+        g = fronts.permute_front(fronts.Front(K=f.K.cpu(), indptr=f.indptr, indices=f.indices, coords=f.coords,
+                                              name=f.name), perm)
+        K = g.K.numpy()
+        levs = tree.levels(g.n, 128)
+        L = len(levs) - 1
+        o = ohodlr.from_dense(K, 128, method="bdlr", eps=1e-4, graph=(g.indptr, g.indices), depth=2,
+                              max_skel=192, max_rank=184)
+        rmax = {p: max(o.U[(p, i)].shape[1] for i in range(len(levs[p]))) for p in range(1, L + 1)}
+        Up = {p: np.zeros((g.n, rmax[p])) for p in range(1, L + 1)}
+        Vp = {p: np.zeros((g.n, rmax[p])) for p in range(1, L + 1)}
+        for p in range(1, L + 1):
+            for i, (lo, hi) in enumerate(levs[p]):
+                slo, shi = levs[p][i ^ 1]
+                r = o.U[(p, i)].shape[1]
+                Up[p][lo:hi, :r] = o.U[(p, i)]
+                Vp[p][slo:shi, :r] = o.V[(p, i)]
+        fac = dict(levels=levs, leaves=[(lo, hi, K[lo:hi, lo:hi]) for lo, hi in levs[L]], U=o.U, V=o.V,
+                   Upanel=Up, Vpanel=Vp, rmax=rmax)
+        P = pack_for_library(fac)
+        h = H.Hodlr.from_factors(g.n, 128, 32, P["leaves"], P["U"], P["V"], P["ranks"], P["rcols"])
+        h.factor()
+        ohodlr.factor(o)
+        B = fronts.rhs(g.n, 3, seed=k).numpy()
+        want = ohodlr.solve(o, B)
+        got = h.solve(torch.from_numpy(B).cuda()).double().cpu().numpy()
+        err = np.abs(got - want).max() / np.abs(want).max()
+        say("  front", k, "n", g.n, "ranks", [rmax[p] for p in range(1, L + 1)], "factor/solve rel err", err)
+        assert err <= 2e-4
+        h.close()

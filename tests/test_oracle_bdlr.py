@@ -288,18 +288,94 @@ def test_top_k_ties_to_the_lower_position():
     assert bdlr.top_k([1.0], 5).tolist() == [0]
 
 
-def test_learned_block_doubles_k_until_the_check_passes():
+def test_node_runs_and_node_picks_hand_cases():
+    P, Q = [0.0, 0.0, 1.0], [2.0, 0.0, 1.0]
+    # three dofs at P, one at Q, one at P again (not adjacent: a node of its own)
+    X = np.array([P, P, P, Q, P])
+    assert bdlr.node_runs(X) == [(0, 3), (3, 1), (4, 1)]
+    # ten equal points: one node of RUN_MAX = 8, then singletons
+    assert bdlr.node_runs(np.array([P] * 10)) == [(0, 8), (8, 1), (9, 1)]
+    assert bdlr.node_runs(np.zeros((0, 3))) == []
+    # 3-dof nodes A (positions 0-2), B (3-5), C (6-8); node score = max of its dofs
+    X = np.array([P] * 3 + [Q] * 3 + [[5.0, 5.0, 5.0]] * 3)
+    sc = np.array([0.1, 0.9, 0.2, 0.5, 0.5, 0.5, 0.3, 0.2, 0.95])
+    # budget 6 / longest node 3 = 2 nodes: C (0.95) and A (0.9)
+    assert bdlr.node_picks(sc, X, 6).tolist() == [0, 1, 2, 6, 7, 8]
+    # budget 5 -> 1 node; budget 2 -> still one node (at least one)
+    assert bdlr.node_picks(sc, X, 5).tolist() == [6, 7, 8]
+    assert bdlr.node_picks(sc, X, 2).tolist() == [6, 7, 8]
+    # ties between nodes go to the lower first position
+    assert bdlr.node_picks(np.ones(9), X, 3).tolist() == [0, 1, 2]
+    # scalar dofs (distinct points): the plain top-k
+    Xs = np.arange(15, dtype=float).reshape(5, 3)
+    assert bdlr.node_picks(np.array([0.5, 2.0, 0.5, 1.0, 0.5]), Xs, 3).tolist() == [0, 1, 3]
+
+
+def test_depth_count_counts_the_distance_layers():
+    indptr, indices, I, J, _ = three_scale_block(40)
+    assert [bdlr.depth_count(indptr, indices, I, J, d) for d in (1, 2, 5)] == [1, 2, 5]
+
+
+def test_learned_block_doubles_until_the_check_passes_then_falls_back():
     # scores that prefer the boundary: the k nearest rows / columns; the block
-    # needs the first three distance layers (k = 4 covers them, k = 2 does not)
+    # needs the first three distance layers (4 picks cover them, 2 do not)
     indptr, indices, I, J, B = three_scale_block(40)
     sr = -np.abs(np.arange(40) - 39.0)   # row 39 touches the columns
     sc = -np.arange(40, dtype=float)     # column 0 touches the rows
-    U, V, k, trace = bdlr.learned_block(B, sr, sc, 1, 192, 1e-10, 1e-10, seed=0, node=1)
-    assert k == 4 and [t["k"] for t in trace] == [1, 2, 4]
+    X = np.arange(120, dtype=float).reshape(40, 3)  # distinct points: one dof per node
+    U, V, k, trace = bdlr.learned_block(B, sr, sc, X, X, (1, 1), 192, 1e-10, 1e-10, seed=0, node=1)
+    assert k == 4 and [t["br"] for t in trace] == [1, 2, 4]
     Ur, Vr = bdlr.skeleton(B, np.arange(36, 40), np.arange(4), 1e-10)
     assert np.array_equal(U, Ur) and np.array_equal(V, Vr)
-    # with at most 2 picks per side no size passes: fallback
-    U, V, k, trace = bdlr.learned_block(B, sr, sc, 1, 2, 1e-10, 1e-10, seed=0, node=1)
-    assert U is None and k == 0 and [t["k"] for t in trace] == [1, 2]
+    # with at most 2 picks per side no size passes; no fallback: the last skeleton
+    U, V, k, trace = bdlr.learned_block(B, sr, sc, X, X, (1, 1), 2, 1e-10, 1e-10, seed=0, node=1)
+    assert k == -2 and [t["br"] for t in trace] == [1, 2]
+    # the attempt limit stops the doubling as well
+    _, _, k, trace = bdlr.learned_block(B, sr, sc, X, X, (1, 1), 192, 1e-10, 1e-10, seed=0, node=1, attempts=2)
+    assert k == -2 and len(trace) == 2
+    # a fallback with a smaller sampled error is kept (kused 0), a worse one is not
+    exact = lambda A: (A.copy(), np.eye(A.shape[1]))
+    U, V, k, trace = bdlr.learned_block(B, sr, sc, X, X, (1, 1), 2, 1e-10, 1e-10, seed=0, node=1, fallback=exact)
+    assert k == 0 and np.array_equal(U @ V.T, B) and trace[-1]["fallback"] and trace[-1]["err"] == 0.0
+    # both candidates on the last picks and a fresh draw outside them (stream attempt 4)
+    rows, cols = trace[-2]["rows"], trace[-2]["cols"]
+    assert rows.tolist() == [38, 39] and cols.tolist() == [0, 1]
+    rng = bdlr.block_stream(0, 1, 4)
+    assert trace[-1]["rows_s"] == bdlr.draw_outside(rng, 40, rows)
+    assert trace[-1]["cols_s"] == bdlr.draw_outside(rng, 40, cols)
+    zero = lambda A: (np.zeros((A.shape[0], 1)), np.zeros((A.shape[1], 1)))
+    U, V, k, trace = bdlr.learned_block(B, sr, sc, X, X, (1, 1), 2, 1e-10, 1e-10, seed=0, node=1, fallback=zero)
+    assert k == -2 and U.shape[1] >= 1 and trace[-1]["err"] > trace[-1]["err_skeleton"] > 0
+    # the zero fallback's estimate: the picked rows exactly, the 16 sampled rows scaled by 38 / 16
+    rs, cs = trace[-1]["rows_s"], trace[-1]["cols_s"]
+    er = np.sum(B[[38, 39]] ** 2) + np.sum(B[rs] ** 2) * 38 / 16
+    ec = np.sum(B[:, [0, 1]] ** 2) + np.sum(B[:, cs] ** 2) * 38 / 16
+    assert trace[-1]["err"] == pytest.approx(np.sqrt(max(er, ec) / np.sum(B ** 2)), rel=1e-14)
 
+
+def test_candidate_error_hand_cases():
+    B = np.arange(1.0, 13.0).reshape(4, 3)
+    U, V = np.zeros((4, 1)), np.zeros((3, 1))
+    nb = np.sum(B ** 2)
+    # no picks: the sampled rows scaled by 4 / 2 (rows) vs columns 1 and 2 scaled by 3 / 2
+    er = (np.sum(B[0] ** 2) + np.sum(B[3] ** 2)) * 2
+    ec = (np.sum(B[:, 1] ** 2) + np.sum(B[:, 2] ** 2)) * 1.5
+    assert bdlr.candidate_error(B, U, V, [], [], [0, 3, -1], [1, 2]) == pytest.approx(np.sqrt(max(er, ec) / nb))
+    # picks count exactly: row 1 picked, rows 0 and 3 sampled of the 3 outside
+    er = np.sum(B[1] ** 2) + (np.sum(B[0] ** 2) + np.sum(B[3] ** 2)) * 3 / 2
+    assert bdlr.candidate_error(B, U, V, [1], [], [0, 3], []) == pytest.approx(np.sqrt(er / nb))
+    # an exact approximation scores 0 whatever is sampled
+    assert bdlr.candidate_error(B, B.copy(), np.eye(3), [1, 2], [0], [0, 3], [1, 2]) == 0.0
+
+
+def test_learned_block_takes_whole_nodes():
+    indptr, indices, I, J, B = three_scale_block(40)
+    sr = -np.abs(np.arange(40) - 39.0)
+    sc = -np.arange(40, dtype=float)
+    # 3-dof nodes: the budget counts dofs, whole nodes are taken
+    # (nodes of positions 0-2, 3-5, ..., 36-38 and a last node of position 39 alone)
+    X3 = np.repeat(np.arange(14.0), 3)[:40, None] * np.ones((1, 3))
+    _, _, _, trace = bdlr.learned_block(B, sr, sc, X3, X3, (6, 6), 192, 1e-10, 1e-10, seed=0, node=1)
+    # rows: the best nodes are {39} and {36, 37, 38}; columns: {0, 1, 2} and {3, 4, 5}
+    assert trace[0]["nrows"] == 4 and trace[0]["ncols"] == 6
 
