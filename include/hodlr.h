@@ -70,9 +70,12 @@ typedef struct {
      columns outside it (hodlr_sampled_error); a block above skel_tol
      retries with both budgets doubled, up to 192 (precision 32) / 128
      (precision 64) picks and at most 4 attempts, all decided on the device.
-     A block that still fails is also compressed by ACA, whose error is
-     estimated on the same samples, and keeps the smaller of the two
-     (hodlr_skel_info). */
+     A block that still fails is also compressed by ACA, and keeps whichever
+     approximation has the smaller error estimated on its picked rows and
+     columns (exactly) and 16 fresh rows and columns outside them
+     (hodlr_skel_info) -- except a block whose budgets are at the pick cap
+     and whose rank is at the rank cap, which keeps its skeleton (ACA is held
+     to the same rank cap). */
   int skel_k;                /* first budget per side, >= 0; 0 (default) =
                                 the side's BDLR pick count at bdlr_depth */
   const float* mlp_params;   /* device float32, 4801 scorer parameters in the

@@ -349,7 +349,9 @@ def learned_block(B, row_scores, col_scores, row_coords, col_coords, budgets, ma
     checks it (check_skeleton, attempt a); a block at or below ``accept``
     passes; otherwise both budgets double (capped) and the block retries, and
     it fails when they cannot grow or after ``attempts`` attempts.  A failed
-    block is compressed by ``fallback(B)`` -> (U, V) (ACA) as well; both
+    block is compressed by ``fallback(B)`` -> (U, V) (ACA) as well, unless
+    its budgets are at the pick cap and its rank at the rank cap (ACA is
+    held to the same rank cap; the block keeps its skeleton); both
     approximations are then measured by candidate_error on the skeleton's
     last picks (exactly) and 16 fresh rows and columns outside them (stream
     attempt ``attempts``), and the block keeps the smaller.  (A sample of the
@@ -376,7 +378,9 @@ def learned_block(B, row_scores, col_scores, row_coords, col_coords, budgets, ma
         if attempt == attempts - 1 or (nr == br and nc == bc):
             break
         br, bc = nr, nc
-    if fallback is None:
+    capped = (br == min(max_skel, m) and bc == min(max_skel, n)
+              and U.shape[1] >= (min(m, n, max_skel) if max_rank is None else min(max_rank, m, n, max_skel)))
+    if fallback is None or capped:
         return U, V, -max(br, bc), trace
     Uf, Vf = fallback(B)
     # both candidates on the same positions: the skeleton's last picks,

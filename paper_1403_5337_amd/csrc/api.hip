@@ -230,7 +230,11 @@ int Tree::max_size(int p) const {
 }
 
 // Common set-up of a new handle once the tree is known.
-static int init_handle(hodlr_s* h, int n, int leaf, int precision) {
+// The status words are cleared on the build's stream: the handle's blocks
+// come from the caching allocator (recycled memory), and a clear on the null
+// stream is not ordered before work on a non-blocking stream (the worker
+// streams of the batched calls).
+static int init_handle(hodlr_s* h, int n, int leaf, int precision, hipStream_t stream) {
   h->tree.build(n, leaf);
   h->precision = precision;
   h->esize = precision == 64 ? 8 : 4;
@@ -246,7 +250,7 @@ static int init_handle(hodlr_s* h, int n, int leaf, int precision) {
   HODLR_HIP(hipMemcpy(h->d_lo.p, t.lo.data(), nn * sizeof(int), hipMemcpyHostToDevice));
   HODLR_HIP(hipMemcpy(h->d_hi.p, t.hi.data(), nn * sizeof(int), hipMemcpyHostToDevice));
   HODLR_TRY(h->status.ensure(4 * sizeof(int)));
-  HODLR_HIP(hipMemset(h->status.p, 0, 4 * sizeof(int)));
+  HODLR_HIP(hipMemsetAsync(h->status.p, 0, 4 * sizeof(int), stream));
   HODLR_TRY(h->Kinv.ensure((size_t)h->nleaf * h->bmax * h->bmax * h->esize));
   return HODLR_OK;
 }
@@ -499,7 +503,7 @@ static int build_impl(const double* K, int n, int ldk, const int* g_rowptr, cons
   h->depth = o.bdlr_depth;
   h->max_rank = o.max_rank;
   h->tol = o.tol;
-  HODLR_TRY(init_handle(h.get(), n, o.leaf, o.precision));
+  HODLR_TRY(init_handle(h.get(), n, o.leaf, o.precision, stream));
   const Tree& t = h->tree;
   // a1: leaf blocks to the factorization precision
   HODLR_TRY(launch_stage_leaves_from_K(h.get(), K, ldk, stream));
@@ -637,7 +641,7 @@ int hodlr_build_from_factors(int n, int leaf, int precision, const double* leave
       return fail(HODLR_EINVAL, "panels, ranks and rcols are required when L > 0");
   }
   std::unique_ptr<hodlr_s> h(new hodlr_s());
-  HODLR_TRY(init_handle(h.get(), n, leaf, precision));
+  HODLR_TRY(init_handle(h.get(), n, leaf, precision, stream));
   const Tree& t = h->tree;
   int cap = rank_cap(precision);
   for (int q = 1; q <= t.L; ++q) {

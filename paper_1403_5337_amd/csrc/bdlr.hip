@@ -1064,10 +1064,12 @@ __global__ void k_learned_init(const BdlrTask* __restrict__ tasks, int nt, const
 
 // After an attempt: a pending block passes at err <= accept; otherwise its
 // budgets double (capped), and it fails when they cannot grow or on the last
-// attempt.
+// attempt: state 2 (the ACA fallback runs), or state 3 when its budgets are
+// at the pick cap and its rank at the rank cap (ACA is held to the same rank
+// cap; the block keeps its skeleton).
 __global__ void k_learned_decide(const BdlrTask* __restrict__ tasks, int nt, const double* __restrict__ err,
-                                 double accept, int skel, int last, int* __restrict__ budget, int* __restrict__ state,
-                                 int* __restrict__ kused) {
+                                 double accept, int skel, int rcap, int last, const int* __restrict__ rank_task,
+                                 int* __restrict__ budget, int* __restrict__ state, int* __restrict__ kused) {
   const int x = blockIdx.x * blockDim.x + threadIdx.x;
   if (x >= nt || state[x] != 0) return;
   const BdlrTask tk = tasks[x];
@@ -1079,7 +1081,8 @@ __global__ void k_learned_decide(const BdlrTask* __restrict__ tasks, int nt, con
   }
   const int nr = min(2 * br, min(skel, tk.m)), nc = min(2 * bc, min(skel, tk.nc));
   if (last || (nr == br && nc == bc)) {
-    state[x] = 2;
+    const bool capped = nr == br && nc == bc && rank_task[x] >= min(rcap, tk.kmax);
+    state[x] = capped ? 3 : 2;
     kused[x] = -max(br, bc);
     return;
   }
@@ -1310,8 +1313,9 @@ static int learned_t(hodlr_s* h, const double* K, int ldk, const int* rowptr, co
     HODLR_TRY((skel_attempt_launch<T, SKEL>(h, K, ldk, nt, maxside, sc, Ucap, Vcap, seed, attempt,
                                             d_state.as<int>(), s)));
     k_learned_decide<<<g1, kBlock, 0, s>>>(sc.tasks.as<BdlrTask>(), nt, sc.err.as<double>(), accept, SKEL,
-                                           attempt == kLearnedAttempts - 1 ? 1 : 0, d_budget.as<int>(),
-                                           d_state.as<int>(), d_kused.as<int>());
+                                           h->precision == 64 ? kRankCap64 : kRankCap32,
+                                           attempt == kLearnedAttempts - 1 ? 1 : 0, sc.rt.as<int>(),
+                                           d_budget.as<int>(), d_state.as<int>(), d_kused.as<int>());
     HODLR_HIP(hipGetLastError());
   }
   std::vector<int> state(nt), kused(nt);

@@ -7,11 +7,12 @@ middle plane of nx x ny x 17 cell grids (8 planes on each side of the
 separator), nx, ny drawn from [32, 64], seeds 1, 2, ...; labels are the
 rows and columns the full-pivot LU keeps from the depth-4 BDLR skeleton of
 each block at 1e-4 (hodlr_skel_labels, source 1).  Held-out evaluation:
-Q1 elasticity fronts with 64 x 32 separator nodes (n = 6144, 8 free node
+Q1 elasticity fronts with 64 x 32 separator nodes (n = 6144, 31 free node
 planes on each side), dofs randomly permuted (seeds 10001, ...), built with
-HODLR_LEARNED, BDLR (depth 2) and ACA; reports the blocks that passed the
-sampled check at each skeleton size, the ACA fallbacks, ranks and GMRES
-iterations to 1e-12.  Writes the parameters to skel_mlp.npy / skel_mlp.json
+HODLR_LEARNED (first budgets the depth-2 pick counts), BDLR (depth 2) and
+ACA; reports the blocks that passed the sampled check at each budget, the
+fallback decisions, ranks and GMRES iterations to 1e-12.  --evaluate-only
+re-runs the evaluation of the committed parameters.  Writes the parameters to skel_mlp.npy / skel_mlp.json
 next to this file (or --out).
 """
 from __future__ import annotations
@@ -46,13 +47,13 @@ def training_fronts(count: int, seed0: int = 1, depth: int = 8):
         yield fronts.tpfa_front((nx, ny, 2 * depth + 1), zs=depth, sigma=1.0, seed=s, device="cuda")
 
 
-def eval_fronts(count: int, seed0: int = 10001, depth: int = 8):
+def eval_fronts(count: int, seed0: int = 10001, depth: int = 31):
     fronts = _gen()
     for s in range(seed0, seed0 + count):
         yield fronts.elasticity_front((64, 32, 2 * depth + 1), zs=depth, perm_seed=s, device="cuda")
 
 
-def evaluate(params, fr, leaf=128, tol=1e-4, skel_k=32, seed=0):
+def evaluate(params, fr, leaf=128, tol=1e-4, skel_k=0, depth=2, seed=0):
     fronts = _gen()
     K, rp, ci, xyz = S.order_front(fr, leaf)
     B = fronts.rhs(fr.n, 1, seed=0).cuda()
@@ -63,8 +64,9 @@ def evaluate(params, fr, leaf=128, tol=1e-4, skel_k=32, seed=0):
             kw["graph"] = (rp, ci)
         if method == "learned":
             kw.update(coords=xyz, mlp_params=params, skel_k=skel_k, seed=seed)
-        if method == "bdlr":
-            kw["depth"] = 2
+        if method != "aca":
+            kw["depth"] = depth
+        H.Hodlr.build(K, **kw).close()  # warm
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         h = H.Hodlr.build(K, **kw)
@@ -76,7 +78,8 @@ def evaluate(params, fr, leaf=128, tol=1e-4, skel_k=32, seed=0):
             info = h.skel_info()
             flat = [k for lv in info for k in lv]
             rec["kept_sizes"] = {str(k): flat.count(k) for k in sorted(set(flat))}
-            rec["fallback_blocks"] = flat.count(0)
+            rec["aca_kept_blocks"] = flat.count(0)
+            rec["failed_skeleton_kept_blocks"] = sum(k < 0 for k in flat)
             rec["blocks"] = len(flat)
         h.factor()
         X, it, rr, status = H.gmres_solve(K, B, h, tol=1e-12)
@@ -95,8 +98,21 @@ def main(argv=None):
     ap.add_argument("--eval", type=int, default=3)
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--out", default=S.WEIGHTS)
+    ap.add_argument("--evaluate-only", action="store_true",
+                    help="evaluate the committed parameters on the held-out fronts and rewrite the metadata's eval")
     args = ap.parse_args(argv)
     H.lib()
+    if args.evaluate_only:
+        params = S.load()
+        meta = json.load(open(args.out.replace(".npy", ".json")))
+        meta["eval"] = [evaluate(params, fr) for fr in eval_fronts(args.eval)]
+        meta["eval_recipe"] = ("Q1 elasticity, 64 x 32 x 63 free nodes, separator plane z = 31 (n = 6144), dofs "
+                               "permuted by seeds 10001..; learned: first budgets the depth-2 BDLR pick counts, "
+                               "ACA fallback; BDLR depth 2; build times after one warm build")
+        for e in meta["eval"]:
+            print("# eval", json.dumps(e), flush=True)
+        S.save(params, meta, args.out, args.out.replace(".npy", ".json"))
+        return
     t0 = time.perf_counter()
     pairs = []
     for i, fr in enumerate(training_fronts(args.fronts)):

@@ -333,18 +333,25 @@ def test_learned_block_doubles_until_the_check_passes_then_falls_back():
     # the attempt limit stops the doubling as well
     _, _, k, trace = bdlr.learned_block(B, sr, sc, X, X, (1, 1), 192, 1e-10, 1e-10, seed=0, node=1, attempts=2)
     assert k == -2 and len(trace) == 2
-    # a fallback with a smaller sampled error is kept (kused 0), a worse one is not
+    # at the pick cap with the rank at its cap, no fallback runs (ACA would be held to the same rank)
     exact = lambda A: (A.copy(), np.eye(A.shape[1]))
     U, V, k, trace = bdlr.learned_block(B, sr, sc, X, X, (1, 1), 2, 1e-10, 1e-10, seed=0, node=1, fallback=exact)
+    assert k == -2 and U.shape[1] == 2 and not trace[-1].get("fallback")
+    # stopped by the attempt limit below the caps: a fallback with a smaller
+    # sampled error is kept (kused 0), a worse one is not
+    U, V, k, trace = bdlr.learned_block(B, sr, sc, X, X, (1, 1), 192, 1e-10, 1e-10, seed=0, node=1, attempts=2,
+                                        fallback=exact)
     assert k == 0 and np.array_equal(U @ V.T, B) and trace[-1]["fallback"] and trace[-1]["err"] == 0.0
-    # both candidates on the last picks and a fresh draw outside them (stream attempt 4)
+    # both candidates on the last picks and a fresh draw outside them (stream
+    # attempt = the attempt limit, here 2)
     rows, cols = trace[-2]["rows"], trace[-2]["cols"]
     assert rows.tolist() == [38, 39] and cols.tolist() == [0, 1]
-    rng = bdlr.block_stream(0, 1, 4)
+    rng = bdlr.block_stream(0, 1, 2)
     assert trace[-1]["rows_s"] == bdlr.draw_outside(rng, 40, rows)
     assert trace[-1]["cols_s"] == bdlr.draw_outside(rng, 40, cols)
     zero = lambda A: (np.zeros((A.shape[0], 1)), np.zeros((A.shape[1], 1)))
-    U, V, k, trace = bdlr.learned_block(B, sr, sc, X, X, (1, 1), 2, 1e-10, 1e-10, seed=0, node=1, fallback=zero)
+    U, V, k, trace = bdlr.learned_block(B, sr, sc, X, X, (1, 1), 192, 1e-10, 1e-10, seed=0, node=1, attempts=2,
+                                        fallback=zero)
     assert k == -2 and U.shape[1] >= 1 and trace[-1]["err"] > trace[-1]["err_skeleton"] > 0
     # the zero fallback's estimate: the picked rows exactly, the 16 sampled rows scaled by 38 / 16
     rs, cs = trace[-1]["rows_s"], trace[-1]["cols_s"]
