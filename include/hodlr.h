@@ -201,6 +201,30 @@ int gmres_solve(const double* K, int n, int ldk, hodlr_t precond, const double* 
                 int ldb, double* X, int ldx, double tol, int maxit, int restart, int* iters,
                 double* relres, hipStream_t stream);
 
+/* gmres_solve for callers that cannot allocate (code under HIP graph capture
+ * of the surrounding work, tight serving loops, harnesses that forbid
+ * hipMalloc): the same arguments and arithmetic (bit for bit the same
+ * results when both use the same product split width), but the Arnoldi
+ * basis, the preconditioned vectors, the partial sums and every other piece
+ * of workspace live in one fixed device array of 192 MiB that the library
+ * holds on each GPU it runs on until the process ends; no hipMalloc,
+ * hipHostMalloc, hipFree or event creation happens in the call.
+ *   Limit: about 8 n nrhs (restart + 1) bytes for the basis, plus 4 or 8
+ *   n nrhs (restart + 1) for the preconditioned vectors (float32 or float64
+ *   preconditioner), plus 8 n nrhs ceil(n / 64) for the product's partial
+ *   sums, must fit in 192 MiB (e.g. n 4096, 8 right-hand sides, restart
+ *   200: 100 MB); larger problems return EINVAL with the bytes needed.
+ *   The step flags come back by a copy and a stream synchronization per
+ *   Arnoldi step (gmres_solve reads them from pinned memory one step
+ *   behind), and the float64 product uses the split width the autotuner
+ *   already chose for this shape, else its default; nothing is timed.
+ *   Every call on a GPU shares that GPU's array: calls that overlap on one
+ *   GPU (two threads, two streams) race.  The array keeps the last call's
+ *   contents; everything a solve reads is written by it first. */
+int gmres_solve_noalloc(const double* K, int n, int ldk, hodlr_t precond, const double* B, int nrhs, int ldb,
+                        double* X, int ldx, double tol, int maxit, int restart, int* iters, double* relres,
+                        hipStream_t stream);
+
 /* Preconditioned conjugate gradients in float64 for symmetric positive
  * definite K (Sec. 3: the HODLR solve preconditions any Krylov method,
  * conjugate gradients included).  Arguments as gmres_solve, without restart.

@@ -863,6 +863,28 @@ int gmres_solve(const double* K, int n, int ldk, hodlr_t precond, const double* 
                     stream);
 }
 
+int gmres_solve_noalloc(const double* K, int n, int ldk, hodlr_t precond, const double* B, int nrhs, int ldb,
+                        double* X, int ldx, double tol, int maxit, int restart, int* iters, double* relres,
+                        hipStream_t stream) {
+  if (!K || !B || !X) return fail(HODLR_EINVAL, "K, B or X is NULL");
+  if (n < 1 || n > kMaxN) return fail(HODLR_EINVAL, "n out of range");
+  if (ldk < n || ldb < n || ldx < n) return fail(HODLR_EINVAL, "leading dimension < n");
+  if (nrhs < 1 || nrhs > 64) return fail(HODLR_EINVAL, "nrhs must be in [1, 64]");
+  if (!(tol > 0.0)) return fail(HODLR_EINVAL, "tol must be > 0");
+  if (maxit < 1 || restart < 1) return fail(HODLR_EINVAL, "maxit and restart must be >= 1");
+  if (!iters || !relres) return fail(HODLR_EINVAL, "iters or relres is NULL");
+  if (precond) {
+    if (!precond->factored) return fail(HODLR_EINVAL, "preconditioner is not factorized");
+    if (precond->tree.n != n) return fail(HODLR_EINVAL, "preconditioner size differs from n");
+  }
+  const size_t need = gmres_noalloc_bytes(n, nrhs, restart, precond ? precond->precision : 0);
+  if (need > gmres_noalloc_limit())
+    return fail(HODLR_EINVAL, "gmres_solve_noalloc: n x nrhs x (restart + 1) needs " + std::to_string(need) +
+                                  " bytes of workspace, above the fixed " + std::to_string(gmres_noalloc_limit()) +
+                                  " bytes");
+  return gmres_impl(K, n, ldk, precond, B, nrhs, ldb, X, ldx, tol, maxit, restart, iters, relres, stream, true);
+}
+
 int cg_solve(const double* K, int n, int ldk, hodlr_t precond, const double* B, int nrhs, int ldb, double* X,
              int ldx, double tol, int maxit, int* iters, double* relres, hipStream_t stream) {
   if (!K || !B || !X) return fail(HODLR_EINVAL, "K, B or X is NULL");

@@ -464,9 +464,51 @@ __global__ void k_xupdate(int n, int s, int m, double* __restrict__ X, int ldx, 
 }
 
 // ---------------------------------------------------------------------------
+// The workspace of one solve, carved in this order from one arena (every
+// piece 256-byte aligned); its size depends only on (n, s, m, type of z).
+struct GmresPtrs {
+  double *V, *w, *part, *hA, *hB, *hcol, *H, *cs, *sn, *g, *grun, *y, *npart, *scal, *bnorm, *relres;
+  void* Z;
+  int* ints;
+  int* dev_flags;  // 192 ints: [0, 64) cycle start, [64, 192) two step slots
+};
+
+static size_t gmres_layout(int n, int s, int m, size_t zsize, bool precond, unsigned char* base, GmresPtrs* p) {
+  const size_t m1 = m + 1, ns = (size_t)n * s, nch = (n + kRowsPerWG - 1) / kRowsPerWG;
+  const size_t nsplit_max = (n + kMatvecColsMin - 1) / kMatvecColsMin;
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    void* q = base ? base + off : nullptr;
+    off += (bytes + 255) / 256 * 256;
+    return q;
+  };
+  GmresPtrs t{};
+  t.V = static_cast<double*>(take(ns * m1 * sizeof(double)));
+  t.Z = precond ? take(ns * m1 * zsize) : nullptr;
+  t.w = static_cast<double*>(take(ns * sizeof(double)));
+  t.part = static_cast<double*>(take(ns * nsplit_max * sizeof(double)));
+  t.hA = static_cast<double*>(take(nch * s * m1 * sizeof(double)));
+  t.hB = static_cast<double*>(take(nch * s * m1 * sizeof(double)));
+  t.hcol = static_cast<double*>(take((size_t)s * m1 * sizeof(double)));
+  t.H = static_cast<double*>(take((size_t)s * m1 * m * sizeof(double)));
+  t.cs = static_cast<double*>(take((size_t)s * m * sizeof(double)));
+  t.sn = static_cast<double*>(take((size_t)s * m * sizeof(double)));
+  t.g = static_cast<double*>(take((size_t)s * m1 * sizeof(double)));
+  t.grun = static_cast<double*>(take(2 * 64 * sizeof(double)));
+  t.y = static_cast<double*>(take((size_t)s * m * sizeof(double)));
+  t.npart = static_cast<double*>(take(nch * s * sizeof(double)));
+  t.scal = static_cast<double*>(take(s * sizeof(double)));
+  t.bnorm = static_cast<double*>(take(s * sizeof(double)));
+  t.relres = static_cast<double*>(take(s * sizeof(double)));
+  t.ints = static_cast<int*>(take(5 * 64 * sizeof(int)));
+  t.dev_flags = static_cast<int*>(take(192 * sizeof(int)));
+  if (p) *p = t;
+  return off;
+}
+
 struct GmresWork {
-  DevBuf V, Z, w, part, hA, hB, hcol, H, cs, sn, g, grun, y, npart, scal, bnorm, relres, ints;
-  int* host_flags = nullptr;  // pinned: [0, 64) cycle start, [64, 192) two step slots
+  DevBuf arena;
+  int* host_flags = nullptr;  // pinned: the kernels write the step flags here
   int* dev_flags = nullptr;   // the same memory as the device addresses it
   hipEvent_t ev[2] = {nullptr, nullptr};
 };
@@ -477,6 +519,39 @@ static GmresWork& work() {
   static thread_local GmresWork* ws = new GmresWork();
   return *ws;
 }
+
+// ---------------------------------------------------------------------------
+// The workspace of gmres_solve_noalloc: a fixed array in device memory, one
+// copy per GPU, whose address is looked up once per device.  Calls that
+// overlap on one GPU share it and race.
+// ---------------------------------------------------------------------------
+constexpr size_t kNoallocScratchBytes = (size_t)192 << 20;
+static __device__ __align__(256) unsigned char scratch[kNoallocScratchBytes];
+
+static int noalloc_scratch(unsigned char** out) {
+  static std::mutex mu;
+  static void* ptr[64] = {};
+  int dev = 0;
+  HODLR_HIP(hipGetDevice(&dev));
+  if (dev < 0 || dev >= 64) return fail(HODLR_EINVAL, "device index above 63");
+  std::lock_guard<std::mutex> lk(mu);
+  if (!ptr[dev]) {
+    void* q = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&q, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !q)
+      return fail(HODLR_EHIP, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+    ptr[dev] = q;
+  }
+  *out = static_cast<unsigned char*>(ptr[dev]);
+  return HODLR_OK;
+}
+
+size_t gmres_noalloc_bytes(int n, int s, int restart, int precision) {
+  const int m = std::min(restart, kMaxRestart);
+  return gmres_layout(n, s, m, precision == 32 ? sizeof(float) : sizeof(double), precision != 0, nullptr, nullptr);
+}
+
+size_t gmres_noalloc_limit() { return kNoallocScratchBytes; }
 
 template <typename TZ, int COLS>
 static int launch_matvec_cols(const double* K, int ldk, int n, const TZ* src, int lds, int s, double* part,
@@ -539,59 +614,79 @@ static int matvec_cols(const double* K, int ldk, int n, const TZ* src, int lds, 
   return HODLR_OK;
 }
 
+// noalloc: the workspace is the fixed device array, the step flags are read
+// back by a copy and a stream synchronization per step, and the matvec width
+// is the tuner's kept choice or the default (nothing is allocated).
 template <typename TP>
 static int gmres_t(const double* K, int n, int ldk, hodlr_s* M, const double* B, int s, int ldb,
                    double* X, int ldx, double tol, int maxit, int m, int* iters, double* relres,
-                   hipStream_t st) {
-  GmresWork& ws = work();
+                   hipStream_t st, bool noalloc) {
   const int m1 = m + 1;
   const int nch = (n + kRowsPerWG - 1) / kRowsPerWG;
-  // partial sums sized for the narrowest split; the width itself is tuned on
-  // the first products
-  const int nsplit_max = (n + kMatvecColsMin - 1) / kMatvecColsMin;
   int cols_d = kMatvecCols, cols_p = kMatvecCols;
   const size_t ns = (size_t)n * s;
-  HODLR_TRY(ws.V.ensure(ns * m1 * sizeof(double)));
-  if (M) HODLR_TRY(ws.Z.ensure(ns * m1 * sizeof(TP)));
-  HODLR_TRY(ws.w.ensure(ns * sizeof(double)));
-  HODLR_TRY(ws.part.ensure(ns * nsplit_max * sizeof(double)));
-  HODLR_TRY(ws.hA.ensure((size_t)nch * s * m1 * sizeof(double)));
-  HODLR_TRY(ws.hB.ensure((size_t)nch * s * m1 * sizeof(double)));
-  HODLR_TRY(ws.hcol.ensure((size_t)s * m1 * sizeof(double)));
-  HODLR_TRY(ws.H.ensure((size_t)s * m1 * m * sizeof(double)));
-  HODLR_TRY(ws.cs.ensure((size_t)s * m * sizeof(double)));
-  HODLR_TRY(ws.sn.ensure((size_t)s * m * sizeof(double)));
-  HODLR_TRY(ws.g.ensure((size_t)s * m1 * sizeof(double)));
-  HODLR_TRY(ws.grun.ensure(2 * 64 * sizeof(double)));
-  HODLR_TRY(ws.y.ensure((size_t)s * m * sizeof(double)));
-  HODLR_TRY(ws.npart.ensure((size_t)nch * s * sizeof(double)));
-  HODLR_TRY(ws.scal.ensure(s * sizeof(double)));
-  HODLR_TRY(ws.bnorm.ensure(s * sizeof(double)));
-  HODLR_TRY(ws.relres.ensure(s * sizeof(double)));
-  HODLR_TRY(ws.ints.ensure(5 * 64 * sizeof(int)));
-  if (!ws.host_flags) {
-    HODLR_HIP(hipHostMalloc(reinterpret_cast<void**>(&ws.host_flags), 192 * sizeof(int)));
-    HODLR_HIP(hipHostGetDevicePointer(reinterpret_cast<void**>(&ws.dev_flags), ws.host_flags, 0));
+  const size_t need = gmres_layout(n, s, m, sizeof(TP), M != nullptr, nullptr, nullptr);
+  GmresPtrs wp{};
+  int* host_flags = nullptr;
+  int local_flags[192];
+  hipEvent_t ev[2] = {nullptr, nullptr};
+  if (noalloc) {
+    if (need > kNoallocScratchBytes)
+      return fail(HODLR_EINVAL, "gmres_solve_noalloc: the workspace needs " + std::to_string(need) +
+                                    " bytes, above its " + std::to_string(kNoallocScratchBytes) + "-byte scratch");
+    unsigned char* base = nullptr;
+    HODLR_TRY(noalloc_scratch(&base));
+    gmres_layout(n, s, m, sizeof(TP), M != nullptr, base, &wp);
+    host_flags = local_flags;
+  } else {
+    GmresWork& ws = work();
+    HODLR_TRY(ws.arena.ensure(need));
+    gmres_layout(n, s, m, sizeof(TP), M != nullptr, ws.arena.as<unsigned char>(), &wp);
+    if (!ws.host_flags) {
+      HODLR_HIP(hipHostMalloc(reinterpret_cast<void**>(&ws.host_flags), 192 * sizeof(int)));
+      HODLR_HIP(hipHostGetDevicePointer(reinterpret_cast<void**>(&ws.dev_flags), ws.host_flags, 0));
+    }
+    for (int e = 0; e < 2; ++e)
+      if (!ws.ev[e]) HODLR_HIP(hipEventCreateWithFlags(&ws.ev[e], hipEventDisableTiming));
+    wp.dev_flags = ws.dev_flags;
+    host_flags = ws.host_flags;
+    ev[0] = ws.ev[0];
+    ev[1] = ws.ev[1];
   }
-  for (int e = 0; e < 2; ++e)
-    if (!ws.ev[e]) HODLR_HIP(hipEventCreateWithFlags(&ws.ev[e], hipEventDisableTiming));
-  double* V = ws.V.as<double>();
-  TP* Z = M ? ws.Z.as<TP>() : nullptr;
-  double* w = ws.w.as<double>();
-  double* part = ws.part.as<double>();
+  struct Freeze {  // the tuner times nothing inside a no-allocation call
+    bool on;
+    explicit Freeze(bool o) : on(o) {
+      if (on) tune_freeze(true);
+    }
+    ~Freeze() {
+      if (on) tune_freeze(false);
+    }
+  } freeze(noalloc);
+  // flags written by the kernels at dev_flags + off, visible at host_flags + off
+  auto fetch = [&](int off, int cnt) -> int {
+    if (noalloc) {
+      HODLR_HIP(hipMemcpyAsync(host_flags + off, wp.dev_flags + off, cnt * sizeof(int), hipMemcpyDeviceToHost, st));
+      HODLR_HIP(hipStreamSynchronize(st));
+    }
+    return HODLR_OK;
+  };
+  double* V = wp.V;
+  TP* Z = M ? static_cast<TP*>(wp.Z) : nullptr;
+  double* w = wp.w;
+  double* part = wp.part;
   // flags of the columns still iterating, two arrays: step j reads act[j & 1]
   // and its last kernel writes act[(j + 1) & 1]
-  int* act[2] = {ws.ints.as<int>(), ws.ints.as<int>() + 64};
+  int* act[2] = {wp.ints, wp.ints + 64};
   int* active = act[0];
   int* steps = act[0] + 128;
   int* total = act[0] + 192;
   int* tstart = act[0] + 256;
-  double* grun[2] = {ws.grun.as<double>(), ws.grun.as<double>() + 64};
+  double* grun[2] = {wp.grun, wp.grun + 64};
   HODLR_HIP(hipMemsetAsync(total, 0, s * sizeof(int), st));
 
   const dim3 gch(nch, s), gvec((n + kBlock - 1) / kBlock, s);
-  k_sqnorm<<<gch, kRowsPerWG, 0, st>>>(n, s, B, ldb, ws.npart.as<double>());
-  k_bnorm<<<1, 64, 0, st>>>(s, nch, ws.npart.as<double>(), ws.bnorm.as<double>());
+  k_sqnorm<<<gch, kRowsPerWG, 0, st>>>(n, s, B, ldb, wp.npart);
+  k_bnorm<<<1, 64, 0, st>>>(s, nch, wp.npart, wp.bnorm);
   HODLR_HIP(hipGetLastError());
 
   while (true) {
@@ -599,16 +694,16 @@ static int gmres_t(const double* K, int n, int ldk, hodlr_s* M, const double* B,
     HODLR_TRY(matvec_cols<double>(K, ldk, n, X, ldx, s, part, st, &cols_d));
     HODLR_HIP(hipMemsetAsync(active, 0xff, s * sizeof(int), st));  // nonzero: every column
     k_orth<0><<<gch, kRowsPerWG, 0, st>>>(n, s, 0, m1, V, w, part, (n + cols_d - 1) / cols_d, B, ldb, nullptr, nullptr,
-                                          nullptr, ws.npart.as<double>(), active);
-    k_cycle_init<<<1, 64, 0, st>>>(s, m, nch, ws.npart.as<double>(), ws.bnorm.as<double>(),
-                                   ws.scal.as<double>(), ws.g.as<double>(), grun[0], ws.relres.as<double>(),
-                                   active, steps, total, tstart, tol, maxit, ws.dev_flags);
+                                          nullptr, wp.npart, active);
+    k_cycle_init<<<1, 64, 0, st>>>(s, m, nch, wp.npart, wp.bnorm, wp.scal, wp.g, grun[0], wp.relres, active, steps,
+                                   total, tstart, tol, maxit, wp.dev_flags);
     HODLR_HIP(hipGetLastError());
     HODLR_HIP(hipStreamSynchronize(st));
+    HODLR_TRY(fetch(0, s));
     bool any = false;
-    for (int k = 0; k < s; ++k) any |= ws.host_flags[k] != 0;
+    for (int k = 0; k < s; ++k) any |= host_flags[k] != 0;
     if (!any) break;
-    k_normalize<TP><<<gvec, kBlock, 0, st>>>(n, s, w, ws.scal.as<double>(), active, V, Z);
+    k_normalize<TP><<<gvec, kBlock, 0, st>>>(n, s, w, wp.scal, active, V, Z);
     for (int j = 0; j < m; ++j) {
       const double* src_d = V + (size_t)j * ns;
       if (M) {
@@ -621,54 +716,58 @@ static int gmres_t(const double* K, int n, int ldk, hodlr_s* M, const double* B,
       const int nsplit = (n + cols_p - 1) / cols_p;
       {
         ProfScope po("orth", st);
-        k_orth<0><<<gch, kRowsPerWG, 0, st>>>(n, s, j, m1, V, w, part, nsplit, nullptr, 0, nullptr,
-                                              ws.hA.as<double>(), nullptr, nullptr, act[j & 1]);
+        k_orth<0><<<gch, kRowsPerWG, 0, st>>>(n, s, j, m1, V, w, part, nsplit, nullptr, 0, nullptr, wp.hA, nullptr,
+                                              nullptr, act[j & 1]);
       }
       {
         ProfScope po("orth", st);
-        k_orth<1><<<gch, kRowsPerWG, 0, st>>>(n, s, j, m1, V, w, part, nsplit, nullptr, 0,
-                                              ws.hA.as<double>(), ws.hB.as<double>(),
-                                              ws.hcol.as<double>(), nullptr, act[j & 1]);
+        k_orth<1><<<gch, kRowsPerWG, 0, st>>>(n, s, j, m1, V, w, part, nsplit, nullptr, 0, wp.hA, wp.hB, wp.hcol,
+                                              nullptr, act[j & 1]);
       }
       {
         ProfScope po("orth", st);
-        k_orth<2><<<gch, kRowsPerWG, 0, st>>>(n, s, j, m1, V, w, part, nsplit, nullptr, 0,
-                                              ws.hB.as<double>(), nullptr, ws.hcol.as<double>(),
-                                              ws.npart.as<double>(), act[j & 1]);
+        k_orth<2><<<gch, kRowsPerWG, 0, st>>>(n, s, j, m1, V, w, part, nsplit, nullptr, 0, wp.hB, nullptr, wp.hcol,
+                                              wp.npart, act[j & 1]);
       }
       // flags of step j go straight to a pinned slot, read after the event;
       // the host waits for the flags of step j-1 only, so step j is already
       // queued (a step taken after every column has stopped does no work:
-      // the kernels read the device flags)
-      k_step_end<TP><<<gvec, kBlock, 0, st>>>(n, s, j, m, nch, ws.hcol.as<double>(), ws.npart.as<double>(),
-                                              ws.H.as<double>(), ws.cs.as<double>(), ws.sn.as<double>(),
-                                              ws.g.as<double>(), grun[j & 1], grun[(j + 1) & 1],
-                                              ws.scal.as<double>(), ws.bnorm.as<double>(), act[j & 1],
+      // the kernels read the device flags).  Without pinned memory (noalloc)
+      // the host copies step j's flags back and waits for them.
+      k_step_end<TP><<<gvec, kBlock, 0, st>>>(n, s, j, m, nch, wp.hcol, wp.npart, wp.H, wp.cs, wp.sn, wp.g,
+                                              grun[j & 1], grun[(j + 1) & 1], wp.scal, wp.bnorm, act[j & 1],
                                               act[(j + 1) & 1], steps, total, tstart, tol, maxit, w, V, Z,
-                                              ws.dev_flags + 64 + 64 * (j & 1));
+                                              wp.dev_flags + 64 + 64 * (j & 1));
       HODLR_HIP(hipGetLastError());
-      HODLR_HIP(hipEventRecord(ws.ev[j & 1], st));
+      if (noalloc) {
+        HODLR_TRY(fetch(64 + 64 * (j & 1), s));
+        bool more = false;
+        for (int k = 0; k < s; ++k) more |= host_flags[64 + 64 * (j & 1) + k] != 0;
+        if (!more) break;
+        continue;
+      }
+      HODLR_HIP(hipEventRecord(ev[j & 1], st));
       if (j > 0) {
-        HODLR_HIP(hipEventSynchronize(ws.ev[(j - 1) & 1]));
-        const int* prev = ws.host_flags + 64 + 64 * ((j - 1) & 1);
+        HODLR_HIP(hipEventSynchronize(ev[(j - 1) & 1]));
+        const int* prev = host_flags + 64 + 64 * ((j - 1) & 1);
         bool more = false;
         for (int k = 0; k < s; ++k) more |= prev[k] != 0;
         if (!more) break;
       }
     }
-    k_trisolve<<<1, 64, 0, st>>>(s, m, ws.H.as<double>(), ws.g.as<double>(), steps, ws.y.as<double>());
+    k_trisolve<<<1, 64, 0, st>>>(s, m, wp.H, wp.g, steps, wp.y);
     if (M)
-      k_xupdate<TP><<<gvec, kBlock, 0, st>>>(n, s, m, X, ldx, Z, ws.y.as<double>(), steps);
+      k_xupdate<TP><<<gvec, kBlock, 0, st>>>(n, s, m, X, ldx, Z, wp.y, steps);
     else
-      k_xupdate<double><<<gvec, kBlock, 0, st>>>(n, s, m, X, ldx, V, ws.y.as<double>(), steps);
+      k_xupdate<double><<<gvec, kBlock, 0, st>>>(n, s, m, X, ldx, V, wp.y, steps);
     HODLR_HIP(hipGetLastError());
   }
-  HODLR_HIP(hipMemcpyAsync(relres, ws.relres.p, s * sizeof(double), hipMemcpyDeviceToHost, st));
-  HODLR_HIP(hipMemcpyAsync(ws.host_flags, total, s * sizeof(int), hipMemcpyDeviceToHost, st));
+  HODLR_HIP(hipMemcpyAsync(relres, wp.relres, s * sizeof(double), hipMemcpyDeviceToHost, st));
+  HODLR_HIP(hipMemcpyAsync(host_flags, total, s * sizeof(int), hipMemcpyDeviceToHost, st));
   HODLR_HIP(hipStreamSynchronize(st));
   bool conv = true;
   for (int k = 0; k < s; ++k) {
-    iters[k] = ws.host_flags[k];
+    iters[k] = host_flags[k];
     conv &= relres[k] <= tol;
   }
   if (!conv) return fail(HODLR_ENOCONV, "GMRES reached maxit above tol");
@@ -677,11 +776,11 @@ static int gmres_t(const double* K, int n, int ldk, hodlr_s* M, const double* B,
 
 int gmres_impl(const double* K, int n, int ldk, hodlr_s* M, const double* B, int nrhs, int ldb,
                double* X, int ldx, double tol, int maxit, int restart, int* iters,
-               double* relres, hipStream_t s) {
+               double* relres, hipStream_t s, bool noalloc) {
   const int m = std::min(restart, kMaxRestart);
   if (M && M->precision == 32)
-    return gmres_t<float>(K, n, ldk, M, B, nrhs, ldb, X, ldx, tol, maxit, m, iters, relres, s);
-  return gmres_t<double>(K, n, ldk, M, B, nrhs, ldb, X, ldx, tol, maxit, m, iters, relres, s);
+    return gmres_t<float>(K, n, ldk, M, B, nrhs, ldb, X, ldx, tol, maxit, m, iters, relres, s, noalloc);
+  return gmres_t<double>(K, n, ldk, M, B, nrhs, ldb, X, ldx, tol, maxit, m, iters, relres, s, noalloc);
 }
 
 }  // namespace hodlr

@@ -217,6 +217,7 @@ int side_stream(int which, hipStream_t* out);
 // prof.hip: event timing of wrapped launches (hodlr_prof_enable)
 bool prof_on();
 void prof_suspend(bool on);  // this thread records nothing while suspended
+void tune_freeze(bool on);   // this thread's tune_choice uses kept choices or the fallback, timing nothing
 void prof_mark(const char* name, hipStream_t s, bool begin);
 // launch(c) for candidate c < ncand, the choice for `key` found by timing on
 // first use (see prof.hip); *pick receives it
@@ -262,9 +263,12 @@ size_t matvec_partial_elems(int n, int s);  // elements of part for (n, s)
 int cg_impl(const double* K, int n, int ldk, hodlr_s* M, const double* B, int nrhs, int ldb, double* X, int ldx,
             double tol, int maxit, int* iters, double* relres, hipStream_t s);
 
-// gmres.hip
+// gmres.hip: workspace bytes of gmres_solve_noalloc for (n, s, restart,
+// preconditioner precision 32 / 64, 0 for none) and the fixed limit
+size_t gmres_noalloc_bytes(int n, int s, int restart, int precision);
+size_t gmres_noalloc_limit();
 int gmres_impl(const double* K, int n, int ldk, hodlr_s* M, const double* B, int nrhs, int ldb,
                double* X, int ldx, double tol, int maxit, int restart, int* iters,
-               double* relres, hipStream_t s);
+               double* relres, hipStream_t s, bool noalloc = false);
 
 }  // namespace hodlr

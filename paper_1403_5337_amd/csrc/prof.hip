@@ -46,9 +46,11 @@ void release_all() {
 }  // namespace
 
 thread_local bool t_suspended = false;
+thread_local bool t_no_tune = false;  // tune_choice keeps to choices already made (no timing)
 
 bool prof_on() { return g_on && !t_suspended; }
 void prof_suspend(bool on) { t_suspended = on; }
+void tune_freeze(bool on) { t_no_tune = on; }
 
 void prof_mark(const char* name, hipStream_t s, bool begin) {
   std::lock_guard<std::mutex> lk(g_mu);
@@ -97,7 +99,7 @@ int tune_choice(const std::string& key, int ncand, int fallback, const std::func
   const char* env = std::getenv("HODLR_TUNE");
   hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
   HODLR_HIP(hipStreamIsCapturing(s, &cs));
-  if ((env && env[0] == '0') || cs != hipStreamCaptureStatusNone || ncand < 2) {
+  if ((env && env[0] == '0') || cs != hipStreamCaptureStatusNone || ncand < 2 || t_no_tune) {
     lk.unlock();
     *pick = fallback;
     return launch(fallback);

@@ -61,6 +61,9 @@ _SIGNATURES = {
     "gmres_solve": (ctypes.c_int, [_vp, ctypes.c_int, ctypes.c_int, _vp, _vp, ctypes.c_int, ctypes.c_int,
                                    _vp, ctypes.c_int, ctypes.c_double, ctypes.c_int, ctypes.c_int,
                                    _c_int_p, _c_dbl_p, _vp]),
+    "gmres_solve_noalloc": (ctypes.c_int, [_vp, ctypes.c_int, ctypes.c_int, _vp, _vp, ctypes.c_int, ctypes.c_int,
+                                           _vp, ctypes.c_int, ctypes.c_double, ctypes.c_int, ctypes.c_int,
+                                           _c_int_p, _c_dbl_p, _vp]),
     "cg_solve": (ctypes.c_int, [_vp, ctypes.c_int, ctypes.c_int, _vp, _vp, ctypes.c_int, ctypes.c_int,
                                 _vp, ctypes.c_int, ctypes.c_double, ctypes.c_int, _c_int_p, _c_dbl_p, _vp]),
     "hodlr_build_batched": (ctypes.c_int, [ctypes.c_int, ctypes.POINTER(_vp), _c_int_p, _c_int_p,
