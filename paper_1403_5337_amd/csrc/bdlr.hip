@@ -105,6 +105,8 @@ __device__ void pick_side(const uint8_t* d, int len, int depth, int max_skel, in
   __syncthreads();
 }
 
+constexpr int kSelNb = 8;  // neighbour indices loaded together
+
 __global__ void __launch_bounds__(kBlock)
     k_bdlr_select(const int* __restrict__ rowptr, const int* __restrict__ col,
                   const BdlrTask* __restrict__ tasks, int depth, int max_skel, int stride, int* __restrict__ sel,
@@ -114,50 +116,45 @@ __global__ void __launch_bounds__(kBlock)
   const BdlrTask tk = tasks[blockIdx.x];
   const int t = threadIdx.x;
   const int r0 = tk.row0, r1 = tk.row0 + tk.m, c0 = tk.col0, c1 = tk.col0 + tk.nc;
-  // boundary sets: an edge into the other set
-  for (int i = t; i < tk.m; i += kBlock) {
-    const int v = r0 + i;
-    uint8_t dv = 255;
-    for (int e = rowptr[v]; e < rowptr[v + 1]; ++e) {
-      const int u = col[e];
-      if (u >= c0 && u < c1) {
-        dv = 0;
-        break;
+  // boundary sets: an edge into the other set (neighbour lists read
+  // kSelNb entries at a time, the loads issued together)
+  for (int sd = 0; sd < 2; ++sd) {
+    const int s0 = sd == 0 ? r0 : c0, len = sd == 0 ? tk.m : tk.nc;
+    const int o0 = sd == 0 ? c0 : r0, o1 = sd == 0 ? c1 : r1;
+    uint8_t* d = sd == 0 ? dI : dJ;
+    for (int i = t; i < len; i += kBlock) {
+      const int v = s0 + i, e1 = rowptr[v + 1];
+      uint8_t dv = 255;
+      for (int e0 = rowptr[v]; e0 < e1 && dv != 0; e0 += kSelNb) {
+        int u[kSelNb];
+#pragma unroll
+        for (int k = 0; k < kSelNb; ++k) u[k] = e0 + k < e1 ? col[e0 + k] : -1;
+#pragma unroll
+        for (int k = 0; k < kSelNb; ++k)
+          if (u[k] >= o0 && u[k] < o1) dv = 0;
       }
+      d[i] = dv;
     }
-    dI[i] = dv;
-  }
-  for (int j = t; j < tk.nc; j += kBlock) {
-    const int v = c0 + j;
-    uint8_t dv = 255;
-    for (int e = rowptr[v]; e < rowptr[v + 1]; ++e) {
-      const int u = col[e];
-      if (u >= r0 && u < r1) {
-        dv = 0;
-        break;
-      }
-    }
-    dJ[j] = dv;
   }
   __syncthreads();
   // breadth-first layers inside each set: the vertices of layer lvl mark
   // their unmarked out-neighbours in the same set (benign races: every
   // writer of a vertex writes the same layer number)
   for (int lvl = 0; lvl + 1 < depth; ++lvl) {
-    for (int i = t; i < tk.m; i += kBlock) {
-      if (dI[i] != lvl) continue;
-      const int v = r0 + i;
-      for (int e = rowptr[v]; e < rowptr[v + 1]; ++e) {
-        const int u = col[e];
-        if (u >= r0 && u < r1 && dI[u - r0] == 255) dI[u - r0] = (uint8_t)(lvl + 1);
-      }
-    }
-    for (int j = t; j < tk.nc; j += kBlock) {
-      if (dJ[j] != lvl) continue;
-      const int v = c0 + j;
-      for (int e = rowptr[v]; e < rowptr[v + 1]; ++e) {
-        const int u = col[e];
-        if (u >= c0 && u < c1 && dJ[u - c0] == 255) dJ[u - c0] = (uint8_t)(lvl + 1);
+    for (int sd = 0; sd < 2; ++sd) {
+      const int s0 = sd == 0 ? r0 : c0, s1 = sd == 0 ? r1 : c1, len = s1 - s0;
+      uint8_t* d = sd == 0 ? dI : dJ;
+      for (int i = t; i < len; i += kBlock) {
+        if (d[i] != lvl) continue;
+        const int v = s0 + i, e1 = rowptr[v + 1];
+        for (int e0 = rowptr[v]; e0 < e1; e0 += kSelNb) {
+          int u[kSelNb];
+#pragma unroll
+          for (int k = 0; k < kSelNb; ++k) u[k] = e0 + k < e1 ? col[e0 + k] : -1;
+#pragma unroll
+          for (int k = 0; k < kSelNb; ++k)
+            if (u[k] >= s0 && u[k] < s1 && d[u[k] - s0] == 255) d[u[k] - s0] = (uint8_t)(lvl + 1);
+        }
       }
     }
     __syncthreads();

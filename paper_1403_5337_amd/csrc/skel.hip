@@ -57,7 +57,11 @@ __device__ float block_max(float v, float* red) {
 // that side, both sides in one level loop.  dist[sd]: LDS, len entries;
 // 0xffff = not reached.  Side 0 is [a0, a0+alen), side 1 [b0, b0+blen)
 // (contiguous ranges of vertex ids); the boundary of a side is its vertices
-// with an edge into the other side.
+// with an edge into the other side.  A vertex's neighbour list is read kNb
+// entries at a time with the loads issued together (the lists are long on
+// 3-dof meshes, and each read is a round trip to the cache).
+constexpr int kNb = 8;
+
 __device__ void block_bfs(const int* __restrict__ rowptr, const int* __restrict__ col, int a0, int alen, int b0,
                           int blen, unsigned short (*dist)[kSideMax], int* s_changed) {
   const int t = threadIdx.x;
@@ -65,14 +69,15 @@ __device__ void block_bfs(const int* __restrict__ rowptr, const int* __restrict_
     const int s0 = sd == 0 ? a0 : b0, len = sd == 0 ? alen : blen;
     const int o0 = sd == 0 ? b0 : a0, olen = sd == 0 ? blen : alen;
     for (int i = t; i < len; i += kBlock) {
-      const int v = s0 + i;
+      const int v = s0 + i, e1 = rowptr[v + 1];
       unsigned short d = 0xffff;
-      for (int e = rowptr[v]; e < rowptr[v + 1]; ++e) {
-        const int u = col[e];
-        if (u >= o0 && u < o0 + olen) {
-          d = 0;
-          break;
-        }
+      for (int e0 = rowptr[v]; e0 < e1 && d != 0; e0 += kNb) {
+        int u[kNb];
+#pragma unroll
+        for (int k = 0; k < kNb; ++k) u[k] = e0 + k < e1 ? col[e0 + k] : -1;
+#pragma unroll
+        for (int k = 0; k < kNb; ++k)
+          if (u[k] >= o0 && u[k] < o0 + olen) d = 0;
       }
       dist[sd][i] = d;
     }
@@ -88,13 +93,17 @@ __device__ void block_bfs(const int* __restrict__ rowptr, const int* __restrict_
       const int s0 = sd == 0 ? a0 : b0, len = sd == 0 ? alen : blen;
       for (int i = t; i < len; i += kBlock) {
         if (dist[sd][i] != lvl) continue;
-        const int v = s0 + i;
-        for (int e = rowptr[v]; e < rowptr[v + 1]; ++e) {
-          const int u = col[e];
-          if (u >= s0 && u < s0 + len && dist[sd][u - s0] == 0xffff) {
-            dist[sd][u - s0] = (unsigned short)(lvl + 1);
-            ch = 1;
-          }
+        const int v = s0 + i, e1 = rowptr[v + 1];
+        for (int e0 = rowptr[v]; e0 < e1; e0 += kNb) {
+          int u[kNb];
+#pragma unroll
+          for (int k = 0; k < kNb; ++k) u[k] = e0 + k < e1 ? col[e0 + k] : -1;
+#pragma unroll
+          for (int k = 0; k < kNb; ++k)
+            if (u[k] >= s0 && u[k] < s0 + len && dist[sd][u[k] - s0] == 0xffff) {
+              dist[sd][u[k] - s0] = (unsigned short)(lvl + 1);
+              ch = 1;
+            }
         }
       }
     }
