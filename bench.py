@@ -145,27 +145,32 @@ def cpu_baseline(front, w, nrhs_sample, method, depth, solver="gmres", budget_s=
 
 
 # HBM bytes per launch from rocprofv3 FETCH_SIZE / WRITE_SIZE runs of this
-# bench (profiles/tpfa4096_hbm_counters.md), calibrated by a 256 MiB copy
-# (FETCH_SIZE reads half the bytes moved, WRITE_SIZE all of them).  The
-# figures belong to the kernel source they were taken with: a changed source
-# reports traffic = null until the counters are taken again.
+# bench (profiles/*_hbm_counters.md), calibrated by a 256 MiB copy
+# (FETCH_SIZE reads half the bytes moved, WRITE_SIZE all of them), per
+# (kernel, workload).  The figures belong to the kernel source they were
+# taken with: a changed source reports traffic = null until the counters are
+# taken again.
 TRAFFIC = {
-    "apply_level": {"source": "paper_1403_5337_amd/csrc/solve.hip",
-                    "sha256": "792a556e9f24caac7c69b9f5dd5185421785192b1fc8398ea7f456996596c677",
-                    "workload": "tpfa4096", "fetch_kib": 1598.0, "write_kib": 236.0,
-                    "fetch_factor": 2.0, "write_factor": 1.0, "rocprof_avg_us": 7.94},
-    # the float64 product on float32 z, the width the tuner keeps on this front (512 columns as 4 chunks)
-    "matvec": {"source": "paper_1403_5337_amd/csrc/gmres.hip",
-               "sha256": "195835287e5149775f5607f87b5b079ae0d7a402d704c836da93e604c71ba018",
-               "workload": "tpfa4096", "fetch_kib": 66135.0, "write_kib": 2048.0,
-               "fetch_factor": 2.0, "write_factor": 1.0, "rocprof_avg_us": 23.95},
+    ("apply_level", "tpfa4096"): {"source": "paper_1403_5337_amd/csrc/solve.hip",
+                                  "sha256": "792a556e9f24caac7c69b9f5dd5185421785192b1fc8398ea7f456996596c677",
+                                  "fetch_kib": 1598.0, "write_kib": 236.0,
+                                  "fetch_factor": 2.0, "write_factor": 1.0, "rocprof_avg_us": 7.94},
+    ("apply_level", "elastic6144"): {"source": "paper_1403_5337_amd/csrc/solve.hip",
+                                     "sha256": "792a556e9f24caac7c69b9f5dd5185421785192b1fc8398ea7f456996596c677",
+                                     "fetch_kib": 4421.4, "write_kib": 67.3,
+                                     "fetch_factor": 2.0, "write_factor": 1.0, "rocprof_avg_us": 12.94},
+    # the float64 product on float32 z (the width the tuner kept in that run)
+    ("matvec", "elastic6144"): {"source": "paper_1403_5337_amd/csrc/gmres.hip",
+                                "sha256": "13c5b3d369c8543ea62a0cd8002c8bd092dfc146eef830eccd8be950a349b90b",
+                                "fetch_kib": 147582.5, "write_kib": 2304.0,
+                                "fetch_factor": 2.0, "write_factor": 1.0, "rocprof_avg_us": 49.16},
 }
 
 
 def measured_traffic(name, workload):
     import hashlib
-    t = TRAFFIC.get(name)
-    if not t or t["workload"] != workload:
+    t = TRAFFIC.get((name, workload))
+    if not t:
         return None, None
     path = os.path.join(os.path.dirname(os.path.abspath(__file__)), t["source"])
     try:

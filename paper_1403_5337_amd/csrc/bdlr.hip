@@ -732,10 +732,13 @@ __device__ void topk_side(const unsigned* key, int len, int k, int* out, int* co
   __syncthreads();
 }
 
-// |K(I, J)|_F^2 of every block, in kNormChunks column chunks per block; a
-// thread keeps four loads in flight (a chunk is read as one flat range of
-// column-major entries).
-constexpr int kNormChunks = 64;
+// |K(I, J)|_F^2 of every block, in kNormChunks column chunks per block (a
+// chunk of a small block may be empty); a thread keeps eight loads in flight
+// (a chunk is read as one flat range of column-major entries).  Many chunks
+// per block keep the largest blocks spread over many workgroups.
+// k_norm_total then adds a block's chunks in a fixed order into its first
+// slot, which is what the checks read.
+constexpr int kNormChunks = 256;
 __global__ void __launch_bounds__(kBlock)
     k_block_norm2(const double* __restrict__ K, int ldk, const BdlrTask* __restrict__ tasks,
                   double* __restrict__ part) {
@@ -743,19 +746,32 @@ __global__ void __launch_bounds__(kBlock)
   const BdlrTask tk = tasks[blockIdx.x];
   const int per = (tk.nc + kNormChunks - 1) / kNormChunks, j0 = blockIdx.y * per, j1 = min(tk.nc, j0 + per);
   const long tot = j1 > j0 ? (long)tk.m * (j1 - j0) : 0;
+  constexpr int kU = 8;
   double acc = 0.0;
-  for (long e0 = threadIdx.x; e0 < tot; e0 += 4 * kBlock) {
-    double v[4];
+  for (long e0 = threadIdx.x; e0 < tot; e0 += kU * kBlock) {
+    double v[kU];
 #pragma unroll
-    for (int u = 0; u < 4; ++u) {
+    for (int u = 0; u < kU; ++u) {
       const long e = e0 + (long)u * kBlock;
       v[u] = e < tot ? K[(size_t)(tk.col0 + j0 + e / tk.m) * ldk + tk.row0 + e % tk.m] : 0.0;
     }
 #pragma unroll
-    for (int u = 0; u < 4; ++u) acc += v[u] * v[u];
+    for (int u = 0; u < kU; ++u) acc += v[u] * v[u];
   }
   acc = block_sum(acc, red);
   if (threadIdx.x == 0) part[(size_t)blockIdx.x * kNormChunks + blockIdx.y] = acc;
+}
+
+// One wave per block: lane l adds chunks l, l + 64, ... in order, then the
+// lanes are combined by a fixed butterfly; the total goes to chunk slot 0.
+__global__ void __launch_bounds__(64) k_norm_total(double* __restrict__ part) {
+  double* p = part + (size_t)blockIdx.x * kNormChunks;
+  const int lane = threadIdx.x;
+  double s = 0.0;
+  for (int c = lane; c < kNormChunks; c += 64) s += p[c];
+  for (int o = 1; o < 64; o <<= 1) s += __shfl_xor(s, o, 64);
+  __syncthreads();
+  if (lane == 0) p[0] = s;
 }
 
 // Estimated relative Frobenius error of U V^T on the block: the residual on
@@ -858,8 +874,7 @@ __global__ void k_skel_err(const BdlrTask* __restrict__ tasks, int ntask, const 
     const int outside = (side == 0 ? tk.m : tk.nc) - counts[2 * x + side];
     if (used > 0) est = fmax(est, num * (double)outside / (double)used);
   }
-  double nb = 0.0;
-  for (int c = 0; c < kNormChunks; ++c) nb += norm2[(size_t)tk.task * kNormChunks + c];
+  const double nb = norm2[(size_t)tk.task * kNormChunks];  // the block's total (k_norm_total)
   err[x] = nb > 0.0 ? sqrt(est / nb) : sqrt(est);
 }
 
@@ -972,6 +987,8 @@ static int block_norms(const double* K, int ldk, const std::vector<BdlrTask>& ta
   HODLR_HIP(hipMemcpyAsync(sc.tasks.p, tasks.data(), nt * sizeof(BdlrTask), hipMemcpyHostToDevice, s));
   ProfScope prof("skel_check", s);
   k_block_norm2<<<dim3(nt, kNormChunks), kBlock, 0, s>>>(K, ldk, sc.tasks.as<BdlrTask>(), sc.norm.as<double>());
+  HODLR_HIP(hipGetLastError());
+  k_norm_total<<<nt, 64, 0, s>>>(sc.norm.as<double>());
   HODLR_HIP(hipGetLastError());
   return HODLR_OK;
 }
@@ -1256,8 +1273,7 @@ __global__ void k_cand_err(const BdlrTask* __restrict__ tasks, int nt, const int
     const double e = exact + (used > 0 ? sampled * (double)outside / (double)used : 0.0);
     est = fmax(est, e);
   }
-  double nb = 0.0;
-  for (int c = 0; c < kNormChunks; ++c) nb += norm2[(size_t)tk.task * kNormChunks + c];
+  const double nb = norm2[(size_t)tk.task * kNormChunks];  // the block's total (k_norm_total)
   err[x] = nb > 0.0 ? sqrt(est / nb) : sqrt(est);
 }
 

@@ -126,6 +126,75 @@ __global__ void __launch_bounds__(kBlock)
   }
 }
 
+// The same product in float32 on the matrix cores (v_mfma_f32_32x32x2f32):
+// one workgroup per (leaf, 64-column tile of Z); the leaf inverse and the
+// tile go to LDS by asynchronous copies (inner dimension padded to even with
+// zeros, inverse rows to a multiple of 32), each of the four waves computes
+// up to three 32 x 32 output quarters, and the tile is written back in place
+// (every read of it precedes the writes).  Used while both fit in LDS.
+typedef float f32x16 __attribute__((ext_vector_type(16)));
+
+static size_t leaf_apply_mfma_lds(int bmax) {
+  const int nrt = (bmax + 31) / 32, bp = (bmax + 7) & ~7, ld = 32 * nrt + 1;
+  return (size_t)(bp + 64) * ld * sizeof(float);
+}
+
+__global__ void __launch_bounds__(kBlock)
+    k_leaf_apply_mfma(const float* __restrict__ Kinv, int bmax, const int* __restrict__ lo,
+                      const int* __restrict__ hi, int id0, float* __restrict__ Z, int ldz, int ncols) {
+  extern __shared__ __align__(16) float lsm[];
+  const int leaf = blockIdx.x, c0 = blockIdx.y * 64, id = id0 + leaf, t = threadIdx.x;
+  const int lane = t & 63, w = t >> 6, kl = lane >> 5, r32 = lane & 31;
+  const int l0 = lo[id], b = hi[id] - l0, nc = min(64, ncols - c0);
+  // inner dimension padded to a multiple of 8 (four MFMA steps per round)
+  const int nrt = (b + 31) / 32, bp = (b + 7) & ~7, ld = 32 * nrt + 1;
+  float* Ks = lsm;            // column k at Ks + k ld, rows [0, 32 nrt)
+  float* Zs = lsm + bp * ld;  // column j at Zs + j ld, rows [0, bp)
+  const float* Ki = Kinv + (size_t)leaf * bmax * bmax;
+  for (int k = w; k < b; k += kBlock / 64) dma_span(Ks + (size_t)k * ld, Ki + (size_t)k * bmax, b);
+  for (int j = w; j < nc; j += kBlock / 64) dma_span(Zs + (size_t)j * ld, Z + (size_t)(c0 + j) * ldz + l0, b);
+  // zeros outside what the copies fill
+  const int tail = 32 * nrt - b;
+  for (int e = t; e < b * tail; e += kBlock) Ks[(size_t)(e / tail) * ld + b + e % tail] = 0.f;
+  for (int e = t; e < (bp - b) * 32 * nrt; e += kBlock) Ks[(size_t)(b + e / (32 * nrt)) * ld + e % (32 * nrt)] = 0.f;
+  for (int e = t; e < nc * (bp - b); e += kBlock) Zs[(size_t)(e / (bp - b)) * ld + b + e % (bp - b)] = 0.f;
+  for (int e = t; e < (64 - nc) * bp; e += kBlock) Zs[(size_t)(nc + e / bp) * ld + e % bp] = 0.f;
+  dma_wait();
+  // wave w: quarters w, w + 4, w + 8 (row tiles w / 2, w / 2 + 2, w / 2 + 4,
+  // all in column tile w % 2), updated together so their products overlap
+  const int ct = w & 1, rt0 = w >> 1;
+  const int nq = min(3, (nrt - rt0 + 1) / 2);
+  if (nq <= 0) return;
+  f32x16 acc[3] = {f32x16{}, f32x16{}, f32x16{}};
+  const float* Bp = Zs + (size_t)(32 * ct + r32) * ld + kl;
+  const float* Ap = Ks + 32 * rt0 + r32 + (size_t)kl * ld;
+  for (int k = 0; k < bp; k += 8) {
+    float bv[4], av[3][4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      bv[u] = Bp[k + 2 * u];
+#pragma unroll
+      for (int qi = 0; qi < 3; ++qi) av[qi][u] = qi < nq ? Ap[(size_t)(k + 2 * u) * ld + 64 * qi] : 0.f;
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+#pragma unroll
+      for (int qi = 0; qi < 3; ++qi)
+        if (qi < nq) acc[qi] = __builtin_amdgcn_mfma_f32_32x32x2f32(av[qi][u], bv[u], acc[qi], 0, 0, 0);
+  }
+  // D(v) at lane l: row 8 (v / 4) + 4 (l / 32) + v % 4, column l % 32
+#pragma unroll
+  for (int qi = 0; qi < 3; ++qi) {
+    if (qi >= nq) break;
+    const int rt = rt0 + 2 * qi;
+#pragma unroll
+    for (int v = 0; v < 16; ++v) {
+      const int i = 32 * rt + 8 * (v >> 2) + 4 * kl + (v & 3), j = 32 * ct + r32;
+      if (i < b && j < nc) Z[(size_t)(c0 + j) * ldz + l0 + i] = acc[qi][v];
+    }
+  }
+}
+
 __global__ void k_fill_int(int* p, int n, int v) {
   for (int i = threadIdx.x; i < n; i += blockDim.x) p[i] = v;
 }
@@ -684,8 +753,16 @@ static int factor_t(hodlr_s* h, hipStream_t s) {
   T* Y = h->Y.as<T>();
   {
     ProfScope prof_("leaf_apply", s);
-    k_leaf_apply<T, kCT><<<dim3(h->nleaf, cdiv(h->R, kCT)), kBlock, 0, s>>>(
-        h->Kinv.as<T>(), h->bmax, h->d_lo.as<int>(), h->d_hi.as<int>(), node_id(L, 0), Y, n, h->R);
+    const size_t lds = leaf_apply_mfma_lds(h->bmax);
+    if (sizeof(T) == 4 && lds <= 160 * 1024) {
+      HODLR_TRY(allow_lds(k_leaf_apply_mfma, lds));
+      k_leaf_apply_mfma<<<dim3(h->nleaf, cdiv(h->R, 64)), kBlock, lds, s>>>(
+          reinterpret_cast<const float*>(h->Kinv.p), h->bmax, h->d_lo.as<int>(), h->d_hi.as<int>(), node_id(L, 0),
+          reinterpret_cast<float*>(Y), n, h->R);
+    } else {
+      k_leaf_apply<T, kCT><<<dim3(h->nleaf, cdiv(h->R, kCT)), kBlock, 0, s>>>(
+          h->Kinv.as<T>(), h->bmax, h->d_lo.as<int>(), h->d_hi.as<int>(), node_id(L, 0), Y, n, h->R);
+    }
   }
   HODLR_HIP(hipGetLastError());
   HODLR_TRY(factor_levels<T>(h, s, false));

@@ -224,30 +224,78 @@ __device__ void stage_params(const float* __restrict__ P, int bf16, float* W) {
 }
 
 // logits of N samples, grid-stride over samples
+// Forward pass on the matrix cores (v_mfma_f32_32x32x2f32, float32 products
+// and accumulation), one wave per 32 samples, computed transposed so that no
+// layer's output has to be re-laid out: layer 1 is W1 (64 x 8) times X^T
+// (8 x 32 samples); in the result lane l holds, for sample l % 32, the
+// hidden units 32 t + 8 (v / 4) + 4 (l / 32) + v % 4 of its registers v.
+// Layer 2 (W2 times H1^T) takes those registers directly as its B operand:
+// at step (t, v) lanes < 32 supply hidden unit 32 t + 8 (v / 4) + v % 4 and
+// lanes >= 32 the unit 4 above it, so A supplies W2's column of the same
+// unit, lane by lane.  Layer 3 is a dot product per lane, the two lanes of
+// a sample added at the end.  The weights sit in LDS with padded rows.
+typedef float f32x16 __attribute__((ext_vector_type(16)));
+
 __global__ void __launch_bounds__(kBlock)
     k_mlp_forward(const float* __restrict__ X, int N, const float* __restrict__ P, int bf16,
                   float* __restrict__ z_out) {
-  __shared__ float W[NP];
-  stage_params(P, bf16, W);
-  for (int s = blockIdx.x * kBlock + threadIdx.x; s < N; s += gridDim.x * kBlock) {
-    float x[NF], h1[HD];
+  __shared__ float W1s[HD][NF + 1], W2s[HD][HD + 1], b1s[HD], b2s[HD], w3s[HD], b3s;
+  const int t = threadIdx.x, lane = t & 63, kl = lane >> 5, r32 = lane & 31;
+  for (int e = t; e < HD * NF; e += kBlock) {
+    const float w = P[OW1 + e];
+    W1s[e / NF][e % NF] = bf16 ? bf16_round(w) : w;
+  }
+  for (int e = t; e < HD * HD; e += kBlock) {
+    const float w = P[OW2 + e];
+    W2s[e / HD][e % HD] = bf16 ? bf16_round(w) : w;
+  }
+  if (t < HD) {
+    b1s[t] = bf16 ? bf16_round(P[OB1 + t]) : P[OB1 + t];
+    b2s[t] = bf16 ? bf16_round(P[OB2 + t]) : P[OB2 + t];
+    w3s[t] = bf16 ? bf16_round(P[OW3 + t]) : P[OW3 + t];
+  }
+  if (t == 0) b3s = bf16 ? bf16_round(P[OB3]) : P[OB3];
+  __syncthreads();
+  const int waves = gridDim.x * (kBlock / 64);
+  for (int tile = blockIdx.x * (kBlock / 64) + (t >> 6); tile * 32 < N; tile += waves) {
+    const int sm = tile * 32 + r32;
+    const bool live = sm < N;
+    f32x16 acc1[2] = {f32x16{}, f32x16{}};
 #pragma unroll
-    for (int a = 0; a < NF; ++a) x[a] = X[(size_t)s * NF + a];
+    for (int step = 0; step < NF / 2; ++step) {
+      const int f = 2 * step + kl;
+      const float b = live ? X[(size_t)sm * NF + f] : 0.f;
 #pragma unroll
-    for (int o = 0; o < HD; ++o) {
-      float a1 = W[OB1 + o];
-#pragma unroll
-      for (int a = 0; a < NF; ++a) a1 = fmaf(W[OW1 + o * NF + a], x[a], a1);
-      h1[o] = fmaxf(a1, 0.f);
+      for (int tt = 0; tt < 2; ++tt) acc1[tt] = __builtin_amdgcn_mfma_f32_32x32x2f32(W1s[32 * tt + r32][f], b, acc1[tt], 0, 0, 0);
     }
-    float z = W[OB3];
-    for (int o = 0; o < HD; ++o) {
-      float a2 = W[OB2 + o];
 #pragma unroll
-      for (int i = 0; i < HD; ++i) a2 = fmaf(W[OW2 + o * HD + i], h1[i], a2);
-      z = fmaf(W[OW3 + o], fmaxf(a2, 0.f), z);
-    }
-    z_out[s] = z;
+    for (int tt = 0; tt < 2; ++tt)
+#pragma unroll
+      for (int v = 0; v < 16; ++v) {
+        const int h = 32 * tt + 8 * (v >> 2) + 4 * kl + (v & 3);
+        acc1[tt][v] = fmaxf(acc1[tt][v] + b1s[h], 0.f);
+      }
+    f32x16 acc2[2] = {f32x16{}, f32x16{}};
+#pragma unroll
+    for (int tt = 0; tt < 2; ++tt)
+#pragma unroll
+      for (int v = 0; v < 16; ++v) {
+        const int h = 32 * tt + 8 * (v >> 2) + 4 * kl + (v & 3);
+        const float b = acc1[tt][v];
+#pragma unroll
+        for (int ot = 0; ot < 2; ++ot)
+          acc2[ot] = __builtin_amdgcn_mfma_f32_32x32x2f32(W2s[32 * ot + r32][h], b, acc2[ot], 0, 0, 0);
+      }
+    float zp = 0.f;
+#pragma unroll
+    for (int ot = 0; ot < 2; ++ot)
+#pragma unroll
+      for (int v = 0; v < 16; ++v) {
+        const int o = 32 * ot + 8 * (v >> 2) + 4 * kl + (v & 3);
+        zp = fmaf(w3s[o], fmaxf(acc2[ot][v] + b2s[o], 0.f), zp);
+      }
+    zp += __shfl_xor(zp, 32, 64);
+    if (kl == 0 && live) z_out[sm] = zp + b3s;
   }
 }
 
@@ -441,7 +489,8 @@ int launch_skel_labels(const std::vector<SkelBlock>& blocks, const int* piv, int
 
 int launch_mlp_forward(const float* X, int N, const float* P, int bf16, float* z, hipStream_t s) {
   if (N <= 0) return HODLR_OK;
-  const int grid = std::min(1024, (N + kBlock - 1) / kBlock);
+  const int tiles = (N + 31) / 32, per_wg = kBlock / 64;
+  const int grid = std::min(2048, (tiles + per_wg - 1) / per_wg);
   k_mlp_forward<<<grid, kBlock, 0, s>>>(X, N, P, bf16, z);
   HODLR_HIP(hipGetLastError());
   return HODLR_OK;
