@@ -390,8 +390,10 @@ int hodlr_skel_info(hodlr_t h, int* kused);
  *   x, y, z scaled to [0, 1] over the bounding box of S (0 on a flat axis)
  *   |K_vv| / max on S
  *   min(1, distance from v to the bounding box of O / diagonal of S's box)
- * g_rowptr/g_col/coords/K as for hodlr_build; feats: device, 2 n L x 8.
- * Asynchronous.  Errors: EINVAL (2 <= n <= 16384, n > leaf), ENOMEM, EHIP. */
+ * g_rowptr/g_col/coords/K as for hodlr_build; feats: device, 2 n L x 8,
+ * 16-byte aligned (each sample is written as two 16-byte stores).
+ * Asynchronous.  Errors: EINVAL (2 <= n <= 16384, n > leaf, feats not
+ * 16-byte aligned), ENOMEM, EHIP. */
 int hodlr_skel_features(const int* g_rowptr, const int* g_col, const float* coords, const double* K, int n,
                         int ldk, int leaf, float* feats, hipStream_t stream);
 

@@ -2,6 +2,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <cstdint>
 #include <map>
 #include <memory>
 #include <condition_variable>
@@ -1029,6 +1030,7 @@ int hodlr_skel_features(const int* g_rowptr, const int* g_col, const float* coor
   if (n < 2 || n > 16384) return fail(HODLR_EINVAL, "n must be in [2, 16384]");
   if (ldk < n) return fail(HODLR_EINVAL, "ldk < n");
   if (leaf < 1 || leaf > kLeafMax) return fail(HODLR_EINVAL, "leaf out of range");
+  if (reinterpret_cast<uintptr_t>(feats) % 16) return fail(HODLR_EINVAL, "feats must be 16-byte aligned");
   Tree t;
   t.build(n, leaf);
   if (t.L == 0) return fail(HODLR_EINVAL, "n <= leaf: the tree has no off-diagonal blocks");

@@ -36,7 +36,7 @@ struct BdlrTask {
   int samp0;     // first sample of the block in the learned proposer's numbering
   int capcol, kmax;
   int sel_off;   // ints: rows at sel_off, columns at sel_off + max_skel
-  size_t inv_off;  // elements: U11^-1 then L11^-T, max_skel^2 each
+  size_t inv_off;  // elements: G = Ahat11^-1 (r x r, column-major), max_skel^2 reserved
   size_t cg_off;   // elements: C panel (m x kmax) then R^T panel (nc x kmax)
   int task;        // position in the build's whole task list (attempt loops)
 };
@@ -166,24 +166,39 @@ __global__ void __launch_bounds__(kBlock)
 
 // Full-pivot elimination of Ahat held in registers: thread (lane, w) of the
 // NW waves owns rows lane + 64 a and columns w + NW b of the tile.  Nothing
-// moves: a pivot column is retired (skipped from then on, a wave-uniform
-// bit), and a pivot row is zeroed by its own update (its multiplier is p/p =
-// 1, so each entry becomes x - x = 0) and stays zero, so the largest |entry|
-// over the active columns is the pivot search over the Schur complement with
-// no row mask.  A step tracks only the per-row maxima during the update; the
+// moves: a pivot column and a pivot row are retired (a wave-uniform column
+// bit, a per-lane row bit) and drop out of the pivot search, which is the
+// largest |entry| of the Schur complement (ties: lowest row, then lowest
+// column).  A step tracks only the per-row maxima during the update; the
 // waves' maxima are combined across one barrier, then the one wave holding
-// the maximum finds its position (lowest row, then lowest column, by ballots)
-// and publishes the pivot column before the second barrier.  Equal maxima in
-// several waves take a third barrier to agree on the lowest position.  Only
-// the pivot sequence is kept (prow, pcol: positions in Ahat).  With 16 waves
-// (1024 threads) every SIMD runs four waves, which keeps its VALU busy while
-// each wave waits on its own instruction stream.
+// the maximum finds its position (the lowest row by a ballot per register
+// row, then the lowest column by a ballot per register column) and
+// publishes the pivot column before the second barrier.  Equal maxima in
+// several waves take a third barrier to agree on the lowest position.  The
+// pivot sequence is kept (prow, pcol: positions in Ahat).  Sixteen waves
+// (four per SIMD) keep the VALU busy while each wave waits on its own chain
+// of cross-lane steps; eight wider waves measured slower.
+//
+// Every step is also the exchange (Gauss-Jordan) step on the retired rows and
+// columns, so the inverse of the pivot block comes out of the same sweep.
+// With pivot p at (pr, pc), multipliers l = x(:, pc) / p and pivot row v =
+// x(pr, :), the exchange step sets every other entry to x - l v, the pivot
+// column to l, the pivot row to -v / p and the pivot to 1 / p.  Here the
+// pivot row is kept as v with -1 at the pivot, i.e. -p times its exchanged
+// value (its multiplier is taken as 0): the later steps act on each row
+// linearly, so the row keeps that factor, and it is divided out once at the
+// end.  After r steps the entry at (pivot row k, pivot column l), divided by
+// -p_k, is Ahat11^-1 (k, l), with Ahat11 = Ahat(pivot rows, pivot columns)
+// in pivot order; it is written to G (r x r, column-major).  The retired
+// entries are updated on every step, so the update covers all columns.
+// The multipliers are x(:, pc) times the rounded reciprocal of p.
 constexpr int kLuWaves = 16;
 constexpr int kLuBlock = 64 * kLuWaves;
 
 // Position 256 i + j of the first entry (lowest row i, then lowest column j)
 // of this wave with |x| == M over the active columns; M must be the wave's
-// own maximum, so some row maximum ma[a] equals it.
+// own maximum, so some row maximum ma[a] equals it.  One ballot per register
+// row, then one per register column of the chosen row.
 template <typename T, int RA, int CB, int NW>
 __device__ __forceinline__ int first_position(const T (&x)[RA][CB], const T (&ma)[RA], T M, unsigned cact,
                                               int w) {
@@ -198,23 +213,25 @@ __device__ __forceinline__ int first_position(const T (&x)[RA][CB], const T (&ma
   }
   as = __builtin_amdgcn_readfirstlane(as);
   ls = __builtin_amdgcn_readfirstlane(ls);
-  unsigned m = 0;
+  int bs = 0;
 #pragma unroll
   for (int a = 0; a < RA; ++a)
     if (a == as) {
 #pragma unroll
-      for (int b = 0; b < CB; ++b)
-        if ((cact >> b) & 1u) m |= (fabs(x[a][b]) == M ? 1u : 0u) << b;
+      for (int b = CB - 1; b >= 0; --b)  // the lowest matching column wins
+        if ((cact >> b) & 1u) {
+          const unsigned long long bal = __ballot(fabs(x[a][b]) == M);
+          if ((bal >> ls) & 1ull) bs = b;
+        }
     }
-  const unsigned mb = (unsigned)__builtin_amdgcn_readlane((int)m, ls);
-  const int bs = mb ? __ffs(mb) - 1 : 0;
   return ((ls + 64 * max(as, 0)) << 8) + w + NW * bs;
 }
 
 template <typename T, int RA, int CB, int NW>
 __device__ int full_pivot_steps(const double* __restrict__ Kb, int ldk, const int* srow, const int* scol,
-                                int nr, int nc, int kmax, T eps, int* prow, int* pcol, T* colv,
-                                T (*sv)[NW], int (*si)[NW], int* spos) {
+                                int nr, int nc, int kmax, T eps, int* prow, int* pcol, T* pval, T* colv,
+                                T (*sv)[NW], int (*si)[NW], int* spos, T* __restrict__ G, int* rpos, int* cpos,
+                                bool* bad) {
   static_assert(NW <= 16, "the maxima of the waves are combined inside one 16-lane row");
   static_assert(CB <= 32, "one bit per register column");
   const int t = threadIdx.x, lane = t & 63;
@@ -222,6 +239,9 @@ __device__ int full_pivot_steps(const double* __restrict__ Kb, int ldk, const in
   unsigned cact = 0;  // per wave: bit b = column w + NW b still active
 #pragma unroll
   for (int b = 0; b < CB; ++b) cact |= (w + NW * b < nc ? 1u : 0u) << b;
+  unsigned ract = 0;  // per lane: bit a = row lane + 64 a still active
+#pragma unroll
+  for (int a = 0; a < RA; ++a) ract |= (lane + 64 * a < nr ? 1u : 0u) << a;
   T x[RA][CB];
 #pragma unroll
   for (int a = 0; a < RA; ++a) {
@@ -233,7 +253,7 @@ __device__ int full_pivot_steps(const double* __restrict__ Kb, int ldk, const in
       x[a][b] = (i < nr && j < nc) ? (T)Kb[(size_t)scol[j] * ldk + ri] : T(0);
     }
   }
-  T ma[RA];  // per register row: largest |entry| over the active columns
+  T ma[RA];  // per register row: largest |entry| over the active columns (0 on a retired row)
 #pragma unroll
   for (int a = 0; a < RA; ++a) {
     ma[a] = T(0);
@@ -281,7 +301,7 @@ __device__ int full_pivot_steps(const double* __restrict__ Kb, int ldk, const in
     }
     enc = __builtin_amdgcn_readfirstlane(enc);
     if (enc >= 0) {
-      // publish the pivot column (the pivot row included: its multiplier is 1)
+      // publish the pivot column
       const int bs = (enc & 255) / NW;
 #pragma unroll
       for (int b = 0; b < CB; ++b)
@@ -289,7 +309,6 @@ __device__ int full_pivot_steps(const double* __restrict__ Kb, int ldk, const in
 #pragma unroll
           for (int a = 0; a < RA; ++a) colv[lane + 64 * a] = x[a][b];
         }
-      cact &= ~(1u << bs);
       if (lane == 0) {
         spos[par] = enc;
         prow[k] = enc >> 8;
@@ -297,12 +316,14 @@ __device__ int full_pivot_steps(const double* __restrict__ Kb, int ldk, const in
       }
     }
     __syncthreads();
-    const int pi = spos[par], pr = pi >> 8;
+    const int pi = __builtin_amdgcn_readfirstlane(spos[par]), pr = pi >> 8, pc = pi & 255;
     const int pl = pr & 63, ap = pr >> 6;
-    const T p = colv[pr];
+    const int bp = pc % NW == w ? pc / NW : -1;  // the pivot column's register column in this wave, or -1
+    const T p = colv[pr], pinv = T(1) / p;
+    if (t == 0) pval[k] = p;
     T l[RA];
 #pragma unroll
-    for (int a = 0; a < RA; ++a) l[a] = colv[lane + 64 * a] / p;
+    for (int a = 0; a < RA; ++a) l[a] = (a == ap && lane == pl) ? T(0) : colv[lane + 64 * a] * pinv;
     // the pivot row's entries, from the lane that holds them
     T rv[CB];
 #pragma unroll
@@ -311,36 +332,87 @@ __device__ int full_pivot_steps(const double* __restrict__ Kb, int ldk, const in
 #pragma unroll
         for (int b = 0; b < CB; ++b) rv[b] = lane_value(x[a][b], pl);
       }
+    if (lane == pl) ract &= ~(1u << ap);
+    if (bp >= 0) cact &= ~(1u << bp);
 #pragma unroll
     for (int a = 0; a < RA; ++a) ma[a] = T(0);
 #pragma unroll
-    for (int b = 0; b < CB; ++b)
+    for (int b = 0; b < CB; ++b) {
       if ((cact >> b) & 1u) {
 #pragma unroll
         for (int a = 0; a < RA; ++a) {
           x[a][b] = fma(-l[a], rv[b], x[a][b]);
           ma[a] = fmax(ma[a], fabs(x[a][b]));
         }
+      } else {
+#pragma unroll
+        for (int a = 0; a < RA; ++a) x[a][b] = fma(-l[a], rv[b], x[a][b]);
       }
+    }
+    // the pivot column takes the multipliers, the pivot -1
+#pragma unroll
+    for (int b = 0; b < CB; ++b)
+      if (b == bp) {
+#pragma unroll
+        for (int a = 0; a < RA; ++a) x[a][b] = (a == ap && lane == pl) ? T(-1) : l[a];
+      }
+#pragma unroll
+    for (int a = 0; a < RA; ++a)
+      if (!((ract >> a) & 1u)) ma[a] = T(0);
     r = k + 1;
+  }
+  if (G) {
+    // Ahat11^-1 (k, l) = x(prow[k], pcol[l]) / -pval[k]: the steps of the
+    // rows and columns, then one store per owned entry of the pivot block
+    __syncthreads();
+    for (int q = t; q < 64 * RA; q += blockDim.x) rpos[q] = -1;
+    for (int q = t; q < NW * CB; q += blockDim.x) cpos[q] = -1;
+    __syncthreads();
+    for (int q = t; q < r; q += blockDim.x) {
+      rpos[prow[q]] = q;
+      cpos[pcol[q]] = q;
+    }
+    __syncthreads();
+    int nonfinite = 0;
+#pragma unroll
+    for (int a = 0; a < RA; ++a) {
+      const int rk = rpos[lane + 64 * a];
+      if (rk < 0) continue;
+      const T d = -pval[rk];
+#pragma unroll
+      for (int b = 0; b < CB; ++b) {
+        const int cl = cpos[w + NW * b];
+        if (cl >= 0) {
+          const T g = x[a][b] / d;
+          G[rk + (size_t)cl * r] = g;
+          nonfinite |= !(fabs(g) < T(INFINITY)) ? 1 : 0;
+        }
+      }
+    }
+    *bad = __syncthreads_or(nonfinite) != 0;
   }
   return r;
 }
 
-// Pivots of every block: the elimination runs on the smallest register tile
-// (64, 128 or SKEL square) that holds Ahat.  rank_out / rank_task receive the
-// number of pivots; k_bdlr_ginv follows.
+// Pivots of every block, and (inv given) G = Ahat11^-1 with Ahat11 =
+// Ahat(pivot rows, pivot columns) in pivot order (r x r, column-major at
+// inv + inv_off): C(:, pivot columns) G R(pivot rows, :) is the pseudo-
+// skeleton C~ R~ of eq. Ahat.  The elimination runs on the smallest register
+// tile (64, 128 or SKEL square) that holds Ahat.  rank_out / rank_task
+// receive the number of pivots; a non-finite entry of G drops the block
+// (rank 0).
 template <typename T, int SKEL>
 __global__ void __launch_bounds__(kLuBlock)
     k_bdlr_lu(const double* __restrict__ K, int ldk, const BdlrTask* __restrict__ tasks,
               const int* __restrict__ sel, const int* __restrict__ counts, T eps, int rcap,
-              int* __restrict__ piv_out, int* __restrict__ rank_out, int* __restrict__ rank_task,
-              const int* __restrict__ skip) {
+              int* __restrict__ piv_out, T* __restrict__ inv, int* __restrict__ rank_out,
+              int* __restrict__ rank_task, const int* __restrict__ skip) {
   static_assert(SKEL % 64 == 0 && SKEL <= 256 && SKEL % kLuWaves == 0, "tile shape");
-  __shared__ int srow[SKEL], scol[SKEL], prow[SKEL], pcol[SKEL];
-  __shared__ T colv[SKEL];
-  __shared__ T sv[2][kLuWaves];
-  __shared__ int si[2][kLuWaves], spos[2];
+  constexpr int NW = kLuWaves;
+  __shared__ int srow[SKEL], scol[SKEL], prow[SKEL], pcol[SKEL], rpos[SKEL], cpos[SKEL];
+  __shared__ T pval[SKEL], colv[SKEL];
+  __shared__ T sv[2][NW];
+  __shared__ int si[2][NW], spos[2];
   const int task = blockIdx.x, t = threadIdx.x;
   if (skip && skip[task]) return;
   const BdlrTask tk = tasks[task];
@@ -353,61 +425,36 @@ __global__ void __launch_bounds__(kLuBlock)
   const double* Kb = K + (size_t)tk.col0 * ldk + tk.row0;
   const int kmax = min(min(nr, nc), min(tk.kmax, rcap));
   const int side = max(nr, nc);
-  constexpr int NW = kLuWaves;
+  T* G = inv ? inv + tk.inv_off : nullptr;
+  bool bad = false;
   int r;
   if (side <= 64)
-    r = full_pivot_steps<T, 1, 64 / NW, NW>(Kb, ldk, srow, scol, nr, nc, kmax, eps, prow, pcol, colv, sv, si, spos);
+    r = full_pivot_steps<T, 1, 64 / NW, NW>(Kb, ldk, srow, scol, nr, nc, kmax, eps, prow, pcol, pval, colv, sv,
+                                            si, spos, G, rpos, cpos, &bad);
   else if (side <= 128 || SKEL <= 128)
-    r = full_pivot_steps<T, 2, 128 / NW, NW>(Kb, ldk, srow, scol, nr, nc, kmax, eps, prow, pcol, colv, sv, si,
-                                             spos);
+    r = full_pivot_steps<T, 2, 128 / NW, NW>(Kb, ldk, srow, scol, nr, nc, kmax, eps, prow, pcol, pval, colv, sv,
+                                             si, spos, G, rpos, cpos, &bad);
   else
-    r = full_pivot_steps<T, SKEL / 64, SKEL / NW, NW>(Kb, ldk, srow, scol, nr, nc, kmax, eps, prow, pcol, colv, sv,
-                                                      si, spos);
+    r = full_pivot_steps<T, SKEL / 64, SKEL / NW, NW>(Kb, ldk, srow, scol, nr, nc, kmax, eps, prow, pcol, pval,
+                                                      colv, sv, si, spos, G, rpos, cpos, &bad);
   __syncthreads();
   for (int q = t; q < r; q += blockDim.x) {
     piv_out[tk.sel_off + q] = srow[prow[q]];         // picked rows in pivot order
     piv_out[tk.sel_off + SKEL + q] = scol[pcol[q]];  // picked columns in pivot order
   }
   if (t == 0) {
-    rank_out[tk.node] = r;
-    rank_task[task] = r;
+    rank_out[tk.node] = bad ? 0 : r;
+    rank_task[task] = bad ? 0 : r;
   }
 }
 
-// G = Ahat11^-1 with Ahat11 = Ahat(pivot rows, pivot columns), read again
-// from K; (L11 U11)^-1 = U11^-1 L11^-1, so C(:, pivot columns) G R(pivot
-// rows, :) is the pseudo-skeleton C~ R~.  A numerically singular Ahat11 drops
-// the block (rank 0).
-template <typename T, int SKEL>
-__global__ void __launch_bounds__(gj_threads<T>())
-    k_bdlr_ginv(const double* __restrict__ K, int ldk, const BdlrTask* __restrict__ tasks,
-                const int* __restrict__ piv, T* __restrict__ inv, int* __restrict__ rank_out,
-                int* __restrict__ rank_task, const int* __restrict__ skip) {
-  __shared__ GjScratch<T, (sizeof(T) == 8 ? kRankCap64 : kRankCap32)> gw;
-  const int task = blockIdx.x, t = threadIdx.x;
-  if (skip && skip[task]) return;
-  const BdlrTask tk = tasks[task];
-  const int r = rank_task[task];
-  if (r == 0) return;
-  const double* Kb = K + (size_t)tk.col0 * ldk + tk.row0;
-  const int* pr = piv + tk.sel_off;
-  const int* pc = piv + tk.sel_off + SKEL;
-  T* G = inv + tk.inv_off;  // r x r, ld r
-  const bool ok = gj_invert([&](int i, int j) { return (T)Kb[(size_t)pc[j] * ldk + pr[i]]; }, r, G, r, gw);
-  if (!ok && t == 0) {
-    rank_out[tk.node] = 0;
-    rank_task[task] = 0;
-  }
-}
-
-// The pivots, then G, of ns blocks.
+// The pivots and G of ns blocks.
 template <typename T, int SKEL>
 static int launch_bdlr_lu(const double* K, int ldk, const BdlrTask* tasks, int ns, const int* sel, const int* cnt,
                           T eps, int rcap, int* piv, T* inv, int* rank_out, int* rank_task, hipStream_t s,
                           const int* skip = nullptr) {
-  k_bdlr_lu<T, SKEL><<<ns, kLuBlock, 0, s>>>(K, ldk, tasks, sel, cnt, eps, rcap, piv, rank_out, rank_task, skip);
-  HODLR_HIP(hipGetLastError());
-  k_bdlr_ginv<T, SKEL><<<ns, gj_threads<T>(), 0, s>>>(K, ldk, tasks, piv, inv, rank_out, rank_task, skip);
+  k_bdlr_lu<T, SKEL><<<ns, kLuBlock, 0, s>>>(K, ldk, tasks, sel, cnt, eps, rcap, piv, inv, rank_out, rank_task,
+                                              skip);
   HODLR_HIP(hipGetLastError());
   return HODLR_OK;
 }
@@ -615,44 +662,18 @@ static int bdlr_t(hodlr_s* h, const double* K, int ldk, const int* rowptr, const
   {
     ProfScope prof("bdlr_lu", s);
     k_bdlr_lu<T, SKEL><<<nt, kLuBlock, 0, s>>>(K, ldk, d_tasks.as<BdlrTask>(), d_sel.as<int>(), d_cnt.as<int>(),
-                                                (T)h->tol, rcap, d_piv.as<int>(), h->d_rank.as<int>(), d_rt.as<int>(),
-                                                nullptr);
+                                                (T)h->tol, rcap, d_piv.as<int>(), d_inv.as<T>(), h->d_rank.as<int>(),
+                                                d_rt.as<int>(), nullptr);
   }
   HODLR_HIP(hipGetLastError());
-  // the gather needs only the pivots: it runs on a second stream beside the
-  // inverses of the pivot blocks (a block the inverse finds singular gets
-  // rank 0, and its gathered columns are never read)
   const int nch = (maxside + kBlock - 1) / kBlock;
-  hipStream_t side = nullptr;
-  HODLR_TRY(side_stream(1, &side));
-  struct Events {  // joins the side stream on every return (the scratch above outlives it)
-    hipStream_t side = nullptr;
-    hipEvent_t e[2] = {nullptr, nullptr};
-    ~Events() {
-      if (side) (void)hipStreamSynchronize(side);
-      for (auto x : e)
-        if (x) (void)hipEventDestroy(x);
-    }
-  } ev;
-  ev.side = side;
-  for (auto& x : ev.e) HODLR_HIP(hipEventCreateWithFlags(&x, hipEventDisableTiming));
-  HODLR_HIP(hipEventRecord(ev.e[0], s));
-  HODLR_HIP(hipStreamWaitEvent(side, ev.e[0], 0));
   {
-    ProfScope prof("bdlr_gather", side);
-    k_bdlr_gather<T, SKEL><<<dim3(nt, nch, 2), kBlock, 0, side>>>(K, ldk, d_tasks.as<BdlrTask>(), d_piv.as<int>(),
-                                                                 d_rt.as<int>(), d_cg.as<T>(), Ucap, Vcap, tr.n,
-                                                                 nullptr);
+    ProfScope prof("bdlr_gather", s);
+    k_bdlr_gather<T, SKEL><<<dim3(nt, nch, 2), kBlock, 0, s>>>(K, ldk, d_tasks.as<BdlrTask>(), d_piv.as<int>(),
+                                                              d_rt.as<int>(), d_cg.as<T>(), Ucap, Vcap, tr.n,
+                                                              nullptr);
   }
   HODLR_HIP(hipGetLastError());
-  HODLR_HIP(hipEventRecord(ev.e[1], side));
-  {
-    ProfScope prof("bdlr_lu", s);
-    k_bdlr_ginv<T, SKEL><<<nt, gj_threads<T>(), 0, s>>>(K, ldk, d_tasks.as<BdlrTask>(), d_piv.as<int>(), d_inv.as<T>(),
-                                               h->d_rank.as<int>(), d_rt.as<int>(), nullptr);
-  }
-  HODLR_HIP(hipGetLastError());
-  HODLR_HIP(hipStreamWaitEvent(s, ev.e[1], 0));
   {
     ProfScope prof("bdlr_factors", s);
     k_bdlr_factors<T><<<dim3(nt, (maxside + 63) / 64, (rcap + 63) / 64), kBlock, 0, s>>>(
@@ -662,9 +683,7 @@ static int bdlr_t(hodlr_s* h, const double* K, int ldk, const int* rowptr, const
   if (piv_export)
     HODLR_HIP(hipMemcpyAsync(piv_export, d_piv.p, (size_t)selo * sizeof(int), hipMemcpyDeviceToDevice, s));
   // the scratch goes back to the allocator once s is past its last reader
-  // (s has waited for the side stream's gather)
   for (DevBuf* b : {&d_tasks, &d_sel, &d_piv, &d_cnt, &d_rt, &d_inv, &d_cg}) b->release_after(s);
-  ev.side = nullptr;
   return HODLR_OK;
 }
 
@@ -680,56 +699,6 @@ __device__ __forceinline__ unsigned score_key(float x) {
   if (x != x) return 0u;
   const unsigned u = __float_as_uint(x);
   return (u & 0x80000000u) ? ~u : (u | 0x80000000u);
-}
-
-__device__ int block_count(int v, int* red) {
-  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-  __syncthreads();
-  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
-  __syncthreads();
-  int r = 0;
-  for (int w = 0; w < kBlock / 64; ++w) r += red[w];
-  __syncthreads();
-  return r;
-}
-
-// The k largest keys of one side (ties to the lower position), listed in
-// increasing position.
-__device__ void topk_side(const unsigned* key, int len, int k, int* out, int* count, int* buf, int* red) {
-  const int t = threadIdx.x;
-  unsigned thr = 0u;  // the k-th largest key (radix select from the top bit)
-  int take = len;     // entries equal to thr that are kept
-  if (k < len) {
-    for (int bit = 31; bit >= 0; --bit) {
-      const unsigned cand = thr | (1u << bit);
-      int c = 0;
-      for (int i = t; i < len; i += kBlock) c += key[i] >= cand;
-      if (block_count(c, red) >= k) thr = cand;
-    }
-    int gt = 0;
-    for (int i = t; i < len; i += kBlock) gt += key[i] > thr;
-    take = k - block_count(gt, red);
-  }
-  const bool all = k >= len;
-  const int seg = (len + kBlock - 1) / kBlock, b0 = min(len, t * seg), b1 = min(len, b0 + seg);
-  int tot;
-  int ne = 0;
-  for (int i = b0; i < b1; ++i) ne += (key[i] == thr);
-  const int eq = block_exclusive_scan(ne, buf, &tot);
-  int ns = 0;
-  for (int i = b0, e = eq; i < b1; ++i) {
-    const bool ise = key[i] == thr;
-    ns += all || key[i] > thr || (ise && e < take);
-    e += ise;
-  }
-  int pos = block_exclusive_scan(ns, buf, &tot);
-  for (int i = b0, e = eq; i < b1; ++i) {
-    const bool ise = key[i] == thr;
-    if (all || key[i] > thr || (ise && e < take)) out[pos++] = i;
-    e += ise;
-  }
-  if (t == 0) *count = tot;
-  __syncthreads();
 }
 
 // |K(I, J)|_F^2 of every block, in kNormChunks column chunks per block (a
@@ -783,12 +752,22 @@ __global__ void __launch_bounds__(64) k_norm_total(double* __restrict__ part) {
 // |K(I, J)|_F^2.
 //
 // k_skel_check: workgroup (task, chunk, group) sums the squared residual of
-// the group's rows over its chunk of the columns (and of the group's columns
-// over its chunk of the rows) into part; the other factor's entries are
-// loaded 8 at a time.  A task has gridDim.z groups of 2 ns positions (one
-// group: the samples).  k_skel_err then adds a task's chunks in order and
-// forms the estimate, so the result does not depend on timing.
-constexpr int kCheckChunks = 16;
+// the group's rows over its chunk of kCheckX columns (and of the group's
+// columns over its chunk of kCheckX rows) into part: lane l takes position
+// l of the chunk, and the four waves split the rank, their partial products
+// added in wave order through LDS.  The factors' entries are loaded 16 at a
+// time.  A task has gridDim.z groups of 2 ns positions (one group: the
+// samples) and gridDim.y = check_chunks(tasks) chunks (chunks past a side's
+// end write 0).  k_skel_err then adds a task's chunks in order and forms the
+// estimate, so the result does not depend on timing.
+constexpr int kCheckX = 64;
+constexpr int kCheckWaves = kBlock / 64;
+
+static int check_chunks(const std::vector<BdlrTask>& tasks) {
+  int mx = 1;
+  for (const BdlrTask& t : tasks) mx = std::max(mx, std::max(t.m, t.nc));
+  return (mx + kCheckX - 1) / kCheckX;
+}
 
 template <typename T>
 __global__ void __launch_bounds__(kBlock)
@@ -796,37 +775,56 @@ __global__ void __launch_bounds__(kBlock)
                  const int* __restrict__ rank_task, const T* __restrict__ Ucap, const T* __restrict__ Vcap,
                  int ldu, const int* __restrict__ samp, int ns, double* __restrict__ part,
                  const int* __restrict__ skip) {
-  constexpr int RC = sizeof(T) == 8 ? kRankCap64 : kRankCap32, NS = 16, kL = 8;
+  constexpr int RC = sizeof(T) == 8 ? kRankCap64 : kRankCap32, NS = 16, kL = 16;
+  constexpr int kStage = (NS * RC + kBlock - 1) / kBlock;  // staged entries per thread
+  static_assert(NS == 4 * kCheckWaves, "each wave finishes four positions");
   __shared__ T uv[NS][RC];
+  __shared__ double acc[kCheckWaves][NS][64];
   __shared__ int sp[2 * NS];
   __shared__ double red[kBlock / 64];
   if (skip && skip[blockIdx.x]) return;
   const BdlrTask tk = tasks[blockIdx.x];
-  const int r = rank_task[blockIdx.x], t = threadIdx.x;
+  const int r = rank_task[blockIdx.x], t = threadIdx.x, lane = t & 63, w = t >> 6;
   const size_t grp = (size_t)blockIdx.x * gridDim.z + blockIdx.z;  // position group of this task
+  const size_t slot = (grp * gridDim.y + blockIdx.y) * 2;
   if (t < 2 * NS) sp[t] = (t % NS) < ns ? samp[grp * 2 * ns + (t / NS) * ns + t % NS] : -1;
   __syncthreads();
   const T* U = Ucap + (size_t)tk.capcol * ldu;
   const T* V = Vcap + (size_t)tk.capcol * ldu;
   for (int side = 0; side < 2; ++side) {
+    const int len = side == 0 ? tk.nc : tk.m;
+    const int x0 = blockIdx.y * kCheckX;
+    if (x0 >= len) {  // (uniform over the workgroup)
+      if (t == 0) part[slot + side] = 0.0;
+      continue;
+    }
     // the fixed factor's sampled rows: U(row0 + p, :) (side 0) or V(col0 + p, :)
     const T* F = side == 0 ? U + tk.row0 : V + tk.col0;
     const T* O = side == 0 ? V + tk.col0 : U + tk.row0;
-    for (int e = t; e < NS * r; e += kBlock) {
-      const int q = e % NS, l = e / NS, p = sp[side * NS + q];
-      uv[q][l] = p >= 0 ? F[(size_t)l * ldu + p] : T(0);
+    {
+      T v[kStage];
+#pragma unroll
+      for (int k = 0; k < kStage; ++k) {
+        const int e = t + k * kBlock, q = e % NS, l = e / NS;
+        const int p = e < NS * r ? sp[side * NS + q] : -1;
+        v[k] = p >= 0 ? F[(size_t)l * ldu + p] : T(0);
+      }
+#pragma unroll
+      for (int k = 0; k < kStage; ++k) {
+        const int e = t + k * kBlock;
+        if (e < NS * r) uv[e % NS][e / NS] = v[k];
+      }
     }
     __syncthreads();
-    const int len = side == 0 ? tk.nc : tk.m;
-    const int per = (len + kCheckChunks - 1) / kCheckChunks;
-    const int x0 = blockIdx.y * per, x1 = min(len, x0 + per);
-    double num = 0.0;
-    for (int x = x0 + t; x < x1; x += kBlock) {
-      double a[NS];
+    const int x = x0 + lane;
+    const bool in = x < len;
+    const int rq = (r + kCheckWaves - 1) / kCheckWaves, l0 = min(r, w * rq), l1 = min(r, l0 + rq);
+    double a[NS];
 #pragma unroll
-      for (int q = 0; q < NS; ++q) a[q] = 0.0;
-      int l = 0;
-      for (; l + kL <= r; l += kL) {
+    for (int q = 0; q < NS; ++q) a[q] = 0.0;
+    if (in) {
+      int l = l0;
+      for (; l + kL <= l1; l += kL) {
         double o[kL];
 #pragma unroll
         for (int u = 0; u < kL; ++u) o[u] = (double)O[(size_t)(l + u) * ldu + x];
@@ -835,32 +833,46 @@ __global__ void __launch_bounds__(kBlock)
 #pragma unroll
           for (int q = 0; q < NS; ++q) a[q] += (double)uv[q][l + u] * o[u];
       }
-      for (; l < r; ++l) {
+      for (; l < l1; ++l) {
         const double o = (double)O[(size_t)l * ldu + x];
 #pragma unroll
         for (int q = 0; q < NS; ++q) a[q] += (double)uv[q][l] * o;
       }
-      double b[NS];
+    }
 #pragma unroll
-      for (int q = 0; q < NS; ++q) {
-        const int p = sp[side * NS + q];
-        b[q] = p < 0 ? 0.0
+    for (int q = 0; q < NS; ++q) acc[w][q][lane] = a[q];
+    __syncthreads();
+    // thread (lane, w): positions 4 w .. 4 w + 3 at x
+    double num = 0.0;
+    if (in) {
+      double b[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int p = sp[side * NS + 4 * w + u];
+        b[u] = p < 0 ? 0.0
                      : side == 0 ? K[(size_t)(tk.col0 + x) * ldk + tk.row0 + p]
                                  : K[(size_t)(tk.col0 + p) * ldk + tk.row0 + x];
       }
 #pragma unroll
-      for (int q = 0; q < NS; ++q)
-        if (sp[side * NS + q] >= 0) num += (b[q] - a[q]) * (b[q] - a[q]);
+      for (int u = 0; u < 4; ++u) {
+        const int q = 4 * w + u;
+        if (sp[side * NS + q] >= 0) {
+          double s = acc[0][q][lane];
+#pragma unroll
+          for (int k = 1; k < kCheckWaves; ++k) s += acc[k][q][lane];
+          num += (b[u] - s) * (b[u] - s);
+        }
+      }
     }
     num = block_sum(num, red);
-    if (t == 0) part[(grp * kCheckChunks + blockIdx.y) * 2 + side] = num;
+    if (t == 0) part[slot + side] = num;
     __syncthreads();
   }
 }
 
 __global__ void k_skel_err(const BdlrTask* __restrict__ tasks, int ntask, const int* __restrict__ counts,
                            const double* __restrict__ norm2, const int* __restrict__ samp, int ns,
-                           const double* __restrict__ part, double* __restrict__ err,
+                           const double* __restrict__ part, int nch, double* __restrict__ err,
                            const int* __restrict__ skip) {
   const int x = blockIdx.x * blockDim.x + threadIdx.x;
   if (x >= ntask || (skip && skip[x])) return;
@@ -868,7 +880,7 @@ __global__ void k_skel_err(const BdlrTask* __restrict__ tasks, int ntask, const 
   double est = 0.0;
   for (int side = 0; side < 2; ++side) {
     double num = 0.0;
-    for (int c = 0; c < kCheckChunks; ++c) num += part[((size_t)x * kCheckChunks + c) * 2 + side];
+    for (int c = 0; c < nch; ++c) num += part[((size_t)x * nch + c) * 2 + side];
     int used = 0;
     for (int q = 0; q < ns; ++q) used += samp[(size_t)x * 2 * ns + side * ns + q] >= 0;
     const int outside = (side == 0 ? tk.m : tk.nc) - counts[2 * x + side];
@@ -878,9 +890,13 @@ __global__ void k_skel_err(const BdlrTask* __restrict__ tasks, int ntask, const 
   err[x] = nb > 0.0 ? sqrt(est / nb) : sqrt(est);
 }
 
-// splitmix64 (Steele, Lea & Flood 2014): the sample stream of a block
-__device__ __forceinline__ unsigned long long splitmix64(unsigned long long& x) {
-  unsigned long long z = (x += 0x9E3779B97F4A7C15ull);
+// splitmix64 (Steele, Lea & Flood 2014): the sample stream of a block.  The
+// state advances by a fixed increment per draw, so draw c (from 0) of the
+// stream seeded with x0 is the mix of x0 + (c + 1) * increment, which lets
+// every draw be computed on its own lane.
+constexpr unsigned long long kSplitmixGamma = 0x9E3779B97F4A7C15ull;
+__device__ __forceinline__ unsigned long long splitmix64_draw(unsigned long long x0, unsigned long long c) {
+  unsigned long long z = x0 + (c + 1) * kSplitmixGamma;
   z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
   z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
   return z ^ (z >> 31);
@@ -902,34 +918,33 @@ __device__ __forceinline__ int avail_at(const int* picked, int npick, int p) {
 constexpr int kSkelSamples = 16;  // sampled rows (columns) per block side
 
 // NS positions of [0, len) outside the picks, without replacement: the first
-// NS steps of a Fisher-Yates shuffle of the unpicked positions, taken from
-// the stream st.  The list itself is never built: its entries are computed
-// on demand (avail_at), and the entries the swaps moved are kept in fixed
+// NS steps of a Fisher-Yates shuffle of the list of unpicked positions.  Step
+// x swaps list entries x and j[x] (j[x] = x + draw mod (navail - x), drawn
+// beforehand, as are the entries' initial values ax[x] and aj[x]); the list
+// itself is never built: the entries the swaps moved are kept in fixed
 // register slots, 2x for position x and 2x + 1 for the position j swapped
-// with it at step x; a lookup takes the latest slot holding the position.
+// with it at step x, and a lookup takes the latest slot holding the position.
 // Every loop is unrolled, so the slots stay in registers.
 template <int NS>
-__device__ void draw_side(unsigned long long& st, int len, const int* picked, int npick, int* out) {
+__device__ void draw_side(int navail, const int* j_of, const int* ax, const int* aj, int* out) {
   int opos[2 * NS], oval[2 * NS];
 #pragma unroll
   for (int k = 0; k < 2 * NS; ++k) opos[k] = -1;
-  const int navail = len - npick;
 #pragma unroll
   for (int x = 0; x < NS; ++x) {
-    const int na = navail - x;
-    if (na <= 0) {
+    if (navail - x <= 0) {
       out[x] = -1;
       continue;
     }
-    const int j = x + (int)(splitmix64(st) % (unsigned long long)na);
+    const int j = j_of[x];
     int vx = -1, vj = -1;
 #pragma unroll
     for (int k = 2 * x - 1; k >= 0; --k) {  // latest first
       if (vx < 0 && opos[k] == x) vx = oval[k];
       if (vj < 0 && opos[k] == j) vj = oval[k];
     }
-    if (vx < 0) vx = avail_at(picked, npick, x);
-    if (vj < 0) vj = avail_at(picked, npick, j);
+    if (vx < 0) vx = ax[x];
+    if (vj < 0) vj = aj[x];
     opos[2 * x] = x;
     oval[2 * x] = vj;
     opos[2 * x + 1] = j;
@@ -938,33 +953,49 @@ __device__ void draw_side(unsigned long long& st, int len, const int* picked, in
   }
 }
 
-// One wave per block of the attempt: the picks go to LDS, then one lane
-// draws the row samples and then the column samples, from one stream seeded
-// by the block's node and the attempt.
+// One wave per block of the attempt: the picks go to LDS; one stream seeded
+// by the block's node and the attempt gives the row draws, then the column
+// draws.  Lane q < 2 NS computes draw q % NS of side q / NS and the two list
+// entries it swaps; then lane 0 (rows) and lane 1 (columns) run the swaps.
 constexpr int kDrawPicks = 256;  // >= the largest skeleton (192 / 128)
 __global__ void __launch_bounds__(64)
     k_draw_samples(const BdlrTask* __restrict__ tasks, const int* __restrict__ sel, const int* __restrict__ cnt,
                    int skel, unsigned long long seed, int attempt, int ns, int* __restrict__ samp,
                    const int* __restrict__ skip) {
+  constexpr int NS = kSkelSamples;
   __shared__ int pk[2][kDrawPicks];
+  __shared__ int jv[2][NS], ax[2][NS], aj[2][NS];
   const int x = blockIdx.x, t = threadIdx.x;
   if (skip && skip[x]) return;
   const BdlrTask tk = tasks[x];
-  const int nr = min(cnt[2 * x], kDrawPicks), nc = min(cnt[2 * x + 1], kDrawPicks);
-  for (int i = t; i < nr; i += 64) pk[0][i] = sel[tk.sel_off + i];
-  for (int i = t; i < nc; i += 64) pk[1][i] = sel[tk.sel_off + skel + i];
+  const int np[2] = {min(cnt[2 * x], kDrawPicks), min(cnt[2 * x + 1], kDrawPicks)};
+  for (int i = t; i < np[0]; i += 64) pk[0][i] = sel[tk.sel_off + i];
+  for (int i = t; i < np[1]; i += 64) pk[1][i] = sel[tk.sel_off + skel + i];
   __syncthreads();
-  if (t != 0) return;
-  unsigned long long st = seed ^ (0xD1B54A32D192ED03ull * (unsigned long long)tk.node) ^
-                          (0x8CB92BA72F3D8DD7ull * (unsigned long long)(attempt + 1));
-  draw_side<kSkelSamples>(st, tk.m, pk[0], nr, samp + (size_t)x * 2 * ns);
-  draw_side<kSkelSamples>(st, tk.nc, pk[1], nc, samp + (size_t)x * 2 * ns + ns);
+  const unsigned long long st = seed ^ (0xD1B54A32D192ED03ull * (unsigned long long)tk.node) ^
+                                (0x8CB92BA72F3D8DD7ull * (unsigned long long)(attempt + 1));
+  const int navail[2] = {tk.m - np[0], tk.nc - np[1]};
+  if (t < 2 * NS) {
+    const int sd = t / NS, q = t % NS, na = navail[sd] - q;
+    if (na > 0) {
+      // the row side draws once per step with a nonempty list
+      const int c = (sd == 0 ? 0 : min(NS, max(0, navail[0]))) + q;
+      const int j = q + (int)(splitmix64_draw(st, (unsigned long long)c) % (unsigned long long)na);
+      jv[sd][q] = j;
+      ax[sd][q] = avail_at(pk[sd], np[sd], q);
+      aj[sd][q] = avail_at(pk[sd], np[sd], j);
+    }
+  }
+  __syncthreads();
+  if (t < 2) draw_side<NS>(navail[t], jv[t], ax[t], aj[t], samp + (size_t)x * 2 * ns + t * ns);
 }
 
 // Scratch of the attempt loops (learned proposals, adaptive BDLR depth).
 struct SkelScratch {
   DevBuf tasks, sel, piv, cnt, rt, inv, cg, samp, err, norm, part;
-  int ensure(int nt, int selo, size_t invo, size_t cgo, size_t esize) {
+  int nch = 1;  // check chunks per side (check_chunks of the build's tasks)
+  int ensure(int nt, int selo, size_t invo, size_t cgo, size_t esize, int nchunks) {
+    nch = nchunks;
     HODLR_TRY(tasks.ensure(nt * sizeof(BdlrTask)));
     HODLR_TRY(sel.ensure((size_t)selo * sizeof(int)));
     HODLR_TRY(piv.ensure((size_t)selo * sizeof(int)));
@@ -974,7 +1005,7 @@ struct SkelScratch {
     HODLR_TRY(cg.ensure(std::max<size_t>(cgo, 1) * esize));
     HODLR_TRY(samp.ensure((size_t)nt * 2 * kSkelSamples * sizeof(int)));
     HODLR_TRY(err.ensure((size_t)nt * sizeof(double)));
-    HODLR_TRY(part.ensure((size_t)nt * kCheckChunks * 2 * sizeof(double)));
+    HODLR_TRY(part.ensure((size_t)nt * nch * 2 * sizeof(double)));
     return norm.ensure((size_t)nt * kNormChunks * sizeof(double));
   }
 };
@@ -998,38 +1029,54 @@ static int block_norms(const double* K, int ldk, const std::vector<BdlrTask>& ta
 // Vcap, then the sampled error of every block (samples drawn on the device
 // outside its picks, from a stream seeded by the block and the attempt) into
 // sc.err.  Blocks with skip[x] != 0 (skip may be NULL) are left untouched.
+// The per-task arrays of an attempt launch, offset to its first task (a
+// launch covers ns consecutive tasks of sc.tasks); the picks, pivots,
+// inverses, panels and norms are reached through the task records
+// (sel_off, inv_off, cg_off, task) and are shared by every launch.
+struct AttemptView {
+  const BdlrTask* tasks;
+  int *cnt, *rt, *samp;
+  double *part, *err;
+};
+static AttemptView attempt_view(SkelScratch& sc, int x0) {
+  return {sc.tasks.as<BdlrTask>() + x0,
+          sc.cnt.as<int>() + 2 * x0,
+          sc.rt.as<int>() + x0,
+          sc.samp.as<int>() + (size_t)x0 * 2 * kSkelSamples,
+          sc.part.as<double>() + (size_t)x0 * sc.nch * 2,
+          sc.err.as<double>() + x0};
+}
+
 template <typename T, int SKEL>
-static int skel_attempt_launch(hodlr_s* h, const double* K, int ldk, int ns, int maxside, SkelScratch& sc, T* Ucap,
-                               T* Vcap, unsigned long long seed, int attempt, const int* skip, hipStream_t s) {
+static int skel_attempt_launch(hodlr_s* h, const double* K, int ldk, int ns, int maxside, SkelScratch& sc,
+                               const AttemptView& v, T* Ucap, T* Vcap, unsigned long long seed, int attempt,
+                               const int* skip, hipStream_t s) {
   const Tree& tr = h->tree;
   const int rcap = h->precision == 64 ? kRankCap64 : kRankCap32;
   {
     ProfScope prof("bdlr_lu", s);
-    HODLR_TRY((launch_bdlr_lu<T, SKEL>(K, ldk, sc.tasks.as<BdlrTask>(), ns, sc.sel.as<int>(), sc.cnt.as<int>(),
-                                       (T)h->tol, rcap, sc.piv.as<int>(), sc.inv.as<T>(), h->d_rank.as<int>(),
-                                       sc.rt.as<int>(), s, skip)));
+    HODLR_TRY((launch_bdlr_lu<T, SKEL>(K, ldk, v.tasks, ns, sc.sel.as<int>(), v.cnt, (T)h->tol, rcap,
+                                       sc.piv.as<int>(), sc.inv.as<T>(), h->d_rank.as<int>(), v.rt, s, skip)));
   }
   const int nch = (maxside + kBlock - 1) / kBlock;
   {
     ProfScope prof("bdlr_gather", s);
-    k_bdlr_gather<T, SKEL><<<dim3(ns, nch, 2), kBlock, 0, s>>>(K, ldk, sc.tasks.as<BdlrTask>(), sc.piv.as<int>(),
-                                                              sc.rt.as<int>(), sc.cg.as<T>(), Ucap, Vcap, tr.n, skip);
+    k_bdlr_gather<T, SKEL><<<dim3(ns, nch, 2), kBlock, 0, s>>>(K, ldk, v.tasks, sc.piv.as<int>(), v.rt, sc.cg.as<T>(),
+                                                              Ucap, Vcap, tr.n, skip);
     k_bdlr_factors<T><<<dim3(ns, (maxside + 63) / 64, (rcap + 63) / 64), kBlock, 0, s>>>(
-        sc.tasks.as<BdlrTask>(), sc.rt.as<int>(), sc.cg.as<T>(), sc.inv.as<T>(), Ucap, tr.n, skip);
+        v.tasks, v.rt, sc.cg.as<T>(), sc.inv.as<T>(), Ucap, tr.n, skip);
   }
   HODLR_HIP(hipGetLastError());
   static_assert(SKEL <= kDrawPicks, "the picks of a side must fit the sampler's LDS");
-  k_draw_samples<<<ns, 64, 0, s>>>(sc.tasks.as<BdlrTask>(), sc.sel.as<int>(), sc.cnt.as<int>(), SKEL, seed, attempt,
-                                   kSkelSamples, sc.samp.as<int>(), skip);
+  k_draw_samples<<<ns, 64, 0, s>>>(v.tasks, sc.sel.as<int>(), v.cnt, SKEL, seed, attempt, kSkelSamples, v.samp,
+                                   skip);
   HODLR_HIP(hipGetLastError());
   {
     ProfScope prof("skel_check", s);
-    k_skel_check<T><<<dim3(ns, kCheckChunks), kBlock, 0, s>>>(K, ldk, sc.tasks.as<BdlrTask>(), sc.rt.as<int>(),
-                                                               Ucap, Vcap, tr.n, sc.samp.as<int>(), kSkelSamples,
-                                                               sc.part.as<double>(), skip);
-    k_skel_err<<<(ns + kBlock - 1) / kBlock, kBlock, 0, s>>>(sc.tasks.as<BdlrTask>(), ns, sc.cnt.as<int>(),
-                                                            sc.norm.as<double>(), sc.samp.as<int>(), kSkelSamples,
-                                                            sc.part.as<double>(), sc.err.as<double>(), skip);
+    k_skel_check<T><<<dim3(ns, sc.nch), kBlock, 0, s>>>(K, ldk, v.tasks, v.rt, Ucap, Vcap, tr.n, v.samp,
+                                                         kSkelSamples, v.part, skip);
+    k_skel_err<<<(ns + kBlock - 1) / kBlock, kBlock, 0, s>>>(v.tasks, ns, v.cnt, sc.norm.as<double>(), v.samp,
+                                                            kSkelSamples, v.part, sc.nch, v.err, skip);
   }
   HODLR_HIP(hipGetLastError());
   return HODLR_OK;
@@ -1042,7 +1089,8 @@ static int skel_attempt(hodlr_s* h, const double* K, int ldk, const std::vector<
                         SkelScratch& sc, T* Ucap, T* Vcap, unsigned long long seed, int attempt,
                         std::vector<double>& err, std::vector<int>& cnt, hipStream_t s) {
   const int ns = (int)sub.size();
-  HODLR_TRY((skel_attempt_launch<T, SKEL>(h, K, ldk, ns, maxside, sc, Ucap, Vcap, seed, attempt, nullptr, s)));
+  HODLR_TRY((skel_attempt_launch<T, SKEL>(h, K, ldk, ns, maxside, sc, attempt_view(sc, 0), Ucap, Vcap, seed,
+                                          attempt, nullptr, s)));
   err.assign(ns, 0.0);
   cnt.assign(2 * ns, 0);
   HODLR_HIP(hipMemcpyAsync(err.data(), sc.err.p, ns * sizeof(double), hipMemcpyDeviceToHost, s));
@@ -1116,68 +1164,173 @@ __device__ __forceinline__ bool same_point(const float* __restrict__ xyz, int u,
   return xyz[3 * u] == xyz[3 * v] && xyz[3 * u + 1] == xyz[3 * v + 1] && xyz[3 * u + 2] == xyz[3 * v + 2];
 }
 
-__global__ void __launch_bounds__(kBlock)
+constexpr int kTopBlock = 1024, kTopWaves = kTopBlock / 64;
+
+// Inclusive prefix over the workgroup's per-thread values (in thread order);
+// *total receives the sum.  Two barriers.
+__device__ int top_scan(int v, int* wsum, int* total) {
+  const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+  int x = v;
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    const int y = __shfl_up(x, o, 64);
+    if (lane >= o) x += y;
+  }
+  if (lane == 63) wsum[w] = x;
+  __syncthreads();
+  int before = 0, tot = 0;
+#pragma unroll
+  for (int k = 0; k < kTopWaves; ++k) {
+    const int c = wsum[k];
+    before += k < w ? c : 0;
+    tot += c;
+  }
+  *total = tot;
+  __syncthreads();
+  return before + x;
+}
+
+// Workgroup maximum and sum of two per-thread values.  Two barriers.
+__device__ void top_reduce(int& mx, int& sum, int (*red)[2]) {
+  const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+  for (int o = 32; o > 0; o >>= 1) {
+    mx = max(mx, __shfl_xor(mx, o, 64));
+    sum += __shfl_xor(sum, o, 64);
+  }
+  if (lane == 0) {
+    red[w][0] = mx;
+    red[w][1] = sum;
+  }
+  __syncthreads();
+  mx = 0;
+  sum = 0;
+  for (int k = 0; k < kTopWaves; ++k) {
+    mx = max(mx, red[k][0]);
+    sum += red[k][1];
+  }
+  __syncthreads();
+}
+
+// One workgroup per block; per side: equal-point flags, the node runs and
+// keys, the knode-th largest key by a radix select on 8-bit digits, then the
+// chosen nodes' dofs listed in increasing position.
+__global__ void __launch_bounds__(kTopBlock)
     k_skel_topk_nodes(const float* __restrict__ score, const float* __restrict__ xyz,
                       const BdlrTask* __restrict__ tasks, const int* __restrict__ budget,
                       const int* __restrict__ skip, int skel, int* __restrict__ sel, int* __restrict__ counts) {
   __shared__ unsigned key[kBdlrMaxSide];
+  __shared__ float sco[kBdlrMaxSide];
+  __shared__ unsigned char eqp[kBdlrMaxSide];  // position i has the point of position i - 1
   __shared__ unsigned char run[kBdlrMaxSide];  // dofs of the node starting here, 0 elsewhere
   __shared__ unsigned char flag[kBdlrMaxSide];
-  __shared__ int chosen[kDrawPicks];
-  __shared__ int buf[kBlock], red[kBlock / 64];
-  __shared__ int s_nchosen;
+  __shared__ int hist[256];
+  __shared__ int wsum[kTopWaves], red[kTopWaves][2];
+  __shared__ unsigned s_digit, s_need;
   const int x = blockIdx.x, t = threadIdx.x;
   if (skip && skip[x]) return;
   const BdlrTask tk = tasks[x];
   for (int side = 0; side < 2; ++side) {
     const int len = side == 0 ? tk.m : tk.nc, v0 = side == 0 ? tk.row0 : tk.col0;
     const int off = tk.samp0 + (side == 0 ? 0 : tk.m);
+    for (int i = t; i < len; i += kTopBlock) {
+      eqp[i] = i > 0 && same_point(xyz, v0 + i, v0 + i - 1) ? 1 : 0;
+      sco[i] = score[off + i];
+      flag[i] = 0;
+    }
+    __syncthreads();
+    // equal points form an equivalence (exact comparison), so position j has
+    // the point of position i < j iff eqp holds on (i, j]
+    auto back = [&](int i) {  // equal predecessors, counted up to kRunMax
+      int c = 0;
+      while (c < kRunMax && i - c > 0 && eqp[i - c]) ++c;
+      return c;
+    };
     int longest = 0, nstart = 0;
-    for (int i = t; i < len; i += kBlock) {
-      int back = 0;  // equal predecessors, counted up to kRunMax
-      while (back < kRunMax && i - back - 1 >= 0 && same_point(xyz, v0 + i, v0 + i - back - 1)) ++back;
-      const bool start = back == 0 || back >= kRunMax;
+    for (int i = t; i < len; i += kTopBlock) {
+      const int bk = back(i);
+      const bool start = bk == 0 || bk >= kRunMax;
       int g = 0;
       float best = -INFINITY;
       if (start) {
         g = 1;
-        best = score[off + i];
-        while (g < kRunMax && i + g < len && same_point(xyz, v0 + i, v0 + i + g)) {
-          // a dof with kRunMax equal predecessors starts a node of its own
-          int b2 = 0;
-          while (b2 < kRunMax && i + g - b2 - 1 >= 0 && same_point(xyz, v0 + i + g, v0 + i + g - b2 - 1)) ++b2;
-          if (b2 >= kRunMax) break;
-          best = fmaxf(best, score[off + i + g]);
+        best = sco[i];
+        // a dof with kRunMax equal predecessors starts a node of its own
+        while (g < kRunMax && i + g < len && eqp[i + g] && back(i + g) < kRunMax) {
+          best = fmaxf(best, sco[i + g]);
           ++g;
         }
       }
       run[i] = (unsigned char)g;
-      flag[i] = 0;
       key[i] = start ? max(score_key(best), 1u) : 0u;
       longest = max(longest, g);
       nstart += start ? 1 : 0;
     }
-    for (int o = 32; o > 0; o >>= 1) longest = max(longest, __shfl_xor(longest, o, 64));
-    __syncthreads();
-    if ((t & 63) == 0) red[t >> 6] = longest;
-    __syncthreads();
-    longest = 0;
-    for (int w = 0; w < kBlock / 64; ++w) longest = max(longest, red[w]);
-    nstart = block_count(nstart, red);  // (block_count ends with a barrier)
+    top_reduce(longest, nstart, red);
     const int k = min(budget[2 * x + side], min(skel, len));
     const int knode = min(nstart, max(1, k / max(1, longest)));
-    topk_side(key, len, knode, chosen, &s_nchosen, buf, red);
-    const int nch = s_nchosen;
-    for (int c = t; c < nch; c += kBlock) {
-      const int p = chosen[c];
-      for (int j = 0; j < run[p]; ++j) flag[p + j] = 1;
+    // the knode-th largest key thr, digit by digit from the top; take = the
+    // number of keys equal to thr that are chosen (the lowest positions)
+    unsigned thr = 0u, mask = 0u;
+    int take = knode;
+    const bool all = knode >= len;
+    if (!all) {
+      for (int shift = 24; shift >= 0; shift -= 8) {
+        for (int q = t; q < 256; q += kTopBlock) hist[q] = 0;
+        __syncthreads();
+        for (int i = t; i < len; i += kTopBlock) {
+          const unsigned kv = key[i];
+          if ((kv & mask) == thr) atomicAdd(&hist[(kv >> shift) & 255u], 1);
+        }
+        __syncthreads();
+        if (t < 64) {
+          // lane l holds digits 255 - 4 l .. 252 - 4 l; suffix sums from the top
+          int c[4], cs = 0;
+#pragma unroll
+          for (int u = 0; u < 4; ++u) {
+            c[u] = hist[255 - 4 * t - u];
+            cs += c[u];
+          }
+          int incl = cs;
+#pragma unroll
+          for (int o = 1; o < 64; o <<= 1) {
+            const int y = __shfl_up(incl, o, 64);
+            if (t >= o) incl += y;
+          }
+          int above = incl - cs;  // keys in the digits above this lane's four
+          for (int u = 0; u < 4; ++u) {
+            if (above < take && above + c[u] >= take) {
+              s_digit = 255u - 4u * t - u;
+              s_need = (unsigned)(take - above);
+            }
+            above += c[u];
+          }
+        }
+        __syncthreads();
+        // (the next write of s_digit comes two barriers later, and hist was
+        // read before the barrier above)
+        thr |= s_digit << shift;
+        mask |= 255u << shift;
+        take = (int)s_need;
+      }
+    }
+    // positions of the keys equal to thr, in order, pick the first take
+    const int seg = (len + kTopBlock - 1) / kTopBlock, b0 = min(len, t * seg), b1 = min(len, b0 + seg);
+    int ne = 0, tot;
+    if (!all)
+      for (int i = b0; i < b1; ++i) ne += key[i] == thr ? 1 : 0;
+    int e = top_scan(ne, wsum, &tot) - ne;
+    for (int i = b0; i < b1; ++i) {
+      const unsigned kv = key[i];
+      const bool ise = !all && kv == thr;
+      if (kv != 0u && (all || kv > thr || (ise && e < take)))
+        for (int j = 0; j < run[i]; ++j) flag[i + j] = 1;
+      e += ise ? 1 : 0;
     }
     __syncthreads();
     // the flagged positions in increasing order
-    const int seg = (len + kBlock - 1) / kBlock, b0 = min(len, t * seg), b1 = min(len, b0 + seg);
-    int nf = 0, tot;
+    int nf = 0;
     for (int i = b0; i < b1; ++i) nf += flag[i];
-    int pos = block_exclusive_scan(nf, buf, &tot);
+    int pos = top_scan(nf, wsum, &tot) - nf;
     int* out = sel + tk.sel_off + side * skel;
     for (int i = b0; i < b1; ++i)
       if (flag[i]) out[pos++] = i;
@@ -1253,7 +1406,8 @@ __global__ void k_cand_positions(const BdlrTask* __restrict__ tasks, int nt, con
 
 __global__ void k_cand_err(const BdlrTask* __restrict__ tasks, int nt, const int* __restrict__ cnt,
                            const double* __restrict__ norm2, const int* __restrict__ pos, int G,
-                           const double* __restrict__ part, const int* __restrict__ skip, double* __restrict__ err) {
+                           const double* __restrict__ part, int nch, const int* __restrict__ skip,
+                           double* __restrict__ err) {
   const int x = blockIdx.x * blockDim.x + threadIdx.x;
   if (x >= nt || (skip && skip[x])) return;
   const BdlrTask tk = tasks[x];
@@ -1261,8 +1415,8 @@ __global__ void k_cand_err(const BdlrTask* __restrict__ tasks, int nt, const int
   for (int side = 0; side < 2; ++side) {
     double exact = 0.0, sampled = 0.0;
     for (int g = 0; g < G; ++g)
-      for (int c = 0; c < kCheckChunks; ++c) {
-        const double v = part[(((size_t)x * G + g) * kCheckChunks + c) * 2 + side];
+      for (int c = 0; c < nch; ++c) {
+        const double v = part[(((size_t)x * G + g) * nch + c) * 2 + side];
         if (g == G - 1) sampled += v;
         else exact += v;
       }
@@ -1299,7 +1453,7 @@ static int learned_t(hodlr_s* h, const double* K, int ldk, const int* rowptr, co
   HODLR_TRY(d_state.ensure((size_t)nt * sizeof(int)));
   HODLR_TRY(d_kused.ensure((size_t)nt * sizeof(int)));
   SkelScratch sc;
-  HODLR_TRY(sc.ensure(nt, selo, invo, cgo, sizeof(T)));
+  HODLR_TRY(sc.ensure(nt, selo, invo, cgo, sizeof(T), check_chunks(tasks)));
   HODLR_TRY(block_norms(K, ldk, tasks, sc, s));  // also uploads the task table to sc.tasks
   {
     ProfScope prof("skel_features", s);
@@ -1315,21 +1469,64 @@ static int learned_t(hodlr_s* h, const double* K, int ldk, const int* rowptr, co
   k_learned_init<<<g1, kBlock, 0, s>>>(sc.tasks.as<BdlrTask>(), nt, d_dcnt.as<int>(), kinit, SKEL,
                                        d_budget.as<int>(), d_state.as<int>(), d_kused.as<int>());
   HODLR_HIP(hipGetLastError());
-  // every attempt is queued at once; blocks already decided skip its kernels
-  for (int attempt = 0; attempt < kLearnedAttempts; ++attempt) {
-    {
-      ProfScope prof("skel_topk", s);
-      k_skel_topk_nodes<<<nt, kBlock, 0, s>>>(d_score.as<float>(), xyz, sc.tasks.as<BdlrTask>(), d_budget.as<int>(),
-                                              d_state.as<int>(), SKEL, sc.sel.as<int>(), sc.cnt.as<int>());
+  // Every attempt is queued at once; blocks already decided skip its
+  // kernels.  A block's attempts depend only on its own decisions, so the
+  // blocks of levels 1 and 2 (the largest picks, so the longest
+  // eliminations) run their attempts on a side stream beside those of the
+  // other levels, and the build waits for the longer of the two chains.
+  struct Group {
+    int x0, n, maxside;
+    hipStream_t st;
+  };
+  std::vector<Group> groups;
+  {
+    int nA = 0;
+    while (nA < nt && 31 - __builtin_clz(tasks[nA].node + 1) <= 2) ++nA;
+    for (int g = 0; g < 2; ++g) {
+      const int x0 = g == 0 ? 0 : nA, x1 = g == 0 ? nA : nt;
+      if (x1 <= x0) continue;
+      int ms = 0;
+      for (int x = x0; x < x1; ++x) ms = std::max(ms, std::max(tasks[x].m, tasks[x].nc));
+      groups.push_back({x0, x1 - x0, ms, s});
     }
-    HODLR_HIP(hipGetLastError());
-    HODLR_TRY((skel_attempt_launch<T, SKEL>(h, K, ldk, nt, maxside, sc, Ucap, Vcap, seed, attempt,
-                                            d_state.as<int>(), s)));
-    k_learned_decide<<<g1, kBlock, 0, s>>>(sc.tasks.as<BdlrTask>(), nt, sc.err.as<double>(), accept, SKEL,
-                                           h->precision == 64 ? kRankCap64 : kRankCap32,
-                                           attempt == kLearnedAttempts - 1 ? 1 : 0, sc.rt.as<int>(),
-                                           d_budget.as<int>(), d_state.as<int>(), d_kused.as<int>());
-    HODLR_HIP(hipGetLastError());
+  }
+  struct Join {  // waits for the side stream on every return (the scratch outlives its work)
+    hipStream_t side = nullptr;
+    hipEvent_t e[2] = {nullptr, nullptr};
+    ~Join() {
+      if (side) (void)hipStreamSynchronize(side);
+      for (auto x : e)
+        if (x) (void)hipEventDestroy(x);
+    }
+  } join;
+  if (groups.size() == 2) {
+    HODLR_TRY(side_stream(1, &groups[0].st));
+    join.side = groups[0].st;
+    for (auto& x : join.e) HODLR_HIP(hipEventCreateWithFlags(&x, hipEventDisableTiming));
+    HODLR_HIP(hipEventRecord(join.e[0], s));
+    HODLR_HIP(hipStreamWaitEvent(join.side, join.e[0], 0));
+  }
+  for (int attempt = 0; attempt < kLearnedAttempts; ++attempt)
+    for (const Group& g : groups) {
+      const AttemptView v = attempt_view(sc, g.x0);
+      int* state_g = d_state.as<int>() + g.x0;
+      int* budget_g = d_budget.as<int>() + 2 * g.x0;
+      {
+        ProfScope prof("skel_topk", g.st);
+        k_skel_topk_nodes<<<g.n, kTopBlock, 0, g.st>>>(d_score.as<float>(), xyz, v.tasks, budget_g, state_g, SKEL,
+                                                       sc.sel.as<int>(), v.cnt);
+      }
+      HODLR_HIP(hipGetLastError());
+      HODLR_TRY((skel_attempt_launch<T, SKEL>(h, K, ldk, g.n, g.maxside, sc, v, Ucap, Vcap, seed, attempt, state_g,
+                                              g.st)));
+      k_learned_decide<<<(g.n + kBlock - 1) / kBlock, kBlock, 0, g.st>>>(
+          v.tasks, g.n, v.err, accept, SKEL, h->precision == 64 ? kRankCap64 : kRankCap32,
+          attempt == kLearnedAttempts - 1 ? 1 : 0, v.rt, budget_g, state_g, d_kused.as<int>() + g.x0);
+      HODLR_HIP(hipGetLastError());
+    }
+  if (join.side) {
+    HODLR_HIP(hipEventRecord(join.e[1], join.side));
+    HODLR_HIP(hipStreamWaitEvent(s, join.e[1], 0));
   }
   std::vector<int> state(nt), kused(nt);
   HODLR_HIP(hipMemcpyAsync(state.data(), d_state.p, nt * sizeof(int), hipMemcpyDeviceToHost, s));
@@ -1347,7 +1544,7 @@ static int learned_t(hodlr_s* h, const double* K, int ldk, const int* rowptr, co
     {
       constexpr int G = (SKEL + kSkelSamples - 1) / kSkelSamples + 1;
       HODLR_TRY(pos2.ensure((size_t)nt * G * 2 * kSkelSamples * sizeof(int)));
-      HODLR_TRY(part2.ensure((size_t)nt * G * kCheckChunks * 2 * sizeof(double)));
+      HODLR_TRY(part2.ensure((size_t)nt * G * sc.nch * 2 * sizeof(double)));
     }
     HODLR_TRY(U2.ensure((size_t)tr.n * C * sizeof(T)));
     HODLR_TRY(V2.ensure((size_t)tr.n * C * sizeof(T)));
@@ -1374,11 +1571,11 @@ static int learned_t(hodlr_s* h, const double* K, int ldk, const int* rowptr, co
     {
       ProfScope prof("skel_check", s);
       for (int cand = 0; cand < 2; ++cand) {
-        k_skel_check<T><<<dim3(nt, kCheckChunks, G), kBlock, 0, s>>>(
+        k_skel_check<T><<<dim3(nt, sc.nch, G), kBlock, 0, s>>>(
             K, ldk, sc.tasks.as<BdlrTask>(), cand ? rank2.as<int>() : sc.rt.as<int>(), cand ? U2.as<T>() : Ucap,
             cand ? V2.as<T>() : Vcap, tr.n, pos2.as<int>(), kSkelSamples, part2.as<double>(), skip2.as<int>());
         k_cand_err<<<g1, kBlock, 0, s>>>(sc.tasks.as<BdlrTask>(), nt, sc.cnt.as<int>(), sc.norm.as<double>(),
-                                         pos2.as<int>(), G, part2.as<double>(), skip2.as<int>(),
+                                         pos2.as<int>(), G, part2.as<double>(), sc.nch, skip2.as<int>(),
                                          cand ? err2.as<double>() : sc.err.as<double>());
       }
     }
@@ -1419,7 +1616,7 @@ static int adaptive_t(hodlr_s* h, const double* K, int ldk, const int* rowptr, c
   int maxside = 0;
   for (auto& tk : tasks) maxside = std::max(maxside, std::max(tk.m, tk.nc));
   SkelScratch sc;
-  HODLR_TRY(sc.ensure(nt, selo, invo, cgo, sizeof(T)));
+  HODLR_TRY(sc.ensure(nt, selo, invo, cgo, sizeof(T), check_chunks(tasks)));
   HODLR_TRY(block_norms(K, ldk, tasks, sc, s));
   HODLR_HIP(hipMemsetAsync(h->d_rank.p, 0, tr.nnodes() * sizeof(int), s));
   h->skel_k.assign(tr.nnodes(), -1);
@@ -1532,18 +1729,19 @@ int sampled_error_t(const double* K, int ldk, const Tree& tr, const T* U, const 
   HODLR_TRY(sc.tasks.ensure(nt * sizeof(BdlrTask)));
   HODLR_TRY(sc.rt.ensure(nt * sizeof(int)));
   HODLR_TRY(sc.norm.ensure((size_t)nt * kNormChunks * sizeof(double)));
-  HODLR_TRY(sc.part.ensure((size_t)nt * kCheckChunks * 2 * sizeof(double)));
+  const int nch = check_chunks(tasks);
+  HODLR_TRY(sc.part.ensure((size_t)nt * nch * 2 * sizeof(double)));
   HODLR_HIP(hipMemcpyAsync(sc.rt.p, ranks, nt * sizeof(int), hipMemcpyHostToDevice, s));
   HODLR_TRY(block_norms(K, ldk, tasks, sc, s));
   k_draw_samples<<<nt, 64, 0, s>>>(sc.tasks.as<BdlrTask>(), picks, counts, max_skel, seed, attempt, kSkelSamples,
                                    samples, nullptr);
   HODLR_HIP(hipGetLastError());
-  k_skel_check<T><<<dim3(nt, kCheckChunks), kBlock, 0, s>>>(K, ldk, sc.tasks.as<BdlrTask>(), sc.rt.as<int>(), U, V,
+  k_skel_check<T><<<dim3(nt, nch), kBlock, 0, s>>>(K, ldk, sc.tasks.as<BdlrTask>(), sc.rt.as<int>(), U, V,
                                                              tr.n, samples, kSkelSamples, sc.part.as<double>(),
                                                              nullptr);
   HODLR_HIP(hipGetLastError());
   k_skel_err<<<(nt + kBlock - 1) / kBlock, kBlock, 0, s>>>(sc.tasks.as<BdlrTask>(), nt, counts, sc.norm.as<double>(),
-                                                          samples, kSkelSamples, sc.part.as<double>(), err,
+                                                          samples, kSkelSamples, sc.part.as<double>(), nch, err,
                                                           nullptr);
   HODLR_HIP(hipGetLastError());
   HODLR_HIP(hipStreamSynchronize(s));  // the scratch goes back to the allocator cache

@@ -41,161 +41,152 @@ __device__ __forceinline__ float bf16_round(float x) {
 // ---------------------------------------------------------------------------
 // Features
 // ---------------------------------------------------------------------------
-__device__ float block_max(float v, float* red) {
-  for (int o = 32; o > 0; o >>= 1) v = fmaxf(v, __shfl_xor(v, o, 64));
-  const int w = threadIdx.x >> 6;
-  __syncthreads();
-  if ((threadIdx.x & 63) == 0) red[w] = v;
-  __syncthreads();
-  float r = red[0];
-  for (int k = 1; k < kBlock / 64; ++k) r = fmaxf(r, red[k]);
-  __syncthreads();
-  return r;
-}
+// One workgroup per (block, side): the side's breadth-first distances from
+// its boundary, its statistics and its vertices' features.  The side is a
+// contiguous range of vertex ids, so its row pointers are one slice, staged
+// in LDS; a vertex's neighbour list is read kNb entries at a time with the
+// loads issued together (one round trip to the cache for most vertices of a
+// 3-dof mesh).
+constexpr int kFeatBlock = 1024, kFeatWaves = kFeatBlock / 64;
+constexpr int kNb = 32;
+constexpr int kStats = 15;  // own: dmax, degree, |K_vv|, -lo[3], hi[3]; other side: -lo[3], hi[3]
+constexpr unsigned kUnreached = 0xffffffffu;
+constexpr int kMaxLayer = kSideMax;  // a side of len vertices has at most len layers
 
-// Breadth-first distances from the boundary of each side of a block, inside
-// that side, both sides in one level loop.  dist[sd]: LDS, len entries;
-// 0xffff = not reached.  Side 0 is [a0, a0+alen), side 1 [b0, b0+blen)
-// (contiguous ranges of vertex ids); the boundary of a side is its vertices
-// with an edge into the other side.  A vertex's neighbour list is read kNb
-// entries at a time with the loads issued together (the lists are long on
-// 3-dof meshes, and each read is a round trip to the cache).
-constexpr int kNb = 8;
-
-__device__ void block_bfs(const int* __restrict__ rowptr, const int* __restrict__ col, int a0, int alen, int b0,
-                          int blen, unsigned short (*dist)[kSideMax], int* s_changed) {
-  const int t = threadIdx.x;
-  for (int sd = 0; sd < 2; ++sd) {
-    const int s0 = sd == 0 ? a0 : b0, len = sd == 0 ? alen : blen;
-    const int o0 = sd == 0 ? b0 : a0, olen = sd == 0 ? blen : alen;
-    for (int i = t; i < len; i += kBlock) {
-      const int v = s0 + i, e1 = rowptr[v + 1];
-      unsigned short d = 0xffff;
-      for (int e0 = rowptr[v]; e0 < e1 && d != 0; e0 += kNb) {
+// dcount (optional): per block, the number of row and of column vertices at
+// distance < cnt_depth (the picks of BDLR at that depth before any cap).
+__global__ void __launch_bounds__(kFeatBlock)
+    k_skel_features(const int* __restrict__ rowptr, const int* __restrict__ col, const float* __restrict__ xyz,
+                    const double* __restrict__ K, int ldk, const SkelBlock* __restrict__ blocks,
+                    float* __restrict__ feats, int cnt_depth, int* __restrict__ dcount) {
+  __shared__ unsigned dist[kSideMax];  // kUnreached = not reached
+  __shared__ int rp[kSideMax + 1];
+  __shared__ float red[kFeatWaves][kStats];
+  __shared__ float st[kStats];
+  __shared__ int flag[3], cnt;
+  const SkelBlock b = blocks[blockIdx.x];
+  const int sd = blockIdx.y, t = threadIdx.x, lane = t & 63, w = t >> 6;
+  const int s0 = sd == 0 ? b.row0 : b.col0, len = sd == 0 ? b.m : b.nc;
+  const int o0 = sd == 0 ? b.col0 : b.row0, olen = sd == 0 ? b.nc : b.m;
+  for (int i = t; i <= len; i += kFeatBlock) rp[i] = rowptr[s0 + i];
+  if (t < 3) flag[t] = 0;
+  if (t == 0) cnt = 0;
+  __syncthreads();
+  // the boundary: vertices with an edge into the other side
+  for (int i = t; i < len; i += kFeatBlock) {
+    const int e1 = rp[i + 1];
+    unsigned d = kUnreached;
+    for (int e0 = rp[i]; e0 < e1 && d != 0; e0 += kNb) {
+      int u[kNb];
+#pragma unroll
+      for (int k = 0; k < kNb; ++k) u[k] = e0 + k < e1 ? col[e0 + k] : -1;
+#pragma unroll
+      for (int k = 0; k < kNb; ++k)
+        if ((unsigned)(u[k] - o0) < (unsigned)olen) d = 0;
+    }
+    dist[i] = d;
+  }
+  __syncthreads();
+  // layer lvl lowers its neighbours inside the side to lvl + 1 (LDS atomic
+  // minima without return, so the loads of a neighbour list go out together
+  // and nothing waits on LDS).  A vertex first lowered in layer lvl is at
+  // distance lvl + 1, and no later layer lowers it further.  One barrier per
+  // layer: a thread that found a vertex of layer lvl sets flag[lvl % 3];
+  // thread 0 clears the flag of layer lvl + 1 before the barrier of layer
+  // lvl, after every reader of that slot (layer lvl - 2) has passed the
+  // barrier of lvl - 1.  The search ends at the first empty layer.
+  for (int lvl = 0; lvl < kMaxLayer; ++lvl) {
+    int found = 0;
+    for (int i = t; i < len; i += kFeatBlock) {
+      if (dist[i] != (unsigned)lvl) continue;
+      found = 1;
+      const int e1 = rp[i + 1];
+      for (int e0 = rp[i]; e0 < e1; e0 += kNb) {
         int u[kNb];
 #pragma unroll
         for (int k = 0; k < kNb; ++k) u[k] = e0 + k < e1 ? col[e0 + k] : -1;
 #pragma unroll
-        for (int k = 0; k < kNb; ++k)
-          if (u[k] >= o0 && u[k] < o0 + olen) d = 0;
-      }
-      dist[sd][i] = d;
-    }
-  }
-  __syncthreads();
-  // layer lvl marks its unmarked out-neighbours inside its side (benign
-  // races: every writer of a vertex writes the same layer number)
-  for (int lvl = 0; lvl < 0xfffe; ++lvl) {
-    if (t == 0) *s_changed = 0;
-    __syncthreads();
-    int ch = 0;
-    for (int sd = 0; sd < 2; ++sd) {
-      const int s0 = sd == 0 ? a0 : b0, len = sd == 0 ? alen : blen;
-      for (int i = t; i < len; i += kBlock) {
-        if (dist[sd][i] != lvl) continue;
-        const int v = s0 + i, e1 = rowptr[v + 1];
-        for (int e0 = rowptr[v]; e0 < e1; e0 += kNb) {
-          int u[kNb];
-#pragma unroll
-          for (int k = 0; k < kNb; ++k) u[k] = e0 + k < e1 ? col[e0 + k] : -1;
-#pragma unroll
-          for (int k = 0; k < kNb; ++k)
-            if (u[k] >= s0 && u[k] < s0 + len && dist[sd][u[k] - s0] == 0xffff) {
-              dist[sd][u[k] - s0] = (unsigned short)(lvl + 1);
-              ch = 1;
-            }
+        for (int k = 0; k < kNb; ++k) {
+          const int j = u[k] - s0;
+          if ((unsigned)j < (unsigned)len) atomicMin(&dist[j], (unsigned)(lvl + 1));
         }
       }
     }
-    if (ch) *s_changed = 1;
+    if (found) flag[lvl % 3] = 1;
+    if (t == 0) flag[(lvl + 1) % 3] = 0;
     __syncthreads();
-    const int any = *s_changed;
-    __syncthreads();
-    if (!any) break;
+    if (!flag[lvl % 3]) break;
   }
-}
-
-// dcount (optional): per block, the number of row and of column vertices at
-// distance < cnt_depth (the picks of BDLR at that depth before any cap).
-__global__ void __launch_bounds__(kBlock)
-    k_skel_features(const int* __restrict__ rowptr, const int* __restrict__ col, const float* __restrict__ xyz,
-                    const double* __restrict__ K, int ldk, const SkelBlock* __restrict__ blocks,
-                    float* __restrict__ feats, int cnt_depth, int* __restrict__ dcount) {
-  __shared__ unsigned short dist[2][kSideMax];
-  __shared__ float red[kBlock / 64];
-  __shared__ int s_changed;
-  const SkelBlock b = blocks[blockIdx.x];
-  const int t = threadIdx.x;
-  block_bfs(rowptr, col, b.row0, b.m, b.col0, b.nc, dist, &s_changed);
-  if (dcount) {
-    __shared__ int cnt[2];
-    if (t < 2) cnt[t] = 0;
-    __syncthreads();
-    for (int sd = 0; sd < 2; ++sd) {
-      const int len = sd == 0 ? b.m : b.nc;
-      int c = 0;
-      for (int i = t; i < len; i += kBlock) c += dist[sd][i] < cnt_depth ? 1 : 0;
-      for (int o = 32; o > 0; o >>= 1) c += __shfl_xor(c, o, 64);
-      if ((t & 63) == 0 && c) atomicAdd(&cnt[sd], c);
-    }
-    __syncthreads();
-    if (t < 2) dcount[2 * blockIdx.x + t] = cnt[t];
-  }
-  // per side: dmax, max degree, box, max |K_vv|
-  float st[2][10];
-  for (int sd = 0; sd < 2; ++sd) {
-    const int s0 = sd == 0 ? b.row0 : b.col0, len = sd == 0 ? b.m : b.nc;
-    float dm = 0.f, dg = 0.f, kd = 0.f, lo[3] = {INFINITY, INFINITY, INFINITY},
-          hi[3] = {-INFINITY, -INFINITY, -INFINITY};
-    for (int i = t; i < len; i += kBlock) {
-      const int v = s0 + i;
-      if (dist[sd][i] != 0xffff) dm = fmaxf(dm, (float)dist[sd][i]);
-      dg = fmaxf(dg, (float)(rowptr[v + 1] - rowptr[v]));
-      kd = fmaxf(kd, (float)fabs(K[(size_t)v * ldk + v]));
-      for (int a = 0; a < 3; ++a) {
-        const float x = xyz[3 * v + a];
-        lo[a] = fminf(lo[a], x);
-        hi[a] = fmaxf(hi[a], x);
-      }
-    }
-    st[sd][0] = block_max(dm, red);
-    st[sd][1] = block_max(dg, red);
-    st[sd][2] = block_max(kd, red);
+  // statistics, all as maxima (minima negated)
+  float v[kStats];
+  for (int q = 0; q < kStats; ++q) v[q] = -INFINITY;
+  v[0] = v[1] = v[2] = 0.f;
+  int c = 0;
+  for (int i = t; i < len; i += kFeatBlock) {
+    const int x = s0 + i;
+    const unsigned d = dist[i];
+    if (d != kUnreached) v[0] = fmaxf(v[0], (float)d);
+    c += d < (unsigned)max(cnt_depth, 0) ? 1 : 0;
+    v[1] = fmaxf(v[1], (float)(rp[i + 1] - rp[i]));
+    v[2] = fmaxf(v[2], (float)fabs(K[(size_t)x * ldk + x]));
     for (int a = 0; a < 3; ++a) {
-      st[sd][3 + a] = -block_max(-lo[a], red);
-      st[sd][6 + a] = block_max(hi[a], red);
+      const float p = xyz[3 * x + a];
+      v[3 + a] = fmaxf(v[3 + a], -p);
+      v[6 + a] = fmaxf(v[6 + a], p);
     }
   }
-  for (int sd = 0; sd < 2; ++sd) {
-    const int s0 = sd == 0 ? b.row0 : b.col0, len = sd == 0 ? b.m : b.nc;
-    const int samp = b.samp0 + (sd == 0 ? 0 : b.m);
-    const float* S = st[sd];
-    const float* O = st[sd ^ 1];
-    float ext[3], diag2 = 0.f;
+  for (int i = t; i < olen; i += kFeatBlock)
     for (int a = 0; a < 3; ++a) {
-      ext[a] = S[6 + a] - S[3 + a];
-      diag2 += ext[a] * ext[a];
+      const float p = xyz[3 * (o0 + i) + a];
+      v[9 + a] = fmaxf(v[9 + a], -p);
+      v[12 + a] = fmaxf(v[12 + a], p);
     }
-    const float diag = sqrtf(diag2);
-    const int olen = sd == 0 ? b.nc : b.m;
-    for (int i = t; i < len; i += kBlock) {
-      const int v = s0 + i;
-      const float d = dist[sd][i] == 0xffff ? S[0] + 1.f : (float)dist[sd][i];
-      float f[NF];
-      f[0] = d / (S[0] + 1.f);
-      f[1] = 1.f / (1.f + d);
-      f[2] = S[1] > 0.f ? (float)(rowptr[v + 1] - rowptr[v]) / S[1] : 0.f;
-      float g2 = 0.f;
-      for (int a = 0; a < 3; ++a) {
-        const float x = xyz[3 * v + a];
-        f[3 + a] = ext[a] > 0.f ? (x - S[3 + a]) / ext[a] : 0.f;
-        const float gap = fmaxf(0.f, fmaxf(O[3 + a] - x, x - O[6 + a]));
-        g2 += gap * gap;
-      }
-      f[6] = S[2] > 0.f ? (float)fabs(K[(size_t)v * ldk + v]) / S[2] : 0.f;
-      f[7] = (olen > 0 && diag > 0.f) ? fminf(1.f, sqrtf(g2) / diag) : 0.f;
-      for (int a = 0; a < NF; ++a) feats[(size_t)(samp + i) * NF + a] = f[a];
+#pragma unroll
+  for (int q = 0; q < kStats; ++q)
+    for (int o = 32; o > 0; o >>= 1) v[q] = fmaxf(v[q], __shfl_xor(v[q], o, 64));
+  for (int o = 32; o > 0; o >>= 1) c += __shfl_xor(c, o, 64);
+  if (lane == 0) {
+    for (int q = 0; q < kStats; ++q) red[w][q] = v[q];
+    if (c) atomicAdd(&cnt, c);
+  }
+  __syncthreads();
+  if (t < kStats) {
+    float r = red[0][t];
+    for (int k = 1; k < kFeatWaves; ++k) r = fmaxf(r, red[k][t]);
+    st[t] = r;
+  }
+  __syncthreads();
+  if (dcount && t == 0) dcount[2 * blockIdx.x + sd] = cnt;
+  const float dmax = st[0], dgmax = st[1], kdmax = st[2];
+  float lo[3], ext[3], olo[3], ohi[3], diag2 = 0.f;
+  for (int a = 0; a < 3; ++a) {
+    lo[a] = -st[3 + a];
+    ext[a] = st[6 + a] - lo[a];
+    olo[a] = -st[9 + a];
+    ohi[a] = st[12 + a];
+    diag2 += ext[a] * ext[a];
+  }
+  const float diag = sqrtf(diag2);
+  float* F = feats + (size_t)(b.samp0 + (sd == 0 ? 0 : b.m)) * NF;
+  for (int i = t; i < len; i += kFeatBlock) {
+    const int x = s0 + i;
+    const float d = dist[i] == kUnreached ? dmax + 1.f : (float)dist[i];
+    float f[NF];
+    f[0] = d / (dmax + 1.f);
+    f[1] = 1.f / (1.f + d);
+    f[2] = dgmax > 0.f ? (float)(rp[i + 1] - rp[i]) / dgmax : 0.f;
+    float g2 = 0.f;
+    for (int a = 0; a < 3; ++a) {
+      const float p = xyz[3 * x + a];
+      f[3 + a] = ext[a] > 0.f ? (p - lo[a]) / ext[a] : 0.f;
+      const float gap = fmaxf(0.f, fmaxf(olo[a] - p, p - ohi[a]));
+      g2 += gap * gap;
     }
+    f[6] = kdmax > 0.f ? (float)fabs(K[(size_t)x * ldk + x]) / kdmax : 0.f;
+    f[7] = (olen > 0 && diag > 0.f) ? fminf(1.f, sqrtf(g2) / diag) : 0.f;
+    float4* o = reinterpret_cast<float4*>(F + (size_t)i * NF);
+    o[0] = make_float4(f[0], f[1], f[2], f[3]);
+    o[1] = make_float4(f[4], f[5], f[6], f[7]);
   }
 }
 
@@ -468,8 +459,8 @@ int launch_skel_features(const int* rowptr, const int* col, const float* xyz, co
   DevBuf d;
   HODLR_TRY(d.ensure(blocks.size() * sizeof(SkelBlock)));
   HODLR_HIP(hipMemcpyAsync(d.p, blocks.data(), blocks.size() * sizeof(SkelBlock), hipMemcpyHostToDevice, s));
-  k_skel_features<<<(unsigned)blocks.size(), kBlock, 0, s>>>(rowptr, col, xyz, K, ldk, d.as<SkelBlock>(), feats,
-                                                            cnt_depth, dcount);
+  k_skel_features<<<dim3((unsigned)blocks.size(), 2), kFeatBlock, 0, s>>>(rowptr, col, xyz, K, ldk,
+                                                                         d.as<SkelBlock>(), feats, cnt_depth, dcount);
   HODLR_HIP(hipGetLastError());
   d.release_after(s);  // the block table goes back to the cache once the kernel has read it
   return HODLR_OK;
