@@ -19,6 +19,7 @@
 // pseudo-skeleton C~ R~ of eq. Ahat; the split between the two factors
 // differs (one r x r inverse and one panel product instead of two of each).
 #include <algorithm>
+#include <cstring>
 #include <climits>
 #include <cstdint>
 
@@ -701,46 +702,62 @@ __device__ __forceinline__ unsigned score_key(float x) {
   return (u & 0x80000000u) ? ~u : (u | 0x80000000u);
 }
 
-// |K(I, J)|_F^2 of every block, in kNormChunks column chunks per block (a
-// chunk of a small block may be empty); a thread keeps eight loads in flight
-// (a chunk is read as one flat range of column-major entries).  Many chunks
-// per block keep the largest blocks spread over many workgroups.
-// k_norm_total then adds a block's chunks in a fixed order into its first
-// slot, which is what the checks read.
-constexpr int kNormChunks = 256;
+// |K(I, J)|_F^2 of every block.  The blocks are cut into chunks of whole
+// columns of about kNormEntries entries, numbered across all blocks (block x
+// owns chunks c0[x] .. c0[x + 1] - 1), one workgroup per chunk, so the work
+// per workgroup is the same for every block size.  A thread walks the
+// chunk's entries in column-major order with a stride of the workgroup size
+// (row and column advanced incrementally, no division per load), eight
+// loads in flight.  k_norm_total then adds a block's chunks in order into
+// norm2[x], the slot the checks read; the chunk sums sit after the nt totals.
+constexpr int kNormEntries = 16384;
 __global__ void __launch_bounds__(kBlock)
     k_block_norm2(const double* __restrict__ K, int ldk, const BdlrTask* __restrict__ tasks,
-                  double* __restrict__ part) {
+                  const int* __restrict__ c0, int nt, double* __restrict__ part) {
   __shared__ double red[kBlock / 64];
-  const BdlrTask tk = tasks[blockIdx.x];
-  const int per = (tk.nc + kNormChunks - 1) / kNormChunks, j0 = blockIdx.y * per, j1 = min(tk.nc, j0 + per);
-  const long tot = j1 > j0 ? (long)tk.m * (j1 - j0) : 0;
+  const int c = blockIdx.x, t = threadIdx.x;
+  int lo = 0, hi = nt;  // the block of chunk c: the last x with c0[x] <= c
+  while (hi - lo > 1) {
+    const int mid = (lo + hi) >> 1;
+    if (c0[mid] <= c) lo = mid;
+    else hi = mid;
+  }
+  const BdlrTask tk = tasks[lo];
+  const int m = tk.m, cols = max(1, kNormEntries / m);
+  const int j0 = (c - c0[lo]) * cols, ncol = min(tk.nc, j0 + cols) - j0;
+  const double* B = K + (size_t)(tk.col0 + j0) * ldk + tk.row0;
+  const int di = kBlock % m, dj = kBlock / m;
+  int i = t % m, j = t / m;
   constexpr int kU = 8;
   double acc = 0.0;
-  for (long e0 = threadIdx.x; e0 < tot; e0 += kU * kBlock) {
+  while (j < ncol) {
     double v[kU];
 #pragma unroll
     for (int u = 0; u < kU; ++u) {
-      const long e = e0 + (long)u * kBlock;
-      v[u] = e < tot ? K[(size_t)(tk.col0 + j0 + e / tk.m) * ldk + tk.row0 + e % tk.m] : 0.0;
+      v[u] = j < ncol ? B[(size_t)j * ldk + i] : 0.0;
+      i += di;
+      j += dj;
+      if (i >= m) {
+        i -= m;
+        ++j;
+      }
     }
 #pragma unroll
     for (int u = 0; u < kU; ++u) acc += v[u] * v[u];
   }
   acc = block_sum(acc, red);
-  if (threadIdx.x == 0) part[(size_t)blockIdx.x * kNormChunks + blockIdx.y] = acc;
+  if (t == 0) part[c] = acc;
 }
 
 // One wave per block: lane l adds chunks l, l + 64, ... in order, then the
-// lanes are combined by a fixed butterfly; the total goes to chunk slot 0.
-__global__ void __launch_bounds__(64) k_norm_total(double* __restrict__ part) {
-  double* p = part + (size_t)blockIdx.x * kNormChunks;
-  const int lane = threadIdx.x;
+// lanes are combined by a fixed butterfly.
+__global__ void __launch_bounds__(64)
+    k_norm_total(const int* __restrict__ c0, const double* __restrict__ part, double* __restrict__ norm2) {
+  const int x = blockIdx.x, lane = threadIdx.x;
   double s = 0.0;
-  for (int c = lane; c < kNormChunks; c += 64) s += p[c];
+  for (int c = c0[x] + lane; c < c0[x + 1]; c += 64) s += part[c];
   for (int o = 1; o < 64; o <<= 1) s += __shfl_xor(s, o, 64);
-  __syncthreads();
-  if (lane == 0) p[0] = s;
+  if (lane == 0) norm2[x] = s;
 }
 
 // Estimated relative Frobenius error of U V^T on the block: the residual on
@@ -748,8 +765,7 @@ __global__ void __launch_bounds__(64) k_norm_total(double* __restrict__ part) {
 // (rows sampled), over |K(I, J)|_F^2; the same over columns; the larger of
 // the two (float64).  samp: per task 2 * ns entries (rows, then columns; -1 =
 // unused), ns <= 16; counts: rows and columns picked per task; norm2: per
-// task of the whole list (BdlrTask::task), kNormChunks partial sums of
-// |K(I, J)|_F^2.
+// task of the whole list (BdlrTask::task), |K(I, J)|_F^2.
 //
 // k_skel_check: workgroup (task, chunk, group) sums the squared residual of
 // the group's rows over its chunk of kCheckX columns (and of the group's
@@ -886,7 +902,7 @@ __global__ void k_skel_err(const BdlrTask* __restrict__ tasks, int ntask, const 
     const int outside = (side == 0 ? tk.m : tk.nc) - counts[2 * x + side];
     if (used > 0) est = fmax(est, num * (double)outside / (double)used);
   }
-  const double nb = norm2[(size_t)tk.task * kNormChunks];  // the block's total (k_norm_total)
+  const double nb = norm2[tk.task];  // the block's total (k_norm_total)
   err[x] = nb > 0.0 ? sqrt(est / nb) : sqrt(est);
 }
 
@@ -1006,7 +1022,7 @@ struct SkelScratch {
     HODLR_TRY(samp.ensure((size_t)nt * 2 * kSkelSamples * sizeof(int)));
     HODLR_TRY(err.ensure((size_t)nt * sizeof(double)));
     HODLR_TRY(part.ensure((size_t)nt * nch * 2 * sizeof(double)));
-    return norm.ensure((size_t)nt * kNormChunks * sizeof(double));
+    return HODLR_OK;  // norm: sized by block_norms
   }
 };
 
@@ -1015,11 +1031,27 @@ struct SkelScratch {
 // then overwrites with its own.
 static int block_norms(const double* K, int ldk, const std::vector<BdlrTask>& tasks, SkelScratch& sc, hipStream_t s) {
   const int nt = (int)tasks.size();
-  HODLR_HIP(hipMemcpyAsync(sc.tasks.p, tasks.data(), nt * sizeof(BdlrTask), hipMemcpyHostToDevice, s));
+  // chunk numbering (c0, nt + 1 ints) after the task records in one upload
+  std::vector<int> c0(nt + 1, 0);
+  for (int x = 0; x < nt; ++x) {
+    const int cols = std::max(1, kNormEntries / std::max(tasks[x].m, 1));
+    c0[x + 1] = c0[x] + (tasks[x].nc + cols - 1) / cols;
+  }
+  const int nchunk = c0[nt];
+  const size_t tb = (size_t)nt * sizeof(BdlrTask);
+  std::vector<unsigned char> up(tb + (nt + 1) * sizeof(int));
+  std::memcpy(up.data(), tasks.data(), tb);
+  std::memcpy(up.data() + tb, c0.data(), (nt + 1) * sizeof(int));
+  HODLR_TRY(sc.tasks.ensure(up.size()));
+  HODLR_TRY(sc.norm.ensure(((size_t)nt + nchunk) * sizeof(double)));
+  HODLR_HIP(hipMemcpyAsync(sc.tasks.p, up.data(), up.size(), hipMemcpyHostToDevice, s));
+  const int* d_c0 = reinterpret_cast<const int*>(static_cast<unsigned char*>(sc.tasks.p) + tb);
   ProfScope prof("skel_check", s);
-  k_block_norm2<<<dim3(nt, kNormChunks), kBlock, 0, s>>>(K, ldk, sc.tasks.as<BdlrTask>(), sc.norm.as<double>());
-  HODLR_HIP(hipGetLastError());
-  k_norm_total<<<nt, 64, 0, s>>>(sc.norm.as<double>());
+  if (nchunk > 0) {
+    k_block_norm2<<<nchunk, kBlock, 0, s>>>(K, ldk, sc.tasks.as<BdlrTask>(), d_c0, nt, sc.norm.as<double>() + nt);
+    HODLR_HIP(hipGetLastError());
+  }
+  k_norm_total<<<nt, 64, 0, s>>>(d_c0, sc.norm.as<double>() + nt, sc.norm.as<double>());
   HODLR_HIP(hipGetLastError());
   return HODLR_OK;
 }
@@ -1427,7 +1459,7 @@ __global__ void k_cand_err(const BdlrTask* __restrict__ tasks, int nt, const int
     const double e = exact + (used > 0 ? sampled * (double)outside / (double)used : 0.0);
     est = fmax(est, e);
   }
-  const double nb = norm2[(size_t)tk.task * kNormChunks];  // the block's total (k_norm_total)
+  const double nb = norm2[tk.task];  // the block's total (k_norm_total)
   err[x] = nb > 0.0 ? sqrt(est / nb) : sqrt(est);
 }
 
@@ -1728,7 +1760,6 @@ int sampled_error_t(const double* K, int ldk, const Tree& tr, const T* U, const 
   SkelScratch sc;
   HODLR_TRY(sc.tasks.ensure(nt * sizeof(BdlrTask)));
   HODLR_TRY(sc.rt.ensure(nt * sizeof(int)));
-  HODLR_TRY(sc.norm.ensure((size_t)nt * kNormChunks * sizeof(double)));
   const int nch = check_chunks(tasks);
   HODLR_TRY(sc.part.ensure((size_t)nt * nch * 2 * sizeof(double)));
   HODLR_HIP(hipMemcpyAsync(sc.rt.p, ranks, nt * sizeof(int), hipMemcpyHostToDevice, s));

@@ -322,20 +322,32 @@ __global__ void __launch_bounds__(kBlock) k_scan(const int* __restrict__ deg, in
   if (t == kBlock - 1) out[n] = part[kBlock - 1];
 }
 
-__global__ void k_fill_sorted(const int* __restrict__ rowptr, const int* __restrict__ col,
-                              const int* __restrict__ perm, const int* __restrict__ inv,
-                              const int* __restrict__ rowptr_out, int* __restrict__ col_out, int n) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+// One wave per new row i: the row's new column ids, each placed at its rank
+// (the entries below it, equal entries by their old order), so the row is
+// sorted ascending.  The entries are taken 64 at a time, one per lane; a
+// rank counts over all chunks of the row.
+__global__ void __launch_bounds__(kBlock)
+    k_fill_sorted(const int* __restrict__ rowptr, const int* __restrict__ col, const int* __restrict__ perm,
+                  const int* __restrict__ inv, const int* __restrict__ rowptr_out, int* __restrict__ col_out,
+                  int n) {
+  const int lane = threadIdx.x & 63;
+  const int i = __builtin_amdgcn_readfirstlane(blockIdx.x * (kBlock / 64) + (threadIdx.x >> 6));
   if (i >= n) return;
-  const int src = perm[i], b = rowptr[src], e = rowptr[src + 1], o = rowptr_out[i];
-  for (int x = b; x < e; ++x) {
-    const int v = inv[col[x]];
-    int y = o + (x - b);
-    while (y > o && col_out[y - 1] > v) {  // insertion sort of the short row
-      col_out[y] = col_out[y - 1];
-      --y;
+  const int src = perm[i], b = rowptr[src], deg = rowptr[src + 1] - b, o = rowptr_out[i];
+  for (int cx = 0; cx < deg; cx += 64) {
+    const int x = cx + lane;
+    const int v = x < deg ? inv[col[b + x]] : INT_MAX;
+    int rank = 0;
+    for (int cy = 0; cy < deg; cy += 64) {
+      const int y = cy + lane;
+      const int u = cy == cx ? v : (y < deg ? inv[col[b + y]] : INT_MAX);
+      const int ny = min(64, deg - cy);
+      for (int j = 0; j < ny; ++j) {
+        const int uj = __builtin_amdgcn_readlane(u, j);
+        rank += (uj < v || (uj == v && cy + j < x)) ? 1 : 0;
+      }
     }
-    col_out[y] = v;
+    if (x < deg) col_out[o + rank] = v;
   }
 }
 
@@ -351,7 +363,8 @@ int launch_permute_graph(const int* rowptr, const int* col, int n, const int* pe
   k_inverse_perm<<<g, kBlock, 0, s>>>(perm, inv, n);
   k_new_degree<<<g, kBlock, 0, s>>>(rowptr, perm, deg, n);
   k_scan<<<1, kBlock, 0, s>>>(deg, rowptr_out, n);
-  k_fill_sorted<<<g, kBlock, 0, s>>>(rowptr, col, perm, inv, rowptr_out, col_out, n);
+  k_fill_sorted<<<(n + kBlock / 64 - 1) / (kBlock / 64), kBlock, 0, s>>>(rowptr, col, perm, inv, rowptr_out,
+                                                                        col_out, n);
   const hipError_t le = hipGetLastError();
   HODLR_HIP(hipFreeAsync(scratch, s));
   if (le != hipSuccess) return fail(HODLR_EHIP, std::string("graph permutation launch: ") + hipGetErrorString(le));
