@@ -329,46 +329,33 @@ __global__ void __launch_bounds__(kSolveThreads)
   const int lane = t & 63, cw = t >> 6;
   const T xr = (lane < rn && cw < nc) ? Xin[(size_t)cw * ldxi + row0 + lane] : T(0);
   // t_P = [W(rows a)^T x_a (r_b entries); W(rows b)^T x_b (r_a entries)] from
-  // the group sums of both children, as [z][SM]
+  // the group sums of both children, as [z][SM]: entry e = z + r c (c < nc)
+  // adds its ng slots in slot order with up to kJ loads in one round trip
+  // (issued in batches of 4; a batch past the last slot is skipped, and the
+  // addresses are clamped into range).  Columns c >= nc are zero.
   const size_t usz = (size_t)rq * nc, gstride = (size_t)gin * usz;
   const int ng = upn / gin;
-  // up to kJ slots per element in one round trip, issued in batches of 4
-  // (a batch past the last slot is skipped); the addresses are clamped into
-  // range and the entries outside the block are masked afterwards
-  constexpr int kE = 2, kJ = 16;
-  for (int e0 = 0; e0 < r * SM; e0 += kE * kSolveThreads) {
-    T s[kE];
-    const T* p0[kE];
-    bool ok[kE];
-#pragma unroll
-    for (int a = 0; a < kE; ++a) {
-      const int e = e0 + t + a * kSolveThreads, z = e % r, cc = min(e / r, nc - 1);
-      ok[a] = e < r * SM && e / r < nc;
+  constexpr int kJ = sizeof(T) == 8 ? 16 : SM == 8 ? 48 : 32;
+  for (int e = t; e < r * SM; e += kSolveThreads) {
+    const int z = e % r, cc = e / r;
+    T sum = T(0);
+    if (cc < nc) {
       const int node = (z < rb) ? 2 * par : 2 * par + 1, zz = (z < rb) ? z : z - rb;
-      p0[a] = Pin + (size_t)node * upn * usz + zz + (size_t)cc * rq;
-      s[a] = T(0);
-    }
-    for (int j0 = 0; j0 < ng; j0 += kJ) {
-      T v[kE][kJ];
+      const T* p0 = Pin + (size_t)node * upn * usz + zz + (size_t)cc * rq;
+      for (int j0 = 0; j0 < ng; j0 += kJ) {
+        T v[kJ];
 #pragma unroll
-      for (int bq = 0; bq < kJ; bq += 4)
-        if (j0 + bq < ng) {
+        for (int bq = 0; bq < kJ; bq += 4)
+          if (j0 + bq < ng) {
 #pragma unroll
-          for (int a = 0; a < kE; ++a)
-#pragma unroll
-            for (int j = bq; j < bq + 4; ++j) v[a][j] = p0[a][(size_t)min(j0 + j, ng - 1) * gstride];
-        }
-#pragma unroll
-      for (int a = 0; a < kE; ++a)
+            for (int j = bq; j < bq + 4; ++j) v[j] = p0[(size_t)min(j0 + j, ng - 1) * gstride];
+          }
 #pragma unroll
         for (int j = 0; j < kJ; ++j)
-          if (j0 + j < ng) s[a] += v[a][j];
+          if (j0 + j < ng) sum += v[j];
+      }
     }
-#pragma unroll
-    for (int a = 0; a < kE; ++a) {
-      const int e = e0 + t + a * kSolveThreads;
-      if (e < r * SM) sm.tb[(e % r) * SM + e / r] = ok[a] ? s[a] : T(0);
-    }
+    sm.tb[z * SM + cc] = sum;
   }
   unit_pipeline<T, SM>(sm, Eu, (size_t)ldE, r, Wu, (size_t)ldw, nwc, rn, nc, xr, true, Xout + row0,
                        (size_t)ldxo, Pu, rp, jn);
