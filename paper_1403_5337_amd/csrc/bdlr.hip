@@ -974,19 +974,22 @@ __device__ void draw_side(int navail, const int* j_of, const int* ax, const int*
 // draws.  Lane q < 2 NS computes draw q % NS of side q / NS and the two list
 // entries it swaps; then lane 0 (rows) and lane 1 (columns) run the swaps.
 constexpr int kDrawPicks = 256;  // >= the largest skeleton (192 / 128)
-__global__ void __launch_bounds__(64)
-    k_draw_samples(const BdlrTask* __restrict__ tasks, const int* __restrict__ sel, const int* __restrict__ cnt,
-                   int skel, unsigned long long seed, int attempt, int ns, int* __restrict__ samp,
-                   const int* __restrict__ skip) {
+struct DrawLds {
+  int pk[2][kDrawPicks];
+  int jv[2][kSkelSamples], ax[2][kSkelSamples], aj[2][kSkelSamples];
+};
+// The draws of one task by the first wave of the calling workgroup (the
+// picks sel / cnt of the task at x are final); out: 2 ns ints.
+__device__ void draw_task(const BdlrTask& tk, int x, const int* __restrict__ sel, const int* __restrict__ cnt,
+                          int skel, unsigned long long seed, int attempt, int ns, int* __restrict__ out,
+                          DrawLds& d) {
   constexpr int NS = kSkelSamples;
-  __shared__ int pk[2][kDrawPicks];
-  __shared__ int jv[2][NS], ax[2][NS], aj[2][NS];
-  const int x = blockIdx.x, t = threadIdx.x;
-  if (skip && skip[x]) return;
-  const BdlrTask tk = tasks[x];
+  const int t = threadIdx.x;
   const int np[2] = {min(cnt[2 * x], kDrawPicks), min(cnt[2 * x + 1], kDrawPicks)};
-  for (int i = t; i < np[0]; i += 64) pk[0][i] = sel[tk.sel_off + i];
-  for (int i = t; i < np[1]; i += 64) pk[1][i] = sel[tk.sel_off + skel + i];
+  if (t < 64) {
+    for (int i = t; i < np[0]; i += 64) d.pk[0][i] = sel[tk.sel_off + i];
+    for (int i = t; i < np[1]; i += 64) d.pk[1][i] = sel[tk.sel_off + skel + i];
+  }
   __syncthreads();
   const unsigned long long st = seed ^ (0xD1B54A32D192ED03ull * (unsigned long long)tk.node) ^
                                 (0x8CB92BA72F3D8DD7ull * (unsigned long long)(attempt + 1));
@@ -997,13 +1000,23 @@ __global__ void __launch_bounds__(64)
       // the row side draws once per step with a nonempty list
       const int c = (sd == 0 ? 0 : min(NS, max(0, navail[0]))) + q;
       const int j = q + (int)(splitmix64_draw(st, (unsigned long long)c) % (unsigned long long)na);
-      jv[sd][q] = j;
-      ax[sd][q] = avail_at(pk[sd], np[sd], q);
-      aj[sd][q] = avail_at(pk[sd], np[sd], j);
+      d.jv[sd][q] = j;
+      d.ax[sd][q] = avail_at(d.pk[sd], np[sd], q);
+      d.aj[sd][q] = avail_at(d.pk[sd], np[sd], j);
     }
   }
   __syncthreads();
-  if (t < 2) draw_side<NS>(navail[t], jv[t], ax[t], aj[t], samp + (size_t)x * 2 * ns + t * ns);
+  if (t < 2) draw_side<NS>(navail[t], d.jv[t], d.ax[t], d.aj[t], out + t * ns);
+}
+
+__global__ void __launch_bounds__(64)
+    k_draw_samples(const BdlrTask* __restrict__ tasks, const int* __restrict__ sel, const int* __restrict__ cnt,
+                   int skel, unsigned long long seed, int attempt, int ns, int* __restrict__ samp,
+                   const int* __restrict__ skip) {
+  __shared__ DrawLds d;
+  const int x = blockIdx.x;
+  if (skip && skip[x]) return;
+  draw_task(tasks[x], x, sel, cnt, skel, seed, attempt, ns, samp + (size_t)x * 2 * ns, d);
 }
 
 // Scratch of the attempt loops (learned proposals, adaptive BDLR depth).
@@ -1082,7 +1095,7 @@ static AttemptView attempt_view(SkelScratch& sc, int x0) {
 template <typename T, int SKEL>
 static int skel_attempt_launch(hodlr_s* h, const double* K, int ldk, int ns, int maxside, SkelScratch& sc,
                                const AttemptView& v, T* Ucap, T* Vcap, unsigned long long seed, int attempt,
-                               const int* skip, hipStream_t s) {
+                               const int* skip, hipStream_t s, bool own_draw_err = true) {
   const Tree& tr = h->tree;
   const int rcap = h->precision == 64 ? kRankCap64 : kRankCap32;
   {
@@ -1100,15 +1113,18 @@ static int skel_attempt_launch(hodlr_s* h, const double* K, int ldk, int ns, int
   }
   HODLR_HIP(hipGetLastError());
   static_assert(SKEL <= kDrawPicks, "the picks of a side must fit the sampler's LDS");
-  k_draw_samples<<<ns, 64, 0, s>>>(v.tasks, sc.sel.as<int>(), v.cnt, SKEL, seed, attempt, kSkelSamples, v.samp,
-                                   skip);
-  HODLR_HIP(hipGetLastError());
+  if (own_draw_err) {  // (else the caller's pick kernel drew them)
+    k_draw_samples<<<ns, 64, 0, s>>>(v.tasks, sc.sel.as<int>(), v.cnt, SKEL, seed, attempt, kSkelSamples, v.samp,
+                                     skip);
+    HODLR_HIP(hipGetLastError());
+  }
   {
     ProfScope prof("skel_check", s);
     k_skel_check<T><<<dim3(ns, sc.nch), kBlock, 0, s>>>(K, ldk, v.tasks, v.rt, Ucap, Vcap, tr.n, v.samp,
                                                          kSkelSamples, v.part, skip);
-    k_skel_err<<<(ns + kBlock - 1) / kBlock, kBlock, 0, s>>>(v.tasks, ns, v.cnt, sc.norm.as<double>(), v.samp,
-                                                            kSkelSamples, v.part, sc.nch, v.err, skip);
+    if (own_draw_err)  // (else the caller's decision kernel forms the estimates)
+      k_skel_err<<<(ns + kBlock - 1) / kBlock, kBlock, 0, s>>>(v.tasks, ns, v.cnt, sc.norm.as<double>(), v.samp,
+                                                              kSkelSamples, v.part, sc.nch, v.err, skip);
   }
   HODLR_HIP(hipGetLastError());
   return HODLR_OK;
@@ -1133,7 +1149,8 @@ static int skel_attempt(hodlr_s* h, const double* K, int ldk, const std::vector<
 
 // ---------------------------------------------------------------------------
 // Learned proposals, decided on the device.  State per block: 0 pending, 1
-// accepted, 2 failed (the largest size tried is above the acceptance); the
+// accepted, 2 failed (the largest size tried is above the acceptance), 3
+// failed at the caps (keeps its skeleton); the
 // per-side budgets (rows, columns) double after every failing attempt, up to
 // the skeleton cap; kused: the budget that passed.
 // ---------------------------------------------------------------------------
@@ -1156,19 +1173,34 @@ __global__ void k_learned_init(const BdlrTask* __restrict__ tasks, int nt, const
   kused[x] = 0;
 }
 
-// After an attempt: a pending block passes at err <= accept; otherwise its
+// After an attempt, for each pending block: its error estimate (as
+// k_skel_err), then the decision: it passes at err <= accept; otherwise its
 // budgets double (capped), and it fails when they cannot grow or on the last
 // attempt: state 2 (the ACA fallback runs), or state 3 when its budgets are
 // at the pick cap and its rank at the rank cap (ACA is held to the same rank
 // cap; the block keeps its skeleton).
-__global__ void k_learned_decide(const BdlrTask* __restrict__ tasks, int nt, const double* __restrict__ err,
-                                 double accept, int skel, int rcap, int last, const int* __restrict__ rank_task,
-                                 int* __restrict__ budget, int* __restrict__ state, int* __restrict__ kused) {
+__global__ void k_err_decide(const BdlrTask* __restrict__ tasks, int nt, const int* __restrict__ counts,
+                             const double* __restrict__ norm2, const int* __restrict__ samp, int ns,
+                             const double* __restrict__ part, int nch, double* __restrict__ err, double accept,
+                             int skel, int rcap, int last, const int* __restrict__ rank_task, int* __restrict__ budget,
+                             int* __restrict__ state, int* __restrict__ kused) {
   const int x = blockIdx.x * blockDim.x + threadIdx.x;
   if (x >= nt || state[x] != 0) return;
   const BdlrTask tk = tasks[x];
+  double est = 0.0;
+  for (int side = 0; side < 2; ++side) {
+    double num = 0.0;
+    for (int c = 0; c < nch; ++c) num += part[((size_t)x * nch + c) * 2 + side];
+    int used = 0;
+    for (int q = 0; q < ns; ++q) used += samp[(size_t)x * 2 * ns + side * ns + q] >= 0;
+    const int outside = (side == 0 ? tk.m : tk.nc) - counts[2 * x + side];
+    if (used > 0) est = fmax(est, num * (double)outside / (double)used);
+  }
+  const double nb = norm2[tk.task];
+  const double e = nb > 0.0 ? sqrt(est / nb) : sqrt(est);
+  err[x] = e;
   const int br = budget[2 * x], bc = budget[2 * x + 1];
-  if (err[x] <= accept) {
+  if (e <= accept) {
     state[x] = 1;
     kused[x] = max(br, bc);
     return;
@@ -1245,11 +1277,14 @@ __device__ void top_reduce(int& mx, int& sum, int (*red)[2]) {
 
 // One workgroup per block; per side: equal-point flags, the node runs and
 // keys, the knode-th largest key by a radix select on 8-bit digits, then the
-// chosen nodes' dofs listed in increasing position.
+// chosen nodes' dofs listed in increasing position.  Then the attempt's
+// sample draws of the block (as k_draw_samples).
 __global__ void __launch_bounds__(kTopBlock)
     k_skel_topk_nodes(const float* __restrict__ score, const float* __restrict__ xyz,
                       const BdlrTask* __restrict__ tasks, const int* __restrict__ budget,
-                      const int* __restrict__ skip, int skel, int* __restrict__ sel, int* __restrict__ counts) {
+                      const int* __restrict__ skip, int skel, int* __restrict__ sel, int* __restrict__ counts,
+                      unsigned long long seed, int attempt, int* __restrict__ samp) {
+  __shared__ DrawLds dl;
   __shared__ unsigned key[kBdlrMaxSide];
   __shared__ float sco[kBdlrMaxSide];
   __shared__ unsigned char eqp[kBdlrMaxSide];  // position i has the point of position i - 1
@@ -1369,6 +1404,8 @@ __global__ void __launch_bounds__(kTopBlock)
     if (t == 0) counts[2 * x + side] = tot;
     __syncthreads();
   }
+  // the attempt's sample draws for this block, from its final picks
+  draw_task(tk, x, sel, counts, skel, seed, attempt, kSkelSamples, samp + (size_t)x * 2 * kSkelSamples, dl);
 }
 
 // The per-task rank of the fallback (ACA) approximation of failed blocks,
@@ -1546,14 +1583,15 @@ static int learned_t(hodlr_s* h, const double* K, int ldk, const int* rowptr, co
       {
         ProfScope prof("skel_topk", g.st);
         k_skel_topk_nodes<<<g.n, kTopBlock, 0, g.st>>>(d_score.as<float>(), xyz, v.tasks, budget_g, state_g, SKEL,
-                                                       sc.sel.as<int>(), v.cnt);
+                                                       sc.sel.as<int>(), v.cnt, seed, attempt, v.samp);
       }
       HODLR_HIP(hipGetLastError());
       HODLR_TRY((skel_attempt_launch<T, SKEL>(h, K, ldk, g.n, g.maxside, sc, v, Ucap, Vcap, seed, attempt, state_g,
-                                              g.st)));
-      k_learned_decide<<<(g.n + kBlock - 1) / kBlock, kBlock, 0, g.st>>>(
-          v.tasks, g.n, v.err, accept, SKEL, h->precision == 64 ? kRankCap64 : kRankCap32,
-          attempt == kLearnedAttempts - 1 ? 1 : 0, v.rt, budget_g, state_g, d_kused.as<int>() + g.x0);
+                                              g.st, false)));
+      k_err_decide<<<(g.n + kBlock - 1) / kBlock, kBlock, 0, g.st>>>(
+          v.tasks, g.n, v.cnt, sc.norm.as<double>(), v.samp, kSkelSamples, v.part, sc.nch, v.err, accept, SKEL,
+          h->precision == 64 ? kRankCap64 : kRankCap32, attempt == kLearnedAttempts - 1 ? 1 : 0, v.rt, budget_g,
+          state_g, d_kused.as<int>() + g.x0);
       HODLR_HIP(hipGetLastError());
     }
   if (join.side) {
