@@ -1042,7 +1042,9 @@ struct SkelScratch {
 // |K(I, J)|_F^2 of every block of the build, once (the attempts read them by
 // BdlrTask::task); the task list goes through sc.tasks, which each attempt
 // then overwrites with its own.
-static int block_norms(const double* K, int ldk, const std::vector<BdlrTask>& tasks, SkelScratch& sc, hipStream_t s) {
+// Uploads the task records and the chunk numbering (one copy on s); the
+// norm kernels follow on run (which must be ordered after s's copy).
+static int norm_upload(const std::vector<BdlrTask>& tasks, SkelScratch& sc, hipStream_t s, int* nchunk_out) {
   const int nt = (int)tasks.size();
   // chunk numbering (c0, nt + 1 ints) after the task records in one upload
   std::vector<int> c0(nt + 1, 0);
@@ -1058,15 +1060,26 @@ static int block_norms(const double* K, int ldk, const std::vector<BdlrTask>& ta
   HODLR_TRY(sc.tasks.ensure(up.size()));
   HODLR_TRY(sc.norm.ensure(((size_t)nt + nchunk) * sizeof(double)));
   HODLR_HIP(hipMemcpyAsync(sc.tasks.p, up.data(), up.size(), hipMemcpyHostToDevice, s));
-  const int* d_c0 = reinterpret_cast<const int*>(static_cast<unsigned char*>(sc.tasks.p) + tb);
-  ProfScope prof("skel_check", s);
+  *nchunk_out = nchunk;
+  return HODLR_OK;
+}
+
+static int norm_launch(const double* K, int ldk, int nt, int nchunk, SkelScratch& sc, hipStream_t run) {
+  const int* d_c0 = reinterpret_cast<const int*>(static_cast<unsigned char*>(sc.tasks.p) + (size_t)nt * sizeof(BdlrTask));
+  ProfScope prof("skel_check", run);
   if (nchunk > 0) {
-    k_block_norm2<<<nchunk, kBlock, 0, s>>>(K, ldk, sc.tasks.as<BdlrTask>(), d_c0, nt, sc.norm.as<double>() + nt);
+    k_block_norm2<<<nchunk, kBlock, 0, run>>>(K, ldk, sc.tasks.as<BdlrTask>(), d_c0, nt, sc.norm.as<double>() + nt);
     HODLR_HIP(hipGetLastError());
   }
-  k_norm_total<<<nt, 64, 0, s>>>(d_c0, sc.norm.as<double>() + nt, sc.norm.as<double>());
+  k_norm_total<<<nt, 64, 0, run>>>(d_c0, sc.norm.as<double>() + nt, sc.norm.as<double>());
   HODLR_HIP(hipGetLastError());
   return HODLR_OK;
+}
+
+static int block_norms(const double* K, int ldk, const std::vector<BdlrTask>& tasks, SkelScratch& sc, hipStream_t s) {
+  int nchunk = 0;
+  HODLR_TRY(norm_upload(tasks, sc, s, &nchunk));
+  return norm_launch(K, ldk, (int)tasks.size(), nchunk, sc, s);
 }
 
 // One attempt over the ns blocks whose tasks are in sc.tasks and picks in
@@ -1523,26 +1536,13 @@ static int learned_t(hodlr_s* h, const double* K, int ldk, const int* rowptr, co
   HODLR_TRY(d_kused.ensure((size_t)nt * sizeof(int)));
   SkelScratch sc;
   HODLR_TRY(sc.ensure(nt, selo, invo, cgo, sizeof(T), check_chunks(tasks)));
-  HODLR_TRY(block_norms(K, ldk, tasks, sc, s));  // also uploads the task table to sc.tasks
-  {
-    ProfScope prof("skel_features", s);
-    HODLR_TRY(launch_skel_features(rowptr, col, xyz, K, ldk, blocks, d_feat.as<float>(), s, h->depth,
-                                   d_dcnt.as<int>()));
-  }
-  {
-    ProfScope prof("skel_score", s);
-    HODLR_TRY(launch_mlp_forward(d_feat.as<float>(), N, params, 1, d_score.as<float>(), s));
-  }
-  HODLR_HIP(hipMemsetAsync(h->d_rank.p, 0, tr.nnodes() * sizeof(int), s));
-  const int g1 = (nt + kBlock - 1) / kBlock;
-  k_learned_init<<<g1, kBlock, 0, s>>>(sc.tasks.as<BdlrTask>(), nt, d_dcnt.as<int>(), kinit, SKEL,
-                                       d_budget.as<int>(), d_state.as<int>(), d_kused.as<int>());
-  HODLR_HIP(hipGetLastError());
   // Every attempt is queued at once; blocks already decided skip its
   // kernels.  A block's attempts depend only on its own decisions, so the
   // blocks of levels 1 and 2 (the largest picks, so the longest
   // eliminations) run their attempts on a side stream beside those of the
-  // other levels, and the build waits for the longer of the two chains.
+  // other levels, and the build waits for the longer of the two chains.  The
+  // side stream first computes the block norms while the features and the
+  // scores are computed on the build's stream.
   struct Group {
     int x0, n, maxside;
     hipStream_t st;
@@ -1561,19 +1561,45 @@ static int learned_t(hodlr_s* h, const double* K, int ldk, const int* rowptr, co
   }
   struct Join {  // waits for the side stream on every return (the scratch outlives its work)
     hipStream_t side = nullptr;
-    hipEvent_t e[2] = {nullptr, nullptr};
+    hipEvent_t e[4] = {nullptr, nullptr, nullptr, nullptr};
     ~Join() {
       if (side) (void)hipStreamSynchronize(side);
       for (auto x : e)
         if (x) (void)hipEventDestroy(x);
     }
   } join;
+  int nchunk = 0;
+  HODLR_TRY(norm_upload(tasks, sc, s, &nchunk));  // (the task table for every kernel below)
   if (groups.size() == 2) {
     HODLR_TRY(side_stream(1, &groups[0].st));
     join.side = groups[0].st;
     for (auto& x : join.e) HODLR_HIP(hipEventCreateWithFlags(&x, hipEventDisableTiming));
     HODLR_HIP(hipEventRecord(join.e[0], s));
     HODLR_HIP(hipStreamWaitEvent(join.side, join.e[0], 0));
+    HODLR_TRY(norm_launch(K, ldk, nt, nchunk, sc, join.side));
+    HODLR_HIP(hipEventRecord(join.e[2], join.side));
+  } else {
+    HODLR_TRY(norm_launch(K, ldk, nt, nchunk, sc, s));
+  }
+  {
+    ProfScope prof("skel_features", s);
+    HODLR_TRY(launch_skel_features(rowptr, col, xyz, K, ldk, blocks, d_feat.as<float>(), s, h->depth,
+                                   d_dcnt.as<int>()));
+  }
+  {
+    ProfScope prof("skel_score", s);
+    HODLR_TRY(launch_mlp_forward(d_feat.as<float>(), N, params, 1, d_score.as<float>(), s));
+  }
+  HODLR_HIP(hipMemsetAsync(h->d_rank.p, 0, tr.nnodes() * sizeof(int), s));
+  const int g1 = (nt + kBlock - 1) / kBlock;
+  k_learned_init<<<g1, kBlock, 0, s>>>(sc.tasks.as<BdlrTask>(), nt, d_dcnt.as<int>(), kinit, SKEL,
+                                       d_budget.as<int>(), d_state.as<int>(), d_kused.as<int>());
+  HODLR_HIP(hipGetLastError());
+  if (join.side) {
+    // the side stream's attempts need the budgets; the build's need the norms
+    HODLR_HIP(hipEventRecord(join.e[3], s));
+    HODLR_HIP(hipStreamWaitEvent(join.side, join.e[3], 0));
+    HODLR_HIP(hipStreamWaitEvent(s, join.e[2], 0));
   }
   for (int attempt = 0; attempt < kLearnedAttempts; ++attempt)
     for (const Group& g : groups) {
