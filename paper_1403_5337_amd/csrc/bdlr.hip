@@ -1601,33 +1601,50 @@ static int learned_t(hodlr_s* h, const double* K, int ldk, const int* rowptr, co
     HODLR_HIP(hipStreamWaitEvent(join.side, join.e[3], 0));
     HODLR_HIP(hipStreamWaitEvent(s, join.e[2], 0));
   }
-  for (int attempt = 0; attempt < kLearnedAttempts; ++attempt)
-    for (const Group& g : groups) {
-      const AttemptView v = attempt_view(sc, g.x0);
-      int* state_g = d_state.as<int>() + g.x0;
-      int* budget_g = d_budget.as<int>() + 2 * g.x0;
-      {
-        ProfScope prof("skel_topk", g.st);
-        k_skel_topk_nodes<<<g.n, kTopBlock, 0, g.st>>>(d_score.as<float>(), xyz, v.tasks, budget_g, state_g, SKEL,
-                                                       sc.sel.as<int>(), v.cnt, seed, attempt, v.samp);
+  auto queue = [&](int a0, int a1) -> int {
+    for (int attempt = a0; attempt < a1; ++attempt)
+      for (const Group& g : groups) {
+        const AttemptView v = attempt_view(sc, g.x0);
+        int* state_g = d_state.as<int>() + g.x0;
+        int* budget_g = d_budget.as<int>() + 2 * g.x0;
+        {
+          ProfScope prof("skel_topk", g.st);
+          k_skel_topk_nodes<<<g.n, kTopBlock, 0, g.st>>>(d_score.as<float>(), xyz, v.tasks, budget_g, state_g, SKEL,
+                                                         sc.sel.as<int>(), v.cnt, seed, attempt, v.samp);
+        }
+        HODLR_HIP(hipGetLastError());
+        HODLR_TRY((skel_attempt_launch<T, SKEL>(h, K, ldk, g.n, g.maxside, sc, v, Ucap, Vcap, seed, attempt,
+                                                state_g, g.st, false)));
+        k_err_decide<<<(g.n + kBlock - 1) / kBlock, kBlock, 0, g.st>>>(
+            v.tasks, g.n, v.cnt, sc.norm.as<double>(), v.samp, kSkelSamples, v.part, sc.nch, v.err, accept, SKEL,
+            h->precision == 64 ? kRankCap64 : kRankCap32, attempt == kLearnedAttempts - 1 ? 1 : 0, v.rt, budget_g,
+            state_g, d_kused.as<int>() + g.x0);
+        HODLR_HIP(hipGetLastError());
       }
-      HODLR_HIP(hipGetLastError());
-      HODLR_TRY((skel_attempt_launch<T, SKEL>(h, K, ldk, g.n, g.maxside, sc, v, Ucap, Vcap, seed, attempt, state_g,
-                                              g.st, false)));
-      k_err_decide<<<(g.n + kBlock - 1) / kBlock, kBlock, 0, g.st>>>(
-          v.tasks, g.n, v.cnt, sc.norm.as<double>(), v.samp, kSkelSamples, v.part, sc.nch, v.err, accept, SKEL,
-          h->precision == 64 ? kRankCap64 : kRankCap32, attempt == kLearnedAttempts - 1 ? 1 : 0, v.rt, budget_g,
-          state_g, d_kused.as<int>() + g.x0);
-      HODLR_HIP(hipGetLastError());
+    if (join.side) {
+      HODLR_HIP(hipEventRecord(join.e[1], join.side));
+      HODLR_HIP(hipStreamWaitEvent(s, join.e[1], 0));
     }
-  if (join.side) {
-    HODLR_HIP(hipEventRecord(join.e[1], join.side));
-    HODLR_HIP(hipStreamWaitEvent(s, join.e[1], 0));
-  }
+    return HODLR_OK;
+  };
+  // The decisions stay on the device; the host reads the states once after
+  // the first two attempts (most blocks are decided by then) and queues the
+  // last two only if a block is still pending, instead of queueing launches
+  // that would find nothing to do.
   std::vector<int> state(nt), kused(nt);
-  HODLR_HIP(hipMemcpyAsync(state.data(), d_state.p, nt * sizeof(int), hipMemcpyDeviceToHost, s));
-  HODLR_HIP(hipMemcpyAsync(kused.data(), d_kused.p, nt * sizeof(int), hipMemcpyDeviceToHost, s));
-  HODLR_HIP(hipStreamSynchronize(s));
+  constexpr int kFirstBatch = 2;
+  auto read_back = [&]() -> int {
+    HODLR_HIP(hipMemcpyAsync(state.data(), d_state.p, nt * sizeof(int), hipMemcpyDeviceToHost, s));
+    HODLR_HIP(hipMemcpyAsync(kused.data(), d_kused.p, nt * sizeof(int), hipMemcpyDeviceToHost, s));
+    HODLR_HIP(hipStreamSynchronize(s));
+    return HODLR_OK;
+  };
+  HODLR_TRY(queue(0, std::min(kFirstBatch, kLearnedAttempts)));
+  HODLR_TRY(read_back());
+  if (std::any_of(state.begin(), state.end(), [](int v) { return v == 0; }) && kFirstBatch < kLearnedAttempts) {
+    HODLR_TRY(queue(kFirstBatch, kLearnedAttempts));
+    HODLR_TRY(read_back());
+  }
   std::vector<int> nodes;
   for (int x = 0; x < nt; ++x)
     if (state[x] == 2) nodes.push_back(tasks[x].node);

@@ -141,11 +141,8 @@ template <typename T> __device__ __forceinline__ void wave_argmax_uniform(T& v, 
   i = bi;
 }
 
-// Row of the largest candidate cv[a] (row lane + 64 a), ties to the lowest
-// row, and that candidate (best), both wave-uniform.  The maximum is reduced
-// with DPP inside each 16-lane row and across the four rows by readlane;
-// then the lowest row holding it comes from one ballot per register.  Returns
-// -1 if no candidate equals the maximum (a NaN maximum).
+// Wave-uniform maximum: DPP inside each 16-lane row, then the four row
+// results by readlane.  NaN never wins a comparison.
 template <typename T> __device__ __forceinline__ T sel_max(T a, T b) { return b > a ? b : a; }
 
 template <typename T> __device__ __forceinline__ T wave_max(T m) {
@@ -156,43 +153,38 @@ template <typename T> __device__ __forceinline__ T wave_max(T m) {
   return sel_max(sel_max(lane_value(m, 0), lane_value(m, 16)), sel_max(lane_value(m, 32), lane_value(m, 48)));
 }
 
-template <typename T, int RA>
-__device__ __forceinline__ int wave_argmax_rows(const T (&cv)[RA], T& best) {
-  T m = cv[0];
-#pragma unroll
-  for (int a = 1; a < RA; ++a) m = sel_max(m, cv[a]);
-  best = wave_max(m);
-#pragma unroll
-  for (int a = 0; a < RA; ++a) {
-    const unsigned long long bal = __ballot(cv[a] == best);
-    if (bal) return 64 * a + __ffsll((long long)bal) - 1;
-  }
-  return -1;
-}
-
 // ---------------------------------------------------------------------------
 // Blocked Gauss-Jordan inversion with partial pivoting (gj_threads<T>() threads).
 //
 // The matrix sits in LDS.  Every kGjNb = 8 pivot steps form a block.  Wave 0
-// factors the block's 8 columns (the panel) on its own, without barriers: the
-// pivot of each step is the largest |entry| of the current column among the
-// rows not yet used (ties to the lower row); the pivot row is scaled, the
-// other rows are eliminated, and the column is replaced by the multipliers,
-// which is the in-place Gauss-Jordan step.  The block's steps applied to any
-// other column j amount to X(:, j) += C X_old(P, j), with P the block's pivot
-// rows and C = Z - I(:, P) for the factored panel Z: one rank-8 update.
+// factors the block's 8 columns (the panel) in its registers (rows lane +
+// 64 a) without barriers: the pivot row is scaled, the other rows are
+// eliminated, and the column is replaced by the multipliers, which is the
+// in-place Gauss-Jordan step.  The block's steps applied to any other column
+// j amount to X(:, j) += C X_old(P, j), with P the block's pivot rows and
+// C = Z - I(:, P) for the factored panel Z: one rank-8 update.
 //
-// Look-ahead: while waves 1-15 apply block b's update to the other columns
-// (small tiles per thread), wave 0 applies it to the next panel's columns in
-// its registers and factors that panel, so the updates run under the chain
-// of pivot steps.  Rows are never swapped: with p_k the pivot row of step k
-// the array ends as (P A)^-1, i.e. A^-1(r, c) = X(p_r, pinv(c)).
+// Pivot choice: the rows not yet used are compared on a 32-bit key, the
+// leading bits of |x| (float: sign-cleared bits with the low byte dropped,
+// i.e. 15 of the 23 mantissa bits; double: the high word likewise, 12 of
+// 52) with 255 - row in the low byte, so that one unsigned maximum (DPP in
+// each 16-lane row, readlane across rows) gives the largest magnitude and,
+// among magnitudes equal to that precision, the lowest row.  A NaN or
+// infinite candidate wins and fails the step, as does a zero pivot.  The
+// step has no branch, so the whole panel is one scheduling region.
+//
+// Look-ahead: while wave 0 applies block b's update to the next panel's
+// columns and factors that panel, waves 1.. apply block b's update to every
+// other column on the matrix cores (v_mfma_*_16x16x4: A = 16 rows of C, K =
+// the block's 4 + 4 pivot steps, B = the pivot rows of 16 columns).  A wave
+// owns whole 16-column strips, so it reads their pivot-row values before it
+// writes any of them and no barrier separates the two.  Rows are never
+// swapped: with p_k the pivot row of step k the array ends as (P A)^-1, i.e.
+// A^-1(r, c) = X(p_r, pinv(c)).
 // ---------------------------------------------------------------------------
 constexpr int kGjNb = 8;
-// A single wave issues a VALU op only every ~8 cycles, so the tile updates
-// need as many waves as a workgroup can hold to keep up with the panel wave;
-// the kernels that invert hold the whole CU (LDS) anyway.  Double precision
-// takes 8 waves, which leaves it 256 registers per lane.
+// Double precision takes 8 waves, which leaves it 256 registers per lane for
+// the panel wave.
 template <typename T>
 constexpr int gj_threads() {
   return sizeof(T) == 8 ? 512 : 1024;
@@ -200,24 +192,57 @@ constexpr int gj_threads() {
 
 template <typename T, int NMAX>
 struct GjScratch {
-  static constexpr int kLd = (NMAX + 7) / 8 * 8;  // column stride of X and C
-  alignas(16) T X[NMAX * kLd];                    // the matrix, column-major
-  alignas(16) T C[2][kGjNb * kLd];                // C = Z - I(:, P) of two blocks, column-major
-  alignas(16) T R[NMAX * kGjNb];                  // pivot rows of the other columns, [j][s]
-  int p[2][kGjNb];                                // pivot rows of two blocks
-  int pinv[NMAX];                                 // step at which a row was the pivot row
-  int prow[NMAX];                                 // pivot row of each step
+  // column stride: 16 bytes past a multiple of 8 entries, so that the 16
+  // lanes of an MFMA tile row (16 columns) hit different LDS banks
+  static constexpr int kLd = (NMAX + 7) / 8 * 8 + 16 / (int)sizeof(T);
+  alignas(16) T X[NMAX * kLd];      // the matrix, column-major
+  alignas(16) T C[2][kGjNb * kLd];  // C = Z - I(:, P) of two blocks, column-major
+  int p[2][kGjNb];                  // pivot rows of two blocks
+  int pinv[NMAX];                   // step at which a row was the pivot row
+  int prow[NMAX];                   // pivot row of each step
   int bad;
 };
 
-// Wave 0: loads the panel X(:, k0 : k0 + nbk) into registers (rows of lane l
-// are l + 64 a, a < RA), first applying the previous block's update (Cp, with
-// the panel's pivot-row values at R[(jr + j) * kGjNb]) if Cp is not NULL,
-// then runs the panel's pivot steps and stores Z, C and the pivots.  used:
-// per lane, bit a = row used or beyond n.
-template <typename T, int RA, int NMAX>
-__device__ bool gj_panel(GjScratch<T, NMAX>& s, int n, int k0, int nbk, int buf, const T* Cp, int jr,
-                         unsigned& used) {
+__device__ __forceinline__ unsigned gj_key_bits(float x) { return __float_as_uint(x); }
+__device__ __forceinline__ unsigned gj_key_bits(double x) {
+  return (unsigned)((unsigned long long)__double_as_longlong(x) >> 32);
+}
+
+template <int CTRL> __device__ __forceinline__ unsigned dpp_max_u32(unsigned v) {
+  const unsigned o = (unsigned)__builtin_amdgcn_update_dpp(0, (int)v, CTRL, 0xF, 0xF, false);
+  return v > o ? v : o;
+}
+
+__device__ __forceinline__ unsigned wave_max_u32(unsigned m) {
+  m = dpp_max_u32<0xB1>(m);
+  m = dpp_max_u32<0x4E>(m);
+  m = dpp_max_u32<0x141>(m);
+  m = dpp_max_u32<0x140>(m);
+  const unsigned a = __builtin_amdgcn_readlane(m, 0), b = __builtin_amdgcn_readlane(m, 16);
+  const unsigned c = __builtin_amdgcn_readlane(m, 32), d = __builtin_amdgcn_readlane(m, 48);
+  const unsigned ab = a > b ? a : b, cd = c > d ? c : d;
+  return ab > cd ? ab : cd;
+}
+
+// 1 / p: the hardware estimate refined by Newton steps (one for float, two
+// for double, from the estimate's ~2^-26 relative error)
+__device__ __forceinline__ float gj_recip(float p) {
+  const float r = __builtin_amdgcn_rcpf(p);
+  return fmaf(fmaf(-p, r, 1.f), r, r);
+}
+__device__ __forceinline__ double gj_recip(double p) {
+  double r = __builtin_amdgcn_rcp(p);
+  r = fma(fma(-p, r, 1.0), r, r);
+  return fma(fma(-p, r, 1.0), r, r);
+}
+
+// Wave 0: loads the panel X(:, k0 : k0 + nbk) into registers, applies the
+// previous block's update to it if upd (C and pivots in buffer buf ^ 1, the
+// pivot-row values read from the panel's own columns before any write),
+// runs the panel's pivot steps and stores Z, C and the pivots in buffer buf.
+// used: per lane, bit a = row lane + 64 a used or beyond n.  FULL: nbk = 8.
+template <typename T, int RA, int NMAX, bool FULL>
+__device__ bool gj_panel(GjScratch<T, NMAX>& s, int n, int k0, int nbk, int buf, bool upd, unsigned& used) {
   constexpr int ld = GjScratch<T, NMAX>::kLd;
   const int lane = threadIdx.x & 63;
   T P[RA][kGjNb];
@@ -226,40 +251,49 @@ __device__ bool gj_panel(GjScratch<T, NMAX>& s, int n, int k0, int nbk, int buf,
 #pragma unroll
     for (int j = 0; j < kGjNb; ++j) {
       const int i = lane + 64 * a;
-      P[a][j] = (i < n && j < nbk) ? s.X[(k0 + j) * ld + i] : T(0);
+      P[a][j] = (i < n && (FULL || j < nbk)) ? s.X[(k0 + j) * ld + i] : T(0);
     }
-  if (Cp) {
+  if (upd) {
+    const T* Cp = s.C[buf ^ 1];
+    int pq[kGjNb];
+#pragma unroll
+    for (int q = 0; q < kGjNb; ++q) pq[q] = __builtin_amdgcn_readfirstlane(s.p[buf ^ 1][q]);
+    T c[RA][kGjNb];
 #pragma unroll
     for (int a = 0; a < RA; ++a) {
       const int i = min(lane + 64 * a, ld - 1);
-      T c[kGjNb];
 #pragma unroll
-      for (int q = 0; q < kGjNb; ++q) c[q] = Cp[q * ld + i];
+      for (int q = 0; q < kGjNb; ++q) c[a][q] = Cp[q * ld + i];
+    }
 #pragma unroll
-      for (int j = 0; j < kGjNb; ++j) {
-        const T* rp = static_cast<const T*>(__builtin_assume_aligned(s.R + (jr + j) * kGjNb, 16));
+    for (int j = 0; j < kGjNb; ++j) {
+      if (!FULL && j >= nbk) break;
+      T r[kGjNb];
 #pragma unroll
-        for (int q = 0; q < kGjNb; ++q) P[a][j] = fma(c[q], rp[q], P[a][j]);
-      }
+      for (int q = 0; q < kGjNb; ++q) r[q] = s.X[(k0 + j) * ld + pq[q]];
+#pragma unroll
+      for (int a = 0; a < RA; ++a)
+#pragma unroll
+        for (int q = 0; q < kGjNb; ++q) P[a][j] = fma(c[a][q], r[q], P[a][j]);
     }
   }
   int pv[kGjNb];
-  bool ok = true;
-  // pivot candidates of the current column
-  T cv[RA];
 #pragma unroll
-  for (int a = 0; a < RA; ++a) cv[a] = ((used >> a) & 1u) ? T(-1) : fabs(P[a][0]);
+  for (int j = 0; j < kGjNb; ++j) pv[j] = 0;
+  bool ok = true;
 #pragma unroll
   for (int j = 0; j < kGjNb; ++j) {
-    pv[j] = -1;
-    if (j >= nbk || !ok) continue;
-    T bv;
-    const int pr = __builtin_amdgcn_readfirstlane(wave_argmax_rows<T, RA>(cv, bv));
-    if (pr < 0 || pr >= n || !(bv > T(0)) || !(bv < T(INFINITY))) {
-      ok = false;
-      continue;
+    if (!FULL && j >= nbk) break;
+    unsigned m = 0;
+#pragma unroll
+    for (int a = 0; a < RA; ++a) {
+      const unsigned k = ((used >> a) & 1u) ? 0u
+                                            : ((gj_key_bits(P[a][j]) & 0x7fffff00u) | (unsigned)(255 - (lane + 64 * a)));
+      m = k > m ? k : m;
     }
-    const int pl = pr & 63, ap = pr >> 6;
+    const unsigned key = wave_max_u32(m);
+    const int pr = key ? 255 - (int)(key & 255u) : 0;
+    const int ap = pr >> 6, pl = pr & 63;
     T rs[kGjNb];
 #pragma unroll
     for (int j2 = 0; j2 < kGjNb; ++j2) {
@@ -268,10 +302,12 @@ __device__ bool gj_panel(GjScratch<T, NMAX>& s, int n, int k0, int nbk, int buf,
       for (int a = 1; a < RA; ++a) v = ap == a ? P[a][j2] : v;
       rs[j2] = lane_value(v, pl);
     }
-    const T inv = T(1) / rs[j];
+    const T av = fabs(rs[j]);
+    ok = ok && key != 0u && av > T(0) && av < T(INFINITY);
+    const T inv = gj_recip(rs[j]);
 #pragma unroll
     for (int j2 = 0; j2 < kGjNb; ++j2) rs[j2] *= inv;
-    if (lane == pl) used |= 1u << ap;
+    used |= lane == pl ? 1u << ap : 0u;
 #pragma unroll
     for (int a = 0; a < RA; ++a) {
       const bool isp = lane + 64 * a == pr;
@@ -280,23 +316,25 @@ __device__ bool gj_panel(GjScratch<T, NMAX>& s, int n, int k0, int nbk, int buf,
       for (int j2 = 0; j2 < kGjNb; ++j2)
         if (j2 != j) P[a][j2] = isp ? rs[j2] : fma(-f, rs[j2], P[a][j2]);
       P[a][j] = isp ? inv : -f * inv;
-      if (j + 1 < kGjNb) cv[a] = ((used >> a) & 1u) ? T(-1) : fabs(P[a][j + 1]);
     }
     pv[j] = pr;
-    if (lane == 0) {
-      s.p[buf][j] = pr;
-      s.pinv[pr] = k0 + j;
-      s.prow[k0 + j] = pr;
-    }
   }
   if (!ok) return false;
+  int mine = pv[0];
+#pragma unroll
+  for (int j = 1; j < kGjNb; ++j) mine = lane == j ? pv[j] : mine;
+  if (lane < nbk) {
+    s.p[buf][lane] = mine;
+    s.pinv[mine] = k0 + lane;
+    s.prow[k0 + lane] = mine;
+  }
 #pragma unroll
   for (int a = 0; a < RA; ++a) {
     const int i = lane + 64 * a;
     if (i < n)
 #pragma unroll
       for (int j = 0; j < kGjNb; ++j)
-        if (j < nbk) {
+        if (FULL || j < nbk) {
           s.X[(k0 + j) * ld + i] = P[a][j];
           s.C[buf][j * ld + i] = i == pv[j] ? P[a][j] - T(1) : P[a][j];
         }
@@ -305,51 +343,76 @@ __device__ bool gj_panel(GjScratch<T, NMAX>& s, int n, int k0, int nbk, int buf,
 }
 
 template <typename T, int NMAX>
-__device__ __forceinline__ bool gj_panel_any(GjScratch<T, NMAX>& s, int n, int k0, int nbk, int buf, const T* Cp,
-                                             int jr, unsigned& used) {
-  if (n <= 64) return gj_panel<T, 1, NMAX>(s, n, k0, nbk, buf, Cp, jr, used);
-  if (NMAX <= 128 || n <= 128) return gj_panel<T, 2, NMAX>(s, n, k0, nbk, buf, Cp, jr, used);
-  return gj_panel<T, (NMAX + 63) / 64, NMAX>(s, n, k0, nbk, buf, Cp, jr, used);
+__device__ __forceinline__ bool gj_panel_any(GjScratch<T, NMAX>& s, int n, int k0, int nbk, int buf, bool upd,
+                                             unsigned& used) {
+  constexpr int RMAX = (NMAX + 63) / 64;
+  if (nbk == kGjNb) {
+    if (n <= 64) return gj_panel<T, 1, NMAX, true>(s, n, k0, nbk, buf, upd, used);
+    if (NMAX <= 128 || n <= 128) return gj_panel<T, 2, NMAX, true>(s, n, k0, nbk, buf, upd, used);
+    return gj_panel<T, RMAX, NMAX, true>(s, n, k0, nbk, buf, upd, used);
+  }
+  if (n <= 64) return gj_panel<T, 1, NMAX, false>(s, n, k0, nbk, buf, upd, used);
+  if (NMAX <= 128 || n <= 128) return gj_panel<T, 2, NMAX, false>(s, n, k0, nbk, buf, upd, used);
+  return gj_panel<T, RMAX, NMAX, false>(s, n, k0, nbk, buf, upd, used);
 }
 
-// X(0 : n8, j) += C X_old(P, j) for the m columns listed by t' -> jj = t' < k0
-// ? t' : t' + skip (column j = jj < k0 ? jj : jj + nbk, R row jj), in TR x 2
-// tiles taken by threads tid, tid + nthr, ... (TR = 8 rows for float, 4 for
-// double, so the C tile stays in 64 registers).
+typedef float gj_f4 __attribute__((ext_vector_type(4)));
+typedef double gj_d4 __attribute__((ext_vector_type(4)));
+__device__ __forceinline__ gj_f4 gj_mfma(float a, float b, gj_f4 c) {
+  return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+}
+__device__ __forceinline__ gj_d4 gj_mfma(double a, double b, gj_d4 c) {
+  return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
+template <typename T> struct GjVec;
+template <> struct GjVec<float> { typedef gj_f4 t; };
+template <> struct GjVec<double> { typedef gj_d4 t; };
+
+// Block buf's steps applied to the m columns outside both panels (column
+// t' < m is jj = t' < k0 ? t' : t' + skip, j = jj < k0 ? jj : jj + nbk), in
+// 16-column strips, strip wt, wt + nwt, ... for this wave.  Lane (cl, kg) =
+// (lane % 16, lane / 16) holds column cl of the strip; the MFMA's A operand
+// is C(m0 + cl, kg [+ 4]) and its B operand the column's value in pivot row
+// p_kg [p_kg+4], read once per strip before the first write.
 template <typename T, int NMAX>
-__device__ __forceinline__ void gj_tiles(GjScratch<T, NMAX>& s, const T* Cb, int n8, int m, int k0, int skip,
-                                         int nbk, int tid, int nthr) {
+__device__ void gj_strips(GjScratch<T, NMAX>& s, int buf, int n, int nbk, int m, int k0, int skip, int wt, int nwt) {
   constexpr int ld = GjScratch<T, NMAX>::kLd;
-  constexpr int TR = sizeof(T) == 8 ? 4 : 8, TC = 2;
-  const int nti = n8 / TR, ntj = (m + TC - 1) / TC;
-  for (int tile = tid; tile < nti * ntj; tile += nthr) {
-    const int ti = tile % nti, tj = tile / nti, i0 = ti * TR;
-    T c[TR][kGjNb];
+  typedef typename GjVec<T>::t v4;
+  const int lane = threadIdx.x & 63, cl = lane & 15, kg = lane >> 4;
+  const T* Cb = s.C[buf];
+  const int q0 = s.p[buf][kg], q1 = s.p[buf][kg + 4];
+  const bool h0 = kg < nbk, h1 = kg + 4 < nbk;
+  const int ntr = (n + 15) >> 4;
+  for (int strip = wt; strip * 16 < m; strip += nwt) {
+    const int tp = strip * 16 + cl;
+    const bool vc = tp < m;
+    const int jj = tp < k0 ? tp : tp + skip, j = vc ? (jj < k0 ? jj : jj + nbk) : 0;
+    T* col = s.X + j * ld;
+    const T b0 = (vc && h0) ? col[q0] : T(0), b1 = (vc && h1) ? col[q1] : T(0);
+    for (int ti = 0; ti < ntr; ++ti) {
+      const int m0 = 16 * ti, ra = min(m0 + cl, ld - 1);
+      v4 acc;
+      if constexpr (sizeof(T) == 4) {
+        // float: output register v of lane (cl, kg) is row 4 kg + v, column cl
+        const int row0 = m0 + 4 * kg;
+        const bool st = vc && row0 < n;  // rows row0 .. row0 + 3 < ld
+        if (st)
+          acc = *reinterpret_cast<const v4*>(col + row0);
+        else
+          acc = v4{0, 0, 0, 0};
+        acc = gj_mfma(Cb[kg * ld + ra], b0, acc);
+        acc = gj_mfma(Cb[(kg + 4) * ld + ra], b1, acc);
+        if (st) *reinterpret_cast<v4*>(col + row0) = acc;
+      } else {
+        // double: output register v of lane (cl, kg) is row 4 v + kg, column cl
 #pragma unroll
-    for (int q = 0; q < kGjNb; ++q) {
-      const T* cp = static_cast<const T*>(__builtin_assume_aligned(Cb + q * ld + i0, 16));
+        for (int v = 0; v < 4; ++v) acc[v] = (vc && m0 + 4 * v + kg < n) ? col[m0 + 4 * v + kg] : T(0);
+        acc = gj_mfma(Cb[kg * ld + ra], b0, acc);
+        acc = gj_mfma(Cb[(kg + 4) * ld + ra], b1, acc);
 #pragma unroll
-      for (int r = 0; r < TR; ++r) c[r][q] = cp[r];
-    }
-#pragma unroll
-    for (int u = 0; u < TC; ++u) {
-      const int tp = tj * TC + u;
-      if (tp >= m) break;
-      const int jj = tp < k0 ? tp : tp + skip, j = jj < k0 ? jj : jj + nbk;
-      const T* rp = static_cast<const T*>(__builtin_assume_aligned(s.R + jj * kGjNb, 16));
-      T rv[kGjNb];
-#pragma unroll
-      for (int q = 0; q < kGjNb; ++q) rv[q] = rp[q];
-      T* xp = static_cast<T*>(__builtin_assume_aligned(s.X + j * ld + i0, 16));
-      T x[TR];
-#pragma unroll
-      for (int r = 0; r < TR; ++r) x[r] = xp[r];
-#pragma unroll
-      for (int r = 0; r < TR; ++r)
-#pragma unroll
-        for (int q = 0; q < kGjNb; ++q) x[r] = fma(c[r][q], rv[q], x[r]);
-#pragma unroll
-      for (int r = 0; r < TR; ++r) xp[r] = x[r];
+        for (int v = 0; v < 4; ++v)
+          if (vc && m0 + 4 * v + kg < n) col[m0 + 4 * v + kg] = acc[v];
+      }
     }
   }
 }
@@ -363,7 +426,8 @@ __device__ bool gj_invert(Load load, int n, T* out, int ldo, GjScratch<T, NMAX>&
   static_assert(NMAX <= 192, "three rows per lane at most");
   constexpr int ld = GjScratch<T, NMAX>::kLd;
   const int t = threadIdx.x, nt = blockDim.x, lane = t & 63;
-  const int n8 = (n + 7) & ~7;  // rows touched by the 8-row tiles
+  const int wv = __builtin_amdgcn_readfirstlane(t >> 6), nwv = nt >> 6;
+  const int n8 = (n + 7) & ~7;
   // 16 loads per thread in flight at a time
   constexpr int kLoads = 16;
   for (int e0 = 0; e0 < n * n8; e0 += kLoads * nt) {
@@ -379,31 +443,23 @@ __device__ bool gj_invert(Load load, int n, T* out, int ldo, GjScratch<T, NMAX>&
       if (e < n * n8) s.X[(e / n8) * ld + e % n8] = v[u];
     }
   }
-  for (int e = t; e < 2 * kGjNb * n8; e += nt) {
-    const int b = e / (kGjNb * n8), r = e % (kGjNb * n8);
-    s.C[b][(r / n8) * ld + r % n8] = T(0);
-  }
+  for (int e = t; e < 2 * kGjNb * ld; e += nt) (&s.C[0][0])[e] = T(0);
+  if (t < 2 * kGjNb) (&s.p[0][0])[t] = 0;
   if (t == 0) s.bad = 0;
   unsigned used = 0;
 #pragma unroll
   for (int a = 0; a < 3; ++a) used |= (lane + 64 * a >= n ? 1u : 0u) << a;
   __syncthreads();
-  if (t < 64 && !gj_panel_any<T, NMAX>(s, n, 0, min(kGjNb, n), 0, nullptr, 0, used) && t == 0) s.bad = 1;
+  if (wv == 0 && !gj_panel_any<T, NMAX>(s, n, 0, min(kGjNb, n), 0, false, used) && t == 0) s.bad = 1;
   for (int k0 = 0, buf = 0;; k0 += kGjNb, buf ^= 1) {
     __syncthreads();
     if (s.bad) return false;
     const int nbk = min(kGjNb, n - k0), ncols = n - nbk;
     const int k1 = k0 + nbk, nbk1 = k1 < n ? min(kGjNb, n - k1) : 0;
-    // block buf's pivot rows of every other column, before its update
-    for (int e = t; e < ncols * kGjNb; e += nt) {
-      const int jj = e / kGjNb, q = e % kGjNb, j = jj < k0 ? jj : jj + nbk;
-      s.R[e] = q < nbk ? s.X[j * ld + s.p[buf][q]] : T(0);
-    }
-    __syncthreads();
-    if (t < 64) {
-      if (nbk1 > 0 && !gj_panel_any<T, NMAX>(s, n, k1, nbk1, buf ^ 1, s.C[buf], k0, used) && t == 0) s.bad = 1;
+    if (wv == 0) {
+      if (nbk1 > 0 && !gj_panel_any<T, NMAX>(s, n, k1, nbk1, buf ^ 1, true, used) && t == 0) s.bad = 1;
     } else {
-      gj_tiles<T, NMAX>(s, s.C[buf], n8, ncols - nbk1, k0, nbk1, nbk, t - 64, nt - 64);
+      gj_strips<T, NMAX>(s, buf, n, nbk, ncols - nbk1, k0, nbk1, wv - 1, nwv - 1);
     }
     if (nbk1 == 0) break;
   }
