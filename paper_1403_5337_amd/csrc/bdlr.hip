@@ -1527,17 +1527,20 @@ static int learned_t(hodlr_s* h, const double* K, int ldk, const int* rowptr, co
   const int N = 2 * tr.n * tr.L;  // every vertex is a row of one block and a column of another, per level
   int maxside = 0;
   for (auto& tk : tasks) maxside = std::max(maxside, std::max(tk.m, tk.nc));
-  DevBuf d_feat, d_score, d_dcnt, d_budget, d_state, d_kused;
+  DevBuf d_feat, d_score, d_dcnt, d_budget, d_state;
   HODLR_TRY(d_feat.ensure((size_t)N * 8 * sizeof(float)));
   HODLR_TRY(d_score.ensure((size_t)N * sizeof(float)));
   HODLR_TRY(d_dcnt.ensure((size_t)2 * nt * sizeof(int)));
   HODLR_TRY(d_budget.ensure((size_t)2 * nt * sizeof(int)));
-  HODLR_TRY(d_state.ensure((size_t)nt * sizeof(int)));
-  HODLR_TRY(d_kused.ensure((size_t)nt * sizeof(int)));
+  // block states, then the picks each block used: one read-back
+  HODLR_TRY(d_state.ensure((size_t)2 * nt * sizeof(int)));
+  int* const dstate = d_state.as<int>();
+  int* const dkused = dstate + nt;
   SkelScratch sc;
   HODLR_TRY(sc.ensure(nt, selo, invo, cgo, sizeof(T), check_chunks(tasks)));
-  // Every attempt is queued at once; blocks already decided skip its
-  // kernels.  A block's attempts depend only on its own decisions, so the
+  // The attempts are queued in two batches (the host reads the block states
+  // once in between); blocks already decided skip an attempt's kernels.  A
+  // block's attempts depend only on its own decisions, so the
   // blocks of levels 1 and 2 (the largest picks, so the longest
   // eliminations) run their attempts on a side stream beside those of the
   // other levels, and the build waits for the longer of the two chains.  The
@@ -1593,7 +1596,7 @@ static int learned_t(hodlr_s* h, const double* K, int ldk, const int* rowptr, co
   HODLR_HIP(hipMemsetAsync(h->d_rank.p, 0, tr.nnodes() * sizeof(int), s));
   const int g1 = (nt + kBlock - 1) / kBlock;
   k_learned_init<<<g1, kBlock, 0, s>>>(sc.tasks.as<BdlrTask>(), nt, d_dcnt.as<int>(), kinit, SKEL,
-                                       d_budget.as<int>(), d_state.as<int>(), d_kused.as<int>());
+                                       d_budget.as<int>(), dstate, dkused);
   HODLR_HIP(hipGetLastError());
   if (join.side) {
     // the side stream's attempts need the budgets; the build's need the norms
@@ -1605,7 +1608,7 @@ static int learned_t(hodlr_s* h, const double* K, int ldk, const int* rowptr, co
     for (int attempt = a0; attempt < a1; ++attempt)
       for (const Group& g : groups) {
         const AttemptView v = attempt_view(sc, g.x0);
-        int* state_g = d_state.as<int>() + g.x0;
+        int* state_g = dstate + g.x0;
         int* budget_g = d_budget.as<int>() + 2 * g.x0;
         {
           ProfScope prof("skel_topk", g.st);
@@ -1618,7 +1621,7 @@ static int learned_t(hodlr_s* h, const double* K, int ldk, const int* rowptr, co
         k_err_decide<<<(g.n + kBlock - 1) / kBlock, kBlock, 0, g.st>>>(
             v.tasks, g.n, v.cnt, sc.norm.as<double>(), v.samp, kSkelSamples, v.part, sc.nch, v.err, accept, SKEL,
             h->precision == 64 ? kRankCap64 : kRankCap32, attempt == kLearnedAttempts - 1 ? 1 : 0, v.rt, budget_g,
-            state_g, d_kused.as<int>() + g.x0);
+            state_g, dkused + g.x0);
         HODLR_HIP(hipGetLastError());
       }
     if (join.side) {
@@ -1633,10 +1636,20 @@ static int learned_t(hodlr_s* h, const double* K, int ldk, const int* rowptr, co
   // that would find nothing to do.
   std::vector<int> state(nt), kused(nt);
   constexpr int kFirstBatch = 2;
+  void* pin = nullptr;
+  size_t pin_bytes = 0;
+  HODLR_TRY(pinned_alloc((size_t)2 * nt * sizeof(int), &pin, &pin_bytes));
+  struct PinGuard {
+    void* p;
+    size_t b;
+    ~PinGuard() { pinned_free(p, b); }
+  } pin_guard{pin, pin_bytes};
   auto read_back = [&]() -> int {
-    HODLR_HIP(hipMemcpyAsync(state.data(), d_state.p, nt * sizeof(int), hipMemcpyDeviceToHost, s));
-    HODLR_HIP(hipMemcpyAsync(kused.data(), d_kused.p, nt * sizeof(int), hipMemcpyDeviceToHost, s));
+    HODLR_HIP(hipMemcpyAsync(pin, dstate, 2 * nt * sizeof(int), hipMemcpyDeviceToHost, s));
     HODLR_HIP(hipStreamSynchronize(s));
+    const int* hp = static_cast<const int*>(pin);
+    std::copy(hp, hp + nt, state.begin());
+    std::copy(hp + nt, hp + 2 * nt, kused.begin());
     return HODLR_OK;
   };
   HODLR_TRY(queue(0, std::min(kFirstBatch, kLearnedAttempts)));
@@ -1667,7 +1680,7 @@ static int learned_t(hodlr_s* h, const double* K, int ldk, const int* rowptr, co
     HODLR_HIP(hipMemsetAsync(U2.p, 0, (size_t)tr.n * C * sizeof(T), s));
     HODLR_HIP(hipMemsetAsync(V2.p, 0, (size_t)tr.n * C * sizeof(T), s));
     HODLR_TRY(launch_aca(h, K, ldk, U2.p, V2.p, capoff, cap, s, &nodes));
-    k_fallback_prep<<<g1, kBlock, 0, s>>>(sc.tasks.as<BdlrTask>(), nt, d_state.as<int>(), h->d_rank.as<int>(),
+    k_fallback_prep<<<g1, kBlock, 0, s>>>(sc.tasks.as<BdlrTask>(), nt, dstate, h->d_rank.as<int>(),
                                           rank2.as<int>(), skip2.as<int>());
     HODLR_HIP(hipGetLastError());
     // both candidates measured on the same positions: the skeleton's last
@@ -1693,21 +1706,23 @@ static int learned_t(hodlr_s* h, const double* K, int ldk, const int* rowptr, co
       }
     }
     HODLR_HIP(hipGetLastError());
-    k_fallback_choose<T><<<dim3(nt, 8), kBlock, 0, s>>>(sc.tasks.as<BdlrTask>(), d_state.as<int>(),
+    k_fallback_choose<T><<<dim3(nt, 8), kBlock, 0, s>>>(sc.tasks.as<BdlrTask>(), dstate,
                                                         sc.err.as<double>(), err2.as<double>(), sc.rt.as<int>(),
                                                         U2.as<T>(), V2.as<T>(), Ucap, Vcap, tr.n,
-                                                        h->d_rank.as<int>(), d_kused.as<int>());
+                                                        h->d_rank.as<int>(), dkused);
     HODLR_HIP(hipGetLastError());
-    HODLR_HIP(hipMemcpyAsync(kused.data(), d_kused.p, nt * sizeof(int), hipMemcpyDeviceToHost, s));
+    HODLR_HIP(hipMemcpyAsync(kused.data(), dkused, nt * sizeof(int), hipMemcpyDeviceToHost, s));
     HODLR_HIP(hipStreamSynchronize(s));
   }
   h->skel_k.assign(tr.nnodes(), -1);
   for (int x = 0; x < nt; ++x) h->skel_k[tasks[x].node] = kused[x];
-  // the scratch goes back to the allocator once the stream is past its readers
-  for (DevBuf* b : {&d_feat, &d_score, &d_dcnt, &d_budget, &d_state, &d_kused}) b->release_after(s);
+  // the stream (joined with the side stream) was synchronized above, so no
+  // queued work reads the scratch: it goes back to the allocator at once,
+  // without an event per buffer
+  for (DevBuf* b : {&d_feat, &d_score, &d_dcnt, &d_budget, &d_state}) b->release();
   for (DevBuf* b : {&sc.tasks, &sc.sel, &sc.piv, &sc.cnt, &sc.rt, &sc.inv, &sc.cg, &sc.samp, &sc.err, &sc.norm,
                     &sc.part})
-    b->release_after(s);
+    b->release();
   return HODLR_OK;
 }
 
