@@ -16,6 +16,7 @@
 // right-hand side k at V + (j s + k) n (so the s vectors of step j form one
 // n x s matrix), preconditioned vectors likewise in Z.
 #include <algorithm>
+#include <atomic>
 #include <cmath>
 #include <mutex>
 
@@ -44,10 +45,10 @@ typedef double f64x4 __attribute__((ext_vector_type(4)));
 template <typename TZ, int NB, int COLS>
 __global__ void __launch_bounds__(kRowsPerWG)
     k_matvec_mfma(const double* __restrict__ K, int ldk, int n, const TZ* __restrict__ src, int lds, int s,
-                  double* __restrict__ part) {
+                  double* __restrict__ part, int rev) {
   constexpr int kQ = COLS / 4;
   __shared__ double zs[COLS * 16 * NB];  // z(c, k) at zs[c 16 NB + k]
-  const int t = threadIdx.x, lane = t & 63, w = t >> 6, sp = blockIdx.y;
+  const int t = threadIdx.x, lane = t & 63, w = t >> 6, sp = rev ? gridDim.y - 1 - blockIdx.y : blockIdx.y;
   const int c0 = sp * COLS, cn = min(COLS, n - c0);
   const int m = lane & 15, kl = lane >> 4;
   const int row = blockIdx.x * 64 + 16 * w + m;
@@ -104,10 +105,10 @@ __global__ void __launch_bounds__(kRowsPerWG)
 template <typename TZ, int NB, int CH>
 __global__ void __launch_bounds__(kRowsPerWG)
     k_matvec_chunks(const double* __restrict__ K, int ldk, int n, const TZ* __restrict__ src, int lds, int s,
-                    double* __restrict__ part) {
+                    double* __restrict__ part, int rev) {
   constexpr int COLS = 128, kQ = COLS / 4, WD = CH * COLS;
   __shared__ double zs[WD * 16 * NB];  // z(c, k) at zs[c 16 NB + k]
-  const int t = threadIdx.x, lane = t & 63, w = t >> 6, sp = blockIdx.y;
+  const int t = threadIdx.x, lane = t & 63, w = t >> 6, sp = rev ? gridDim.y - 1 - blockIdx.y : blockIdx.y;
   const int c0 = sp * WD, cn = min(WD, n - c0);
   const int m = lane & 15, kl = lane >> 4;
   const int row = blockIdx.x * 64 + 16 * w + m;
@@ -555,9 +556,9 @@ size_t gmres_noalloc_limit() { return kNoallocScratchBytes; }
 
 template <typename TZ, int COLS>
 static int launch_matvec_cols(const double* K, int ldk, int n, const TZ* src, int lds, int s, double* part,
-                              hipStream_t st) {
+                              hipStream_t st, int rev) {
   const dim3 grid((n + 63) / 64, (n + COLS - 1) / COLS);
-#define HODLR_MV(NB) k_matvec_mfma<TZ, NB, COLS><<<grid, kRowsPerWG, 0, st>>>(K, ldk, n, src, lds, s, part)
+#define HODLR_MV(NB) k_matvec_mfma<TZ, NB, COLS><<<grid, kRowsPerWG, 0, st>>>(K, ldk, n, src, lds, s, part, rev)
   if (s <= 16) HODLR_MV(1);
   else if (s <= 32) HODLR_MV(2);
   else HODLR_MV(4);
@@ -568,12 +569,12 @@ static int launch_matvec_cols(const double* K, int ldk, int n, const TZ* src, in
 
 template <typename TZ, int CH>
 static int launch_matvec_chunks(const double* K, int ldk, int n, const TZ* src, int lds, int s, double* part,
-                                hipStream_t st) {
+                                hipStream_t st, int rev) {
   const dim3 grid((n + 63) / 64, (n + 128 * CH - 1) / (128 * CH));
   if (s <= 16)
-    k_matvec_chunks<TZ, 1, CH><<<grid, kRowsPerWG, 0, st>>>(K, ldk, n, src, lds, s, part);
+    k_matvec_chunks<TZ, 1, CH><<<grid, kRowsPerWG, 0, st>>>(K, ldk, n, src, lds, s, part, rev);
   else if (s <= 32)
-    k_matvec_chunks<TZ, 2, CH><<<grid, kRowsPerWG, 0, st>>>(K, ldk, n, src, lds, s, part);
+    k_matvec_chunks<TZ, 2, CH><<<grid, kRowsPerWG, 0, st>>>(K, ldk, n, src, lds, s, part, rev);
   else
     return fail(HODLR_EINVAL, "chunked product: too many right-hand sides for the staged z");
   HODLR_HIP(hipGetLastError());
@@ -592,10 +593,17 @@ template <typename TZ>
 static int launch_matvec(const double* K, int ldk, int n, const TZ* src, int lds, int s, double* part, int cols,
                          hipStream_t st) {
   ProfScope prof("matvec", st);
-  if (cols == 64) return launch_matvec_cols<TZ, 64>(K, ldk, n, src, lds, s, part, st);
-  if (cols == 256) return launch_matvec_cols<TZ, 256>(K, ldk, n, src, lds, s, part, st);
-  if (cols == 512) return launch_matvec_chunks<TZ, 4>(K, ldk, n, src, lds, s, part, st);
-  return launch_matvec_cols<TZ, 128>(K, ldk, n, src, lds, s, part, st);
+  // successive products sweep K in opposite directions (column splits in
+  // increasing, then decreasing order), so that each one starts on the part
+  // of K the previous one read last, which the last-level cache still holds
+  // when K is larger than the cache; each split writes its own partial sums,
+  // so the result does not depend on the direction
+  static std::atomic<unsigned> calls{0};
+  const int rev = (int)(calls.fetch_add(1, std::memory_order_relaxed) & 1u);
+  if (cols == 64) return launch_matvec_cols<TZ, 64>(K, ldk, n, src, lds, s, part, st, rev);
+  if (cols == 256) return launch_matvec_cols<TZ, 256>(K, ldk, n, src, lds, s, part, st, rev);
+  if (cols == 512) return launch_matvec_chunks<TZ, 4>(K, ldk, n, src, lds, s, part, st, rev);
+  return launch_matvec_cols<TZ, 128>(K, ldk, n, src, lds, s, part, st, rev);
 }
 
 // The split width for (n, right-hand-side block, type of z): chosen on the
