@@ -152,18 +152,18 @@ def cpu_baseline(front, w, nrhs_sample, method, depth, solver="gmres", budget_s=
 # taken again.
 TRAFFIC = {
     ("apply_level", "tpfa4096"): {"source": "paper_1403_5337_amd/csrc/solve.hip",
-                                  "sha256": "792a556e9f24caac7c69b9f5dd5185421785192b1fc8398ea7f456996596c677",
-                                  "fetch_kib": 1598.0, "write_kib": 236.0,
-                                  "fetch_factor": 2.0, "write_factor": 1.0, "rocprof_avg_us": 7.94},
+                                  "sha256": "f56ddc9fb45eadc524c64ebb253ba40e0ab29dfcae0706716562ecef16d8971a",
+                                  "fetch_kib": 1611.0, "write_kib": 236.0,
+                                  "fetch_factor": 2.0, "write_factor": 1.0, "rocprof_avg_us": 8.34},
     ("apply_level", "elastic6144"): {"source": "paper_1403_5337_amd/csrc/solve.hip",
-                                     "sha256": "792a556e9f24caac7c69b9f5dd5185421785192b1fc8398ea7f456996596c677",
-                                     "fetch_kib": 4421.4, "write_kib": 67.3,
-                                     "fetch_factor": 2.0, "write_factor": 1.0, "rocprof_avg_us": 12.94},
-    # the float64 product on float32 z (the width the tuner kept in that run)
+                                     "sha256": "f56ddc9fb45eadc524c64ebb253ba40e0ab29dfcae0706716562ecef16d8971a",
+                                     "fetch_kib": 4434.3, "write_kib": 67.3,
+                                     "fetch_factor": 2.0, "write_factor": 1.0, "rocprof_avg_us": 10.23},
+    # the float64 product on float32 z at the 128-column split width
     ("matvec", "elastic6144"): {"source": "paper_1403_5337_amd/csrc/gmres.hip",
-                                "sha256": "13c5b3d369c8543ea62a0cd8002c8bd092dfc146eef830eccd8be950a349b90b",
-                                "fetch_kib": 147582.5, "write_kib": 2304.0,
-                                "fetch_factor": 2.0, "write_factor": 1.0, "rocprof_avg_us": 49.16},
+                                "sha256": "a6fa7f427e09be517a95bd70438d6b6adb75b4a8d7ce8dee7863ae81c7584b96",
+                                "fetch_kib": 147578.5, "write_kib": 2304.0,
+                                "fetch_factor": 2.0, "write_factor": 1.0, "rocprof_avg_us": 45.91},
 }
 
 
