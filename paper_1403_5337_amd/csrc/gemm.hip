@@ -19,6 +19,9 @@ constexpr int kTile = 64, kKc = 32;  // tile side; K splits are multiples of kKc
 // K chunk staged in LDS per step: 32 (float), 16 (double)
 template <typename T> constexpr int chunk_k() { return sizeof(T) == 8 ? 16 : 32; }
 
+// A zero word for the loads of entries outside an operand (never written).
+__device__ double g_gemm_zero[2];
+
 struct TaskDev {
   const void* A;
   const void* B;
@@ -120,24 +123,41 @@ __global__ void __launch_bounds__(kBlock)
   const int ks = rem / tk.tiles_n;
   const int i0 = tm * kTile, j0 = tn * kTile;
   const int kb = ks * tk.kchunk, ke = min(tk.k, kb + tk.kchunk);
-  const T* A = static_cast<const T*>(tk.A);
-  const T* B = static_cast<const T*>(tk.B);
-  T* C = static_cast<T*>(tk.C) + (size_t)ks * tk.cstride;
-  // loads: 64 x KC of op(A) and KC x 64 of B, NL elements each per thread
+  // the operands as global-memory pointers (the task table only holds
+  // generic ones), so that their loads count on the vector-memory counter
+  // alone and do not wait behind LDS traffic
+  typedef const __attribute__((address_space(1))) T* GP;
+  typedef __attribute__((address_space(1))) T* GPW;
+  const GP A = (GP)tk.A;
+  const GP B = (GP)tk.B;
+  const GPW C = (GPW)tk.C + (size_t)ks * tk.cstride;
+  // loads: 64 x KC of op(A) and KC x 64 of B, NL elements each per thread.
+  // An entry outside the operand reads a zero word instead: the address is
+  // chosen, not the value, so no load sits behind a branch and all of them
+  // are in flight together.
+  const GP Z = (GP)(const void*)g_gemm_zero;
   T av[NL], bv[NL];
   auto load = [&](int k0) {
+    if (tk.transA) {  // op(A)(i, kk) = A[kk + i lda]: contiguous along kk
+#pragma unroll
+      for (int u = 0; u < NL; ++u) {
+        const int e = t + u * kBlock, kk = e % KC, i = e / KC;
+        const bool in = i0 + i < tk.m && k0 + kk < ke;
+        av[u] = *(in ? A + (size_t)(i0 + i) * tk.lda + k0 + kk : Z);
+      }
+    } else {  // A[i + kk lda]: contiguous along i
+#pragma unroll
+      for (int u = 0; u < NL; ++u) {
+        const int e = t + u * kBlock, i = e % kTile, kk = e / kTile;
+        const bool in = i0 + i < tk.m && k0 + kk < ke;
+        av[u] = *(in ? A + (size_t)(k0 + kk) * tk.lda + i0 + i : Z);
+      }
+    }
 #pragma unroll
     for (int u = 0; u < NL; ++u) {
-      const int e = t + u * kBlock;
-      if (tk.transA) {  // op(A)(i, kk) = A[kk + i lda]: contiguous along kk
-        const int kk = e % KC, i = e / KC;
-        av[u] = (i0 + i < tk.m && k0 + kk < ke) ? A[(size_t)(i0 + i) * tk.lda + k0 + kk] : T(0);
-      } else {  // A[i + kk lda]: contiguous along i
-        const int i = e % kTile, kk = e / kTile;
-        av[u] = (i0 + i < tk.m && k0 + kk < ke) ? A[(size_t)(k0 + kk) * tk.lda + i0 + i] : T(0);
-      }
-      const int kk = e % KC, j = e / KC;
-      bv[u] = (j0 + j < tk.n && k0 + kk < ke) ? B[(size_t)(j0 + j) * tk.ldb + k0 + kk] : T(0);
+      const int e = t + u * kBlock, kk = e % KC, j = e / KC;
+      const bool in = j0 + j < tk.n && k0 + kk < ke;
+      bv[u] = *(in ? B + (size_t)(j0 + j) * tk.ldb + k0 + kk : Z);
     }
   };
   auto store = [&](int buf) {
@@ -173,7 +193,7 @@ __global__ void __launch_bounds__(kBlock)
     MfmaAcc<T>::coord(q, lane, ii, jj);
     const int i = i0 + wm + ii, j = j0 + wn + jj;
     if (i >= tk.m || j >= tk.n) continue;
-    T* cp = C + i + (size_t)j * tk.ldc;
+    const GPW cp = C + i + (size_t)j * tk.ldc;
     T val = alpha * acc.get(q);
     if (tk.ksplit == 1) {
       if (tk.mode == kGemmAccumulate) val += *cp;
