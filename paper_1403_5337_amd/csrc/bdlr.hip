@@ -767,6 +767,9 @@ __global__ void __launch_bounds__(64)
 // unused), ns <= 16; counts: rows and columns picked per task; norm2: per
 // task of the whole list (BdlrTask::task), |K(I, J)|_F^2.
 //
+// A zero word for loads of entries outside the data (never written).
+__device__ double g_bdlr_zero[2];
+
 // k_skel_check: workgroup (task, chunk, group) sums the squared residual of
 // the group's rows over its chunk of kCheckX columns (and of the group's
 // columns over its chunk of kCheckX rows) into part: lane l takes position
@@ -823,7 +826,9 @@ __global__ void __launch_bounds__(kBlock)
       for (int k = 0; k < kStage; ++k) {
         const int e = t + k * kBlock, q = e % NS, l = e / NS;
         const int p = e < NS * r ? sp[side * NS + q] : -1;
-        v[k] = p >= 0 ? F[(size_t)l * ldu + p] : T(0);
+        // the address is chosen, not the value (a zero word for the entries
+        // outside), so the loads are in flight together
+        v[k] = *(p >= 0 ? F + (size_t)l * ldu + p : reinterpret_cast<const T*>(g_bdlr_zero));
       }
 #pragma unroll
       for (int k = 0; k < kStage; ++k) {
@@ -841,13 +846,17 @@ __global__ void __launch_bounds__(kBlock)
     if (in) {
       int l = l0;
       for (; l + kL <= l1; l += kL) {
-        double o[kL];
+        // the kL loads from one base, all issued before the first use
+        const T* Ob = O + (size_t)l * ldu + x;
+        T o[kL];
 #pragma unroll
-        for (int u = 0; u < kL; ++u) o[u] = (double)O[(size_t)(l + u) * ldu + x];
+        for (int u = 0; u < kL; ++u) o[u] = Ob[u * ldu];
 #pragma unroll
-        for (int u = 0; u < kL; ++u)
+        for (int u = 0; u < kL; ++u) {
+          const double ou = (double)o[u];
 #pragma unroll
-          for (int q = 0; q < NS; ++q) a[q] += (double)uv[q][l + u] * o[u];
+          for (int q = 0; q < NS; ++q) a[q] += (double)uv[q][l + u] * ou;
+        }
       }
       for (; l < l1; ++l) {
         const double o = (double)O[(size_t)l * ldu + x];
@@ -865,9 +874,9 @@ __global__ void __launch_bounds__(kBlock)
 #pragma unroll
       for (int u = 0; u < 4; ++u) {
         const int p = sp[side * NS + 4 * w + u];
-        b[u] = p < 0 ? 0.0
-                     : side == 0 ? K[(size_t)(tk.col0 + x) * ldk + tk.row0 + p]
-                                 : K[(size_t)(tk.col0 + p) * ldk + tk.row0 + x];
+        b[u] = *(p < 0 ? g_bdlr_zero
+                       : side == 0 ? K + (size_t)(tk.col0 + x) * ldk + tk.row0 + p
+                                   : K + (size_t)(tk.col0 + p) * ldk + tk.row0 + x);
       }
 #pragma unroll
       for (int u = 0; u < 4; ++u) {

@@ -100,16 +100,29 @@ __device__ void rcb_node(const float* __restrict__ coords, int* __restrict__ per
   const int t = threadIdx.x;
   float key[E];
   int pos[E];
+  // every load issued unconditionally (addresses clamped into the node), the
+  // vertex ids first, then their coordinates, so each batch is one round trip
+  int v[E];
+#pragma unroll
+  for (int r = 0; r < E; ++r) v[r] = perm[l0 + min(t * E + r, len - 1)];
+#pragma unroll
+  for (int r = 0; r < E; ++r) key[r] = coords[3 * (size_t)v[r] + ax];
 #pragma unroll
   for (int r = 0; r < E; ++r) {
     const int e = t * E + r;
     pos[r] = e < len ? e : INT_MAX;
-    key[r] = e < len ? coords[3 * (size_t)perm[l0 + e] + ax] : INFINITY;
+    key[r] = e < len ? key[r] : INFINITY;
   }
   rcb_sort<E>(key, pos, P, skey, spos);
   // perm(l0 + e) <- perm(l0 + pos(e)); the old entries go through LDS
   int* old = spos;
-  for (int e = t; e < len; e += blockDim.x) old[e] = perm[l0 + e];
+#pragma unroll
+  for (int r = 0; r < E; ++r) v[r] = perm[l0 + min(t + r * (int)blockDim.x, len - 1)];
+#pragma unroll
+  for (int r = 0; r < E; ++r) {
+    const int e = t + r * (int)blockDim.x;
+    if (e < len) old[e] = v[r];
+  }
   __syncthreads();
 #pragma unroll
   for (int r = 0; r < E; ++r) {
@@ -131,14 +144,26 @@ __global__ void __launch_bounds__(kRcbThreads)
   int P = 1;
   while (P < len) P <<= 1;
   float mn[3] = {FLT_MAX, FLT_MAX, FLT_MAX}, mx[3] = {-FLT_MAX, -FLT_MAX, -FLT_MAX};
-  for (int e = t; e < len; e += nt) {
-    const int v = perm[l0 + e];
+  // batches of 8 entries per thread: the vertex ids, then their coordinates,
+  // each batch of loads in flight together (addresses clamped into the node)
+  constexpr int kB = 8;
+  for (int e0 = 0; e0 < len; e0 += kB * nt) {
+    int v[kB];
 #pragma unroll
-    for (int a = 0; a < 3; ++a) {
-      const float c = coords[3 * (size_t)v + a];
-      mn[a] = fminf(mn[a], c);
-      mx[a] = fmaxf(mx[a], c);
-    }
+    for (int u = 0; u < kB; ++u) v[u] = perm[l0 + min(e0 + t + u * nt, len - 1)];
+    float c[kB][3];
+#pragma unroll
+    for (int u = 0; u < kB; ++u)
+#pragma unroll
+      for (int a = 0; a < 3; ++a) c[u][a] = coords[3 * (size_t)v[u] + a];
+#pragma unroll
+    for (int u = 0; u < kB; ++u)
+      if (e0 + t + u * nt < len)
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+          mn[a] = fminf(mn[a], c[u][a]);
+          mx[a] = fmaxf(mx[a], c[u][a]);
+        }
   }
 #pragma unroll
   for (int a = 0; a < 3; ++a)
