@@ -164,6 +164,25 @@ void dev_free_after(void* p, size_t nbytes, hipStream_t s) {
   g_pending.push_back({nbytes, p, ev, cur_device()});
 }
 
+int event_take(hipEvent_t* out) {
+  {
+    std::lock_guard<std::mutex> lk(g_alloc_mu);
+    if (!g_event_pool.empty()) {
+      *out = g_event_pool.back();
+      g_event_pool.pop_back();
+      return HODLR_OK;
+    }
+  }
+  HODLR_HIP(hipEventCreateWithFlags(out, hipEventDisableTiming));
+  return HODLR_OK;
+}
+
+void event_give(hipEvent_t e) {
+  if (!e) return;
+  std::lock_guard<std::mutex> lk(g_alloc_mu);
+  g_event_pool.push_back(e);
+}
+
 void release_cached_memory() {
   std::lock_guard<std::mutex> lk(g_alloc_mu);
   int dev = cur_device();
@@ -248,8 +267,12 @@ static int init_handle(hodlr_s* h, int n, int leaf, int precision, hipStream_t s
   HODLR_TRY(h->d_lo.ensure(nn * sizeof(int)));
   HODLR_TRY(h->d_hi.ensure(nn * sizeof(int)));
   HODLR_TRY(h->d_rank.ensure(nn * sizeof(int)));
-  HODLR_HIP(hipMemcpy(h->d_lo.p, t.lo.data(), nn * sizeof(int), hipMemcpyHostToDevice));
-  HODLR_HIP(hipMemcpy(h->d_hi.p, t.hi.data(), nn * sizeof(int), hipMemcpyHostToDevice));
+  // the node ranges from the process-wide copy of this tree's ranges on the
+  // device, by copies ordered on the stream (no host round trip)
+  const int *dlo = nullptr, *dhi = nullptr;
+  HODLR_TRY(device_tree_ranges(t, &dlo, &dhi));
+  HODLR_HIP(hipMemcpyAsync(h->d_lo.p, dlo, nn * sizeof(int), hipMemcpyDeviceToDevice, stream));
+  HODLR_HIP(hipMemcpyAsync(h->d_hi.p, dhi, nn * sizeof(int), hipMemcpyDeviceToDevice, stream));
   HODLR_TRY(h->status.ensure(4 * sizeof(int)));
   HODLR_HIP(hipMemsetAsync(h->status.p, 0, 4 * sizeof(int), stream));
   HODLR_TRY(h->Kinv.ensure((size_t)h->nleaf * h->bmax * h->bmax * h->esize));
@@ -517,13 +540,12 @@ static int build_impl(const double* K, int n, int ldk, const int* g_rowptr, cons
     hipEvent_t ev[2] = {nullptr, nullptr};
     ~Fork() {
       if (side) (void)hipStreamSynchronize(side);
-      for (auto e : ev)
-        if (e) (void)hipEventDestroy(e);
+      for (auto e : ev) event_give(e);
     }
   } fork;
   if (o.method != HODLR_ACA) {
     HODLR_TRY(side_stream(0, &fork.side));
-    for (auto& e : fork.ev) HODLR_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+    for (auto& e : fork.ev) HODLR_TRY(event_take(&e));
     HODLR_HIP(hipEventRecord(fork.ev[0], stream));
     HODLR_HIP(hipStreamWaitEvent(fork.side, fork.ev[0], 0));
     HODLR_TRY(h->lstatus.ensure(4 * sizeof(int)));

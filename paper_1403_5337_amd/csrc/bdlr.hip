@@ -1053,7 +1053,13 @@ struct SkelScratch {
 // then overwrites with its own.
 // Uploads the task records and the chunk numbering (one copy on s); the
 // norm kernels follow on run (which must be ordered after s's copy).
-static int norm_upload(const std::vector<BdlrTask>& tasks, SkelScratch& sc, hipStream_t s, int* nchunk_out) {
+// staging (optional): pinned host memory of norm_upload_bytes(nt) bytes that
+// stays valid until the stream is past the copy; without it the tables are
+// copied from pageable memory.
+static size_t norm_upload_bytes(int nt) { return (size_t)nt * sizeof(BdlrTask) + ((size_t)nt + 1) * sizeof(int); }
+
+static int norm_upload(const std::vector<BdlrTask>& tasks, SkelScratch& sc, hipStream_t s, int* nchunk_out,
+                       void* staging = nullptr) {
   const int nt = (int)tasks.size();
   // chunk numbering (c0, nt + 1 ints) after the task records in one upload
   std::vector<int> c0(nt + 1, 0);
@@ -1062,13 +1068,18 @@ static int norm_upload(const std::vector<BdlrTask>& tasks, SkelScratch& sc, hipS
     c0[x + 1] = c0[x] + (tasks[x].nc + cols - 1) / cols;
   }
   const int nchunk = c0[nt];
-  const size_t tb = (size_t)nt * sizeof(BdlrTask);
-  std::vector<unsigned char> up(tb + (nt + 1) * sizeof(int));
-  std::memcpy(up.data(), tasks.data(), tb);
-  std::memcpy(up.data() + tb, c0.data(), (nt + 1) * sizeof(int));
-  HODLR_TRY(sc.tasks.ensure(up.size()));
+  const size_t tb = (size_t)nt * sizeof(BdlrTask), ub = norm_upload_bytes(nt);
+  std::vector<unsigned char> up;
+  unsigned char* hp = static_cast<unsigned char*>(staging);
+  if (!hp) {
+    up.resize(ub);
+    hp = up.data();
+  }
+  std::memcpy(hp, tasks.data(), tb);
+  std::memcpy(hp + tb, c0.data(), (nt + 1) * sizeof(int));
+  HODLR_TRY(sc.tasks.ensure(ub));
   HODLR_TRY(sc.norm.ensure(((size_t)nt + nchunk) * sizeof(double)));
-  HODLR_HIP(hipMemcpyAsync(sc.tasks.p, up.data(), up.size(), hipMemcpyHostToDevice, s));
+  HODLR_HIP(hipMemcpyAsync(sc.tasks.p, hp, ub, hipMemcpyHostToDevice, s));
   *nchunk_out = nchunk;
   return HODLR_OK;
 }
@@ -1536,7 +1547,7 @@ static int learned_t(hodlr_s* h, const double* K, int ldk, const int* rowptr, co
   const int N = 2 * tr.n * tr.L;  // every vertex is a row of one block and a column of another, per level
   int maxside = 0;
   for (auto& tk : tasks) maxside = std::max(maxside, std::max(tk.m, tk.nc));
-  DevBuf d_feat, d_score, d_dcnt, d_budget, d_state;
+  DevBuf d_feat, d_score, d_dcnt, d_budget, d_state, d_blk;
   HODLR_TRY(d_feat.ensure((size_t)N * 8 * sizeof(float)));
   HODLR_TRY(d_score.ensure((size_t)N * sizeof(float)));
   HODLR_TRY(d_dcnt.ensure((size_t)2 * nt * sizeof(int)));
@@ -1576,16 +1587,39 @@ static int learned_t(hodlr_s* h, const double* K, int ldk, const int* rowptr, co
     hipEvent_t e[4] = {nullptr, nullptr, nullptr, nullptr};
     ~Join() {
       if (side) (void)hipStreamSynchronize(side);
-      for (auto x : e)
-        if (x) (void)hipEventDestroy(x);
+      for (auto x : e) event_give(x);
     }
   } join;
+  // One pinned block for this build's uploads (task and chunk tables, the
+  // feature block table) and its read-back of the block states: the copies
+  // are then asynchronous, and the block outlives them (it is returned after
+  // the read-back's synchronization, or after the guards' on an early return).
+  const size_t ub = (norm_upload_bytes(nt) + 255) & ~(size_t)255;
+  const size_t bb = (blocks.size() * sizeof(SkelBlock) + 255) & ~(size_t)255;
+  void* pin = nullptr;
+  size_t pin_bytes = 0;
+  HODLR_TRY(pinned_alloc(ub + bb + (size_t)2 * nt * sizeof(int), &pin, &pin_bytes));
+  struct PinGuard {
+    void* p;
+    size_t b;
+    hipStream_t s;
+    ~PinGuard() {
+      (void)hipStreamSynchronize(s);  // (a no-op after the read-back)
+      pinned_free(p, b);
+    }
+  } pin_guard{pin, pin_bytes, s};
+  unsigned char* const pin_up = static_cast<unsigned char*>(pin);
+  unsigned char* const pin_blk = pin_up + ub;
+  int* const pin_rb = reinterpret_cast<int*>(pin_blk + bb);
   int nchunk = 0;
-  HODLR_TRY(norm_upload(tasks, sc, s, &nchunk));  // (the task table for every kernel below)
+  HODLR_TRY(norm_upload(tasks, sc, s, &nchunk, pin_up));  // (the task table for every kernel below)
+  HODLR_TRY(d_blk.ensure(blocks.size() * sizeof(SkelBlock)));
+  std::memcpy(pin_blk, blocks.data(), blocks.size() * sizeof(SkelBlock));
+  HODLR_HIP(hipMemcpyAsync(d_blk.p, pin_blk, blocks.size() * sizeof(SkelBlock), hipMemcpyHostToDevice, s));
   if (groups.size() == 2) {
     HODLR_TRY(side_stream(1, &groups[0].st));
     join.side = groups[0].st;
-    for (auto& x : join.e) HODLR_HIP(hipEventCreateWithFlags(&x, hipEventDisableTiming));
+    for (auto& x : join.e) HODLR_TRY(event_take(&x));
     HODLR_HIP(hipEventRecord(join.e[0], s));
     HODLR_HIP(hipStreamWaitEvent(join.side, join.e[0], 0));
     HODLR_TRY(norm_launch(K, ldk, nt, nchunk, sc, join.side));
@@ -1596,7 +1630,7 @@ static int learned_t(hodlr_s* h, const double* K, int ldk, const int* rowptr, co
   {
     ProfScope prof("skel_features", s);
     HODLR_TRY(launch_skel_features(rowptr, col, xyz, K, ldk, blocks, d_feat.as<float>(), s, h->depth,
-                                   d_dcnt.as<int>()));
+                                   d_dcnt.as<int>(), d_blk.as<SkelBlock>()));
   }
   {
     ProfScope prof("skel_score", s);
@@ -1645,18 +1679,10 @@ static int learned_t(hodlr_s* h, const double* K, int ldk, const int* rowptr, co
   // that would find nothing to do.
   std::vector<int> state(nt), kused(nt);
   constexpr int kFirstBatch = 2;
-  void* pin = nullptr;
-  size_t pin_bytes = 0;
-  HODLR_TRY(pinned_alloc((size_t)2 * nt * sizeof(int), &pin, &pin_bytes));
-  struct PinGuard {
-    void* p;
-    size_t b;
-    ~PinGuard() { pinned_free(p, b); }
-  } pin_guard{pin, pin_bytes};
   auto read_back = [&]() -> int {
-    HODLR_HIP(hipMemcpyAsync(pin, dstate, 2 * nt * sizeof(int), hipMemcpyDeviceToHost, s));
+    HODLR_HIP(hipMemcpyAsync(pin_rb, dstate, 2 * nt * sizeof(int), hipMemcpyDeviceToHost, s));
     HODLR_HIP(hipStreamSynchronize(s));
-    const int* hp = static_cast<const int*>(pin);
+    const int* hp = pin_rb;
     std::copy(hp, hp + nt, state.begin());
     std::copy(hp + nt, hp + 2 * nt, kused.begin());
     return HODLR_OK;
@@ -1728,7 +1754,7 @@ static int learned_t(hodlr_s* h, const double* K, int ldk, const int* rowptr, co
   // the stream (joined with the side stream) was synchronized above, so no
   // queued work reads the scratch: it goes back to the allocator at once,
   // without an event per buffer
-  for (DevBuf* b : {&d_feat, &d_score, &d_dcnt, &d_budget, &d_state}) b->release();
+  for (DevBuf* b : {&d_feat, &d_score, &d_dcnt, &d_budget, &d_state, &d_blk}) b->release();
   for (DevBuf* b : {&sc.tasks, &sc.sel, &sc.piv, &sc.cnt, &sc.rt, &sc.inv, &sc.cg, &sc.samp, &sc.err, &sc.norm,
                     &sc.part})
     b->release();

@@ -75,6 +75,11 @@ void release_cached_memory();
 // must not be returned while a copy from it may still be pending.
 int pinned_alloc(size_t nbytes, void** out, size_t* got);
 void pinned_free(void* p, size_t nbytes);
+// events (no timing) from a process-wide pool: taking one creates it only if
+// the pool is empty; an event goes back once no wait on it is still to be
+// queued (a wait already queued is not affected by a later record)
+int event_take(hipEvent_t* out);
+void event_give(hipEvent_t e);
 
 // ---------------------------------------------------------------------------
 // Device buffer (RAII over the caching allocator)
@@ -157,6 +162,9 @@ namespace hodlr {
 // ---------------------------------------------------------------------------
 // order.hip
 int launch_rcb(const float* coords, int n, const Tree& t, int* perm, hipStream_t s);
+// the tree's node ranges (lo, then hi) on the current device, uploaded once
+// per (device, n, leaf) and kept for the process
+int device_tree_ranges(const Tree& t, const int** lo, const int** hi);
 int launch_permute(const double* Kin, int n, int ldi, const int* perm, double* Kout, int ldo,
                    hipStream_t s);
 int launch_permute_rows(const float* in, int n, int width, const int* perm, float* out, hipStream_t s);
@@ -243,9 +251,11 @@ struct SkelBlock {
 };
 std::vector<SkelBlock> skel_blocks(const Tree& t);  // level order; samples total 2 n L
 // dcount (optional, 2 ints per block): row and column vertices at distance < cnt_depth
+// d_blocks (optional): the block table already on the device (else it is
+// uploaded here)
 int launch_skel_features(const int* rowptr, const int* col, const float* xyz, const double* K, int ldk,
                          const std::vector<SkelBlock>& blocks, float* feats, hipStream_t s, int cnt_depth = 0,
-                         int* dcount = nullptr);
+                         int* dcount = nullptr, const SkelBlock* d_blocks = nullptr);
 int launch_skel_labels(const std::vector<SkelBlock>& blocks, const int* piv, int kcap, const int* rank,
                        float* labels, hipStream_t s);
 int launch_mlp_forward(const float* X, int N, const float* P, int bf16, float* z, hipStream_t s);

@@ -210,7 +210,7 @@ __global__ void k_iota(int* p, int n) {
 // Node ranges of the tree of (n, leaf) on the current device, uploaded once
 // and kept for the process (a few KB each), so the ordering never waits for
 // the stream to drain before releasing them.
-static int tree_ranges(const Tree& t, const int** lo, const int** hi) {
+int device_tree_ranges(const Tree& t, const int** lo, const int** hi) {
   static std::mutex mu;
   static std::map<std::tuple<int, int, int>, std::pair<int*, int*>> cache;
   int dev = 0;
@@ -242,7 +242,7 @@ int launch_rcb(const float* coords, int n, const Tree& t, int* perm, hipStream_t
   HODLR_HIP(hipGetLastError());
   if (t.L == 0) return HODLR_OK;
   const int *dlo = nullptr, *dhi = nullptr;
-  HODLR_TRY(tree_ranges(t, &dlo, &dhi));
+  HODLR_TRY(device_tree_ranges(t, &dlo, &dhi));
   for (int p = 0; p < t.L; ++p) {
     k_rcb_level<<<1 << p, kRcbThreads, 0, s>>>(coords, perm, dlo, dhi, node_id(p, 0));
     HODLR_HIP(hipGetLastError());

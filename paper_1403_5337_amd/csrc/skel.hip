@@ -452,17 +452,20 @@ std::vector<SkelBlock> skel_blocks(const Tree& t) {
 
 int launch_skel_features(const int* rowptr, const int* col, const float* xyz, const double* K, int ldk,
                          const std::vector<SkelBlock>& blocks, float* feats, hipStream_t s, int cnt_depth,
-                         int* dcount) {
+                         int* dcount, const SkelBlock* d_blocks) {
   if (blocks.empty()) return HODLR_OK;
   for (const SkelBlock& b : blocks)
     if (b.m > kSideMax || b.nc > kSideMax) return fail(HODLR_EINVAL, "block side above 8192");
   DevBuf d;
-  HODLR_TRY(d.ensure(blocks.size() * sizeof(SkelBlock)));
-  HODLR_HIP(hipMemcpyAsync(d.p, blocks.data(), blocks.size() * sizeof(SkelBlock), hipMemcpyHostToDevice, s));
-  k_skel_features<<<dim3((unsigned)blocks.size(), 2), kFeatBlock, 0, s>>>(rowptr, col, xyz, K, ldk,
-                                                                         d.as<SkelBlock>(), feats, cnt_depth, dcount);
+  if (!d_blocks) {
+    HODLR_TRY(d.ensure(blocks.size() * sizeof(SkelBlock)));
+    HODLR_HIP(hipMemcpyAsync(d.p, blocks.data(), blocks.size() * sizeof(SkelBlock), hipMemcpyHostToDevice, s));
+    d_blocks = d.as<SkelBlock>();
+  }
+  k_skel_features<<<dim3((unsigned)blocks.size(), 2), kFeatBlock, 0, s>>>(rowptr, col, xyz, K, ldk, d_blocks,
+                                                                         feats, cnt_depth, dcount);
   HODLR_HIP(hipGetLastError());
-  d.release_after(s);  // the block table goes back to the cache once the kernel has read it
+  if (d.p) d.release_after(s);  // the block table goes back to the cache once the kernel has read it
   return HODLR_OK;
 }
 
