@@ -6,9 +6,8 @@
 // from the root down, its dofs are sorted by the coordinate of largest
 // extent (first axis on ties; equal keys keep their current order) and the
 // left child takes the first floor(len/2).  One workgroup sorts one node with
-// a bitonic sort of (key, position) pairs, which is stable by construction
-// because positions break ties; the pairs stay in registers except for the
-// strides that cross waves.
+// a stable LSD radix sort (four 8-bit passes) of monotone integer keys made
+// from the coordinates, through LDS.
 #include <algorithm>
 #include <cfloat>
 #include <climits>
@@ -25,124 +24,141 @@ namespace hodlr {
 constexpr int kRcbMax = 16384;
 constexpr int kRcbThreads = 1024;
 
-// (k, p) becomes the smaller (take_min) or the larger of itself and (ko, po)
-// in the order "key, then position".
-__device__ __forceinline__ void rcb_pick(float& k, int& p, float ko, int po, bool take_min) {
-  const bool o_less = (ko < k) | ((ko == k) & (po < p));
-  const bool take = take_min ? o_less : !o_less;
-  k = take ? ko : k;
-  p = take ? po : p;
+// Sort key of a coordinate: the float's bits made monotone as an unsigned
+// integer (negative values bit-inverted, the sign bit set on the others), with
+// -0 taken as +0 and every NaN as one value above +inf, so that integer order
+// is the order of the values and equal values (and all NaNs, last) keep their
+// positions, as a stable sort by value does.
+__device__ __forceinline__ unsigned rcb_key(float x) {
+  unsigned u = __float_as_uint(x);
+  if (u == 0x80000000u) u = 0u;
+  if ((u & 0x7fffffffu) > 0x7f800000u) return 0xfffffffeu;
+  return (u & 0x80000000u) ? ~u : (u | 0x80000000u);
 }
 
-// Bitonic sort of P (a power of two, <= 1024 E) (key, position) pairs held
-// E per thread: element e = t E + r.  Strides below E stay in registers,
-// strides below 64 E pair lanes of one wave, larger strides go through LDS.
+// Stable LSD radix sort (four passes of 8-bit digits) of the node's keys,
+// followed by perm(l0 + e) <- perm(l0 + position of the e-th smallest).
+// Positions are laid out wave-major: wave w holds positions w 64 E + 64 r +
+// lane (r < E), so a wave's elements are contiguous and each of its E rows
+// is in lane order.  Padding positions (>= len) take the key 0xffffffff and
+// stay behind every real key.  A pass: each wave ranks its elements by digit
+// row by row (lanes of equal digit found by eight ballots; the wave's running
+// count per digit in LDS), one scan over (digit, wave) gives every group its
+// first destination, and the elements are scattered through LDS.
 template <int E>
-__device__ void rcb_sort(float (&key)[E], int (&pos)[E], int P, float* skey, int* spos) {
-  const int t = threadIdx.x;
-  const bool live = t * E < P;
-  for (int k = 2; k <= P; k <<= 1) {
-    for (int j = k >> 1; j > 0; j >>= 1) {
-      if (j < E) {
+__device__ void rcb_radix_node(const float* __restrict__ coords, int* __restrict__ perm, int l0, int len, int ax,
+                               unsigned* sk, int* sv, int* cnt, int* wsum) {
+  constexpr int kW = kRcbThreads / 64;  // waves
+  const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+  const unsigned long long below = (1ull << lane) - 1ull;
+  unsigned key[E];
+  int val[E];
+  {
+    int v[E];
 #pragma unroll
-        for (int jj = E / 2; jj >= 1; jj >>= 1) {
-          if (jj != j) continue;
+    for (int r = 0; r < E; ++r) v[r] = perm[l0 + min(w * 64 * E + 64 * r + lane, len - 1)];
 #pragma unroll
-          for (int r = 0; r < E; ++r) {
-            const int rr = r ^ jj;
-            if (rr < r) continue;
-            const bool up = (((t * E + r) & k) == 0);
-            const float ka = key[r], kb = key[rr];
-            const int pa = pos[r], pb = pos[rr];
-            const bool a_gt_b = (ka > kb) | ((ka == kb) & (pa > pb));
-            if (a_gt_b == up) {
-              key[r] = kb;
-              key[rr] = ka;
-              pos[r] = pb;
-              pos[rr] = pa;
-            }
-          }
-        }
-      } else if (j < 64 * E) {
-        const int m = j / E;  // partner lane: t ^ m
-        const bool lower = (t & m) == 0;
-#pragma unroll
-        for (int r = 0; r < E; ++r) {
-          const float ko = __shfl_xor(key[r], m, 64);
-          const int po = __shfl_xor(pos[r], m, 64);
-          const bool up = (((t * E + r) & k) == 0);
-          rcb_pick(key[r], pos[r], ko, po, lower == up);
-        }
-      } else {
-        if (live)
-#pragma unroll
-          for (int r = 0; r < E; ++r) {
-            skey[t * E + r] = key[r];
-            spos[t * E + r] = pos[r];
-          }
-        __syncthreads();
-        if (live)
-#pragma unroll
-          for (int r = 0; r < E; ++r) {
-            const int e = t * E + r, x = e ^ j;
-            const bool up = ((e & k) == 0);
-            rcb_pick(key[r], pos[r], skey[x], spos[x], ((e & j) == 0) == up);
-          }
-        __syncthreads();
-      }
+    for (int r = 0; r < E; ++r) {
+      const int e = w * 64 * E + 64 * r + lane;
+      const float c = coords[3 * (size_t)v[r] + ax];
+      key[r] = e < len ? rcb_key(c) : 0xffffffffu;
+      val[r] = e;
     }
   }
-}
-
-template <int E>
-__device__ void rcb_node(const float* __restrict__ coords, int* __restrict__ perm, int l0, int len, int P,
-                         int ax, float* skey, int* spos) {
-  const int t = threadIdx.x;
-  float key[E];
-  int pos[E];
-  // every load issued unconditionally (addresses clamped into the node), the
-  // vertex ids first, then their coordinates, so each batch is one round trip
-  int v[E];
+  for (int shift = 0; shift < 32; shift += 8) {
+    int* wc = cnt + w * 256;  // this wave's running counts per digit
 #pragma unroll
-  for (int r = 0; r < E; ++r) v[r] = perm[l0 + min(t * E + r, len - 1)];
+    for (int q = 0; q < 4; ++q) wc[lane + 64 * q] = 0;
+    int dst[E];
 #pragma unroll
-  for (int r = 0; r < E; ++r) key[r] = coords[3 * (size_t)v[r] + ax];
+    for (int r = 0; r < E; ++r) {
+      const unsigned d = (key[r] >> shift) & 255u;
+      unsigned long long m = ~0ull;
 #pragma unroll
-  for (int r = 0; r < E; ++r) {
-    const int e = t * E + r;
-    pos[r] = e < len ? e : INT_MAX;
-    key[r] = e < len ? key[r] : INFINITY;
+      for (int bit = 0; bit < 8; ++bit) {
+        const unsigned long long bal = __ballot((d >> bit) & 1u);
+        m &= ((d >> bit) & 1u) ? bal : ~bal;
+      }
+      const int base = wc[d];
+      const int lead = __ffsll((long long)m) - 1;
+      if (lane == lead) wc[d] = base + __popcll(m);
+      dst[r] = base + __popcll(m & below);  // rank among this wave's equal digits so far
+    }
+    __syncthreads();
+    // exclusive prefix over (digit, wave) in digit-major order: thread t takes
+    // entries 4 t .. 4 t + 3 (digit t / 4, waves 4 (t % 4) .. + 3)
+    {
+      const int d = t >> 2, w0 = (t & 3) * 4;
+      int c[4], tot = 0;
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        c[q] = cnt[(w0 + q) * 256 + d];
+        tot += c[q];
+      }
+      int inc = tot;  // inclusive scan of the thread totals within the wave
+#pragma unroll
+      for (int o = 1; o < 64; o <<= 1) {
+        const int y = __shfl_up(inc, o, 64);
+        if (lane >= o) inc += y;
+      }
+      if (lane == 63) wsum[w] = inc;
+      __syncthreads();
+      int before = 0;
+#pragma unroll
+      for (int k = 0; k < kW; ++k) before += k < w ? wsum[k] : 0;
+      int run = before + inc - tot;
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        cnt[(w0 + q) * 256 + d] = run;
+        run += c[q];
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < E; ++r) {
+      const int o = cnt[w * 256 + ((key[r] >> shift) & 255u)] + dst[r];
+      sk[o] = key[r];
+      sv[o] = val[r];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < E; ++r) {
+      const int e = w * 64 * E + 64 * r + lane;
+      key[r] = sk[e];
+      val[r] = sv[e];
+    }
+    __syncthreads();
   }
-  rcb_sort<E>(key, pos, P, skey, spos);
-  // perm(l0 + e) <- perm(l0 + pos(e)); the old entries go through LDS
-  int* old = spos;
+  // perm(l0 + e) <- perm(l0 + val(e)); the old entries go through LDS
+  int* old = sv;
+  {
+    int v[E];
 #pragma unroll
-  for (int r = 0; r < E; ++r) v[r] = perm[l0 + min(t + r * (int)blockDim.x, len - 1)];
+    for (int r = 0; r < E; ++r) v[r] = perm[l0 + min(t + r * kRcbThreads, len - 1)];
 #pragma unroll
-  for (int r = 0; r < E; ++r) {
-    const int e = t + r * (int)blockDim.x;
-    if (e < len) old[e] = v[r];
+    for (int r = 0; r < E; ++r)
+      if (t + r * kRcbThreads < len) old[t + r * kRcbThreads] = v[r];
   }
   __syncthreads();
 #pragma unroll
   for (int r = 0; r < E; ++r) {
-    const int e = t * E + r;
-    if (e < len && pos[r] < len) perm[l0 + e] = old[pos[r]];
+    const int e = w * 64 * E + 64 * r + lane;
+    if (e < len) perm[l0 + e] = old[val[r]];
   }
 }
 
 __global__ void __launch_bounds__(kRcbThreads)
     k_rcb_level(const float* __restrict__ coords, int* __restrict__ perm, const int* __restrict__ lo,
                 const int* __restrict__ hi, int id0) {
-  __shared__ float skey[kRcbMax];
+  __shared__ unsigned skey[kRcbMax];
   __shared__ int spos[kRcbMax];
+  __shared__ int scnt[kRcbThreads / 64 * 256];
+  __shared__ int swsum[kRcbThreads / 64];
   __shared__ float red[6][kRcbThreads / 64];
   __shared__ int s_axis;
   const int node = blockIdx.x, id = id0 + node, t = threadIdx.x, nt = blockDim.x;
   const int l0 = lo[id], len = hi[id] - l0;
   if (len <= 1) return;
-  int P = 1;
-  while (P < len) P <<= 1;
   float mn[3] = {FLT_MAX, FLT_MAX, FLT_MAX}, mx[3] = {-FLT_MAX, -FLT_MAX, -FLT_MAX};
   // batches of 8 entries per thread: the vertex ids, then their coordinates,
   // each batch of loads in flight together (addresses clamped into the node)
@@ -195,11 +211,11 @@ __global__ void __launch_bounds__(kRcbThreads)
   }
   __syncthreads();
   const int ax = s_axis;
-  if (P <= kRcbThreads) rcb_node<1>(coords, perm, l0, len, P, ax, skey, spos);
-  else if (P <= 2 * kRcbThreads) rcb_node<2>(coords, perm, l0, len, P, ax, skey, spos);
-  else if (P <= 4 * kRcbThreads) rcb_node<4>(coords, perm, l0, len, P, ax, skey, spos);
-  else if (P <= 8 * kRcbThreads) rcb_node<8>(coords, perm, l0, len, P, ax, skey, spos);
-  else rcb_node<16>(coords, perm, l0, len, P, ax, skey, spos);
+  if (len <= kRcbThreads) rcb_radix_node<1>(coords, perm, l0, len, ax, skey, spos, scnt, swsum);
+  else if (len <= 2 * kRcbThreads) rcb_radix_node<2>(coords, perm, l0, len, ax, skey, spos, scnt, swsum);
+  else if (len <= 4 * kRcbThreads) rcb_radix_node<4>(coords, perm, l0, len, ax, skey, spos, scnt, swsum);
+  else if (len <= 8 * kRcbThreads) rcb_radix_node<8>(coords, perm, l0, len, ax, skey, spos, scnt, swsum);
+  else rcb_radix_node<16>(coords, perm, l0, len, ax, skey, spos, scnt, swsum);
 }
 
 __global__ void k_iota(int* p, int n) {
