@@ -62,6 +62,28 @@ def test_rcb_bit_exact(case):
     assert np.array_equal(got, want)
 
 
+@pytest.mark.parametrize("case", ["signed_zeros", "negative_ties", "large_node"])
+def test_rcb_sort_keys_bit_exact(case):
+    """The sort keys of the ordering: -0.0 equals +0.0 and keeps positions,
+    negative and positive values interleave correctly, and equal keys stay in
+    order in a node of the largest size, as the oracle's stable argsort does."""
+    rng = np.random.default_rng(11)
+    if case == "signed_zeros":
+        coords = rng.choice(np.array([-0.0, 0.0, -1.0, 1.0, -0.5], dtype=np.float32), size=(1500, 3))
+        leaf = 7
+    elif case == "negative_ties":
+        coords = (rng.integers(-4, 5, size=(3000, 3)) * 0.25).astype(np.float32)
+        leaf = 40
+    else:
+        coords = rng.integers(0, 3, size=(16384, 3)).astype(np.float32)
+        coords[:, 0] += rng.standard_normal(16384).astype(np.float32) * 1e-3
+        leaf = 4096
+    say("rcb keys", case, coords.shape)
+    want = ordering.rcb_permutation(coords, leaf)
+    got = H.hodlr_order_rcb(torch.from_numpy(coords).cuda(), leaf).cpu().numpy()
+    assert np.array_equal(got, want)
+
+
 def test_permute_rows_bit_exact():
     rng = np.random.default_rng(3)
     for n, w in ((1, 3), (1000, 3), (517, 8), (64, 16)):
