@@ -468,36 +468,41 @@ __global__ void __launch_bounds__(kBlock)
     k_bdlr_gather(const double* __restrict__ K, int ldk, const BdlrTask* __restrict__ tasks,
                   const int* __restrict__ piv, const int* __restrict__ rank_task, T* __restrict__ cg,
                   T* __restrict__ Ucap, T* __restrict__ Vcap, int ldu, const int* __restrict__ skip) {
+  __shared__ int spv[SKEL];  // the side's pivots, read once per workgroup
   const int task = blockIdx.x, side = blockIdx.z, t = threadIdx.x;
   if (skip && skip[task]) return;
   const BdlrTask tk = tasks[task];
   const int r = rank_task[task];
   const int len = side == 0 ? tk.m : tk.nc;
+  if ((int)blockIdx.y * kBlock >= len) return;  // (uniform)
   const int i = blockIdx.y * kBlock + t;
-  if (i >= len) return;
-  {  // the factor columns past the rank are zero (an earlier attempt may have written them)
+  const bool act = i < len;
+  if (act) {  // the factor columns past the rank are zero (an earlier attempt may have written them)
     T* z = (side == 0 ? Ucap + tk.row0 : Vcap + tk.col0) + (size_t)tk.capcol * ldu + i;
     for (int l = r; l < tk.kmax; ++l) z[(size_t)l * ldu] = T(0);
   }
-  if (r == 0) return;
+  if (r == 0) return;  // (uniform)
+  const int* pv = piv + tk.sel_off + (side == 0 ? SKEL : 0);
+  for (int l = t; l < r; l += kBlock) spv[l] = pv[l];
+  __syncthreads();
+  if (!act) return;
   T* out = side == 0 ? cg + tk.cg_off : Vcap + (size_t)tk.capcol * ldu + tk.col0;
   const int ldo = side == 0 ? len : ldu;
-  const int* pv = piv + tk.sel_off + (side == 0 ? SKEL : 0);
-  for (int l0 = 0; l0 < r; l0 += 8) {
-    T v[8];
+  // side 0 reads column pcol_l from row row0 + i, side 1 row prow_l from
+  // column col0 + i; kB entries per batch with their loads in flight together
+  // (the pivot index clamped into the rank, the store only below it)
+  const double* base = side == 0 ? K + tk.row0 + i : K + (size_t)(tk.col0 + i) * ldk + tk.row0;
+  const size_t stride = side == 0 ? (size_t)ldk : 1;
+  constexpr int kB = 16;
+  for (int l0 = 0; l0 < r; l0 += kB) {
+    T v[kB];
 #pragma unroll
-    for (int u = 0; u < 8; ++u) {
-      const int l = l0 + u;
-      if (l < r) {
-        const int p = pv[l];
-        v[u] = side == 0 ? (T)K[(size_t)(tk.col0 + p) * ldk + tk.row0 + i]
-                         : (T)K[(size_t)(tk.col0 + i) * ldk + tk.row0 + p];
-      } else {
-        v[u] = T(0);
-      }
+    for (int u = 0; u < kB; ++u) {
+      const int p = spv[min(l0 + u, r - 1)];
+      v[u] = (T)base[(size_t)(side == 0 ? tk.col0 + p : p) * stride];
     }
 #pragma unroll
-    for (int u = 0; u < 8; ++u)
+    for (int u = 0; u < kB; ++u)
       if (l0 + u < r) out[i + (size_t)(l0 + u) * ldo] = v[u];
   }
 }
