@@ -907,14 +907,35 @@ __global__ void k_skel_err(const BdlrTask* __restrict__ tasks, int ntask, const 
   const int x = blockIdx.x * blockDim.x + threadIdx.x;
   if (x >= ntask || (skip && skip[x])) return;
   const BdlrTask tk = tasks[x];
+  // both sides' chunk sums (adjacent in part) in chunk order, kB chunks per
+  // batch with their loads in flight together (addresses clamped into range)
+  constexpr int kB = 16;
+  double num[2] = {0.0, 0.0};
+  const double2* pp = reinterpret_cast<const double2*>(part) + (size_t)x * nch;
+  for (int c0 = 0; c0 < nch; c0 += kB) {
+    double2 v[kB];
+#pragma unroll
+    for (int u = 0; u < kB; ++u) v[u] = pp[min(c0 + u, nch - 1)];
+#pragma unroll
+    for (int u = 0; u < kB; ++u)
+      if (c0 + u < nch) {
+        num[0] += v[u].x;
+        num[1] += v[u].y;
+      }
+  }
+  int used[2] = {0, 0};
+  for (int q0 = 0; q0 < 2 * ns; q0 += kB) {
+    int sv[kB];
+#pragma unroll
+    for (int u = 0; u < kB; ++u) sv[u] = samp[(size_t)x * 2 * ns + min(q0 + u, 2 * ns - 1)];
+#pragma unroll
+    for (int u = 0; u < kB; ++u)
+      if (q0 + u < 2 * ns) used[(q0 + u) / ns] += sv[u] >= 0;
+  }
   double est = 0.0;
   for (int side = 0; side < 2; ++side) {
-    double num = 0.0;
-    for (int c = 0; c < nch; ++c) num += part[((size_t)x * nch + c) * 2 + side];
-    int used = 0;
-    for (int q = 0; q < ns; ++q) used += samp[(size_t)x * 2 * ns + side * ns + q] >= 0;
     const int outside = (side == 0 ? tk.m : tk.nc) - counts[2 * x + side];
-    if (used > 0) est = fmax(est, num * (double)outside / (double)used);
+    if (used[side] > 0) est = fmax(est, num[side] * (double)outside / (double)used[side]);
   }
   const double nb = norm2[tk.task];  // the block's total (k_norm_total)
   err[x] = nb > 0.0 ? sqrt(est / nb) : sqrt(est);
@@ -1225,14 +1246,35 @@ __global__ void k_err_decide(const BdlrTask* __restrict__ tasks, int nt, const i
   const int x = blockIdx.x * blockDim.x + threadIdx.x;
   if (x >= nt || state[x] != 0) return;
   const BdlrTask tk = tasks[x];
+  // both sides' chunk sums (adjacent in part) in chunk order, kB chunks per
+  // batch with their loads in flight together (addresses clamped into range)
+  constexpr int kB = 16;
+  double num[2] = {0.0, 0.0};
+  const double2* pp = reinterpret_cast<const double2*>(part) + (size_t)x * nch;
+  for (int c0 = 0; c0 < nch; c0 += kB) {
+    double2 v[kB];
+#pragma unroll
+    for (int u = 0; u < kB; ++u) v[u] = pp[min(c0 + u, nch - 1)];
+#pragma unroll
+    for (int u = 0; u < kB; ++u)
+      if (c0 + u < nch) {
+        num[0] += v[u].x;
+        num[1] += v[u].y;
+      }
+  }
+  int used[2] = {0, 0};
+  for (int q0 = 0; q0 < 2 * ns; q0 += kB) {
+    int sv[kB];
+#pragma unroll
+    for (int u = 0; u < kB; ++u) sv[u] = samp[(size_t)x * 2 * ns + min(q0 + u, 2 * ns - 1)];
+#pragma unroll
+    for (int u = 0; u < kB; ++u)
+      if (q0 + u < 2 * ns) used[(q0 + u) / ns] += sv[u] >= 0;
+  }
   double est = 0.0;
   for (int side = 0; side < 2; ++side) {
-    double num = 0.0;
-    for (int c = 0; c < nch; ++c) num += part[((size_t)x * nch + c) * 2 + side];
-    int used = 0;
-    for (int q = 0; q < ns; ++q) used += samp[(size_t)x * 2 * ns + side * ns + q] >= 0;
     const int outside = (side == 0 ? tk.m : tk.nc) - counts[2 * x + side];
-    if (used > 0) est = fmax(est, num * (double)outside / (double)used);
+    if (used[side] > 0) est = fmax(est, num[side] * (double)outside / (double)used[side]);
   }
   const double nb = norm2[tk.task];
   const double e = nb > 0.0 ? sqrt(est / nb) : sqrt(est);
