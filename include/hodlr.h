@@ -166,6 +166,27 @@ int hodlr_build_from_factors(int n, int leaf, int precision, const double* leave
  * ESINGULAR (message names the node). */
 int hodlr_factor(hodlr_t h, hipStream_t stream);
 
+/* hodlr_factor without the synchronization: the same launches (the same
+ * results, bit for bit), queued on the stream, and the handle counts as
+ * factorized at once.  The status words are copied behind the factorization
+ * into pinned host memory that the handle keeps.  A singular leaf or
+ * capacitance matrix is then reported (ESINGULAR, as hodlr_factor reports
+ * it, after which the handle is no longer factorized) by the next call that
+ * waits on the handle: hodlr_factor_wait, or gmres_solve / cg_solve /
+ * gmres_solve_noalloc with the handle as preconditioner, at their first
+ * synchronization and before their first preconditioner application.
+ * hodlr_solve and the solvers order their work behind the factorization
+ * (an event), also on other streams.  For callers whose next step is a
+ * solve: the host prepares it while the GPU still factorizes.
+ * Errors here: EINVAL (NULL or already factorized handle), ESINGULAR for a
+ * singular leaf found by the build, ENOMEM, EHIP. */
+int hodlr_factor_async(hodlr_t h, hipStream_t stream);
+
+/* Waits for a factorization queued by hodlr_factor_async and returns its
+ * status (HODLR_OK, or ESINGULAR naming the node); HODLR_OK at once when
+ * none is pending (already settled, or hodlr_factor).  EINVAL on NULL. */
+int hodlr_factor_wait(hodlr_t h);
+
 /* hodlr_factor for nh handles at once (a batch of fronts, e.g. the
  * separators of a nested-dissection tree): every front's factorization is
  * recorded on its own stream into one HIP graph, which is launched once, so
@@ -179,7 +200,9 @@ int hodlr_factor_batched(hodlr_t* hs, int nh, hipStream_t stream);
  *   B, X    device, n x nrhs, leading dimensions ldb, ldx >= n; element
  *           type float (precision 32) or double (precision 64).  X may alias
  *           B (ldx == ldb).
- * Requires hodlr_factor.  Asynchronous.  Errors: EINVAL, ENOMEM, EHIP. */
+ * Requires hodlr_factor (or hodlr_factor_async: a singular block found
+ * there is reported by hodlr_factor_wait, not here).  Asynchronous.
+ * Errors: EINVAL, ENOMEM, EHIP. */
 int hodlr_solve(hodlr_t h, const void* B, int nrhs, int ldb, void* X, int ldx,
                 hipStream_t stream);
 

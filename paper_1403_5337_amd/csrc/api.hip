@@ -440,6 +440,23 @@ class Workers {
   unsigned long long generation_ = 0;
 };
 
+// ESINGULAR for the status words of a factorization (0: flag, 1: node).
+int singular_status(const int* st) {
+  return fail(HODLR_ESINGULAR, st[0] == 1 ? "singular leaf block " + std::to_string(st[1])
+                                          : "singular capacitance matrix at node " + std::to_string(st[1]));
+}
+
+int settle_factor_status(hodlr_s* h) {
+  if (!h->status_pending) return HODLR_OK;
+  HODLR_HIP(hipEventSynchronize(h->status_ev));
+  h->status_pending = false;
+  if (h->pin_status[0]) {
+    h->factored = false;
+    return singular_status(h->pin_status);
+  }
+  return HODLR_OK;
+}
+
 }  // namespace hodlr
 
 using namespace hodlr;
@@ -706,10 +723,15 @@ int hodlr_build_from_factors(int n, int leaf, int precision, const double* leave
   return HODLR_OK;
 }
 
-int hodlr_factor(hodlr_t h, hipStream_t stream) {
+static int factor_checks(hodlr_t h) {
   if (!h) return fail(HODLR_EINVAL, "handle is NULL");
   if (h->factored) return fail(HODLR_EINVAL, "handle is already factorized");
   if (h->leaf_singular >= 0) return fail(HODLR_ESINGULAR, "singular leaf block " + std::to_string(h->leaf_singular));
+  return HODLR_OK;
+}
+
+int hodlr_factor(hodlr_t h, hipStream_t stream) {
+  HODLR_TRY(factor_checks(h));
   HODLR_TRY(factor_impl(h, stream));
   // the status words come back through pinned host memory, written by a
   // kernel behind the factorization, with one synchronization
@@ -727,13 +749,33 @@ int hodlr_factor(hodlr_t h, hipStream_t stream) {
   HODLR_HIP(hipGetLastError());
   HODLR_HIP(hipStreamSynchronize(stream));
   const int* st = static_cast<const int*>(pin);
-  if (st[0]) {
-    return fail(HODLR_ESINGULAR, st[0] == 1 ? "singular leaf block " + std::to_string(st[1])
-                                            : "singular capacitance matrix at node " +
-                                                  std::to_string(st[1]));
-  }
+  if (st[0]) return singular_status(st);
   h->factored = true;
   return HODLR_OK;
+}
+
+int hodlr_factor_async(hodlr_t h, hipStream_t stream) {
+  HODLR_TRY(factor_checks(h));
+  if (!h->pin_status) {
+    void* pin = nullptr;
+    HODLR_TRY(pinned_alloc(16 * sizeof(int), &pin, &h->pin_status_bytes));
+    h->pin_status = static_cast<int*>(pin);
+  }
+  if (!h->status_ev) HODLR_TRY(event_take(&h->status_ev));
+  HODLR_TRY(factor_impl(h, stream));
+  int* dpin = nullptr;
+  HODLR_HIP(hipHostGetDevicePointer(reinterpret_cast<void**>(&dpin), h->pin_status, 0));
+  k_export_ints<<<1, 64, 0, stream>>>(h->status.as<int>(), 4, h->status.as<int>(), nullptr, dpin);
+  HODLR_HIP(hipGetLastError());
+  HODLR_HIP(hipEventRecord(h->status_ev, stream));
+  h->factored = true;
+  h->status_pending = true;
+  return HODLR_OK;
+}
+
+int hodlr_factor_wait(hodlr_t h) {
+  if (!h) return fail(HODLR_EINVAL, "handle is NULL");
+  return settle_factor_status(h);
 }
 
 // one stream per front of a batch (default priority), kept for the process
@@ -854,6 +896,7 @@ int hodlr_solve(hodlr_t h, const void* B, int nrhs, int ldb, void* X, int ldx,
                 hipStream_t stream) {
   if (!h) return fail(HODLR_EINVAL, "handle is NULL");
   if (!h->factored) return fail(HODLR_EINVAL, "call hodlr_factor first");
+  if (h->status_pending) HODLR_HIP(hipStreamWaitEvent(stream, h->status_ev, 0));
   int n = h->tree.n;
   if (nrhs < 0) return fail(HODLR_EINVAL, "nrhs < 0");
   if (nrhs == 0) return HODLR_OK;

@@ -310,6 +310,8 @@ static int cg_t(const double* K, int n, int ldk, hodlr_s* M, const double* B, in
   int* act = ws.ints.as<int>();
   int* total = act + kCgMaxRhs;
   int* tstart = act + 2 * kCgMaxRhs;
+  // behind a factorization queued without waiting, possibly on another stream
+  if (M && M->status_pending) HODLR_HIP(hipStreamWaitEvent(st, M->status_ev, 0));
   HODLR_HIP(hipMemsetAsync(total, 0, s * sizeof(int), st));
   HODLR_HIP(hipMemsetAsync(tstart, 0xff, s * sizeof(int), st));  // -1: no cycle yet
   k_cg_bnorm<<<s, kCgThreads, 0, st>>>(n, B, ldb, bnorm);
@@ -321,6 +323,7 @@ static int cg_t(const double* K, int n, int ldk, hodlr_s* M, const double* B, in
                                               tol, maxit, ws.dev_flags);
     HODLR_HIP(hipGetLastError());
     HODLR_HIP(hipStreamSynchronize(st));
+    if (M) HODLR_TRY(settle_factor_status(M));  // (a factorization queued without waiting)
     bool any = false;
     for (int k = 0; k < s; ++k) any |= ws.host_flags[k] != 0;
     if (!any) break;

@@ -711,9 +711,36 @@ template <typename T>
 static int factor_t(hodlr_s* h, hipStream_t s) {
   const Tree& t = h->tree;  // (tree)
   const int n = t.n, L = t.L;
-  // every buffer is sized before the first launch: the sequence below has no
-  // allocation, synchronization or pageable copy, so it can be recorded into
-  // a graph (hodlr_factor_batched)
+  // The leaf work needs no batched-product table: it is queued first, so the
+  // GPU runs it while the host plans the products of every level.
+  k_fill_int<<<1, 64, 0, s>>>(h->status.as<int>(), 4, 0);
+  HODLR_HIP(hipGetLastError());
+  if (!h->leaves_inverted) {  // (the build may have run them beside the compression)
+    ProfScope prof_("leaf_inverse", s);
+    k_leaf_inverse<T><<<h->nleaf, gj_threads<T>(), 0, s>>>(h->Kinv.as<T>(), h->bmax, h->d_lo.as<int>(),
+                                                         h->d_hi.as<int>(), node_id(L, 0),
+                                                         h->status.as<int>());
+  }
+  HODLR_HIP(hipGetLastError());
+  if (L == 0 || h->R == 0) return HODLR_OK;
+  T* Y = h->Y.as<T>();
+  {
+    ProfScope prof_("leaf_apply", s);
+    const size_t lds = leaf_apply_mfma_lds(h->bmax);
+    if (sizeof(T) == 4 && lds <= 160 * 1024) {
+      HODLR_TRY(allow_lds(k_leaf_apply_mfma, lds));
+      k_leaf_apply_mfma<<<dim3(h->nleaf, cdiv(h->R, 64)), kBlock, lds, s>>>(
+          reinterpret_cast<const float*>(h->Kinv.p), h->bmax, h->d_lo.as<int>(), h->d_hi.as<int>(), node_id(L, 0),
+          reinterpret_cast<float*>(Y), n, h->R);
+    } else {
+      k_leaf_apply<T, kCT><<<dim3(h->nleaf, cdiv(h->R, kCT)), kBlock, 0, s>>>(
+          h->Kinv.as<T>(), h->bmax, h->d_lo.as<int>(), h->d_hi.as<int>(), node_id(L, 0), Y, n, h->R);
+    }
+  }
+  // every buffer is sized before the first product: the sequence below has
+  // no allocation, synchronization or pageable copy once the buffers are
+  // sized, so it can be recorded into a graph (hodlr_factor_batched, which
+  // sizes them first)
   if (L > 0 && h->R > 0) {
     HODLR_TRY(ensure_work(h, 64));
     size_t tb = 0, wb = 0;
@@ -740,30 +767,6 @@ static int factor_t(hodlr_s* h, hipStream_t s) {
   HODLR_TRY(gemm_upload(h, s));
   h->gemm_mode = kGemmReplay;
   h->gemm_rec_pos = 0;
-  k_fill_int<<<1, 64, 0, s>>>(h->status.as<int>(), 4, 0);
-  HODLR_HIP(hipGetLastError());
-  if (!h->leaves_inverted) {  // (the build may have run them beside the compression)
-    ProfScope prof_("leaf_inverse", s);
-    k_leaf_inverse<T><<<h->nleaf, gj_threads<T>(), 0, s>>>(h->Kinv.as<T>(), h->bmax, h->d_lo.as<int>(),
-                                                         h->d_hi.as<int>(), node_id(L, 0),
-                                                         h->status.as<int>());
-  }
-  HODLR_HIP(hipGetLastError());
-  if (L == 0 || h->R == 0) return HODLR_OK;
-  T* Y = h->Y.as<T>();
-  {
-    ProfScope prof_("leaf_apply", s);
-    const size_t lds = leaf_apply_mfma_lds(h->bmax);
-    if (sizeof(T) == 4 && lds <= 160 * 1024) {
-      HODLR_TRY(allow_lds(k_leaf_apply_mfma, lds));
-      k_leaf_apply_mfma<<<dim3(h->nleaf, cdiv(h->R, 64)), kBlock, lds, s>>>(
-          reinterpret_cast<const float*>(h->Kinv.p), h->bmax, h->d_lo.as<int>(), h->d_hi.as<int>(), node_id(L, 0),
-          reinterpret_cast<float*>(Y), n, h->R);
-    } else {
-      k_leaf_apply<T, kCT><<<dim3(h->nleaf, cdiv(h->R, kCT)), kBlock, 0, s>>>(
-          h->Kinv.as<T>(), h->bmax, h->d_lo.as<int>(), h->d_hi.as<int>(), node_id(L, 0), Y, n, h->R);
-    }
-  }
   HODLR_HIP(hipGetLastError());
   HODLR_TRY(factor_levels<T>(h, s, false));
   if (h->gemm_rec_pos != h->gemm_recs.size()) return fail(HODLR_EINVAL, "batched products replayed out of step");

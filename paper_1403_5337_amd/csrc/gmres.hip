@@ -29,6 +29,7 @@ constexpr int kRowsPerWG = 256;
 constexpr int kMatvecCols = 128;     // default columns of K per workgroup (split-K)
 constexpr int kMatvecColsMin = 64;   // narrowest split the tuner tries (sizes the partial sums)
 constexpr int kMaxRestart = 512;
+constexpr int kFlagInts = 384;       // host-visible flag block (layout at GmresPtrs::dev_flags)
 
 // part[(sp s + k) n + i] = sum over the columns c of split sp of K(i, c)
 // src(c, k), with the matrix cores doing the multiply-adds.  Wave w of
@@ -397,6 +398,10 @@ __global__ void k_cycle_init(int s, int m, int nch, const double* __restrict__ n
   const double rr = bnorm[k] > 0.0 ? beta / bnorm[k] : 0.0;
   relres[k] = rr;
   const int go = (bnorm[k] > 0.0) && (rr > tol) && (total[k] < maxit) && (beta > 0.0);
+  // the steps so far and the true relative residual, beside the flag: after
+  // the cycle start that stops every column they are the call's results
+  host_slot[192 + k] = total[k];
+  reinterpret_cast<double*>(host_slot + 256)[k] = rr;
   active[k] = go;
   steps[k] = 0;
   tstart[k] = total[k];
@@ -471,7 +476,8 @@ struct GmresPtrs {
   double *V, *w, *part, *hA, *hB, *hcol, *H, *cs, *sn, *g, *grun, *y, *npart, *scal, *bnorm, *relres;
   void* Z;
   int* ints;
-  int* dev_flags;  // 192 ints: [0, 64) cycle start, [64, 192) two step slots
+  int* dev_flags;  // kFlagInts ints: [0, 64) cycle start, [64, 192) two step slots,
+                   // [192, 256) steps taken, [256, 384) relative residuals (double)
 };
 
 static size_t gmres_layout(int n, int s, int m, size_t zsize, bool precond, unsigned char* base, GmresPtrs* p) {
@@ -502,7 +508,7 @@ static size_t gmres_layout(int n, int s, int m, size_t zsize, bool precond, unsi
   t.bnorm = static_cast<double*>(take(s * sizeof(double)));
   t.relres = static_cast<double*>(take(s * sizeof(double)));
   t.ints = static_cast<int*>(take(5 * 64 * sizeof(int)));
-  t.dev_flags = static_cast<int*>(take(192 * sizeof(int)));
+  t.dev_flags = static_cast<int*>(take(kFlagInts * sizeof(int)));
   if (p) *p = t;
   return off;
 }
@@ -636,7 +642,7 @@ static int gmres_t(const double* K, int n, int ldk, hodlr_s* M, const double* B,
   const size_t need = gmres_layout(n, s, m, sizeof(TP), M != nullptr, nullptr, nullptr);
   GmresPtrs wp{};
   int* host_flags = nullptr;
-  int local_flags[192];
+  int local_flags[kFlagInts];
   hipEvent_t ev[2] = {nullptr, nullptr};
   if (noalloc) {
     if (need > kNoallocScratchBytes)
@@ -651,7 +657,7 @@ static int gmres_t(const double* K, int n, int ldk, hodlr_s* M, const double* B,
     HODLR_TRY(ws.arena.ensure(need));
     gmres_layout(n, s, m, sizeof(TP), M != nullptr, ws.arena.as<unsigned char>(), &wp);
     if (!ws.host_flags) {
-      HODLR_HIP(hipHostMalloc(reinterpret_cast<void**>(&ws.host_flags), 192 * sizeof(int)));
+      HODLR_HIP(hipHostMalloc(reinterpret_cast<void**>(&ws.host_flags), kFlagInts * sizeof(int)));
       HODLR_HIP(hipHostGetDevicePointer(reinterpret_cast<void**>(&ws.dev_flags), ws.host_flags, 0));
     }
     for (int e = 0; e < 2; ++e)
@@ -690,6 +696,8 @@ static int gmres_t(const double* K, int n, int ldk, hodlr_s* M, const double* B,
   int* total = act[0] + 192;
   int* tstart = act[0] + 256;
   double* grun[2] = {wp.grun, wp.grun + 64};
+  // behind a factorization queued without waiting, possibly on another stream
+  if (M && M->status_pending) HODLR_HIP(hipStreamWaitEvent(st, M->status_ev, 0));
   HODLR_HIP(hipMemsetAsync(total, 0, s * sizeof(int), st));
 
   const dim3 gch(nch, s), gvec((n + kBlock - 1) / kBlock, s);
@@ -708,6 +716,9 @@ static int gmres_t(const double* K, int n, int ldk, hodlr_s* M, const double* B,
     HODLR_HIP(hipGetLastError());
     HODLR_HIP(hipStreamSynchronize(st));
     HODLR_TRY(fetch(0, s));
+    // a factorization queued without waiting reports a singular block here,
+    // before the first preconditioner application is queued
+    if (M) HODLR_TRY(settle_factor_status(M));
     bool any = false;
     for (int k = 0; k < s; ++k) any |= host_flags[k] != 0;
     if (!any) break;
@@ -770,12 +781,14 @@ static int gmres_t(const double* K, int n, int ldk, hodlr_s* M, const double* B,
       k_xupdate<double><<<gvec, kBlock, 0, st>>>(n, s, m, X, ldx, V, wp.y, steps);
     HODLR_HIP(hipGetLastError());
   }
-  HODLR_HIP(hipMemcpyAsync(relres, wp.relres, s * sizeof(double), hipMemcpyDeviceToHost, st));
-  HODLR_HIP(hipMemcpyAsync(host_flags, total, s * sizeof(int), hipMemcpyDeviceToHost, st));
-  HODLR_HIP(hipStreamSynchronize(st));
+  // the loop ends after a synchronized cycle start, which wrote the steps
+  // and residuals to the pinned block (copied back here without it)
+  HODLR_TRY(fetch(192, 192));
+  const double* rr = reinterpret_cast<const double*>(host_flags + 256);
   bool conv = true;
   for (int k = 0; k < s; ++k) {
-    iters[k] = host_flags[k];
+    iters[k] = host_flags[192 + k];
+    relres[k] = rr[k];
     conv &= relres[k] <= tol;
   }
   if (!conv) return fail(HODLR_ENOCONV, "GMRES reached maxit above tol");

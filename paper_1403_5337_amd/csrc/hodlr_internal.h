@@ -147,15 +147,30 @@ struct hodlr_s {
   bool leaves_inverted = false;  // the build already inverted the leaf blocks
   int leaf_singular = -1;        // node id of a singular leaf found by the build
   bool factored = false;
+  // hodlr_factor_async: the status words go to pinned memory behind the
+  // factorization (status_ev recorded after them) and are read by the next
+  // call that waits on the handle (settle_factor_status)
+  bool status_pending = false;
+  int* pin_status = nullptr;
+  size_t pin_status_bytes = 0;
+  hipEvent_t status_ev = nullptr;
   hodlr_s() = default;
   hodlr_s(const hodlr_s&) = delete;
   hodlr_s& operator=(const hodlr_s&) = delete;
   ~hodlr_s() {
     if (gemm_host) hodlr::pinned_free(gemm_host, gemm_host_bytes);
+    if (pin_status) hodlr::pinned_free(pin_status, pin_status_bytes);
+    if (status_ev) hodlr::event_give(status_ev);
   }
 };
 
 namespace hodlr {
+
+// A factorization queued by hodlr_factor_async: waits for its status words
+// (status_ev) and returns ESINGULAR as hodlr_factor does (the handle is then
+// no longer factorized); HODLR_OK when nothing is pending (api.hip).
+int settle_factor_status(hodlr_s* h);
+int singular_status(const int* st);
 
 // ---------------------------------------------------------------------------
 // Kernel launchers (one translation unit each)

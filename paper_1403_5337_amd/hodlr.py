@@ -56,6 +56,8 @@ _SIGNATURES = {
     "hodlr_build_from_factors": (ctypes.c_int, [ctypes.c_int, ctypes.c_int, ctypes.c_int, _vp, _vp, _vp,
                                                 _c_int_p, _c_int_p, ctypes.c_int, _vp, ctypes.POINTER(_vp)]),
     "hodlr_factor": (ctypes.c_int, [_vp, _vp]),
+    "hodlr_factor_async": (ctypes.c_int, [_vp, _vp]),
+    "hodlr_factor_wait": (ctypes.c_int, [_vp]),
     "hodlr_factor_batched": (ctypes.c_int, [ctypes.POINTER(_vp), ctypes.c_int, _vp]),
     "hodlr_solve": (ctypes.c_int, [_vp, _vp, ctypes.c_int, ctypes.c_int, _vp, ctypes.c_int, _vp]),
     "gmres_solve": (ctypes.c_int, [_vp, ctypes.c_int, ctypes.c_int, _vp, _vp, ctypes.c_int, ctypes.c_int,
@@ -269,8 +271,18 @@ class Hodlr:
                                               _ptr(V), rk, rc, len(rcols), _stream(stream), ctypes.byref(h)))
         return cls(h, n, precision)
 
-    def factor(self, stream=None):
-        _check(lib().hodlr_factor(self._h, _stream(stream)))
+    def factor(self, stream=None, wait=True):
+        """wait=False: hodlr_factor_async (a singular block is reported by
+        wait() or by the next solver call that takes this preconditioner)."""
+        if wait:
+            _check(lib().hodlr_factor(self._h, _stream(stream)))
+        else:
+            _check(lib().hodlr_factor_async(self._h, _stream(stream)))
+        return self
+
+    def wait(self):
+        """hodlr_factor_wait: the status of a factorization queued with wait=False."""
+        _check(lib().hodlr_factor_wait(self._h))
         return self
 
     def solve(self, B: torch.Tensor, stream=None) -> torch.Tensor:

@@ -70,6 +70,8 @@ def test_argument_validation(L):
     assert L.hodlr_mlp_adam_step(p, p, 10, p, p, p, 0, 1e-3, 1.0, None, None) == H.HODLR_EINVAL
     assert L.hodlr_skel_info(None, None) == H.HODLR_EINVAL
     assert L.hodlr_factor(None, None) == H.HODLR_EINVAL
+    assert L.hodlr_factor_async(None, None) == H.HODLR_EINVAL
+    assert L.hodlr_factor_wait(None) == H.HODLR_EINVAL
     assert L.hodlr_solve(None, None, 1, 1, None, 1, None) == H.HODLR_EINVAL
     it = (ctypes.c_int * 1)()
     rr = (ctypes.c_double * 1)()

@@ -149,6 +149,61 @@ def test_singular_leaf_reported():
     assert e.value.status == H.HODLR_ESINGULAR
 
 
+def test_async_factor_matches_sync_bit_for_bit():
+    """hodlr_factor_async queues the same launches as hodlr_factor: solves
+    and preconditioned GMRES agree bit for bit, also when the solver runs on
+    another stream (it waits on the factorization's event)."""
+    f = fronts.tpfa_front((12, 10, 7), zs=3, sigma=1.0, seed=1)
+    Kd = f.K.cuda()
+    B = fronts.rhs(f.n, 2, seed=3).cuda()
+    for precision in (32, 64):
+        say("async factor", f.n, precision)
+        hs = H.Hodlr.build(Kd, leaf=64, tol=1e-6, precision=precision).factor()
+        ha = H.Hodlr.build(Kd, leaf=64, tol=1e-6, precision=precision).factor(wait=False)
+        Xs = hs.solve(B)
+        Xa = ha.solve(B)
+        assert torch.equal(Xs, Xa)
+        H.gmres_solve(Kd, B, hs, tol=1e-12, maxit=1000, restart=200)  # tunes the product split once
+        r_s = H.gmres_solve(Kd, B, hs, tol=1e-12, maxit=1000, restart=200)
+        ha2 = H.Hodlr.build(Kd, leaf=64, tol=1e-6, precision=precision)
+        side = torch.cuda.Stream()
+        torch.cuda.synchronize()
+        ha2.factor(wait=False)  # on the current stream; the solve below runs on `side`
+        with torch.cuda.stream(side):
+            r_a = H.gmres_solve(Kd, B, ha2, tol=1e-12, maxit=1000, restart=200)
+        torch.cuda.synchronize()
+        assert r_s[3] == r_a[3] == H.HODLR_OK and r_s[1] == r_a[1] and r_s[2] == r_a[2]
+        assert torch.equal(r_s[0], r_a[0])
+        ha2.wait()  # settled by the solve: nothing pending
+        for h in (hs, ha, ha2):
+            h.close()
+
+
+def test_async_factor_reports_singular_at_the_next_wait():
+    fac = factors.random_hodlr(64, 16, [3, 3], seed=9)
+    lo, hi, blk = fac["leaves"][2]
+    blk[:, 3] = 0.0  # a zero column: singular leaf
+    P = pack_for_library(fac)
+    h = H.Hodlr.from_factors(64, 16, 32, P["leaves"], P["U"], P["V"], P["ranks"], P["rcols"])
+    h.factor(wait=False)  # queued: nothing is reported yet
+    with pytest.raises(H.HodlrError) as e:
+        h.wait()
+    assert e.value.status == H.HODLR_ESINGULAR and "leaf" in str(e.value)
+    h.wait()  # settled: nothing pending any more
+    with pytest.raises(H.HodlrError):
+        h.solve(torch.zeros(64, 1, device="cuda"))  # no longer factorized
+    h.close()
+    # the same block reported by GMRES before its first preconditioner application
+    h = H.Hodlr.from_factors(64, 16, 32, P["leaves"], P["U"], P["V"], P["ranks"], P["rcols"])
+    h.factor(wait=False)
+    K = torch.eye(64, dtype=torch.float64, device="cuda")
+    b = torch.ones(64, 1, dtype=torch.float64, device="cuda")
+    with pytest.raises(H.HodlrError) as e:
+        H.gmres_solve(K, b, h, tol=1e-12, maxit=10, restart=10)
+    assert e.value.status == H.HODLR_ESINGULAR
+    h.close()
+
+
 # ---------------------------------------------------------------------------
 # ACA compression (a2)
 # ---------------------------------------------------------------------------
