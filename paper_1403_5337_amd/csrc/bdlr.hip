@@ -1629,11 +1629,16 @@ static int learned_t(hodlr_s* h, const double* K, int ldk, const int* rowptr, co
       groups.push_back({x0, x1 - x0, ms, s});
     }
   }
-  struct Join {  // waits for the side stream on every return (the scratch outlives its work)
+  // The guards below wait for the streams on every return, so the scratch
+  // and the pinned block outlive their work; "synced" skips the wait when a
+  // read-back has just synchronized the build stream behind the side
+  // stream's join and nothing was queued since.
+  struct Join {
     hipStream_t side = nullptr;
     hipEvent_t e[4] = {nullptr, nullptr, nullptr, nullptr};
+    bool synced = false;
     ~Join() {
-      if (side) (void)hipStreamSynchronize(side);
+      if (side && !synced) (void)hipStreamSynchronize(side);
       for (auto x : e) event_give(x);
     }
   } join;
@@ -1650,11 +1655,12 @@ static int learned_t(hodlr_s* h, const double* K, int ldk, const int* rowptr, co
     void* p;
     size_t b;
     hipStream_t s;
+    bool synced;
     ~PinGuard() {
-      (void)hipStreamSynchronize(s);  // (a no-op after the read-back)
+      if (!synced) (void)hipStreamSynchronize(s);
       pinned_free(p, b);
     }
-  } pin_guard{pin, pin_bytes, s};
+  } pin_guard{pin, pin_bytes, s, false};
   unsigned char* const pin_up = static_cast<unsigned char*>(pin);
   unsigned char* const pin_blk = pin_up + ub;
   int* const pin_rb = reinterpret_cast<int*>(pin_blk + bb);
@@ -1695,6 +1701,7 @@ static int learned_t(hodlr_s* h, const double* K, int ldk, const int* rowptr, co
     HODLR_HIP(hipStreamWaitEvent(s, join.e[2], 0));
   }
   auto queue = [&](int a0, int a1) -> int {
+    join.synced = pin_guard.synced = false;
     for (int attempt = a0; attempt < a1; ++attempt)
       for (const Group& g : groups) {
         const AttemptView v = attempt_view(sc, g.x0);
@@ -1729,6 +1736,7 @@ static int learned_t(hodlr_s* h, const double* K, int ldk, const int* rowptr, co
   auto read_back = [&]() -> int {
     HODLR_HIP(hipMemcpyAsync(pin_rb, dstate, 2 * nt * sizeof(int), hipMemcpyDeviceToHost, s));
     HODLR_HIP(hipStreamSynchronize(s));
+    join.synced = pin_guard.synced = true;
     const int* hp = pin_rb;
     std::copy(hp, hp + nt, state.begin());
     std::copy(hp + nt, hp + 2 * nt, kused.begin());
@@ -1744,6 +1752,7 @@ static int learned_t(hodlr_s* h, const double* K, int ldk, const int* rowptr, co
   for (int x = 0; x < nt; ++x)
     if (state[x] == 2) nodes.push_back(tasks[x].node);
   if (!nodes.empty()) {
+    join.synced = pin_guard.synced = false;
     // fallback: ACA on the failed blocks into panels of their own; the block
     // keeps whichever of the two approximations has the smaller estimate
     int C = 0;

@@ -387,7 +387,9 @@ size_t gemm_table_bound(int ntasks) {
 
 int gemm_prepare(hodlr_s* h, size_t tab_bytes, size_t work_bytes, hipStream_t s) {
   if (h->gemm_tab.bytes < tab_bytes || h->gemm_work.bytes < work_bytes || h->gemm_host_bytes < tab_bytes) {
-    HODLR_HIP(hipStreamSynchronize(s));
+    // a buffer being replaced may still be read by queued products (a
+    // handle's first factorization has none to replace)
+    if (h->gemm_tab.p || h->gemm_work.p || h->gemm_host) HODLR_HIP(hipStreamSynchronize(s));
     if (h->gemm_tab.bytes < tab_bytes) HODLR_TRY(h->gemm_tab.ensure(tab_bytes));
     if (h->gemm_work.bytes < work_bytes) HODLR_TRY(h->gemm_work.ensure(work_bytes));
     if (h->gemm_host_bytes < h->gemm_tab.bytes) {
