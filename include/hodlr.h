@@ -174,7 +174,7 @@ int hodlr_factor(hodlr_t h, hipStream_t stream);
  * it, after which the handle is no longer factorized) by the next call that
  * waits on the handle: hodlr_factor_wait, or gmres_solve / cg_solve /
  * gmres_solve_noalloc with the handle as preconditioner, at their first
- * synchronization and before their first preconditioner application.
+ * synchronization (they then return ESINGULAR; X holds no result).
  * hodlr_solve and the solvers order their work behind the factorization
  * (an event), also on other streams.  For callers whose next step is a
  * solve: the host prepares it while the GPU still factorizes.

@@ -705,6 +705,13 @@ static int gmres_t(const double* K, int n, int ldk, hodlr_s* M, const double* B,
   k_bnorm<<<1, 64, 0, st>>>(s, nch, wp.npart, wp.bnorm);
   HODLR_HIP(hipGetLastError());
 
+  // The first cycle's start is not waited for (except without pinned
+  // memory): its steps are queued at once, so the host prepares them while
+  // the GPU still runs the work queued before the call (a factorization
+  // queued without waiting, say).  The steps of a column that is not active
+  // do nothing, so the cycle start's flags are read with step 0's, behind its
+  // event.
+  bool defer = !noalloc;
   while (true) {
     // true residual of the current x, start of a cycle
     HODLR_TRY(matvec_cols<double>(K, ldk, n, X, ldx, s, part, st, &cols_d));
@@ -714,14 +721,24 @@ static int gmres_t(const double* K, int n, int ldk, hodlr_s* M, const double* B,
     k_cycle_init<<<1, 64, 0, st>>>(s, m, nch, wp.npart, wp.bnorm, wp.scal, wp.g, grun[0], wp.relres, active, steps,
                                    total, tstart, tol, maxit, wp.dev_flags);
     HODLR_HIP(hipGetLastError());
-    HODLR_HIP(hipStreamSynchronize(st));
-    HODLR_TRY(fetch(0, s));
-    // a factorization queued without waiting reports a singular block here,
-    // before the first preconditioner application is queued
-    if (M) HODLR_TRY(settle_factor_status(M));
-    bool any = false;
-    for (int k = 0; k < s; ++k) any |= host_flags[k] != 0;
-    if (!any) break;
+    // the cycle start's flags (and a singular block of a factorization
+    // queued without waiting) are read here, or behind step 0 when deferred
+    auto start_check = [&](bool* any) -> int {
+      if (M) HODLR_TRY(settle_factor_status(M));
+      *any = false;
+      for (int k = 0; k < s; ++k) *any |= host_flags[k] != 0;
+      return HODLR_OK;
+    };
+    const bool deferred = defer;
+    defer = false;
+    if (!deferred) {
+      HODLR_HIP(hipStreamSynchronize(st));
+      HODLR_TRY(fetch(0, s));
+      bool any;
+      HODLR_TRY(start_check(&any));
+      if (!any) break;
+    }
+    bool idle = false;  // a deferred start found no active column
     k_normalize<TP><<<gvec, kBlock, 0, st>>>(n, s, w, wp.scal, active, V, Z);
     for (int j = 0; j < m; ++j) {
       const double* src_d = V + (size_t)j * ns;
@@ -766,6 +783,18 @@ static int gmres_t(const double* K, int n, int ldk, hodlr_s* M, const double* B,
         continue;
       }
       HODLR_HIP(hipEventRecord(ev[j & 1], st));
+      if (deferred && (j == 1 || m == 1)) {
+        HODLR_HIP(hipEventSynchronize(ev[0]));
+        bool any = false;
+        const int rc = start_check(&any);
+        if (rc != HODLR_OK || !any) {
+          // the steps queued behind the start use the workspace: let them end
+          HODLR_HIP(hipStreamSynchronize(st));
+          if (rc != HODLR_OK) return rc;
+          idle = true;
+          break;
+        }
+      }
       if (j > 0) {
         HODLR_HIP(hipEventSynchronize(ev[(j - 1) & 1]));
         const int* prev = host_flags + 64 + 64 * ((j - 1) & 1);
@@ -774,6 +803,7 @@ static int gmres_t(const double* K, int n, int ldk, hodlr_s* M, const double* B,
         if (!more) break;
       }
     }
+    if (idle) break;
     k_trisolve<<<1, 64, 0, st>>>(s, m, wp.H, wp.g, steps, wp.y);
     if (M)
       k_xupdate<TP><<<gvec, kBlock, 0, st>>>(n, s, m, X, ldx, Z, wp.y, steps);

@@ -297,6 +297,25 @@ def test_gmres_restart_and_noconv():
     assert st == H.HODLR_ENOCONV and it == [3, 3] and min(rr) > 1e-12
 
 
+def test_gmres_converged_start_and_restart_one():
+    """An initial guess that already meets tol takes no step (the first
+    cycle's start is read behind its queued step 0, which then does nothing)
+    and X comes back unchanged; restart = 1 still converges."""
+    f = fronts.tpfa_front((12, 10, 7), zs=3, sigma=1.0, seed=1)
+    Kd = f.K.cuda()
+    b = fronts.rhs(f.n, 2, seed=2).cuda()
+    h = H.Hodlr.build(Kd, leaf=64, tol=1e-8, precision=64).factor(wait=False)
+    X, it, rr, st = H.gmres_solve(Kd, b, h, tol=1e-12, maxit=1000, restart=200)
+    assert st == H.HODLR_OK and max(rr) <= 1e-12 and min(it) >= 1
+    X0 = X.clone()
+    X2, it2, rr2, st2 = H.gmres_solve(Kd, b, h, X0=X0, tol=1e-12, maxit=1000, restart=200)
+    assert st2 == H.HODLR_OK and it2 == [0, 0] and max(rr2) <= 1e-12
+    assert torch.equal(X2, X0)
+    X3, it3, rr3, st3 = H.gmres_solve(Kd, b, h, tol=1e-12, maxit=1000, restart=1)
+    assert st3 == H.HODLR_OK and max(rr3) <= 1e-12
+    h.close()
+
+
 def _end_to_end(front, leaf, tol, precision, nrhs, device_gen=False):
     n = front.n
     Kd = front.K.cuda()
