@@ -451,8 +451,11 @@ int hodlr_mlp_grad(const float* feats, const float* labels, int N, const float* 
 int hodlr_mlp_adam_step(const float* feats, const float* labels, int N, float* params, float* m, float* v,
                         int step, float lr, float pos_weight, float* loss, hipStream_t stream);
 
-/* Frees the handle.  Synchronizes the device first (its device blocks go
- * back to the library's allocator cache for reuse). */
+/* Frees the handle; its device blocks go back to the library's allocator
+ * cache for reuse.  Work that the library's calls left queued on the
+ * handle's buffers (hodlr_solve, hodlr_factor_async, the end of a build, a
+ * solver's error return) is tracked by events: if one of them has not
+ * completed, the device is synchronized first; otherwise nothing waits. */
 int hodlr_destroy(hodlr_t h);
 
 /* Returns every cached device block to the HIP runtime (synchronizes the

@@ -446,6 +446,28 @@ int singular_status(const int* st) {
                                           : "singular capacitance matrix at node " + std::to_string(st[1]));
 }
 
+int mark_inflight(hodlr_s* h, hipStream_t s) {
+  size_t keep = 0;
+  for (hipEvent_t e : h->inflight) {
+    if (hipEventQuery(e) == hipSuccess)
+      event_give(e);
+    else
+      h->inflight[keep++] = e;
+  }
+  h->inflight.resize(keep);
+  (void)hipGetLastError();  // a not-ready query leaves no error behind
+  if (h->inflight.size() >= 16) {
+    HODLR_HIP(hipEventSynchronize(h->inflight.front()));
+    event_give(h->inflight.front());
+    h->inflight.erase(h->inflight.begin());
+  }
+  hipEvent_t e = nullptr;
+  HODLR_TRY(event_take(&e));
+  h->inflight.push_back(e);
+  HODLR_HIP(hipEventRecord(e, s));
+  return HODLR_OK;
+}
+
 int settle_factor_status(hodlr_s* h) {
   if (!h->status_pending) return HODLR_OK;
   HODLR_HIP(hipEventSynchronize(h->status_ev));
@@ -640,6 +662,7 @@ static int build_impl(const double* K, int n, int ldk, const int* g_rowptr, cons
     // the capped panels go back to the allocator once the repack has run
     Ucap.release_after(stream);
     Vcap.release_after(stream);
+    HODLR_TRY(mark_inflight(h.get(), stream));
     *out = h.release();
     return HODLR_OK;
   }
@@ -652,6 +675,7 @@ static int build_impl(const double* K, int n, int ldk, const int* g_rowptr, cons
     h->leaves_inverted = true;
     if (ls[0]) h->leaf_singular = ls[1];
   }
+  HODLR_TRY(mark_inflight(h.get(), stream));
   *out = h.release();
   return HODLR_OK;
 }
@@ -908,7 +932,8 @@ int hodlr_solve(hodlr_t h, const void* B, int nrhs, int ldb, void* X, int ldx,
   } else if (ldb != ldx) {
     return fail(HODLR_EINVAL, "aliased B and X need ldb == ldx");
   }
-  return apply_impl(h, X, ldx, nrhs, stream);
+  HODLR_TRY(apply_impl(h, X, ldx, nrhs, stream));
+  return mark_inflight(h, stream);
 }
 
 int gmres_solve(const double* K, int n, int ldk, hodlr_t precond, const double* B, int nrhs,
@@ -925,8 +950,11 @@ int gmres_solve(const double* K, int n, int ldk, hodlr_t precond, const double* 
     if (!precond->factored) return fail(HODLR_EINVAL, "preconditioner is not factorized");
     if (precond->tree.n != n) return fail(HODLR_EINVAL, "preconditioner size differs from n");
   }
-  return gmres_impl(K, n, ldk, precond, B, nrhs, ldb, X, ldx, tol, maxit, restart, iters, relres,
+  const int st = gmres_impl(K, n, ldk, precond, B, nrhs, ldb, X, ldx, tol, maxit, restart, iters, relres,
                     stream);
+  // (an error return may leave work queued behind the preconditioner)
+  if (precond && st != HODLR_OK && st != HODLR_ENOCONV) (void)mark_inflight(precond, stream);
+  return st;
 }
 
 int gmres_solve_noalloc(const double* K, int n, int ldk, hodlr_t precond, const double* B, int nrhs, int ldb,
@@ -948,7 +976,10 @@ int gmres_solve_noalloc(const double* K, int n, int ldk, hodlr_t precond, const 
     return fail(HODLR_EINVAL, "gmres_solve_noalloc: n x nrhs x (restart + 1) needs " + std::to_string(need) +
                                   " bytes of workspace, above the fixed " + std::to_string(gmres_noalloc_limit()) +
                                   " bytes");
-  return gmres_impl(K, n, ldk, precond, B, nrhs, ldb, X, ldx, tol, maxit, restart, iters, relres, stream, true);
+  const int st = gmres_impl(K, n, ldk, precond, B, nrhs, ldb, X, ldx, tol, maxit, restart, iters, relres, stream, true);
+  // (an error return may leave work queued behind the preconditioner)
+  if (precond && st != HODLR_OK && st != HODLR_ENOCONV) (void)mark_inflight(precond, stream);
+  return st;
 }
 
 int cg_solve(const double* K, int n, int ldk, hodlr_t precond, const double* B, int nrhs, int ldb, double* X,
@@ -964,7 +995,10 @@ int cg_solve(const double* K, int n, int ldk, hodlr_t precond, const double* B, 
     if (!precond->factored) return fail(HODLR_EINVAL, "preconditioner is not factorized");
     if (precond->tree.n != n) return fail(HODLR_EINVAL, "preconditioner size differs from n");
   }
-  return cg_impl(K, n, ldk, precond, B, nrhs, ldb, X, ldx, tol, maxit, iters, relres, stream);
+  const int st = cg_impl(K, n, ldk, precond, B, nrhs, ldb, X, ldx, tol, maxit, iters, relres, stream);
+  // (an error return may leave work queued behind the preconditioner)
+  if (precond && st != HODLR_OK && st != HODLR_ENOCONV) (void)mark_inflight(precond, stream);
+  return st;
 }
 
 int hodlr_build_batched(int nf, const double* const* K, const int* n, const int* ldk,
@@ -1078,7 +1112,8 @@ int hodlr_get_factors(hodlr_t h, double* Upanel, double* Vpanel, hipStream_t str
   if (h->factored) return fail(HODLR_EINVAL, "factors are overwritten by hodlr_factor");
   if (!Upanel || !Vpanel) return fail(HODLR_EINVAL, "NULL pointer");
   if (h->tree.L == 0 || h->R == 0) return HODLR_OK;
-  return launch_to_f64_panels(h, Upanel, Vpanel, stream);
+  HODLR_TRY(launch_to_f64_panels(h, Upanel, Vpanel, stream));
+  return mark_inflight(h, stream);
 }
 
 int hodlr_skel_info(hodlr_t h, int* kused) {
@@ -1153,8 +1188,12 @@ int hodlr_mlp_adam_step(const float* feats, const float* labels, int N, float* p
 
 int hodlr_destroy(hodlr_t h) {
   if (!h) return HODLR_OK;
-  // the handle's blocks go back to the allocator cache: finish pending work
-  HODLR_HIP(hipDeviceSynchronize());
+  // the handle's blocks go back to the allocator cache: work still queued on
+  // them must finish first (the calls that leave work queued recorded events)
+  bool busy = h->status_pending && hipEventQuery(h->status_ev) != hipSuccess;
+  for (hipEvent_t e : h->inflight) busy = busy || hipEventQuery(e) != hipSuccess;
+  (void)hipGetLastError();  // a not-ready query leaves no error behind
+  if (busy) HODLR_HIP(hipDeviceSynchronize());
   delete h;
   return HODLR_OK;
 }

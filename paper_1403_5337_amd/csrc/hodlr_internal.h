@@ -154,6 +154,9 @@ struct hodlr_s {
   int* pin_status = nullptr;
   size_t pin_status_bytes = 0;
   hipEvent_t status_ev = nullptr;
+  // events recorded behind work that calls leave queued on the handle's
+  // buffers (hodlr_destroy waits only if one has not completed)
+  std::vector<hipEvent_t> inflight;
   hodlr_s() = default;
   hodlr_s(const hodlr_s&) = delete;
   hodlr_s& operator=(const hodlr_s&) = delete;
@@ -161,6 +164,7 @@ struct hodlr_s {
     if (gemm_host) hodlr::pinned_free(gemm_host, gemm_host_bytes);
     if (pin_status) hodlr::pinned_free(pin_status, pin_status_bytes);
     if (status_ev) hodlr::event_give(status_ev);
+    for (hipEvent_t e : inflight) hodlr::event_give(e);
   }
 };
 
@@ -170,6 +174,9 @@ namespace hodlr {
 // (status_ev) and returns ESINGULAR as hodlr_factor does (the handle is then
 // no longer factorized); HODLR_OK when nothing is pending (api.hip).
 int settle_factor_status(hodlr_s* h);
+// Records an event on s behind work just queued on the handle's buffers
+// (completed events are recycled first; at most 16 are kept).
+int mark_inflight(hodlr_s* h, hipStream_t s);
 int singular_status(const int* st);
 
 // ---------------------------------------------------------------------------
