@@ -21,8 +21,9 @@
 // Every workgroup issues its HBM reads together: the operand columns (E or the
 // leaf inverse, then W) go to LDS by asynchronous global-to-LDS copies while
 // the right-hand side and the group sums are read into registers.  The
-// contraction over the rank splits the rank range across the four waves (one
-// row per lane) and adds the four wave results at the end.
+// contraction over the rank splits the rank range across 4 waves per column
+// group (one row per lane), or across all 16 waves for a single right-hand
+// column, and adds the parts in order at the end.
 #include <algorithm>
 
 #include "device_util.h"
@@ -32,7 +33,19 @@ namespace hodlr {
 
 constexpr int kRows = 64;        // rows per unit
 constexpr int kSolveThreads = 1024;  // 16 waves: four per SIMD
-constexpr int kZParts = 4;       // the rank range of a contraction splits in 4 (x 4 column groups)
+// The 16 waves of a unit split a contraction into kZP parts of the rank (or
+// row) range times kGroups column groups of kC columns: 4 x 4 for blocks of
+// 4 or more right-hand columns, all 16 waves on the range for one column.
+template <int SM>
+struct SolveSplit {
+  static constexpr int kZP = SM >= 4 ? 4 : 16 / SM;
+  static constexpr int kGroups = 16 / kZP;
+  static constexpr int kC = SM / kGroups;
+  static_assert(kZP * kGroups == 16 && kC * kGroups == SM, "16 waves");
+};
+// alignment of a wave's kC consecutive columns in an [z][SM] block
+template <typename T, int SM>
+constexpr int split_align() { return SolveSplit<SM>::kC * sizeof(T) >= 8 ? 8 : (int)sizeof(T); }
 constexpr int kLdW = kRows + 1;  // LDS column stride of staged W columns (read across columns)
 // LDS column stride of the staged E / leaf-inverse columns (read 4 rows at a
 // time, so 16-byte aligned)
@@ -47,7 +60,9 @@ template <> struct SolveCfg<double> { static constexpr int kArena = 224, kT = 2 
 template <typename T, int SM>
 struct SolveSmem {
   alignas(16) T arena[SolveCfg<T>::kArena * lda_lds<T>()];  // staged operand columns
-  alignas(16) T tb[SolveCfg<T>::kT * SM];       // right-hand block (z x SM), then wave sums
+  // right-hand block (z x SM), then the waves' partial sums (kZP x SM x 64)
+  alignas(16) T tb[SolveCfg<T>::kT * SM > SolveSplit<SM>::kZP * SM * kRows ? SolveCfg<T>::kT * SM
+                                                                          : SolveSplit<SM>::kZP * SM * kRows];
   alignas(16) T xs[kRows * SM];                 // x of the unit (i x SM)
 };
 
@@ -86,16 +101,18 @@ __device__ __forceinline__ void stage_stream(T* arena, const T* A, size_t lda, i
 }
 
 // acc[cj] += sum_z A(lane, z - a0) B(z, cb + cj) over this wave's share of
-// [z0, z1): wave w takes the quarter w % 4 of the range and the column group
-// cb = (w / 4) SM / 4.  A in LDS with column stride lda_lds, B in LDS as
+// [z0, z1): wave w takes part w % kZP of the range and the column group
+// cb = (w / kZP) kC.  A in LDS with column stride lda_lds, B in LDS as
 // [z][SM].  The loads of kU consecutive z are issued together; the sum runs
 // in z order.
 template <typename T, int SM>
-__device__ __forceinline__ void contract(const T* A, int a0, const T* B, int z0, int z1, T (&acc)[SM / 4]) {
-  constexpr int kC = SM / 4, kU = 8, kL = lda_lds<T>();
+__device__ __forceinline__ void contract(const T* A, int a0, const T* B, int z0, int z1,
+                                         T (&acc)[SolveSplit<SM>::kC]) {
+  constexpr int kC = SolveSplit<SM>::kC, kZP = SolveSplit<SM>::kZP, kU = 8, kL = lda_lds<T>();
+  constexpr int kAl = split_align<T, SM>();
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int zp = wave % kZParts, cb = (wave / kZParts) * kC;
-  const int per = (z1 - z0 + kZParts - 1) / kZParts;
+  const int zp = wave % kZP, cb = (wave / kZP) * kC;
+  const int per = (z1 - z0 + kZP - 1) / kZP;
   const int zb = z0 + zp * per, ze = min(z1, zb + per);
   int z = zb;
   for (; z + kU <= ze; z += kU) {
@@ -103,7 +120,7 @@ __device__ __forceinline__ void contract(const T* A, int a0, const T* B, int z0,
 #pragma unroll
     for (int k = 0; k < kU; ++k) {
       a[k] = A[(z + k - a0) * kL + lane];
-      const T* bp = static_cast<const T*>(__builtin_assume_aligned(B + (z + k) * SM + cb, 8));
+      const T* bp = static_cast<const T*>(__builtin_assume_aligned(B + (z + k) * SM + cb, kAl));
 #pragma unroll
       for (int cj = 0; cj < kC; ++cj) b[k][cj] = bp[cj];
     }
@@ -114,21 +131,21 @@ __device__ __forceinline__ void contract(const T* A, int a0, const T* B, int z0,
   }
   for (; z < ze; ++z) {
     const T a = A[(z - a0) * kL + lane];
-    const T* bp = static_cast<const T*>(__builtin_assume_aligned(B + z * SM + cb, 8));
+    const T* bp = static_cast<const T*>(__builtin_assume_aligned(B + z * SM + cb, kAl));
 #pragma unroll
     for (int cj = 0; cj < kC; ++cj) acc[cj] += a * bp[cj];
   }
 }
 
-// x(i, c) = xr - (sum of the four rank quarters) (sub) or the sum itself;
+// x(i, c) = xr - (sum of the kZP rank parts, in order) (sub) or the sum itself;
 // written to Xout (rows i < rn, c < nc) and to xs (zero elsewhere).  Thread
 // (lane, wave) finishes row lane of column wave (waves >= SM idle here).
 template <typename T, int SM>
-__device__ __forceinline__ void finalize_x(SolveSmem<T, SM>& sm, const T (&acc)[SM / 4], T xr, bool sub, int rn,
-                                           int nc, T* Xout, size_t ldxo) {
-  constexpr int kC = SM / 4;
+__device__ __forceinline__ void finalize_x(SolveSmem<T, SM>& sm, const T (&acc)[SolveSplit<SM>::kC], T xr,
+                                           bool sub, int rn, int nc, T* Xout, size_t ldxo) {
+  constexpr int kC = SolveSplit<SM>::kC, kZP = SolveSplit<SM>::kZP;
   const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
-  const int zp = wave % kZParts, cb = (wave / kZParts) * kC;
+  const int zp = wave % kZP, cb = (wave / kZP) * kC;
   __syncthreads();  // every wave is done with tb
 #pragma unroll
   for (int cj = 0; cj < kC; ++cj) sm.tb[(zp * SM + cb + cj) * kRows + lane] = acc[cj];
@@ -137,7 +154,7 @@ __device__ __forceinline__ void finalize_x(SolveSmem<T, SM>& sm, const T (&acc)[
     const int c = wave;
     T s = sm.tb[c * kRows + lane];
 #pragma unroll
-    for (int p = 1; p < kZParts; ++p) s += sm.tb[(p * SM + c) * kRows + lane];
+    for (int p = 1; p < kZP; ++p) s += sm.tb[(p * SM + c) * kRows + lane];
     const bool ok = lane < rn && c < nc;
     const T v = ok ? (sub ? xr - s : s) : T(0);
     if (ok) Xout[(size_t)c * ldxo + lane] = v;
@@ -148,16 +165,17 @@ __device__ __forceinline__ void finalize_x(SolveSmem<T, SM>& sm, const T (&acc)[
 
 // Pu(r0 + r, c) = sum_{i < rn} Wl(i, r) xs(i, c) for r < nw, c < nc (Pu has
 // leading dimension rp); Wl in LDS with column stride kLdW.  Lane = r.  Per
-// 64-column block of Wl the 16 waves split as 4 row quarters x 4 column
-// groups of SM / 4; the quarters are added in order through red (LDS,
-// 4 x SM x 64).
+// 64-column block of Wl the 16 waves split as kZP row parts x kGroups column
+// groups of kC; the parts are added in order through red (LDS,
+// kZP x SM x 64).
 template <typename T, int SM>
 __device__ __forceinline__ void unit_partials(const T* Wl, T* red, const T* xs, int rn, int nw, int nc, T* Pu,
                                               int r0, int rp) {
-  constexpr int kC = SM / 4, kU = 4;
+  constexpr int kC = SolveSplit<SM>::kC, kZP = SolveSplit<SM>::kZP, kU = 4;
+  constexpr int kAl = split_align<T, SM>();
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int part = wave % kZParts, cb = (wave / kZParts) * kC;
-  const int per = ((rn + kZParts - 1) / kZParts + kU - 1) / kU * kU;
+  const int part = wave % kZP, cb = (wave / kZP) * kC;
+  const int per = ((rn + kZP - 1) / kZP + kU - 1) / kU * kU;
   const int i0 = part * per, i1 = min(rn, i0 + per);
   for (int b0 = 0; b0 < nw; b0 += 64) {
     const int r = b0 + lane, rc = min(r, nw - 1);
@@ -171,7 +189,7 @@ __device__ __forceinline__ void unit_partials(const T* Wl, T* red, const T* xs, 
 #pragma unroll
       for (int k = 0; k < kU; ++k) {
         w[k] = wc[i + k];
-        const T* xp = static_cast<const T*>(__builtin_assume_aligned(xs + (i + k) * SM + cb, 8));
+        const T* xp = static_cast<const T*>(__builtin_assume_aligned(xs + (i + k) * SM + cb, kAl));
 #pragma unroll
         for (int cj = 0; cj < kC; ++cj) x[k][cj] = xp[cj];
       }
@@ -182,7 +200,7 @@ __device__ __forceinline__ void unit_partials(const T* Wl, T* red, const T* xs, 
     }
     for (; i < i1; ++i) {
       const T w = wc[i];
-      const T* xp = static_cast<const T*>(__builtin_assume_aligned(xs + i * SM + cb, 8));
+      const T* xp = static_cast<const T*>(__builtin_assume_aligned(xs + i * SM + cb, kAl));
 #pragma unroll
       for (int cj = 0; cj < kC; ++cj) acc[cj] += w * xp[cj];
     }
@@ -193,7 +211,7 @@ __device__ __forceinline__ void unit_partials(const T* Wl, T* red, const T* xs, 
       const int c = wave;
       T v = red[c * 64 + lane];
 #pragma unroll
-      for (int p = 1; p < kZParts; ++p) v += red[(p * SM + c) * 64 + lane];
+      for (int p = 1; p < kZP; ++p) v += red[(p * SM + c) * 64 + lane];
       if (r < nw && c < nc) Pu[(size_t)(r0 + r) + (size_t)c * rp] = v;
     }
     __syncthreads();
@@ -240,9 +258,9 @@ __device__ __forceinline__ void unit_pipeline(SolveSmem<T, SM>& sm, const T* A, 
                                               T* Xout, size_t ldxo, T* Pu, int rp, int jn) {
   constexpr int kA = SolveCfg<T>::kArena;
   const int total = ra + nwc;
-  T acc[SM / 4];
+  T acc[SolveSplit<SM>::kC];
 #pragma unroll
-  for (int cj = 0; cj < SM / 4; ++cj) acc[cj] = T(0);
+  for (int cj = 0; cj < SolveSplit<SM>::kC; ++cj) acc[cj] = T(0);
   bool done = false;
   for (int j0 = 0;;) {
     dma_wait();
@@ -335,7 +353,7 @@ __global__ void __launch_bounds__(kSolveThreads)
   // addresses are clamped into range).  Columns c >= nc are zero.
   const size_t usz = (size_t)rq * nc, gstride = (size_t)gin * usz;
   const int ng = upn / gin;
-  constexpr int kJ = sizeof(T) == 8 ? 16 : SM == 8 ? 48 : 32;
+  constexpr int kJ = sizeof(T) == 8 ? 16 : SM <= 8 ? 48 : 32;
   for (int e = t; e < r * SM; e += kSolveThreads) {
     const int z = e % r, cc = e / r;
     T sum = T(0);
@@ -443,7 +461,8 @@ static int apply_t(hodlr_s* h, T* X, int ldx, int nrhs, hipStream_t s) {
   for (int c0 = 0; c0 < nrhs; c0 += 16) {
     const int nc = std::min(16, nrhs - c0);
     T* Xc = X + (size_t)c0 * ldx;
-    if (nc <= 8) HODLR_TRY((solve_t<T, 8>(h, Xc, ldx, nc, s)));
+    if (nc == 1) HODLR_TRY((solve_t<T, 1>(h, Xc, ldx, nc, s)));
+    else if (nc <= 8) HODLR_TRY((solve_t<T, 8>(h, Xc, ldx, nc, s)));
     else HODLR_TRY((solve_t<T, 16>(h, Xc, ldx, nc, s)));
   }
   return HODLR_OK;
