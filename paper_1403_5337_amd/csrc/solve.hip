@@ -57,9 +57,15 @@ template <typename T> struct SolveCfg;
 template <> struct SolveCfg<float> { static constexpr int kArena = 480, kT = 2 * kRankCap32; };
 template <> struct SolveCfg<double> { static constexpr int kArena = 224, kT = 2 * kRankCap64; };
 
+// Operand columns staged at once.  A single right-hand column leaves room for
+// more of them (the widest float level, 2 x 184 E columns plus the parent's
+// 184 W columns, then stages in one round).
+template <typename T, int SM>
+constexpr int arena_cols() { return sizeof(T) == 4 && SM == 1 ? 560 : SolveCfg<T>::kArena; }
+
 template <typename T, int SM>
 struct SolveSmem {
-  alignas(16) T arena[SolveCfg<T>::kArena * lda_lds<T>()];  // staged operand columns
+  alignas(16) T arena[arena_cols<T, SM>() * lda_lds<T>()];  // staged operand columns
   // right-hand block (z x SM), then the waves' partial sums (kZP x SM x 64)
   alignas(16) T tb[SolveCfg<T>::kT * SM > SolveSplit<SM>::kZP * SM * kRows ? SolveCfg<T>::kT * SM
                                                                           : SolveSplit<SM>::kZP * SM * kRows];
@@ -256,7 +262,7 @@ template <typename T, int SM>
 __device__ __forceinline__ void unit_pipeline(SolveSmem<T, SM>& sm, const T* A, size_t lda, int ra, const T* Wp,
                                               size_t ldw, int nwc, int rn, int nc, T xr, bool sub,
                                               T* Xout, size_t ldxo, T* Pu, int rp, int jn) {
-  constexpr int kA = SolveCfg<T>::kArena;
+  constexpr int kA = arena_cols<T, SM>();
   const int total = ra + nwc;
   T acc[SolveSplit<SM>::kC];
 #pragma unroll
@@ -300,7 +306,7 @@ __global__ void __launch_bounds__(kSolveThreads)
   const T* Ki = Kinv + (size_t)leaf * bmax * bmax + row0;
   const T* Wu = W + (size_t)offL * ldw + l0 + row0;
   const int nwc = Pu ? rL : 0;
-  const int jn = min(SolveCfg<T>::kArena, b + nwc);
+  const int jn = min(arena_cols<T, SM>(), b + nwc);
   stage_stream(sm.arena, Ki, (size_t)bmax, b, Wu, (size_t)ldw, 0, jn, rn);
   // right-hand block: the leaf's rows of x, as [k][SM]
   for (int e0 = 0; e0 < b * SM; e0 += 4 * kSolveThreads) {
@@ -341,7 +347,7 @@ __global__ void __launch_bounds__(kSolveThreads)
   const T* Eu = E + (size_t)offE * ldE + row0;
   const T* Wu = W + (size_t)offp * ldw + row0;
   const int nwc = Pu ? rp : 0;
-  const int jn = min(SolveCfg<T>::kArena, r + nwc);
+  const int jn = min(arena_cols<T, SM>(), r + nwc);
   stage_stream(sm.arena, Eu, (size_t)ldE, r, Wu, (size_t)ldw, 0, jn, rn);
   // x of the unit: thread (lane, wave) holds row lane of column wave
   const int lane = t & 63, cw = t >> 6;
