@@ -225,6 +225,7 @@ __global__ void __launch_bounds__(gj_threads<T>())
 
 // y = S^-1 [t_a; t_b] for every parent of level q: t_a = G_a(0:r_b, 0:ccols),
 // t_b = G_b(0:r_a, 0:ccols).  Y is (2 rq) x ccols per parent (ld 2 rq).
+// Workgroup (parent, CT-column chunk), one thread per row of S.
 template <typename T, int CT>
 __global__ void __launch_bounds__(kBlock)
     k_schur_apply(const T* __restrict__ G, int rq, int gcols, int ccols, int nchunk,
@@ -268,6 +269,92 @@ __global__ void __launch_bounds__(kBlock)
       for (int c = 0; c < CT; ++c) acc[c] += s * Tc[z + c * r];
     }
     for (int c = 0; c < nc; ++c) Y[x + (size_t)(c0 + c) * lds] = acc[c];
+  }
+}
+
+// k_schur_apply for levels of few parents and column chunks, where one
+// thread per row leaves most of the GPU idle and each thread's inner loop is
+// one long latency chain.  Workgroup (parent, CT-column chunk, row tiles z,
+// z + gridDim.z, ... of 64
+// rows of S): lane = row, the four waves take quarters of the inner range
+// (16 loads of S in flight per thread), and their sums are added in quarter
+// order through LDS.  The right-hand block T is gathered first, four entries
+// by four split-K chunks per batch (each entry summed in chunk order).
+template <typename T, int CT>
+__global__ void __launch_bounds__(kBlock)
+    k_schur_apply_tiles(const T* __restrict__ G, int rq, int gcols, int ccols, int nchunk,
+                  const int* __restrict__ rank, int q, const T* __restrict__ Sinv, T* __restrict__ Yb) {
+  static_assert(kBlock == 256, "four waves");
+  constexpr int kU = 16, kE = 4, kH = 4;
+  __shared__ T Tc[2 * kRankCap32 * CT];
+  __shared__ T part[4][CT][64];
+  const int i = blockIdx.x, c0 = blockIdx.y * CT, t = threadIdx.x, nt = blockDim.x;
+  const int ra = rank[node_id(q, 2 * i)], rb = rank[node_id(q, 2 * i + 1)], r = ra + rb;
+  if ((int)blockIdx.z * 64 >= r) return;  // (uniform)
+  const int lds = 2 * rq, nc = min(CT, ccols - c0);
+  const size_t cs = (size_t)rq * gcols;  // one chunk's products
+  const T* Ga = G + (size_t)(2 * i) * nchunk * cs;
+  const T* Gb = G + (size_t)(2 * i + 1) * nchunk * cs;
+  const int ne = r * CT;
+  for (int e0 = 0; e0 < ne; e0 += kE * nt) {
+    const T* src[kE];
+    bool ok[kE];
+#pragma unroll
+    for (int k = 0; k < kE; ++k) {
+      const int e = min(e0 + t + k * nt, ne - 1), z = e % r, c = e / r;
+      ok[k] = e0 + t + k * nt < ne && c < nc;
+      src[k] = ((z < rb) ? Ga + z : Gb + (z - rb)) + (size_t)(c0 + min(c, nc - 1)) * rq;
+    }
+    T v[kE];
+#pragma unroll
+    for (int k = 0; k < kE; ++k) v[k] = T(0);
+    for (int h0 = 0; h0 < nchunk; h0 += kH) {
+      T g[kE][kH];
+#pragma unroll
+      for (int k = 0; k < kE; ++k)
+#pragma unroll
+        for (int u = 0; u < kH; ++u) g[k][u] = src[k][(size_t)min(h0 + u, nchunk - 1) * cs];
+#pragma unroll
+      for (int k = 0; k < kE; ++k)
+#pragma unroll
+        for (int u = 0; u < kH; ++u)
+          if (h0 + u < nchunk) v[k] += g[k][u];
+    }
+#pragma unroll
+    for (int k = 0; k < kE; ++k) {
+      const int e = e0 + t + k * nt;
+      if (e < ne) Tc[e] = ok[k] ? v[k] : T(0);  // Tc[z + c r] with e = z + c r
+    }
+  }
+  __syncthreads();
+  const int lane = t & 63, w = t >> 6;
+  const int per = (r + 3) / 4, z0 = w * per, z1 = min(r, z0 + per);
+  for (int x0 = blockIdx.z * 64; x0 < r; x0 += gridDim.z * 64) {  // (uniform)
+    const int x = x0 + lane;
+    const T* S = Sinv + (size_t)i * lds * lds + min(x, r - 1);
+    T acc[CT];
+#pragma unroll
+    for (int c = 0; c < CT; ++c) acc[c] = T(0);
+    for (int zb = z0; zb < z1; zb += kU) {
+      T sv[kU];
+#pragma unroll
+      for (int u = 0; u < kU; ++u) sv[u] = S[(size_t)min(zb + u, z1 - 1) * lds];
+#pragma unroll
+      for (int u = 0; u < kU; ++u)
+        if (zb + u < z1) {
+#pragma unroll
+          for (int c = 0; c < CT; ++c) acc[c] += sv[u] * Tc[zb + u + c * r];
+        }
+    }
+#pragma unroll
+    for (int c = 0; c < CT; ++c) part[w][c][lane] = acc[c];
+    __syncthreads();
+    if (w == 0 && x < r) {
+      T* Y = Yb + (size_t)i * lds * ccols + x;
+      for (int c = 0; c < nc; ++c)
+        Y[(size_t)(c0 + c) * lds] = ((part[0][c][lane] + part[1][c][lane]) + part[2][c][lane]) + part[3][c][lane];
+    }
+    __syncthreads();  // part is rewritten by the next tile
   }
 }
 
@@ -528,8 +615,14 @@ static int level_solve(hodlr_s* h, int q, T* Z, int ldz, int zcols, const T* G, 
   T* Yb = h->Ybuf.as<T>();
   {
     ProfScope prof_("schur_apply", s);
-    k_schur_apply<T, kCT><<<dim3(1 << (q - 1), cdiv(zcols, kCT)), kBlock, 0, s>>>(
-        G, rq, gcols, zcols, nchunk, h->d_rank.as<int>(), q, Sinv, Yb);
+    // few parents x column chunks: rows split over 64-row tiles and inner
+    // quarters (measured faster below 256 workgroups, slower above)
+    const dim3 grid(1 << (q - 1), cdiv(zcols, kCT));
+    if (grid.x * grid.y < 256)
+      k_schur_apply_tiles<T, kCT><<<dim3(grid.x, grid.y, cdiv(2 * rq, 64)), kBlock, 0, s>>>(
+          G, rq, gcols, zcols, nchunk, h->d_rank.as<int>(), q, Sinv, Yb);
+    else
+      k_schur_apply<T, kCT><<<grid, kBlock, 0, s>>>(G, rq, gcols, zcols, nchunk, h->d_rank.as<int>(), q, Sinv, Yb);
   }
   HODLR_HIP(hipGetLastError());
   {
