@@ -152,18 +152,18 @@ def cpu_baseline(front, w, nrhs_sample, method, depth, solver="gmres", budget_s=
 # taken again.
 TRAFFIC = {
     ("apply_level", "tpfa4096"): {"source": "paper_1403_5337_amd/csrc/solve.hip",
-                                  "sha256": "d5e3db8afac3546271c5beed0bba049c2f5e995a686cd2db6cd7e4901aff8021",
+                                  "sha256": "4dc5f267b69ce67025d51d8cab199c4d9ab1f16ab3ff2ddfd4bff7a9fca48695",
                                   "fetch_kib": 1612.0, "write_kib": 236.0,
-                                  "fetch_factor": 2.0, "write_factor": 1.0, "rocprof_avg_us": 8.38},
+                                  "fetch_factor": 2.0, "write_factor": 1.0, "rocprof_avg_us": 8.26},
     ("apply_level", "elastic6144"): {"source": "paper_1403_5337_amd/csrc/solve.hip",
-                                     "sha256": "d5e3db8afac3546271c5beed0bba049c2f5e995a686cd2db6cd7e4901aff8021",
+                                     "sha256": "4dc5f267b69ce67025d51d8cab199c4d9ab1f16ab3ff2ddfd4bff7a9fca48695",
                                      "fetch_kib": 4434.1, "write_kib": 67.3,
-                                     "fetch_factor": 2.0, "write_factor": 1.0, "rocprof_avg_us": 7.70},
+                                     "fetch_factor": 2.0, "write_factor": 1.0, "rocprof_avg_us": 7.24},
     # the float64 product on float32 z at the 128-column split width
     ("matvec", "elastic6144"): {"source": "paper_1403_5337_amd/csrc/gmres.hip",
                                 "sha256": "0ff06d821dda06ed820a440ab140e84372e5ebee118f4cd9ac4048dfefe166f0",
                                 "fetch_kib": 147578.5, "write_kib": 2304.0,
-                                "fetch_factor": 2.0, "write_factor": 1.0, "rocprof_avg_us": 46.08},
+                                "fetch_factor": 2.0, "write_factor": 1.0, "rocprof_avg_us": 46.16},
 }
 
 
