@@ -145,6 +145,16 @@ template <typename T> __device__ __forceinline__ void wave_argmax_uniform(T& v, 
 // results by readlane.  NaN never wins a comparison.
 template <typename T> __device__ __forceinline__ T sel_max(T a, T b) { return b > a ? b : a; }
 
+// A launch gated on per-column activity flags (gate[0..ngate), any nonzero:
+// work to do) does nothing once every column has stopped.  Every thread reads
+// the same flags, so the answer is the same across the workgroup.
+__device__ __forceinline__ bool gate_closed(const int* gate, int ngate) {
+  if (!gate) return false;
+  int any = 0;
+  for (int k = 0; k < ngate; ++k) any |= gate[k];
+  return any == 0;
+}
+
 template <typename T> __device__ __forceinline__ T wave_max(T m) {
   m = sel_max(m, dpp_move<0xB1>(m));
   m = sel_max(m, dpp_move<0x4E>(m));

@@ -46,7 +46,8 @@ typedef double f64x4 __attribute__((ext_vector_type(4)));
 template <typename TZ, int NB, int COLS>
 __global__ void __launch_bounds__(kRowsPerWG)
     k_matvec_mfma(const double* __restrict__ K, int ldk, int n, const TZ* __restrict__ src, int lds, int s,
-                  double* __restrict__ part, int rev) {
+                  double* __restrict__ part, int rev, const int* __restrict__ gate) {
+  if (gate_closed(gate, s)) return;
   constexpr int kQ = COLS / 4;
   __shared__ double zs[COLS * 16 * NB];  // z(c, k) at zs[c 16 NB + k]
   const int t = threadIdx.x, lane = t & 63, w = t >> 6, sp = rev ? gridDim.y - 1 - blockIdx.y : blockIdx.y;
@@ -106,7 +107,8 @@ __global__ void __launch_bounds__(kRowsPerWG)
 template <typename TZ, int NB, int CH>
 __global__ void __launch_bounds__(kRowsPerWG)
     k_matvec_chunks(const double* __restrict__ K, int ldk, int n, const TZ* __restrict__ src, int lds, int s,
-                    double* __restrict__ part, int rev) {
+                    double* __restrict__ part, int rev, const int* __restrict__ gate) {
+  if (gate_closed(gate, s)) return;
   constexpr int COLS = 128, kQ = COLS / 4, WD = CH * COLS;
   __shared__ double zs[WD * 16 * NB];  // z(c, k) at zs[c 16 NB + k]
   const int t = threadIdx.x, lane = t & 63, w = t >> 6, sp = rev ? gridDim.y - 1 - blockIdx.y : blockIdx.y;
@@ -562,9 +564,10 @@ size_t gmres_noalloc_limit() { return kNoallocScratchBytes; }
 
 template <typename TZ, int COLS>
 static int launch_matvec_cols(const double* K, int ldk, int n, const TZ* src, int lds, int s, double* part,
-                              hipStream_t st, int rev) {
+                              hipStream_t st, int rev, const int* gate) {
   const dim3 grid((n + 63) / 64, (n + COLS - 1) / COLS);
-#define HODLR_MV(NB) k_matvec_mfma<TZ, NB, COLS><<<grid, kRowsPerWG, 0, st>>>(K, ldk, n, src, lds, s, part, rev)
+#define HODLR_MV(NB) \
+  k_matvec_mfma<TZ, NB, COLS><<<grid, kRowsPerWG, 0, st>>>(K, ldk, n, src, lds, s, part, rev, gate)
   if (s <= 16) HODLR_MV(1);
   else if (s <= 32) HODLR_MV(2);
   else HODLR_MV(4);
@@ -575,12 +578,12 @@ static int launch_matvec_cols(const double* K, int ldk, int n, const TZ* src, in
 
 template <typename TZ, int CH>
 static int launch_matvec_chunks(const double* K, int ldk, int n, const TZ* src, int lds, int s, double* part,
-                                hipStream_t st, int rev) {
+                                hipStream_t st, int rev, const int* gate) {
   const dim3 grid((n + 63) / 64, (n + 128 * CH - 1) / (128 * CH));
   if (s <= 16)
-    k_matvec_chunks<TZ, 1, CH><<<grid, kRowsPerWG, 0, st>>>(K, ldk, n, src, lds, s, part, rev);
+    k_matvec_chunks<TZ, 1, CH><<<grid, kRowsPerWG, 0, st>>>(K, ldk, n, src, lds, s, part, rev, gate);
   else if (s <= 32)
-    k_matvec_chunks<TZ, 2, CH><<<grid, kRowsPerWG, 0, st>>>(K, ldk, n, src, lds, s, part, rev);
+    k_matvec_chunks<TZ, 2, CH><<<grid, kRowsPerWG, 0, st>>>(K, ldk, n, src, lds, s, part, rev, gate);
   else
     return fail(HODLR_EINVAL, "chunked product: too many right-hand sides for the staged z");
   HODLR_HIP(hipGetLastError());
@@ -597,7 +600,7 @@ static int matvec_choices(int s) { return s <= 32 ? 4 : 3; }
 
 template <typename TZ>
 static int launch_matvec(const double* K, int ldk, int n, const TZ* src, int lds, int s, double* part, int cols,
-                         hipStream_t st) {
+                         hipStream_t st, const int* gate = nullptr) {
   ProfScope prof("matvec", st);
   // successive products sweep K in opposite directions (column splits in
   // increasing, then decreasing order), so that each one starts on the part
@@ -606,23 +609,26 @@ static int launch_matvec(const double* K, int ldk, int n, const TZ* src, int lds
   // so the result does not depend on the direction
   static std::atomic<unsigned> calls{0};
   const int rev = (int)(calls.fetch_add(1, std::memory_order_relaxed) & 1u);
-  if (cols == 64) return launch_matvec_cols<TZ, 64>(K, ldk, n, src, lds, s, part, st, rev);
-  if (cols == 256) return launch_matvec_cols<TZ, 256>(K, ldk, n, src, lds, s, part, st, rev);
-  if (cols == 512) return launch_matvec_chunks<TZ, 4>(K, ldk, n, src, lds, s, part, st, rev);
-  return launch_matvec_cols<TZ, 128>(K, ldk, n, src, lds, s, part, st, rev);
+  if (cols == 64) return launch_matvec_cols<TZ, 64>(K, ldk, n, src, lds, s, part, st, rev, gate);
+  if (cols == 256) return launch_matvec_cols<TZ, 256>(K, ldk, n, src, lds, s, part, st, rev, gate);
+  if (cols == 512) return launch_matvec_chunks<TZ, 4>(K, ldk, n, src, lds, s, part, st, rev, gate);
+  return launch_matvec_cols<TZ, 128>(K, ldk, n, src, lds, s, part, st, rev, gate);
 }
 
 // The split width for (n, right-hand-side block, type of z): chosen on the
 // first product of that shape by timing each width (tune_choice), kept for
-// the process.
+// the process.  gate (s column flags, may be NULL): the product does nothing
+// once every column has stopped; the launches that time the widths are not
+// gated.
 template <typename TZ>
 static int matvec_cols(const double* K, int ldk, int n, const TZ* src, int lds, int s, double* part,
-                       hipStream_t st, int* cols) {
+                       hipStream_t st, int* cols, const int* gate = nullptr) {
   const std::string key = "matvec:" + std::to_string(n) + ":" + std::to_string((s + 15) / 16) + ":" +
                           std::to_string(sizeof(TZ));
   int pick = 1;
+  const int* g = gate && tune_known(key) ? gate : nullptr;
   HODLR_TRY(tune_choice(key, matvec_choices(s), 1, [&](int c) {
-    return launch_matvec<TZ>(K, ldk, n, src, lds, s, part, kMatvecChoices[c], st);
+    return launch_matvec<TZ>(K, ldk, n, src, lds, s, part, kMatvecChoices[c], st, g);
   }, st, &pick));
   *cols = kMatvecChoices[pick];
   return HODLR_OK;
@@ -740,14 +746,20 @@ static int gmres_t(const double* K, int n, int ldk, hodlr_s* M, const double* B,
     }
     bool idle = false;  // a deferred start found no active column
     k_normalize<TP><<<gvec, kBlock, 0, st>>>(n, s, w, wp.scal, active, V, Z);
+    // profiler records before each step: a step found afterwards to have been
+    // queued with no active column did nothing, and its records are dropped
+    size_t mark[2] = {prof_count(), 0};
     for (int j = 0; j < m; ++j) {
+      mark[j & 1] = prof_count();
       const double* src_d = V + (size_t)j * ns;
       if (M) {
         TP* zj = Z + (size_t)j * ns;
-        HODLR_TRY(apply_impl(M, zj, n, s, st));
-        HODLR_TRY(matvec_cols<TP>(K, ldk, n, zj, n, s, part, st, &cols_p));
+        // (the preconditioner and the product of a step taken after every
+        // column has stopped do nothing: gated on the step's flags)
+        HODLR_TRY(apply_impl(M, zj, n, s, st, act[j & 1]));
+        HODLR_TRY(matvec_cols<TP>(K, ldk, n, zj, n, s, part, st, &cols_p, act[j & 1]));
       } else {
-        HODLR_TRY(matvec_cols<double>(K, ldk, n, src_d, n, s, part, st, &cols_p));
+        HODLR_TRY(matvec_cols<double>(K, ldk, n, src_d, n, s, part, st, &cols_p, act[j & 1]));
       }
       const int nsplit = (n + cols_p - 1) / cols_p;
       {
@@ -791,6 +803,7 @@ static int gmres_t(const double* K, int n, int ldk, hodlr_s* M, const double* B,
           // the steps queued behind the start use the workspace: let them end
           HODLR_HIP(hipStreamSynchronize(st));
           if (rc != HODLR_OK) return rc;
+          prof_drop_from(mark[0]);
           idle = true;
           break;
         }
@@ -800,7 +813,10 @@ static int gmres_t(const double* K, int n, int ldk, hodlr_s* M, const double* B,
         const int* prev = host_flags + 64 + 64 * ((j - 1) & 1);
         bool more = false;
         for (int k = 0; k < s; ++k) more |= prev[k] != 0;
-        if (!more) break;
+        if (!more) {
+          prof_drop_from(mark[j & 1]);  // step j was queued behind columns that had all stopped
+          break;
+        }
       }
     }
     if (idle) break;

@@ -237,7 +237,9 @@ int launch_leaf_inverse(hodlr_s* h, int* status, hipStream_t s);
 int ensure_work(hodlr_s* h, int ncols);
 
 // solve.hip
-int apply_impl(hodlr_s* h, void* X, int ldx, int nrhs, hipStream_t s);  // in place
+// in place; gate (nrhs column flags, may be NULL): every launch does nothing
+// once all columns have stopped
+int apply_impl(hodlr_s* h, void* X, int ldx, int nrhs, hipStream_t s, const int* gate = nullptr);
 size_t solve_partial_elems(const hodlr_s* h);
 
 // api.hip: streams for work that runs beside the caller's stream (default
@@ -249,8 +251,14 @@ bool prof_on();
 void prof_suspend(bool on);  // this thread records nothing while suspended
 void tune_freeze(bool on);   // this thread's tune_choice uses kept choices or the fallback, timing nothing
 void prof_mark(const char* name, hipStream_t s, bool begin);
+// records so far, and dropping the records from a count on: launches known
+// afterwards to have done nothing (a step queued after its columns stopped)
+// are kept out of the per-kernel times
+size_t prof_count();
+void prof_drop_from(size_t first);
 // launch(c) for candidate c < ncand, the choice for `key` found by timing on
 // first use (see prof.hip); *pick receives it
+bool tune_known(const std::string& key);  // a choice is kept for key
 int tune_choice(const std::string& key, int ncand, int fallback, const std::function<int(int)>& launch,
                 hipStream_t s, int* pick);
 std::string tune_report();

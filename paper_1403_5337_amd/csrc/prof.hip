@@ -1,12 +1,14 @@
 // Optional per-kernel timing with HIP events recorded on the launch stream.
 // Off by default; when on, every wrapped launch records an event pair, and
 // hodlr_prof_query sums the elapsed times of one kernel name.
+#include <algorithm>
 #include <cstdlib>
 #include <cstring>
 #include <functional>
 #include <map>
 #include <mutex>
 #include <string>
+#include <thread>
 #include <vector>
 
 #include "hodlr_internal.h"
@@ -17,6 +19,7 @@ namespace {
 struct Rec {
   const char* name;
   hipEvent_t a, b;
+  std::thread::id tid;  // the recording thread
 };
 std::mutex g_mu;
 bool g_on = false;
@@ -52,6 +55,25 @@ bool prof_on() { return g_on && !t_suspended; }
 void prof_suspend(bool on) { t_suspended = on; }
 void tune_freeze(bool on) { t_no_tune = on; }
 
+size_t prof_count() {
+  std::lock_guard<std::mutex> lk(g_mu);
+  return g_recs.size();
+}
+void prof_drop_from(size_t first) {  // this thread's records only
+  std::lock_guard<std::mutex> lk(g_mu);
+  const std::thread::id me = std::this_thread::get_id();
+  size_t keep = std::min(first, g_recs.size());
+  for (size_t i = keep; i < g_recs.size(); ++i) {
+    Rec& r = g_recs[i];
+    if (r.tid == me) {
+      if (r.a) g_pool.push_back(r.a);
+      if (r.b) g_pool.push_back(r.b);
+    } else {
+      g_recs[keep++] = r;
+    }
+  }
+  g_recs.resize(keep);
+}
 void prof_mark(const char* name, hipStream_t s, bool begin) {
   std::lock_guard<std::mutex> lk(g_mu);
   if (!g_on) return;
@@ -59,7 +81,7 @@ void prof_mark(const char* name, hipStream_t s, bool begin) {
   if (!e) return;
   (void)hipEventRecord(e, s);
   if (begin) {
-    g_recs.push_back(Rec{name, e, nullptr});
+    g_recs.push_back(Rec{name, e, nullptr, std::this_thread::get_id()});
   } else {
     for (auto it = g_recs.rbegin(); it != g_recs.rend(); ++it)
       if (it->b == nullptr && std::string(it->name) == name) {
@@ -85,6 +107,11 @@ constexpr int kTuneReps = 3;
 std::mutex g_tune_mu;
 std::map<std::string, int> g_tune;
 }  // namespace
+
+bool tune_known(const std::string& key) {
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  return g_tune.count(key) != 0;
+}
 
 int tune_choice(const std::string& key, int ncand, int fallback, const std::function<int(int)>& launch,
                 hipStream_t s, int* pick) {

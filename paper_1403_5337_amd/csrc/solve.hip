@@ -292,7 +292,9 @@ template <typename T, int SM>
 __global__ void __launch_bounds__(kSolveThreads)
     k_solve_leaf(const T* __restrict__ Kinv, int bmax, const int* __restrict__ lo, const int* __restrict__ hi,
                  int idL, const T* __restrict__ Xin, int ldxi, T* __restrict__ Xout, int ldxo, int nc,
-                 const T* __restrict__ W, int ldw, int offL, int rL, int nchL, T* __restrict__ P) {
+                 const T* __restrict__ W, int ldw, int offL, int rL, int nchL, T* __restrict__ P,
+                 const int* __restrict__ gate) {
+  if (gate_closed(gate, nc)) return;
   __shared__ SolveSmem<T, SM> sm;
   const int leaf = blockIdx.x, ch = blockIdx.y, id = idL + leaf, t = threadIdx.x;
   const int l0 = lo[id], b = hi[id] - l0, row0 = ch * kRows, rn = min(kRows, b - row0);
@@ -331,7 +333,8 @@ __global__ void __launch_bounds__(kSolveThreads)
     k_solve_level(int q, const int* __restrict__ lo, const int* __restrict__ hi, const int* __restrict__ rank,
                   const T* Xin, int ldxi, T* Xout, int ldxo, int nc, const T* __restrict__ E, int ldE, int offE,
                   int rq, const T* __restrict__ Pin, int upn, int gin, int nch, const T* __restrict__ W, int ldw,
-                  int offp, int rp, T* __restrict__ Pout) {
+                  int offp, int rp, T* __restrict__ Pout, const int* __restrict__ gate) {
+  if (gate_closed(gate, nc)) return;
   __shared__ SolveSmem<T, SM> sm;
   const int c = blockIdx.x, ch = blockIdx.y, t = threadIdx.x;
   const int par = c >> 1, id = node_id(q, c);
@@ -415,7 +418,7 @@ size_t solve_partial_elems(const hodlr_s* h) {
 }
 
 template <typename T, int SM>
-static int solve_t(hodlr_s* h, T* X, int ldx, int nc, hipStream_t s) {
+static int solve_t(hodlr_s* h, T* X, int ldx, int nc, hipStream_t s, const int* gate) {
   const Tree& t = h->tree;
   const int n = t.n, L = t.L;
   T* P[2] = {h->G.as<T>(), h->G.as<T>() + h->p_half};
@@ -426,7 +429,7 @@ static int solve_t(hodlr_s* h, T* X, int ldx, int nc, hipStream_t s) {
     ProfScope prof_("apply_leaf", s);
     k_solve_leaf<T, SM><<<dim3(h->nleaf, nchL), kSolveThreads, 0, s>>>(
         h->Kinv.as<T>(), h->bmax, h->d_lo.as<int>(), h->d_hi.as<int>(), node_id(L, 0), X, ldx, Xt, n, nc,
-        h->W.as<T>(), n, offL, rL, nchL, L > 0 ? P[0] : nullptr);
+        h->W.as<T>(), n, offL, rL, nchL, L > 0 ? P[0] : nullptr, gate);
   }
   HODLR_HIP(hipGetLastError());
   int cur = 0;
@@ -451,7 +454,8 @@ static int solve_t(hodlr_s* h, T* X, int ldx, int nc, hipStream_t s) {
       ProfScope prof_("apply_level", s);
       k_solve_level<T, SM><<<dim3(1 << q, nch), kSolveThreads, 0, s>>>(
           q, h->d_lo.as<int>(), h->d_hi.as<int>(), h->d_rank.as<int>(), Xt, n, Xo, ldo, nc, h->E.as<T>(), n,
-          h->offE[q - 1], rq, P[cur], upn, gin, nch, h->W.as<T>(), n, offp, rp, q > 1 ? P[cur ^ 1] : nullptr);
+          h->offE[q - 1], rq, P[cur], upn, gin, nch, h->W.as<T>(), n, offp, rp, q > 1 ? P[cur ^ 1] : nullptr,
+          gate);
     }
     HODLR_HIP(hipGetLastError());
     cur ^= 1;
@@ -463,20 +467,21 @@ static int solve_t(hodlr_s* h, T* X, int ldx, int nc, hipStream_t s) {
 }
 
 template <typename T>
-static int apply_t(hodlr_s* h, T* X, int ldx, int nrhs, hipStream_t s) {
+static int apply_t(hodlr_s* h, T* X, int ldx, int nrhs, hipStream_t s, const int* gate) {
   for (int c0 = 0; c0 < nrhs; c0 += 16) {
     const int nc = std::min(16, nrhs - c0);
     T* Xc = X + (size_t)c0 * ldx;
-    if (nc == 1) HODLR_TRY((solve_t<T, 1>(h, Xc, ldx, nc, s)));
-    else if (nc <= 8) HODLR_TRY((solve_t<T, 8>(h, Xc, ldx, nc, s)));
-    else HODLR_TRY((solve_t<T, 16>(h, Xc, ldx, nc, s)));
+    const int* g = gate ? gate + c0 : nullptr;  // this block's columns
+    if (nc == 1) HODLR_TRY((solve_t<T, 1>(h, Xc, ldx, nc, s, g)));
+    else if (nc <= 8) HODLR_TRY((solve_t<T, 8>(h, Xc, ldx, nc, s, g)));
+    else HODLR_TRY((solve_t<T, 16>(h, Xc, ldx, nc, s, g)));
   }
   return HODLR_OK;
 }
 
-int apply_impl(hodlr_s* h, void* X, int ldx, int nrhs, hipStream_t s) {
-  return h->precision == 64 ? apply_t<double>(h, static_cast<double*>(X), ldx, nrhs, s)
-                            : apply_t<float>(h, static_cast<float*>(X), ldx, nrhs, s);
+int apply_impl(hodlr_s* h, void* X, int ldx, int nrhs, hipStream_t s, const int* gate) {
+  return h->precision == 64 ? apply_t<double>(h, static_cast<double*>(X), ldx, nrhs, s, gate)
+                            : apply_t<float>(h, static_cast<float*>(X), ldx, nrhs, s, gate);
 }
 
 }  // namespace hodlr
