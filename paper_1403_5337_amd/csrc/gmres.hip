@@ -667,7 +667,9 @@ static int gmres_t(const double* K, int n, int ldk, hodlr_s* M, const double* B,
       HODLR_HIP(hipHostGetDevicePointer(reinterpret_cast<void**>(&ws.dev_flags), ws.host_flags, 0));
     }
     for (int e = 0; e < 2; ++e)
-      if (!ws.ev[e]) HODLR_HIP(hipEventCreateWithFlags(&ws.ev[e], hipEventDisableTiming));
+      // no system-scope release at the step markers: the flags the host reads
+      // after them are already released by k_step_end's system fence
+      if (!ws.ev[e]) HODLR_HIP(hipEventCreateWithFlags(&ws.ev[e], hipEventDisableTiming | hipEventDisableSystemFence));
     wp.dev_flags = ws.dev_flags;
     host_flags = ws.host_flags;
     ev[0] = ws.ev[0];
