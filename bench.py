@@ -163,7 +163,7 @@ TRAFFIC = {
                                      "fetch_factor": 2.0, "write_factor": 1.0, "rocprof_avg_us": 7.74},
     # the float64 product on float32 z at the 128-column split width
     ("matvec", "elastic6144"): {"source": "paper_1403_5337_amd/csrc/gmres.hip",
-                                "sha256": "5b9e6ed02afacfff2040ead0a67f088c5cae363327f859cdfe8c9c0bb031c031",
+                                "sha256": "d5110fde45157ea8e0efd7b02994c367c7303b5c20a967d4d489011b55a77503",
                                 "fetch_kib": 147583.5, "write_kib": 2304.0,
                                 "fetch_factor": 2.0, "write_factor": 1.0, "rocprof_avg_us": 46.43},
 }
